@@ -1,0 +1,447 @@
+"""Plain FP64 CPU oracle for the stochastic Camassa-Holm particle filter
+(Cotter, Crisan & Singh, arXiv 2402.06927).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  It shares no code with
+the GPU library (``paper_2402_06927_amd``) and never imports it.
+
+The numerical work lives in ``sch_oracle.c`` (plain C, ``-O2
+-ffp-contract=off``); this module builds it with gcc and wraps it with ctypes
+over numpy arrays.  Each wrapper names the C function it calls; the paper
+passages are cited there.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sch_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ORC_OK = 0
+ORC_E_ARG = -1
+ORC_E_SINGULAR = -2
+ORC_E_NONCONVERGED = -3
+ORC_E_NONFINITE = -4
+ORC_E_DEGENERATE = -5
+
+TAG_INIT, TAG_FORECAST, TAG_PCN, TAG_ACCEPT, TAG_RESAMPLE, TAG_OBS, TAG_NUDGE = range(7)
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (plain C, no FMA contraction)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= max(
+        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "sch_oracle.h"))
+    ):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = [
+        "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c11",
+        "-Wall", "-Wextra", "-Wno-unused-parameter", "-shared", "-fPIC",
+        _SRC, "-o", tmp, "-lm",
+    ]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_u32p = C.POINTER(C.c_uint32)
+
+
+class OrcModel(C.Structure):
+    _fields_ = [
+        ("L", C.c_double), ("alpha", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
+        ("nx", C.c_int32), ("n_modes", C.c_int32), ("xi", _dp),
+        ("picard_tol", C.c_double), ("picard_max", C.c_int32),
+    ]
+
+
+class OrcRng(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("cycle", C.c_uint32), ("temper_k", C.c_uint32)]
+
+
+class OrcCycleStats(C.Structure):
+    _fields_ = [
+        ("ess", C.c_double), ("resampled", C.c_int32), ("n_temper", C.c_int32),
+        ("picard_iters", C.c_int64), ("n_accept", C.c_int64), ("status", C.c_int32),
+    ]
+
+
+def _declare(L):
+    sig = {
+        "orc_philox4x32_10": (None, [_u32p, C.c_uint64, _u32p]),
+        "orc_u01": (C.c_double, [C.c_uint32, C.c_uint32]),
+        "orc_normal_pair": (None, [C.c_uint64] + [C.c_uint32] * 4 + [_dp]),
+        "orc_uniform": (C.c_double, [C.c_uint64] + [C.c_uint32] * 4),
+        "orc_draw_increments": (None, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_uint32,
+                                       C.c_uint32, C.c_uint32, C.c_double, _dp]),
+        "orc_dense_solve": (C.c_int, [C.c_int32, _dp, _dp, _dp]),
+        "orc_tridiag_pivot_solve": (C.c_int, [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]),
+        "orc_cyclic_solve": (C.c_int, [C.c_int32, _dp, _dp, _dp, _dp, _dp]),
+        "orc_apply_mass": (None, [C.c_int32, C.c_double, _dp, _dp]),
+        "orc_apply_stiff": (None, [C.c_int32, C.c_double, _dp, _dp]),
+        "orc_apply_advect": (None, [C.c_int32, _dp, _dp, _dp]),
+        "orc_velocity_from_momentum": (C.c_int, [C.POINTER(OrcModel), _dp, _dp]),
+        "orc_momentum_from_velocity": (C.c_int, [C.POINTER(OrcModel), _dp, _dp]),
+        "orc_step": (C.c_int, [C.POINTER(OrcModel), _dp, _dp, _dp, _dp, _ip]),
+        "orc_window": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, _dp, _dp, _ip]),
+        "orc_ensemble_window": (C.c_int, [C.POINTER(OrcModel), C.c_int32, C.c_int32, _dp, _dp,
+                                          _dp, _dp, _ip, _ip, C.c_int32]),
+        "orc_observe": (None, [C.c_int32, C.c_int32, _dp, _dp]),
+        "orc_nll": (C.c_double, [C.c_int32, C.c_int32, _dp, _dp, _dp]),
+        "orc_ensemble_nll": (None, [C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]),
+        "orc_weights": (C.c_double, [C.c_int32, _dp, _dp, C.c_double, _dp, _dp]),
+        "orc_temper": (C.c_int, [C.c_int32, _dp, C.c_double, C.c_double, C.c_int32, _dp, _dp,
+                                 _dp]),
+        "orc_resample_systematic": (C.c_int, [C.c_int32, _dp, C.c_double, _ip]),
+        "orc_resample_textbook": (C.c_int, [C.c_int32, _dp, C.c_double, _ip]),
+        "orc_pcn_accept": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double]),
+        "orc_pcn_linear_chain": (C.c_int64, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _dp, _dp,
+                                             C.c_double, C.c_double, C.c_double, C.c_double,
+                                             C.c_int32, _dp, _dp]),
+        "orc_jitter_pcn": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.POINTER(OrcRng),
+                                     C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     C.c_double, C.c_double, C.c_int32, _ip, C.c_int32]),
+        "orc_bootstrap_cycle": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_uint64,
+                                          C.c_uint32, C.c_int32, C.c_int32, C.c_double, _dp, _dp,
+                                          _dp, C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_tempered_cycle": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_uint64,
+                                         C.c_uint32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                         C.c_double, C.c_int32, C.c_int32, _dp, _dp,
+                                         C.POINTER(OrcCycleStats), C.c_int32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _d(a):
+    """Pointer to a C-contiguous float64 numpy array (None passes NULL)."""
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "need C-contiguous float64"
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    if a is None:
+        return None
+    assert a.dtype == np.int32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def n_threads_default() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+# --------------------------------------------------------------------------- RNG
+def philox4x32_10(ctr, seed: int) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    out = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, C.c_uint64(seed), out)
+    return np.array(list(out), dtype=np.uint32)
+
+
+def u01(hi: int, lo: int) -> float:
+    return lib().orc_u01(hi, lo)
+
+
+def normal_pair(seed, c0, c1, c2, c3):
+    z = np.zeros(2)
+    lib().orc_normal_pair(seed, c0, c1, c2, c3, _d(z))
+    return z
+
+
+def uniform(seed, c0, c1, c2, c3) -> float:
+    return lib().orc_uniform(seed, c0, c1, c2, c3)
+
+
+def draw_increments(seed, n_particles, n_steps, n_modes, step0, tag, word3, dt):
+    out = np.zeros((n_particles, n_steps, n_modes))
+    lib().orc_draw_increments(seed, n_particles, n_steps, n_modes, step0, tag, word3, dt, _d(out))
+    return out
+
+
+# --------------------------------------------------------------------------- model
+@dataclass
+class Model:
+    """Physical and numerical parameters of the SCH model (section 2)."""
+    L: float
+    alpha: float
+    mu: float
+    dt: float
+    xi: np.ndarray  # [n_modes][nx]
+    picard_tol: float = 1e-13
+    picard_max: int = 50
+
+    @property
+    def nx(self) -> int:
+        return int(self.xi.shape[1])
+
+    @property
+    def n_modes(self) -> int:
+        return int(self.xi.shape[0])
+
+    @property
+    def h(self) -> float:
+        return self.L / self.nx
+
+    def c(self) -> OrcModel:
+        self._xi = _f64(self.xi)
+        return OrcModel(self.L, self.alpha, self.mu, self.dt, self.nx, self.n_modes,
+                        _d(self._xi), self.picard_tol, self.picard_max)
+
+
+def dense_solve(A, b):
+    A = _f64(A)
+    b = _f64(b)
+    x = np.zeros_like(b)
+    st = lib().orc_dense_solve(len(b), _d(A), _d(b), _d(x))
+    return st, x
+
+
+def tridiag_pivot_solve(dl, d, du, b):
+    b = np.array(b, dtype=np.float64, copy=True, order="C")
+    nrhs = 1 if b.ndim == 1 else b.shape[0]
+    n = len(d)
+    st = lib().orc_tridiag_pivot_solve(n, nrhs, _d(_f64(dl)), _d(_f64(d)), _d(_f64(du)), _d(b))
+    return st, b
+
+
+def cyclic_solve(a, b, c, d):
+    x = np.zeros(len(b))
+    st = lib().orc_cyclic_solve(len(b), _d(_f64(a)), _d(_f64(b)), _d(_f64(c)), _d(_f64(d)),
+                                _d(x))
+    return st, x
+
+
+def apply_mass(h, f):
+    f = _f64(f)
+    out = np.zeros_like(f)
+    lib().orc_apply_mass(len(f), h, _d(f), _d(out))
+    return out
+
+
+def apply_stiff(h, f):
+    f = _f64(f)
+    out = np.zeros_like(f)
+    lib().orc_apply_stiff(len(f), h, _d(f), _d(out))
+    return out
+
+
+def apply_advect(v, f):
+    f = _f64(f)
+    v = _f64(v)
+    out = np.zeros_like(f)
+    lib().orc_apply_advect(len(f), _d(v), _d(f), _d(out))
+    return out
+
+
+def velocity_from_momentum(model: Model, m):
+    m = _f64(m)
+    u = np.zeros_like(m)
+    cm = model.c()
+    st = lib().orc_velocity_from_momentum(C.byref(cm), _d(m), _d(u))
+    assert st == ORC_OK, st
+    return u
+
+
+def momentum_from_velocity(model: Model, u):
+    """m for each row of u (1-D or [particles][nx])."""
+    u = _f64(u)
+    cm = model.c()
+    if u.ndim == 1:
+        m = np.zeros_like(u)
+        st = lib().orc_momentum_from_velocity(C.byref(cm), _d(u), _d(m))
+        assert st == ORC_OK, st
+        return m
+    m = np.zeros_like(u)
+    for p in range(u.shape[0]):
+        row = np.ascontiguousarray(u[p])
+        out = np.zeros_like(row)
+        st = lib().orc_momentum_from_velocity(C.byref(cm), _d(row), _d(out))
+        assert st == ORC_OK, st
+        m[p] = out
+    return m
+
+
+def step(model: Model, m, u, dW, dLam=None):
+    m = np.array(m, dtype=np.float64, copy=True)
+    u = np.array(u, dtype=np.float64, copy=True)
+    it = C.c_int32(0)
+    cm = model.c()
+    st = lib().orc_step(C.byref(cm), _d(m), _d(u), _d(_f64(dW)),
+                        _d(_f64(dLam)) if dLam is not None else None, C.byref(it))
+    return st, m, u, it.value
+
+
+def window(model: Model, m, u, dW, dLam=None):
+    m = np.array(m, dtype=np.float64, copy=True)
+    u = np.array(u, dtype=np.float64, copy=True)
+    dW = _f64(dW)
+    it = C.c_int32(0)
+    cm = model.c()
+    st = lib().orc_window(C.byref(cm), dW.shape[0], _d(m), _d(u), _d(dW),
+                          _d(_f64(dLam)) if dLam is not None else None, C.byref(it))
+    return st, m, u, it.value
+
+
+def ensemble_window(model: Model, m, u, dW, dLam=None, n_threads=None):
+    """m, u: [P][nx]; dW: [P][n_steps][n_modes]. Returns (worst, m, u, status, iters)."""
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    dW = _f64(dW)
+    P, ns = dW.shape[0], dW.shape[1]
+    status = np.zeros(P, dtype=np.int32)
+    iters = np.zeros(P, dtype=np.int32)
+    cm = model.c()
+    worst = lib().orc_ensemble_window(C.byref(cm), P, ns, _d(m), _d(u), _d(dW),
+                                      _d(_f64(dLam)) if dLam is not None else None,
+                                      _i(status), _i(iters), n_threads or n_threads_default())
+    return worst, m, u, status, iters
+
+
+# --------------------------------------------------------------------------- observation
+def observe(u, n_obs):
+    u = _f64(u)
+    out = np.zeros(n_obs)
+    lib().orc_observe(len(u), n_obs, _d(u), _d(out))
+    return out
+
+
+def nll(u, y, sigma):
+    u = _f64(u)
+    y = _f64(y)
+    sigma = _f64(np.broadcast_to(sigma, y.shape))
+    return lib().orc_nll(len(u), len(y), _d(u), _d(y), _d(sigma))
+
+
+def ensemble_nll(u, y, sigma):
+    u = _f64(u)
+    y = _f64(y)
+    sigma = _f64(np.broadcast_to(sigma, y.shape))
+    phi = np.zeros(u.shape[0])
+    lib().orc_ensemble_nll(u.shape[1], len(y), u.shape[0], _d(u), _d(y), _d(sigma), _d(phi))
+    return phi
+
+
+# --------------------------------------------------------------------------- weights
+def weights(phi, beta, logw_extra=None):
+    phi = _f64(phi)
+    w = np.zeros_like(phi)
+    lo = np.zeros_like(phi)
+    ess = lib().orc_weights(len(phi), _d(phi), _d(_f64(logw_extra)) if logw_extra is not None
+                            else None, beta, _d(w), _d(lo))
+    return ess, w, lo
+
+
+def temper(phi, theta, threshold, n_bisect=50):
+    phi = _f64(phi)
+    w = np.zeros_like(phi)
+    dth = C.c_double(0)
+    ess = C.c_double(0)
+    lib().orc_temper(len(phi), _d(phi), theta, threshold, n_bisect, C.byref(dth), _d(w),
+                     C.byref(ess))
+    return dth.value, w, ess.value
+
+
+def resample_systematic(w, u0):
+    w = _f64(w)
+    idx = np.zeros(len(w), dtype=np.int32)
+    st = lib().orc_resample_systematic(len(w), _d(w), u0, _i(idx))
+    return st, idx
+
+
+def resample_textbook(w, u0):
+    w = _f64(w)
+    idx = np.zeros(len(w), dtype=np.int32)
+    st = lib().orc_resample_textbook(len(w), _d(w), u0, _i(idx))
+    return st, idx
+
+
+# --------------------------------------------------------------------------- pCN
+def jitter_pcn(model: Model, y, sigma, seed, cycle, temper_k, m0, u0, dW, phi, m_end, u_end,
+               theta, rho, n_jitter, n_threads=None):
+    y = _f64(y)
+    sigma = _f64(np.broadcast_to(sigma, y.shape))
+    dW = np.array(dW, dtype=np.float64, copy=True, order="C")
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    m_end = np.array(m_end, dtype=np.float64, copy=True, order="C")
+    u_end = np.array(u_end, dtype=np.float64, copy=True, order="C")
+    P, ns = dW.shape[0], dW.shape[1]
+    acc = np.zeros(P, dtype=np.int32)
+    rg = OrcRng(seed, cycle, temper_k)
+    cm = model.c()
+    lib().orc_jitter_pcn(C.byref(cm), len(y), _d(y), _d(sigma), C.byref(rg), P, ns,
+                         _d(_f64(m0)), _d(_f64(u0)), _d(dW), _d(phi), _d(m_end), _d(u_end),
+                         theta, rho, n_jitter, _i(acc), n_threads or n_threads_default())
+    return dW, phi, m_end, u_end, acc
+
+
+def pcn_accept(theta, phi_old, phi_new, v) -> bool:
+    return bool(lib().orc_pcn_accept(theta, phi_old, phi_new, v))
+
+
+def pcn_linear_chain(seed, n_steps, n_modes, G, y, sigma, theta, rho, dt, n_iter, x0=None):
+    G = _f64(G)
+    y = _f64(y)
+    d = n_steps * n_modes
+    x0 = np.zeros(d) if x0 is None else _f64(x0)
+    samples = np.zeros((n_iter, d))
+    acc = lib().orc_pcn_linear_chain(seed, n_steps, n_modes, len(y), _d(G), _d(y), sigma, theta,
+                                     rho, dt, n_iter, _d(x0), _d(samples))
+    return samples, acc
+
+
+# --------------------------------------------------------------------------- cycles
+def bootstrap_cycle(model: Model, y, sigma, seed, cycle, m, u, logw, n_steps, ess_frac=0.5,
+                    n_threads=None):
+    """One bootstrap cycle, in place on copies; returns (rc, m, u, logw, stats)."""
+    y = _f64(y)
+    sigma = _f64(np.broadcast_to(sigma, y.shape))
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    logw = np.array(logw, dtype=np.float64, copy=True)
+    st = OrcCycleStats()
+    cm = model.c()
+    rc = lib().orc_bootstrap_cycle(C.byref(cm), len(y), _d(y), _d(sigma), seed, cycle,
+                                   m.shape[0], n_steps, ess_frac, _d(m), _d(u), _d(logw),
+                                   C.byref(st), n_threads or n_threads_default())
+    return rc, m, u, logw, st
+
+
+def tempered_cycle(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_threshold,
+                   n_bisect=50, rho=0.99, n_jitter=5, max_temper=100, n_threads=None):
+    y = _f64(y)
+    sigma = _f64(np.broadcast_to(sigma, y.shape))
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    st = OrcCycleStats()
+    cm = model.c()
+    rc = lib().orc_tempered_cycle(C.byref(cm), len(y), _d(y), _d(sigma), seed, cycle,
+                                  m.shape[0], n_steps, ess_threshold, n_bisect, rho, n_jitter,
+                                  max_temper, _d(m), _d(u), C.byref(st),
+                                  n_threads or n_threads_default())
+    return rc, m, u, st

@@ -1,0 +1,151 @@
+/*
+ * sch_oracle.h -- plain, slow, FP64 CPU oracle for the stochastic Camassa-Holm
+ * (SALT) particle filter of Cotter, Crisan & Singh (arXiv 2402.06927).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this code: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no source with the GPU library.
+ *
+ * Every function follows a passage of the paper (cited by section and
+ * equation label) or the textbook definition of the operation.  Where the
+ * paper is silent or garbled the reading taken is stated next to the code.
+ *
+ * Conventions: row-major, particle-major arrays ([particle][node]), node i at
+ * x_i = i*h on the periodic interval [0, L), h = L/nx.  All floating point is
+ * IEEE binary64; the library is compiled with -ffp-contract=off.
+ */
+#ifndef SCH_ORACLE_H
+#define SCH_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes (same meaning as the product library's, own values) ---- */
+enum {
+  ORC_OK = 0,
+  ORC_E_ARG = -1,
+  ORC_E_SINGULAR = -2,
+  ORC_E_NONCONVERGED = -3,
+  ORC_E_NONFINITE = -4,
+  ORC_E_DEGENERATE = -5
+};
+
+/* ---- counter-based RNG: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], uint64_t seed, uint32_t out[4]);
+double orc_u01(uint32_t hi, uint32_t lo);
+void orc_normal_pair(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                     double z[2]);
+double orc_uniform(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3);
+
+/* Stage tags placed in bits 24..31 of counter word 2. */
+enum {
+  ORC_TAG_INIT = 0,
+  ORC_TAG_FORECAST = 1,
+  ORC_TAG_PCN = 2,
+  ORC_TAG_ACCEPT = 3,
+  ORC_TAG_RESAMPLE = 4,
+  ORC_TAG_OBS = 5,
+  ORC_TAG_NUDGE = 6
+};
+
+/* dW[p][n][q] = sqrt(dt) * z for particle p, global step (step0 + n), mode q,
+ * drawn with the given tag and word-3 value (temper k << 16 | jitter j). */
+void orc_draw_increments(uint64_t seed, int32_t n_particles, int32_t n_steps, int32_t n_modes,
+                         uint32_t step0, uint32_t tag, uint32_t word3, double dt, double *dW);
+
+/* ---- model description ---- */
+typedef struct orc_model {
+  double L, alpha, mu, dt;
+  int32_t nx, n_modes;
+  const double *xi; /* [n_modes][nx] nodal values of the noise modes */
+  double picard_tol;
+  int32_t picard_max;
+} orc_model;
+
+/* ---- dense / banded linear algebra ---- */
+int orc_dense_solve(int32_t n, const double *A, const double *b, double *x);
+int orc_tridiag_pivot_solve(int32_t n, int32_t nrhs, const double *dl, const double *d,
+                            const double *du, double *b);
+int orc_cyclic_solve(int32_t n, const double *a, const double *b, const double *c,
+                     const double *d, double *x);
+
+/* ---- P1 operators on the periodic mesh ---- */
+void orc_apply_mass(int32_t nx, double h, const double *f, double *out);
+void orc_apply_stiff(int32_t nx, double h, const double *f, double *out);
+void orc_apply_advect(int32_t nx, const double *v, const double *f, double *out);
+int orc_velocity_from_momentum(const orc_model *md, const double *m, double *u);
+int orc_momentum_from_velocity(const orc_model *md, const double *u, double *m);
+
+/* ---- one implicit-midpoint step and windows ---- */
+int orc_step(const orc_model *md, double *m, double *u, const double *dW, const double *dLam,
+             int32_t *iters);
+int orc_window(const orc_model *md, int32_t n_steps, double *m, double *u, const double *dW,
+               const double *dLam, int32_t *iters);
+int orc_ensemble_window(const orc_model *md, int32_t n_particles, int32_t n_steps, double *m,
+                        double *u, const double *dW, const double *dLam, int32_t *status,
+                        int32_t *iters, int32_t n_threads);
+
+/* ---- observations and likelihood ---- */
+void orc_observe(int32_t nx, int32_t n_obs, const double *u, double *out);
+double orc_nll(int32_t nx, int32_t n_obs, const double *u, const double *y, const double *sigma);
+void orc_ensemble_nll(int32_t nx, int32_t n_obs, int32_t n_particles, const double *u,
+                      const double *y, const double *sigma, double *phi);
+
+/* ---- weights, ESS, tempering ---- */
+double orc_weights(int32_t n, const double *phi, const double *logw_extra, double beta,
+                   double *w, double *logw_out);
+int orc_temper(int32_t n, const double *phi, double theta, double threshold, int32_t n_bisect,
+               double *dtheta, double *w, double *ess);
+
+/* ---- systematic resampling ---- */
+int orc_resample_systematic(int32_t n, const double *w, double u0, int32_t *idx);
+int orc_resample_textbook(int32_t n, const double *w, double u0, int32_t *idx);
+
+/* ---- pCN jittering ---- */
+typedef struct orc_rng {
+  uint64_t seed;
+  uint32_t cycle, temper_k;
+} orc_rng;
+
+void orc_pcn_propose(uint64_t seed, uint32_t particle, uint32_t step0, int32_t n_steps,
+                     int32_t n_modes, uint32_t word3, double rho, double dt, const double *cur,
+                     double *prop);
+int orc_pcn_accept(double theta, double phi_old, double phi_new, double v);
+int64_t orc_pcn_linear_chain(uint64_t seed, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                             const double *G, const double *y, double sigma, double theta,
+                             double rho, double dt, int32_t n_iter, const double *x0,
+                             double *samples);
+int orc_jitter_pcn(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                   const orc_rng *rng, int32_t n_particles, int32_t n_steps, const double *m0,
+                   const double *u0, double *dW, double *phi, double *m_end, double *u_end,
+                   double theta, double rho, int32_t n_jitter, int32_t *n_accept,
+                   int32_t n_threads);
+
+/* ---- filter cycles ---- */
+typedef struct orc_cycle_stats {
+  double ess;          /* ESS before resampling (bootstrap) / after last step */
+  int32_t resampled;   /* bootstrap: 1 if resampled this cycle */
+  int32_t n_temper;    /* tempering steps taken */
+  int64_t picard_iters;/* total Picard iterations over the cycle */
+  int64_t n_accept;    /* pCN acceptances over the cycle */
+  int32_t status;
+} orc_cycle_stats;
+
+int orc_bootstrap_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                        uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                        double ess_frac, double *m, double *u, double *logw,
+                        orc_cycle_stats *st, int32_t n_threads);
+
+int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                       double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                       int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
+                       int32_t n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
