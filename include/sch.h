@@ -1,0 +1,271 @@
+/*
+ * sch.h -- C-ABI of the MI355X (gfx950) library for the particle filter of
+ * the viscous stochastic Camassa-Holm (SALT) equation, after Cotter, Crisan &
+ * Singh, "Data assimilation for the stochastic Camassa-Holm equation using
+ * particle filtering: a numerical investigation" (arXiv 2402.06927).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Memory.  Every array argument is a DEVICE pointer to memory the caller
+ *    owns (allocated by the caller, e.g. through PyTorch); the library never
+ *    allocates, frees or retains user memory.  Calls that need scratch space
+ *    take a caller-owned device workspace of at least sch_workspace_bytes()
+ *    bytes.  Scalars documented as "host" are plain values.
+ *  - Layout.  Row-major, particle-major: a field over the ensemble is
+ *    [n_particles][nx] with nodes contiguous; node i sits at x_i = i L / nx on
+ *    the periodic interval [0, L).  Noise increments are
+ *    [n_particles][n_steps][n_modes].  Floating point is IEEE binary64
+ *    throughout; indices are int32.
+ *  - Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls only enqueue work and return, unless documented as
+ *    synchronising (the cycle drivers read a few scalars back each step).
+ *  - Errors.  Every call returns an int status.  Arguments are validated on
+ *    the host before anything is enqueued; on a non-zero status nothing has
+ *    been enqueued (validation errors) or the HIP runtime reported a failure
+ *    (SCH_E_HIP).  sch_last_error() returns a thread-local message about the
+ *    last failure.  Conditions found on the device (a particle whose implicit
+ *    solve did not converge or produced a non-finite state) are reported per
+ *    particle through the optional `status` arrays, with the same codes.
+ *  - The velocity u must equal the Helmholtz image of the momentum m
+ *    (H u = M m, see sch_velocity); the library treats m as the prognostic
+ *    variable and uses u as the starting guess of the implicit solve.
+ */
+#ifndef SCH_H
+#define SCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCH_OK 0
+#define SCH_E_ARG (-1)          /* null pointer, non-positive size, bad parameter   */
+#define SCH_E_SHAPE (-2)        /* size combination the kernels do not support      */
+#define SCH_E_NONCONVERGED (-3) /* implicit solve hit picard_max without converging */
+#define SCH_E_NONFINITE (-4)    /* a NaN or infinity appeared in a particle state   */
+#define SCH_E_DEGENERATE (-5)   /* all weights zero, or the tempering-step cap hit  */
+#define SCH_E_HIP (-6)          /* the HIP runtime reported an error                */
+
+/* Stage tags of the counter-based generator (bits 24..31 of counter word 2). */
+#define SCH_TAG_INIT 0u
+#define SCH_TAG_FORECAST 1u
+#define SCH_TAG_PCN 2u
+#define SCH_TAG_ACCEPT 3u
+#define SCH_TAG_RESAMPLE 4u
+#define SCH_TAG_OBS 5u
+#define SCH_TAG_NUDGE 6u
+
+/* Model of section 2 (eqs. schce1, sde1, fde1) with the noise in the modes
+ * form dU = sum_q xi_q dW_q of section 2 (the expansion used in earlier SALT
+ * work), discretised with P1 elements on nx periodic cells of width L/nx and
+ * the implicit midpoint rule in time. */
+typedef struct sch_model {
+  double L;          /* domain length                                        */
+  double alpha;      /* Helmholtz length scale in m = u - alpha^2 u_xx       */
+  double mu;         /* viscosity                                            */
+  double dt;         /* time step                                            */
+  int32_t nx;        /* nodes = cells, >= 64                                 */
+  int32_t n_modes;   /* noise modes Q, 1..64                                 */
+  const double *xi;  /* device [n_modes][nx]: nodal values of the modes      */
+  double picard_tol; /* relative max-norm change of m that ends the solve    */
+  int32_t picard_max;/* iteration cap of the implicit solve                  */
+} sch_model;
+
+/* Observations of section 3 (eq. obseq): n_obs points x_j = j L / n_obs,
+ * the P1 velocity evaluated there, Gaussian errors with std sigma_j. */
+typedef struct sch_obs {
+  int32_t n_obs;
+  const double *y;     /* device [n_obs] */
+  const double *sigma; /* device [n_obs] */
+} sch_obs;
+
+/* Keys of the Philox4x32-10 counter-based generator (Salmon et al., SC'11):
+ * seed is the 64-bit key; cycle and temper_k enter the counter. */
+typedef struct sch_rng {
+  uint64_t seed;
+  uint32_t cycle;
+  uint32_t temper_k;
+} sch_rng;
+
+/* Per-cycle statistics returned by the cycle drivers (host struct). */
+typedef struct sch_cycle_stats {
+  double ess;            /* bootstrap: ESS before resampling; tempered: last step */
+  int32_t resampled;     /* bootstrap: 1 if the ensemble was resampled            */
+  int32_t n_temper;      /* tempered: number of tempering steps                   */
+  int64_t picard_iters;  /* implicit-solve iterations summed over the cycle       */
+  int64_t n_accept;      /* tempered: pCN acceptances summed over the cycle       */
+  int64_t particle_steps;/* model steps integrated (all particles, all windows)   */
+  int32_t status;        /* SCH_OK or the first error met                         */
+} sch_cycle_stats;
+
+/* Message about the last failure on the calling thread ("" if none). */
+const char *sch_last_error(void);
+/* Library version, 100 * major + minor. */
+int sch_version(void);
+
+/* Workspace sizes.  `which` is one of the SCH_WS_* values. */
+#define SCH_WS_RESAMPLE 1
+#define SCH_WS_BOOTSTRAP 2
+#define SCH_WS_TEMPERED 3
+size_t sch_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
+                           int32_t n_steps);
+
+/* --------------------------------------------------------------------------
+ * Noise.  dW[p][n][q] = sqrt(dt) z, z ~ N(0,1) by Box-Muller from one Philox
+ * block per mode pair, counter (p, rng->cycle * n_steps + n,
+ * (q/2) | tag << 24, rng->temper_k << 16): the iid N(0, dt) prior of the
+ * Brownian increments (section 3.1.2).  Modes 2k, 2k+1 share one block.
+ * ------------------------------------------------------------------------ */
+int sch_draw_increments(const sch_rng *rng, uint32_t tag, int32_t n_particles, int32_t n_steps,
+                        int32_t n_modes, double dt, double *dW, void *stream);
+
+/* Raw generator output: out[i][0..3] = Philox4x32-10 of the counter
+ * ctr[i][0..3] under the key `seed` (device arrays [n][4] of uint32).  Lets
+ * callers check the stream bit for bit against another implementation. */
+int sch_philox_blocks(uint64_t seed, int32_t n, const uint32_t *ctr, uint32_t *out, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Helmholtz relation, first line of eq. fde1: (M + alpha^2 K) u = M m, with
+ * M, K the P1 mass and stiffness matrices.  sch_velocity gives u from m;
+ * sch_init_momentum gives m from u (M m = (M + alpha^2 K) u; section 2:
+ * m(x,0) from u(x,0)).  In-place use is not allowed.
+ * ------------------------------------------------------------------------ */
+int sch_velocity(const sch_model *model, int32_t n_particles, const double *m, double *u,
+                 void *stream);
+int sch_init_momentum(const sch_model *model, int32_t n_particles, const double *u, double *m,
+                      void *stream);
+
+/* --------------------------------------------------------------------------
+ * sch_ensemble_step: advance every particle n_steps implicit-midpoint steps
+ * of eq. fde1,
+ *   (m^{n+1} - m^n, phi) + mu dt (d_x m^{n+1/2}, d_x phi)
+ *     + (m^{n+1/2} d_x dv, phi) - (m^{n+1/2} dv, d_x phi) = 0,
+ *   dv = dt (u^n + u^{n+1})/2 + sum_q xi_q (dW^n_q + dLambda^n_q),
+ * each step solved to picard_tol.  dLambda is the nudging control of
+ * eq. "SCH nudge" (NULL = zero).
+ *   m, u    in/out [n_particles][nx]
+ *   dW      [n_particles][n_steps][n_modes]
+ *   dLambda [n_particles][n_steps][n_modes] or NULL
+ *   status  out [n_particles] or NULL: SCH_OK, or the code of the first step
+ *           that failed (that particle then stops at that step)
+ *   iters   out [n_particles] or NULL: implicit-solve iterations summed
+ * ------------------------------------------------------------------------ */
+int sch_ensemble_step(const sch_model *model, int32_t n_particles, int32_t n_steps, double *m,
+                      double *u, const double *dW, const double *dLambda, int32_t *status,
+                      int32_t *iters, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Observation operator of eq. obseq: out[p][j] = P1 value of u_p at
+ * x_j = j L / n_obs (cell floor(j nx / n_obs), located in integers).
+ * ------------------------------------------------------------------------ */
+int sch_observe(const sch_model *model, int32_t n_obs, int32_t n_particles, const double *u,
+                double *out, void *stream);
+
+/* --------------------------------------------------------------------------
+ * sch_loglik: negative log of the likelihood weight of eq. loglikeq,
+ *   phi[p] = 1/2 sum_j ((P u_p)_j - y_j)^2 / sigma_j^2.
+ * A non-finite result is stored as +infinity (weight zero).
+ * ------------------------------------------------------------------------ */
+int sch_loglik(const sch_model *model, const sch_obs *obs, int32_t n_particles, const double *u,
+               double *phi, void *stream);
+
+/* --------------------------------------------------------------------------
+ * sch_temper_ess: normalised weights, effective sample size (eq. ess) and the
+ * adaptive tempering increment (section 3.1.2).  With s_p = logw_extra[p] -
+ * beta phi[p], w[p] = exp(s_p) / sum exp(s), ESS = 1 / sum w^2.
+ *   theta      device scalar in/out: temperature before / after the step
+ *   n_bisect   > 0: beta = the largest increment <= 1 - theta whose ESS is
+ *              >= ess_threshold, found by n_bisect halvings (if the full
+ *              remainder keeps the ESS it is taken and theta becomes 1);
+ *              == 0: beta = 1 - theta (no search; the bootstrap filter uses
+ *              theta = 0, beta = 1 with its carried log-weights)
+ *   logw_extra device [n] or NULL (zero)
+ *   dtheta     device scalar out: the increment taken
+ *   w          device [n] out; logw_out device [n] out or NULL: log w
+ *   ess        device scalar out: ESS at the increment taken
+ * n_particles <= 65536.  Runs as one workgroup.
+ * ------------------------------------------------------------------------ */
+int sch_temper_ess(int32_t n_particles, const double *phi, const double *logw_extra,
+                   double *theta, double ess_threshold, int32_t n_bisect, double *dtheta,
+                   double *w, double *logw_out, double *ess, void *stream);
+
+/* --------------------------------------------------------------------------
+ * sch_resample: systematic resampling (section 3.1.1) of normalised weights
+ * w[n] with the uniform *u0 (device scalar in [0,1)), in the integer-exact
+ * form: q_p = floor(w_p 2^(51 - b - e)), b = ceil(log2 n), e the binary
+ * exponent of max w; C_p the inclusive prefix sums of q (exact, < 2^51);
+ * T_j = ((j + u0) * C_{n-1}) / n with each operation rounded once;
+ * idx[j] = min{ p : C_p > T_j } (clamped to n - 1).  Indices are therefore a
+ * pure function of (w, u0), bit-identical to any correct implementation.
+ *   cond_ess, cond_threshold: if cond_ess is not NULL and *cond_ess >=
+ *   cond_threshold, idx becomes the identity (no resampling), evaluated on
+ *   the device.
+ * workspace >= sch_workspace_bytes(SCH_WS_RESAMPLE, NULL, n, 0).
+ * An all-zero or non-finite weight vector makes idx the identity and sets
+ * the device flag *degenerate (int32, may be NULL) to 1.
+ * ------------------------------------------------------------------------ */
+int sch_resample(int32_t n_particles, const double *w, const double *u0, const double *cond_ess,
+                 double cond_threshold, int32_t *idx, int32_t *degenerate, void *workspace,
+                 void *stream);
+
+/* sch_gather: dst[j][:] = src[idx[j]][:] for n_rows rows of row_len doubles
+ * (src and dst both [n_rows][row_len], not overlapping).  A row whose index
+ * lies outside [0, n_rows) is left untouched. */
+int sch_gather(int32_t n_rows, int64_t row_len, const int32_t *idx, const double *src,
+               double *dst, void *stream);
+
+/* --------------------------------------------------------------------------
+ * sch_jitter_pcn: n_jitter preconditioned Crank-Nicolson MCMC moves of each
+ * particle's increments at temperature *theta (section 3.1.2, jittering):
+ *   dW' = rho dW + sqrt(1 - rho^2) sqrt(dt) z     (z ~ N(0,1), tag PCN,
+ *         counter (p, cycle * n_steps + n, pair | tag << 24, temper_k << 16 | j))
+ *   rerun the window from (m0, u0) with dW', phi' = sch_loglik of the end;
+ *   accept with probability min(1, exp(theta (phi - phi'))) using the uniform
+ *   of tag ACCEPT, counter (p, cycle, tag << 24, temper_k << 16 | j).
+ * (The paper prints max(1, .); min is the Metropolis rule it describes.)
+ * On acceptance dW, phi, m_end, u_end are replaced.  A proposal whose
+ * window fails is rejected.
+ *   m0, u0      [n][nx] window-start state (read)
+ *   dW          [n][n_steps][n_modes] in/out;  phi [n] in/out
+ *   m_end,u_end [n][nx] in/out: window-end state of the current increments
+ *   n_accept    out [n] or NULL
+ * ------------------------------------------------------------------------ */
+int sch_jitter_pcn(const sch_model *model, const sch_obs *obs, const sch_rng *rng,
+                   int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
+                   double *dW, double *phi, double *m_end, double *u_end, const double *theta,
+                   double rho, int32_t n_jitter, int32_t *n_accept, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Filter cycles (host-driven sequences of the calls above; they synchronise
+ * the stream to read scalars back).
+ *
+ * sch_pf_bootstrap_cycle -- section 3.1.1: draw increments (tag FORECAST),
+ * advance n_steps, multiply the carried weights by the likelihood, and
+ * resample (uniform of tag RESAMPLE, counter (0, cycle, tag << 24, 0)) when
+ * the ESS falls below ess_frac * n; logw [n] carries normalised log-weights
+ * between cycles (zero after a resampling).
+ *
+ * sch_pf_tempered_cycle -- section 3.1.2: draw increments, run the window,
+ * then raise the temperature from 0 to 1 in adaptive steps; after each step
+ * resample the particles (window-start state, increments, phi, window-end
+ * state; uniform counter (0, cycle, tag << 24, k << 16)) and apply n_jitter
+ * pCN moves at the new temperature.  At most max_temper steps
+ * (SCH_E_DEGENERATE beyond).  On return m, u hold the window-end states.
+ * ------------------------------------------------------------------------ */
+int sch_pf_bootstrap_cycle(const sch_model *model, const sch_obs *obs, uint64_t seed,
+                           uint32_t cycle, int32_t n_particles, int32_t n_steps, double ess_frac,
+                           double *m, double *u, double *logw, void *workspace,
+                           sch_cycle_stats *stats, void *stream);
+
+int sch_pf_tempered_cycle(const sch_model *model, const sch_obs *obs, uint64_t seed,
+                          uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                          double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                          int32_t max_temper, double *m, double *u, void *workspace,
+                          sch_cycle_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCH_H */

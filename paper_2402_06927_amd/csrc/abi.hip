@@ -1,0 +1,497 @@
+// abi.hip -- the C-ABI of include/sch.h: argument validation, kernel
+// selection and launch, and the host-driven filter cycles.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "filter.hpp"
+#include "model.hpp"
+
+using namespace sch;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(SCH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHECK_LAUNCH() HIP_TRY(hipGetLastError())
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// Tile choice: NT threads per particle (power of two, 64..512), each holding
+// up to PMAX consecutive nodes in registers.  NT is the smallest power of two
+// with nx / NT <= 8 (64 at least, 512 at most).
+// ---------------------------------------------------------------------------
+struct Tile {
+  int nt, pmax;
+  bool full;
+};
+
+bool pick_tile(int nx, Tile& tl) {
+  const int per = (nx + 7) / 8;
+  int nt = 64;
+  while (nt < per && nt < 512) nt <<= 1;
+  if (nx < nt) return false;
+  const int need = (nx + nt - 1) / nt;
+  if (need > 16) return false;
+  tl.nt = nt;
+  tl.pmax = need <= 4 ? 4 : (need <= 8 ? 8 : 16);
+  tl.full = (nx % nt == 0) && (nx / nt == tl.pmax);
+  return true;
+}
+
+template <class F>
+int with_tile(const Tile& tl, F&& f) {
+#define SCH_CASE(NT_, PM_)                                                       \
+  if (tl.nt == NT_ && tl.pmax == PM_)                                            \
+    return tl.full ? f.template operator()<PM_, NT_, true>()                     \
+                   : f.template operator()<PM_, NT_, false>();
+  SCH_CASE(64, 4)
+  SCH_CASE(64, 8)
+  SCH_CASE(128, 8)
+  SCH_CASE(256, 8)
+  SCH_CASE(512, 8)
+  SCH_CASE(512, 16)
+#undef SCH_CASE
+  return fail(SCH_E_SHAPE, "no kernel for %d threads x %d nodes", tl.nt, tl.pmax);
+}
+
+int check_model(const sch_model* md, Tile& tl) {
+  if (!md) return fail(SCH_E_ARG, "model is NULL");
+  if (!(md->L > 0) || !(md->alpha > 0) || !(md->mu >= 0) || !(md->dt > 0))
+    return fail(SCH_E_ARG, "need L > 0, alpha > 0, mu >= 0, dt > 0");
+  if (md->nx < 64) return fail(SCH_E_SHAPE, "nx = %d < 64", md->nx);
+  if (md->n_modes < 1 || md->n_modes > 64) return fail(SCH_E_ARG, "n_modes = %d", md->n_modes);
+  if (!md->xi) return fail(SCH_E_ARG, "xi is NULL");
+  if (!(md->picard_tol > 0) || md->picard_max < 1)
+    return fail(SCH_E_ARG, "need picard_tol > 0 and picard_max >= 1");
+  if (!pick_tile(md->nx, tl)) return fail(SCH_E_SHAPE, "nx = %d not supported", md->nx);
+  return SCH_OK;
+}
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// Scratch layout shared by the cycle drivers.
+struct CycleWs {
+  double *m0, *u0, *scratch, *dW, *phi, *w, *scal;  // scal: theta, dtheta, ess, u0
+  int *idx, *status, *iters, *degenerate;
+  unsigned long long *cum, *acc;                     // acc: [0] iters, [1] accepts
+};
+
+CycleWs carve_cycle(void* base, int which, int nx, int nq, int n, int ns, size_t* bytes) {
+  Carve c(base);
+  CycleWs w{};
+  const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * ns * nq;
+  if (which == SCH_WS_TEMPERED) {
+    w.m0 = c.take<double>(state);
+    w.u0 = c.take<double>(state);
+  }
+  w.scratch = c.take<double>(state > inc ? state : inc);
+  w.dW = c.take<double>(inc);
+  w.phi = c.take<double>(n);
+  w.w = c.take<double>(n);
+  w.scal = c.take<double>(8);
+  w.idx = c.take<int>(n);
+  w.status = c.take<int>(n);
+  w.iters = c.take<int>(n);
+  w.degenerate = c.take<int>(4);
+  w.cum = c.take<unsigned long long>(n);
+  w.acc = c.take<unsigned long long>(4);
+  if (bytes) *bytes = c.off + 256;
+  return w;
+}
+
+int launch_window(const sch_model& md, const Tile& tl, int n, int n_steps, double* m, double* u,
+                  const double* dW, const double* dLam, int* status, int* iters,
+                  unsigned long long* iters_acc, hipStream_t st) {
+  WindowArgs A;
+  A.P = make_params(md);
+  A.n_steps = n_steps;
+  A.m = m;
+  A.u = u;
+  A.dW = dW;
+  A.dLam = dLam;
+  A.status = status;
+  A.iters = iters;
+  A.iters_acc = iters_acc;
+  return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+    hipLaunchKernelGGL((k_window<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A);
+    CHECK_LAUNCH();
+    return SCH_OK;
+  });
+}
+
+int launch_helm(const sch_model& md, const Tile& tl, int n, const double* in, double* out,
+                int mode, hipStream_t st) {
+  HelmArgs A;
+  A.P = make_params(md);
+  A.in = in;
+  A.out = out;
+  A.mode = mode;
+  return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+    hipLaunchKernelGGL((k_helmholtz<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A);
+    CHECK_LAUNCH();
+    return SCH_OK;
+  });
+}
+
+int check_obs(const sch_obs* ob) {
+  if (!ob || ob->n_obs < 1 || !ob->y || !ob->sigma) return fail(SCH_E_ARG, "bad observations");
+  return SCH_OK;
+}
+
+int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t seed,
+                  uint32_t cycle, uint32_t temper_k, int n, int n_steps, const double* m0,
+                  const double* u0, double* dW, double* phi, double* m_end, double* u_end,
+                  const double* theta, double rho, int n_jitter, int* n_accept,
+                  unsigned long long* accept_acc, unsigned long long* iters_acc,
+                  hipStream_t st) {
+  JitterArgs A;
+  A.P = make_params(md);
+  A.n_steps = n_steps;
+  A.m0 = m0;
+  A.u0 = u0;
+  A.dW = dW;
+  A.phi = phi;
+  A.m_end = m_end;
+  A.u_end = u_end;
+  A.theta = theta;
+  A.rho = rho;
+  A.n_jitter = n_jitter;
+  A.n_accept = n_accept;
+  A.accept_acc = accept_acc;
+  A.iters_acc = iters_acc;
+  A.n_obs = ob.n_obs;
+  A.y = ob.y;
+  A.sigma = ob.sigma;
+  A.seed = seed;
+  A.cycle = cycle;
+  A.temper_k = temper_k;
+  const size_t dyn = 2 * sizeof(double) * static_cast<size_t>(n_steps) * md.n_modes;
+  if (dyn > 32768) return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel");
+  return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+    hipLaunchKernelGGL((k_jitter<PM, NT, FULL>), dim3(n), dim3(NT), dyn, st, A);
+    CHECK_LAUNCH();
+    return SCH_OK;
+  });
+}
+
+int grid_for(int64_t work, int block) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<int>(g);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* sch_last_error(void) { return g_err.c_str(); }
+
+int sch_version(void) { return 100; }
+
+size_t sch_workspace_bytes(int32_t which, const sch_model* model, int32_t n, int32_t n_steps) {
+  if (n < 1) return 0;
+  if (which == SCH_WS_RESAMPLE) return static_cast<size_t>(n) * sizeof(unsigned long long) + 256;
+  if (!model) return 0;
+  size_t bytes = 0;
+  carve_cycle(nullptr, which, model->nx, model->n_modes, n, n_steps > 0 ? n_steps : 1, &bytes);
+  return bytes;
+}
+
+int sch_draw_increments(const sch_rng* rng, uint32_t tag, int32_t n, int32_t n_steps,
+                        int32_t n_modes, double dt, double* dW, void* stream) {
+  if (!rng || !dW || n < 1 || n_steps < 1 || n_modes < 1 || !(dt > 0) || tag > 255)
+    return fail(SCH_E_ARG, "bad arguments to sch_draw_increments");
+  const int64_t work = static_cast<int64_t>(n) * n_steps * ((n_modes + 1) / 2);
+  hipLaunchKernelGGL(k_draw_increments, dim3(grid_for(work, 256)), dim3(256), 0, S(stream),
+                     rng->seed, rng->cycle * static_cast<uint32_t>(n_steps), tag,
+                     rng->temper_k << 16, n, n_steps, n_modes, std::sqrt(dt), dW);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_philox_blocks(uint64_t seed, int32_t n, const uint32_t* ctr, uint32_t* out,
+                      void* stream) {
+  if (n < 1 || !ctr || !out) return fail(SCH_E_ARG, "bad arguments to sch_philox_blocks");
+  hipLaunchKernelGGL(k_philox_blocks, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), seed, n,
+                     ctr, out);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_velocity(const sch_model* md, int32_t n, const double* m, double* u, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (n < 1 || !m || !u || m == u) return fail(SCH_E_ARG, "bad arguments to sch_velocity");
+  return launch_helm(*md, tl, n, m, u, 0, S(stream));
+}
+
+int sch_init_momentum(const sch_model* md, int32_t n, const double* u, double* m, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (n < 1 || !m || !u || m == u) return fail(SCH_E_ARG, "bad arguments to sch_init_momentum");
+  return launch_helm(*md, tl, n, u, m, 1, S(stream));
+}
+
+int sch_ensemble_step(const sch_model* md, int32_t n, int32_t n_steps, double* m, double* u,
+                      const double* dW, const double* dLam, int32_t* status, int32_t* iters,
+                      void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (n < 1 || n_steps < 0 || !m || !u || !dW) return fail(SCH_E_ARG, "bad arguments to sch_ensemble_step");
+  if (n_steps == 0) return SCH_OK;
+  return launch_window(*md, tl, n, n_steps, m, u, dW, dLam, status, iters, nullptr, S(stream));
+}
+
+int sch_observe(const sch_model* md, int32_t n_obs, int32_t n, const double* u, double* out,
+                void* stream) {
+  if (!md || md->nx < 2 || n_obs < 1 || n < 1 || !u || !out) return fail(SCH_E_ARG, "bad arguments to sch_observe");
+  hipLaunchKernelGGL(k_observe, dim3(n), dim3(kWave), 0, S(stream), md->nx, n_obs, u, out);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_loglik(const sch_model* md, const sch_obs* ob, int32_t n, const double* u, double* phi,
+               void* stream) {
+  if (!md || md->nx < 2 || n < 1 || !u || !phi) return fail(SCH_E_ARG, "bad arguments to sch_loglik");
+  if (int rc = check_obs(ob)) return rc;
+  hipLaunchKernelGGL(k_loglik, dim3(n), dim3(kWave), 0, S(stream), md->nx, ob->n_obs, u, ob->y,
+                     ob->sigma, phi);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_temper_ess(int32_t n, const double* phi, const double* logw_extra, double* theta,
+                   double thr, int32_t n_bisect, double* dtheta, double* w, double* logw_out,
+                   double* ess, void* stream) {
+  if (n < 1 || n > 65536 || !phi || !theta || !dtheta || !w || !ess || n_bisect < 0 ||
+      n_bisect > 200)
+    return fail(SCH_E_ARG, "bad arguments to sch_temper_ess");
+  hipLaunchKernelGGL(k_temper, dim3(1), dim3(kTB), 0, S(stream), n, phi, logw_extra, theta, thr,
+                     n_bisect, dtheta, w, logw_out, ess);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_resample(int32_t n, const double* w, const double* u0, const double* cond_ess,
+                 double cond_thr, int32_t* idx, int32_t* degenerate, void* workspace,
+                 void* stream) {
+  if (n < 1 || n > (1 << 24) || !w || !u0 || !idx || !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_resample");
+  hipLaunchKernelGGL(k_resample, dim3(1), dim3(kTB), 0, S(stream), n, w, u0, cond_ess, cond_thr,
+                     idx, degenerate, static_cast<unsigned long long*>(workspace));
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_gather(int32_t n_rows, int64_t row_len, const int32_t* idx, const double* src,
+               double* dst, void* stream) {
+  if (n_rows < 1 || n_rows > 65535 || row_len < 1 || !idx || !src || !dst || src == dst)
+    return fail(SCH_E_ARG, "bad arguments to sch_gather");
+  const int gx = static_cast<int>(std::min<int64_t>((row_len + 255) / 256, 64));
+  hipLaunchKernelGGL(k_gather, dim3(gx, n_rows), dim3(256), 0, S(stream), n_rows, row_len, idx,
+                     src, dst);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_jitter_pcn(const sch_model* md, const sch_obs* ob, const sch_rng* rng, int32_t n,
+                   int32_t n_steps, const double* m0, const double* u0, double* dW, double* phi,
+                   double* m_end, double* u_end, const double* theta, double rho,
+                   int32_t n_jitter, int32_t* n_accept, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (!rng || n < 1 || n_steps < 1 || !m0 || !u0 || !dW || !phi || !m_end || !u_end || !theta ||
+      !(rho >= 0 && rho <= 1) || n_jitter < 0)
+    return fail(SCH_E_ARG, "bad arguments to sch_jitter_pcn");
+  if (n_jitter == 0) return SCH_OK;
+  return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
+                       dW, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
+                       S(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Filter cycles.
+// ---------------------------------------------------------------------------
+int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
+                           int32_t n, int32_t n_steps, double ess_frac, double* m, double* u,
+                           double* logw, void* workspace, sch_cycle_stats* stats,
+                           void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !logw || !workspace || !stats)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_bootstrap_cycle");
+  hipStream_t st = S(stream);
+  const int nx = md->nx, Q = md->n_modes;
+  CycleWs W = carve_cycle(workspace, SCH_WS_BOOTSTRAP, nx, Q, n, n_steps, nullptr);
+  *stats = sch_cycle_stats{};
+  sch_rng rg{seed, cycle, 0};
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
+  if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, Q, md->dt, W.dW, stream))
+    return rc;
+  if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
+    return rc;
+  if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
+  if (int rc = sch_temper_ess(n, W.phi, logw, W.scal + 0, 0.0, 0, W.scal + 1, W.w, logw,
+                              W.scal + 2, stream))
+    return rc;
+  double ess = 0.0;
+  unsigned long long its = 0;
+  HIP_TRY(hipMemcpyAsync(&ess, W.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&its, W.acc, sizeof its, hipMemcpyDeviceToHost, st));
+  std::vector<int> status(n);
+  HIP_TRY(hipMemcpyAsync(status.data(), W.status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  stats->ess = ess;
+  stats->picard_iters = static_cast<int64_t>(its);
+  stats->particle_steps = static_cast<int64_t>(n) * n_steps;
+  int rc = SCH_OK;
+  for (int p = 0; p < n && rc == SCH_OK; ++p)
+    if (status[p] != SCH_OK) rc = status[p];
+  if (!(ess > 0.0)) {
+    stats->status = SCH_E_DEGENERATE;
+    return fail(SCH_E_DEGENERATE, "all weights vanished in cycle %u", cycle);
+  }
+  if (ess < ess_frac * n) {
+    hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
+                       SCH_TAG_RESAMPLE << 24, 0u, W.scal + 3);
+    if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
+      return r2;
+    if (int r2 = sch_gather(n, nx, W.idx, m, W.scratch, stream)) return r2;
+    HIP_TRY(hipMemcpyAsync(m, W.scratch, sizeof(double) * n * nx, hipMemcpyDeviceToDevice, st));
+    if (int r2 = sch_gather(n, nx, W.idx, u, W.scratch, stream)) return r2;
+    HIP_TRY(hipMemcpyAsync(u, W.scratch, sizeof(double) * n * nx, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, logw, 0.0, int64_t(n));
+    CHECK_LAUNCH();
+    stats->resampled = 1;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  stats->status = rc;
+  if (rc != SCH_OK) return fail(rc, "a particle failed in cycle %u", cycle);
+  return SCH_OK;
+}
+
+int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
+                          int32_t n, int32_t n_steps, double thr, int32_t n_bisect, double rho,
+                          int32_t n_jitter, int32_t max_temper, double* m, double* u,
+                          void* workspace, sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !workspace || !stats || n_bisect < 0 ||
+      max_temper < 1 || !(rho >= 0 && rho <= 1) || n_jitter < 0)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_tempered_cycle");
+  hipStream_t st = S(stream);
+  const int nx = md->nx, Q = md->n_modes;
+  const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
+  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, nullptr);
+  *stats = sch_cycle_stats{};
+  sch_rng rg{seed, cycle, 0};
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
+  HIP_TRY(hipMemcpyAsync(W.m0, m, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(W.u0, u, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+  if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, Q, md->dt, W.dW, stream))
+    return rc;
+  if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
+    return rc;
+  if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
+  int k = 0, rc = SCH_OK;
+  double theta = 0.0, ess = 0.0;
+  int64_t psteps = static_cast<int64_t>(n) * n_steps;
+  while (theta < 1.0) {
+    if (k >= max_temper) {
+      rc = SCH_E_DEGENERATE;
+      fail(rc, "tempering did not reach theta = 1 in %d steps", max_temper);
+      break;
+    }
+    if (int r2 = sch_temper_ess(n, W.phi, nullptr, W.scal + 0, thr, n_bisect, W.scal + 1, W.w,
+                                nullptr, W.scal + 2, stream))
+      return r2;
+    hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
+                       SCH_TAG_RESAMPLE << 24, static_cast<uint32_t>(k) << 16, W.scal + 3);
+    if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
+      return r2;
+    double* fields[4] = {W.m0, W.u0, m, u};
+    for (double* f : fields) {
+      if (int r2 = sch_gather(n, nx, W.idx, f, W.scratch, stream)) return r2;
+      HIP_TRY(hipMemcpyAsync(f, W.scratch, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+    }
+    if (int r2 = sch_gather(n, static_cast<int64_t>(n_steps) * Q, W.idx, W.dW, W.scratch, stream))
+      return r2;
+    HIP_TRY(hipMemcpyAsync(W.dW, W.scratch, sizeof(double) * inc, hipMemcpyDeviceToDevice, st));
+    if (int r2 = sch_gather(n, 1, W.idx, W.phi, W.scratch, stream)) return r2;
+    HIP_TRY(hipMemcpyAsync(W.phi, W.scratch, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    if (n_jitter > 0) {
+      if (int r2 = launch_jitter(*md, tl, *ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
+                                 W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
+                                 nullptr, W.acc + 1, W.acc, st))
+        return r2;
+      psteps += static_cast<int64_t>(n) * n_steps * n_jitter;
+    }
+    HIP_TRY(hipMemcpyAsync(&theta, W.scal + 0, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&ess, W.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ++k;
+    if (!(ess > 0.0)) {
+      rc = SCH_E_DEGENERATE;
+      fail(rc, "all weights vanished in cycle %u", cycle);
+      break;
+    }
+  }
+  unsigned long long acc[2] = {0, 0};
+  std::vector<int> status(n);
+  HIP_TRY(hipMemcpyAsync(acc, W.acc, sizeof acc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(status.data(), W.status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  stats->ess = ess;
+  stats->n_temper = k;
+  stats->picard_iters = static_cast<int64_t>(acc[0]);
+  stats->n_accept = static_cast<int64_t>(acc[1]);
+  stats->particle_steps = psteps;
+  for (int p = 0; p < n && rc == SCH_OK; ++p)
+    if (status[p] != SCH_OK) {
+      rc = status[p];
+      fail(rc, "a particle failed in the forecast of cycle %u", cycle);
+    }
+  stats->status = rc;
+  return rc;
+}
+
+}  // extern "C"

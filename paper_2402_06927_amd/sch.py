@@ -1,0 +1,303 @@
+"""ctypes binding of the C-ABI in include/sch.h.
+
+Argument marshalling only: every function takes torch tensors that live on
+the GPU, checks dtype / contiguity / device, and passes raw device pointers
+and the current HIP stream to ``libsch.so``.  All arithmetic of the method
+runs in the library's kernels.  There is no fallback: if the library is not
+built, or a tensor is not on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsch.so")
+_lib = None
+
+SCH_OK = 0
+SCH_E_ARG = -1
+SCH_E_SHAPE = -2
+SCH_E_NONCONVERGED = -3
+SCH_E_NONFINITE = -4
+SCH_E_DEGENERATE = -5
+SCH_E_HIP = -6
+
+TAG_INIT, TAG_FORECAST, TAG_PCN, TAG_ACCEPT, TAG_RESAMPLE, TAG_OBS, TAG_NUDGE = range(7)
+WS_RESAMPLE, WS_BOOTSTRAP, WS_TEMPERED = 1, 2, 3
+
+
+class SchError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sch error {code}: {msg}")
+        self.code = code
+
+
+_vp = C.c_void_p
+
+
+class SchModelC(C.Structure):
+    _fields_ = [
+        ("L", C.c_double), ("alpha", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
+        ("nx", C.c_int32), ("n_modes", C.c_int32), ("xi", _vp),
+        ("picard_tol", C.c_double), ("picard_max", C.c_int32),
+    ]
+
+
+class SchObsC(C.Structure):
+    _fields_ = [("n_obs", C.c_int32), ("y", _vp), ("sigma", _vp)]
+
+
+class SchRngC(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("cycle", C.c_uint32), ("temper_k", C.c_uint32)]
+
+
+class SchCycleStats(C.Structure):
+    _fields_ = [
+        ("ess", C.c_double), ("resampled", C.c_int32), ("n_temper", C.c_int32),
+        ("picard_iters", C.c_int64), ("n_accept", C.c_int64), ("particle_steps", C.c_int64),
+        ("status", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def lib():
+    """Load libsch.so (built in place by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _declare(L):
+    i32, u32, u64, i64, f64 = C.c_int32, C.c_uint32, C.c_uint64, C.c_int64, C.c_double
+    M, O, R = C.POINTER(SchModelC), C.POINTER(SchObsC), C.POINTER(SchRngC)
+    ST = C.POINTER(SchCycleStats)
+    sig = {
+        "sch_last_error": (C.c_char_p, []),
+        "sch_version": (C.c_int, []),
+        "sch_workspace_bytes": (C.c_size_t, [i32, M, i32, i32]),
+        "sch_draw_increments": (C.c_int, [R, u32, i32, i32, i32, f64, _vp, _vp]),
+        "sch_philox_blocks": (C.c_int, [u64, i32, _vp, _vp, _vp]),
+        "sch_velocity": (C.c_int, [M, i32, _vp, _vp, _vp]),
+        "sch_init_momentum": (C.c_int, [M, i32, _vp, _vp, _vp]),
+        "sch_ensemble_step": (C.c_int, [M, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "sch_observe": (C.c_int, [M, i32, i32, _vp, _vp, _vp]),
+        "sch_loglik": (C.c_int, [M, O, i32, _vp, _vp, _vp]),
+        "sch_temper_ess": (C.c_int, [i32, _vp, _vp, _vp, f64, i32, _vp, _vp, _vp, _vp, _vp]),
+        "sch_resample": (C.c_int, [i32, _vp, _vp, _vp, f64, _vp, _vp, _vp, _vp]),
+        "sch_gather": (C.c_int, [i32, i64, _vp, _vp, _vp, _vp]),
+        "sch_jitter_pcn": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, f64,
+                                     i32, _vp, _vp]),
+        "sch_pf_bootstrap_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, _vp, _vp, _vp, _vp,
+                                             ST, _vp]),
+        "sch_pf_tempered_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
+                                            _vp, _vp, _vp, ST, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def exported_names():
+    """Names of the C-ABI entry points this binding declares."""
+    return [
+        "sch_last_error", "sch_version", "sch_workspace_bytes", "sch_draw_increments",
+        "sch_philox_blocks",
+        "sch_velocity", "sch_init_momentum", "sch_ensemble_step", "sch_observe", "sch_loglik",
+        "sch_temper_ess", "sch_resample", "sch_gather", "sch_jitter_pcn",
+        "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle",
+    ]
+
+
+def _check(rc: int):
+    if rc != SCH_OK:
+        raise SchError(rc, lib().sch_last_error().decode())
+
+
+def _dev(t: torch.Tensor | None, dtype=torch.float64, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Model:
+    """SCH model parameters (section 2) with the noise-mode table on the GPU."""
+    L: float
+    alpha: float
+    mu: float
+    dt: float
+    xi: torch.Tensor  # [n_modes][nx] float64 on the GPU
+    picard_tol: float = 1e-13
+    picard_max: int = 50
+
+    @property
+    def nx(self) -> int:
+        return int(self.xi.shape[1])
+
+    @property
+    def n_modes(self) -> int:
+        return int(self.xi.shape[0])
+
+    def c(self) -> SchModelC:
+        return SchModelC(self.L, self.alpha, self.mu, self.dt, self.nx, self.n_modes,
+                         _dev(self.xi, name="xi"), self.picard_tol, self.picard_max)
+
+
+@dataclass
+class Obs:
+    y: torch.Tensor      # [n_obs]
+    sigma: torch.Tensor  # [n_obs]
+
+    def c(self) -> SchObsC:
+        return SchObsC(int(self.y.numel()), _dev(self.y, name="y"), _dev(self.sigma, name="sigma"))
+
+
+def workspace_bytes(which: int, model: Model | None, n_particles: int, n_steps: int = 0) -> int:
+    mc = model.c() if model is not None else None
+    return int(lib().sch_workspace_bytes(which, C.byref(mc) if mc is not None else None,
+                                         n_particles, n_steps))
+
+
+def workspace(which: int, model: Model | None, n_particles: int, n_steps: int = 0,
+              device="cuda") -> torch.Tensor:
+    nb = workspace_bytes(which, model, n_particles, n_steps)
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------- calls
+def sch_draw_increments(seed: int, cycle: int, temper_k: int, tag: int, dW: torch.Tensor,
+                        dt: float):
+    n, s, q = dW.shape
+    r = SchRngC(seed, cycle, temper_k)
+    _check(lib().sch_draw_increments(C.byref(r), tag, n, s, q, dt, _dev(dW, name="dW"),
+                                     _stream()))
+
+
+def sch_philox_blocks(seed: int, ctr: torch.Tensor, out: torch.Tensor):
+    """ctr, out: int32 tensors [n][4] holding uint32 bit patterns."""
+    _check(lib().sch_philox_blocks(seed, ctr.shape[0], _dev(ctr, torch.int32, "ctr"),
+                                   _dev(out, torch.int32, "out"), _stream()))
+
+
+def sch_velocity(model: Model, m: torch.Tensor, u: torch.Tensor):
+    mc = model.c()
+    _check(lib().sch_velocity(C.byref(mc), m.shape[0], _dev(m, name="m"), _dev(u, name="u"),
+                              _stream()))
+
+
+def sch_init_momentum(model: Model, u: torch.Tensor, m: torch.Tensor):
+    mc = model.c()
+    _check(lib().sch_init_momentum(C.byref(mc), u.shape[0], _dev(u, name="u"), _dev(m, name="m"),
+                                   _stream()))
+
+
+def sch_ensemble_step(model: Model, m: torch.Tensor, u: torch.Tensor, dW: torch.Tensor,
+                      dLambda: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                      iters: torch.Tensor | None = None):
+    mc = model.c()
+    n, s = dW.shape[0], dW.shape[1]
+    _check(lib().sch_ensemble_step(C.byref(mc), n, s, _dev(m, name="m"), _dev(u, name="u"),
+                                   _dev(dW, name="dW"), _dev(dLambda, name="dLambda"),
+                                   _dev(status, torch.int32, "status"),
+                                   _dev(iters, torch.int32, "iters"), _stream()))
+
+
+def sch_observe(model: Model, u: torch.Tensor, out: torch.Tensor):
+    mc = model.c()
+    _check(lib().sch_observe(C.byref(mc), out.shape[-1], u.shape[0], _dev(u, name="u"),
+                             _dev(out, name="out"), _stream()))
+
+
+def sch_loglik(model: Model, obs: Obs, u: torch.Tensor, phi: torch.Tensor):
+    mc, oc = model.c(), obs.c()
+    _check(lib().sch_loglik(C.byref(mc), C.byref(oc), u.shape[0], _dev(u, name="u"),
+                            _dev(phi, name="phi"), _stream()))
+
+
+def sch_temper_ess(phi: torch.Tensor, theta: torch.Tensor, ess_threshold: float, n_bisect: int,
+                   dtheta: torch.Tensor, w: torch.Tensor, ess: torch.Tensor,
+                   logw_extra: torch.Tensor | None = None, logw_out: torch.Tensor | None = None):
+    _check(lib().sch_temper_ess(phi.numel(), _dev(phi, name="phi"),
+                                _dev(logw_extra, name="logw_extra"), _dev(theta, name="theta"),
+                                ess_threshold, n_bisect, _dev(dtheta, name="dtheta"),
+                                _dev(w, name="w"), _dev(logw_out, name="logw_out"),
+                                _dev(ess, name="ess"), _stream()))
+
+
+def sch_resample(w: torch.Tensor, u0: torch.Tensor, idx: torch.Tensor, workspace: torch.Tensor,
+                 cond_ess: torch.Tensor | None = None, cond_threshold: float = 0.0,
+                 degenerate: torch.Tensor | None = None):
+    _check(lib().sch_resample(w.numel(), _dev(w, name="w"), _dev(u0, name="u0"),
+                              _dev(cond_ess, name="cond_ess"), cond_threshold,
+                              _dev(idx, torch.int32, "idx"), _dev(degenerate, torch.int32,
+                                                                 "degenerate"),
+                              _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_gather(idx: torch.Tensor, src: torch.Tensor, dst: torch.Tensor):
+    n = idx.numel()
+    row = src.numel() // src.shape[0]
+    _check(lib().sch_gather(n, row, _dev(idx, torch.int32, "idx"), _dev(src, name="src"),
+                            _dev(dst, name="dst"), _stream()))
+
+
+def sch_jitter_pcn(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
+                   m0: torch.Tensor, u0: torch.Tensor, dW: torch.Tensor, phi: torch.Tensor,
+                   m_end: torch.Tensor, u_end: torch.Tensor, theta: torch.Tensor, rho: float,
+                   n_jitter: int, n_accept: torch.Tensor | None = None):
+    mc, oc = model.c(), obs.c()
+    r = SchRngC(seed, cycle, temper_k)
+    n, s = dW.shape[0], dW.shape[1]
+    _check(lib().sch_jitter_pcn(C.byref(mc), C.byref(oc), C.byref(r), n, s, _dev(m0, name="m0"),
+                                _dev(u0, name="u0"), _dev(dW, name="dW"), _dev(phi, name="phi"),
+                                _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
+                                _dev(theta, name="theta"), rho, n_jitter,
+                                _dev(n_accept, torch.int32, "n_accept"), _stream()))
+
+
+def sch_pf_bootstrap_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
+                           u: torch.Tensor, logw: torch.Tensor, n_steps: int, ess_frac: float,
+                           workspace: torch.Tensor) -> dict:
+    mc, oc = model.c(), obs.c()
+    st = SchCycleStats()
+    _check(lib().sch_pf_bootstrap_cycle(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0],
+                                        n_steps, ess_frac, _dev(m, name="m"), _dev(u, name="u"),
+                                        _dev(logw, name="logw"),
+                                        _dev(workspace, torch.uint8, "workspace"), C.byref(st),
+                                        _stream()))
+    return st.as_dict()
+
+
+def sch_pf_tempered_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
+                          u: torch.Tensor, n_steps: int, ess_threshold: float, n_bisect: int,
+                          rho: float, n_jitter: int, max_temper: int,
+                          workspace: torch.Tensor) -> dict:
+    mc, oc = model.c(), obs.c()
+    st = SchCycleStats()
+    _check(lib().sch_pf_tempered_cycle(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0],
+                                       n_steps, ess_threshold, n_bisect, rho, n_jitter,
+                                       max_temper, _dev(m, name="m"), _dev(u, name="u"),
+                                       _dev(workspace, torch.uint8, "workspace"), C.byref(st),
+                                       _stream()))
+    return st.as_dict()
