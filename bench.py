@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the tempered + jittered SCH particle filter on one MI355X.
+
+One step = one assimilation cycle of the whole hot path on the GPU: forecast
+noise draw, forecast window (40 implicit-midpoint steps per particle),
+likelihood, then adaptive tempering steps, each with ESS bisection, systematic
+resampling, particle gathers and 5 pCN jitter moves (each a full rerun of the
+window).  Workload: Nx = 4096 nodes, 1024 particles, 8 noise modes, 40 steps
+per window, 256 observations (sigma 0.02), ESS threshold N/2, rho = 0.99;
+synthetic twin-experiment data (truth from the same model with seed + 1).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# FP64 vector peak of MI355X (TFLOP/s) and HBM peak (GB/s).
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic floating-point operations per grid node:
+# per implicit-solve iteration: dv (2) + rows of A (7) + tridiagonal
+# factor-and-solve (9) + m* (1) + mass product (4) + Helmholtz solve with
+# stored factors (5) + convergence test (3) = 31; per step: noise
+# assembly (2 Q + 1) and the mass product of the right-hand side (4).
+FLOPS_PER_NODE_ITER = 31
+def flops_per_node_step(n_modes: int) -> int:
+    return 2 * n_modes + 5
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, u_start, m_start, n_threads: int, psteps_per_cycle: float):
+    """Oracle timed on the host: one forecast window of the whole ensemble
+    (the same 1024 particles and 40 steps), scaled to cycles/s with the
+    particle-steps per cycle measured on the GPU."""
+    import oracle as O
+
+    xi = __import__("paper_2402_06927_amd.workloads", fromlist=["x"]).mode_table(
+        wl.L, wl.nx, wl.n_modes, wl.mode_amp)
+    om = O.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
+                 picard_tol=wl.picard_tol, picard_max=wl.picard_max)
+    n = u_start.shape[0]
+    dW = O.draw_increments(wl.seed, n, wl.n_steps, wl.n_modes, 0, O.TAG_FORECAST, 0, wl.dt)
+    t0 = time.perf_counter()
+    worst, _, _, _, _ = O.ensemble_window(om, m_start, u_start, dW, n_threads=n_threads)
+    dt = time.perf_counter() - t0
+    psteps = n * wl.n_steps
+    ps_rate = psteps / dt
+    return {
+        "value": ps_rate / psteps_per_cycle,
+        "unit": "cycles/s",
+        "cores": n_threads,
+        "kind": "oracle",
+        "sample": (f"one forecast window of all {n} particles x {wl.n_steps} steps at Nx={wl.nx} "
+                   f"({psteps} particle-steps, {dt:.1f} s, {ps_rate:.1f} particle-steps/s), "
+                   f"scaled by the {psteps_per_cycle:.0f} particle-steps per cycle measured on "
+                   f"the GPU; oracle status {worst}"),
+        "particle_steps_per_s": ps_rate,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed assimilation cycles")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed cycles before timing")
+    ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=None)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2402_06927_amd import sch
+    from paper_2402_06927_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    sch.lib()
+    wl = W.TEMPERED_4096
+    if args.particles:
+        wl = wl.scaled(n_particles=args.particles)
+    dev = "cuda"
+    n, nx, Q, S = wl.n_particles, wl.nx, wl.n_modes, wl.n_steps
+    n_cycles = args.warmup + args.steps
+    log(f"bench: {wl.name} n={n} nx={nx} Q={Q} S={S} cycles={args.warmup}+{args.steps}")
+
+    xi = torch.tensor(W.mode_table(wl.L, nx, Q, wl.mode_amp), device=dev)
+    model = sch.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
+                      picard_tol=wl.picard_tol, picard_max=wl.picard_max)
+    u0 = W.initial_velocity(wl, n, wl.seed)
+    u = torch.tensor(u0, device=dev)
+    m = torch.empty_like(u)
+    sch.sch_init_momentum(model, u, m)
+
+    # truth run (seed + 1) and observations for every cycle
+    ts = W.truth_seed(wl)
+    ut = torch.tensor(W.initial_velocity(wl, 1, ts), device=dev)
+    mt = torch.empty_like(ut)
+    sch.sch_init_momentum(model, ut, mt)
+    z = torch.tensor(W.obs_noise(wl, ts, n_cycles), device=dev)
+    dWt = torch.empty((1, S, Q), dtype=torch.float64, device=dev)
+    yobs = torch.empty((n_cycles, wl.n_obs), dtype=torch.float64, device=dev)
+    for c in range(n_cycles):
+        sch.sch_draw_increments(ts, c, 0, sch.TAG_FORECAST, dWt, wl.dt)
+        sch.sch_ensemble_step(model, mt, ut, dWt)
+        sch.sch_observe(model, ut, yobs[c:c + 1])
+    yobs += wl.sigma_obs * z
+    sigma = torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64, device=dev)
+    ws = sch.workspace(sch.WS_TEMPERED, model, n, S)
+    m_cpu0, u_cpu0 = None, None
+
+    def run_cycle(c):
+        obs = sch.Obs(yobs[c].contiguous(), sigma)
+        return sch.sch_pf_tempered_cycle(model, obs, wl.seed, c, m, u, S, wl.ess_threshold,
+                                         wl.n_bisect, wl.rho, wl.n_jitter, wl.max_temper, ws)
+
+    for c in range(args.warmup):
+        st = run_cycle(c)
+        log(f"warmup cycle {c}: tempering steps {st['n_temper']}")
+    torch.cuda.synchronize()
+    # the CPU baseline starts from the ensemble of the first timed cycle
+    m_cpu0 = m.cpu().numpy().copy()
+    u_cpu0 = u.cpu().numpy().copy()
+
+    sch.sch_timing_reset()
+    sch.sch_timing_enable(True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(args.warmup, n_cycles):
+        st = run_cycle(c)
+        stats.append(st)
+        log(f"cycle {c}: tempering steps {st['n_temper']}, ess {st['ess']:.1f}, "
+            f"accept {st['n_accept']}, particle-steps {st['particle_steps']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sch.sch_timing_enable(False)
+    tim = sch.sch_timing_read()
+
+    psteps = sum(s["particle_steps"] for s in stats)
+    iters = sum(s["picard_iters"] for s in stats)
+    n_temper = [s["n_temper"] for s in stats]
+    cycles_per_s = args.steps / elapsed
+    psteps_per_s = psteps / elapsed
+
+    # dominant kernel: fused pCN jitter (5 window reruns per launch)
+    jt = tim["jitter"]
+    j_launches = max(jt["launches"], 1)
+    j_psteps = j_launches * n * S * wl.n_jitter
+    j_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"] + flops_per_node_step(Q) * j_psteps)
+    j_ms = jt["ms"] / j_launches
+    j_tflops = (j_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
+    roofline = {
+        "bound": "alu",
+        "achieved": round(j_tflops, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(j_tflops / PEAK_FP64_TFLOPS, 4),
+        "traffic": None,
+        "kernel": "k_jitter (fused pCN proposal + window rerun + likelihood + accept)",
+        "avg_launch_ms": round(j_ms, 3),
+        "algorithmic_flops_per_launch": j_flops / j_launches,
+        "picard_iters_per_step": jt["iters"] / max(j_psteps, 1),
+    }
+
+    out = {
+        "metric": "assimilation cycles/sec + particle-steps/sec at N=1024, Nx=4096, vs plain",
+        "value": round(cycles_per_s, 4),
+        "unit": "cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "filter": "tempered+jittered", "nx": nx, "n_particles": n,
+            "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs, "sigma_obs": wl.sigma_obs,
+            "ess_threshold": wl.ess_threshold, "n_bisect": wl.n_bisect,
+            "n_jitter": wl.n_jitter, "rho": wl.rho,
+        },
+        "particle_steps_per_s": round(psteps_per_s, 1),
+        "tempering_steps_per_cycle": n_temper,
+        "picard_iters_per_step": round(iters / max(psteps, 1), 3),
+        "kernel_ms": {k: round(v["ms"], 3) for k, v in tim.items()},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(f"cpu baseline: oracle, {threads} threads ...")
+        cb = cpu_baseline(wl, u_cpu0, m_cpu0, threads, psteps / args.steps)
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb['particle_steps_per_s']:.1f} particle-steps/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -265,6 +265,26 @@ int sch_pf_tempered_cycle(const sch_model *model, const sch_obs *obs, uint64_t s
                           int32_t max_temper, double *m, double *u, void *workspace,
                           sch_cycle_stats *stats, void *stream);
 
+/* --------------------------------------------------------------------------
+ * Kernel timing for benchmarks.  While enabled (on != 0), the cycle drivers
+ * bracket every launch with HIP events on the launch stream and, at their
+ * synchronisation points, accumulate the elapsed time per kernel class.
+ * sch_timing_read copies the totals: ms[k], launches[k] and iters[k] (the
+ * implicit-solve iterations done by that class, where it has them) for
+ * k < SCH_TK_COUNT; sch_timing_reset zeroes them.  Process-global, not
+ * thread-safe: meant for one benchmarking thread.
+ * ------------------------------------------------------------------------ */
+#define SCH_TK_WINDOW 0   /* forecast window kernel          */
+#define SCH_TK_JITTER 1   /* fused pCN jitter kernel         */
+#define SCH_TK_TEMPER 2   /* weights / ESS / tempering       */
+#define SCH_TK_RESAMPLE 3 /* systematic resampling           */
+#define SCH_TK_GATHER 4   /* particle copies after resampling */
+#define SCH_TK_OTHER 5    /* likelihood, draws, fills        */
+#define SCH_TK_COUNT 6
+int sch_timing_enable(int on);
+int sch_timing_reset(void);
+int sch_timing_read(double *ms, int64_t *launches, int64_t *iters);
+
 #ifdef __cplusplus
 }
 #endif

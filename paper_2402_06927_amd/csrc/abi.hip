@@ -213,10 +213,88 @@ int grid_for(int64_t work, int block) {
   return static_cast<int>(g);
 }
 
+// Event-based timing of kernel classes (see sch_timing_enable).
+struct Timing {
+  bool on = false;
+  double ms[SCH_TK_COUNT] = {};
+  long long launches[SCH_TK_COUNT] = {};
+  long long iters[SCH_TK_COUNT] = {};
+  struct Pend {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pend> pend;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (pool.empty()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+};
+Timing g_tm;
+
+struct TimedScope {
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  TimedScope(int k, hipStream_t s) : kind(k), st(s) {
+    if (g_tm.on && (a = g_tm.get())) (void)hipEventRecord(a, st);
+  }
+  ~TimedScope() {
+    if (!a) return;
+    hipEvent_t b = g_tm.get();
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    g_tm.pend.push_back({kind, a, b});
+  }
+};
+
+// Called after a stream synchronisation: all pending events have completed.
+void timing_flush() {
+  for (auto& p : g_tm.pend) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_tm.ms[p.kind] += ms;
+      g_tm.launches[p.kind] += 1;
+    }
+    g_tm.pool.push_back(p.a);
+    g_tm.pool.push_back(p.b);
+  }
+  g_tm.pend.clear();
+}
+
 }  // namespace
 
 // ===========================================================================
 extern "C" {
+
+int sch_timing_enable(int on) {
+  g_tm.on = on != 0;
+  return SCH_OK;
+}
+
+int sch_timing_reset(void) {
+  for (int k = 0; k < SCH_TK_COUNT; ++k) {
+    g_tm.ms[k] = 0.0;
+    g_tm.launches[k] = 0;
+    g_tm.iters[k] = 0;
+  }
+  return SCH_OK;
+}
+
+int sch_timing_read(double* ms, int64_t* launches, int64_t* iters) {
+  for (int k = 0; k < SCH_TK_COUNT; ++k) {
+    if (ms) ms[k] = g_tm.ms[k];
+    if (launches) launches[k] = g_tm.launches[k];
+    if (iters) iters[k] = g_tm.iters[k];
+  }
+  return SCH_OK;
+}
 
 const char* sch_last_error(void) { return g_err.c_str(); }
 
@@ -362,15 +440,27 @@ int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed
   *stats = sch_cycle_stats{};
   sch_rng rg{seed, cycle, 0};
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
-  if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, Q, md->dt, W.dW, stream))
-    return rc;
-  if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
-    return rc;
-  if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
-  if (int rc = sch_temper_ess(n, W.phi, logw, W.scal + 0, 0.0, 0, W.scal + 1, W.w, logw,
-                              W.scal + 2, stream))
-    return rc;
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, Q, md->dt, W.dW, stream))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_WINDOW, st);
+    if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
+  }
+  {
+    TimedScope ts(SCH_TK_TEMPER, st);
+    if (int rc = sch_temper_ess(n, W.phi, logw, W.scal + 0, 0.0, 0, W.scal + 1, W.w, logw,
+                                W.scal + 2, stream))
+      return rc;
+  }
   double ess = 0.0;
   unsigned long long its = 0;
   HIP_TRY(hipMemcpyAsync(&ess, W.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -378,6 +468,8 @@ int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed
   std::vector<int> status(n);
   HIP_TRY(hipMemcpyAsync(status.data(), W.status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  timing_flush();
+  g_tm.iters[SCH_TK_WINDOW] += static_cast<long long>(its);
   stats->ess = ess;
   stats->picard_iters = static_cast<int64_t>(its);
   stats->particle_steps = static_cast<int64_t>(n) * n_steps;
@@ -389,10 +481,14 @@ int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed
     return fail(SCH_E_DEGENERATE, "all weights vanished in cycle %u", cycle);
   }
   if (ess < ess_frac * n) {
-    hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
-                       SCH_TAG_RESAMPLE << 24, 0u, W.scal + 3);
-    if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
-      return r2;
+    {
+      TimedScope ts(SCH_TK_RESAMPLE, st);
+      hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
+                         SCH_TAG_RESAMPLE << 24, 0u, W.scal + 3);
+      if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
+        return r2;
+    }
+    TimedScope ts(SCH_TK_GATHER, st);
     if (int r2 = sch_gather(n, nx, W.idx, m, W.scratch, stream)) return r2;
     HIP_TRY(hipMemcpyAsync(m, W.scratch, sizeof(double) * n * nx, hipMemcpyDeviceToDevice, st));
     if (int r2 = sch_gather(n, nx, W.idx, u, W.scratch, stream)) return r2;
@@ -402,6 +498,7 @@ int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed
     stats->resampled = 1;
   }
   HIP_TRY(hipStreamSynchronize(st));
+  timing_flush();
   stats->status = rc;
   if (rc != SCH_OK) return fail(rc, "a particle failed in cycle %u", cycle);
   return SCH_OK;
@@ -424,14 +521,26 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
   *stats = sch_cycle_stats{};
   sch_rng rg{seed, cycle, 0};
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
-  HIP_TRY(hipMemcpyAsync(W.m0, m, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(hipMemcpyAsync(W.u0, u, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
-  if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, Q, md->dt, W.dW, stream))
-    return rc;
-  if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
-    return rc;
-  if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
+  {
+    TimedScope ts(SCH_TK_GATHER, st);
+    HIP_TRY(hipMemcpyAsync(W.m0, m, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(W.u0, u, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+  }
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, Q, md->dt, W.dW, stream))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_WINDOW, st);
+    if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
+  }
   int k = 0, rc = SCH_OK;
   double theta = 0.0, ess = 0.0;
   int64_t psteps = static_cast<int64_t>(n) * n_steps;
@@ -441,33 +550,44 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
       fail(rc, "tempering did not reach theta = 1 in %d steps", max_temper);
       break;
     }
-    if (int r2 = sch_temper_ess(n, W.phi, nullptr, W.scal + 0, thr, n_bisect, W.scal + 1, W.w,
-                                nullptr, W.scal + 2, stream))
-      return r2;
-    hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
-                       SCH_TAG_RESAMPLE << 24, static_cast<uint32_t>(k) << 16, W.scal + 3);
-    if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
-      return r2;
-    double* fields[4] = {W.m0, W.u0, m, u};
-    for (double* f : fields) {
-      if (int r2 = sch_gather(n, nx, W.idx, f, W.scratch, stream)) return r2;
-      HIP_TRY(hipMemcpyAsync(f, W.scratch, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+    {
+      TimedScope ts(SCH_TK_TEMPER, st);
+      if (int r2 = sch_temper_ess(n, W.phi, nullptr, W.scal + 0, thr, n_bisect, W.scal + 1, W.w,
+                                  nullptr, W.scal + 2, stream))
+        return r2;
     }
-    if (int r2 = sch_gather(n, static_cast<int64_t>(n_steps) * Q, W.idx, W.dW, W.scratch, stream))
-      return r2;
-    HIP_TRY(hipMemcpyAsync(W.dW, W.scratch, sizeof(double) * inc, hipMemcpyDeviceToDevice, st));
-    if (int r2 = sch_gather(n, 1, W.idx, W.phi, W.scratch, stream)) return r2;
-    HIP_TRY(hipMemcpyAsync(W.phi, W.scratch, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    {
+      TimedScope ts(SCH_TK_RESAMPLE, st);
+      hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
+                         SCH_TAG_RESAMPLE << 24, static_cast<uint32_t>(k) << 16, W.scal + 3);
+      if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
+        return r2;
+    }
+    {
+      TimedScope ts(SCH_TK_GATHER, st);
+      double* fields[4] = {W.m0, W.u0, m, u};
+      for (double* f : fields) {
+        if (int r2 = sch_gather(n, nx, W.idx, f, W.scratch, stream)) return r2;
+        HIP_TRY(hipMemcpyAsync(f, W.scratch, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+      }
+      if (int r2 = sch_gather(n, static_cast<int64_t>(n_steps) * Q, W.idx, W.dW, W.scratch, stream))
+        return r2;
+      HIP_TRY(hipMemcpyAsync(W.dW, W.scratch, sizeof(double) * inc, hipMemcpyDeviceToDevice, st));
+      if (int r2 = sch_gather(n, 1, W.idx, W.phi, W.scratch, stream)) return r2;
+      HIP_TRY(hipMemcpyAsync(W.phi, W.scratch, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    }
     if (n_jitter > 0) {
+      TimedScope ts(SCH_TK_JITTER, st);
       if (int r2 = launch_jitter(*md, tl, *ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
                                  W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
-                                 nullptr, W.acc + 1, W.acc, st))
+                                 nullptr, W.acc + 1, W.acc + 2, st))
         return r2;
       psteps += static_cast<int64_t>(n) * n_steps * n_jitter;
     }
     HIP_TRY(hipMemcpyAsync(&theta, W.scal + 0, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(&ess, W.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    timing_flush();
     ++k;
     if (!(ess > 0.0)) {
       rc = SCH_E_DEGENERATE;
@@ -475,14 +595,17 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
       break;
     }
   }
-  unsigned long long acc[2] = {0, 0};
+  unsigned long long acc[3] = {0, 0, 0};
   std::vector<int> status(n);
   HIP_TRY(hipMemcpyAsync(acc, W.acc, sizeof acc, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(status.data(), W.status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  timing_flush();
+  g_tm.iters[SCH_TK_WINDOW] += static_cast<long long>(acc[0]);
+  g_tm.iters[SCH_TK_JITTER] += static_cast<long long>(acc[2]);
   stats->ess = ess;
   stats->n_temper = k;
-  stats->picard_iters = static_cast<int64_t>(acc[0]);
+  stats->picard_iters = static_cast<int64_t>(acc[0] + acc[2]);
   stats->n_accept = static_cast<int64_t>(acc[1]);
   stats->particle_steps = psteps;
   for (int p = 0; p < n && rc == SCH_OK; ++p)

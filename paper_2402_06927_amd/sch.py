@@ -101,6 +101,10 @@ def _declare(L):
                                              ST, _vp]),
         "sch_pf_tempered_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
                                             _vp, _vp, _vp, ST, _vp]),
+        "sch_timing_enable": (C.c_int, [C.c_int]),
+        "sch_timing_reset": (C.c_int, []),
+        "sch_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -115,7 +119,8 @@ def exported_names():
         "sch_philox_blocks",
         "sch_velocity", "sch_init_momentum", "sch_ensemble_step", "sch_observe", "sch_loglik",
         "sch_temper_ess", "sch_resample", "sch_gather", "sch_jitter_pcn",
-        "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle",
+        "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle", "sch_timing_enable",
+        "sch_timing_reset", "sch_timing_read",
     ]
 
 
@@ -301,3 +306,24 @@ def sch_pf_tempered_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torc
                                        _dev(workspace, torch.uint8, "workspace"), C.byref(st),
                                        _stream()))
     return st.as_dict()
+
+
+TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other")
+
+
+def sch_timing_enable(on: bool = True):
+    _check(lib().sch_timing_enable(1 if on else 0))
+
+
+def sch_timing_reset():
+    _check(lib().sch_timing_reset())
+
+
+def sch_timing_read() -> dict:
+    k = len(TIMING_KINDS)
+    ms = (C.c_double * k)()
+    la = (C.c_int64 * k)()
+    it = (C.c_int64 * k)()
+    _check(lib().sch_timing_read(ms, la, it))
+    return {name: {"ms": ms[i], "launches": la[i], "iters": it[i]}
+            for i, name in enumerate(TIMING_KINDS)}
