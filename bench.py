@@ -127,7 +127,7 @@ def main():
         sch.sch_observe(model, ut, yobs[c:c + 1])
     yobs += wl.sigma_obs * z
     sigma = torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64, device=dev)
-    ws = sch.workspace(sch.WS_TEMPERED, model, n, S)
+    ws = sch.workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
     m_cpu0, u_cpu0 = None, None
 
     def run_cycle(c):

@@ -105,12 +105,15 @@ const char *sch_last_error(void);
 /* Library version, 100 * major + minor. */
 int sch_version(void);
 
-/* Workspace sizes.  `which` is one of the SCH_WS_* values. */
+/* Workspace sizes in bytes.  `which` is one of the SCH_WS_* values;
+ * n_jitter matters for SCH_WS_JITTER and SCH_WS_TEMPERED (pCN moves per
+ * call / per tempering step).  Returns 0 for invalid arguments. */
 #define SCH_WS_RESAMPLE 1
 #define SCH_WS_BOOTSTRAP 2
 #define SCH_WS_TEMPERED 3
+#define SCH_WS_JITTER 4
 size_t sch_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
-                           int32_t n_steps);
+                           int32_t n_steps, int32_t n_jitter);
 
 /* --------------------------------------------------------------------------
  * Noise.  dW[p][n][q] = sqrt(dt) z, z ~ N(0,1) by Box-Muller from one Philox
@@ -231,11 +234,13 @@ int sch_gather(int32_t n_rows, int64_t row_len, const int32_t *idx, const double
  *   dW          [n][n_steps][n_modes] in/out;  phi [n] in/out
  *   m_end,u_end [n][nx] in/out: window-end state of the current increments
  *   n_accept    out [n] or NULL
+ *   workspace   >= sch_workspace_bytes(SCH_WS_JITTER, model, n, n_steps, n_jitter)
  * ------------------------------------------------------------------------ */
 int sch_jitter_pcn(const sch_model *model, const sch_obs *obs, const sch_rng *rng,
                    int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
                    double *dW, double *phi, double *m_end, double *u_end, const double *theta,
-                   double rho, int32_t n_jitter, int32_t *n_accept, void *stream);
+                   double rho, int32_t n_jitter, int32_t *n_accept, void *workspace,
+                   void *stream);
 
 /* --------------------------------------------------------------------------
  * Filter cycles (host-driven sequences of the calls above; they synchronise
@@ -264,6 +269,18 @@ int sch_pf_tempered_cycle(const sch_model *model, const sch_obs *obs, uint64_t s
                           double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
                           int32_t max_temper, double *m, double *u, void *workspace,
                           sch_cycle_stats *stats, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Tuning knobs (process-global).  SCH_TUNE_THREADS forces the threads per
+ * particle of the model kernels (a power of two in 64..512; 0 = automatic:
+ * the smallest power of two giving at most 8 nodes per thread).  A value
+ * that leaves more than 16 nodes per thread, or fewer than one, makes the
+ * model calls return SCH_E_SHAPE.  sch_tune_get returns the current value
+ * (-1 for an unknown key).
+ * ------------------------------------------------------------------------ */
+#define SCH_TUNE_THREADS 2
+int sch_tune_set(int32_t key, int32_t value);
+int sch_tune_get(int32_t key);
 
 /* --------------------------------------------------------------------------
  * Kernel timing for benchmarks.  While enabled (on != 0), the cycle drivers

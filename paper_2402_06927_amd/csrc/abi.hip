@@ -35,27 +35,65 @@ int fail(int code, const char* fmt, ...) {
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+int grid_for(int64_t work, int block) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<int>(g);
+}
+
 // ---------------------------------------------------------------------------
 // Tile choice: NT threads per particle (power of two, 64..512), each holding
 // up to PMAX consecutive nodes in registers.  NT is the smallest power of two
 // with nx / NT <= 8 (64 at least, 512 at most).
 // ---------------------------------------------------------------------------
+// Tile choice: NT threads per particle (power of two, 64..512), each holding
+// up to PMAX consecutive nodes in registers.  By default NT is the smallest
+// power of two with nx / NT <= 8; SCH_TUNE_THREADS overrides it.
 struct Tile {
   int nt, pmax;
   bool full;
 };
 
-bool pick_tile(int nx, Tile& tl) {
-  const int per = (nx + 7) / 8;
-  int nt = 64;
-  while (nt < per && nt < 512) nt <<= 1;
-  if (nx < nt) return false;
-  const int need = (nx + nt - 1) / nt;
-  if (need > 16) return false;
+Tile tile_for(int nx, int nt) {
+  Tile tl{};
   tl.nt = nt;
+  const int need = (nx + nt - 1) / nt;
   tl.pmax = need <= 4 ? 4 : (need <= 8 ? 8 : 16);
   tl.full = (nx % nt == 0) && (nx / nt == tl.pmax);
+  return tl;
+}
+
+int g_tune_threads = 0;  // SCH_TUNE_THREADS
+
+bool pick_tile(int nx, Tile& tl) {
+  if (nx < 64 || nx > 8192) return false;
+  int nt = g_tune_threads;
+  if (nt == 0) {
+    const int per = (nx + 7) / 8;
+    nt = 64;
+    while (nt < per && nt < 512) nt <<= 1;
+  }
+  if (nx < nt || (nx + nt - 1) / nt > 16) return false;
+  tl = tile_for(nx, nt);
   return true;
+}
+
+// Constants of the scan form of the Helmholtz solve (see solve2.hpp).
+HelmConst make_helm(const sch_model& md, const Tile& tl) {
+  HelmConst K{};
+  const double h = md.L / md.nx, a2 = md.alpha * md.alpha;
+  K.ho = h / 6.0 - a2 / h;
+  K.hd = 2.0 * h / 3.0 + 2.0 * a2 / h;
+  const double x = -K.hd / K.ho;  // > 2
+  K.r = 2.0 / (x + std::sqrt((x - 2.0) * (x + 2.0)));
+  const double kappa = -K.ho / K.r;
+  K.coef = 1.0 / (kappa * (1.0 - K.r) * (1.0 + K.r));
+  K.rN1 = 1.0 / (1.0 - std::pow(K.r, static_cast<double>(md.nx)));
+  K.base = md.nx / tl.nt;
+  K.rb = std::pow(K.r, static_cast<double>(K.base));
+  K.rb1 = std::pow(K.r, static_cast<double>(K.base + 1));
+  return K;
 }
 
 template <class F>
@@ -74,6 +112,7 @@ int with_tile(const Tile& tl, F&& f) {
   return fail(SCH_E_SHAPE, "no kernel for %d threads x %d nodes", tl.nt, tl.pmax);
 }
 
+
 int check_model(const sch_model* md, Tile& tl) {
   if (!md) return fail(SCH_E_ARG, "model is NULL");
   if (!(md->L > 0) || !(md->alpha > 0) || !(md->mu >= 0) || !(md->dt > 0))
@@ -86,6 +125,7 @@ int check_model(const sch_model* md, Tile& tl) {
   if (!pick_tile(md->nx, tl)) return fail(SCH_E_SHAPE, "nx = %d not supported", md->nx);
   return SCH_OK;
 }
+
 
 // Bump allocator over the caller's workspace (256-byte aligned pieces).
 struct Carve {
@@ -103,15 +143,25 @@ struct Carve {
 
 // Scratch layout shared by the cycle drivers.
 struct CycleWs {
+  double *zeta, *vacc;                               // pCN random numbers
   double *m0, *u0, *scratch, *dW, *phi, *w, *scal;  // scal: theta, dtheta, ess, u0
   int *idx, *status, *iters, *degenerate;
   unsigned long long *cum, *acc;                     // acc: [0] iters, [1] accepts
 };
 
-CycleWs carve_cycle(void* base, int which, int nx, int nq, int n, int ns, size_t* bytes) {
+CycleWs carve_cycle(void* base, int which, int nx, int nq, int n, int ns, size_t* bytes,
+                    int n_jitter = 0) {
   Carve c(base);
   CycleWs w{};
   const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * ns * nq;
+  if (which == SCH_WS_JITTER || which == SCH_WS_TEMPERED) {
+    w.zeta = c.take<double>(inc * static_cast<size_t>(n_jitter));
+    w.vacc = c.take<double>(static_cast<size_t>(n) * n_jitter);
+    if (which == SCH_WS_JITTER) {
+      if (bytes) *bytes = c.off + 256;
+      return w;
+    }
+  }
   if (which == SCH_WS_TEMPERED) {
     w.m0 = c.take<double>(state);
     w.u0 = c.take<double>(state);
@@ -144,8 +194,9 @@ int launch_window(const sch_model& md, const Tile& tl, int n, int n_steps, doubl
   A.status = status;
   A.iters = iters;
   A.iters_acc = iters_acc;
+  const HelmConst K = make_helm(md, tl);
   return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
-    hipLaunchKernelGGL((k_window<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A);
+    hipLaunchKernelGGL((k_window<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A, K);
     CHECK_LAUNCH();
     return SCH_OK;
   });
@@ -158,8 +209,9 @@ int launch_helm(const sch_model& md, const Tile& tl, int n, const double* in, do
   A.in = in;
   A.out = out;
   A.mode = mode;
+  const HelmConst K = make_helm(md, tl);
   return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
-    hipLaunchKernelGGL((k_helmholtz<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A);
+    hipLaunchKernelGGL((k_helmholtz<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A, K);
     CHECK_LAUNCH();
     return SCH_OK;
   });
@@ -170,12 +222,21 @@ int check_obs(const sch_obs* ob) {
   return SCH_OK;
 }
 
+// Draws the pCN random numbers (zeta [n_jitter][n][n_steps][n_modes],
+// vacc [n_jitter][n]) and launches the fused jitter kernel.
 int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t seed,
                   uint32_t cycle, uint32_t temper_k, int n, int n_steps, const double* m0,
                   const double* u0, double* dW, double* phi, double* m_end, double* u_end,
                   const double* theta, double rho, int n_jitter, int* n_accept,
-                  unsigned long long* accept_acc, unsigned long long* iters_acc,
-                  hipStream_t st) {
+                  unsigned long long* accept_acc, unsigned long long* iters_acc, double* zeta,
+                  double* vacc, hipStream_t st) {
+  {
+    const int64_t work = static_cast<int64_t>(n_jitter) * n * n_steps * ((md.n_modes + 1) / 2);
+    hipLaunchKernelGGL(k_draw_pcn, dim3(grid_for(work, 256)), dim3(256), 0, st, seed,
+                       cycle * static_cast<uint32_t>(n_steps), cycle, temper_k << 16, n_jitter, n,
+                       n_steps, md.n_modes, std::sqrt(md.dt), zeta, vacc);
+    CHECK_LAUNCH();
+  }
   JitterArgs A;
   A.P = make_params(md);
   A.n_steps = n_steps;
@@ -194,24 +255,18 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
   A.n_obs = ob.n_obs;
   A.y = ob.y;
   A.sigma = ob.sigma;
-  A.seed = seed;
-  A.cycle = cycle;
-  A.temper_k = temper_k;
+  A.zeta = zeta;
+  A.vacc = vacc;
   const size_t dyn = 2 * sizeof(double) * static_cast<size_t>(n_steps) * md.n_modes;
   if (dyn > 32768) return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel");
+  const HelmConst K = make_helm(md, tl);
   return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
-    hipLaunchKernelGGL((k_jitter<PM, NT, FULL>), dim3(n), dim3(NT), dyn, st, A);
+    hipLaunchKernelGGL((k_jitter<PM, NT, FULL>), dim3(n), dim3(NT), dyn, st, A, K);
     CHECK_LAUNCH();
     return SCH_OK;
   });
 }
 
-int grid_for(int64_t work, int block) {
-  int64_t g = (work + block - 1) / block;
-  if (g < 1) g = 1;
-  if (g > 65536) g = 65536;
-  return static_cast<int>(g);
-}
 
 // Event-based timing of kernel classes (see sch_timing_enable).
 struct Timing {
@@ -273,6 +328,20 @@ void timing_flush() {
 // ===========================================================================
 extern "C" {
 
+int sch_tune_set(int32_t key, int32_t value) {
+  if (key == SCH_TUNE_THREADS && (value == 0 || (value >= 64 && value <= 512 &&
+                                                 (value & (value - 1)) == 0))) {
+    g_tune_threads = value;
+    return SCH_OK;
+  }
+  return fail(SCH_E_ARG, "bad tuning key %d or value %d", key, value);
+}
+
+int sch_tune_get(int32_t key) {
+  if (key == SCH_TUNE_THREADS) return g_tune_threads;
+  return -1;
+}
+
 int sch_timing_enable(int on) {
   g_tm.on = on != 0;
   return SCH_OK;
@@ -300,12 +369,14 @@ const char* sch_last_error(void) { return g_err.c_str(); }
 
 int sch_version(void) { return 100; }
 
-size_t sch_workspace_bytes(int32_t which, const sch_model* model, int32_t n, int32_t n_steps) {
+size_t sch_workspace_bytes(int32_t which, const sch_model* model, int32_t n, int32_t n_steps,
+                           int32_t n_jitter) {
   if (n < 1) return 0;
   if (which == SCH_WS_RESAMPLE) return static_cast<size_t>(n) * sizeof(unsigned long long) + 256;
-  if (!model) return 0;
+  if (!model || n_jitter < 0) return 0;
   size_t bytes = 0;
-  carve_cycle(nullptr, which, model->nx, model->n_modes, n, n_steps > 0 ? n_steps : 1, &bytes);
+  carve_cycle(nullptr, which, model->nx, model->n_modes, n, n_steps > 0 ? n_steps : 1, &bytes,
+              n_jitter);
   return bytes;
 }
 
@@ -409,17 +480,19 @@ int sch_gather(int32_t n_rows, int64_t row_len, const int32_t* idx, const double
 int sch_jitter_pcn(const sch_model* md, const sch_obs* ob, const sch_rng* rng, int32_t n,
                    int32_t n_steps, const double* m0, const double* u0, double* dW, double* phi,
                    double* m_end, double* u_end, const double* theta, double rho,
-                   int32_t n_jitter, int32_t* n_accept, void* stream) {
+                   int32_t n_jitter, int32_t* n_accept, void* workspace, void* stream) {
   Tile tl;
   if (int rc = check_model(md, tl)) return rc;
   if (int rc = check_obs(ob)) return rc;
   if (!rng || n < 1 || n_steps < 1 || !m0 || !u0 || !dW || !phi || !m_end || !u_end || !theta ||
-      !(rho >= 0 && rho <= 1) || n_jitter < 0)
+      !(rho >= 0 && rho <= 1) || n_jitter < 0 || (n_jitter > 0 && !workspace))
     return fail(SCH_E_ARG, "bad arguments to sch_jitter_pcn");
   if (n_jitter == 0) return SCH_OK;
+  CycleWs W = carve_cycle(workspace, SCH_WS_JITTER, md->nx, md->n_modes, n, n_steps, nullptr,
+                          n_jitter);
   return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
                        dW, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
-                       S(stream));
+                       W.zeta, W.vacc, S(stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -517,7 +590,7 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
   hipStream_t st = S(stream);
   const int nx = md->nx, Q = md->n_modes;
   const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
-  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, nullptr);
+  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, nullptr, n_jitter);
   *stats = sch_cycle_stats{};
   sch_rng rg{seed, cycle, 0};
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
@@ -580,7 +653,7 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
       TimedScope ts(SCH_TK_JITTER, st);
       if (int r2 = launch_jitter(*md, tl, *ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
                                  W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
-                                 nullptr, W.acc + 1, W.acc + 2, st))
+                                 nullptr, W.acc + 1, W.acc + 2, W.zeta, W.vacc, st))
         return r2;
       psteps += static_cast<int64_t>(n) * n_steps * n_jitter;
     }

@@ -97,9 +97,21 @@ struct RowLds {
   double tail_y[NT], tail_g[NT], tail_k[NT];  // last-row spike values per chunk
   double pcr[2][4][NT];                       // cyclic reduction, double buffered
   double s[NT];                               // interface unknowns
-  double first[NT], last[NT];                 // halo exchange
+  double first[2][NT], last[2][NT];           // halo exchange, double buffered
   double red[3][NT / kWave];                  // workgroup reductions
+  double helm[2][NT / kWave][8];              // per-wavefront records of solve_helm()
+  int stop[16];                               // per-level "coupling remains" flags
 };
+
+// 1/x to full double precision: hardware estimate plus two Newton steps
+// (about one ulp; the divisors here are pivots bounded away from zero).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 
 // A row of the periodic mesh is split over the NT threads of a workgroup:
 // thread t owns the `cnt` consecutive rows starting at `start`, held in
@@ -130,10 +142,12 @@ __device__ __forceinline__ double right_of(const double (&v)[PMAX], int j, int c
 }
 
 // Publishes each thread's first and last row value and returns the left and
-// right neighbours of the chunk (periodic).
+// right neighbours of the chunk (periodic).  The two buffers alternate
+// between calls (hs toggles), so one barrier per exchange suffices: a buffer
+// is rewritten only after the barrier of the exchange in between.
 template <int PMAX, int NT, bool FULL>
 __device__ __forceinline__ void halo(const double (&v)[PMAX], int cnt, RowLds<NT>& L, int t,
-                                     double& hl, double& hr) {
+                                     double& hl, double& hr, int& hs) {
   double lastv = v[PMAX - 1];
   if (!FULL) {
     lastv = v[0];
@@ -141,34 +155,38 @@ __device__ __forceinline__ void halo(const double (&v)[PMAX], int cnt, RowLds<NT
     for (int j = 1; j < PMAX; ++j)
       if (j == cnt - 1) lastv = v[j];
   }
-  L.first[t] = v[0];
-  L.last[t] = lastv;
+  L.first[hs][t] = v[0];
+  L.last[hs][t] = lastv;
   __syncthreads();
-  hl = L.last[(t + NT - 1) & (NT - 1)];
-  hr = L.first[(t + 1) & (NT - 1)];
-  __syncthreads();
+  hl = L.last[hs][(t + NT - 1) & (NT - 1)];
+  hr = L.first[hs][(t + 1) & (NT - 1)];
+  hs ^= 1;
 }
 
 // Parallel cyclic reduction of the periodic tridiagonal system with one
 // equation per thread, A_t s_{t-1} + B_t s_t + C_t s_{t+1} = R_t.  After
-// log2(NT) levels every equation couples s_t only to itself.
+// log2(NT) levels every equation couples s_t only to itself.  The reduction
+// stops earlier once every remaining coupling is below 2^-60 of its
+// diagonal (then s_t = R_t / B_t to within rounding); the decision is shared
+// through a per-level LDS flag read after the level's barrier.
 template <int NT>
 __device__ __forceinline__ double pcr_cyclic(double A, double B, double C, double R,
-                                             double (&buf)[2][4][NT], int t) {
+                                             RowLds<NT>& L, int t) {
+  if (t < 16) L.stop[t] = 0;
   int cur = 0;
-  buf[0][0][t] = A;
-  buf[0][1][t] = B;
-  buf[0][2][t] = C;
-  buf[0][3][t] = R;
+  L.pcr[0][0][t] = A;
+  L.pcr[0][1][t] = B;
+  L.pcr[0][2][t] = C;
+  L.pcr[0][3][t] = R;
   __syncthreads();
-#pragma unroll
-  for (int d = 1; d < NT; d <<= 1) {
+  int level = 0;
+  for (int d = 1; d < NT; d <<= 1, ++level) {
     const int tm = (t - d) & (NT - 1), tp = (t + d) & (NT - 1);
-    const double Am = buf[cur][0][tm], Bm = buf[cur][1][tm], Cm = buf[cur][2][tm],
-                 Rm = buf[cur][3][tm];
-    const double Ap = buf[cur][0][tp], Bp = buf[cur][1][tp], Cp = buf[cur][2][tp],
-                 Rp = buf[cur][3][tp];
-    const double k1 = A / Bm, k2 = C / Bp;
+    const double Am = L.pcr[cur][0][tm], Bm = L.pcr[cur][1][tm], Cm = L.pcr[cur][2][tm],
+                 Rm = L.pcr[cur][3][tm];
+    const double Ap = L.pcr[cur][0][tp], Bp = L.pcr[cur][1][tp], Cp = L.pcr[cur][2][tp],
+                 Rp = L.pcr[cur][3][tp];
+    const double k1 = A * rcp64(Bm), k2 = C * rcp64(Bp);
     const double nA = -k1 * Am;
     const double nB = B - k1 * Cm - k2 * Ap;
     const double nC = -k2 * Cp;
@@ -178,11 +196,14 @@ __device__ __forceinline__ double pcr_cyclic(double A, double B, double C, doubl
     C = nC;
     R = nR;
     cur ^= 1;
-    buf[cur][0][t] = A;
-    buf[cur][1][t] = B;
-    buf[cur][2][t] = C;
-    buf[cur][3][t] = R;
+    L.pcr[cur][0][t] = A;
+    L.pcr[cur][1][t] = B;
+    L.pcr[cur][2][t] = C;
+    L.pcr[cur][3][t] = R;
+    if (__any(fabs(A) + fabs(C) > 0x1.0p-60 * fabs(B)) && (t & (kWave - 1)) == 0)
+      atomicOr(&L.stop[level], 1);
     __syncthreads();
+    if (L.stop[level] == 0) return R / B;
   }
   return R / (A + B + C);
 }
@@ -194,12 +215,13 @@ __device__ __forceinline__ double pcr_cyclic(double A, double B, double C, doubl
 // remaining rows by Thomas' algorithm into x_j = y_j + g_j s_t + k_j s_{t+1}
 // (two spike columns), the interface rows form a periodic tridiagonal system
 // of NT unknowns solved by cyclic reduction, and the chunk is recombined.
-// row(j, a, b, c) returns the coefficients of local slot j.  No pivoting: the
+// row(j, a, b, c) returns the coefficients of local slot j and d(j) its
+// right-hand side (both evaluated once per slot).  No pivoting: the
 // systems solved here (mass, Helmholtz and the implicit-midpoint matrix at
 // the model's parameters) are diagonally dominant.
-template <int PMAX, int NT, bool FULL, class RowF>
-__device__ __forceinline__ void cyclic_solve(RowF row, const double (&d)[PMAX], double (&x)[PMAX],
-                                             int cnt, RowLds<NT>& L, int t) {
+template <int PMAX, int NT, bool FULL, class RowF, class DF>
+__device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], int cnt,
+                                             RowLds<NT>& L, int t) {
   static_assert(PMAX >= 2, "need at least two rows per thread");
   double cp[PMAX], g[PMAX], k[PMAX];
   // forward elimination over the interior slots 1..cnt-1; inactive slots
@@ -210,8 +232,8 @@ __device__ __forceinline__ void cyclic_solve(RowF row, const double (&d)[PMAX], 
   for (int j = 1; j < PMAX; ++j) {
     double a, b, c;
     row(j, a, b, c);
-    const double inv = 1.0 / (b - a * cprev);
-    double cj = c * inv, yj = (d[j] - a * yprev) * inv, gj = -a * gprev * inv;
+    const double inv = rcp64(b - a * cprev);
+    double cj = c * inv, yj = (d(j) - a * yprev) * inv, gj = -a * gprev * inv;
     if (!FULL && j >= cnt) {
       cj = -1.0;
       yj = 0.0;
@@ -261,8 +283,8 @@ __device__ __forceinline__ void cyclic_solve(RowF row, const double (&d)[PMAX], 
   const double A = a0 * gpl;
   const double B = b0 + a0 * kpl + c0 * gn;
   const double C = c0 * kn;
-  const double R = d[0] - a0 * ypl - c0 * yn;
-  const double s = pcr_cyclic<NT>(A, B, C, R, L.pcr, t);
+  const double R = d(0) - a0 * ypl - c0 * yn;
+  const double s = pcr_cyclic<NT>(A, B, C, R, L, t);
   L.s[t] = s;
   __syncthreads();
   const double snext = L.s[(t + 1) & (NT - 1)];

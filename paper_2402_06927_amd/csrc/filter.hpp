@@ -36,6 +36,37 @@ __global__ void k_philox_blocks(uint64_t seed, int n, const uint32_t* ctr, uint3
   }
 }
 
+// Random numbers of n_jitter pCN moves (section 3.1.2): zeta[j][p][n][q] =
+// sqrt(dt) z with z from the PCN-tagged block (p, step0 + n, pair | tag << 24,
+// word3 | j), and the acceptance uniform vacc[j][p] from the ACCEPT-tagged
+// block (p, cycle, tag << 24, word3 | j).
+__global__ void k_draw_pcn(uint64_t seed, uint32_t step0, uint32_t cycle, uint32_t word3,
+                           int n_jitter, int n_particles, int n_steps, int n_modes, double sdt,
+                           double* zeta, double* vacc) {
+  const int n_pairs = (n_modes + 1) / 2;
+  const int64_t per = static_cast<int64_t>(n_particles) * n_steps * n_pairs;
+  const int64_t total = per * n_jitter;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int j = static_cast<int>(i / per);
+    const int64_t r = i - j * per;
+    const int kk = static_cast<int>(r % n_pairs);
+    const int64_t pn = r / n_pairs;
+    const int n = static_cast<int>(pn % n_steps);
+    const int p = static_cast<int>(pn / n_steps);
+    const uint32_t w3 = word3 | static_cast<uint32_t>(j);
+    double z0, z1;
+    normal2(seed, static_cast<uint32_t>(p), step0 + static_cast<uint32_t>(n),
+            static_cast<uint32_t>(kk) | (SCH_TAG_PCN << 24), w3, z0, z1);
+    double* row = zeta + (static_cast<int64_t>(j) * n_particles * n_steps + pn) * n_modes;
+    row[2 * kk] = sdt * z0;
+    if (2 * kk + 1 < n_modes) row[2 * kk + 1] = sdt * z1;
+    if (n == 0 && kk == 0)
+      vacc[static_cast<int64_t>(j) * n_particles + p] =
+          uniform1(seed, static_cast<uint32_t>(p), cycle, SCH_TAG_ACCEPT << 24, w3);
+  }
+}
+
 // One uniform in [0,1) into a device scalar.
 __global__ void k_draw_uniform(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                double* out) {

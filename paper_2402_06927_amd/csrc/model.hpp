@@ -1,9 +1,12 @@
 // model.hpp -- kernels of the SCH forward model on gfx950: one workgroup per
 // particle, the particle's row of nx nodes split in register chunks over the
-// workgroup's threads, every linear system solved with cyclic_solve().
+// workgroup's threads.  The varying implicit-midpoint systems are solved with
+// cyclic_solve(), the constant Helmholtz system with the scan form of
+// solve_helm().
 #pragma once
 
 #include "device.hpp"
+#include "helm.hpp"
 
 namespace sch {
 
@@ -13,7 +16,6 @@ struct StepParams {
   double h, dt, tol;
   double a_off, a_diag;  // constant parts of the step matrix rows:
                          // h/6 - mu dt/(2h) and 2h/3 + mu dt/h
-  double h_off, h_diag;  // Helmholtz rows: h/6 - alpha^2/h and 2h/3 + 2 alpha^2/h
   const double* xi;      // [n_modes][nx]
 };
 
@@ -27,39 +29,36 @@ inline StepParams make_params(const sch_model& md) {
   P.tol = md.picard_tol;
   P.a_off = P.h / 6.0 - md.mu * md.dt / (2.0 * P.h);
   P.a_diag = 2.0 * P.h / 3.0 + md.mu * md.dt / P.h;
-  const double a2 = md.alpha * md.alpha;
-  P.h_off = P.h / 6.0 - a2 / P.h;
-  P.h_diag = 2.0 * P.h / 3.0 + 2.0 * a2 / P.h;
   P.xi = md.xi;
   return P;
 }
 
-// Mass-matrix product (M v)_j = h/6 v_{j-1} + 2h/3 v_j + h/6 v_{j+1} on a chunk.
+// Mass-matrix product scale * (M v)_j = scale * (h/6 v_{j-1} + 2h/3 v_j + h/6 v_{j+1}).
 template <int PMAX, int NT, bool FULL>
 __device__ __forceinline__ void mass_apply(const double (&v)[PMAX], double (&out)[PMAX], double h,
-                                           int cnt, RowLds<NT>& L, int t, double scale) {
+                                           int cnt, RowLds<NT>& L, int t, double scale, int& hs) {
   double hl, hr;
-  halo<PMAX, NT, FULL>(v, cnt, L, t, hl, hr);
+  halo<PMAX, NT, FULL>(v, cnt, L, t, hl, hr, hs);
   const double c1 = scale * h / 6.0, c0 = scale * 2.0 * h / 3.0;
 #pragma unroll
   for (int j = 0; j < PMAX; ++j)
-    out[j] = c1 * (left_of<PMAX, FULL>(v, j, hl) + right_of<PMAX, FULL>(v, j, cnt, hr)) + c0 * v[j];
+    out[j] = fma(c1, left_of<PMAX, FULL>(v, j, hl) + right_of<PMAX, FULL>(v, j, cnt, hr), c0 * v[j]);
 }
 
-// u = H^{-1} M m on a chunk (Helmholtz relation, first line of eq. fde1).
-template <int PMAX, int NT, bool FULL>
-__device__ __forceinline__ void helmholtz(const StepParams& P, const double (&m)[PMAX],
-                                          double (&u)[PMAX], int cnt, RowLds<NT>& L, int t) {
-  double r[PMAX];
-  mass_apply<PMAX, NT, FULL>(m, r, P.h, cnt, L, t, 1.0);
-  const double ho = P.h_off, hd = P.h_diag;
-  auto rowH = [&](int, double& a, double& b, double& c) {
-    a = ho;
-    b = hd;
-    c = ho;
-  };
-  cyclic_solve<PMAX, NT, FULL>(rowH, r, u, cnt, L, t);
-}
+// Per-thread solver state carried through a kernel: the halo and record
+// buffer parities.
+struct Parity {
+  int hs = 0, slot = 0;
+};
+
+// Two per-node arrays of the window (the explicit part of dv and the previous
+// Picard iterate) live in LDS as [slot][thread] when they fit next to the
+// solver's LDS, in registers otherwise.
+template <int PMAX, int NT>
+struct AuxLds {
+  static constexpr bool kInLds = 2 * PMAX * NT * sizeof(double) <= 65536;
+  double a[kInLds ? 2 : 1][kInLds ? PMAX : 1][kInLds ? NT : 1];
+};
 
 // One assimilation window of n_steps implicit-midpoint steps (eq. fde1) for
 // the particle whose chunk is held in m, u.  inc(n, q) returns the noise
@@ -72,71 +71,96 @@ __device__ __forceinline__ void helmholtz(const StepParams& P, const double (&m)
 //   a_i = h/6 - mu dt/(2h) - dv_{i-1}/4
 //   b_i = 2h/3 + mu dt/h + (dv_{i+1} - dv_{i-1})/4
 //   c_i = h/6 - mu dt/(2h) + dv_{i+1}/4
-// (the exact P1 integrals of the advective terms of eq. fde1).
+// (the exact P1 integrals of the advective terms of eq. fde1).  The right-
+// hand side 2 M m^n is formed row by row inside the solve.  The convergence
+// test's workgroup reduction rides on the Helmholtz solve's barrier.
 // Returns SCH_OK or the status of the first failing step; on non-convergence
 // the last iterate is kept, on a non-finite iterate the step's input is kept.
 template <int PMAX, int NT, bool FULL, class IncF>
-__device__ int run_window(const StepParams& P, IncF inc, int n_steps, double (&m)[PMAX],
-                          double (&u)[PMAX], const Chunk& ch, RowLds<NT>& L, int t, int& iters) {
+__device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int n_steps,
+                          double (&m)[PMAX], double (&u)[PMAX], const Chunk& ch, RowLds<NT>& L,
+                          AuxLds<PMAX, NT>& X, int t, Parity& par, int& iters) {
+  constexpr bool kLds = AuxLds<PMAX, NT>::kInLds;
   const int cnt = ch.cnt;
   const double hdt = 0.5 * P.dt;
+  const double f1 = P.h / 3.0, f0 = 4.0 * P.h / 3.0;  // 2 M: (h/3, 4h/3, h/3)
+  double rD[kLds ? 1 : PMAX], rP[kLds ? 1 : PMAX];
+  auto getD = [&](int j) -> double { if constexpr (kLds) return X.a[0][j][t]; else return rD[j]; };
+  auto setD = [&](int j, double v) { if constexpr (kLds) X.a[0][j][t] = v; else rD[j] = v; };
+  auto getP = [&](int j) -> double { if constexpr (kLds) return X.a[1][j][t]; else return rP[j]; };
+  auto setP = [&](int j, double v) { if constexpr (kLds) X.a[1][j][t] = v; else rP[j] = v; };
   for (int n = 0; n < n_steps; ++n) {
     // dU^n + dt/2 u^n, the explicit part of dv
-    double dUp[PMAX];
+    {
+      double e[PMAX];
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) dUp[j] = hdt * u[j];
-    for (int q = 0; q < P.n_modes; ++q) {
-      const double w = inc(n, q);
-      const double* xq = P.xi + static_cast<size_t>(q) * P.nx + ch.start;
+      for (int j = 0; j < PMAX; ++j) e[j] = hdt * u[j];
+      for (int q = 0; q < P.n_modes; ++q) {
+        const double w = inc(n, q);
+        const double* xq = P.xi + static_cast<size_t>(q) * P.nx + ch.start;
 #pragma unroll
-      for (int j = 0; j < PMAX; ++j)
-        if (FULL || j < cnt) dUp[j] += xq[j] * w;
+        for (int j = 0; j < PMAX; ++j)
+          if (FULL || j < cnt) e[j] = fma(xq[j], w, e[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) {
+        setD(j, e[j]);
+        setP(j, m[j]);
+      }
     }
-    double f[PMAX];
-    mass_apply<PMAX, NT, FULL>(m, f, P.h, cnt, L, t, 2.0);
+    double mL, mR;
+    halo<PMAX, NT, FULL>(m, cnt, L, t, mL, mR, par.hs);
+    auto fget = [&](int j) -> double {
+      return fma(f1, left_of<PMAX, FULL>(m, j, mL) + right_of<PMAX, FULL>(m, j, cnt, mR),
+                 f0 * m[j]);
+    };
 
-    double us[PMAX], mp[PMAX], ms[PMAX];
+    double us[PMAX], ms[PMAX];
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) {
-      us[j] = u[j];
-      mp[j] = m[j];
-    }
+    for (int j = 0; j < PMAX; ++j) us[j] = u[j];
     int status = SCH_E_NONCONVERGED, k = 1;
     for (; k <= P.picard_max; ++k) {
       double dv[PMAX];
 #pragma unroll
-      for (int j = 0; j < PMAX; ++j) dv[j] = hdt * us[j] + dUp[j];
+      for (int j = 0; j < PMAX; ++j) dv[j] = fma(hdt, us[j], getD(j));
       double vl, vr;
-      halo<PMAX, NT, FULL>(dv, cnt, L, t, vl, vr);
+      halo<PMAX, NT, FULL>(dv, cnt, L, t, vl, vr, par.hs);
       const double ao = P.a_off, ad = P.a_diag;
       auto rowA = [&](int j, double& a, double& b, double& c) {
         const double vm = left_of<PMAX, FULL>(dv, j, vl);
         const double vp = right_of<PMAX, FULL>(dv, j, cnt, vr);
-        a = ao - 0.25 * vm;
-        b = ad + 0.25 * (vp - vm);
-        c = ao + 0.25 * vp;
+        a = fma(-0.25, vm, ao);
+        b = fma(0.25, vp - vm, ad);
+        c = fma(0.25, vp, ao);
       };
-      cyclic_solve<PMAX, NT, FULL>(rowA, f, ms, cnt, L, t);
-#pragma unroll
-      for (int j = 0; j < PMAX; ++j) ms[j] -= m[j];
-      helmholtz<PMAX, NT, FULL>(P, ms, us, cnt, L, t);
+      cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t);
       double diff = 0.0, scale = 0.0;
       int bad = 0;
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) {
+        ms[j] -= m[j];
         if (FULL || j < cnt) {
-          diff = fmax(diff, fabs(ms[j] - mp[j]));
+          diff = fmax(diff, fabs(ms[j] - getP(j)));
           scale = fmax(scale, fabs(ms[j]));
-          bad |= !isfinite(ms[j]) || !isfinite(us[j]);
+          bad |= !isfinite(ms[j]);
         }
-        mp[j] = ms[j];
+        setP(j, ms[j]);
       }
-      block_max2_or<NT>(diff, scale, bad, L, t);
-      if (bad) {
+      diff = wave_max(diff);
+      scale = wave_max(scale);
+      bad = wave_or(bad);
+      // u* = H^{-1} M m*
+      double r[PMAX];
+      mass_apply<PMAX, NT, FULL>(ms, r, P.h, cnt, L, t, 1.0, par.hs);
+      double uL, uR, gdiff, gscale, gbad;
+      solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale,
+                                 bad ? 1.0 : 0.0, gdiff, gscale, gbad);
+      par.slot ^= 1;
+      if (gbad > 0.0) {
         status = SCH_E_NONFINITE;
         break;
       }
-      if (diff <= P.tol * scale) {
+      if (gdiff <= P.tol * gscale) {
         status = SCH_OK;
         break;
       }
@@ -157,9 +181,9 @@ __device__ int run_window(const StepParams& P, IncF inc, int n_steps, double (&m
 // each thread takes the observation points that fall in its own cells.
 template <int PMAX, int NT, bool FULL>
 __device__ double block_nll(const double (&u)[PMAX], const Chunk& ch, int nx, int n_obs,
-                            const double* y, const double* sigma, RowLds<NT>& L, int t) {
+                            const double* y, const double* sigma, RowLds<NT>& L, int t, int& hs) {
   double hl, hr;
-  halo<PMAX, NT, FULL>(u, ch.cnt, L, t, hl, hr);
+  halo<PMAX, NT, FULL>(u, ch.cnt, L, t, hl, hr, hs);
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
@@ -206,8 +230,9 @@ struct WindowArgs {
 };
 
 template <int PMAX, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) k_window(const WindowArgs A) {
+__global__ void __launch_bounds__(NT) k_window(const WindowArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
+  __shared__ AuxLds<PMAX, NT> X;
   const int p = blockIdx.x, t = threadIdx.x;
   const Chunk ch = chunk_of<NT>(A.P.nx, t);
   double* mp = A.m + static_cast<size_t>(p) * A.P.nx;
@@ -224,7 +249,8 @@ __global__ void __launch_bounds__(NT) k_window(const WindowArgs A) {
     return w;
   };
   int iters = 0;
-  const int st = run_window<PMAX, NT, FULL>(A.P, inc, A.n_steps, m, u, ch, L, t, iters);
+  Parity par;
+  const int st = run_window<PMAX, NT, FULL>(A.P, K, inc, A.n_steps, m, u, ch, L, X, t, par, iters);
   store_chunk<PMAX, FULL>(mp, ch, m);
   store_chunk<PMAX, FULL>(up, ch, u);
   if (t == 0) {
@@ -252,53 +278,43 @@ struct JitterArgs {
   int n_obs;
   const double* y;
   const double* sigma;
-  uint64_t seed;
-  uint32_t cycle, temper_k;
+  const double* zeta;  // [n_jitter][n][n_steps][n_modes]: sqrt(dt) z of the proposals
+  const double* vacc;  // [n_jitter][n]: acceptance uniforms
 };
 
+// n_jitter pCN moves of one particle's increments (section 3.1.2): proposal,
+// window rerun from the window-start state (re-read from global memory for
+// every proposal), likelihood and Metropolis accept in one launch.
 template <int PMAX, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) k_jitter(const JitterArgs A) {
+__global__ void __launch_bounds__(NT) k_jitter(const JitterArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
+  __shared__ AuxLds<PMAX, NT> X;
   extern __shared__ double dyn[];  // [2][n_steps][n_modes]: current increments, proposal
   const int p = blockIdx.x, t = threadIdx.x;
   const int nx = A.P.nx, Q = A.P.n_modes, S = A.n_steps;
   const Chunk ch = chunk_of<NT>(nx, t);
   double* cur = dyn;
   double* prop = dyn + S * Q;
-  double m0[PMAX], u0[PMAX];
-  load_chunk<PMAX, FULL>(A.m0 + static_cast<size_t>(p) * nx, ch, m0);
-  load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u0);
   double* dWp = A.dW + static_cast<size_t>(p) * S * Q;
   for (int i = t; i < S * Q; i += NT) cur[i] = dWp[i];
   double phi = A.phi[p];
   const double theta = *A.theta;
-  const double srho = sqrt(1.0 - A.rho * A.rho), sdt = sqrt(A.P.dt);
-  const int n_pairs = (Q + 1) / 2;
+  const double srho = sqrt(1.0 - A.rho * A.rho);
   int acc = 0, iters = 0;
+  Parity par;
   __syncthreads();
   for (int j = 0; j < A.n_jitter; ++j) {
-    const uint32_t w3 = (A.temper_k << 16) | static_cast<uint32_t>(j);
-    for (int i = t; i < S * n_pairs; i += NT) {
-      const int n = i / n_pairs, kk = i - n * n_pairs;
-      double z0, z1;
-      normal2(A.seed, static_cast<uint32_t>(p), A.cycle * static_cast<uint32_t>(S) + n,
-              static_cast<uint32_t>(kk) | (SCH_TAG_PCN << 24), w3, z0, z1);
-      const int q0 = 2 * kk;
-      prop[n * Q + q0] = A.rho * cur[n * Q + q0] + srho * (sdt * z0);
-      if (q0 + 1 < Q) prop[n * Q + q0 + 1] = A.rho * cur[n * Q + q0 + 1] + srho * (sdt * z1);
-    }
+    const double* zj = A.zeta + (static_cast<size_t>(j) * gridDim.x + p) * S * Q;
+    for (int i = t; i < S * Q; i += NT) prop[i] = A.rho * cur[i] + srho * zj[i];
     __syncthreads();
     double m[PMAX], u[PMAX];
-#pragma unroll
-    for (int q = 0; q < PMAX; ++q) {
-      m[q] = m0[q];
-      u[q] = u0[q];
-    }
+    load_chunk<PMAX, FULL>(A.m0 + static_cast<size_t>(p) * nx, ch, m);
+    load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u);
     auto inc = [&](int n, int q) { return prop[n * Q + q]; };
-    const int st = run_window<PMAX, NT, FULL>(A.P, inc, S, m, u, ch, L, t, iters);
-    double phin = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t);
+    const int st = run_window<PMAX, NT, FULL>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
+    double phin = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t, par.hs);
     if (st != SCH_OK || !isfinite(phin)) phin = INFINITY;
-    const double v = uniform1(A.seed, static_cast<uint32_t>(p), A.cycle, SCH_TAG_ACCEPT << 24, w3);
+    const double v = A.vacc[static_cast<size_t>(j) * gridDim.x + p];
     bool accept;
     if (!(phin < INFINITY)) {
       accept = false;
@@ -334,30 +350,34 @@ struct HelmArgs {
 };
 
 template <int PMAX, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) k_helmholtz(const HelmArgs A) {
+__global__ void __launch_bounds__(NT) k_helmholtz(const HelmArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   const int p = blockIdx.x, t = threadIdx.x;
   const Chunk ch = chunk_of<NT>(A.P.nx, t);
   double v[PMAX], o[PMAX];
   load_chunk<PMAX, FULL>(A.in + static_cast<size_t>(p) * A.P.nx, ch, v);
+  int hs = 0;
   if (A.mode == 0) {
-    helmholtz<PMAX, NT, FULL>(A.P, v, o, ch.cnt, L, t);
+    double r[PMAX];
+    mass_apply<PMAX, NT, FULL>(v, r, A.P.h, ch.cnt, L, t, 1.0, hs);
+    double uL, uR, g0, g1, g2;
+    solve_helm<PMAX, NT, FULL>(K, r, o, uL, uR, ch.cnt, L, 0, t, 0.0, 0.0, 0.0, g0, g1, g2);
   } else {
     // right-hand side H u = M u + alpha^2 K u, then the mass solve
     double hl, hr;
-    halo<PMAX, NT, FULL>(v, ch.cnt, L, t, hl, hr);
+    halo<PMAX, NT, FULL>(v, ch.cnt, L, t, hl, hr, hs);
     double r[PMAX];
 #pragma unroll
     for (int j = 0; j < PMAX; ++j)
-      r[j] = A.P.h_off * (left_of<PMAX, FULL>(v, j, hl) + right_of<PMAX, FULL>(v, j, ch.cnt, hr)) +
-             A.P.h_diag * v[j];
+      r[j] = K.ho * (left_of<PMAX, FULL>(v, j, hl) + right_of<PMAX, FULL>(v, j, ch.cnt, hr)) +
+             K.hd * v[j];
     const double mo = A.P.h / 6.0, md = 2.0 * A.P.h / 3.0;
     auto rowM = [&](int, double& a, double& b, double& c) {
       a = mo;
       b = md;
       c = mo;
     };
-    cyclic_solve<PMAX, NT, FULL>(rowM, r, o, ch.cnt, L, t);
+    cyclic_solve<PMAX, NT, FULL>(rowM, [&](int j) { return r[j]; }, o, ch.cnt, L, t);
   }
   store_chunk<PMAX, FULL>(A.out + static_cast<size_t>(p) * A.P.nx, ch, o);
 }

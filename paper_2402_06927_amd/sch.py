@@ -27,7 +27,7 @@ SCH_E_DEGENERATE = -5
 SCH_E_HIP = -6
 
 TAG_INIT, TAG_FORECAST, TAG_PCN, TAG_ACCEPT, TAG_RESAMPLE, TAG_OBS, TAG_NUDGE = range(7)
-WS_RESAMPLE, WS_BOOTSTRAP, WS_TEMPERED = 1, 2, 3
+WS_RESAMPLE, WS_BOOTSTRAP, WS_TEMPERED, WS_JITTER = 1, 2, 3, 4
 
 
 class SchError(RuntimeError):
@@ -84,7 +84,7 @@ def _declare(L):
     sig = {
         "sch_last_error": (C.c_char_p, []),
         "sch_version": (C.c_int, []),
-        "sch_workspace_bytes": (C.c_size_t, [i32, M, i32, i32]),
+        "sch_workspace_bytes": (C.c_size_t, [i32, M, i32, i32, i32]),
         "sch_draw_increments": (C.c_int, [R, u32, i32, i32, i32, f64, _vp, _vp]),
         "sch_philox_blocks": (C.c_int, [u64, i32, _vp, _vp, _vp]),
         "sch_velocity": (C.c_int, [M, i32, _vp, _vp, _vp]),
@@ -96,11 +96,13 @@ def _declare(L):
         "sch_resample": (C.c_int, [i32, _vp, _vp, _vp, f64, _vp, _vp, _vp, _vp]),
         "sch_gather": (C.c_int, [i32, i64, _vp, _vp, _vp, _vp]),
         "sch_jitter_pcn": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, f64,
-                                     i32, _vp, _vp]),
+                                     i32, _vp, _vp, _vp]),
         "sch_pf_bootstrap_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, _vp, _vp, _vp, _vp,
                                              ST, _vp]),
         "sch_pf_tempered_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
                                             _vp, _vp, _vp, ST, _vp]),
+        "sch_tune_set": (C.c_int, [i32, i32]),
+        "sch_tune_get": (C.c_int, [i32]),
         "sch_timing_enable": (C.c_int, [C.c_int]),
         "sch_timing_reset": (C.c_int, []),
         "sch_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
@@ -119,7 +121,8 @@ def exported_names():
         "sch_philox_blocks",
         "sch_velocity", "sch_init_momentum", "sch_ensemble_step", "sch_observe", "sch_loglik",
         "sch_temper_ess", "sch_resample", "sch_gather", "sch_jitter_pcn",
-        "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle", "sch_timing_enable",
+        "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
+        "sch_timing_enable",
         "sch_timing_reset", "sch_timing_read",
     ]
 
@@ -178,15 +181,18 @@ class Obs:
         return SchObsC(int(self.y.numel()), _dev(self.y, name="y"), _dev(self.sigma, name="sigma"))
 
 
-def workspace_bytes(which: int, model: Model | None, n_particles: int, n_steps: int = 0) -> int:
+def workspace_bytes(which: int, model: Model | None, n_particles: int, n_steps: int = 0,
+                    n_jitter: int = 0) -> int:
     mc = model.c() if model is not None else None
     return int(lib().sch_workspace_bytes(which, C.byref(mc) if mc is not None else None,
-                                         n_particles, n_steps))
+                                         n_particles, n_steps, n_jitter))
 
 
 def workspace(which: int, model: Model | None, n_particles: int, n_steps: int = 0,
-              device="cuda") -> torch.Tensor:
-    nb = workspace_bytes(which, model, n_particles, n_steps)
+              n_jitter: int = 0, device="cuda") -> torch.Tensor:
+    nb = workspace_bytes(which, model, n_particles, n_steps, n_jitter)
+    if nb <= 0:
+        raise SchError(SCH_E_ARG, "invalid workspace request")
     return torch.empty(nb, dtype=torch.uint8, device=device)
 
 
@@ -270,15 +276,19 @@ def sch_gather(idx: torch.Tensor, src: torch.Tensor, dst: torch.Tensor):
 def sch_jitter_pcn(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
                    m0: torch.Tensor, u0: torch.Tensor, dW: torch.Tensor, phi: torch.Tensor,
                    m_end: torch.Tensor, u_end: torch.Tensor, theta: torch.Tensor, rho: float,
-                   n_jitter: int, n_accept: torch.Tensor | None = None):
+                   n_jitter: int, n_accept: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None):
     mc, oc = model.c(), obs.c()
     r = SchRngC(seed, cycle, temper_k)
     n, s = dW.shape[0], dW.shape[1]
+    if workspace is None:
+        workspace = globals()["workspace"](WS_JITTER, model, n, s, n_jitter)
     _check(lib().sch_jitter_pcn(C.byref(mc), C.byref(oc), C.byref(r), n, s, _dev(m0, name="m0"),
                                 _dev(u0, name="u0"), _dev(dW, name="dW"), _dev(phi, name="phi"),
                                 _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
                                 _dev(theta, name="theta"), rho, n_jitter,
-                                _dev(n_accept, torch.int32, "n_accept"), _stream()))
+                                _dev(n_accept, torch.int32, "n_accept"),
+                                _dev(workspace, torch.uint8, "workspace"), _stream()))
 
 
 def sch_pf_bootstrap_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
@@ -327,3 +337,14 @@ def sch_timing_read() -> dict:
     _check(lib().sch_timing_read(ms, la, it))
     return {name: {"ms": ms[i], "launches": la[i], "iters": it[i]}
             for i, name in enumerate(TIMING_KINDS)}
+
+
+TUNE_THREADS = 2
+
+
+def sch_tune_set(key: int, value: int):
+    _check(lib().sch_tune_set(key, value))
+
+
+def sch_tune_get(key: int) -> int:
+    return int(lib().sch_tune_get(key))

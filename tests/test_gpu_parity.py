@@ -318,7 +318,7 @@ def test_tempered_cycle_parity(sch):
     sig = np.full(wl.n_obs, wl.sigma_obs)
     m_o, u_o = m0.copy(), u0.copy()
     m, u = T(m0), T(u0)
-    ws = sch.workspace(sch.WS_TEMPERED, gm, n, wl.n_steps)
+    ws = sch.workspace(sch.WS_TEMPERED, gm, n, wl.n_steps, wl.n_jitter)
     for c in range(wl.n_cycles):
         _say("tempered cycle", c)
         rc, m_o, u_o, st_o = O.tempered_cycle(om, ys[c], sig, wl.seed, c, m_o, u_o, wl.n_steps,
