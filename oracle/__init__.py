@@ -73,6 +73,14 @@ class OrcModel(C.Structure):
     ]
 
 
+class OrcLbfgsOpts(C.Structure):
+    _fields_ = [("gtol", C.c_double), ("max_iter", C.c_int32), ("mem", C.c_int32),
+                ("max_back", C.c_int32)]
+
+
+OBJECTIVE = C.CFUNCTYPE(C.c_int, C.c_void_p, _dp, _dp, _dp)
+
+
 class OrcRng(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("cycle", C.c_uint32), ("temper_k", C.c_uint32)]
 
@@ -126,6 +134,17 @@ def _declare(L):
                                          C.c_uint32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                          C.c_double, C.c_int32, C.c_int32, _dp, _dp,
                                          C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_nudge_objective": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_int32,
+                                          _dp, _dp, _dp, _dp, _dp]),
+        "orc_nudge_grad": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_int32, _dp,
+                                     _dp, _dp, _dp, _dp, _dp]),
+        "orc_nudge_grad_tangent": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_int32,
+                                             _dp, _dp, _dp, _dp, _dp]),
+        "orc_lbfgs": (C.c_int, [C.c_int32, OBJECTIVE, C.c_void_p, _dp, C.c_double, C.c_double,
+                                C.c_int32, C.c_int32, C.c_int32, _dp, _ip, _ip]),
+        "orc_nudge_ensemble": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_int32,
+                                         C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(OrcLbfgsOpts),
+                                         _dp, _ip, _ip, _ip, _ip, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -445,3 +464,107 @@ def tempered_cycle(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_thres
                                   max_temper, _d(m), _d(u), C.byref(st),
                                   n_threads or n_threads_default())
     return rc, m, u, st
+
+
+# --------------------------------------------------------------------------- nudging
+# L-BFGS settings of the nudging stages: memory 8, at most 30 accepted steps,
+# stop at |grad|_inf <= 1e-8 (1 + |J|), at most 30 halvings per line search.
+LBFGS_GTOL = 1e-8
+LBFGS_MAX_ITER = 30
+LBFGS_MEM = 8
+LBFGS_MAX_BACK = 30
+
+
+def _obs_arrays(y, sigma):
+    y = _f64(y)
+    return y, _f64(np.broadcast_to(sigma, y.shape))
+
+
+def nudge_objective(model: Model, y, sigma, m0, u0, dW, dLam=None):
+    """J = Phi(u^N) + sum_n (|dLam^n|^2/2 + dLam^n.dW^n)/dt (orc_nudge_objective)."""
+    y, sg = _obs_arrays(y, sigma)
+    dW = _f64(dW)
+    J = C.c_double(0.0)
+    cm = model.c()
+    st = lib().orc_nudge_objective(C.byref(cm), len(y), _d(y), _d(sg), dW.shape[0],
+                                   _d(_f64(m0)), _d(_f64(u0)), _d(dW),
+                                   _d(_f64(dLam)) if dLam is not None else None, C.byref(J))
+    return st, J.value
+
+
+def nudge_grad(model: Model, y, sigma, m0, u0, dW, dLam=None):
+    """Reverse-sweep adjoint: returns (status, J, dJ/ddLam [n_steps][Q]) (orc_nudge_grad)."""
+    y, sg = _obs_arrays(y, sigma)
+    dW = _f64(dW)
+    J = C.c_double(0.0)
+    g = np.zeros_like(dW)
+    cm = model.c()
+    st = lib().orc_nudge_grad(C.byref(cm), len(y), _d(y), _d(sg), dW.shape[0], _d(_f64(m0)),
+                              _d(_f64(u0)), _d(dW),
+                              _d(_f64(dLam)) if dLam is not None else None, C.byref(J), _d(g))
+    return st, J.value, g
+
+
+def nudge_grad_tangent(model: Model, y, sigma, m0, u0, dW, dLam=None):
+    """Dense forward-mode gradient (small nx only) (orc_nudge_grad_tangent)."""
+    y, sg = _obs_arrays(y, sigma)
+    dW = _f64(dW)
+    g = np.zeros_like(dW)
+    cm = model.c()
+    st = lib().orc_nudge_grad_tangent(C.byref(cm), len(y), _d(y), _d(sg), dW.shape[0],
+                                      _d(_f64(m0)), _d(_f64(u0)), _d(dW),
+                                      _d(_f64(dLam)) if dLam is not None else None, _d(g))
+    return st, g
+
+
+def lbfgs(fun, x0, h0=1.0, gtol=LBFGS_GTOL, max_iter=LBFGS_MAX_ITER, mem=LBFGS_MEM,
+          max_back=LBFGS_MAX_BACK):
+    """Run the oracle's L-BFGS on a Python objective fun(x) -> (status, f, g).
+    Returns (status, x, f, iterations, evaluations)."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    n = len(x)
+
+    def cb(_ctx, xp, fp, gp):
+        xv = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+        st, f, g = fun(xv)
+        fp[0] = f
+        for i in range(n):
+            gp[i] = g[i]
+        return int(st)
+
+    cfun = OBJECTIVE(cb)
+    f = C.c_double(0.0)
+    it = C.c_int32(0)
+    ev = C.c_int32(0)
+    st = lib().orc_lbfgs(n, cfun, None, _d(x), h0, gtol, max_iter, mem, max_back, C.byref(f),
+                         C.byref(it), C.byref(ev))
+    return st, x, f.value, it.value, ev.value
+
+
+def nudge_ensemble(model: Model, y, sigma, m, u, dW, dLam0=None, gtol=LBFGS_GTOL,
+                   max_iter=LBFGS_MAX_ITER, mem=LBFGS_MEM, max_back=LBFGS_MAX_BACK,
+                   n_threads=None):
+    """Sequential adapted nudging of every particle over one window.
+    m, u: [P][nx] (start state); dW: [P][S][Q] revealed increments; dLam0: warm
+    start or None.  Returns dict(worst, m, u, dLam, logG, iters, evals,
+    lbfgs_status, status)."""
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    dW = _f64(dW)
+    P, S = dW.shape[0], dW.shape[1]
+    dLam = (np.zeros_like(dW) if dLam0 is None
+            else np.array(dLam0, dtype=np.float64, copy=True, order="C"))
+    logG = np.zeros(P)
+    iters = np.zeros(P, dtype=np.int32)
+    evals = np.zeros(P, dtype=np.int32)
+    lst = np.zeros(P, dtype=np.int32)
+    status = np.zeros(P, dtype=np.int32)
+    opts = OrcLbfgsOpts(gtol, max_iter, mem, max_back)
+    cm = model.c()
+    worst = lib().orc_nudge_ensemble(C.byref(cm), len(y), _d(y), _d(sg), P, S, _d(m), _d(u),
+                                     _d(dW), _d(dLam), C.byref(opts), _d(logG), _i(iters),
+                                     _i(evals), _i(lst), _i(status),
+                                     n_threads or n_threads_default())
+    return dict(worst=worst, m=m, u=u, dLam=dLam, logG=logG, iters=iters, evals=evals,
+                lbfgs_status=lst, status=status)

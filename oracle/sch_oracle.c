@@ -934,3 +934,513 @@ int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, cons
   free(acc);
   return rc;
 }
+
+/* ========================================================================== */
+/* Nudging (section 3.1.3).                                                    */
+/*                                                                            */
+/* A control dLambda^n in R^Q enters beside the Brownian increment in every    */
+/* step (eq. "SCH nudge", modes form): dU^n = sum_q xi_q (dW^n_q + dLambda^n_q).*/
+/* The objective of one window from the state (m0, u0) over n_steps steps is   */
+/*   J = Phi(u^N) + sum_n ( |dLambda^n|^2 / 2 + dLambda^n . dW^n ) / dt,        */
+/* i.e. the negative log-likelihood plus minus the log of the discrete         */
+/* Girsanov factor (eq. "girsanov DG approx" with Lambda = dLambda / dt; the   */
+/* sign follows from the ratio of the Gaussian densities of dW + dLambda       */
+/* under the model and under the nudged proposal).  Minimising J maximises the */
+/* weight W~ = W + G read as log-weights.                                      */
+/*                                                                            */
+/* Gradient.  With s = m^n + m^{n+1} the step solves                            */
+/*   F(s) = A(dv) s - 2 M m^n = 0,  dv = (dt/2) R s + dU^n,  R = H^{-1} M,      */
+/* where A(dv) = M + (mu dt/2) K + (1/2) C(dv).  Writing C(v) f = D(f) v,       */
+/*   dF/ds = Jac = A(dv) + (dt/4) D(s) R,  dF/dm^n = -2 M,  dF/ddU = D(s)/2.    */
+/* Reverse sweep: lambda_N = R^T P^T diag(1/sigma^2) (P u^N - y); per step,     */
+/*   nu = Jac^{-T} lambda_{n+1},  lambda_n = 2 M nu - lambda_{n+1},             */
+/*   dJ/ddU^n = -(1/2) D(s)^T nu,                                               */
+/*   dJ/ddLambda^n_q = xi_q . dJ/ddU^n + (dLambda^n_q + dW^n_q) / dt.           */
+/* Jac^T nu = lambda is solved by the fixed point                              */
+/*   nu <- A^{-T} (lambda - (dt/4) M H^{-1} D(s)^T nu),                         */
+/* each A^{-T} and H^{-1} a pivoted cyclic solve, to picard_tol.               */
+/* ========================================================================== */
+
+/* (D(f)^T w)_j = (f_{j-1} + f_j)/2 w_{j-1} - (f_j + f_{j+1})/2 w_{j+1} */
+static void advect_transpose(int32_t n, const double *f, const double *w, double *out) {
+  for (int32_t j = 0; j < n; ++j) {
+    int32_t jm = wrap(j - 1, n), jp = wrap(j + 1, n);
+    out[j] = 0.5 * (f[jm] + f[j]) * w[jm] - 0.5 * (f[j] + f[jp]) * w[jp];
+  }
+}
+
+static double girsanov_term(int32_t n_steps, int32_t nq, double dt, const double *dW,
+                            const double *dLam) {
+  double g = 0.0;
+  if (!dLam) return 0.0;
+  for (int32_t i = 0; i < n_steps * nq; ++i)
+    g += 0.5 * dLam[i] * dLam[i] / dt + dLam[i] * dW[i] / dt;
+  return g;
+}
+
+/* P^T (P u - y) / sigma^2, scattered back to the nodes */
+static void obs_adjoint(int32_t nx, int32_t n_obs, const double *u, const double *y,
+                        const double *sigma, double *out) {
+  double *pu = (double *)malloc(sizeof(double) * n_obs);
+  orc_observe(nx, n_obs, u, pu);
+  for (int32_t i = 0; i < nx; ++i) out[i] = 0.0;
+  for (int32_t j = 0; j < n_obs; ++j) {
+    int64_t num = (int64_t)j * nx;
+    int32_t e = (int32_t)(num / n_obs);
+    double r = (double)(num % n_obs) / (double)n_obs;
+    double res = (pu[j] - y[j]) / (sigma[j] * sigma[j]);
+    out[e % nx] += (1.0 - r) * res;
+    out[(e + 1) % nx] += r * res;
+  }
+  free(pu);
+}
+
+int orc_nudge_objective(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                        int32_t n_steps, const double *m0, const double *u0, const double *dW,
+                        const double *dLam, double *J) {
+  int32_t nx = md->nx;
+  double *m = (double *)malloc(sizeof(double) * nx), *u = (double *)malloc(sizeof(double) * nx);
+  memcpy(m, m0, sizeof(double) * nx);
+  memcpy(u, u0, sizeof(double) * nx);
+  int32_t it;
+  int st = orc_window(md, n_steps, m, u, dW, dLam, &it);
+  *J = orc_nll(nx, n_obs, u, y, sigma) + girsanov_term(n_steps, md->n_modes, md->dt, dW, dLam);
+  free(m);
+  free(u);
+  return st;
+}
+
+/* rows of A(dv) */
+static void step_rows(const orc_model *md, const double *dv, double *lo, double *di, double *up) {
+  int32_t n = md->nx;
+  double h = md->L / n, dt = md->dt, mu = md->mu;
+  for (int32_t i = 0; i < n; ++i) {
+    double vm = dv[wrap(i - 1, n)], vp = dv[wrap(i + 1, n)];
+    lo[i] = h / 6.0 + 0.5 * mu * dt * (-1.0 / h) + 0.5 * (-0.5 * vm);
+    di[i] = 2.0 * h / 3.0 + 0.5 * mu * dt * (2.0 / h) + 0.5 * (0.5 * vp - 0.5 * vm);
+    up[i] = h / 6.0 + 0.5 * mu * dt * (-1.0 / h) + 0.5 * (0.5 * vp);
+  }
+}
+
+/* H w = z (Helmholtz matrix, pivoted cyclic solve) */
+static int helm_solve(const orc_model *md, const double *z, double *w) {
+  int32_t n = md->nx;
+  double h = md->L / n, a2 = md->alpha * md->alpha;
+  double *lo = (double *)malloc(sizeof(double) * n), *di = (double *)malloc(sizeof(double) * n);
+  double *up = (double *)malloc(sizeof(double) * n);
+  for (int32_t i = 0; i < n; ++i) {
+    lo[i] = h / 6.0 + a2 * (-1.0 / h);
+    di[i] = 2.0 * h / 3.0 + a2 * (2.0 / h);
+    up[i] = h / 6.0 + a2 * (-1.0 / h);
+  }
+  int st = orc_cyclic_solve(n, lo, di, up, z, w);
+  free(lo);
+  free(di);
+  free(up);
+  return st;
+}
+
+/* dU^n = sum_q xi_q (dW^n_q + dLambda^n_q) */
+static void noise_field(const orc_model *md, const double *dW, const double *dLam, double *dU) {
+  int32_t n = md->nx;
+  for (int32_t i = 0; i < n; ++i) dU[i] = 0.0;
+  for (int32_t q = 0; q < md->n_modes; ++q) {
+    double inc = dW[q] + (dLam ? dLam[q] : 0.0);
+    for (int32_t i = 0; i < n; ++i) dU[i] += md->xi[(size_t)q * n + i] * inc;
+  }
+}
+
+int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                   int32_t n_steps, const double *m0, const double *u0, const double *dW,
+                   const double *dLam, double *J, double *grad) {
+  int32_t nx = md->nx, nq = md->n_modes;
+  double h = md->L / nx, dt = md->dt;
+  size_t sz = sizeof(double) * nx;
+  double *M = (double *)malloc(sz * (size_t)(n_steps + 1)), *U = (double *)malloc(sz * (size_t)(n_steps + 1));
+  memcpy(M, m0, sz);
+  memcpy(U, u0, sz);
+  int st = ORC_OK;
+  for (int32_t n = 0; n < n_steps && st == ORC_OK; ++n) {
+    memcpy(M + (size_t)(n + 1) * nx, M + (size_t)n * nx, sz);
+    memcpy(U + (size_t)(n + 1) * nx, U + (size_t)n * nx, sz);
+    int32_t it;
+    st = orc_step(md, M + (size_t)(n + 1) * nx, U + (size_t)(n + 1) * nx, dW + (size_t)n * nq,
+                  dLam ? dLam + (size_t)n * nq : NULL, &it);
+  }
+  const double *uN = U + (size_t)n_steps * nx;
+  *J = orc_nll(nx, n_obs, uN, y, sigma) + girsanov_term(n_steps, nq, dt, dW, dLam);
+
+  double *lam = (double *)malloc(sz), *tmp = (double *)malloc(sz), *tmp2 = (double *)malloc(sz);
+  double *nu = (double *)malloc(sz), *nun = (double *)malloc(sz), *s = (double *)malloc(sz);
+  double *dv = (double *)malloc(sz), *dU = (double *)malloc(sz), *rhs = (double *)malloc(sz);
+  double *lo = (double *)malloc(sz), *di = (double *)malloc(sz), *up = (double *)malloc(sz);
+  double *tlo = (double *)malloc(sz), *tup = (double *)malloc(sz), *g = (double *)malloc(sz);
+  /* seed lambda_N = M H^{-1} P^T residual */
+  obs_adjoint(nx, n_obs, uN, y, sigma, tmp);
+  if (st == ORC_OK) st = helm_solve(md, tmp, tmp2);
+  orc_apply_mass(nx, h, tmp2, lam);
+  for (int32_t n = n_steps - 1; n >= 0 && st == ORC_OK; --n) {
+    const double *mn = M + (size_t)n * nx, *mn1 = M + (size_t)(n + 1) * nx;
+    const double *un = U + (size_t)n * nx, *un1 = U + (size_t)(n + 1) * nx;
+    noise_field(md, dW + (size_t)n * nq, dLam ? dLam + (size_t)n * nq : NULL, dU);
+    for (int32_t i = 0; i < nx; ++i) {
+      s[i] = mn[i] + mn1[i];
+      dv[i] = dt * 0.5 * (un[i] + un1[i]) + dU[i];
+    }
+    step_rows(md, dv, lo, di, up);
+    /* A^T rows: sub = up[i-1], diag = di[i], super = lo[i+1] */
+    for (int32_t i = 0; i < nx; ++i) {
+      tlo[i] = up[wrap(i - 1, nx)];
+      tup[i] = lo[wrap(i + 1, nx)];
+    }
+    st = orc_cyclic_solve(nx, tlo, di, tup, lam, nu);
+    int conv = 0;
+    for (int32_t k = 0; k < md->picard_max && st == ORC_OK; ++k) {
+      advect_transpose(nx, s, nu, tmp);
+      st = helm_solve(md, tmp, tmp2);
+      if (st != ORC_OK) break;
+      orc_apply_mass(nx, h, tmp2, tmp);
+      for (int32_t i = 0; i < nx; ++i) rhs[i] = lam[i] - 0.25 * dt * tmp[i];
+      st = orc_cyclic_solve(nx, tlo, di, tup, rhs, nun);
+      double diff = 0.0, scale = 0.0;
+      for (int32_t i = 0; i < nx; ++i) {
+        double d = fabs(nun[i] - nu[i]);
+        if (d > diff) diff = d;
+        if (fabs(nun[i]) > scale) scale = fabs(nun[i]);
+      }
+      memcpy(nu, nun, sz);
+      if (diff <= md->picard_tol * scale) {
+        conv = 1;
+        break;
+      }
+    }
+    if (st == ORC_OK && !conv) st = ORC_E_NONCONVERGED;
+    /* gradient with respect to dU^n, then the modes */
+    advect_transpose(nx, s, nu, g);
+    for (int32_t q = 0; q < nq; ++q) {
+      double acc = 0.0;
+      for (int32_t i = 0; i < nx; ++i) acc += md->xi[(size_t)q * nx + i] * (-0.5 * g[i]);
+      double l = dLam ? dLam[(size_t)n * nq + q] : 0.0;
+      grad[(size_t)n * nq + q] = acc + (l + dW[(size_t)n * nq + q]) / dt;
+    }
+    /* lambda_n = 2 M nu - lambda_{n+1} */
+    orc_apply_mass(nx, h, nu, tmp);
+    for (int32_t i = 0; i < nx; ++i) lam[i] = 2.0 * tmp[i] - lam[i];
+  }
+  free(M); free(U); free(lam); free(tmp); free(tmp2); free(nu); free(nun); free(s); free(dv);
+  free(dU); free(rhs); free(lo); free(di); free(up); free(tlo); free(tup); free(g);
+  return st;
+}
+
+/* Forward-mode (tangent-linear) gradient with dense matrices, for small nx:
+ * for every control component (n0, q) the perturbation of m is propagated
+ * through the linearised steps dm^{n+1} = Jac^{-1}(2 M dm^n - D(s) d(dU)/2) - dm^n
+ * with Jac = A + (dt/4) D(s) H^{-1} M assembled densely and solved by dense LU.
+ * Independent of the reverse sweep's transposed solves. */
+int orc_nudge_grad_tangent(const orc_model *md, int32_t n_obs, const double *y,
+                           const double *sigma, int32_t n_steps, const double *m0,
+                           const double *u0, const double *dW, const double *dLam,
+                           double *grad) {
+  int32_t nx = md->nx, nq = md->n_modes;
+  double h = md->L / nx, dt = md->dt;
+  size_t sz = sizeof(double) * nx, sz2 = sizeof(double) * (size_t)nx * nx;
+  double *M = (double *)malloc(sz * (size_t)(n_steps + 1)), *U = (double *)malloc(sz * (size_t)(n_steps + 1));
+  memcpy(M, m0, sz);
+  memcpy(U, u0, sz);
+  int st = ORC_OK;
+  for (int32_t n = 0; n < n_steps && st == ORC_OK; ++n) {
+    memcpy(M + (size_t)(n + 1) * nx, M + (size_t)n * nx, sz);
+    memcpy(U + (size_t)(n + 1) * nx, U + (size_t)n * nx, sz);
+    int32_t it;
+    st = orc_step(md, M + (size_t)(n + 1) * nx, U + (size_t)(n + 1) * nx, dW + (size_t)n * nq,
+                  dLam ? dLam + (size_t)n * nq : NULL, &it);
+  }
+  /* dense R = H^{-1} M */
+  double *R = (double *)malloc(sz2), *col = (double *)malloc(sz), *e = (double *)malloc(sz);
+  double *Jm = (double *)malloc(sz2), *dm = (double *)malloc(sz), *rhs = (double *)malloc(sz);
+  double *tmp = (double *)malloc(sz), *dUd = (double *)malloc(sz), *s = (double *)malloc(sz);
+  double *dv = (double *)malloc(sz), *dU = (double *)malloc(sz), *lo = (double *)malloc(sz);
+  double *di = (double *)malloc(sz), *up = (double *)malloc(sz), *x = (double *)malloc(sz);
+  double *adjN = (double *)malloc(sz), *t2 = (double *)malloc(sz);
+  for (int32_t j = 0; j < nx && st == ORC_OK; ++j) {
+    for (int32_t i = 0; i < nx; ++i) e[i] = i == j ? 1.0 : 0.0;
+    orc_apply_mass(nx, h, e, tmp);
+    st = helm_solve(md, tmp, col);
+    for (int32_t i = 0; i < nx; ++i) R[(size_t)i * nx + j] = col[i];
+  }
+  /* dPhi/dm^N = R^T P^T residual, as a row vector */
+  obs_adjoint(nx, n_obs, U + (size_t)n_steps * nx, y, sigma, t2);
+  for (int32_t j = 0; j < nx; ++j) {
+    double a = 0.0;
+    for (int32_t i = 0; i < nx; ++i) a += R[(size_t)i * nx + j] * t2[i];
+    adjN[j] = a;
+  }
+  for (int32_t n0 = 0; n0 < n_steps && st == ORC_OK; ++n0)
+    for (int32_t q = 0; q < nq && st == ORC_OK; ++q) {
+      for (int32_t i = 0; i < nx; ++i) dm[i] = 0.0;
+      for (int32_t n = n0; n < n_steps && st == ORC_OK; ++n) {
+        const double *mn = M + (size_t)n * nx, *mn1 = M + (size_t)(n + 1) * nx;
+        const double *un = U + (size_t)n * nx, *un1 = U + (size_t)(n + 1) * nx;
+        noise_field(md, dW + (size_t)n * nq, dLam ? dLam + (size_t)n * nq : NULL, dU);
+        for (int32_t i = 0; i < nx; ++i) {
+          s[i] = mn[i] + mn1[i];
+          dv[i] = dt * 0.5 * (un[i] + un1[i]) + dU[i];
+        }
+        step_rows(md, dv, lo, di, up);
+        /* Jac = A + (dt/4) D(s) R, column by column: D(s) R e_j = C(R e_j) s */
+        for (int32_t i = 0; i < (int32_t)((size_t)nx * nx); ++i) Jm[i] = 0.0;
+        for (int32_t i = 0; i < nx; ++i) {
+          Jm[(size_t)i * nx + wrap(i - 1, nx)] += lo[i];
+          Jm[(size_t)i * nx + i] += di[i];
+          Jm[(size_t)i * nx + wrap(i + 1, nx)] += up[i];
+        }
+        for (int32_t j = 0; j < nx; ++j) {
+          for (int32_t i = 0; i < nx; ++i) col[i] = R[(size_t)i * nx + j];
+          orc_apply_advect(nx, col, s, tmp);
+          for (int32_t i = 0; i < nx; ++i) Jm[(size_t)i * nx + j] += 0.25 * dt * tmp[i];
+        }
+        orc_apply_mass(nx, h, dm, rhs);
+        for (int32_t i = 0; i < nx; ++i) rhs[i] *= 2.0;
+        if (n == n0) {
+          for (int32_t i = 0; i < nx; ++i) dUd[i] = md->xi[(size_t)q * nx + i];
+          orc_apply_advect(nx, dUd, s, tmp); /* C(d dU) s = D(s) d dU */
+          for (int32_t i = 0; i < nx; ++i) rhs[i] -= 0.5 * tmp[i];
+        }
+        st = orc_dense_solve(nx, Jm, rhs, x);
+        for (int32_t i = 0; i < nx; ++i) dm[i] = x[i] - dm[i];
+      }
+      double a = 0.0;
+      for (int32_t i = 0; i < nx; ++i) a += adjN[i] * dm[i];
+      double l = dLam ? dLam[(size_t)n0 * nq + q] : 0.0;
+      grad[(size_t)n0 * nq + q] = a + (l + dW[(size_t)n0 * nq + q]) / dt;
+    }
+  free(M); free(U); free(R); free(col); free(e); free(Jm); free(dm); free(rhs); free(tmp);
+  free(dUd); free(s); free(dv); free(dU); free(lo); free(di); free(up); free(x); free(adjN);
+  free(t2);
+  return st;
+}
+
+/* ========================================================================== */
+/* L-BFGS with backtracking Armijo search.  The paper optimises the nudging    */
+/* objective with BFGS through an automatic adjoint (section 3.1.3); here the  */
+/* limited-memory variant (Nocedal & Wright, Algorithms 7.4/7.5):              */
+/*  * stop when |g|_inf <= gtol (1 + |f|) or after max_iter accepted steps;     */
+/*  * direction by the two-loop recursion over the last `mem` pairs, with      */
+/*    H0 = gamma I, gamma = s.y / y.y of the newest pair, or gamma = h0 when    */
+/*    no pair is stored (the caller passes dt: the inverse Hessian of the       */
+/*    Girsanov term);                                                          */
+/*  * a direction with g.p >= 0 drops the memory and restarts from -h0 g;      */
+/*  * trial x + a p, a = 1, 1/2, ... (at most max_back halvings); accept when   */
+/*    f(trial) is finite and f(trial) <= f + c1 a g.p + 1e-13 |f|, c1 = 1e-4:   */
+/*    the last term lets a step pass whose decrease is below the rounding of f  */
+/*    near the optimum, where the plain test fails on rounding alone;          */
+/*  * the pair (s, y) is kept when s.y > 1e-10 |s|_2 |y|_2.                     */
+/* Status: 0 converged, 1 iteration cap, 2 line search failed, < 0 objective   */
+/* error.                                                                      */
+/* ========================================================================== */
+int orc_lbfgs(int32_t n, orc_objective fn, void *ctx, double *x, double h0, double gtol,
+              int32_t max_iter, int32_t mem, int32_t max_back, double *f_out, int32_t *iters,
+              int32_t *evals) {
+  double *g = (double *)malloc(sizeof(double) * n), *p = (double *)malloc(sizeof(double) * n);
+  double *xt = (double *)malloc(sizeof(double) * n), *gt = (double *)malloc(sizeof(double) * n);
+  double *S = (double *)malloc(sizeof(double) * n * mem), *Y = (double *)malloc(sizeof(double) * n * mem);
+  double *rho = (double *)malloc(sizeof(double) * mem), *al = (double *)malloc(sizeof(double) * mem);
+  int32_t head = 0, count = 0, k = 0, ne = 0, status = 1;
+  double f;
+  int st = fn(ctx, x, &f, g);
+  ++ne;
+  if (st != 0) status = st < 0 ? st : -1;
+  while (st == 0) {
+    double gmax = 0.0;
+    for (int32_t i = 0; i < n; ++i) gmax = fmax(gmax, fabs(g[i]));
+    if (gmax <= gtol * (1.0 + fabs(f))) {
+      status = 0;
+      break;
+    }
+    if (k >= max_iter) {
+      status = 1;
+      break;
+    }
+    /* two-loop recursion: newest pair first, then oldest first */
+    for (int32_t i = 0; i < n; ++i) p[i] = -g[i];
+    for (int32_t c = 0; c < count; ++c) {
+      int32_t j = (head - 1 - c + mem) % mem;
+      double d = 0.0;
+      for (int32_t i = 0; i < n; ++i) d += S[j * n + i] * p[i];
+      al[j] = rho[j] * d;
+      for (int32_t i = 0; i < n; ++i) p[i] -= al[j] * Y[j * n + i];
+    }
+    double gamma = h0;
+    if (count > 0) {
+      int32_t j = (head - 1 + mem) % mem;
+      double sy = 0.0, yy = 0.0;
+      for (int32_t i = 0; i < n; ++i) {
+        sy += S[j * n + i] * Y[j * n + i];
+        yy += Y[j * n + i] * Y[j * n + i];
+      }
+      gamma = sy / yy;
+    }
+    for (int32_t i = 0; i < n; ++i) p[i] *= gamma;
+    for (int32_t c = count - 1; c >= 0; --c) {
+      int32_t j = (head - 1 - c + mem) % mem;
+      double d = 0.0;
+      for (int32_t i = 0; i < n; ++i) d += Y[j * n + i] * p[i];
+      double b = rho[j] * d;
+      for (int32_t i = 0; i < n; ++i) p[i] += (al[j] - b) * S[j * n + i];
+    }
+    double gp = 0.0;
+    for (int32_t i = 0; i < n; ++i) gp += g[i] * p[i];
+    if (!(gp < 0.0)) {
+      count = 0;
+      head = 0;
+      gp = 0.0;
+      for (int32_t i = 0; i < n; ++i) {
+        p[i] = -h0 * g[i];
+        gp += g[i] * p[i];
+      }
+    }
+    /* backtracking */
+    double a = 1.0, ft = 0.0;
+    int accepted = 0;
+    for (int32_t b = 0; b <= max_back; ++b) {
+      for (int32_t i = 0; i < n; ++i) xt[i] = x[i] + a * p[i];
+      st = fn(ctx, xt, &ft, gt);
+      ++ne;
+      if (st < 0) break;
+      if (st == 0 && isfinite(ft) && ft <= f + 1e-4 * a * gp + 1e-13 * fabs(f)) {
+        accepted = 1;
+        break;
+      }
+      st = 0;
+      a *= 0.5;
+    }
+    if (st < 0) {
+      status = st;
+      break;
+    }
+    if (!accepted) {
+      status = 2;
+      break;
+    }
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+      double si = xt[i] - x[i], yi = gt[i] - g[i];
+      S[head * n + i] = si;
+      Y[head * n + i] = yi;
+      sy += si * yi;
+      ss += si * si;
+      yy += yi * yi;
+    }
+    if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
+      rho[head] = 1.0 / sy;
+      head = (head + 1) % mem;
+      if (count < mem) ++count;
+    }
+    memcpy(x, xt, sizeof(double) * n);
+    memcpy(g, gt, sizeof(double) * n);
+    f = ft;
+    ++k;
+  }
+  *f_out = f;
+  if (iters) *iters = k;
+  if (evals) *evals = ne;
+  free(g); free(p); free(xt); free(gt); free(S); free(Y); free(rho); free(al);
+  return status;
+}
+
+/* Objective of one adapted stage: from (m, u) run `n_steps` steps with zero
+ * Brownian increments, the control x in the first step only and zero control
+ * afterwards; f = Phi(u^N) + |x|^2 / (2 dt). */
+typedef struct {
+  const orc_model *md;
+  int32_t n_obs, n_steps;
+  const double *y, *sigma, *m, *u;
+  double *dW, *dLam, *grad;
+} stage_ctx;
+
+static int stage_objective(void *vctx, const double *x, double *f, double *g) {
+  stage_ctx *c = (stage_ctx *)vctx;
+  int32_t nq = c->md->n_modes;
+  memcpy(c->dLam, x, sizeof(double) * nq);
+  int st = orc_nudge_grad(c->md, c->n_obs, c->y, c->sigma, c->n_steps, c->m, c->u, c->dW,
+                          c->dLam, f, c->grad);
+  memcpy(g, c->grad, sizeof(double) * nq);
+  if (st == ORC_E_NONFINITE || st == ORC_E_NONCONVERGED) return 1; /* reject trial */
+  return st == ORC_OK ? 0 : st;
+}
+
+/* Sequential adapted nudging of one particle over a window (section 3.1.3,
+ * the stage-by-stage scheme): for each step n the control dLambda^n is
+ * optimised with the later increments and controls set to zero, then the
+ * increment dW^n is revealed and the state advanced with dW^n + dLambda^n.
+ * dLam holds the warm start on entry and the controls on exit; logG is the
+ * log Girsanov factor of the realised path. */
+int orc_nudge_particle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       int32_t n_steps, double *m, double *u, const double *dW, double *dLam,
+                       const orc_lbfgs_opts *opt, double *logG, int32_t *iters_total,
+                       int32_t *evals_total, int32_t *worst_status) {
+  int32_t nx = md->nx, nq = md->n_modes;
+  stage_ctx c;
+  c.md = md;
+  c.n_obs = n_obs;
+  c.y = y;
+  c.sigma = sigma;
+  c.m = m;
+  c.u = u;
+  c.dW = (double *)calloc((size_t)n_steps * nq, sizeof(double));
+  c.dLam = (double *)calloc((size_t)n_steps * nq, sizeof(double));
+  c.grad = (double *)calloc((size_t)n_steps * nq, sizeof(double));
+  double lg = 0.0;
+  int32_t it_tot = 0, ev_tot = 0, worst = 0;
+  int st = ORC_OK;
+  for (int32_t n = 0; n < n_steps; ++n) {
+    c.n_steps = n_steps - n;
+    double *x = dLam + (size_t)n * nq, f;
+    int32_t it = 0, ev = 0;
+    int ls = orc_lbfgs(nq, stage_objective, &c, x, md->dt, opt->gtol, opt->max_iter, opt->mem,
+                       opt->max_back, &f, &it, &ev);
+    it_tot += it;
+    ev_tot += ev;
+    if (ls < 0) {
+      st = ls;
+      break;
+    }
+    if (ls > worst) worst = ls;
+    int32_t pit;
+    st = orc_step(md, m, u, dW + (size_t)n * nq, x, &pit);
+    if (st != ORC_OK) break;
+    for (int32_t q = 0; q < nq; ++q)
+      lg -= 0.5 * x[q] * x[q] / md->dt + x[q] * dW[(size_t)n * nq + q] / md->dt;
+  }
+  (void)nx;
+  free(c.dW);
+  free(c.dLam);
+  free(c.grad);
+  *logG = lg;
+  if (iters_total) *iters_total = it_tot;
+  if (evals_total) *evals_total = ev_tot;
+  if (worst_status) *worst_status = worst;
+  return st;
+}
+
+int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       int32_t n_particles, int32_t n_steps, double *m, double *u, const double *dW,
+                       double *dLam, const orc_lbfgs_opts *opt, double *logG, int32_t *iters,
+                       int32_t *evals, int32_t *lbfgs_status, int32_t *status, int32_t n_threads) {
+  int32_t nx = md->nx, nq = md->n_modes;
+  int worst = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int32_t p = 0; p < n_particles; ++p) {
+    int st = orc_nudge_particle(md, n_obs, y, sigma, n_steps, m + (size_t)p * nx,
+                                u + (size_t)p * nx, dW + (size_t)p * n_steps * nq,
+                                dLam + (size_t)p * n_steps * nq, opt, logG + p,
+                                iters ? iters + p : NULL, evals ? evals + p : NULL,
+                                lbfgs_status ? lbfgs_status + p : NULL);
+    if (status) status[p] = st;
+    if (st != ORC_OK) {
+#pragma omp critical
+      if (worst == ORC_OK) worst = st;
+    }
+  }
+  return worst;
+}

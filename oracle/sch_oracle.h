@@ -145,6 +145,38 @@ int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, cons
                        int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
                        int32_t n_threads);
 
+/* ---- nudging objective and its gradient ---- */
+int orc_nudge_objective(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                        int32_t n_steps, const double *m0, const double *u0, const double *dW,
+                        const double *dLam, double *J);
+int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                   int32_t n_steps, const double *m0, const double *u0, const double *dW,
+                   const double *dLam, double *J, double *grad);
+int orc_nudge_grad_tangent(const orc_model *md, int32_t n_obs, const double *y,
+                           const double *sigma, int32_t n_steps, const double *m0,
+                           const double *u0, const double *dW, const double *dLam,
+                           double *grad);
+
+/* ---- L-BFGS and the sequential adapted nudging scheme ---- */
+typedef int (*orc_objective)(void *ctx, const double *x, double *f, double *g);
+typedef struct {
+  double gtol;      /* stop at |g|_inf <= gtol (1 + |f|) */
+  int32_t max_iter; /* accepted steps per stage */
+  int32_t mem;      /* stored pairs */
+  int32_t max_back; /* halvings per line search */
+} orc_lbfgs_opts;
+int orc_lbfgs(int32_t n, orc_objective fn, void *ctx, double *x, double h0, double gtol,
+              int32_t max_iter, int32_t mem, int32_t max_back, double *f_out, int32_t *iters,
+              int32_t *evals);
+int orc_nudge_particle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       int32_t n_steps, double *m, double *u, const double *dW, double *dLam,
+                       const orc_lbfgs_opts *opt, double *logG, int32_t *iters_total,
+                       int32_t *evals_total, int32_t *worst_status);
+int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       int32_t n_particles, int32_t n_steps, double *m, double *u, const double *dW,
+                       double *dLam, const orc_lbfgs_opts *opt, double *logG, int32_t *iters,
+                       int32_t *evals, int32_t *lbfgs_status, int32_t *status, int32_t n_threads);
+
 #ifdef __cplusplus
 }
 #endif
