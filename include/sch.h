@@ -105,15 +105,19 @@ const char *sch_last_error(void);
 /* Library version, 100 * major + minor. */
 int sch_version(void);
 
-/* Workspace sizes in bytes.  `which` is one of the SCH_WS_* values;
- * n_jitter matters for SCH_WS_JITTER and SCH_WS_TEMPERED (pCN moves per
- * call / per tempering step).  Returns 0 for invalid arguments. */
+/* Workspace sizes in bytes.  `which` is one of the SCH_WS_* values; `extra`
+ * is the number of pCN moves per call / per tempering step for SCH_WS_JITTER
+ * and SCH_WS_TEMPERED, the checkpoint interval (steps) for SCH_WS_NUDGE_GRAD
+ * and SCH_WS_NUDGE, and ignored otherwise.  Returns 0 for invalid
+ * arguments. */
 #define SCH_WS_RESAMPLE 1
 #define SCH_WS_BOOTSTRAP 2
 #define SCH_WS_TEMPERED 3
 #define SCH_WS_JITTER 4
+#define SCH_WS_NUDGE_GRAD 5
+#define SCH_WS_NUDGE 6
 size_t sch_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
-                           int32_t n_steps, int32_t n_jitter);
+                           int32_t n_steps, int32_t extra);
 
 /* --------------------------------------------------------------------------
  * Noise.  dW[p][n][q] = sqrt(dt) z, z ~ N(0,1) by Box-Muller from one Philox
@@ -243,6 +247,75 @@ int sch_jitter_pcn(const sch_model *model, const sch_obs *obs, const sch_rng *rn
                    void *stream);
 
 /* --------------------------------------------------------------------------
+ * Nudging (section 3.1.3).  The control dLambda^n enters each step beside
+ * the increment (eq. "SCH nudge": dU^n = sum_q xi_q (dW^n_q + dLambda^n_q)),
+ * and the particle's log-weight gains the log of the discrete Girsanov
+ * factor (eq. "girsanov DG approx" with the control per step dLambda =
+ * Lambda dt):  log G = -sum_n (|dLambda^n|^2 / 2 + dLambda^n . dW^n) / dt.
+ * (This is the ratio of the N(0, dt) density of the increment to that of the
+ * shifted increment; the continuous form in the paper carries the opposite
+ * sign on the stochastic integral.)
+ *
+ * sch_nudge_grad: for every particle the objective
+ *   J = phi(u^S) - log G
+ * of one window of n_steps steps from (m0, u0) (phi as in sch_loglik) and its
+ * gradient dJ/d(dLambda) by the discrete adjoint of the implicit-midpoint
+ * steps: exact for the converged steps, including the dependence of the
+ * advecting velocity on the new state through the Helmholtz relation.  The
+ * forward pass keeps the state every ckpt_every steps; the reverse pass
+ * recomputes each segment from its checkpoint.
+ *   m0, u0   [n][nx]; dW, dLambda [n][n_steps][n_modes] or NULL (zero)
+ *   J        out [n] (+infinity where a step failed)
+ *   grad     out [n][n_steps][n_modes]
+ *   status   out [n] or NULL: SCH_OK, or the first failure (forward or adjoint)
+ *   workspace >= sch_workspace_bytes(SCH_WS_NUDGE_GRAD, model, n, n_steps,
+ *               ckpt_every)
+ * ------------------------------------------------------------------------ */
+int sch_nudge_grad(const sch_model *model, const sch_obs *obs, int32_t n_particles,
+                   int32_t n_steps, const double *m0, const double *u0, const double *dW,
+                   const double *dLambda, int32_t ckpt_every, double *J, double *grad,
+                   int32_t *status, void *workspace, void *stream);
+
+/* L-BFGS settings of sch_nudge_run (host struct).  The paper optimises with
+ * BFGS; the limited-memory form keeps the per-particle state small.
+ *   gtol      stop when |grad|_inf <= gtol (1 + |J|)
+ *   max_iter  accepted steps per stage
+ *   mem       stored correction pairs, 1..16
+ *   max_back  step halvings per backtracking (Armijo, c1 = 1e-4) search */
+typedef struct sch_lbfgs_opts {
+  double gtol;
+  int32_t max_iter;
+  int32_t mem;
+  int32_t max_back;
+} sch_lbfgs_opts;
+
+/* sch_nudge_run: the sequential adapted nudging of section 3.1.3 over one
+ * window, for every particle: for n = 0 .. n_steps-1, minimise over
+ * dLambda^n the objective of the remaining steps n .. n_steps-1 with the
+ * later increments and controls set to zero (phi of the window end plus
+ * |dLambda^n|^2 / (2 dt)), by L-BFGS started at dLambda^n (warm_start != 0)
+ * or at zero; then advance the particle one step with dW^n + dLambda^n.
+ *   m, u        in/out [n][nx]: window-start state in, nudged window end out
+ *   dW          [n][n_steps][n_modes]: the increments revealed stage by stage
+ *   dLambda     [n][n_steps][n_modes]: warm start in (if warm_start), controls out
+ *   logG        out [n]: log Girsanov factor of the realised path
+ *   lbfgs_status out [n] or NULL: the largest L-BFGS status over the stages
+ *               (0 converged, 1 iteration cap, 2 line search failed,
+ *               3 objective failed at the starting point)
+ *   iters, evals out [n] or NULL: accepted L-BFGS steps and objective
+ *               evaluations summed over the stages
+ *   status      out [n] or NULL: SCH_OK or the first failed advance (the
+ *               particle's later stages still run from the kept state)
+ *   workspace   >= sch_workspace_bytes(SCH_WS_NUDGE, model, n, n_steps,
+ *                  ckpt_every)
+ * Synchronises the stream after every batch of objective evaluations. */
+int sch_nudge_run(const sch_model *model, const sch_obs *obs, int32_t n_particles,
+                  int32_t n_steps, double *m, double *u, const double *dW, double *dLambda,
+                  int32_t warm_start, const sch_lbfgs_opts *opts, int32_t ckpt_every,
+                  double *logG, int32_t *lbfgs_status, int32_t *iters, int32_t *evals,
+                  int32_t *status, void *workspace, void *stream);
+
+/* --------------------------------------------------------------------------
  * Filter cycles (host-driven sequences of the calls above; they synchronise
  * the stream to read scalars back).
  *
@@ -297,7 +370,8 @@ int sch_tune_get(int32_t key);
 #define SCH_TK_RESAMPLE 3 /* systematic resampling           */
 #define SCH_TK_GATHER 4   /* particle copies after resampling */
 #define SCH_TK_OTHER 5    /* likelihood, draws, fills        */
-#define SCH_TK_COUNT 6
+#define SCH_TK_NUDGE 6    /* nudging objective + adjoint     */
+#define SCH_TK_COUNT 7
 int sch_timing_enable(int on);
 int sch_timing_reset(void);
 int sch_timing_read(double *ms, int64_t *launches, int64_t *iters);

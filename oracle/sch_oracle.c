@@ -1235,8 +1235,11 @@ int orc_nudge_grad_tangent(const orc_model *md, int32_t n_obs, const double *y,
 /*    the last term lets a step pass whose decrease is below the rounding of f  */
 /*    near the optimum, where the plain test fails on rounding alone;          */
 /*  * the pair (s, y) is kept when s.y > 1e-10 |s|_2 |y|_2.                     */
-/* Status: 0 converged, 1 iteration cap, 2 line search failed, < 0 objective   */
-/* error.                                                                      */
+/* The objective returns 0, or > 0 when it cannot be evaluated at x (a trial  */
+/* point is then rejected like one failing the Armijo test), or < 0 for a hard */
+/* error that ends the run.                                                    */
+/* Status: 0 converged, 1 iteration cap, 2 line search failed, 3 objective     */
+/* failed at the starting point (x unchanged), < 0 hard objective error.       */
 /* ========================================================================== */
 int orc_lbfgs(int32_t n, orc_objective fn, void *ctx, double *x, double h0, double gtol,
               int32_t max_iter, int32_t mem, int32_t max_back, double *f_out, int32_t *iters,
@@ -1249,7 +1252,7 @@ int orc_lbfgs(int32_t n, orc_objective fn, void *ctx, double *x, double h0, doub
   double f;
   int st = fn(ctx, x, &f, g);
   ++ne;
-  if (st != 0) status = st < 0 ? st : -1;
+  if (st != 0) status = st < 0 ? st : 3;
   while (st == 0) {
     double gmax = 0.0;
     for (int32_t i = 0; i < n; ++i) gmax = fmax(gmax, fabs(g[i]));
@@ -1365,8 +1368,7 @@ static int stage_objective(void *vctx, const double *x, double *f, double *g) {
   int st = orc_nudge_grad(c->md, c->n_obs, c->y, c->sigma, c->n_steps, c->m, c->u, c->dW,
                           c->dLam, f, c->grad);
   memcpy(g, c->grad, sizeof(double) * nq);
-  if (st == ORC_E_NONFINITE || st == ORC_E_NONCONVERGED) return 1; /* reject trial */
-  return st == ORC_OK ? 0 : st;
+  return st == ORC_OK ? 0 : 1; /* any failure rejects the point */
 }
 
 /* Sequential adapted nudging of one particle over a window (section 3.1.3,

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "filter.hpp"
 #include "model.hpp"
 
@@ -217,6 +218,80 @@ int launch_helm(const sch_model& md, const Tile& tl, int n, const double* in, do
   });
 }
 
+// Nudging scratch: checkpoints [n][n_segments][2][nx], segment states
+// [n][ckpt_every + 1][2][nx] and two iteration counters; for sch_nudge_run
+// also the batched L-BFGS state.
+struct NudgeWs {
+  double *ckpt, *seg;
+  unsigned long long* acc;
+  LbfgsState lb;
+  double* inc1;
+  int *worst, *iters, *evals, *status, *tmp;
+};
+
+NudgeWs carve_nudge(void* base, bool full, int nx, int nq, int n, int ns, int ce, size_t* bytes) {
+  Carve c(base);
+  NudgeWs w{};
+  const size_t nseg = static_cast<size_t>((ns + ce - 1) / ce);
+  w.ckpt = c.take<double>(static_cast<size_t>(n) * nseg * 2 * nx);
+  w.seg = c.take<double>(static_cast<size_t>(n) * (ce + 1) * 2 * nx);
+  w.acc = c.take<unsigned long long>(2);
+  if (full) {
+    const size_t v = static_cast<size_t>(n) * nq, mq = v * kLbfgsMaxMem;
+    w.lb.x = c.take<double>(v);
+    w.lb.g = c.take<double>(v);
+    w.lb.p = c.take<double>(v);
+    w.lb.xt = c.take<double>(v);
+    w.lb.gt = c.take<double>(v);
+    w.lb.ft = c.take<double>(n);
+    w.lb.f = c.take<double>(n);
+    w.lb.gp = c.take<double>(n);
+    w.lb.a = c.take<double>(n);
+    w.lb.S = c.take<double>(mq);
+    w.lb.Y = c.take<double>(mq);
+    w.lb.rho = c.take<double>(static_cast<size_t>(n) * kLbfgsMaxMem);
+    int** ints[] = {&w.lb.head, &w.lb.count, &w.lb.k, &w.lb.nback, &w.lb.phase,
+                    &w.lb.lstat, &w.lb.active, &w.lb.est, &w.lb.evals, &w.worst,
+                    &w.iters, &w.evals, &w.status, &w.tmp};
+    for (int** ip : ints) *ip = c.take<int>(n);
+    w.lb.n_active = c.take<unsigned int>(1);
+    w.inc1 = c.take<double>(v);
+  }
+  if (bytes) *bytes = c.off + 256;
+  return w;
+}
+
+int launch_nudge_grad(const sch_model& md, const Tile& tl, const sch_obs& ob, int n,
+                      int n_steps, int ctrl_steps, const double* m0, const double* u0,
+                      const double* dW, const double* dLam, int ce, double* J, double* grad,
+                      int* status, const int* active, const NudgeWs& W, hipStream_t st) {
+  NudgeArgs A;
+  A.P = make_params(md);
+  A.n_steps = n_steps;
+  A.ctrl_steps = ctrl_steps;
+  A.ckpt_every = ce;
+  A.m0 = m0;
+  A.u0 = u0;
+  A.dW = dW;
+  A.dLam = dLam;
+  A.n_obs = ob.n_obs;
+  A.y = ob.y;
+  A.sigma = ob.sigma;
+  A.J = J;
+  A.grad = grad;
+  A.status = status;
+  A.active = active;
+  A.ckpt = W.ckpt;
+  A.seg = W.seg;
+  A.iters_acc = W.acc;
+  const HelmConst K = make_helm(md, tl);
+  return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+    hipLaunchKernelGGL((k_nudge_grad<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A, K);
+    CHECK_LAUNCH();
+    return SCH_OK;
+  });
+}
+
 int check_obs(const sch_obs* ob) {
   if (!ob || ob->n_obs < 1 || !ob->y || !ob->sigma) return fail(SCH_E_ARG, "bad observations");
   return SCH_OK;
@@ -370,11 +445,18 @@ const char* sch_last_error(void) { return g_err.c_str(); }
 int sch_version(void) { return 100; }
 
 size_t sch_workspace_bytes(int32_t which, const sch_model* model, int32_t n, int32_t n_steps,
-                           int32_t n_jitter) {
+                           int32_t extra) {
   if (n < 1) return 0;
   if (which == SCH_WS_RESAMPLE) return static_cast<size_t>(n) * sizeof(unsigned long long) + 256;
-  if (!model || n_jitter < 0) return 0;
+  if (!model || extra < 0) return 0;
   size_t bytes = 0;
+  if (which == SCH_WS_NUDGE_GRAD || which == SCH_WS_NUDGE) {
+    if (n_steps < 1 || extra < 1) return 0;
+    carve_nudge(nullptr, which == SCH_WS_NUDGE, model->nx, model->n_modes, n, n_steps, extra,
+                &bytes);
+    return bytes;
+  }
+  const int n_jitter = extra;
   carve_cycle(nullptr, which, model->nx, model->n_modes, n, n_steps > 0 ? n_steps : 1, &bytes,
               n_jitter);
   return bytes;
@@ -493,6 +575,96 @@ int sch_jitter_pcn(const sch_model* md, const sch_obs* ob, const sch_rng* rng, i
   return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
                        dW, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
                        W.zeta, W.vacc, S(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Nudging.
+// ---------------------------------------------------------------------------
+int sch_nudge_grad(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_steps,
+                   const double* m0, const double* u0, const double* dW, const double* dLam,
+                   int32_t ce, double* J, double* grad, int32_t* status, void* workspace,
+                   void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n_steps < 1 || ce < 1 || !m0 || !u0 || !J || !grad || !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_nudge_grad");
+  NudgeWs W = carve_nudge(workspace, false, md->nx, md->n_modes, n, n_steps, ce, nullptr);
+  hipStream_t st = S(stream);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 2);
+  return launch_nudge_grad(*md, tl, *ob, n, n_steps, n_steps, m0, u0, dW, dLam, ce, J, grad,
+                           status, nullptr, W, st);
+}
+
+int sch_nudge_run(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_steps, double* m,
+                  double* u, const double* dW, double* dLam, int32_t warm_start,
+                  const sch_lbfgs_opts* opts, int32_t ce, double* logG, int32_t* lbfgs_status,
+                  int32_t* iters, int32_t* evals, int32_t* status, void* workspace,
+                  void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n_steps < 1 || ce < 1 || !m || !u || !dW || !dLam || !logG || !opts ||
+      !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_nudge_run");
+  if (!(opts->gtol >= 0) || opts->max_iter < 0 || opts->mem < 1 ||
+      opts->mem > kLbfgsMaxMem || opts->max_back < 0 || opts->max_back > 60)
+    return fail(SCH_E_ARG, "bad L-BFGS settings");
+  hipStream_t st = S(stream);
+  const int Q = md->n_modes;
+  NudgeWs W = carve_nudge(workspace, true, md->nx, Q, n, n_steps, ce, nullptr);
+  int* worst = lbfgs_status ? lbfgs_status : W.worst;
+  int* its = iters ? iters : W.iters;
+  int* evs = evals ? evals : W.evals;
+  int* sts = status ? status : W.status;
+  const int gb = grid_for(n, 256);
+  hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, logG, 0.0, int64_t(n));
+  for (int* a : {worst, its, evs, sts})
+    hipLaunchKernelGGL(k_fill_i32, dim3(gb), dim3(256), 0, st, a, 0, n);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 2);
+  CHECK_LAUNCH();
+  LbfgsParams LP{n, Q, opts->mem, opts->max_iter, opts->max_back, opts->gtol, md->dt};
+  const int64_t max_ev = 1 + static_cast<int64_t>(opts->max_iter) * (opts->max_back + 1);
+  for (int s = 0; s < n_steps; ++s) {
+    hipLaunchKernelGGL(k_lbfgs_init, dim3(gb), dim3(256), 0, st, W.lb, LP,
+                       warm_start ? dLam + static_cast<size_t>(s) * Q : nullptr, n_steps * Q);
+    CHECK_LAUNCH();
+    bool done = false;
+    for (int64_t ev = 0; ev <= max_ev && !done; ++ev) {
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st,
+                         reinterpret_cast<int*>(W.lb.n_active), 0, 1);
+      {
+        TimedScope ts(SCH_TK_NUDGE, st);
+        if (int rc = launch_nudge_grad(*md, tl, *ob, n, n_steps - s, 1, m, u, nullptr, W.lb.xt,
+                                       ce, W.lb.ft, W.lb.gt, W.lb.est, W.lb.active, W, st))
+          return rc;
+      }
+      hipLaunchKernelGGL(k_lbfgs_update, dim3(gb), dim3(256), 0, st, W.lb, LP);
+      CHECK_LAUNCH();
+      unsigned int act = 0;
+      HIP_TRY(hipMemcpyAsync(&act, W.lb.n_active, sizeof act, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      timing_flush();
+      done = act == 0;
+    }
+    if (!done) return fail(SCH_E_ARG, "L-BFGS did not stop within its evaluation bound");
+    hipLaunchKernelGGL(k_nudge_commit, dim3(gb), dim3(256), 0, st, W.lb, LP, n_steps, s, dW,
+                       dLam, W.inc1, logG, worst, its, evs, md->dt);
+    CHECK_LAUNCH();
+    {
+      TimedScope ts(SCH_TK_WINDOW, st);
+      if (int rc = launch_window(*md, tl, n, 1, m, u, W.inc1, nullptr, W.tmp, nullptr, W.acc, st))
+        return rc;
+    }
+    hipLaunchKernelGGL(k_status_merge, dim3(gb), dim3(256), 0, st, sts, W.tmp, n);
+    CHECK_LAUNCH();
+  }
+  unsigned long long acc[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(acc, W.acc, sizeof acc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  timing_flush();
+  g_tm.iters[SCH_TK_NUDGE] += static_cast<long long>(acc[0] + acc[1]);
+  return SCH_OK;
 }
 
 // ---------------------------------------------------------------------------

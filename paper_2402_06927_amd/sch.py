@@ -27,7 +27,7 @@ SCH_E_DEGENERATE = -5
 SCH_E_HIP = -6
 
 TAG_INIT, TAG_FORECAST, TAG_PCN, TAG_ACCEPT, TAG_RESAMPLE, TAG_OBS, TAG_NUDGE = range(7)
-WS_RESAMPLE, WS_BOOTSTRAP, WS_TEMPERED, WS_JITTER = 1, 2, 3, 4
+WS_RESAMPLE, WS_BOOTSTRAP, WS_TEMPERED, WS_JITTER, WS_NUDGE_GRAD, WS_NUDGE = 1, 2, 3, 4, 5, 6
 
 
 class SchError(RuntimeError):
@@ -66,6 +66,11 @@ class SchCycleStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class SchLbfgsOpts(C.Structure):
+    _fields_ = [("gtol", C.c_double), ("max_iter", C.c_int32), ("mem", C.c_int32),
+                ("max_back", C.c_int32)]
+
+
 def lib():
     """Load libsch.so (built in place by __graft_entry__.build())."""
     global _lib
@@ -101,6 +106,11 @@ def _declare(L):
                                              ST, _vp]),
         "sch_pf_tempered_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
                                             _vp, _vp, _vp, ST, _vp]),
+        "sch_nudge_grad": (C.c_int, [M, O, i32, i32, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp,
+                                     _vp, _vp]),
+        "sch_nudge_run": (C.c_int, [M, O, i32, i32, _vp, _vp, _vp, _vp, i32,
+                                    C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp]),
         "sch_tune_set": (C.c_int, [i32, i32]),
         "sch_tune_get": (C.c_int, [i32]),
         "sch_timing_enable": (C.c_int, [C.c_int]),
@@ -121,7 +131,7 @@ def exported_names():
         "sch_philox_blocks",
         "sch_velocity", "sch_init_momentum", "sch_ensemble_step", "sch_observe", "sch_loglik",
         "sch_temper_ess", "sch_resample", "sch_gather", "sch_jitter_pcn",
-        "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
+        "sch_nudge_grad", "sch_nudge_run", "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
         "sch_timing_enable",
         "sch_timing_reset", "sch_timing_read",
     ]
@@ -182,15 +192,17 @@ class Obs:
 
 
 def workspace_bytes(which: int, model: Model | None, n_particles: int, n_steps: int = 0,
-                    n_jitter: int = 0) -> int:
+                    extra: int = 0) -> int:
+    """Bytes of scratch for a call; `extra` is the pCN moves (WS_JITTER,
+    WS_TEMPERED) or the checkpoint interval (WS_NUDGE_GRAD, WS_NUDGE)."""
     mc = model.c() if model is not None else None
     return int(lib().sch_workspace_bytes(which, C.byref(mc) if mc is not None else None,
-                                         n_particles, n_steps, n_jitter))
+                                         n_particles, n_steps, extra))
 
 
 def workspace(which: int, model: Model | None, n_particles: int, n_steps: int = 0,
-              n_jitter: int = 0, device="cuda") -> torch.Tensor:
-    nb = workspace_bytes(which, model, n_particles, n_steps, n_jitter)
+              extra: int = 0, device="cuda") -> torch.Tensor:
+    nb = workspace_bytes(which, model, n_particles, n_steps, extra)
     if nb <= 0:
         raise SchError(SCH_E_ARG, "invalid workspace request")
     return torch.empty(nb, dtype=torch.uint8, device=device)
@@ -318,7 +330,49 @@ def sch_pf_tempered_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torc
     return st.as_dict()
 
 
-TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other")
+def sch_nudge_grad(model: Model, obs: Obs, m0: torch.Tensor, u0: torch.Tensor,
+                   dW: torch.Tensor | None, dLambda: torch.Tensor | None, J: torch.Tensor,
+                   grad: torch.Tensor, ckpt_every: int = 8, status: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None):
+    """J [n] and dJ/d(dLambda) [n][n_steps][Q]; the window length is grad.shape[1]."""
+    mc, oc = model.c(), obs.c()
+    n, s = grad.shape[0], grad.shape[1]
+    if workspace is None:
+        workspace = globals()["workspace"](WS_NUDGE_GRAD, model, n, s, ckpt_every)
+    _check(lib().sch_nudge_grad(C.byref(mc), C.byref(oc), n, s, _dev(m0, name="m0"),
+                                _dev(u0, name="u0"), _dev(dW, name="dW"),
+                                _dev(dLambda, name="dLambda"), ckpt_every, _dev(J, name="J"),
+                                _dev(grad, name="grad"), _dev(status, torch.int32, "status"),
+                                _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+LBFGS_GTOL, LBFGS_MAX_ITER, LBFGS_MEM, LBFGS_MAX_BACK = 1e-8, 30, 8, 30
+
+
+def sch_nudge_run(model: Model, obs: Obs, m: torch.Tensor, u: torch.Tensor, dW: torch.Tensor,
+                  dLambda: torch.Tensor, logG: torch.Tensor, warm_start: bool = False,
+                  gtol: float = LBFGS_GTOL, max_iter: int = LBFGS_MAX_ITER,
+                  mem: int = LBFGS_MEM, max_back: int = LBFGS_MAX_BACK, ckpt_every: int = 8,
+                  lbfgs_status: torch.Tensor | None = None, iters: torch.Tensor | None = None,
+                  evals: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                  workspace: torch.Tensor | None = None):
+    mc, oc = model.c(), obs.c()
+    n, s = dW.shape[0], dW.shape[1]
+    if workspace is None:
+        workspace = globals()["workspace"](WS_NUDGE, model, n, s, ckpt_every)
+    opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
+    _check(lib().sch_nudge_run(C.byref(mc), C.byref(oc), n, s, _dev(m, name="m"),
+                               _dev(u, name="u"), _dev(dW, name="dW"),
+                               _dev(dLambda, name="dLambda"), 1 if warm_start else 0,
+                               C.byref(opts), ckpt_every, _dev(logG, name="logG"),
+                               _dev(lbfgs_status, torch.int32, "lbfgs_status"),
+                               _dev(iters, torch.int32, "iters"),
+                               _dev(evals, torch.int32, "evals"),
+                               _dev(status, torch.int32, "status"),
+                               _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other", "nudge")
 
 
 def sch_timing_enable(on: bool = True):

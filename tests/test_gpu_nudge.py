@@ -1,0 +1,202 @@
+"""GPU nudging objective, adjoint gradient and batched L-BFGS versus the
+oracle (section 3.1.3), on the same seeded inputs.
+
+Bars: J and the gradient within relative L2 1e-10 of the oracle's reverse
+sweep (both solve every step and every adjoint step to the window's 1e-13
+tolerance); the L-BFGS controls within 1e-6 of their scale (two runs of the
+same deterministic optimiser whose gradients differ by rounding can stop one
+iteration apart, and a last step moves the control by at most about
+gtol (1 + |J|) dt)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import pairing as PR
+from paper_2402_06927_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sch():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_06927_amd import sch as S
+
+    S.lib()
+    return S
+
+
+def T(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _problem(wl, n, ctrl_scale=0.5):
+    """Prior particles, observations of the truth at the end of one window,
+    revealed increments (tag NUDGE) and a random control."""
+    u, m, _, _ = PR.prior(wl, n)
+    y = PR.oracle_observations(wl, 1)[0]
+    dW = O.draw_increments(wl.seed, n, wl.n_steps, wl.n_modes, 0, O.TAG_NUDGE, 0, wl.dt)
+    rng = np.random.default_rng(wl.nx + n)
+    dLam = ctrl_scale * np.sqrt(wl.dt) * rng.standard_normal(dW.shape)
+    return m, u, y, dW, dLam
+
+
+def _obs(sch, wl, y, sigma=None):
+    s = wl.sigma_obs if sigma is None else sigma
+    return sch.Obs(T(y), T(np.full(wl.n_obs, s)))
+
+
+GRAD_CASES = [
+    # nx, n, Q, S, ckpt: several segments with a ragged last one, ragged node
+    # chunks, one segment, one step per segment, single step
+    (256, 5, 4, 20, 8),
+    (100, 3, 4, 9, 4),
+    (600, 3, 8, 10, 3),
+    (1000, 2, 8, 12, 50),
+    (128, 3, 2, 6, 1),
+    (2048, 2, 8, 40, 8),
+    (4096, 1, 8, 9, 8),
+    (64, 2, 4, 1, 8),
+]
+
+
+@pytest.mark.parametrize("nx,n,q,s,ce", GRAD_CASES)
+def test_nudge_grad_parity(sch, nx, n, q, s, ce):
+    _say("nudge_grad", nx, n, q, s, ce)
+    wl = W.NUDGING_2048.scaled(nx=nx, n_modes=q, n_steps=s, n_obs=min(nx, 64))
+    m, u, y, dW, dLam = _problem(wl, n)
+    gm = PR.gpu_model(wl)
+    om = PR.oracle_model(wl)
+    J = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((n, s, q), dtype=torch.float64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    sch.sch_nudge_grad(gm, _obs(sch, wl, y), T(m), T(u), T(dW), T(dLam), J, g, ce, st)
+    assert np.all(N(st) == 0)
+    Jg, gg = N(J), N(g)
+    for p in range(n):
+        rs, Jr, gr = O.nudge_grad(om, y, wl.sigma_obs, m[p], u[p], dW[p], dLam[p])
+        assert rs == 0
+        assert abs(Jg[p] - Jr) <= 1e-10 * abs(Jr)
+        assert PR.rel_l2(gg[p], gr) < PR.REL_TOL, (p, PR.rel_l2(gg[p], gr))
+        gir = (dLam[p] + dW[p]) / wl.dt
+        # the data part alone, on its own scale
+        assert PR.rel_l2(gg[p] - gir, gr - gir) < 1e-9
+
+
+def test_nudge_grad_null_inputs_and_no_data(sch):
+    wl = W.NUDGING_2048.scaled(nx=256, n_steps=6, n_modes=4, n_obs=32)
+    n = 3
+    m, u, y, dW, dLam = _problem(wl, n)
+    gm = PR.gpu_model(wl)
+    om = PR.oracle_model(wl)
+    J = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((n, wl.n_steps, wl.n_modes), dtype=torch.float64, device="cuda")
+    # no increment and no control: J is the plain likelihood, grad its adjoint
+    sch.sch_nudge_grad(gm, _obs(sch, wl, y), T(m), T(u), None, None, J, g)
+    zero = np.zeros_like(dW[0])
+    for p in range(n):
+        _, Jr, gr = O.nudge_grad(om, y, wl.sigma_obs, m[p], u[p], zero, None)
+        assert abs(N(J)[p] - Jr) <= 1e-10 * abs(Jr)
+        assert PR.rel_l2(N(g)[p], gr) < PR.REL_TOL
+    # sigma -> infinity: only the Girsanov term is left
+    sch.sch_nudge_grad(gm, _obs(sch, wl, y, 1e30), T(m), T(u), T(dW), T(dLam), J, g)
+    np.testing.assert_allclose(N(g), (dLam + dW) / wl.dt, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(N(J), np.sum(0.5 * dLam ** 2 + dLam * dW, axis=(1, 2)) / wl.dt,
+                               rtol=1e-13)
+
+
+def test_nudge_grad_full_size_sampled(sch):
+    """Nudging workload at full size (2048 particles, nx = 2048, 40 steps,
+    8 modes, 256 observations, checkpoints every 8 steps); three particles
+    checked against the oracle."""
+    wl = W.NUDGING_2048
+    n = wl.n_particles
+    _say("nudge_grad full size", wl.nx, n, wl.n_steps)
+    m, u, y, dW, dLam = _problem(wl, n)
+    gm = PR.gpu_model(wl)
+    om = PR.oracle_model(wl)
+    J = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((n, wl.n_steps, wl.n_modes), dtype=torch.float64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    sch.sch_nudge_grad(gm, _obs(sch, wl, y), T(m), T(u), T(dW), T(dLam), J, g, 8, st)
+    assert np.all(N(st) == 0)
+    Jg, gg = N(J), N(g)
+    assert np.all(np.isfinite(Jg))
+    for p in (0, 1023, n - 1):
+        _, Jr, gr = O.nudge_grad(om, y, wl.sigma_obs, m[p], u[p], dW[p], dLam[p])
+        assert abs(Jg[p] - Jr) <= 1e-10 * abs(Jr)
+        assert PR.rel_l2(gg[p], gr) < PR.REL_TOL
+
+
+def test_autograd_function_matches_adjoint_and_differences(sch):
+    from paper_2402_06927_amd import nudge
+
+    wl = W.NUDGING_2048.scaled(nx=256, n_steps=10, n_modes=4, n_obs=32)
+    n = 4
+    m, u, y, dW, dLam = _problem(wl, n)
+    gm = PR.gpu_model(wl)
+    obs = _obs(sch, wl, y)
+    x = T(dLam).requires_grad_(True)
+    J, st = nudge.nudge_objective(x, gm, obs, T(m), T(u), T(dW), 4)
+    assert np.all(N(st) == 0)
+    wts = T(np.arange(1, n + 1, dtype=np.float64))
+    (J * wts).sum().backward()
+    Jr = torch.empty(n, dtype=torch.float64, device="cuda")
+    gr = torch.empty_like(x)
+    sch.sch_nudge_grad(gm, obs, T(m), T(u), T(dW), T(dLam), Jr, gr, 4)
+    np.testing.assert_array_equal(N(J), N(Jr))
+    np.testing.assert_allclose(N(x.grad), N(gr) * np.arange(1, n + 1)[:, None, None], rtol=1e-15)
+    # central differences on the GPU, h = 1e-6, along random directions
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal(dLam.shape)
+    d /= np.linalg.norm(d.reshape(n, -1), axis=1)[:, None, None]
+    h = 1e-6
+    Jp, _ = nudge.nudge_objective(T(dLam + h * d), gm, obs, T(m), T(u), T(dW))
+    Jm, _ = nudge.nudge_objective(T(dLam - h * d), gm, obs, T(m), T(u), T(dW))
+    fd = (N(Jp) - N(Jm)) / (2 * h)
+    ad = np.sum(N(gr) * d, axis=(1, 2))
+    scale = np.abs(N(gr)).reshape(n, -1).max(axis=1)
+    assert np.all(np.abs(fd - ad) <= 1e-6 * np.maximum(np.abs(ad), scale)), (fd, ad)
+
+
+@pytest.mark.parametrize("nx,n,q,s,warm", [(128, 6, 4, 6, False), (300, 5, 8, 5, True)])
+def test_nudge_run_parity(sch, nx, n, q, s, warm):
+    _say("nudge_run", nx, n, q, s, warm)
+    wl = W.NUDGING_2048.scaled(nx=nx, n_modes=q, n_steps=s, n_obs=min(nx, 64))
+    m, u, y, dW, dLam = _problem(wl, n, ctrl_scale=0.2)
+    om = PR.oracle_model(wl)
+    ref = O.nudge_ensemble(om, y, wl.sigma_obs, m, u, dW, dLam0=dLam if warm else None)
+    assert ref["worst"] == 0
+    gm = PR.gpu_model(wl)
+    mg, ug = T(m), T(u)
+    dl = T(dLam) if warm else torch.zeros((n, s, q), dtype=torch.float64, device="cuda")
+    logG = torch.empty(n, dtype=torch.float64, device="cuda")
+    ls = torch.empty(n, dtype=torch.int32, device="cuda")
+    its = torch.empty(n, dtype=torch.int32, device="cuda")
+    evs = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    sch.sch_nudge_run(gm, _obs(sch, wl, y), mg, ug, T(dW), dl, logG, warm_start=warm,
+                      lbfgs_status=ls, iters=its, evals=evs, status=st)
+    assert np.all(N(st) == 0)
+    np.testing.assert_array_equal(N(ls), ref["lbfgs_status"])
+    scale = np.abs(ref["dLam"]).max()
+    np.testing.assert_allclose(N(dl), ref["dLam"], rtol=0, atol=1e-6 * scale)
+    np.testing.assert_allclose(N(logG), ref["logG"], rtol=1e-6, atol=1e-8)
+    assert PR.rel_l2(N(ug), ref["u"]) < 1e-8
+    assert PR.rel_l2(N(mg), ref["m"]) < 1e-8
+    # same optimiser: iteration counts agree up to a stop one step apart per stage
+    assert np.all(np.abs(N(its) - ref["iters"]) <= s)
+    _say("iters", N(its), ref["iters"], "evals", N(evs), ref["evals"])
