@@ -39,6 +39,23 @@ def flops_per_node_step(n_modes: int) -> int:
     return 2 * n_modes + 5
 
 
+# HBM traffic of one k_jitter launch at this workload from two rocprofv3
+# counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
+# 1 GiB copy), valid for the kernel sources with the hash below.
+TRAFFIC_JITTER_BYTES = (1842696.2 * 2.0 + 8523888.9 * 1.0) * 1024
+TRAFFIC_SOURCES_HASH = "566572296f593d36"
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("device.hpp", "helm.hpp", "model.hpp"):
+        with open(os.path.join(ROOT, "paper_2402_06927_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -73,6 +90,107 @@ def cpu_baseline(wl, u_start, m_start, n_threads: int, psteps_per_cycle: float):
     }
 
 
+def copy_probe(nbytes: int):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    traffic counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
+    import torch
+
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
+
+
+def bench_nudging(args):
+    """One step = the sequential adapted nudging of one 40-step window for
+    all 2048 particles at Nx = 2048 (8 modes, 256 observations, sigma 0.02,
+    L-BFGS memory 8, checkpoints every 8 steps) plus the likelihood of the
+    nudged ends."""
+    import torch
+
+    from paper_2402_06927_amd import sch
+    from paper_2402_06927_amd import workloads as W
+
+    wl = W.NUDGING_2048
+    if args.particles:
+        wl = wl.scaled(n_particles=args.particles)
+    dev = "cuda"
+    n, nx, Q, S = wl.n_particles, wl.nx, wl.n_modes, wl.n_steps
+    log(f"bench: {wl.name} n={n} nx={nx} Q={Q} S={S} windows={args.warmup}+{args.steps}")
+    xi = torch.tensor(W.mode_table(wl.L, nx, Q, wl.mode_amp), device=dev)
+    model = sch.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
+                      picard_tol=wl.picard_tol, picard_max=wl.picard_max)
+    u_init = torch.tensor(W.initial_velocity(wl, n, wl.seed), device=dev)
+    m_init = torch.empty_like(u_init)
+    sch.sch_init_momentum(model, u_init, m_init)
+    ts = W.truth_seed(wl)
+    ut = torch.tensor(W.initial_velocity(wl, 1, ts), device=dev)
+    mt = torch.empty_like(ut)
+    sch.sch_init_momentum(model, ut, mt)
+    dWt = torch.empty((1, S, Q), dtype=torch.float64, device=dev)
+    sch.sch_draw_increments(ts, 0, 0, sch.TAG_FORECAST, dWt, wl.dt)
+    sch.sch_ensemble_step(model, mt, ut, dWt)
+    y = torch.empty((1, wl.n_obs), dtype=torch.float64, device=dev)
+    sch.sch_observe(model, ut, y)
+    y = y[0] + wl.sigma_obs * torch.tensor(W.obs_noise(wl, ts, 1)[0], device=dev)
+    obs = sch.Obs(y.contiguous(), torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64,
+                                             device=dev))
+    dW = torch.empty((n, S, Q), dtype=torch.float64, device=dev)
+    sch.sch_draw_increments(wl.seed, 0, 0, sch.TAG_NUDGE, dW, wl.dt)
+    ws = sch.workspace(sch.WS_NUDGE, model, n, S, 8)
+    dLam = torch.zeros_like(dW)
+    logG = torch.empty(n, dtype=torch.float64, device=dev)
+    iters = torch.empty(n, dtype=torch.int32, device=dev)
+    evals = torch.empty(n, dtype=torch.int32, device=dev)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def run():
+        m, u = m_init.clone(), u_init.clone()
+        sch.sch_nudge_run(model, obs, m, u, dW, dLam, logG, iters=iters, evals=evals,
+                          workspace=ws)
+        sch.sch_loglik(model, obs, u, phi)
+        return u
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    sch.sch_timing_reset()
+    sch.sch_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sch.sch_timing_enable(False)
+    tim = sch.sch_timing_read()
+    ev = float(evals.double().mean())
+    it = float(iters.double().mean())
+    # step-equivalents per particle: each evaluation of stage s runs S - s
+    # forward steps, recomputes them, and sweeps them backwards
+    out = {
+        "metric": "nudged windows/s (sequential adapted nudging, L-BFGS + adjoint)",
+        "value": round(args.steps / elapsed, 4),
+        "unit": "windows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "filter": "nudging", "nx": nx, "n_particles": n,
+                   "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs, "sigma_obs": wl.sigma_obs,
+                   "lbfgs_mem": 8, "ckpt_every": 8},
+        "lbfgs_evals_per_particle": round(ev, 2),
+        "lbfgs_iters_per_particle": round(it, 2),
+        "mean_phi_nudged": float(phi.mean()),
+        "kernel_ms": {k: round(v["ms"], 3) for k, v in tim.items()},
+        "nudge_launches": tim["nudge"]["launches"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +199,10 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
+    ap.add_argument("--workload", choices=("tempered", "nudging"), default="tempered",
+                    help="tempered: the headline filter; nudging: one nudged window")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="run only a plain copy of BYTES (traffic-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -89,6 +211,13 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.workload == "nudging":
+        bench_nudging(args)
+        return
 
     from paper_2402_06927_amd import sch
     from paper_2402_06927_amd import workloads as W
@@ -177,7 +306,8 @@ def main():
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(j_tflops / PEAK_FP64_TFLOPS, 4),
-        "traffic": None,
+        "traffic": (TRAFFIC_JITTER_BYTES if kernel_sources_hash() == TRAFFIC_SOURCES_HASH
+                    and wl.nx == 4096 and n == 1024 else None),
         "kernel": "k_jitter (fused pCN proposal + window rerun + likelihood + accept)",
         "avg_launch_ms": round(j_ms, 3),
         "algorithmic_flops_per_launch": j_flops / j_launches,
