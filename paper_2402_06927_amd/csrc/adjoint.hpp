@@ -50,35 +50,45 @@ struct NudgeArgs {
   unsigned long long* iters_acc;  // [2]: forward Picard and adjoint fixed-point iterations
 };
 
-// P^T diag(sigma^-2) (P u - y) at the chunk's nodes (node i gathers the
-// observation points of cells i-1 and i).
+// P^T diag(sigma^-2) (P u - y) at the chunk's nodes.  A point in cell e
+// (fraction r) adds (1 - r) res to node e and r res to node e + 1; the thread
+// walks the points of cells start-1 .. start+cnt-1 (one integer division per
+// cell run) and keeps the shares that land on its own nodes.
 template <int PMAX, int NT, bool FULL>
 __device__ void obs_adjoint(const double (&u)[PMAX], const Chunk& ch, int nx, int n_obs,
                             const double* y, const double* sigma, double (&out)[PMAX],
                             RowLds<NT>& L, int t, int& hs) {
   double hl, hr;
   halo<PMAX, NT, FULL>(u, ch.cnt, L, t, hl, hr, hs);
+  const double dn = static_cast<double>(n_obs);
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) out[j] = 0.0;
+  {
+    // the cell left of the chunk (periodic)
+    const int64_t e = ch.start == 0 ? nx - 1 : ch.start - 1;
+    const int64_t lim = (e + 1) * n_obs, base = e * n_obs;
+    for (int64_t o = (base + nx - 1) / nx; o * nx < lim; ++o) {
+      const double r = static_cast<double>(o * nx - base) / dn;
+      const double s = sigma[o];
+      const double res = ((1.0 - r) * hl + r * u[0] - y[o]) / (s * s);
+      out[0] += r * res;
+    }
+  }
+  int64_t o = (static_cast<int64_t>(ch.start) * n_obs + nx - 1) / nx;
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
-    out[j] = 0.0;
     if (!FULL && j >= ch.cnt) continue;
     const int64_t node = ch.start + j;
-    const double ul = left_of<PMAX, FULL>(u, j, hl), ur = right_of<PMAX, FULL>(u, j, ch.cnt, hr);
-    double acc = 0.0;
-    // cell `node`: (1 - r) share
-    for (int64_t o = (node * n_obs + nx - 1) / nx; o < ((node + 1) * n_obs + nx - 1) / nx; ++o) {
-      const double r = static_cast<double>((o * nx) % n_obs) / static_cast<double>(n_obs);
+    const int64_t lim = (node + 1) * n_obs, base = node * n_obs;
+    const double ur = right_of<PMAX, FULL>(u, j, ch.cnt, hr);
+    const bool own_next = (j + 1 < PMAX) && (FULL || j + 1 < ch.cnt);
+    for (; o * nx < lim; ++o) {
+      const double r = static_cast<double>(o * nx - base) / dn;
       const double s = sigma[o];
-      acc += (1.0 - r) * (((1.0 - r) * u[j] + r * ur) - y[o]) / (s * s);
+      const double res = ((1.0 - r) * u[j] + r * ur - y[o]) / (s * s);
+      out[j] += (1.0 - r) * res;
+      if (own_next) out[j + 1 < PMAX ? j + 1 : j] += r * res;
     }
-    // cell `node - 1` (periodic): r share
-    const int64_t e = node == 0 ? nx - 1 : node - 1;
-    for (int64_t o = (e * n_obs + nx - 1) / nx; o < ((e + 1) * n_obs + nx - 1) / nx; ++o) {
-      const double r = static_cast<double>((o * nx) % n_obs) / static_cast<double>(n_obs);
-      const double s = sigma[o];
-      acc += r * (((1.0 - r) * ul + r * u[j]) - y[o]) / (s * s);
-    }
-    out[j] = acc;
   }
 }
 

@@ -223,7 +223,7 @@ template <int PMAX, int NT, bool FULL, class RowF, class DF>
 __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], int cnt,
                                              RowLds<NT>& L, int t) {
   static_assert(PMAX >= 2, "need at least two rows per thread");
-  double cp[PMAX], g[PMAX], k[PMAX];
+  double cp[PMAX], g[PMAX];
   // forward elimination over the interior slots 1..cnt-1; inactive slots
   // (j >= cnt) are given c' = -1, y' = g' = 0 so the back sweep passes the
   // right-spike seed (k = 1) and zeros through them unchanged.
@@ -246,7 +246,8 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     yprev = yj;
     gprev = gj;
   }
-  // back substitution for y and both spikes
+  // back substitution for y and both spikes; the right spike k_j is the
+  // running product of -c'_i over i = j..PMAX-1 and is rebuilt when needed
   double yn = 0.0, gn = 0.0, kn = 1.0;
   double yL = 0.0, gL = 1.0, kL = 0.0;  // last row of the chunk (the interface if cnt == 1)
 #pragma unroll
@@ -256,7 +257,6 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     const double kj = -cp[j] * kn;
     x[j] = yj;
     g[j] = gj;
-    k[j] = kj;
     yn = yj;
     gn = gj;
     kn = kj;
@@ -265,11 +265,11 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
       gL = gj;
       kL = kj;
     }
-  }
-  if (FULL) {
-    yL = x[PMAX - 1];
-    gL = g[PMAX - 1];
-    kL = k[PMAX - 1];
+    if (FULL && j == PMAX - 1) {
+      yL = yj;
+      gL = gj;
+      kL = kj;
+    }
   }
   // interface equation of chunk t
   L.tail_y[t] = yL;
@@ -289,8 +289,12 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
   __syncthreads();
   const double snext = L.s[(t + 1) & (NT - 1)];
   x[0] = s;
+  double kr = 1.0;
 #pragma unroll
-  for (int j = 1; j < PMAX; ++j) x[j] = x[j] + g[j] * s + k[j] * snext;
+  for (int j = PMAX - 1; j >= 1; --j) {
+    kr *= -cp[j];
+    x[j] = x[j] + g[j] * s + kr * snext;
+  }
 }
 
 // Workgroup-wide max of two values and logical or of a flag.

@@ -95,28 +95,49 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
     rec[6] = red2;
   }
   __syncthreads();
-  // carries entering this wavefront from the left / right, and the global
-  // totals (non-periodic scans started from zero at the domain ends)
-  double inm = 1.0, inc = 0.0, allfm = 1.0, allfc = 0.0;
-  double rim = 1.0, ric = 0.0, allbm = 1.0, allbc = 0.0;
-  gred0 = 0.0;
-  gred1 = 0.0;
-  gred2 = 0.0;
-#pragma unroll
-  for (int v = 0; v < W; ++v) {
-    const double* rec = L.helm[slot][v];
-    compose(allfm, allfc, rec[0], rec[1], allfm, allfc);
-    if (v < wv) compose(inm, inc, rec[0], rec[1], inm, inc);
-    gred0 = fmax(gred0, rec[4]);
-    gred1 = fmax(gred1, rec[5]);
-    gred2 = fmax(gred2, rec[6]);
+  // Combine the W records: lane v < W of every wavefront takes record v; the
+  // forward records compose left to right, the backward ones right to left,
+  // by shuffle scans over those lanes (identities in the other lanes).
+  double f0 = 1.0, f1 = 0.0, b0 = 1.0, b1 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  if (lane < W) {
+    const double* rec = L.helm[slot][lane];
+    f0 = rec[0];
+    f1 = rec[1];
+    b0 = rec[2];
+    b1 = rec[3];
+    q0 = rec[4];
+    q1 = rec[5];
+    q2 = rec[6];
   }
 #pragma unroll
-  for (int v = W - 1; v >= 0; --v) {
-    const double* rec = L.helm[slot][v];
-    compose(allbm, allbc, rec[2], rec[3], allbm, allbc);
-    if (v > wv) compose(rim, ric, rec[2], rec[3], rim, ric);
+  for (int d = 1; d < W; d <<= 1) {
+    const double pm = __shfl_up(f0, d), pc = __shfl_up(f1, d);
+    const double qm = __shfl_down(b0, d), qc = __shfl_down(b1, d);
+    if (lane >= d) compose(pm, pc, f0, f1, f0, f1);
+    if (lane + d < W) compose(qm, qc, b0, b1, b0, b1);
+    q0 = fmax(q0, __shfl_xor(q0, d));
+    q1 = fmax(q1, __shfl_xor(q1, d));
+    q2 = fmax(q2, __shfl_xor(q2, d));
   }
+  // lanes >= W reduced zeros among themselves: take lane 0's maxima
+  gred0 = __shfl(q0, 0);
+  gred1 = __shfl(q1, 0);
+  gred2 = __shfl(q2, 0);
+  // totals, and the carries entering this wavefront from the left / right
+  const double allfm = __shfl(f0, W - 1), allfc = __shfl(f1, W - 1);
+  const double allbm = __shfl(b0, 0), allbc = __shfl(b1, 0);
+  double inm = __shfl(f0, wv > 0 ? wv - 1 : 0), inc = __shfl(f1, wv > 0 ? wv - 1 : 0);
+  double rim = __shfl(b0, wv + 1 < W ? wv + 1 : 0), ric = __shfl(b1, wv + 1 < W ? wv + 1 : 0);
+  if (wv == 0) {
+    inm = 1.0;
+    inc = 0.0;
+  }
+  if (wv == W - 1) {
+    rim = 1.0;
+    ric = 0.0;
+  }
+  (void)allfm;
+  (void)allbm;
   // thread-exclusive carries: forward carry at node start-1, product r^start;
   // backward carry at node end+1, product r^(nx - end - 1)
   double pfm, pfc, pbm, pbc;

@@ -179,21 +179,26 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
 
 // Negative log-likelihood of the particle's velocity chunk (eq. loglikeq):
 // each thread takes the observation points that fall in its own cells.
+// Point o lies in cell e = floor(o nx / n_obs) at fraction
+// r = (o nx - e n_obs) / n_obs; the thread finds its first point with one
+// integer division and walks on with integer multiplications only.
 template <int PMAX, int NT, bool FULL>
 __device__ double block_nll(const double (&u)[PMAX], const Chunk& ch, int nx, int n_obs,
                             const double* y, const double* sigma, RowLds<NT>& L, int t, int& hs) {
   double hl, hr;
   halo<PMAX, NT, FULL>(u, ch.cnt, L, t, hl, hr, hs);
   double acc = 0.0;
+  int64_t o = (static_cast<int64_t>(ch.start) * n_obs + nx - 1) / nx;
+  const double dn = static_cast<double>(n_obs);
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
     if (!FULL && j >= ch.cnt) continue;
     const int64_t node = ch.start + j;
-    const int64_t jlo = (node * n_obs + nx - 1) / nx;
-    const int64_t jhi = ((node + 1) * n_obs + nx - 1) / nx;
+    const int64_t lim = (node + 1) * n_obs, base = node * n_obs;
     const double ur = right_of<PMAX, FULL>(u, j, ch.cnt, hr);
-    for (int64_t o = jlo; o < jhi; ++o) {
-      const double r = static_cast<double>((o * nx) % n_obs) / static_cast<double>(n_obs);
+#pragma unroll 1
+    for (; o * nx < lim; ++o) {
+      const double r = static_cast<double>(o * nx - base) / dn;
       const double pu = (1.0 - r) * u[j] + r * ur;
       const double e = (pu - y[o]) / sigma[o];
       acc += e * e;
