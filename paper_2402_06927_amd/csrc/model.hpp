@@ -207,6 +207,34 @@ __device__ double block_nll(const double (&u)[PMAX], const Chunk& ch, int nx, in
   return 0.5 * block_sum<NT>(acc, L, t);
 }
 
+// Node e of a row staged in the auxiliary LDS array `slot` as [slot][j][t]
+// (the chunk layout of chunk_of: the first nx % NT threads hold one node more).
+template <int PMAX, int NT>
+__device__ __forceinline__ double staged_at(const AuxLds<PMAX, NT>& X, int slot, int nx, int e) {
+  const int base = nx / NT, rem = nx % NT, split = rem * (base + 1);
+  if (e < split) return X.a[slot][e % (base + 1)][e / (base + 1)];
+  const int f = e - split;
+  return X.a[slot][f % base][rem + f / base];
+}
+
+// The likelihood of block_nll with the velocity staged in auxiliary LDS
+// slot 0: one thread per observation point.
+template <int PMAX, int NT>
+__device__ double staged_nll(const AuxLds<PMAX, NT>& X, int nx, int n_obs, const double* y,
+                             const double* sigma, RowLds<NT>& L, int t) {
+  const double dn = static_cast<double>(n_obs);
+  double acc = 0.0;
+  for (int o = t; o < n_obs; o += NT) {
+    const int64_t num = static_cast<int64_t>(o) * nx;
+    const int e = static_cast<int>(num / n_obs);
+    const double r = static_cast<double>(num - static_cast<int64_t>(e) * n_obs) / dn;
+    const double pu = (1.0 - r) * staged_at(X, 0, nx, e) + r * staged_at(X, 0, nx, e + 1 == nx ? 0 : e + 1);
+    const double d = (pu - y[o]) / sigma[o];
+    acc += d * d;
+  }
+  return 0.5 * block_sum<NT>(acc, L, t);
+}
+
 template <int PMAX, bool FULL>
 __device__ __forceinline__ void load_chunk(const double* g, const Chunk& ch, double (&v)[PMAX]) {
 #pragma unroll
@@ -317,20 +345,40 @@ __global__ void __launch_bounds__(NT) k_jitter(const JitterArgs A, const HelmCon
     load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u);
     auto inc = [&](int n, int q) { return prop[n * Q + q]; };
     const int st = run_window<PMAX, NT, FULL>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
-    double phin = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t, par.hs);
+    bool accept = false;
+    double phin;
+    if constexpr (AuxLds<PMAX, NT>::kInLds) {
+      // stage the end state (u in slot 0, m in slot 1): no chunk arrays stay
+      // live through the likelihood and the copy-out
+#pragma unroll
+      for (int jj = 0; jj < PMAX; ++jj) {
+        X.a[0][jj][t] = u[jj];
+        X.a[1][jj][t] = m[jj];
+      }
+      __syncthreads();
+      phin = staged_nll<PMAX, NT>(X, nx, A.n_obs, A.y, A.sigma, L, t);
+    } else {
+      phin = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t, par.hs);
+    }
     if (st != SCH_OK || !isfinite(phin)) phin = INFINITY;
     const double v = A.vacc[static_cast<size_t>(j) * gridDim.x + p];
-    bool accept;
-    if (!(phin < INFINITY)) {
-      accept = false;
-    } else {
+    if (phin < INFINITY) {
       const double logr = theta * (phi - phin);
       accept = logr >= 0.0 ? true : (v < exp(logr));
     }
     if (accept) {
       for (int i = t; i < S * Q; i += NT) cur[i] = prop[i];
-      store_chunk<PMAX, FULL>(A.m_end + static_cast<size_t>(p) * nx, ch, m);
-      store_chunk<PMAX, FULL>(A.u_end + static_cast<size_t>(p) * nx, ch, u);
+      if constexpr (AuxLds<PMAX, NT>::kInLds) {
+        double* me = A.m_end + static_cast<size_t>(p) * nx;
+        double* ue = A.u_end + static_cast<size_t>(p) * nx;
+        for (int i = t; i < nx; i += NT) {
+          me[i] = staged_at(X, 1, nx, i);
+          ue[i] = staged_at(X, 0, nx, i);
+        }
+      } else {
+        store_chunk<PMAX, FULL>(A.m_end + static_cast<size_t>(p) * nx, ch, m);
+        store_chunk<PMAX, FULL>(A.u_end + static_cast<size_t>(p) * nx, ch, u);
+      }
       phi = phin;
       ++acc;
     }
