@@ -344,6 +344,83 @@ int sch_pf_tempered_cycle(const sch_model *model, const sch_obs *obs, uint64_t s
                           sch_cycle_stats *stats, void *stream);
 
 /* --------------------------------------------------------------------------
+ * Batched runner: many independent bootstrap filters (sch_pf_bootstrap_cycle
+ * semantics, section 3.1.1) of uneven grid and ensemble sizes advanced one
+ * assimilation cycle at a time for all of them together.  The forecast of
+ * every particle of every instance runs in one persistent kernel per tile
+ * class, whose workgroups take (instance, particle) items from a queue,
+ * longest first; likelihood, weights, conditional resampling and gathers are
+ * batched over instances; all decisions are taken on the device, so a cycle
+ * is captured once into a HIP graph and replayed.
+ *
+ * sch_instance (host struct, one per instance; all arrays device memory the
+ * caller keeps alive while the batch exists):
+ *   nx, n_particles   grid nodes (64..8192) and particles (1..65536)
+ *   xi                [n_modes][nx] noise modes
+ *   m, u              in/out [n_particles][nx] ensemble state
+ *   logw              in/out [n_particles] normalised log-weights (zero after
+ *                     a resampling; start with zeros)
+ *   y                 [cycles][n_obs]: row c holds the observations of cycle c
+ *   sigma             [n_obs]
+ *   seed              generator key of the instance (increments, resampling)
+ *   threads           threads per particle (power of two 64..512; 0 = the
+ *                     default choice of the model calls, or SCH_TUNE_THREADS)
+ * sch_batch_params: physics and filter settings shared by all instances.
+ *
+ * STATUS: the batched runner is switched off in this version --
+ * sch_batch_create returns SCH_E_ARG before any device work (its first GPU
+ * runs stalled and the cause is not yet found).
+ *
+ * sch_batch_create lays the batch out in the caller's workspace (at least
+ * sch_batch_workspace_bytes) and returns an opaque handle (host memory owned
+ * by the library until sch_batch_destroy).  sch_batch_run advances n_cycles
+ * cycles, cycle0 .. cycle0 + n_cycles - 1 (the cycle number selects the
+ * observation row and the generator counters); with use_graph != 0 the cycle
+ * is captured into a HIP graph on first use (on a stream the library creates)
+ * and replayed on `stream` -- this path is currently switched off and returns
+ * SCH_E_ARG; use_graph = 0 enqueues the same kernels directly.  sch_batch_read synchronises `stream` and copies
+ * per-instance results to host arrays (each may be NULL): the ESS of the last
+ * cycle, the number of resamplings since creation, and the first failure of
+ * any particle (SCH_OK if none); picard_iters receives the implicit-solve
+ * iterations summed since creation.  Calls on one batch must not overlap.
+ * ------------------------------------------------------------------------ */
+typedef struct sch_instance {
+  int32_t nx;
+  int32_t n_particles;
+  const double *xi;
+  double *m;
+  double *u;
+  double *logw;
+  const double *y;
+  const double *sigma;
+  uint64_t seed;
+  int32_t threads;
+} sch_instance;
+
+typedef struct sch_batch_params {
+  double L, alpha, mu, dt;
+  int32_t n_modes;    /* 1..64                                     */
+  int32_t n_steps;    /* steps per assimilation window             */
+  int32_t n_obs;      /* observation points per instance           */
+  double ess_frac;    /* resample when ESS < ess_frac * n_particles */
+  double picard_tol;
+  int32_t picard_max;
+} sch_batch_params;
+
+typedef struct sch_batch sch_batch;
+
+size_t sch_batch_workspace_bytes(const sch_batch_params *params, int32_t n_instances,
+                                 const sch_instance *instances);
+int sch_batch_create(const sch_batch_params *params, int32_t n_instances,
+                     const sch_instance *instances, void *workspace, size_t workspace_bytes,
+                     sch_batch **out, void *stream);
+int sch_batch_run(sch_batch *batch, uint32_t cycle0, int32_t n_cycles, int32_t use_graph,
+                  void *stream);
+int sch_batch_read(sch_batch *batch, double *ess, int32_t *resampled, int32_t *status,
+                   int64_t *picard_iters, void *stream);
+int sch_batch_destroy(sch_batch *batch);
+
+/* --------------------------------------------------------------------------
  * Tuning knobs (process-global).  SCH_TUNE_THREADS forces the threads per
  * particle of the model kernels (a power of two in 64..512; 0 = automatic:
  * the smallest power of two giving at most 8 nodes per thread).  A value

@@ -180,11 +180,11 @@ __device__ double ess_at(int n, const double* phi, const double* extra, double b
   return s1 * s1 / s2;
 }
 
-__global__ void __launch_bounds__(kTB) k_temper(int n, const double* phi, const double* extra,
-                                                double* theta_io, double thr, int n_bisect,
-                                                double* dtheta_out, double* w, double* logw_out,
-                                                double* ess_out) {
-  __shared__ TemperLds L;
+// Body of k_temper for one workgroup of kTB threads (also used per
+// instance by the batched runner).
+__device__ void temper_body(int n, const double* phi, const double* extra, double* theta_io,
+                            double thr, int n_bisect, double* dtheta_out, double* w,
+                            double* logw_out, double* ess_out, TemperLds& L) {
   const double theta = *theta_io;
   const double rem = 1.0 - theta;
   double smax, tot;
@@ -210,11 +210,20 @@ __global__ void __launch_bounds__(kTB) k_temper(int n, const double* phi, const 
     w[p] = dead ? 0.0 : exp(s - smax) / tot;
     if (logw_out) logw_out[p] = dead ? -INFINITY : (s - smax) - ltot;
   }
+  __syncthreads();  // every thread has read *theta_io
   if (threadIdx.x == 0) {
     *dtheta_out = pick;
     *ess_out = e;
     *theta_io = (pick == rem) ? 1.0 : theta + pick;
   }
+}
+
+__global__ void __launch_bounds__(kTB) k_temper(int n, const double* phi, const double* extra,
+                                                double* theta_io, double thr, int n_bisect,
+                                                double* dtheta_out, double* w, double* logw_out,
+                                                double* ess_out) {
+  __shared__ TemperLds L;
+  temper_body(n, phi, extra, theta_io, thr, n_bisect, dtheta_out, w, logw_out, ess_out, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,11 +243,11 @@ __device__ __forceinline__ double systematic_point(int j, double u0, double Q, i
   return __ddiv_rn(t, static_cast<double>(n));
 }
 
-__global__ void __launch_bounds__(kTB) k_resample(int n, const double* w, const double* u0p,
-                                                  const double* cond_ess, double cond_thr,
-                                                  int* idx, int* degenerate,
-                                                  unsigned long long* cum) {
-  __shared__ ResampleLds L;
+// Body of k_resample for one workgroup of kTB threads (also used per
+// instance by the batched runner).
+__device__ void resample_body(int n, const double* w, const double* u0p, const double* cond_ess,
+                              double cond_thr, int* idx, int* degenerate,
+                              unsigned long long* cum, ResampleLds& L) {
   const int t = threadIdx.x;
   if (cond_ess && *cond_ess >= cond_thr) {
     for (int j = t; j < n; j += kTB) idx[j] = j;
@@ -315,6 +324,14 @@ __global__ void __launch_bounds__(kTB) k_resample(int n, const double* w, const 
     }
     idx[j] = a < n ? a : n - 1;
   }
+}
+
+__global__ void __launch_bounds__(kTB) k_resample(int n, const double* w, const double* u0p,
+                                                  const double* cond_ess, double cond_thr,
+                                                  int* idx, int* degenerate,
+                                                  unsigned long long* cum) {
+  __shared__ ResampleLds L;
+  resample_body(n, w, u0p, cond_ess, cond_thr, idx, degenerate, cum, L);
 }
 
 // dst[j][:] = src[idx[j]][:]

@@ -66,6 +66,19 @@ class SchCycleStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class SchInstanceC(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("n_particles", C.c_int32), ("xi", _vp), ("m", _vp),
+                ("u", _vp), ("logw", _vp), ("y", _vp), ("sigma", _vp), ("seed", C.c_uint64),
+                ("threads", C.c_int32)]
+
+
+class SchBatchParamsC(C.Structure):
+    _fields_ = [("L", C.c_double), ("alpha", C.c_double), ("mu", C.c_double),
+                ("dt", C.c_double), ("n_modes", C.c_int32), ("n_steps", C.c_int32),
+                ("n_obs", C.c_int32), ("ess_frac", C.c_double), ("picard_tol", C.c_double),
+                ("picard_max", C.c_int32)]
+
+
 class SchLbfgsOpts(C.Structure):
     _fields_ = [("gtol", C.c_double), ("max_iter", C.c_int32), ("mem", C.c_int32),
                 ("max_back", C.c_int32)]
@@ -111,6 +124,13 @@ def _declare(L):
         "sch_nudge_run": (C.c_int, [M, O, i32, i32, _vp, _vp, _vp, _vp, i32,
                                     C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                     _vp]),
+        "sch_batch_workspace_bytes": (C.c_size_t, [C.POINTER(SchBatchParamsC), i32,
+                                                   C.POINTER(SchInstanceC)]),
+        "sch_batch_create": (C.c_int, [C.POINTER(SchBatchParamsC), i32, C.POINTER(SchInstanceC),
+                                       _vp, C.c_size_t, C.POINTER(_vp), _vp]),
+        "sch_batch_run": (C.c_int, [_vp, u32, i32, i32, _vp]),
+        "sch_batch_read": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "sch_batch_destroy": (C.c_int, [_vp]),
         "sch_tune_set": (C.c_int, [i32, i32]),
         "sch_tune_get": (C.c_int, [i32]),
         "sch_timing_enable": (C.c_int, [C.c_int]),
@@ -131,7 +151,9 @@ def exported_names():
         "sch_philox_blocks",
         "sch_velocity", "sch_init_momentum", "sch_ensemble_step", "sch_observe", "sch_loglik",
         "sch_temper_ess", "sch_resample", "sch_gather", "sch_jitter_pcn",
-        "sch_nudge_grad", "sch_nudge_run", "sch_pf_bootstrap_cycle", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
+        "sch_nudge_grad", "sch_nudge_run", "sch_pf_bootstrap_cycle",
+        "sch_batch_workspace_bytes", "sch_batch_create", "sch_batch_run", "sch_batch_read",
+        "sch_batch_destroy", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
         "sch_timing_enable",
         "sch_timing_reset", "sch_timing_read",
     ]
@@ -370,6 +392,73 @@ def sch_nudge_run(model: Model, obs: Obs, m: torch.Tensor, u: torch.Tensor, dW: 
                                _dev(evals, torch.int32, "evals"),
                                _dev(status, torch.int32, "status"),
                                _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+@dataclass
+class Instance:
+    """One filter of a batch: its grid, state and observations (GPU tensors)."""
+    xi: torch.Tensor     # [n_modes][nx]
+    m: torch.Tensor      # [n][nx] in/out
+    u: torch.Tensor      # [n][nx] in/out
+    logw: torch.Tensor   # [n] in/out
+    y: torch.Tensor      # [cycles][n_obs]
+    sigma: torch.Tensor  # [n_obs]
+    seed: int
+    threads: int = 0
+
+    def c(self) -> SchInstanceC:
+        return SchInstanceC(int(self.m.shape[1]), int(self.m.shape[0]), _dev(self.xi, name="xi"),
+                            _dev(self.m, name="m"), _dev(self.u, name="u"),
+                            _dev(self.logw, name="logw"), _dev(self.y, name="y"),
+                            _dev(self.sigma, name="sigma"), self.seed, self.threads)
+
+
+class Batch:
+    """Handle of sch_batch_*: many bootstrap filters advanced together.  Keeps
+    the instance tensors and the workspace alive until close()."""
+
+    def __init__(self, L: float, alpha: float, mu: float, dt: float, n_modes: int, n_steps: int,
+                 n_obs: int, ess_frac: float, instances: list[Instance],
+                 picard_tol: float = 1e-13, picard_max: int = 50):
+        self.instances = list(instances)
+        self.params = SchBatchParamsC(L, alpha, mu, dt, n_modes, n_steps, n_obs, ess_frac,
+                                      picard_tol, picard_max)
+        arr = (SchInstanceC * len(self.instances))(*[i.c() for i in self.instances])
+        self._arr = arr
+        nb = int(lib().sch_batch_workspace_bytes(C.byref(self.params), len(arr), arr))
+        if nb <= 0:
+            raise SchError(SCH_E_ARG, lib().sch_last_error().decode())
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.instances[0].m.device)
+        h = _vp()
+        _check(lib().sch_batch_create(C.byref(self.params), len(arr), arr,
+                                      _dev(self.workspace, torch.uint8, "workspace"), nb,
+                                      C.byref(h), _stream()))
+        self.handle = h
+
+    def run(self, cycle0: int, n_cycles: int = 1, use_graph: bool = False):
+        _check(lib().sch_batch_run(self.handle, cycle0, n_cycles, 1 if use_graph else 0,
+                                   _stream()))
+
+    def read(self) -> dict:
+        k = len(self.instances)
+        ess = (C.c_double * k)()
+        res = (C.c_int32 * k)()
+        st = (C.c_int32 * k)()
+        it = C.c_int64(0)
+        _check(lib().sch_batch_read(self.handle, ess, res, st, C.byref(it), _stream()))
+        return {"ess": list(ess), "resampled": list(res), "status": list(st),
+                "picard_iters": it.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sch_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other", "nudge")
