@@ -182,3 +182,15 @@ def uneven_instances(n_instances: int = 64, seed: int = MASTER_SEED,
             nx = max(nx_multiple, nx_multiple * round(nx / nx_multiple))
         out.append(Instance(nx=nx, n_particles=npart, seed=seed + 2 * i))
     return out
+
+
+def mlp_init_params(n_in: int, n_hidden: int, n_out: int, seed: int) -> np.ndarray:
+    """Initial parameters of the warm-start network as one vector in the order
+    W1 [H][F], b1 [H], W2 [H][H], b2 [H], W3 [O][H], b3 [O] (weights
+    He-normal with std sqrt(2 / fan_in), zero biases)."""
+    g = _rng(seed, 12)
+    F, H, O = n_in, n_hidden, n_out
+    parts = [g.standard_normal(H * F) * math.sqrt(2.0 / F), np.zeros(H),
+             g.standard_normal(H * H) * math.sqrt(2.0 / H), np.zeros(H),
+             g.standard_normal(O * H) * math.sqrt(2.0 / H), np.zeros(O)]
+    return np.concatenate(parts)
