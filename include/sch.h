@@ -421,6 +421,76 @@ int sch_batch_read(sch_batch *batch, double *ess, int32_t *resampled, int32_t *s
 int sch_batch_destroy(sch_batch *batch);
 
 /* --------------------------------------------------------------------------
+ * Learned nudging warm start.  A perceptron n_in -> n_hidden -> n_hidden ->
+ * n_out with ReLU activations maps a particle's window-start features to the
+ * nudging controls of the window; its prediction seeds the L-BFGS stages of
+ * sch_nudge_run (warm_start = 1), and a particle whose observation misfit is
+ * larger than a threshold calibrated on the training data starts from zero
+ * (plain nudging) instead.  Mixed precision on the matrix cores: bfloat16
+ * operands (features, weights, activations, back-propagated errors; round to
+ * nearest even), float32 accumulation, float32 master weights, biases,
+ * gradients and Adam state.  (No passage of the paper: an extension of its
+ * nudging step, section 3.1.3.)
+ *
+ * sch_mlp (host struct):
+ *   n_in, n_hidden, n_out   layer sizes
+ *   params        device float32 [sch_mlp_param_count]: W1 [H][F], b1 [H],
+ *                 W2 [H][H], b2 [H], W3 [O][H], b3 [O] (row-major, out x in)
+ *   weights_bf16  device bf16 bits [H F + H H + O H]: W1 | W2 | W3, refreshed
+ *                 by sch_mlp_sync and sch_mlp_adam
+ * sch_mlp_forward: Y [batch][n_out] (float32) from X [batch][n_in] (bf16
+ *   bits); keeps the activations in the workspace
+ *   (>= sch_mlp_workspace_bytes(net, batch)).
+ * sch_mlp_backward: after sch_mlp_forward on the same X and workspace, the
+ *   mean-squared error of Y against T [batch][n_out] (device double *loss,
+ *   averaged over all batch x n_out values) and its gradient grad (device
+ *   float32, parameter layout).
+ * sch_mlp_adam: one Adam step (Kingma & Ba) at step >= 1 on params with the
+ *   moments m, v (device float32, parameter layout), then refreshes the
+ *   bfloat16 weights.
+ * sch_mlp_features: per particle, the misfit y - P u (n_obs values) followed
+ *   by u (nx values); X = bf16((x - mean) / sdev) if X is given, raw float32
+ *   values into raw and the misfit norm |y - P u|_2 into misfit if given.
+ * sch_mlp_encode: X = bf16((raw - mean) / sdev) for stored raw features
+ *   [n][cols] (the scaling of sch_mlp_features).
+ * sch_mlp_colstats: column means and deviations of A [rows][cols] (float32;
+ *   a deviation below 1e-12 is replaced by 1).
+ * sch_mlp_targets: T = (dLambda - mean) / sdev as float32 (plain float32 copy
+ *   when mean is NULL); dLambda is [n][cols] double.
+ * sch_mlp_controls: dLambda = Y sdev + mean as double, or 0 for particles with
+ *   misfit[p] > threshold (misfit may be NULL: no fallback).
+ * ------------------------------------------------------------------------ */
+typedef struct sch_mlp {
+  int32_t n_in;
+  int32_t n_hidden;
+  int32_t n_out;
+  float *params;
+  uint16_t *weights_bf16;
+} sch_mlp;
+
+size_t sch_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out);
+size_t sch_mlp_workspace_bytes(const sch_mlp *net, int32_t batch);
+int sch_mlp_sync(const sch_mlp *net, void *stream);
+int sch_mlp_forward(const sch_mlp *net, int32_t batch, const uint16_t *X, float *Y,
+                    void *workspace, void *stream);
+int sch_mlp_backward(const sch_mlp *net, int32_t batch, const uint16_t *X, const float *Y,
+                     const float *T, double *loss, float *grad, void *workspace, void *stream);
+int sch_mlp_adam(const sch_mlp *net, const float *grad, float *m, float *v, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream);
+int sch_mlp_features(const sch_model *model, const sch_obs *obs, int32_t n_particles,
+                     const double *u, const float *mean, const float *sdev, uint16_t *X,
+                     float *raw, double *misfit, void *stream);
+int sch_mlp_encode(int32_t n, int32_t cols, const float *raw, const float *mean,
+                   const float *sdev, uint16_t *X, void *stream);
+int sch_mlp_colstats(int32_t rows, int32_t cols, const float *A, float *mean, float *sdev,
+                     void *stream);
+int sch_mlp_targets(int32_t n, int32_t cols, const double *dLambda, const float *mean,
+                    const float *sdev, float *T, void *stream);
+int sch_mlp_controls(int32_t n, int32_t cols, const float *Y, const float *mean,
+                     const float *sdev, const double *misfit, double threshold,
+                     double *dLambda, void *stream);
+
+/* --------------------------------------------------------------------------
  * Tuning knobs (process-global).  SCH_TUNE_THREADS forces the threads per
  * particle of the model kernels (a power of two in 64..512; 0 = automatic:
  * the smallest power of two giving at most 8 nodes per thread).  A value

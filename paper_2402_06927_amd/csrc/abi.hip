@@ -737,3 +737,4 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
 }  // extern "C"
 
 #include "batch_abi.hpp"
+#include "mlp_abi.hpp"

@@ -1,0 +1,248 @@
+// mlp_abi.hpp -- C-ABI of the warm-start network (sch_mlp_*).  Part of the
+// abi.hip translation unit (included at its end).
+#pragma once
+
+#include "host.hpp"
+#include "mlp.hpp"
+
+namespace {
+
+using namespace sch;
+
+bool mlp_ok(const sch_mlp* n) {
+  return n && n->n_in >= 1 && n->n_hidden >= 1 && n->n_out >= 1 && n->params && n->weights_bf16;
+}
+
+// Activations of the last forward pass, kept in the caller's workspace for
+// the backward pass: Z1, Z2 (float32), H1, H2 (bf16), then the backward
+// temporaries dY (float32, bf16), dZ2, dZ1 (float32, bf16).
+struct MlpWs {
+  float *Z1, *Z2, *dY32, *dZ2, *dZ1;
+  uint16_t *H1, *H2, *dY16, *dZ2b, *dZ1b;
+  size_t bytes;
+};
+
+MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
+  Carve c(base);
+  MlpWs w{};
+  const size_t bh = static_cast<size_t>(batch) * d.H, bo = static_cast<size_t>(batch) * d.O;
+  w.Z1 = c.take<float>(bh);
+  w.Z2 = c.take<float>(bh);
+  w.H1 = c.take<uint16_t>(bh);
+  w.H2 = c.take<uint16_t>(bh);
+  w.dY32 = c.take<float>(bo);
+  w.dY16 = c.take<uint16_t>(bo);
+  w.dZ2 = c.take<float>(bh);
+  w.dZ2b = c.take<uint16_t>(bh);
+  w.dZ1 = c.take<float>(bh);
+  w.dZ1b = c.take<uint16_t>(bh);
+  w.bytes = c.off + 256;
+  return w;
+}
+
+GemmArgs gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
+              const uint16_t* B, int64_t sbk, int64_t sbn) {
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.sam = sam;
+  g.sak = sak;
+  g.B = B;
+  g.sbk = sbk;
+  g.sbn = sbn;
+  return g;
+}
+
+void launch_gemm(const GemmArgs& g, hipStream_t st) {
+  const dim3 grid((g.N + kGN - 1) / kGN, (g.M + kGM - 1) / kGM);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sch_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out) {
+  if (n_in < 1 || n_hidden < 1 || n_out < 1) return 0;
+  return static_cast<size_t>(mlp_dims(n_in, n_hidden, n_out).n_params);
+}
+
+size_t sch_mlp_workspace_bytes(const sch_mlp* net, int32_t batch) {
+  if (!net || net->n_in < 1 || net->n_hidden < 1 || net->n_out < 1 || batch < 1) return 0;
+  return carve_mlp(nullptr, mlp_dims(net->n_in, net->n_hidden, net->n_out), batch).bytes;
+}
+
+int sch_mlp_sync(const sch_mlp* net, void* stream) {
+  if (!mlp_ok(net)) return fail(SCH_E_ARG, "bad network");
+  const MlpDims d = mlp_dims(net->n_in, net->n_hidden, net->n_out);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(d.n_params, 256)), dim3(256), 0, S(stream), d,
+                     net->params, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                     net->weights_bf16);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_forward(const sch_mlp* net, int32_t batch, const uint16_t* X, float* Y,
+                    void* workspace, void* stream) {
+  if (!mlp_ok(net) || batch < 1 || !X || !Y || !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_forward");
+  const MlpDims d = mlp_dims(net->n_in, net->n_hidden, net->n_out);
+  const MlpWs w = carve_mlp(workspace, d, batch);
+  hipStream_t st = S(stream);
+  const float* p = net->params;
+  const uint16_t* wb = net->weights_bf16;
+  const int F = d.F, H = d.H, O = d.O;
+  GemmArgs g = gemm(batch, H, F, X, F, 1, wb, 1, F);  // Z1 = X W1^T + b1
+  g.bias = p + d.ob1;
+  g.C32 = w.Z1;
+  g.ldc = H;
+  g.C16 = w.H1;
+  g.ldc16 = H;
+  g.relu = 1;
+  launch_gemm(g, st);
+  g = gemm(batch, H, H, w.H1, H, 1, wb + d.qW2, 1, H);  // Z2 = H1 W2^T + b2
+  g.bias = p + d.ob2;
+  g.C32 = w.Z2;
+  g.ldc = H;
+  g.C16 = w.H2;
+  g.ldc16 = H;
+  g.relu = 1;
+  launch_gemm(g, st);
+  g = gemm(batch, O, H, w.H2, H, 1, wb + d.qW3, 1, H);  // Y = H2 W3^T + b3
+  g.bias = p + d.ob3;
+  g.C32 = Y;
+  g.ldc = O;
+  launch_gemm(g, st);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const float* Y,
+                     const float* T, double* loss, float* grad, void* workspace, void* stream) {
+  if (!mlp_ok(net) || batch < 1 || !X || !Y || !T || !loss || !grad || !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_backward");
+  const MlpDims d = mlp_dims(net->n_in, net->n_hidden, net->n_out);
+  const MlpWs w = carve_mlp(workspace, d, batch);
+  hipStream_t st = S(stream);
+  const uint16_t* wb = net->weights_bf16;
+  const int F = d.F, H = d.H, O = d.O;
+  const int64_t bo = static_cast<int64_t>(batch) * O;
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, loss, 0.0, int64_t(1));
+  hipLaunchKernelGGL(k_mse, dim3(grid_for(bo, 256)), dim3(256), 0, st, bo, Y, T,
+                     1.0f / static_cast<float>(bo), w.dY32, w.dY16, loss);
+  // dW3 = dY^T H2, db3 = column sums of dY
+  GemmArgs g = gemm(O, H, batch, w.dY16, 1, O, w.H2, H, 1);
+  g.C32 = grad + d.oW3;
+  g.ldc = H;
+  launch_gemm(g, st);
+  hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, st, batch, O, w.dY32,
+                     grad + d.ob3);
+  // dZ2 = (dY W3) * [Z2 > 0]
+  g = gemm(batch, H, O, w.dY16, O, 1, wb + d.qW3, H, 1);
+  g.mask = w.Z2;
+  g.ldm = H;
+  g.C32 = w.dZ2;
+  g.ldc = H;
+  g.C16 = w.dZ2b;
+  g.ldc16 = H;
+  launch_gemm(g, st);
+  // dW2 = dZ2^T H1, db2
+  g = gemm(H, H, batch, w.dZ2b, 1, H, w.H1, H, 1);
+  g.C32 = grad + d.oW2;
+  g.ldc = H;
+  launch_gemm(g, st);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, batch, H, w.dZ2,
+                     grad + d.ob2);
+  // dZ1 = (dZ2 W2) * [Z1 > 0]
+  g = gemm(batch, H, H, w.dZ2b, H, 1, wb + d.qW2, H, 1);
+  g.mask = w.Z1;
+  g.ldm = H;
+  g.C32 = w.dZ1;
+  g.ldc = H;
+  g.C16 = w.dZ1b;
+  g.ldc16 = H;
+  launch_gemm(g, st);
+  // dW1 = dZ1^T X, db1
+  g = gemm(H, F, batch, w.dZ1b, 1, H, X, F, 1);
+  g.C32 = grad + d.oW1;
+  g.ldc = F;
+  launch_gemm(g, st);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, batch, H, w.dZ1,
+                     grad + d.ob1);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_adam(const sch_mlp* net, const float* grad, float* m, float* v, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!mlp_ok(net) || !grad || !m || !v || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+      !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_adam");
+  const MlpDims d = mlp_dims(net->n_in, net->n_hidden, net->n_out);
+  const float c1 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta1), step)));
+  const float c2 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta2), step)));
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(d.n_params, 256)), dim3(256), 0, S(stream), d,
+                     net->params, grad, m, v, lr, beta1, beta2, eps, c1, c2, net->weights_bf16);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_features(const sch_model* md, const sch_obs* ob, int32_t n, const double* u,
+                     const float* mean, const float* sdev, uint16_t* X, float* raw,
+                     double* misfit, void* stream) {
+  if (!md || md->nx < 2 || !ob || ob->n_obs < 1 || !ob->y || n < 1 || !u ||
+      (X && (!mean || !sdev)) || (!X && !raw && !misfit))
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_features");
+  hipLaunchKernelGGL(k_mlp_features, dim3(n), dim3(256), 0, S(stream), md->nx, ob->n_obs, u,
+                     ob->y, mean, sdev, X, raw, misfit);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_colstats(int32_t rows, int32_t cols, const float* A, float* mean, float* sdev,
+                     void* stream) {
+  if (rows < 1 || cols < 1 || !A || !mean || !sdev)
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_colstats");
+  hipLaunchKernelGGL(k_colstats, dim3((cols + 255) / 256), dim3(256), 0, S(stream), rows, cols,
+                     A, mean, sdev);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_encode(int32_t n, int32_t cols, const float* raw, const float* mean,
+                   const float* sdev, uint16_t* X, void* stream) {
+  if (n < 1 || cols < 1 || !raw || !mean || !sdev || !X)
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_encode");
+  const int64_t total = static_cast<int64_t>(n) * cols;
+  hipLaunchKernelGGL(k_mlp_encode, dim3(grid_for(total, 256)), dim3(256), 0, S(stream), total,
+                     cols, raw, mean, sdev, X);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_targets(int32_t n, int32_t cols, const double* dLam, const float* mean,
+                    const float* sdev, float* T, void* stream) {
+  if (n < 1 || cols < 1 || !dLam || !T || (mean && !sdev))
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_targets");
+  const int64_t total = static_cast<int64_t>(n) * cols;
+  hipLaunchKernelGGL(k_mlp_targets, dim3(grid_for(total, 256)), dim3(256), 0, S(stream), total,
+                     cols, dLam, mean, sdev, T);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+int sch_mlp_controls(int32_t n, int32_t cols, const float* Y, const float* mean,
+                     const float* sdev, const double* misfit, double threshold, double* dLam,
+                     void* stream) {
+  if (n < 1 || cols < 1 || !Y || !mean || !sdev || !dLam)
+    return fail(SCH_E_ARG, "bad arguments to sch_mlp_controls");
+  const int64_t total = static_cast<int64_t>(n) * cols;
+  hipLaunchKernelGGL(k_mlp_controls, dim3(grid_for(total, 256)), dim3(256), 0, S(stream), total,
+                     cols, Y, mean, sdev, misfit, threshold, dLam);
+  CHECK_LAUNCH();
+  return SCH_OK;
+}
+
+}  // extern "C"

@@ -79,6 +79,11 @@ class SchBatchParamsC(C.Structure):
                 ("picard_max", C.c_int32)]
 
 
+class SchMlpC(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("n_out", C.c_int32),
+                ("params", _vp), ("weights_bf16", _vp)]
+
+
 class SchLbfgsOpts(C.Structure):
     _fields_ = [("gtol", C.c_double), ("max_iter", C.c_int32), ("mem", C.c_int32),
                 ("max_back", C.c_int32)]
@@ -131,6 +136,19 @@ def _declare(L):
         "sch_batch_run": (C.c_int, [_vp, u32, i32, i32, _vp]),
         "sch_batch_read": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "sch_batch_destroy": (C.c_int, [_vp]),
+        "sch_mlp_param_count": (C.c_size_t, [i32, i32, i32]),
+        "sch_mlp_workspace_bytes": (C.c_size_t, [C.POINTER(SchMlpC), i32]),
+        "sch_mlp_sync": (C.c_int, [C.POINTER(SchMlpC), _vp]),
+        "sch_mlp_forward": (C.c_int, [C.POINTER(SchMlpC), i32, _vp, _vp, _vp, _vp]),
+        "sch_mlp_backward": (C.c_int, [C.POINTER(SchMlpC), i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       _vp]),
+        "sch_mlp_adam": (C.c_int, [C.POINTER(SchMlpC), _vp, _vp, _vp, i32, C.c_float,
+                                   C.c_float, C.c_float, C.c_float, _vp]),
+        "sch_mlp_features": (C.c_int, [M, O, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "sch_mlp_colstats": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp]),
+        "sch_mlp_encode": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
+        "sch_mlp_targets": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
+        "sch_mlp_controls": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, f64, _vp, _vp]),
         "sch_tune_set": (C.c_int, [i32, i32]),
         "sch_tune_get": (C.c_int, [i32]),
         "sch_timing_enable": (C.c_int, [C.c_int]),
@@ -153,7 +171,9 @@ def exported_names():
         "sch_temper_ess", "sch_resample", "sch_gather", "sch_jitter_pcn",
         "sch_nudge_grad", "sch_nudge_run", "sch_pf_bootstrap_cycle",
         "sch_batch_workspace_bytes", "sch_batch_create", "sch_batch_run", "sch_batch_read",
-        "sch_batch_destroy", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
+        "sch_batch_destroy", "sch_mlp_param_count", "sch_mlp_workspace_bytes", "sch_mlp_sync",
+        "sch_mlp_forward", "sch_mlp_backward", "sch_mlp_adam", "sch_mlp_features",
+        "sch_mlp_colstats", "sch_mlp_encode", "sch_mlp_targets", "sch_mlp_controls", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
         "sch_timing_enable",
         "sch_timing_reset", "sch_timing_read",
     ]
@@ -459,6 +479,107 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------- warm-start network
+def sch_mlp_param_count(n_in: int, n_hidden: int, n_out: int) -> int:
+    return int(lib().sch_mlp_param_count(n_in, n_hidden, n_out))
+
+
+@dataclass
+class Mlp:
+    """Warm-start network: float32 master parameters and their bfloat16 weight
+    copy (GPU tensors)."""
+    n_in: int
+    n_hidden: int
+    n_out: int
+    params: torch.Tensor        # float32 [sch_mlp_param_count]
+    weights_bf16: torch.Tensor  # bfloat16 [H F + H H + O H]
+
+    def c(self) -> SchMlpC:
+        return SchMlpC(self.n_in, self.n_hidden, self.n_out,
+                       _dev(self.params, torch.float32, "params"),
+                       _dev(self.weights_bf16, torch.bfloat16, "weights_bf16"))
+
+
+def sch_mlp_workspace_bytes(net: Mlp, batch: int) -> int:
+    nc = net.c()
+    return int(lib().sch_mlp_workspace_bytes(C.byref(nc), batch))
+
+
+def sch_mlp_sync(net: Mlp):
+    nc = net.c()
+    _check(lib().sch_mlp_sync(C.byref(nc), _stream()))
+
+
+def sch_mlp_forward(net: Mlp, X: torch.Tensor, Y: torch.Tensor, workspace: torch.Tensor):
+    nc = net.c()
+    _check(lib().sch_mlp_forward(C.byref(nc), X.shape[0], _dev(X, torch.bfloat16, "X"),
+                                 _dev(Y, torch.float32, "Y"),
+                                 _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_mlp_backward(net: Mlp, X: torch.Tensor, Y: torch.Tensor, T: torch.Tensor,
+                     loss: torch.Tensor, grad: torch.Tensor, workspace: torch.Tensor):
+    nc = net.c()
+    _check(lib().sch_mlp_backward(C.byref(nc), X.shape[0], _dev(X, torch.bfloat16, "X"),
+                                  _dev(Y, torch.float32, "Y"), _dev(T, torch.float32, "T"),
+                                  _dev(loss, torch.float64, "loss"),
+                                  _dev(grad, torch.float32, "grad"),
+                                  _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_mlp_adam(net: Mlp, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+                 lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    nc = net.c()
+    _check(lib().sch_mlp_adam(C.byref(nc), _dev(grad, torch.float32, "grad"),
+                              _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"), step,
+                              lr, beta1, beta2, eps, _stream()))
+
+
+def sch_mlp_features(model: Model, obs: Obs, u: torch.Tensor, mean: torch.Tensor | None,
+                     sdev: torch.Tensor | None, X: torch.Tensor | None = None,
+                     raw: torch.Tensor | None = None, misfit: torch.Tensor | None = None):
+    mc, oc = model.c(), obs.c()
+    _check(lib().sch_mlp_features(C.byref(mc), C.byref(oc), u.shape[0], _dev(u, name="u"),
+                                  _dev(mean, torch.float32, "mean"),
+                                  _dev(sdev, torch.float32, "sdev"),
+                                  _dev(X, torch.bfloat16, "X"), _dev(raw, torch.float32, "raw"),
+                                  _dev(misfit, name="misfit"), _stream()))
+
+
+def sch_mlp_colstats(A: torch.Tensor, mean: torch.Tensor, sdev: torch.Tensor):
+    _check(lib().sch_mlp_colstats(A.shape[0], A.shape[1], _dev(A, torch.float32, "A"),
+                                  _dev(mean, torch.float32, "mean"),
+                                  _dev(sdev, torch.float32, "sdev"), _stream()))
+
+
+def sch_mlp_encode(raw: torch.Tensor, mean: torch.Tensor, sdev: torch.Tensor, X: torch.Tensor):
+    _check(lib().sch_mlp_encode(raw.shape[0], raw.shape[1], _dev(raw, torch.float32, "raw"),
+                                _dev(mean, torch.float32, "mean"),
+                                _dev(sdev, torch.float32, "sdev"),
+                                _dev(X, torch.bfloat16, "X"), _stream()))
+
+
+def sch_mlp_targets(dLam: torch.Tensor, mean: torch.Tensor | None, sdev: torch.Tensor | None,
+                    T: torch.Tensor):
+    n = dLam.shape[0]
+    cols = dLam.numel() // n
+    _check(lib().sch_mlp_targets(n, cols, _dev(dLam, name="dLambda"),
+                                 _dev(mean, torch.float32, "mean"),
+                                 _dev(sdev, torch.float32, "sdev"),
+                                 _dev(T, torch.float32, "T"), _stream()))
+
+
+def sch_mlp_controls(Y: torch.Tensor, mean: torch.Tensor, sdev: torch.Tensor,
+                     misfit: torch.Tensor | None, threshold: float, dLam: torch.Tensor):
+    n = Y.shape[0]
+    cols = Y.numel() // n
+    _check(lib().sch_mlp_controls(n, cols, _dev(Y, torch.float32, "Y"),
+                                  _dev(mean, torch.float32, "mean"),
+                                  _dev(sdev, torch.float32, "sdev"),
+                                  _dev(misfit, name="misfit"), threshold,
+                                  _dev(dLam, name="dLambda"), _stream()))
 
 
 TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other", "nudge")
