@@ -191,6 +191,126 @@ def bench_nudging(args):
     print(json.dumps(out), flush=True)
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def bench_warmstart(args):
+    """Plain versus warm-started nudging at the nudging workload (Nx = 2048,
+    2048 particles, 40 steps, 8 modes, 256 observations): the network
+    (256 + 2048 -> 256 -> 256 -> 320) is trained on the GPU on the plain-
+    nudging solutions of --train-windows windows, then one step = one nudged
+    window of the whole ensemble, timed for both starts on the same inputs."""
+    import torch
+
+    from paper_2402_06927_amd import sch
+    from paper_2402_06927_amd import warmstart as WS
+    from paper_2402_06927_amd import workloads as W
+
+    wl = W.NUDGING_2048
+    if args.particles:
+        wl = wl.scaled(n_particles=args.particles)
+    dev = "cuda"
+    n, nx, Q, S, nobs = wl.n_particles, wl.nx, wl.n_modes, wl.n_steps, wl.n_obs
+    n_train = args.train_windows
+    log(f"bench: warm start, {wl.name}, {n_train} training windows")
+    xi = torch.tensor(W.mode_table(wl.L, nx, Q, wl.mode_amp), device=dev)
+    model = sch.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi)
+    ts = W.truth_seed(wl)
+    ut = torch.tensor(W.initial_velocity(wl, 1, ts), device=dev)
+    mt = torch.empty_like(ut)
+    sch.sch_init_momentum(model, ut, mt)
+    u = torch.tensor(W.initial_velocity(wl, n, wl.seed), device=dev)
+    m = torch.empty_like(u)
+    sch.sch_init_momentum(model, u, m)
+    z = torch.tensor(W.obs_noise(wl, ts, n_train + 1), device=dev)
+    sig = torch.full((nobs,), wl.sigma_obs, dtype=torch.float64, device=dev)
+
+    def obs_for(c):
+        dWt = torch.empty((1, S, Q), dtype=torch.float64, device=dev)
+        sch.sch_draw_increments(ts, c, 0, sch.TAG_FORECAST, dWt, wl.dt)
+        sch.sch_ensemble_step(model, mt, ut, dWt)
+        y = torch.empty((1, nobs), dtype=torch.float64, device=dev)
+        sch.sch_observe(model, ut, y)
+        return sch.Obs((y[0] + wl.sigma_obs * z[c]).contiguous(), sig)
+
+    ws = WS.WarmStart(nobs, nx, S, Q)
+    nws = sch.workspace(sch.WS_NUDGE, model, n, S, 8)
+    parts = []
+    for c in range(n_train):
+        obs = obs_for(c)
+        dW = torch.empty((n, S, Q), dtype=torch.float64, device=dev)
+        sch.sch_draw_increments(wl.seed, c, 0, sch.TAG_NUDGE, dW, wl.dt)
+        parts.append(ws.collect(model, obs, m, u, dW, nws))
+        log(f"training window {c} collected")
+    data = WS.concat(parts)
+    ws.fit_scaling(data)
+    X, T = ws.encode(data)
+    B = 256
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    hist = ws.train(X, T, epochs=args.epochs, batch=B, lr=1e-3, log=log)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    steps = args.epochs * (X.shape[0] // B)
+    F, H, O = ws.F, ws.H, ws.O
+    # training step: forward 2 B (F H + H H + H O), backward twice that
+    flops_step = 3 * 2 * B * (F * H + H * H + H * O)
+    obs = obs_for(n_train)
+    dW = torch.empty((n, S, Q), dtype=torch.float64, device=dev)
+    sch.sch_draw_increments(wl.seed, n_train, 0, sch.TAG_NUDGE, dW, wl.dt)
+    res = {}
+    for mode in ("plain", "warm"):
+        times, evs, phis = [], [], []
+        for rep in range(args.warmup + args.steps):
+            mm, uu = m.clone(), u.clone()
+            dl = torch.zeros_like(dW)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "warm":
+                ws.predict(model, obs, uu, dl)
+            logG = torch.empty(n, dtype=torch.float64, device=dev)
+            ev = torch.empty(n, dtype=torch.int32, device=dev)
+            sch.sch_nudge_run(model, obs, mm, uu, dW, dl, logG, warm_start=(mode == "warm"),
+                              evals=ev, workspace=nws)
+            phi = torch.empty(n, dtype=torch.float64, device=dev)
+            sch.sch_loglik(model, obs, uu, phi)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(time.perf_counter() - t0)
+                evs.append(float(ev.double().mean()))
+                phis.append(float(phi.mean()))
+        res[mode] = {"windows_per_s": len(times) / sum(times),
+                     "evals_per_particle": sum(evs) / len(evs),
+                     "mean_phi": sum(phis) / len(phis)}
+        log(f"{mode}: {res[mode]}")
+    train_tflops = flops_step * steps / (train_ms * 1e-3) / 1e12
+    out = {
+        "metric": "nudged windows/s with the learned warm start (plain nudging beside it)",
+        "value": round(res["warm"]["windows_per_s"], 4),
+        "unit": "windows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 / res["warm"]["windows_per_s"], 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 model, bf16/f32 network", "data": "synthetic",
+        "config": {"workload": wl.name + "_warmstart", "nx": nx, "n_particles": n,
+                   "n_modes": Q, "n_steps": S, "n_obs": nobs, "network": [F, H, H, O],
+                   "training_pairs": int(X.shape[0]), "epochs": args.epochs, "batch": B},
+        "plain": res["plain"], "warm": res["warm"],
+        "speedup": round(res["warm"]["windows_per_s"] / res["plain"]["windows_per_s"], 4),
+        "phi_rel_diff": abs(res["warm"]["mean_phi"] - res["plain"]["mean_phi"])
+        / res["plain"]["mean_phi"],
+        "training_loss": [hist[0], hist[-1]],
+        "roofline": {"bound": "mfma", "achieved": round(train_tflops, 3),
+                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(train_tflops / PEAK_BF16_TFLOPS, 5), "traffic": None,
+                     "kernel": "network training step (k_gemm_bf16 forward + backward, Adam)",
+                     "algorithmic_flops_per_step": flops_step},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,8 +319,12 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--workload", choices=("tempered", "nudging"), default="tempered",
-                    help="tempered: the headline filter; nudging: one nudged window")
+    ap.add_argument("--workload", choices=("tempered", "nudging", "warmstart"),
+                    default="tempered",
+                    help="tempered: the headline filter; nudging: one nudged window; "
+                         "warmstart: plain vs learned warm-start nudging")
+    ap.add_argument("--train-windows", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="run only a plain copy of BYTES (traffic-counter calibration)")
     args = ap.parse_args()
@@ -217,6 +341,9 @@ def main():
         return
     if args.workload == "nudging":
         bench_nudging(args)
+        return
+    if args.workload == "warmstart":
+        bench_warmstart(args)
         return
 
     from paper_2402_06927_amd import sch
