@@ -311,6 +311,71 @@ def bench_warmstart(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mlp(args):
+    """The warm-start network at its configured shape, 4352 (256 misfits +
+    4096 velocities) -> 256 -> 256 -> 320, on 4096 particles: one step = one
+    forward pass of the whole ensemble (inference), plus one training step
+    (forward, backward, Adam) on a batch of 1024, both timed with events."""
+    import numpy as np
+    import torch
+
+    from paper_2402_06927_amd import sch
+    from paper_2402_06927_amd import workloads as W
+
+    F, H, O, B, Bt = 4352, 256, 320, 4096, 1024
+    dev = "cuda"
+    p = W.mlp_init_params(F, H, O, 1)
+    net = sch.Mlp(F, H, O, torch.tensor(p, dtype=torch.float32, device=dev),
+                  torch.empty(H * F + H * H + O * H, dtype=torch.bfloat16, device=dev))
+    sch.sch_mlp_sync(net)
+    g = np.random.default_rng(2)
+    X = torch.tensor(g.standard_normal((B, F)), dtype=torch.float32, device=dev).to(torch.bfloat16)
+    T = torch.tensor(g.standard_normal((B, O)), dtype=torch.float32, device=dev)
+    Y = torch.empty((B, O), dtype=torch.float32, device=dev)
+    ws = torch.empty(sch.sch_mlp_workspace_bytes(net, B), dtype=torch.uint8, device=dev)
+    grad = torch.zeros_like(net.params)
+    m, v = torch.zeros_like(grad), torch.zeros_like(grad)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        sch.sch_mlp_forward(net, X, Y, ws)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        sch.sch_mlp_forward(net, X, Y, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / args.steps
+    flops_fwd = 2 * B * (F * H + H * H + H * O)
+    Xt, Tt, Yt = X[:Bt], T[:Bt], Y[:Bt]
+    e0.record()
+    for k in range(args.steps):
+        sch.sch_mlp_forward(net, Xt, Yt, ws)
+        sch.sch_mlp_backward(net, Xt, Yt, Tt, loss, grad, ws)
+        sch.sch_mlp_adam(net, grad, m, v, k + 1, 1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / args.steps
+    flops_train = 3 * 2 * Bt * (F * H + H * H + H * O)
+    tf = flops_fwd / (fwd_ms * 1e-3) / 1e12
+    out = {
+        "metric": "warm-start network inference, particles/s (4352-256-256-320, bf16 MFMA)",
+        "value": round(B / (fwd_ms * 1e-3), 1), "unit": "particles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fwd_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 x bf16 -> f32", "data": "synthetic",
+        "config": {"workload": "warmstart_network_b4096", "network": [F, H, H, O], "batch": B,
+                   "train_batch": Bt},
+        "train_step_ms": round(train_ms, 4),
+        "train_tflops": round(flops_train / (train_ms * 1e-3) / 1e12, 3),
+        "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tf / PEAK_BF16_TFLOPS, 5), "traffic": None,
+                     "kernel": "k_gemm_bf16 (three layers of one forward pass)",
+                     "algorithmic_flops_per_launch": flops_fwd},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,7 +384,7 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--workload", choices=("tempered", "nudging", "warmstart"),
+    ap.add_argument("--workload", choices=("tempered", "nudging", "warmstart", "mlp"),
                     default="tempered",
                     help="tempered: the headline filter; nudging: one nudged window; "
                          "warmstart: plain vs learned warm-start nudging")
@@ -344,6 +409,9 @@ def main():
         return
     if args.workload == "warmstart":
         bench_warmstart(args)
+        return
+    if args.workload == "mlp":
+        bench_mlp(args)
         return
 
     from paper_2402_06927_amd import sch

@@ -46,10 +46,51 @@ struct GemmArgs {
   int relu;
 };
 
-constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 4;
+constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 8;  // LDS rows of 80 bytes
+
+// Epilogue and matrix-core steps shared by both loaders.
+__device__ __forceinline__ void gemm_chunk(const uint16_t (&As)[kGM][kGK + kGPad],
+                                           const uint16_t (&Bs)[kGN][kGK + kGPad], int wm,
+                                           int wn, int lane, f32x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int ks = 0; ks < kGK; ks += 16) {
+    bf16x4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = *reinterpret_cast<const bf16x4*>(&As[wm + 16 * i + (lane & 15)][ks + 4 * (lane >> 4)]);
+      b[i] = *reinterpret_cast<const bf16x4*>(&Bs[wn + 16 * i + (lane & 15)][ks + 4 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int m0, int n0, int wm, int wn,
+                                           int lane, const f32x4 (&acc)[2][2]) {
+  // lane l of a 16 x 16 tile holds rows 4 (l / 16) .. + 3 of column l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + 16 * j + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[i][j][r];
+        if (g.bias) v += g.bias[n];
+        if (g.mask && !(g.mask[m * g.ldm + n] > 0.f)) v = 0.f;
+        if (g.C32) g.C32[m * g.ldc + n] = v;
+        if (g.C16) g.C16[m * g.ldc16 + n] = f2bf(g.relu ? fmaxf(v, 0.f) : v);
+      }
+}
 
 // 256 threads = 4 wavefronts, each computing a 32 x 32 block as 2 x 2 matrix-
-// core tiles of 16 x 16; K advances in chunks of 32 staged in LDS.
+// core tiles of 16 x 16; K advances in chunks of 32 staged in LDS.  Element-
+// wise loads: any operand layout with one unit stride.
 __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[kGM][kGK + kGPad];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[kGN][kGK + kGPad];
@@ -74,38 +115,53 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmArgs g) {
       Bs[nn][kb] = (gn < g.N && gkb < g.K) ? g.B[gkb * g.sbk + gn * g.sbn] : uint16_t(0);
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kGK; ks += 16) {
-      bf16x4 a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const bf16x4*>(&As[wm + 16 * i + (lane & 15)][ks + 4 * (lane >> 4)]);
-        b[i] = *reinterpret_cast<const bf16x4*>(&Bs[wn + 16 * i + (lane & 15)][ks + 4 * (lane >> 4)]);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
+    gemm_chunk(As, Bs, wm, wn, lane, acc);
     __syncthreads();
   }
-  // lane l of a 16 x 16 tile holds rows 4 (l / 16) .. + 3 of column l % 16
+  gemm_store(g, m0, n0, wm, wn, lane, acc);
+}
+
+// Both operands contiguous along K (sak = sbk = 1), K, sam, sbn multiples of 8
+// and 16-byte aligned rows: each thread moves 8 bf16 of A and of B per chunk
+// with one 16-byte load each, and the next chunk is fetched into registers
+// while the matrix cores work on the current one.
+__global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kGM][kGK + kGPad];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kGN][kGK + kGPad];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * kGM, n0 = blockIdx.x * kGN;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int row = t >> 2, seg = (t & 3) * 8;  // 64 rows x 4 segments of 8
+  const int gm = m0 + row, gn = n0 + row;
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  // a segment is read only when it lies inside the row (k0 + seg < K implies
+  // k0 + seg + 8 <= K since both are multiples of 8)
+  auto fetch = [&](int k0, uint4& ra, uint4& rb) {
+    const bool in_k = k0 + seg < g.K;
+    ra = (gm < g.M && in_k) ? *reinterpret_cast<const uint4*>(g.A + gm * g.sam + k0 + seg) : zero;
+    rb = (gn < g.N && in_k) ? *reinterpret_cast<const uint4*>(g.B + gn * g.sbn + k0 + seg) : zero;
+  };
+  f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
-        const int n = n0 + wn + 16 * j + (lane & 15);
-        if (m >= g.M || n >= g.N) continue;
-        float v = acc[i][j][r];
-        if (g.bias) v += g.bias[n];
-        if (g.mask && !(g.mask[m * g.ldm + n] > 0.f)) v = 0.f;
-        if (g.C32) g.C32[m * g.ldc + n] = v;
-        if (g.C16) g.C16[m * g.ldc16 + n] = f2bf(g.relu ? fmaxf(v, 0.f) : v);
-      }
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra, rb;
+  fetch(0, ra, rb);
+  for (int k0 = 0; k0 < g.K; k0 += kGK) {
+    // K is a multiple of 8 but maybe not of 32: zero the segments past K
+    if (k0 + seg >= g.K) {
+      ra = zero;
+      rb = zero;
+    }
+    *reinterpret_cast<uint4*>(&As[row][seg]) = ra;
+    *reinterpret_cast<uint4*>(&Bs[row][seg]) = rb;
+    __syncthreads();
+    if (k0 + kGK < g.K) fetch(k0 + kGK, ra, rb);
+    gemm_chunk(As, Bs, wm, wn, lane, acc);
+    __syncthreads();
+  }
+  gemm_store(g, m0, n0, wm, wn, lane, acc);
 }
 
 // Mean-squared error of Y against T ([rows][cols]) and its gradient

@@ -55,9 +55,16 @@ GemmArgs gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
   return g;
 }
 
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 void launch_gemm(const GemmArgs& g, hipStream_t st) {
   const dim3 grid((g.N + kGN - 1) / kGN, (g.M + kGM - 1) / kGM);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+  const bool kc = g.sak == 1 && g.sbk == 1 && g.K % 8 == 0 && g.sam % 8 == 0 &&
+                  g.sbn % 8 == 0 && aligned16(g.A) && aligned16(g.B);
+  if (kc)
+    hipLaunchKernelGGL(k_gemm_bf16_kc, grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
 }
 
 }  // namespace
