@@ -70,22 +70,58 @@ __device__ __forceinline__ double uniform1(uint64_t seed, uint32_t c0, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.
+// Cross-lane moves without LDS: DPP row shifts (a lane reads lane l -/+ d of
+// its 16-lane row, or keeps `old` where no such lane exists), whole-wave
+// shifts by one, and readlane broadcasts into scalar registers.
+// ---------------------------------------------------------------------------
+constexpr int kDppRowShr = 0x110, kDppRowShl = 0x100, kDppWaveShr1 = 0x138,
+              kDppWaveShl1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double src, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(src), CTRL, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(src), CTRL, 0xf,
+                                             0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int src, int old) {
+  return __builtin_amdgcn_update_dpp(old, src, CTRL, 0xf, 0xf, false);
+}
+// lane must be wave-uniform
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// ---------------------------------------------------------------------------
+// Wave reductions (every lane receives the result): inclusive prefix within
+// each row by row shifts, then the four row results from lanes 15, 31, 47, 63.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_f64<kDppRowShr + 1>(v, 0.0);
+  v += dpp_f64<kDppRowShr + 2>(v, 0.0);
+  v += dpp_f64<kDppRowShr + 4>(v, 0.0);
+  v += dpp_f64<kDppRowShr + 8>(v, 0.0);
+  return (readlane_f64(v, 15) + readlane_f64(v, 31)) + (readlane_f64(v, 47) + readlane_f64(v, 63));
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  v = fmax(v, dpp_f64<kDppRowShr + 1>(v, v));
+  v = fmax(v, dpp_f64<kDppRowShr + 2>(v, v));
+  v = fmax(v, dpp_f64<kDppRowShr + 4>(v, v));
+  v = fmax(v, dpp_f64<kDppRowShr + 8>(v, v));
+  return fmax(fmax(readlane_f64(v, 15), readlane_f64(v, 31)),
+              fmax(readlane_f64(v, 47), readlane_f64(v, 63)));
 }
 __device__ __forceinline__ int wave_or(int v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
-  return v;
+  v |= dpp_i32<kDppRowShr + 1>(v, 0);
+  v |= dpp_i32<kDppRowShr + 2>(v, 0);
+  v |= dpp_i32<kDppRowShr + 4>(v, 0);
+  v |= dpp_i32<kDppRowShr + 8>(v, 0);
+  return __builtin_amdgcn_readlane(v, 15) | __builtin_amdgcn_readlane(v, 31) |
+         __builtin_amdgcn_readlane(v, 47) | __builtin_amdgcn_readlane(v, 63);
 }
 
 // ---------------------------------------------------------------------------

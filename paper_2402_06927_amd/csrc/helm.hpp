@@ -34,6 +34,43 @@ __device__ __forceinline__ void compose(double m1, double c1, double m2, double 
   c = fma(m2, c1, c2);
 }
 
+// Inclusive affine scan inside each 16-lane row: CTRL = row shift right
+// (forward: compose the lanes to the left first) or left (backward: the
+// lanes to the right first).
+template <int CTRL>
+__device__ __forceinline__ void scan_rows(double& m, double& c) {
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) {
+    double pm, pc;
+    if (d == 1) { pm = dpp_f64<CTRL + 1>(m, 1.0); pc = dpp_f64<CTRL + 1>(c, 0.0); }
+    else if (d == 2) { pm = dpp_f64<CTRL + 2>(m, 1.0); pc = dpp_f64<CTRL + 2>(c, 0.0); }
+    else if (d == 4) { pm = dpp_f64<CTRL + 4>(m, 1.0); pc = dpp_f64<CTRL + 4>(c, 0.0); }
+    else { pm = dpp_f64<CTRL + 8>(m, 1.0); pc = dpp_f64<CTRL + 8>(c, 0.0); }
+    compose(pm, pc, m, c, m, c);
+  }
+}
+
+// Scans of the per-wavefront records held in lanes 0..W-1 (W <= 8): forward
+// and backward affine compositions and running maxima of three partials.
+template <int W>
+__device__ __forceinline__ void record_scan(double& f0, double& f1, double& b0, double& b1,
+                                            double& q0, double& q1, double& q2) {
+#define SCH_RSTEP(D)                                                              \
+  if constexpr (W > D) {                                                          \
+    double pm = dpp_f64<kDppRowShr + D>(f0, 1.0), pc = dpp_f64<kDppRowShr + D>(f1, 0.0); \
+    compose(pm, pc, f0, f1, f0, f1);                                              \
+    double qm = dpp_f64<kDppRowShl + D>(b0, 1.0), qc = dpp_f64<kDppRowShl + D>(b1, 0.0); \
+    compose(qm, qc, b0, b1, b0, b1);                                              \
+    q0 = fmax(q0, dpp_f64<kDppRowShr + D>(q0, q0));                               \
+    q1 = fmax(q1, dpp_f64<kDppRowShr + D>(q1, q1));                               \
+    q2 = fmax(q2, dpp_f64<kDppRowShr + D>(q2, q2));                               \
+  }
+  SCH_RSTEP(1)
+  SCH_RSTEP(2)
+  SCH_RSTEP(4)
+#undef SCH_RSTEP
+}
+
 template <int PMAX, int NT, bool FULL, class LT>
 __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)[PMAX],
                                            double (&u)[PMAX], double& uL, double& uR, int cnt,
@@ -60,30 +97,40 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   }
   const double cmn = acc;  // backward carry out of the chunk (at its first node)
   const double mth = (FULL || cnt == K.base) ? K.rb : K.rb1;
-  // inclusive scans over lanes: forward (m, c) composes lanes 0..lane,
-  // backward composes lanes lane..63
+  // Inclusive scans over the lanes, forward (lanes 0..lane) and backward
+  // (lanes lane..63): Hillis-Steele steps inside each 16-lane row by DPP row
+  // shifts (identity where the row has no partner), then the rows are joined
+  // with the row results read from the row ends into scalar registers.
+  const int row = lane >> 4;
   double fm = mth, fc = cpl, bm = mth, bc = cmn;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const double pm = __shfl_up(fm, d), pc = __shfl_up(fc, d);
-    const double qm = __shfl_down(bm, d), qc = __shfl_down(bc, d);
-    if (lane >= d) compose(pm, pc, fm, fc, fm, fc);
-    if (lane + d < kWave) compose(qm, qc, bm, bc, bm, bc);
+  scan_rows<kDppRowShr>(fm, fc);
+  scan_rows<kDppRowShl>(bm, bc);
+  {
+    const double r0m = readlane_f64(fm, 15), r0c = readlane_f64(fc, 15);
+    const double r1m = readlane_f64(fm, 31), r1c = readlane_f64(fc, 31);
+    const double r2m = readlane_f64(fm, 47), r2c = readlane_f64(fc, 47);
+    double p2m, p2c, p3m, p3c;
+    compose(r0m, r0c, r1m, r1c, p2m, p2c);
+    compose(p2m, p2c, r2m, r2c, p3m, p3c);
+    const double pm = row == 0 ? 1.0 : row == 1 ? r0m : row == 2 ? p2m : p3m;
+    const double pc = row == 0 ? 0.0 : row == 1 ? r0c : row == 2 ? p2c : p3c;
+    compose(pm, pc, fm, fc, fm, fc);
+    const double t1m = readlane_f64(bm, 16), t1c = readlane_f64(bc, 16);
+    const double t2m = readlane_f64(bm, 32), t2c = readlane_f64(bc, 32);
+    const double t3m = readlane_f64(bm, 48), t3c = readlane_f64(bc, 48);
+    double h1m, h1c, h0m, h0c;
+    compose(t3m, t3c, t2m, t2c, h1m, h1c);
+    compose(h1m, h1c, t1m, t1c, h0m, h0c);
+    const double hm = row == 3 ? 1.0 : row == 2 ? t3m : row == 1 ? h1m : h0m;
+    const double hc = row == 3 ? 0.0 : row == 2 ? t3c : row == 1 ? h1c : h0c;
+    compose(hm, hc, bm, bc, bm, bc);
   }
-  // exclusive values within the wavefront
-  double xfm = __shfl_up(fm, 1), xfc = __shfl_up(fc, 1);
-  double xbm = __shfl_down(bm, 1), xbc = __shfl_down(bc, 1);
-  if (lane == 0) {
-    xfm = 1.0;
-    xfc = 0.0;
-  }
-  if (lane == kWave - 1) {
-    xbm = 1.0;
-    xbc = 0.0;
-  }
+  // exclusive values within the wavefront (identity at the ends)
+  const double xfm = dpp_f64<kDppWaveShr1>(fm, 1.0), xfc = dpp_f64<kDppWaveShr1>(fc, 0.0);
+  const double xbm = dpp_f64<kDppWaveShl1>(bm, 1.0), xbc = dpp_f64<kDppWaveShl1>(bc, 0.0);
   // wavefront totals and reduction partials to LDS
-  const double tfm = __shfl(fm, kWave - 1), tfc = __shfl(fc, kWave - 1);
-  const double tbm = __shfl(bm, 0), tbc = __shfl(bc, 0);
+  const double tfm = readlane_f64(fm, kWave - 1), tfc = readlane_f64(fc, kWave - 1);
+  const double tbm = readlane_f64(bm, 0), tbc = readlane_f64(bc, 0);
   if (lane == 0) {
     double* rec = L.helm[slot][wv];
     rec[0] = tfm;
@@ -95,9 +142,10 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
     rec[6] = red2;
   }
   __syncthreads();
-  // Combine the W records: lane v < W of every wavefront takes record v; the
-  // forward records compose left to right, the backward ones right to left,
-  // by shuffle scans over those lanes (identities in the other lanes).
+  // Combine the W records: lane v < W of every wavefront takes record v
+  // (identities elsewhere); forward records compose left to right, backward
+  // ones right to left, by DPP steps inside row 0; the values this wavefront
+  // needs are read back with readlane.
   double f0 = 1.0, f1 = 0.0, b0 = 1.0, b1 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
   if (lane < W) {
     const double* rec = L.helm[slot][lane];
@@ -109,35 +157,22 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
     q1 = rec[5];
     q2 = rec[6];
   }
-#pragma unroll
-  for (int d = 1; d < W; d <<= 1) {
-    const double pm = __shfl_up(f0, d), pc = __shfl_up(f1, d);
-    const double qm = __shfl_down(b0, d), qc = __shfl_down(b1, d);
-    if (lane >= d) compose(pm, pc, f0, f1, f0, f1);
-    if (lane + d < W) compose(qm, qc, b0, b1, b0, b1);
-    q0 = fmax(q0, __shfl_xor(q0, d));
-    q1 = fmax(q1, __shfl_xor(q1, d));
-    q2 = fmax(q2, __shfl_xor(q2, d));
+  record_scan<W>(f0, f1, b0, b1, q0, q1, q2);
+  gred0 = readlane_f64(q0, W - 1);
+  gred1 = readlane_f64(q1, W - 1);
+  gred2 = readlane_f64(q2, W - 1);
+  const double allfc = readlane_f64(f1, W - 1);
+  const double allbc = readlane_f64(b1, 0);
+  const int wvu = __builtin_amdgcn_readfirstlane(wv);
+  double inm = 1.0, inc = 0.0, rim = 1.0, ric = 0.0;
+  if (wvu > 0) {
+    inm = readlane_f64(f0, wvu - 1);
+    inc = readlane_f64(f1, wvu - 1);
   }
-  // lanes >= W reduced zeros among themselves: take lane 0's maxima
-  gred0 = __shfl(q0, 0);
-  gred1 = __shfl(q1, 0);
-  gred2 = __shfl(q2, 0);
-  // totals, and the carries entering this wavefront from the left / right
-  const double allfm = __shfl(f0, W - 1), allfc = __shfl(f1, W - 1);
-  const double allbm = __shfl(b0, 0), allbc = __shfl(b1, 0);
-  double inm = __shfl(f0, wv > 0 ? wv - 1 : 0), inc = __shfl(f1, wv > 0 ? wv - 1 : 0);
-  double rim = __shfl(b0, wv + 1 < W ? wv + 1 : 0), ric = __shfl(b1, wv + 1 < W ? wv + 1 : 0);
-  if (wv == 0) {
-    inm = 1.0;
-    inc = 0.0;
+  if (wvu + 1 < W) {
+    rim = readlane_f64(b0, wvu + 1);
+    ric = readlane_f64(b1, wvu + 1);
   }
-  if (wv == W - 1) {
-    rim = 1.0;
-    ric = 0.0;
-  }
-  (void)allfm;
-  (void)allbm;
   // thread-exclusive carries: forward carry at node start-1, product r^start;
   // backward carry at node end+1, product r^(nx - end - 1)
   double pfm, pfc, pbm, pbc;
