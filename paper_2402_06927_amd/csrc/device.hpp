@@ -239,9 +239,9 @@ __device__ __forceinline__ double pcr_cyclic(double A, double B, double C, doubl
     if (__any(fabs(A) + fabs(C) > 0x1.0p-60 * fabs(B)) && (t & (kWave - 1)) == 0)
       atomicOr(&L.stop[level], 1);
     __syncthreads();
-    if (L.stop[level] == 0) return R / B;
+    if (L.stop[level] == 0) return R * rcp64(B);
   }
-  return R / (A + B + C);
+  return R * rcp64(A + B + C);
 }
 
 // Workgroup solve of the periodic tridiagonal system

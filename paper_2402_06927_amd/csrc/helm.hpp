@@ -21,6 +21,7 @@ namespace sch {
 
 struct HelmConst {
   double r, coef;   // root and 1/(kappa (1 - r^2)), kappa = -o / r
+  double rinv;      // 1 / r
   double rN1;       // 1/(1 - r^nx)
   double rb, rb1;   // r^base, r^(base+1): multipliers of chunks of base / base+1 rows
   int base;         // nx / NT
@@ -187,7 +188,7 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   // factor grows by r per slot
   double rf = r;
   double rbk = mth;  // r^(cnt - j), starting at j = 0
-  const double ir = 1.0 / r;
+  const double ir = K.rinv;
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
     u[j] = K.coef * fma(rbk, Em, fma(rf, Ep, sc[j]));

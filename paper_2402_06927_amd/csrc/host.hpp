@@ -88,6 +88,7 @@ inline HelmConst make_helm(const sch_model& md, const Tile& tl) {
   K.base = md.nx / tl.nt;
   K.rb = std::pow(K.r, static_cast<double>(K.base));
   K.rb1 = std::pow(K.r, static_cast<double>(K.base + 1));
+  K.rinv = 1.0 / K.r;
   return K;
 }
 

@@ -134,29 +134,29 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
         c = fma(0.25, vp, ao);
       };
       cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t);
+      // max change and max size of m*; a non-finite entry makes the change
+      // +infinity (fmax would drop a NaN), which marks the iterate as failed
       double diff = 0.0, scale = 0.0;
-      int bad = 0;
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) {
         ms[j] -= m[j];
         if (FULL || j < cnt) {
-          diff = fmax(diff, fabs(ms[j] - getP(j)));
+          const double dj = fabs(ms[j] - getP(j));
+          diff = fmax(diff, (dj <= 1.7976931348623157e308) ? dj : INFINITY);
           scale = fmax(scale, fabs(ms[j]));
-          bad |= !isfinite(ms[j]);
         }
         setP(j, ms[j]);
       }
       diff = wave_max(diff);
       scale = wave_max(scale);
-      bad = wave_or(bad);
       // u* = H^{-1} M m*
       double r[PMAX];
       mass_apply<PMAX, NT, FULL>(ms, r, P.h, cnt, L, t, 1.0, par.hs);
-      double uL, uR, gdiff, gscale, gbad;
-      solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale,
-                                 bad ? 1.0 : 0.0, gdiff, gscale, gbad);
+      double uL, uR, gdiff, gscale, gunused;
+      solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale, 0.0,
+                                 gdiff, gscale, gunused);
       par.slot ^= 1;
-      if (gbad > 0.0) {
+      if (!(gdiff < INFINITY)) {
         status = SCH_E_NONFINITE;
         break;
       }
