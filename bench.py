@@ -43,6 +43,7 @@ def flops_per_node_step(n_modes: int) -> int:
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
 # 1 GiB copy), valid for the kernel sources with the hash below.
 TRAFFIC_JITTER_BYTES = (285185.5 * 2.0 + 353465.5 * 1.0) * 1024
+TRAFFIC_THREADS = 512
 TRAFFIC_SOURCES_HASH = "e768d8ee29103dc0"
 
 
@@ -388,6 +389,8 @@ def main():
                     default="tempered",
                     help="tempered: the headline filter; nudging: one nudged window; "
                          "warmstart: plain vs learned warm-start nudging")
+    ap.add_argument("--threads", type=int, default=0,
+                    help="threads per particle of the model kernels (0 = automatic)")
     ap.add_argument("--train-windows", type=int, default=4)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -404,6 +407,10 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
+    if args.threads:
+        from paper_2402_06927_amd import sch as _sch
+
+        _sch.sch_tune_set(_sch.TUNE_THREADS, args.threads)
     if args.workload == "nudging":
         bench_nudging(args)
         return
@@ -453,6 +460,13 @@ def main():
     sigma = torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64, device=dev)
     ws = sch.workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
     m_cpu0, u_cpu0 = None, None
+    if not args.threads:
+        from paper_2402_06927_amd import autotune
+
+        tuned, tile_ms = autotune.tune(model, m, u)
+        log(f"autotuned threads per particle: {tuned} ({tile_ms})")
+    else:
+        tuned, tile_ms = args.threads, {}
 
     def run_cycle(c):
         obs = sch.Obs(yobs[c].contiguous(), sigma)
@@ -502,7 +516,7 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(j_tflops / PEAK_FP64_TFLOPS, 4),
         "traffic": (TRAFFIC_JITTER_BYTES if kernel_sources_hash() == TRAFFIC_SOURCES_HASH
-                    and wl.nx == 4096 and n == 1024 else None),
+                    and wl.nx == 4096 and n == 1024 and tuned == TRAFFIC_THREADS else None),
         "kernel": "k_jitter (fused pCN proposal + window rerun + likelihood + accept)",
         "avg_launch_ms": round(j_ms, 3),
         "algorithmic_flops_per_launch": j_flops / j_launches,
@@ -526,7 +540,7 @@ def main():
             "workload": wl.name, "filter": "tempered+jittered", "nx": nx, "n_particles": n,
             "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs, "sigma_obs": wl.sigma_obs,
             "ess_threshold": wl.ess_threshold, "n_bisect": wl.n_bisect,
-            "n_jitter": wl.n_jitter, "rho": wl.rho,
+            "n_jitter": wl.n_jitter, "rho": wl.rho, "threads_per_particle": tuned,
         },
         "particle_steps_per_s": round(psteps_per_s, 1),
         "tempering_steps_per_cycle": n_temper,

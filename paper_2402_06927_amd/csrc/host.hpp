@@ -102,6 +102,7 @@ inline int with_tile(const Tile& tl, F&& f) {
   SCH_CASE(64, 8)
   SCH_CASE(128, 8)
   SCH_CASE(256, 8)
+  SCH_CASE(256, 16)
   SCH_CASE(512, 8)
   SCH_CASE(512, 16)
 #undef SCH_CASE

@@ -332,3 +332,48 @@ def test_tempered_cycle_parity(sch):
         assert st["n_accept"] == st_o.n_accept
         assert PR.rel_l2(N(m), m_o) < PR.REL_TOL, c
         assert PR.rel_l2(N(u), u_o) < PR.REL_TOL, c
+
+
+@pytest.mark.parametrize("nx", [100, 600, 1000, 2048, 4096])
+def test_window_parity_every_tile(sch, nx):
+    """Every compiled tile (threads per particle x register slots) the tuner
+    may choose for this grid gives the oracle's window."""
+    from paper_2402_06927_amd import autotune as A
+
+    wl = W.BOOTSTRAP_256.scaled(nx=nx, n_modes=8, n_steps=6)
+    om, gm = PR.oracle_model(wl), PR.gpu_model(wl)
+    n = 3
+    u0, m0, _, _ = PR.prior(wl, n)
+    dW = O.draw_increments(wl.seed, n, wl.n_steps, 8, 0, O.TAG_FORECAST, 0, wl.dt)
+    worst, m_ref, u_ref, _, _ = O.ensemble_window(om, m0, u0, dW)
+    assert worst == 0
+    try:
+        for nt in A.candidates(nx):
+            _say("tile", nx, nt)
+            sch.sch_tune_set(sch.TUNE_THREADS, nt)
+            m, u = T(m0), T(u0)
+            status = torch.full((n,), 99, dtype=torch.int32, device="cuda")
+            sch.sch_ensemble_step(gm, m, u, T(dW), None, status)
+            assert np.all(N(status) == 0), nt
+            assert PR.rel_l2(N(m), m_ref) < PR.REL_TOL, nt
+            assert PR.rel_l2(N(u), u_ref) < PR.REL_TOL, nt
+    finally:
+        sch.sch_tune_set(sch.TUNE_THREADS, 0)
+
+
+def test_autotuner_picks_a_compiled_tile(sch, tmp_path):
+    from paper_2402_06927_amd import autotune as A
+
+    wl = W.BOOTSTRAP_256.scaled(nx=2048, n_modes=8)
+    gm = PR.gpu_model(wl)
+    u0, m0, _, _ = PR.prior(wl, 16)
+    cache = str(tmp_path / "tiles.json")
+    try:
+        best, timing = A.tune(gm, T(m0), T(u0), cache=cache)
+        assert best in A.candidates(2048) and set(timing) == set(A.candidates(2048))
+        assert sch.sch_tune_get(sch.TUNE_THREADS) == best
+        assert A.load_cache(cache) == {2048: best}
+        again, t2 = A.tune(gm, T(m0), T(u0), cache=cache)
+        assert again == best and t2 == {}
+    finally:
+        sch.sch_tune_set(sch.TUNE_THREADS, 0)
