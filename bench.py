@@ -42,9 +42,9 @@ def flops_per_node_step(n_modes: int) -> int:
 # HBM traffic of one k_jitter launch at this workload from two rocprofv3
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
 # 1 GiB copy), valid for the kernel sources with the hash below.
-TRAFFIC_JITTER_BYTES = (285185.5 * 2.0 + 353465.5 * 1.0) * 1024
-TRAFFIC_THREADS = 512
-TRAFFIC_SOURCES_HASH = "e768d8ee29103dc0"
+TRAFFIC_JITTER_BYTES = (93526.9 * 2.0 + 218375.8 * 1.0) * 1024
+TRAFFIC_THREADS = 256
+TRAFFIC_SOURCES_HASH = "691f951da1a08211"
 
 
 def kernel_sources_hash() -> str:

@@ -52,10 +52,11 @@ def save_cache(path: str, table: dict):
     os.replace(tmp, path)
 
 
-def tune(model: sch.Model, m: torch.Tensor, u: torch.Tensor, n_steps: int = 4, reps: int = 2,
+def tune(model: sch.Model, m: torch.Tensor, u: torch.Tensor, n_steps: int = 6, reps: int = 3,
          cache: str | None = None, apply: bool = True) -> tuple[int, dict]:
     """Fastest thread count for the grid of `model` on the ensemble (m, u)
-    (not modified: copies are stepped).  Returns (threads, {threads: ms})."""
+    (not modified: copies are stepped; per tile the best of `reps` timed
+    windows of n_steps steps).  Returns (threads, {threads: ms})."""
     nx = model.nx
     table = load_cache(cache)
     if nx in table and table[nx] in candidates(nx):
@@ -70,15 +71,17 @@ def tune(model: sch.Model, m: torch.Tensor, u: torch.Tensor, n_steps: int = 4, r
         sch.sch_tune_set(sch.TUNE_THREADS, nt)
         mm, uu = m.clone(), u.clone()
         sch.sch_ensemble_step(model, mm, uu, dW)  # warm-up
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        best_ms = float("inf")
         for _ in range(reps):
             mm.copy_(m)
             uu.copy_(u)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             sch.sch_ensemble_step(model, mm, uu, dW)
-        e1.record()
-        torch.cuda.synchronize()
-        timing[nt] = e0.elapsed_time(e1) / reps
+            e1.record()
+            torch.cuda.synchronize()
+            best_ms = min(best_ms, e0.elapsed_time(e1))
+        timing[nt] = best_ms
     best = min(timing, key=timing.get)
     sch.sch_tune_set(sch.TUNE_THREADS, best if apply else 0)
     if cache:

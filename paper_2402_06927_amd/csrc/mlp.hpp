@@ -181,13 +181,23 @@ __global__ void k_mse(int64_t n, const float* Y, const float* T, float inv_count
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(loss, acc * inv_count);
 }
 
-// out[c] = sum_r A[r][c] (one thread per column, float64 accumulation).
-__global__ void k_colsum(int rows, int cols, const float* A, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// out[c] = sum_r A[r][c]: 256 threads per 32 columns, 8 row lanes each
+// summing every 8th row in float64, then the 8 partials in a fixed order.
+__global__ void __launch_bounds__(256) k_colsum(int rows, int cols, const float* A, float* out) {
+  __shared__ double part[8][32];
+  const int cl = threadIdx.x & 31, rl = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + cl;
   double s = 0.0;
-  for (int r = 0; r < rows; ++r) s += A[static_cast<int64_t>(r) * cols + c];
-  out[c] = static_cast<float>(s);
+  if (c < cols)
+    for (int r = rl; r < rows; r += 8) s += A[static_cast<int64_t>(r) * cols + c];
+  part[rl][cl] = s;
+  __syncthreads();
+  if (rl == 0 && c < cols) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t += part[i][cl];
+    out[c] = static_cast<float>(t);
+  }
 }
 
 // Column means and standard deviations (two passes, float64 accumulation);

@@ -144,7 +144,7 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   g.C32 = grad + d.oW3;
   g.ldc = H;
   launch_gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, st, batch, O, w.dY32,
+  hipLaunchKernelGGL(k_colsum, dim3((O + 31) / 32), dim3(256), 0, st, batch, O, w.dY32,
                      grad + d.ob3);
   // dZ2 = (dY W3) * [Z2 > 0]
   g = gemm(batch, H, O, w.dY16, O, 1, wb + d.qW3, H, 1);
@@ -160,7 +160,7 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   g.C32 = grad + d.oW2;
   g.ldc = H;
   launch_gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, batch, H, w.dZ2,
+  hipLaunchKernelGGL(k_colsum, dim3((H + 31) / 32), dim3(256), 0, st, batch, H, w.dZ2,
                      grad + d.ob2);
   // dZ1 = (dZ2 W2) * [Z1 > 0]
   g = gemm(batch, H, H, w.dZ2b, H, 1, wb + d.qW2, H, 1);
@@ -176,7 +176,7 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   g.C32 = grad + d.oW1;
   g.ldc = F;
   launch_gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, batch, H, w.dZ1,
+  hipLaunchKernelGGL(k_colsum, dim3((H + 31) / 32), dim3(256), 0, st, batch, H, w.dZ1,
                      grad + d.ob1);
   CHECK_LAUNCH();
   return SCH_OK;
