@@ -367,18 +367,14 @@ int sch_pf_tempered_cycle(const sch_model *model, const sch_obs *obs, uint64_t s
  *                     default choice of the model calls, or SCH_TUNE_THREADS)
  * sch_batch_params: physics and filter settings shared by all instances.
  *
- * STATUS: the batched runner is switched off in this version --
- * sch_batch_create returns SCH_E_ARG before any device work (its first GPU
- * runs stalled and the cause is not yet found).
- *
  * sch_batch_create lays the batch out in the caller's workspace (at least
  * sch_batch_workspace_bytes) and returns an opaque handle (host memory owned
  * by the library until sch_batch_destroy).  sch_batch_run advances n_cycles
  * cycles, cycle0 .. cycle0 + n_cycles - 1 (the cycle number selects the
  * observation row and the generator counters); with use_graph != 0 the cycle
  * is captured into a HIP graph on first use (on a stream the library creates)
- * and replayed on `stream` -- this path is currently switched off and returns
- * SCH_E_ARG; use_graph = 0 enqueues the same kernels directly.  sch_batch_read synchronises `stream` and copies
+ * and replayed on `stream`; use_graph = 0 enqueues the same kernels directly.
+ * sch_batch_read synchronises `stream` and copies
  * per-instance results to host arrays (each may be NULL): the ESS of the last
  * cycle, the number of resamplings since creation, and the first failure of
  * any particle (SCH_OK if none); picard_iters receives the implicit-solve

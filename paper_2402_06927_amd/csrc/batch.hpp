@@ -89,10 +89,20 @@ __global__ void __launch_bounds__(NT) k_batch_window(BatchDev B, const int* item
   __shared__ AuxLds<PMAX, NT> X;
   __shared__ int s_item;
   const int t = threadIdx.x;
+  // Work fetch without a lane-divergent branch: a divergent `if (t == 0)`
+  // at the top of this loop lets the compiler split the loop by lanes
+  // (thread 0 taken out to fetch while the rest of its wavefront re-runs the
+  // old item, forever).  Wavefront 0 takes a uniform branch, all its lanes
+  // join one atomic that adds 1 (lane 0's term), and the index lives in
+  // scalar registers.
+  const bool wave0 = __builtin_amdgcn_readfirstlane(t) == 0;
   for (;;) {
-    if (t == 0) s_item = static_cast<int>(atomicAdd(queue, 1u));
+    if (wave0) {
+      const unsigned v = atomicAdd(queue, t == 0 ? 1u : 0u);
+      s_item = static_cast<int>(__builtin_amdgcn_readfirstlane(v));
+    }
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n_items) break;
     const int g = items[it];

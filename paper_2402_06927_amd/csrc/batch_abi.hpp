@@ -32,12 +32,6 @@ namespace {
 
 using namespace sch;
 
-// The batched runner stalled in its first two test runs on the GPU (graph
-// replay, then direct launches) and the cause has not been found; until it
-// is, creating a batch fails before any device work.
-constexpr bool kBatchEnabled = false;
-constexpr bool kBatchGraphEnabled = false;
-
 
 // Tile of one instance: the threads the caller asked for, else the model
 // calls' choice; nodes per thread 4, 8 or 16.
@@ -172,8 +166,6 @@ int sch_batch_create(const sch_batch_params* bp, int32_t n_inst, const sch_insta
   int64_t G = 0, state = 0;
   if (int rc = check_batch(bp, n_inst, in, G, state)) return rc;
   if (!workspace || !out) return fail(SCH_E_ARG, "bad arguments to sch_batch_create");
-  if (!kBatchEnabled)
-    return fail(SCH_E_ARG, "the batched runner is switched off (its kernels stalled in testing)");
   for (int i = 0; i < n_inst; ++i)
     if (!in[i].xi || !in[i].m || !in[i].u || !in[i].logw || !in[i].y || !in[i].sigma)
       return fail(SCH_E_ARG, "instance %d has a NULL array", i);
@@ -323,10 +315,6 @@ int sch_batch_run(sch_batch* b, uint32_t cycle0, int32_t n_cycles, int32_t use_g
       if (int rc = enqueue_cycle(b, st)) return rc;
     return SCH_OK;
   }
-  // The graph replay stalled in its first test run and the cause has not been
-  // found; until it is, the capture path is switched off.
-  if (!kBatchGraphEnabled)
-    return fail(SCH_E_ARG, "graph replay of the batched runner is switched off; use use_graph = 0");
   if (!b->exec) {
     // capture one cycle on a stream of our own (the caller's may be the null
     // stream, which cannot be captured)

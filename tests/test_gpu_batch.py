@@ -98,12 +98,7 @@ def _compare(b, gi, ref, c, res_prev):
     return out["resampled"]
 
 
-BATCH_OFF = ("the batched runner is switched off: its first two GPU runs (graph replay, then "
-             "direct launches) stalled and the cause is not found yet")
-
-
-@pytest.mark.skip(BATCH_OFF)
-@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("use_graph", [False, True])
 def test_batch_parity_small(sch, use_graph):
     """Eight instances with ragged grids (nx in [64, 1200]) and ensembles in
     [4, 48], bootstrap physics of the Nx = 256 workload, three cycles; two
@@ -127,7 +122,6 @@ def test_batch_parity_small(sch, use_graph):
     b.close()
 
 
-@pytest.mark.skip(BATCH_OFF)
 def test_batch_graph_replays_match_direct_launches(sch):
     base = W.BOOTSTRAP_256.scaled(n_steps=8)
     insts = W.uneven_instances(5, seed=77, nx_range=(64, 700), np_range=(8, 40))
@@ -146,27 +140,36 @@ def test_batch_graph_replays_match_direct_launches(sch):
     assert runs[0][2]["picard_iters"] == runs[1][2]["picard_iters"]
 
 
-def test_batch_reports_switched_off(sch):
-    """Creating a batch fails with a clear error before any device work."""
+def test_batch_rejects_bad_instances(sch):
+    """Shape and argument errors are reported before any device work."""
     base = W.BOOTSTRAP_256.scaled(n_steps=2)
     insts = W.uneven_instances(2, seed=5, nx_range=(64, 128), np_range=(4, 8))
-    gi = []
-    for ins in insts:
-        z = torch.zeros((ins.n_particles, ins.nx), dtype=torch.float64, device="cuda")
-        gi.append(sch.Instance(xi=torch.zeros((base.n_modes, ins.nx), dtype=torch.float64,
-                                              device="cuda"),
-                               m=z, u=z.clone(), logw=torch.zeros(ins.n_particles,
-                                                                  dtype=torch.float64,
-                                                                  device="cuda"),
-                               y=torch.zeros((1, base.n_obs), dtype=torch.float64, device="cuda"),
-                               sigma=torch.ones(base.n_obs, dtype=torch.float64, device="cuda"),
-                               seed=ins.seed))
-    with pytest.raises(sch.SchError, match="switched off"):
-        sch.Batch(base.L, base.alpha, base.mu, base.dt, base.n_modes, base.n_steps, base.n_obs,
-                  base.ess_frac, gi)
+
+    def make(threads=0, y=True):
+        gi = []
+        for ins in insts:
+            z = torch.zeros((ins.n_particles, ins.nx), dtype=torch.float64, device="cuda")
+            gi.append(sch.Instance(
+                xi=torch.zeros((base.n_modes, ins.nx), dtype=torch.float64, device="cuda"),
+                m=z, u=z.clone(),
+                logw=torch.zeros(ins.n_particles, dtype=torch.float64, device="cuda"),
+                y=torch.zeros((1, base.n_obs), dtype=torch.float64, device="cuda") if y else None,
+                sigma=torch.ones(base.n_obs, dtype=torch.float64, device="cuda"),
+                seed=ins.seed, threads=threads))
+        return gi
+
+    def batch(gi):
+        return sch.Batch(base.L, base.alpha, base.mu, base.dt, base.n_modes, base.n_steps,
+                         base.n_obs, base.ess_frac, gi)
+
+    with pytest.raises(sch.SchError, match="NULL"):
+        batch(make(y=False))
+    with pytest.raises(sch.SchError, match="no tile"):
+        batch(make(threads=256))  # more threads than nodes
+    with pytest.raises(sch.SchError, match="no tile"):
+        batch(make(threads=96))   # not a power of two
 
 
-@pytest.mark.skip(BATCH_OFF)
 def test_batch_full_size_sampled(sch):
     """The 64-instance workload at full size (nx log-uniform in [512, 8192],
     ensembles log-uniform in [64, 2048]); the three smallest instances are
