@@ -42,9 +42,9 @@ def flops_per_node_step(n_modes: int) -> int:
 # HBM traffic of one k_jitter launch at this workload from two rocprofv3
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
 # 1 GiB copy), valid for the kernel sources with the hash below.
-TRAFFIC_JITTER_BYTES = (93526.9 * 2.0 + 218375.8 * 1.0) * 1024
+TRAFFIC_JITTER_BYTES = (93047.2 * 2.0 + 218439.4 * 1.0) * 1024
 TRAFFIC_THREADS = 256
-TRAFFIC_SOURCES_HASH = "691f951da1a08211"
+TRAFFIC_SOURCES_HASH = "04da7758a08855d9"
 
 
 def kernel_sources_hash() -> str:
@@ -377,6 +377,160 @@ def bench_mlp(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_batch(args):
+    """64 independent bootstrap filters of uneven sizes (grids log-uniform in
+    [512, 8192], ensembles log-uniform in [64, 2048]; physics of the Nx = 256
+    bootstrap workload with per-instance seeds) advanced together: one step =
+    one assimilation cycle of every instance as one HIP graph replay
+    (forecast noise, persistent forecast kernels per tile class, likelihood,
+    weights, conditional resampling, gathers).  Tiles come from the autotuner
+    (one tuning per group of grids with the same tile options)."""
+    import torch
+
+    from paper_2402_06927_amd import autotune
+    from paper_2402_06927_amd import sch
+    from paper_2402_06927_amd import workloads as W
+
+    sch.lib()
+    base = W.BOOTSTRAP_256
+    insts = W.uneven_instances(64)
+    dev = "cuda"
+    Q, S, nobs = base.n_modes, base.n_steps, base.n_obs
+    n_cycles = args.warmup + args.steps + 1
+    node_states = sum(i.nx * i.n_particles for i in insts)
+    G = sum(i.n_particles for i in insts)
+    log(f"bench batch: {len(insts)} instances, {G} particles, {node_states} node-states")
+
+    def make_model(nx, xi=None):
+        if xi is None:
+            xi = torch.tensor(W.mode_table(base.L, nx, Q, base.mode_amp), device=dev)
+        return sch.Model(L=base.L, alpha=base.alpha, mu=base.mu, dt=base.dt, xi=xi,
+                         picard_tol=base.picard_tol, picard_max=base.picard_max)
+
+    t0 = time.perf_counter()
+    tiles = autotune.tune_batch(make_model, [i.nx for i in insts])
+    log(f"tiles per grid group: {sorted(set(tiles.values()))} ({time.perf_counter() - t0:.1f} s)")
+    gi, models = [], []
+    sig = torch.full((nobs,), base.sigma_obs, dtype=torch.float64, device=dev)
+    for k, ins in enumerate(insts):
+        wl = base.scaled(nx=ins.nx, n_particles=ins.n_particles, seed=ins.seed)
+        xi = torch.tensor(W.mode_table(wl.L, wl.nx, Q, wl.mode_amp), device=dev)
+        model = make_model(ins.nx, xi)
+        u = torch.tensor(W.initial_velocity(wl, ins.n_particles, wl.seed), device=dev)
+        m = torch.empty_like(u)
+        sch.sch_init_momentum(model, u, m)
+        # truth (seed + 1) and its observations for every cycle
+        ts = W.truth_seed(wl)
+        ut = torch.tensor(W.initial_velocity(wl, 1, ts), device=dev)
+        mt = torch.empty_like(ut)
+        sch.sch_init_momentum(model, ut, mt)
+        z = torch.tensor(W.obs_noise(wl, ts, n_cycles), device=dev)
+        dWt = torch.empty((1, S, Q), dtype=torch.float64, device=dev)
+        y = torch.empty((n_cycles, nobs), dtype=torch.float64, device=dev)
+        for c in range(n_cycles):
+            sch.sch_draw_increments(ts, c, 0, sch.TAG_FORECAST, dWt, wl.dt)
+            sch.sch_ensemble_step(model, mt, ut, dWt)
+            sch.sch_observe(model, ut, y[c:c + 1])
+        y += wl.sigma_obs * z
+        gi.append(sch.Instance(xi=xi, m=m, u=u, logw=torch.zeros(ins.n_particles,
+                                                                 dtype=torch.float64, device=dev),
+                               y=y, sigma=sig, seed=ins.seed, threads=tiles[ins.nx]))
+        models.append(model)
+    b = sch.Batch(base.L, base.alpha, base.mu, base.dt, Q, S, nobs, base.ess_frac, gi,
+                  base.picard_tol, base.picard_max)
+    torch.cuda.synchronize()
+    log(f"set-up {time.perf_counter() - t0:.1f} s")
+    for c in range(args.warmup):
+        b.run(c, 1, use_graph=True)
+    out0 = b.read()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    e0.record()
+    for c in range(args.warmup, args.warmup + args.steps):
+        b.run(c, 1, use_graph=True)
+    e1.record()
+    out1 = b.read()
+    elapsed = time.perf_counter() - t1
+    ms = e0.elapsed_time(e1) / args.steps
+    iters_graph = out1["picard_iters"] - out0["picard_iters"]
+    # one more cycle with direct launches and timing events: the forecast
+    # kernels' share
+    sch.sch_timing_reset()
+    sch.sch_timing_enable(True)
+    b.run(args.warmup + args.steps, 1, use_graph=False)
+    out2 = b.read()
+    sch.sch_timing_enable(False)
+    tim = sch.sch_timing_read()
+    iters_direct = out2["picard_iters"] - out1["picard_iters"]
+    b.close()
+    node_steps = node_states * S
+    kbar = iters_direct / (G * S)
+    flops = node_steps * (FLOPS_PER_NODE_ITER * kbar + flops_per_node_step(Q))
+    w_ms = tim["window"]["ms"]
+    tf = flops / (w_ms * 1e-3) / 1e12 if w_ms > 0 else 0.0
+    out = {
+        "metric": "batched uneven filters: assimilation cycles/s of all 64 instances (one graph replay per cycle)",
+        "value": round(1e3 / ms, 4), "unit": "cycles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch64_uneven", "instances": len(insts), "particles": G,
+                   "node_states": node_states, "nx_range": [512, 8192],
+                   "particles_range": [64, 2048], "n_modes": Q, "n_steps": S, "n_obs": nobs,
+                   "filter": "bootstrap", "tiles": {str(k): v for k, v in sorted(tiles.items())}},
+        "node_steps_per_s": round(node_steps * 1e3 / ms, 1),
+        "particle_steps_per_s": round(G * S * 1e3 / ms, 1),
+        "picard_iters_per_step": round(iters_graph / (G * S * args.steps), 3),
+        "resamplings": out1["resampled"],
+        "host_ms_per_cycle": round(1e3 * elapsed / args.steps, 3),
+        "kernel_ms_direct_cycle": {k: round(v["ms"], 3) for k, v in tim.items()},
+        "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_batch_window (persistent forecast, all tile classes of one cycle)",
+                     "avg_launch_ms": round(w_ms, 3), "algorithmic_flops_per_launch": flops,
+                     "picard_iters_per_step": round(kbar, 3)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        order = sorted(range(len(insts)), key=lambda k: insts[k].nx * insts[k].n_particles)
+        # forecast windows of instances from the median size upwards until
+        # about 10 s of oracle work
+        done_ns, spent, used, worst = 0, 0.0, [], 0
+        for k in order[len(order) // 2:]:
+            ins = insts[k]
+            wl = base.scaled(nx=ins.nx, n_particles=ins.n_particles, seed=ins.seed)
+            xi = W.mode_table(wl.L, wl.nx, Q, wl.mode_amp)
+            om = O.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
+                         picard_tol=wl.picard_tol, picard_max=wl.picard_max)
+            u = W.initial_velocity(wl, ins.n_particles, wl.seed)
+            mo = O.momentum_from_velocity(om, u)
+            dW = O.draw_increments(wl.seed, ins.n_particles, S, Q, 0, O.TAG_FORECAST, 0, wl.dt)
+            log(f"cpu baseline: oracle forecast of instance {k} (nx {ins.nx}, "
+                f"{ins.n_particles} particles), {threads} threads ...")
+            t2 = time.perf_counter()
+            st, _, _, _, _ = O.ensemble_window(om, mo, u, dW, n_threads=threads)
+            spent += time.perf_counter() - t2
+            worst = worst or st
+            done_ns += ins.nx * ins.n_particles * S
+            used.append(k)
+            if spent >= 10.0:
+                break
+        rate = done_ns / spent
+        out["cpu_baseline"] = {
+            "value": rate / node_steps, "unit": "cycles/s", "cores": threads, "kind": "oracle",
+            "sample": (f"forecast windows of {len(used)} instances from the median size up "
+                       f"({done_ns} node-steps in {spent:.1f} s, {rate:.3g} node-steps/s), "
+                       f"scaled by the {node_steps} node-steps of one cycle of all 64 "
+                       f"instances; oracle status {worst}"),
+            "node_steps_per_s": rate,
+        }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,10 +539,11 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--workload", choices=("tempered", "nudging", "warmstart", "mlp"),
+    ap.add_argument("--workload", choices=("tempered", "nudging", "warmstart", "mlp", "batch"),
                     default="tempered",
                     help="tempered: the headline filter; nudging: one nudged window; "
-                         "warmstart: plain vs learned warm-start nudging")
+                         "warmstart: plain vs learned warm-start nudging; mlp: the "
+                         "warm-start network; batch: 64 uneven filters in one graph")
     ap.add_argument("--threads", type=int, default=0,
                     help="threads per particle of the model kernels (0 = automatic)")
     ap.add_argument("--train-windows", type=int, default=4)
@@ -419,6 +574,9 @@ def main():
         return
     if args.workload == "mlp":
         bench_mlp(args)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
 
     from paper_2402_06927_amd import sch

@@ -88,3 +88,43 @@ def tune(model: sch.Model, m: torch.Tensor, u: torch.Tensor, n_steps: int = 6, r
         table[nx] = best
         save_cache(cache, table)
     return best, timing
+
+
+def tile_key(nx: int) -> tuple:
+    """Instances whose grids share this key have the same compiled tiles to
+    choose from."""
+    return tuple((nt, slots(nx, nt)) for nt in candidates(nx))
+
+
+def tune_batch(make_model, nxs, n_particles: int = 1024, cache: str | None = None,
+               seed: int = 1) -> dict[int, int]:
+    """Threads per particle for every grid size in `nxs` (the instances of a
+    batch): grids are grouped by their tile options, each group is tuned once
+    at its median grid on a sample ensemble of `n_particles` (smooth random
+    states; enough workgroups to fill the chip for every tile, so that the
+    smaller tiles are not judged on a half-empty GPU), and the choice
+    applies to the whole group.  `make_model(nx)`
+    returns an sch.Model for grid nx.  Leaves SCH_TUNE_THREADS unset."""
+    import numpy as np
+
+    groups: dict[tuple, list[int]] = {}
+    for nx in sorted(set(int(x) for x in nxs)):
+        groups.setdefault(tile_key(nx), []).append(nx)
+    choice = {}
+    g = np.random.default_rng(seed)
+    for key, members in groups.items():
+        if len(key) == 1:
+            best = key[0][0]
+        else:
+            nx = members[len(members) // 2]
+            model = make_model(nx)
+            x = np.arange(nx) / nx
+            u = np.stack([0.2 / np.cosh((x - 0.5) * 20.0 + 0.1 * g.standard_normal()) ** 2
+                          for _ in range(n_particles)])
+            ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+            mt = torch.empty_like(ut)
+            sch.sch_init_momentum(model, ut, mt)
+            best, _ = tune(model, mt, ut, cache=cache, apply=False)
+        for nx in members:
+            choice[nx] = best
+    return choice

@@ -244,8 +244,9 @@ struct TimedScope {
   int kind;
   hipStream_t st;
   hipEvent_t a = nullptr;
+  // kind < 0: no timing
   TimedScope(int k, hipStream_t s) : kind(k), st(s) {
-    if (g_tm.on && (a = g_tm.get())) (void)hipEventRecord(a, st);
+    if (k >= 0 && g_tm.on && (a = g_tm.get())) (void)hipEventRecord(a, st);
   }
   ~TimedScope() {
     if (!a) return;

@@ -117,33 +117,51 @@ int with_batch_class(int nt, int pm, F&& f) {
   return fail(SCH_E_SHAPE, "no batched kernel for %d threads x %d nodes", nt, pm);
 }
 
-// One assimilation cycle of every instance, enqueued on `st`.
-int enqueue_cycle(sch_batch* b, hipStream_t st) {
+// One assimilation cycle of every instance, enqueued on `st`.  `timed`
+// brackets the kernel classes with timing events (direct launches only, not
+// under graph capture).
+int enqueue_cycle(sch_batch* b, hipStream_t st, bool timed) {
   const BatchDev& B = b->dev;
-  for (auto& c : b->classes) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, c.queue, 0u, 1);
-  }
+  auto scope = [&](int kind) { return TimedScope(timed ? kind : -1, st); };
   {
+    auto ts = scope(SCH_TK_OTHER);
+    for (auto& c : b->classes)
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, c.queue, 0u, 1);
     const int64_t work = static_cast<int64_t>(b->G) * b->n_steps * ((b->n_modes + 1) / 2);
     hipLaunchKernelGGL(k_batch_draw, dim3(grid_for(work, 256)), dim3(256), 0, st, B);
   }
-  for (auto& c : b->classes) {
-    const int* items = b->items + c.first;
-    const int n_items = c.count;
-    unsigned int* q = c.queue;
-    const int grid = c.grid;
-    if (int rc = with_batch_class(c.nt, c.pmax, [&]<int PM, int NT>() -> int {
-          hipLaunchKernelGGL((k_batch_window<PM, NT>), dim3(grid), dim3(NT), 0, st, B, items,
-                             n_items, q);
-          return SCH_OK;
-        }))
-      return rc;
+  {
+    auto ts = scope(SCH_TK_WINDOW);
+    for (auto& c : b->classes) {
+      const int* items = b->items + c.first;
+      const int n_items = c.count;
+      unsigned int* q = c.queue;
+      const int grid = c.grid;
+      if (int rc = with_batch_class(c.nt, c.pmax, [&]<int PM, int NT>() -> int {
+            hipLaunchKernelGGL((k_batch_window<PM, NT>), dim3(grid), dim3(NT), 0, st, B, items,
+                               n_items, q);
+            return SCH_OK;
+          }))
+        return rc;
+    }
   }
-  hipLaunchKernelGGL(k_batch_loglik, dim3(b->G), dim3(kWave), 0, st, B);
-  hipLaunchKernelGGL(k_batch_weights, dim3(b->n_inst), dim3(kTB), 0, st, B);
-  hipLaunchKernelGGL(k_batch_resample, dim3(b->n_inst), dim3(kTB), 0, st, B);
-  hipLaunchKernelGGL(k_batch_gather, dim3(b->G), dim3(256), 0, st, B, 0);
-  hipLaunchKernelGGL(k_batch_gather, dim3(b->G), dim3(256), 0, st, B, 1);
+  {
+    auto ts = scope(SCH_TK_OTHER);
+    hipLaunchKernelGGL(k_batch_loglik, dim3(b->G), dim3(kWave), 0, st, B);
+  }
+  {
+    auto ts = scope(SCH_TK_TEMPER);
+    hipLaunchKernelGGL(k_batch_weights, dim3(b->n_inst), dim3(kTB), 0, st, B);
+  }
+  {
+    auto ts = scope(SCH_TK_RESAMPLE);
+    hipLaunchKernelGGL(k_batch_resample, dim3(b->n_inst), dim3(kTB), 0, st, B);
+  }
+  {
+    auto ts = scope(SCH_TK_GATHER);
+    hipLaunchKernelGGL(k_batch_gather, dim3(b->G), dim3(256), 0, st, B, 0);
+    hipLaunchKernelGGL(k_batch_gather, dim3(b->G), dim3(256), 0, st, B, 1);
+  }
   hipLaunchKernelGGL(k_batch_next_cycle, dim3(1), dim3(64), 0, st, b->cycle);
   CHECK_LAUNCH();
   return SCH_OK;
@@ -312,7 +330,7 @@ int sch_batch_run(sch_batch* b, uint32_t cycle0, int32_t n_cycles, int32_t use_g
   CHECK_LAUNCH();
   if (!use_graph) {
     for (int c = 0; c < n_cycles; ++c)
-      if (int rc = enqueue_cycle(b, st)) return rc;
+      if (int rc = enqueue_cycle(b, st, true)) return rc;
     return SCH_OK;
   }
   if (!b->exec) {
@@ -324,7 +342,7 @@ int sch_batch_run(sch_batch* b, uint32_t cycle0, int32_t n_cycles, int32_t use_g
       (void)hipStreamDestroy(cs);
       return fail(SCH_E_HIP, "graph capture could not start");
     }
-    const int rc = enqueue_cycle(b, cs);
+    const int rc = enqueue_cycle(b, cs, false);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
@@ -361,6 +379,7 @@ int sch_batch_read(sch_batch* b, double* ess, int32_t* resampled, int32_t* statu
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(&acc, B.acc, sizeof acc, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  timing_flush();
   if (status)
     for (int i = 0; i < b->n_inst; ++i) {
       status[i] = SCH_OK;

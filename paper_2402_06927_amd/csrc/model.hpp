@@ -53,11 +53,14 @@ struct Parity {
 
 // Two per-node arrays of the window (the explicit part of dv and the previous
 // Picard iterate) live in LDS as [slot][thread] when they fit next to the
-// solver's LDS, in registers otherwise.
+// solver's LDS (64 KiB for both); when only one fits, the explicit part goes
+// to LDS and the iterate stays in registers; otherwise both do.
 template <int PMAX, int NT>
 struct AuxLds {
-  static constexpr bool kInLds = 2 * PMAX * NT * sizeof(double) <= 65536;
-  double a[kInLds ? 2 : 1][kInLds ? PMAX : 1][kInLds ? NT : 1];
+  static constexpr size_t kBytes = static_cast<size_t>(PMAX) * NT * sizeof(double);
+  static constexpr bool kInLds = 2 * kBytes <= 65536;  // both arrays
+  static constexpr bool kDInLds = kBytes <= 65536;     // the explicit part
+  double a[kInLds ? 2 : 1][kDInLds ? PMAX : 1][kDInLds ? NT : 1];
 };
 
 // One assimilation window of n_steps implicit-midpoint steps (eq. fde1) for
@@ -80,13 +83,13 @@ template <int PMAX, int NT, bool FULL, class IncF>
 __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int n_steps,
                           double (&m)[PMAX], double (&u)[PMAX], const Chunk& ch, RowLds<NT>& L,
                           AuxLds<PMAX, NT>& X, int t, Parity& par, int& iters) {
-  constexpr bool kLds = AuxLds<PMAX, NT>::kInLds;
+  constexpr bool kLds = AuxLds<PMAX, NT>::kInLds, kDLds = AuxLds<PMAX, NT>::kDInLds;
   const int cnt = ch.cnt;
   const double hdt = 0.5 * P.dt;
   const double f1 = P.h / 3.0, f0 = 4.0 * P.h / 3.0;  // 2 M: (h/3, 4h/3, h/3)
-  double rD[kLds ? 1 : PMAX], rP[kLds ? 1 : PMAX];
-  auto getD = [&](int j) -> double { if constexpr (kLds) return X.a[0][j][t]; else return rD[j]; };
-  auto setD = [&](int j, double v) { if constexpr (kLds) X.a[0][j][t] = v; else rD[j] = v; };
+  double rD[kDLds ? 1 : PMAX], rP[kLds ? 1 : PMAX];
+  auto getD = [&](int j) -> double { if constexpr (kDLds) return X.a[0][j][t]; else return rD[j]; };
+  auto setD = [&](int j, double v) { if constexpr (kDLds) X.a[0][j][t] = v; else rD[j] = v; };
   auto getP = [&](int j) -> double { if constexpr (kLds) return X.a[1][j][t]; else return rP[j]; };
   auto setP = [&](int j, double v) { if constexpr (kLds) X.a[1][j][t] = v; else rP[j] = v; };
   for (int n = 0; n < n_steps; ++n) {
