@@ -154,7 +154,9 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
   int status = SCH_E_NONCONVERGED, k = 1;
   for (; k <= P.picard_max + 1; ++k) {
     double nn[PMAX];
-    cyclic_solve<PMAX, NT, FULL>(rowAT, [&](int j) { return rhs[j]; }, nn, cnt, L, t);
+    double xl_unused, xr_unused;
+    cyclic_solve<PMAX, NT, FULL>(rowAT, [&](int j) { return rhs[j]; }, nn, cnt, L, t, xl_unused,
+                                 xr_unused);
     double diff = 0.0, scale = 0.0;
     int bad = 0;
 #pragma unroll

@@ -89,6 +89,13 @@ template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int src, int old) {
   return __builtin_amdgcn_update_dpp(old, src, CTRL, 0xf, 0xf, false);
 }
+// The same with bound control: lanes without a source lane read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64z(double src) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(src), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(src), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
 // lane must be wave-uniform
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -139,14 +146,12 @@ struct RowLds {
   int stop[16];                               // per-level "coupling remains" flags
 };
 
-// 1/x to full double precision: hardware estimate plus two Newton steps
-// (about one ulp; the divisors here are pivots bounded away from zero).
+// 1/x for the solvers' pivots: the hardware estimate (relative error about
+// 5e-8 on gfx950) and one Newton step, which squares that error (at most
+// about 11 ulp, 2e-15 relative); the pivots are bounded away from zero.
 __device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
 // A row of the periodic mesh is split over the NT threads of a workgroup:
@@ -252,12 +257,14 @@ __device__ __forceinline__ double pcr_cyclic(double A, double B, double C, doubl
 // (two spike columns), the interface rows form a periodic tridiagonal system
 // of NT unknowns solved by cyclic reduction, and the chunk is recombined.
 // row(j, a, b, c) returns the coefficients of local slot j and d(j) its
-// right-hand side (both evaluated once per slot).  No pivoting: the
+// right-hand side (both evaluated once per slot).  xl and xr receive the
+// solution at the row before the chunk and the row after it (the halo of x,
+// from the interface values, without another exchange).  No pivoting: the
 // systems solved here (mass, Helmholtz and the implicit-midpoint matrix at
 // the model's parameters) are diagonally dominant.
 template <int PMAX, int NT, bool FULL, class RowF, class DF>
 __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], int cnt,
-                                             RowLds<NT>& L, int t) {
+                                             RowLds<NT>& L, int t, double& xl, double& xr) {
   static_assert(PMAX >= 2, "need at least two rows per thread");
   double cp[PMAX], g[PMAX];
   // forward elimination over the interior slots 1..cnt-1; inactive slots
@@ -324,6 +331,9 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
   L.s[t] = s;
   __syncthreads();
   const double snext = L.s[(t + 1) & (NT - 1)];
+  // last row of chunk t-1: y + g s_{t-1} + k s_t with its tail values
+  xl = fma(kpl, s, fma(gpl, L.s[tm], ypl));
+  xr = snext;
   x[0] = s;
   double kr = 1.0;
 #pragma unroll

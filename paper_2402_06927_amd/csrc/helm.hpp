@@ -8,8 +8,8 @@
 // where F+ and F- are the periodic solutions of the first-order recurrences
 // F+_i = f_i + r F+_{i-1} and F-_i = f_i + r F-_{i+1}.  Both recurrences are
 // linear scans: each thread scans its chunk, the chunk carries are combined
-// across lanes by shuffles and across wavefronts through one LDS record per
-// wavefront, and the periodic images add r^(i+1) G+_{N-1} / (1 - r^N) (resp.
+// across lanes by DPP row shifts and readlane and across wavefronts through
+// one LDS record per wavefront, and the periodic images add r^(i+1) G+_{N-1} / (1 - r^N) (resp.
 // r^(N-i) G-_0 / (1 - r^N)) to the non-periodic scans G+-.  The record also
 // carries three reduction partials, so a caller can fold a workgroup
 // reduction into the same barrier.
@@ -98,40 +98,93 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   }
   const double cmn = acc;  // backward carry out of the chunk (at its first node)
   const double mth = (FULL || cnt == K.base) ? K.rb : K.rb1;
-  // Inclusive scans over the lanes, forward (lanes 0..lane) and backward
-  // (lanes lane..63): Hillis-Steele steps inside each 16-lane row by DPP row
-  // shifts (identity where the row has no partner), then the rows are joined
-  // with the row results read from the row ends into scalar registers.
   const int row = lane >> 4;
-  double fm = mth, fc = cpl, bm = mth, bc = cmn;
-  scan_rows<kDppRowShr>(fm, fc);
-  scan_rows<kDppRowShl>(bm, bc);
-  {
-    const double r0m = readlane_f64(fm, 15), r0c = readlane_f64(fc, 15);
-    const double r1m = readlane_f64(fm, 31), r1c = readlane_f64(fc, 31);
-    const double r2m = readlane_f64(fm, 47), r2c = readlane_f64(fc, 47);
-    double p2m, p2c, p3m, p3c;
-    compose(r0m, r0c, r1m, r1c, p2m, p2c);
-    compose(p2m, p2c, r2m, r2c, p3m, p3c);
-    const double pm = row == 0 ? 1.0 : row == 1 ? r0m : row == 2 ? p2m : p3m;
-    const double pc = row == 0 ? 0.0 : row == 1 ? r0c : row == 2 ? p2c : p3c;
-    compose(pm, pc, fm, fc, fm, fc);
-    const double t1m = readlane_f64(bm, 16), t1c = readlane_f64(bc, 16);
-    const double t2m = readlane_f64(bm, 32), t2c = readlane_f64(bc, 32);
-    const double t3m = readlane_f64(bm, 48), t3c = readlane_f64(bc, 48);
-    double h1m, h1c, h0m, h0c;
-    compose(t3m, t3c, t2m, t2c, h1m, h1c);
-    compose(h1m, h1c, t1m, t1c, h0m, h0c);
-    const double hm = row == 3 ? 1.0 : row == 2 ? t3m : row == 1 ? h1m : h0m;
-    const double hc = row == 3 ? 0.0 : row == 2 ? t3c : row == 1 ? h1c : h0c;
-    compose(hm, hc, bm, bc, bm, bc);
+  double fc = cpl, bc = cmn;          // offsets of the inclusive scans
+  double xfm, xfc, xbm, xbc;          // exclusive carries within the wavefront
+  double tfm, tfc, tbm, tbc;          // wavefront totals
+  if constexpr (FULL) {
+    // Every chunk has PMAX rows, so the factor of any run of lanes is a
+    // power of r^PMAX: only the offsets need cross-lane steps.
+    const double rb = K.rb, rb2 = rb * rb, rb4 = rb2 * rb2, rb8 = rb4 * rb4, rb16 = rb8 * rb8,
+                 rb32 = rb16 * rb16, rb64 = rb32 * rb32;
+    auto pw = [&](int e) {  // rb^e, 0 <= e <= 64
+      double p = (e & 1) ? rb : 1.0;
+      p *= (e & 2) ? rb2 : 1.0;
+      p *= (e & 4) ? rb4 : 1.0;
+      p *= (e & 8) ? rb8 : 1.0;
+      p *= (e & 16) ? rb16 : 1.0;
+      p *= (e & 32) ? rb32 : 1.0;
+      return (e & 64) ? p * rb64 : p;
+    };
+    const int i16 = lane & 15;
+    fc = fma(rb, dpp_f64z<kDppRowShr + 1>(fc), fc);
+    fc = fma(rb2, dpp_f64z<kDppRowShr + 2>(fc), fc);
+    fc = fma(rb4, dpp_f64z<kDppRowShr + 4>(fc), fc);
+    fc = fma(rb8, dpp_f64z<kDppRowShr + 8>(fc), fc);
+    bc = fma(rb, dpp_f64z<kDppRowShl + 1>(bc), bc);
+    bc = fma(rb2, dpp_f64z<kDppRowShl + 2>(bc), bc);
+    bc = fma(rb4, dpp_f64z<kDppRowShl + 4>(bc), bc);
+    bc = fma(rb8, dpp_f64z<kDppRowShl + 8>(bc), bc);
+    {
+      const double r0c = readlane_f64(fc, 15), r1c = readlane_f64(fc, 31),
+                   r2c = readlane_f64(fc, 47);
+      const double p2c = fma(rb16, r0c, r1c), p3c = fma(rb16, p2c, r2c);
+      const double pc = row == 0 ? 0.0 : row == 1 ? r0c : row == 2 ? p2c : p3c;
+      fc = fma(pw(i16 + 1), pc, fc);
+      const double t1c = readlane_f64(bc, 16), t2c = readlane_f64(bc, 32),
+                   t3c = readlane_f64(bc, 48);
+      const double h1c = fma(rb16, t3c, t2c), h0c = fma(rb16, h1c, t1c);
+      const double hc = row == 3 ? 0.0 : row == 2 ? t3c : row == 1 ? h1c : h0c;
+      bc = fma(pw(16 - i16), hc, bc);
+    }
+    xfm = pw(lane);
+    xfc = dpp_f64z<kDppWaveShr1>(fc);
+    xbm = pw(kWave - 1 - lane);
+    xbc = dpp_f64z<kDppWaveShl1>(bc);
+    tfm = rb64;
+    tfc = readlane_f64(fc, kWave - 1);
+    tbm = rb64;
+    tbc = readlane_f64(bc, 0);
+  } else {
+    // Inclusive scans over the lanes, forward (lanes 0..lane) and backward
+    // (lanes lane..63): Hillis-Steele steps inside each 16-lane row by DPP
+    // row shifts (identity where the row has no partner), then the rows are
+    // joined with the row results read from the row ends into scalar
+    // registers.
+    double fm = mth, bm = mth;
+    scan_rows<kDppRowShr>(fm, fc);
+    scan_rows<kDppRowShl>(bm, bc);
+    {
+      const double r0m = readlane_f64(fm, 15), r0c = readlane_f64(fc, 15);
+      const double r1m = readlane_f64(fm, 31), r1c = readlane_f64(fc, 31);
+      const double r2m = readlane_f64(fm, 47), r2c = readlane_f64(fc, 47);
+      double p2m, p2c, p3m, p3c;
+      compose(r0m, r0c, r1m, r1c, p2m, p2c);
+      compose(p2m, p2c, r2m, r2c, p3m, p3c);
+      const double pm = row == 0 ? 1.0 : row == 1 ? r0m : row == 2 ? p2m : p3m;
+      const double pc = row == 0 ? 0.0 : row == 1 ? r0c : row == 2 ? p2c : p3c;
+      compose(pm, pc, fm, fc, fm, fc);
+      const double t1m = readlane_f64(bm, 16), t1c = readlane_f64(bc, 16);
+      const double t2m = readlane_f64(bm, 32), t2c = readlane_f64(bc, 32);
+      const double t3m = readlane_f64(bm, 48), t3c = readlane_f64(bc, 48);
+      double h1m, h1c, h0m, h0c;
+      compose(t3m, t3c, t2m, t2c, h1m, h1c);
+      compose(h1m, h1c, t1m, t1c, h0m, h0c);
+      const double hm = row == 3 ? 1.0 : row == 2 ? t3m : row == 1 ? h1m : h0m;
+      const double hc = row == 3 ? 0.0 : row == 2 ? t3c : row == 1 ? h1c : h0c;
+      compose(hm, hc, bm, bc, bm, bc);
+    }
+    // exclusive values within the wavefront (identity at the ends)
+    xfm = dpp_f64<kDppWaveShr1>(fm, 1.0);
+    xfc = dpp_f64<kDppWaveShr1>(fc, 0.0);
+    xbm = dpp_f64<kDppWaveShl1>(bm, 1.0);
+    xbc = dpp_f64<kDppWaveShl1>(bc, 0.0);
+    tfm = readlane_f64(fm, kWave - 1);
+    tfc = readlane_f64(fc, kWave - 1);
+    tbm = readlane_f64(bm, 0);
+    tbc = readlane_f64(bc, 0);
   }
-  // exclusive values within the wavefront (identity at the ends)
-  const double xfm = dpp_f64<kDppWaveShr1>(fm, 1.0), xfc = dpp_f64<kDppWaveShr1>(fc, 0.0);
-  const double xbm = dpp_f64<kDppWaveShl1>(bm, 1.0), xbc = dpp_f64<kDppWaveShl1>(bc, 0.0);
   // wavefront totals and reduction partials to LDS
-  const double tfm = readlane_f64(fm, kWave - 1), tfc = readlane_f64(fc, kWave - 1);
-  const double tbm = readlane_f64(bm, 0), tbc = readlane_f64(bc, 0);
   if (lane == 0) {
     double* rec = L.helm[slot][wv];
     rec[0] = tfm;

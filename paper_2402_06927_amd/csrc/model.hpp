@@ -33,16 +33,25 @@ inline StepParams make_params(const sch_model& md) {
   return P;
 }
 
-// Mass-matrix product scale * (M v)_j = scale * (h/6 v_{j-1} + 2h/3 v_j + h/6 v_{j+1}).
+// Mass-matrix product scale * (M v)_j = scale * (h/6 v_{j-1} + 2h/3 v_j + h/6 v_{j+1})
+// with the chunk's halo values hl, hr given.
+template <int PMAX, bool FULL>
+__device__ __forceinline__ void mass_apply_h(const double (&v)[PMAX], double (&out)[PMAX],
+                                             double h, int cnt, double hl, double hr,
+                                             double scale) {
+  const double c1 = scale * h / 6.0, c0 = scale * 2.0 * h / 3.0;
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j)
+    out[j] = fma(c1, left_of<PMAX, FULL>(v, j, hl) + right_of<PMAX, FULL>(v, j, cnt, hr), c0 * v[j]);
+}
+
+// The same with the halo exchanged through LDS.
 template <int PMAX, int NT, bool FULL>
 __device__ __forceinline__ void mass_apply(const double (&v)[PMAX], double (&out)[PMAX], double h,
                                            int cnt, RowLds<NT>& L, int t, double scale, int& hs) {
   double hl, hr;
   halo<PMAX, NT, FULL>(v, cnt, L, t, hl, hr, hs);
-  const double c1 = scale * h / 6.0, c0 = scale * 2.0 * h / 3.0;
-#pragma unroll
-  for (int j = 0; j < PMAX; ++j)
-    out[j] = fma(c1, left_of<PMAX, FULL>(v, j, hl) + right_of<PMAX, FULL>(v, j, cnt, hr), c0 * v[j]);
+  mass_apply_h<PMAX, FULL>(v, out, h, cnt, hl, hr, scale);
 }
 
 // Per-thread solver state carried through a kernel: the halo and record
@@ -136,7 +145,8 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
         b = fma(0.25, vp - vm, ad);
         c = fma(0.25, vp, ao);
       };
-      cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t);
+      double sl, sr;  // halo of s = m^n + m*
+      cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t, sl, sr);
       // max change and max size of m*; a non-finite entry makes the change
       // +infinity (fmax would drop a NaN), which marks the iterate as failed
       double diff = 0.0, scale = 0.0;
@@ -154,7 +164,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
       scale = wave_max(scale);
       // u* = H^{-1} M m*
       double r[PMAX];
-      mass_apply<PMAX, NT, FULL>(ms, r, P.h, cnt, L, t, 1.0, par.hs);
+      mass_apply_h<PMAX, FULL>(ms, r, P.h, cnt, sl - mL, sr - mR, 1.0);
       double uL, uR, gdiff, gscale, gunused;
       solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale, 0.0,
                                  gdiff, gscale, gunused);
@@ -433,7 +443,8 @@ __global__ void __launch_bounds__(NT) k_helmholtz(const HelmArgs A, const HelmCo
       b = md;
       c = mo;
     };
-    cyclic_solve<PMAX, NT, FULL>(rowM, [&](int j) { return r[j]; }, o, ch.cnt, L, t);
+    double ol, orr;
+    cyclic_solve<PMAX, NT, FULL>(rowM, [&](int j) { return r[j]; }, o, ch.cnt, L, t, ol, orr);
   }
   store_chunk<PMAX, FULL>(A.out + static_cast<size_t>(p) * A.P.nx, ch, o);
 }
