@@ -83,7 +83,7 @@ __global__ void k_batch_draw(BatchDev B) {
 // particle indices, longest job first; *queue must be zero at launch.  Every
 // workgroup leaves once the queue is exhausted.
 template <int PMAX, int NT>
-__global__ void __launch_bounds__(NT) k_batch_window(BatchDev B, const int* items, int n_items,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_batch_window(BatchDev B, const int* items, int n_items,
                                                      unsigned int* queue) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;

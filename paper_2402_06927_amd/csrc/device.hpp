@@ -133,17 +133,17 @@ __device__ __forceinline__ int wave_or(int v) {
 
 // ---------------------------------------------------------------------------
 // Shared memory of the row solver for a workgroup of NT threads (NT a power
-// of two, >= 64).
+// of two, 64..512).  Values cross lanes of one wavefront by DPP and
+// ds_bpermute; only what crosses wavefronts goes through LDS.
 // ---------------------------------------------------------------------------
 template <int NT>
 struct RowLds {
-  double tail_y[NT], tail_g[NT], tail_k[NT];  // last-row spike values per chunk
-  double pcr[2][4][NT];                       // cyclic reduction, double buffered
-  double s[NT];                               // interface unknowns
-  double first[2][NT], last[2][NT];           // halo exchange, double buffered
-  double red[3][NT / kWave];                  // workgroup reductions
-  double helm[2][NT / kWave][8];              // per-wavefront records of solve_helm()
-  int stop[16];                               // per-level "coupling remains" flags
+  static constexpr int W = NT / kWave;
+  double eq[4][NT];            // interface equations (A, B, C, R), one per chunk
+  double etail[3][W];          // last-row spike values of each wavefront's last chunk
+  double edge[2][W][6];        // wavefront edge values of halo exchanges, double buffered
+  double red[3][W];            // workgroup reductions
+  double helm[2][W][8];        // per-wavefront records of solve_helm()
 };
 
 // 1/x for the solvers' pivots: the hardware estimate (relative error about
@@ -182,71 +182,214 @@ __device__ __forceinline__ double right_of(const double (&v)[PMAX], int j, int c
   return last ? hr : v[j + 1 < PMAX ? j + 1 : PMAX - 1];
 }
 
-// Publishes each thread's first and last row value and returns the left and
-// right neighbours of the chunk (periodic).  The two buffers alternate
-// between calls (hs toggles), so one barrier per exchange suffices: a buffer
-// is rewritten only after the barrier of the exchange in between.
+// Value in the chunk's last active slot.
+template <int PMAX, bool FULL>
+__device__ __forceinline__ double last_of(const double (&v)[PMAX], int cnt) {
+  if (FULL) return v[PMAX - 1];
+  double r = v[0];
+#pragma unroll
+  for (int j = 1; j < PMAX; ++j)
+    if (j == cnt - 1) r = v[j];
+  return r;
+}
+
+// ds_bpermute of a double: every lane reads `v` of lane `src` (0..63).
+__device__ __forceinline__ double bperm_f64(double v, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Periodic neighbour exchange of K values per thread: thread t receives
+// last[i] of thread t-1 in fromL[i] and first[i] of thread t+1 in fromR[i]
+// (indices mod NT).  Inside a wavefront by whole-wave DPP shifts; the
+// wavefront ends go through LDS (one barrier) or, for a single wavefront,
+// through readlane.  The edge buffers alternate between calls (hs toggles),
+// so a buffer is rewritten only after the barrier of the exchange in between.
+template <int NT, int K>
+__device__ __forceinline__ void exchange(const double (&first)[K], const double (&last)[K],
+                                         double (&fromL)[K], double (&fromR)[K], RowLds<NT>& L,
+                                         int t, int& hs) {
+  constexpr int W = NT / kWave;
+  static_assert(K <= 3, "at most three values per exchange");
+  const int lane = t & (kWave - 1);
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    fromL[i] = dpp_f64<kDppWaveShr1>(last[i], 0.0);
+    fromR[i] = dpp_f64<kDppWaveShl1>(first[i], 0.0);
+  }
+  if constexpr (W == 1) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double wl = readlane_f64(last[i], kWave - 1), wr = readlane_f64(first[i], 0);
+      fromL[i] = lane == 0 ? wl : fromL[i];
+      fromR[i] = lane == kWave - 1 ? wr : fromR[i];
+    }
+  } else {
+    const int w = t / kWave;
+    if (lane == kWave - 1) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) L.edge[hs][w][2 * i + 1] = last[i];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) L.edge[hs][w][2 * i] = first[i];
+    }
+    __syncthreads();
+    const int wl = (w + W - 1) & (W - 1), wr = (w + 1) & (W - 1);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double a = L.edge[hs][wl][2 * i + 1], b = L.edge[hs][wr][2 * i];
+      fromL[i] = lane == 0 ? a : fromL[i];
+      fromR[i] = lane == kWave - 1 ? b : fromR[i];
+    }
+    hs ^= 1;
+  }
+}
+
+// Left and right neighbours of the chunk (periodic).
 template <int PMAX, int NT, bool FULL>
 __device__ __forceinline__ void halo(const double (&v)[PMAX], int cnt, RowLds<NT>& L, int t,
                                      double& hl, double& hr, int& hs) {
-  double lastv = v[PMAX - 1];
-  if (!FULL) {
-    lastv = v[0];
-#pragma unroll
-    for (int j = 1; j < PMAX; ++j)
-      if (j == cnt - 1) lastv = v[j];
-  }
-  L.first[hs][t] = v[0];
-  L.last[hs][t] = lastv;
-  __syncthreads();
-  hl = L.last[hs][(t + NT - 1) & (NT - 1)];
-  hr = L.first[hs][(t + 1) & (NT - 1)];
-  hs ^= 1;
+  const double f[1] = {v[0]}, l[1] = {last_of<PMAX, FULL>(v, cnt)};
+  double a[1], b[1];
+  exchange<NT, 1>(f, l, a, b, L, t, hs);
+  hl = a[0];
+  hr = b[0];
 }
 
-// Parallel cyclic reduction of the periodic tridiagonal system with one
-// equation per thread, A_t s_{t-1} + B_t s_t + C_t s_{t+1} = R_t.  After
-// log2(NT) levels every equation couples s_t only to itself.  The reduction
-// stops earlier once every remaining coupling is below 2^-60 of its
-// diagonal (then s_t = R_t / B_t to within rounding); the decision is shared
-// through a per-level LDS flag read after the level's barrier.
-template <int NT>
-__device__ __forceinline__ double pcr_cyclic(double A, double B, double C, double R,
-                                             RowLds<NT>& L, int t) {
-  if (t < 16) L.stop[t] = 0;
-  int cur = 0;
-  L.pcr[0][0][t] = A;
-  L.pcr[0][1][t] = B;
-  L.pcr[0][2][t] = C;
-  L.pcr[0][3][t] = R;
-  __syncthreads();
-  int level = 0;
-  for (int d = 1; d < NT; d <<= 1, ++level) {
-    const int tm = (t - d) & (NT - 1), tp = (t + d) & (NT - 1);
-    const double Am = L.pcr[cur][0][tm], Bm = L.pcr[cur][1][tm], Cm = L.pcr[cur][2][tm],
-                 Rm = L.pcr[cur][3][tm];
-    const double Ap = L.pcr[cur][0][tp], Bp = L.pcr[cur][1][tp], Cp = L.pcr[cur][2][tp],
-                 Rp = L.pcr[cur][3][tp];
-    const double k1 = A * rcp64(Bm), k2 = C * rcp64(Bp);
-    const double nA = -k1 * Am;
-    const double nB = B - k1 * Cm - k2 * Ap;
-    const double nC = -k2 * Cp;
-    const double nR = R - k1 * Rm - k2 * Rp;
-    A = nA;
-    B = nB;
-    C = nC;
-    R = nR;
-    cur ^= 1;
-    L.pcr[cur][0][t] = A;
-    L.pcr[cur][1][t] = B;
-    L.pcr[cur][2][t] = C;
-    L.pcr[cur][3][t] = R;
-    if (__any(fabs(A) + fabs(C) > 0x1.0p-60 * fabs(B)) && (t & (kWave - 1)) == 0)
-      atomicOr(&L.stop[level], 1);
-    __syncthreads();
-    if (L.stop[level] == 0) return R * rcp64(B);
+// Partition elimination of the rows 1..E-1 of a run of E consecutive rows
+// whose first unknown z_0 and whose successor z_E (the next run's z_0) are
+// kept: on exit z_j = y[j] + g[j] z_0 + k[j] z_E for j = 1..E-1.  The
+// coefficient arrays are indexed by the run's rows.
+template <int E>
+__device__ __forceinline__ void spike_eliminate(const double (&A)[E], const double (&B)[E],
+                                                const double (&C)[E], const double (&R)[E],
+                                                double (&y)[E], double (&g)[E], double (&k)[E]) {
+  double cp[E];
+  double cprev = 0.0, yprev = 0.0, gprev = 1.0;
+#pragma unroll
+  for (int j = 1; j < E; ++j) {
+    const double inv = rcp64(B[j] - A[j] * cprev);
+    cp[j] = C[j] * inv;
+    y[j] = (R[j] - A[j] * yprev) * inv;
+    g[j] = -A[j] * gprev * inv;
+    cprev = cp[j];
+    yprev = y[j];
+    gprev = g[j];
   }
-  return R * rcp64(A + B + C);
+  double yn = 0.0, gn = 0.0, kn = 1.0;
+#pragma unroll
+  for (int j = E - 1; j >= 1; --j) {
+    y[j] = y[j] - cp[j] * yn;
+    g[j] = g[j] - cp[j] * gn;
+    k[j] = -cp[j] * kn;
+    yn = y[j];
+    gn = g[j];
+    kn = k[j];
+  }
+}
+
+// Solve of the periodic tridiagonal interface system of the NT chunks,
+//   A_t s_{t-1} + B_t s_t + C_t s_{t+1} = R_t   (t mod NT),
+// redundantly by every wavefront: lane l holds the E = NT/64 consecutive
+// equations E l .. E l + E - 1 in eA..eR, eliminates all but the first by
+// the partition method, and the 64 remaining equations (one per lane,
+// periodic) are solved by cyclic reduction across the lanes (ds_bpermute),
+// stopping once every coupling is below 2^-60 of its diagonal.  Returns, for
+// the calling thread t = 64 w + lane, s_t, s_{t+1} and s_{t-1}.
+template <int NT>
+__device__ __forceinline__ void interface_solve(const double (&eA)[NT / kWave],
+                                                const double (&eB)[NT / kWave],
+                                                const double (&eC)[NT / kWave],
+                                                const double (&eR)[NT / kWave], int t, double& s,
+                                                double& snext, double& sprev) {
+  constexpr int E = NT / kWave;
+  const int lane = t & (kWave - 1);
+  double y[E], g[E], k[E];
+  y[0] = 0.0;
+  g[0] = 1.0;
+  k[0] = 0.0;
+  spike_eliminate<E>(eA, eB, eC, eR, y, g, k);
+  // run tails: the last unknown in terms of (z_0, z_E); first interior row
+  const double yT = E > 1 ? y[E - 1] : 0.0, gT = E > 1 ? g[E - 1] : 1.0,
+               kT = E > 1 ? k[E - 1] : 0.0;
+  const double y1 = E > 1 ? y[1 < E ? 1 : 0] : 0.0, g1 = E > 1 ? g[1 < E ? 1 : 0] : 0.0,
+               k1 = E > 1 ? k[1 < E ? 1 : 0] : 1.0;
+  // tails of lane l-1 (periodic over the 64 lanes)
+  double pY = dpp_f64<kDppWaveShr1>(yT, 0.0), pG = dpp_f64<kDppWaveShr1>(gT, 0.0),
+         pK = dpp_f64<kDppWaveShr1>(kT, 0.0);
+  {
+    const double wy = readlane_f64(yT, kWave - 1), wg = readlane_f64(gT, kWave - 1),
+                 wk = readlane_f64(kT, kWave - 1);
+    pY = lane == 0 ? wy : pY;
+    pG = lane == 0 ? wg : pG;
+    pK = lane == 0 ? wk : pK;
+  }
+  double A = eA[0] * pG;
+  double B = fma(eA[0], pK, fma(eC[0], g1, eB[0]));
+  double C = eC[0] * k1;
+  double R = fma(-eA[0], pY, fma(-eC[0], y1, eR[0]));
+  double z = 0.0;
+  {
+    bool done = false;
+#pragma unroll 1
+    for (int d = 1; d < kWave; d <<= 1) {
+      if (!__any(fabs(A) + fabs(C) > 0x1.0p-60 * fabs(B))) {
+        z = R * rcp64(B);
+        done = true;
+        break;
+      }
+      const int lm = (lane - d) & (kWave - 1), lp = (lane + d) & (kWave - 1);
+      const double Am = bperm_f64(A, lm), Bm = bperm_f64(B, lm), Cm = bperm_f64(C, lm),
+                   Rm = bperm_f64(R, lm);
+      const double Ap = bperm_f64(A, lp), Bp = bperm_f64(B, lp), Cp = bperm_f64(C, lp),
+                   Rp = bperm_f64(R, lp);
+      const double q1 = A * rcp64(Bm), q2 = C * rcp64(Bp);
+      const double nA = -q1 * Am;
+      const double nB = B - q1 * Cm - q2 * Ap;
+      const double nC = -q2 * Cp;
+      const double nR = R - q1 * Rm - q2 * Rp;
+      A = nA;
+      B = nB;
+      C = nC;
+      R = nR;
+    }
+    // after every level each equation couples z_l to itself only
+    if (!done) z = R * rcp64(A + B + C);
+  }
+  // the run's unknowns
+  const double zn = [&] {
+    const double v = dpp_f64<kDppWaveShl1>(z, 0.0), w0 = readlane_f64(z, 0);
+    return lane == kWave - 1 ? w0 : v;
+  }();
+  double zr[E];
+  zr[0] = z;
+#pragma unroll
+  for (int e = 1; e < E; ++e) zr[e] = fma(k[e], zn, fma(g[e], z, y[e]));
+  // thread t = 64 w + lane owns unknown t, held by lane t / E, slot lane % E
+  const int wu = __builtin_amdgcn_readfirstlane(t / kWave);
+  const int src = (kWave / E) * wu + lane / E;
+  double sv = zr[0];
+  if constexpr (E > 1) {
+    sv = bperm_f64(zr[0], src);
+#pragma unroll
+    for (int e = 1; e < E; ++e) {
+      const double v = bperm_f64(zr[e], src);
+      sv = (lane % E) == e ? v : sv;
+    }
+  }
+  s = sv;
+  {
+    const double v = dpp_f64<kDppWaveShl1>(sv, 0.0);
+    const double w = readlane_f64(zr[0], ((kWave / E) * (wu + 1)) & (kWave - 1));
+    snext = lane == kWave - 1 ? w : v;
+  }
+  {
+    const double v = dpp_f64<kDppWaveShr1>(sv, 0.0);
+    const double w = readlane_f64(zr[E - 1], ((kWave / E) * wu + kWave - 1) & (kWave - 1));
+    sprev = lane == 0 ? w : v;
+  }
 }
 
 // Workgroup solve of the periodic tridiagonal system
@@ -255,17 +398,22 @@ __device__ __forceinline__ double pcr_cyclic(double A, double B, double C, doubl
 // of every chunk is an interface unknown s_t; each thread eliminates its
 // remaining rows by Thomas' algorithm into x_j = y_j + g_j s_t + k_j s_{t+1}
 // (two spike columns), the interface rows form a periodic tridiagonal system
-// of NT unknowns solved by cyclic reduction, and the chunk is recombined.
-// row(j, a, b, c) returns the coefficients of local slot j and d(j) its
-// right-hand side (both evaluated once per slot).  xl and xr receive the
-// solution at the row before the chunk and the row after it (the halo of x,
-// from the interface values, without another exchange).  No pivoting: the
-// systems solved here (mass, Helmholtz and the implicit-midpoint matrix at
-// the model's parameters) are diagonally dominant.
+// of NT unknowns solved by interface_solve() behind one barrier, and the
+// chunk is recombined.  row(j, a, b, c) returns the coefficients of local
+// slot j and d(j) its right-hand side (both evaluated once per slot).  xl and
+// xr receive the solution at the row before the chunk and the row after it
+// (the halo of x, from the interface values, without another exchange).  No
+// pivoting: the systems solved here (mass, Helmholtz and the implicit-
+// midpoint matrix at the model's parameters) are diagonally dominant.
+#ifndef SCH_SWEEP_FENCE
+#define SCH_SWEEP_FENCE 4
+#endif
 template <int PMAX, int NT, bool FULL, class RowF, class DF>
 __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], int cnt,
                                              RowLds<NT>& L, int t, double& xl, double& xr) {
   static_assert(PMAX >= 2, "need at least two rows per thread");
+  constexpr int W = NT / kWave;
+  const int lane = t & (kWave - 1);
   double cp[PMAX], g[PMAX];
   // forward elimination over the interior slots 1..cnt-1; inactive slots
   // (j >= cnt) are given c' = -1, y' = g' = 0 so the back sweep passes the
@@ -288,6 +436,9 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     cprev = cj;
     yprev = yj;
     gprev = gj;
+    // bound the scheduler's look-ahead: rows hoisted from far ahead of the
+    // recurrence would each hold four registers pairs
+    if (j % SCH_SWEEP_FENCE == 0) __builtin_amdgcn_sched_barrier(0);
   }
   // back substitution for y and both spikes; the right spike k_j is the
   // running product of -c'_i over i = j..PMAX-1 and is rebuilt when needed
@@ -314,25 +465,68 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
       kL = kj;
     }
   }
-  // interface equation of chunk t
-  L.tail_y[t] = yL;
-  L.tail_g[t] = gL;
-  L.tail_k[t] = kL;
-  __syncthreads();
-  const int tm = (t + NT - 1) & (NT - 1);
-  const double ypl = L.tail_y[tm], gpl = L.tail_g[tm], kpl = L.tail_k[tm];
+  // interface equation of chunk t: a0 x_{-1} + b0 s_t + c0 x_1 = d0 with
+  // x_{-1} = ypl + gpl s_{t-1} + kpl s_t (thread t-1's last row) and
+  // x_1 = yn + gn s_t + kn s_{t+1}
+  double ypl = dpp_f64<kDppWaveShr1>(yL, 0.0), gpl = dpp_f64<kDppWaveShr1>(gL, 0.0),
+         kpl = dpp_f64<kDppWaveShr1>(kL, 0.0);
   double a0, b0, c0;
   row(0, a0, b0, c0);
-  const double A = a0 * gpl;
-  const double B = b0 + a0 * kpl + c0 * gn;
-  const double C = c0 * kn;
-  const double R = d(0) - a0 * ypl - c0 * yn;
-  const double s = pcr_cyclic<NT>(A, B, C, R, L, t);
-  L.s[t] = s;
-  __syncthreads();
-  const double snext = L.s[(t + 1) & (NT - 1)];
+  const double Bp = fma(c0, gn, b0), Rp = fma(-c0, yn, d(0)), C = c0 * kn;
+  double s, snext, sprev;
+  if constexpr (W == 1) {
+    const double wy = readlane_f64(yL, kWave - 1), wg = readlane_f64(gL, kWave - 1),
+                 wk = readlane_f64(kL, kWave - 1);
+    ypl = lane == 0 ? wy : ypl;
+    gpl = lane == 0 ? wg : gpl;
+    kpl = lane == 0 ? wk : kpl;
+    const double eA[1] = {a0 * gpl}, eB[1] = {fma(a0, kpl, Bp)}, eC[1] = {C},
+                 eR[1] = {fma(-a0, ypl, Rp)};
+    interface_solve<NT>(eA, eB, eC, eR, t, s, snext, sprev);
+  } else {
+    // the equation of each wavefront's first chunk goes to LDS without its
+    // left-tail terms (A holds a0); the reader completes it from L.etail
+    const int w = t / kWave;
+    const bool firstlane = lane == 0;
+    L.eq[0][t] = firstlane ? a0 : a0 * gpl;
+    L.eq[1][t] = firstlane ? Bp : fma(a0, kpl, Bp);
+    L.eq[2][t] = C;
+    L.eq[3][t] = firstlane ? Rp : fma(-a0, ypl, Rp);
+    if (lane == kWave - 1) {
+      L.etail[0][w] = yL;
+      L.etail[1][w] = gL;
+      L.etail[2][w] = kL;
+    }
+    __syncthreads();
+    {
+      const int wp = (w + W - 1) & (W - 1);
+      const double ty = L.etail[0][wp], tg = L.etail[1][wp], tk = L.etail[2][wp];
+      ypl = firstlane ? ty : ypl;
+      gpl = firstlane ? tg : gpl;
+      kpl = firstlane ? tk : kpl;
+    }
+    double eA[W], eB[W], eC[W], eR[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      eA[e] = L.eq[0][W * lane + e];
+      eB[e] = L.eq[1][W * lane + e];
+      eC[e] = L.eq[2][W * lane + e];
+      eR[e] = L.eq[3][W * lane + e];
+    }
+    {
+      // equation W*lane is the first of a wavefront when (W*lane) % 64 == 0
+      const int wq = ((W * lane) / kWave + W - 1) & (W - 1);
+      const double ty = L.etail[0][wq], tg = L.etail[1][wq], tk = L.etail[2][wq];
+      const bool first = ((W * lane) & (kWave - 1)) == 0;
+      const double a = eA[0];
+      eA[0] = first ? a * tg : eA[0];
+      eB[0] = first ? fma(a, tk, eB[0]) : eB[0];
+      eR[0] = first ? fma(-a, ty, eR[0]) : eR[0];
+    }
+    interface_solve<NT>(eA, eB, eC, eR, t, s, snext, sprev);
+  }
   // last row of chunk t-1: y + g s_{t-1} + k s_t with its tail values
-  xl = fma(kpl, s, fma(gpl, L.s[tm], ypl));
+  xl = fma(kpl, s, fma(gpl, sprev, ypl));
   xr = snext;
   x[0] = s;
   double kr = 1.0;

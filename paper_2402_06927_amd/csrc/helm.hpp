@@ -81,22 +81,16 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   constexpr int W = NT / kWave;
   const int lane = t & (kWave - 1), wv = t / kWave;
   const double r = K.r;
-  // local scans; sc[j] = (forward + backward - f) local sums
-  double sc[PMAX];
+  // carries out of the chunk: the local forward scan at its last node and
+  // the local backward scan at its first node
   double acc = 0.0;
 #pragma unroll
-  for (int j = 0; j < PMAX; ++j) {
-    acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
-    sc[j] = acc - f[j];
-  }
-  const double cpl = acc;  // forward carry out of the chunk
+  for (int j = 0; j < PMAX; ++j) acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+  const double cpl = acc;
   acc = 0.0;
 #pragma unroll
-  for (int j = PMAX - 1; j >= 0; --j) {
-    if (FULL || j < cnt) acc = fma(r, acc, f[j]);
-    sc[j] += acc;
-  }
-  const double cmn = acc;  // backward carry out of the chunk (at its first node)
+  for (int j = PMAX - 1; j >= 0; --j) acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+  const double cmn = acc;
   const double mth = (FULL || cnt == K.base) ? K.rb : K.rb1;
   const int row = lane >> 4;
   double fc = cpl, bc = cmn;          // offsets of the inclusive scans
@@ -236,17 +230,20 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   const double gamp = allfc * K.rN1, gamm = allbc * K.rN1;
   const double Ep = fma(pfm, gamp, pfc);
   const double Em = fma(pbm, gamm, pbc);
-  // u_j = coef (sc_j + r^(j+1) Ep + r^(cnt-j) Em): the backward factor is
-  // r^(cnt-j) = r^cnt / r^j, built from the chunk multiplier; the forward
-  // factor grows by r per slot
-  double rf = r;
-  double rbk = mth;  // r^(cnt - j), starting at j = 0
-  const double ir = K.rinv;
+  // the global scans inside the chunk, rerun from the carries into it:
+  // F+_j = f_j + r F+_{j-1} from F+_{start-1} = Ep, F-_j = f_j + r F-_{j+1}
+  // from F-_{end+1} = Em; u_j = coef (F+_j + F-_j - f_j)
+  acc = Ep;
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
-    u[j] = K.coef * fma(rbk, Em, fma(rf, Ep, sc[j]));
-    rf *= r;
-    rbk *= ir;
+    acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+    u[j] = acc - f[j];
+  }
+  acc = Em;
+#pragma unroll
+  for (int j = PMAX - 1; j >= 0; --j) {
+    acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+    u[j] = K.coef * (u[j] + acc);
   }
   // bordering values from the Helmholtz rows of the first and last node,
   // o u_{i-1} + d u_i + o u_{i+1} = f_i (meaningful for chunks of >= 2 rows)

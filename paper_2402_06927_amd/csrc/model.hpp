@@ -85,10 +85,16 @@ struct AuxLds {
 //   c_i = h/6 - mu dt/(2h) + dv_{i+1}/4
 // (the exact P1 integrals of the advective terms of eq. fde1).  The right-
 // hand side 2 M m^n is formed row by row inside the solve.  The convergence
-// test's workgroup reduction rides on the Helmholtz solve's barrier.
+// test's workgroup reduction rides on the Helmholtz solve's barrier.  The
+// halo of m^n, of the explicit part of dv and of u^n is exchanged once per
+// step; inside the iteration the halo of u* comes from the Helmholtz rows at
+// the chunk's ends (chunks of at least two rows), so an iteration has two
+// barriers: the interface solve and the Helmholtz solve.
 // Returns SCH_OK or the status of the first failing step; on non-convergence
-// the last iterate is kept, on a non-finite iterate the step's input is kept.
-template <int PMAX, int NT, bool FULL, class IncF>
+// the last iterate is kept, on a non-finite iterate the step's input is kept
+// (KEEP) or the state is left undefined (!KEEP, for callers that discard a
+// failed window: u^n then need not stay live through the iteration).
+template <int PMAX, int NT, bool FULL, bool KEEP = true, class IncF>
 __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int n_steps,
                           double (&m)[PMAX], double (&u)[PMAX], const Chunk& ch, RowLds<NT>& L,
                           AuxLds<PMAX, NT>& X, int t, Parity& par, int& iters) {
@@ -96,6 +102,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
   const int cnt = ch.cnt;
   const double hdt = 0.5 * P.dt;
   const double f1 = P.h / 3.0, f0 = 4.0 * P.h / 3.0;  // 2 M: (h/3, 4h/3, h/3)
+  const bool bordered = FULL || K.base >= 2;
   double rD[kDLds ? 1 : PMAX], rP[kLds ? 1 : PMAX];
   auto getD = [&](int j) -> double { if constexpr (kDLds) return X.a[0][j][t]; else return rD[j]; };
   auto setD = [&](int j, double v) { if constexpr (kDLds) X.a[0][j][t] = v; else rD[j] = v; };
@@ -103,6 +110,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
   auto setP = [&](int j, double v) { if constexpr (kLds) X.a[1][j][t] = v; else rP[j] = v; };
   for (int n = 0; n < n_steps; ++n) {
     // dU^n + dt/2 u^n, the explicit part of dv
+    double eL, eR, mL, mR, uL, uR;
     {
       double e[PMAX];
 #pragma unroll
@@ -114,29 +122,53 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
         for (int j = 0; j < PMAX; ++j)
           if (FULL || j < cnt) e[j] = fma(xq[j], w, e[j]);
       }
+      const double fst[3] = {m[0], e[0], u[0]};
+      const double lst[3] = {last_of<PMAX, FULL>(m, cnt), last_of<PMAX, FULL>(e, cnt),
+                             last_of<PMAX, FULL>(u, cnt)};
+      double fl[3], fr[3];
+      exchange<NT, 3>(fst, lst, fl, fr, L, t, par.hs);
+      mL = fl[0];
+      mR = fr[0];
+      eL = fl[1];
+      eR = fr[1];
+      uL = fl[2];
+      uR = fr[2];
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) {
         setD(j, e[j]);
         setP(j, m[j]);
       }
     }
-    double mL, mR;
-    halo<PMAX, NT, FULL>(m, cnt, L, t, mL, mR, par.hs);
     auto fget = [&](int j) -> double {
       return fma(f1, left_of<PMAX, FULL>(m, j, mL) + right_of<PMAX, FULL>(m, j, cnt, mR),
                  f0 * m[j]);
     };
 
-    double us[PMAX], ms[PMAX];
+    double us[PMAX];
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) us[j] = u[j];
     int status = SCH_E_NONCONVERGED, k = 1;
     for (; k <= P.picard_max; ++k) {
+      // Keep the step's invariants (the right-hand side 2 M m^n and the
+      // LDS-resident explicit part) out of registers across iterations:
+      // hoisting them would cost 64 registers per thread and halve the
+      // workgroups a compute unit holds.
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) asm volatile("" : "+v"(m[j]));
       double dv[PMAX];
 #pragma unroll
-      for (int j = 0; j < PMAX; ++j) dv[j] = fma(hdt, us[j], getD(j));
+      for (int j = 0; j < PMAX; ++j) {
+        double dj = getD(j);
+        asm volatile("" : "+v"(dj));
+        dv[j] = fma(hdt, us[j], dj);
+      }
       double vl, vr;
-      halo<PMAX, NT, FULL>(dv, cnt, L, t, vl, vr, par.hs);
+      if (bordered) {
+        vl = fma(hdt, uL, eL);
+        vr = fma(hdt, uR, eR);
+      } else {
+        halo<PMAX, NT, FULL>(dv, cnt, L, t, vl, vr, par.hs);
+      }
       const double ao = P.a_off, ad = P.a_diag;
       auto rowA = [&](int j, double& a, double& b, double& c) {
         const double vm = left_of<PMAX, FULL>(dv, j, vl);
@@ -145,27 +177,30 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
         b = fma(0.25, vp - vm, ad);
         c = fma(0.25, vp, ao);
       };
+      double ms[PMAX];
       double sl, sr;  // halo of s = m^n + m*
       cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t, sl, sr);
       // max change and max size of m*; a non-finite entry makes the change
-      // +infinity (fmax would drop a NaN), which marks the iterate as failed
-      double diff = 0.0, scale = 0.0;
+      // +infinity (fmax would drop a NaN), which marks the iterate as failed.
+      // fin accumulates 0 * m*_j, which stays 0 unless an entry is not finite.
+      double diff = 0.0, scale = 0.0, fin = 0.0;
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) {
         ms[j] -= m[j];
         if (FULL || j < cnt) {
-          const double dj = fabs(ms[j] - getP(j));
-          diff = fmax(diff, (dj <= 1.7976931348623157e308) ? dj : INFINITY);
+          diff = fmax(diff, fabs(ms[j] - getP(j)));
           scale = fmax(scale, fabs(ms[j]));
+          fin = fma(ms[j], 0.0, fin);
         }
         setP(j, ms[j]);
       }
+      diff = fin == 0.0 ? diff : INFINITY;
       diff = wave_max(diff);
       scale = wave_max(scale);
       // u* = H^{-1} M m*
       double r[PMAX];
       mass_apply_h<PMAX, FULL>(ms, r, P.h, cnt, sl - mL, sr - mR, 1.0);
-      double uL, uR, gdiff, gscale, gunused;
+      double gdiff, gscale, gunused;
       solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale, 0.0,
                                  gdiff, gscale, gunused);
       par.slot ^= 1;
@@ -179,10 +214,11 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
       }
     }
     iters += k > P.picard_max ? P.picard_max : k;
-    if (status == SCH_E_NONFINITE) return status;
+    if (KEEP && status == SCH_E_NONFINITE) return status;
+    // the accepted iterate m* was stored as the last "previous iterate"
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) {
-      m[j] = ms[j];
+      m[j] = getP(j);
       u[j] = us[j];
     }
     if (status != SCH_OK) return status;
@@ -276,7 +312,7 @@ struct WindowArgs {
 };
 
 template <int PMAX, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) k_window(const WindowArgs A, const HelmConst K) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_window(const WindowArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
   const int p = blockIdx.x, t = threadIdx.x;
@@ -332,7 +368,7 @@ struct JitterArgs {
 // window rerun from the window-start state (re-read from global memory for
 // every proposal), likelihood and Metropolis accept in one launch.
 template <int PMAX, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) k_jitter(const JitterArgs A, const HelmConst K) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_jitter(const JitterArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
   extern __shared__ double dyn[];  // [2][n_steps][n_modes]: current increments, proposal
@@ -357,7 +393,8 @@ __global__ void __launch_bounds__(NT) k_jitter(const JitterArgs A, const HelmCon
     load_chunk<PMAX, FULL>(A.m0 + static_cast<size_t>(p) * nx, ch, m);
     load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u);
     auto inc = [&](int n, int q) { return prop[n * Q + q]; };
-    const int st = run_window<PMAX, NT, FULL>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
+    const int st =
+        run_window<PMAX, NT, FULL, false>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
     bool accept = false;
     double phin;
     if constexpr (AuxLds<PMAX, NT>::kInLds) {
