@@ -89,11 +89,20 @@ template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int src, int old) {
   return __builtin_amdgcn_update_dpp(old, src, CTRL, 0xf, 0xf, false);
 }
-// The same with bound control: lanes without a source lane read 0.
+// The same with bound control: lanes without a source lane read 0 (no old
+// value, so no register copy ahead of the move).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64z(double src) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(src), CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(src), CTRL, 0xf, 0xf, true);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(src), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(src), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+// Row broadcast into the rows selected by ROWS; the other rows' results are
+// undefined (callers read only lanes of the selected rows afterwards).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64b(double src) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(src), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(src), CTRL, ROWS, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 // lane must be wave-uniform
@@ -108,19 +117,32 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // each row by row shifts, then the four row results from lanes 15, 31, 47, 63.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64<kDppRowShr + 1>(v, 0.0);
-  v += dpp_f64<kDppRowShr + 2>(v, 0.0);
-  v += dpp_f64<kDppRowShr + 4>(v, 0.0);
-  v += dpp_f64<kDppRowShr + 8>(v, 0.0);
+  v += dpp_f64z<kDppRowShr + 1>(v);
+  v += dpp_f64z<kDppRowShr + 2>(v);
+  v += dpp_f64z<kDppRowShr + 4>(v);
+  v += dpp_f64z<kDppRowShr + 8>(v);
   return (readlane_f64(v, 15) + readlane_f64(v, 31)) + (readlane_f64(v, 47) + readlane_f64(v, 63));
 }
+// max of two doubles as one v_max_f64: fmax() would first canonicalise
+// operands that arrive through lane moves (two more instructions each); the
+// operands here are results of arithmetic, never signalling NaNs.
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+// (of nonnegative values: lanes without a partner take 0).  After the row
+// steps, lane 15 of each row is broadcast into the next row and lane 31 into
+// rows 2 and 3, so lane 63 holds the wave's maximum.
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
 __device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_f64<kDppRowShr + 1>(v, v));
-  v = fmax(v, dpp_f64<kDppRowShr + 2>(v, v));
-  v = fmax(v, dpp_f64<kDppRowShr + 4>(v, v));
-  v = fmax(v, dpp_f64<kDppRowShr + 8>(v, v));
-  return fmax(fmax(readlane_f64(v, 15), readlane_f64(v, 31)),
-              fmax(readlane_f64(v, 47), readlane_f64(v, 63)));
+  v = vmax(v, dpp_f64z<kDppRowShr + 1>(v));
+  v = vmax(v, dpp_f64z<kDppRowShr + 2>(v));
+  v = vmax(v, dpp_f64z<kDppRowShr + 4>(v));
+  v = vmax(v, dpp_f64z<kDppRowShr + 8>(v));
+  v = vmax(v, dpp_f64b<kDppRowBcast15, 0xa>(v));
+  v = vmax(v, dpp_f64b<kDppRowBcast31, 0xc>(v));
+  return readlane_f64(v, 63);
 }
 __device__ __forceinline__ int wave_or(int v) {
   v |= dpp_i32<kDppRowShr + 1>(v, 0);
@@ -215,8 +237,8 @@ __device__ __forceinline__ void exchange(const double (&first)[K], const double 
   const int lane = t & (kWave - 1);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    fromL[i] = dpp_f64<kDppWaveShr1>(last[i], 0.0);
-    fromR[i] = dpp_f64<kDppWaveShl1>(first[i], 0.0);
+    fromL[i] = dpp_f64z<kDppWaveShr1>(last[i]);
+    fromR[i] = dpp_f64z<kDppWaveShl1>(first[i]);
   }
   if constexpr (W == 1) {
 #pragma unroll
@@ -270,10 +292,10 @@ __device__ __forceinline__ void spike_eliminate(const double (&A)[E], const doub
   double cprev = 0.0, yprev = 0.0, gprev = 1.0;
 #pragma unroll
   for (int j = 1; j < E; ++j) {
-    const double inv = rcp64(B[j] - A[j] * cprev);
+    const double inv = rcp64(j == 1 ? B[j] : B[j] - A[j] * cprev);
     cp[j] = C[j] * inv;
-    y[j] = (R[j] - A[j] * yprev) * inv;
-    g[j] = -A[j] * gprev * inv;
+    y[j] = (j == 1 ? R[j] : R[j] - A[j] * yprev) * inv;
+    g[j] = (j == 1 ? -A[j] : -A[j] * gprev) * inv;
     cprev = cp[j];
     yprev = y[j];
     gprev = g[j];
@@ -317,8 +339,8 @@ __device__ __forceinline__ void interface_solve(const double (&eA)[NT / kWave],
   const double y1 = E > 1 ? y[1 < E ? 1 : 0] : 0.0, g1 = E > 1 ? g[1 < E ? 1 : 0] : 0.0,
                k1 = E > 1 ? k[1 < E ? 1 : 0] : 1.0;
   // tails of lane l-1 (periodic over the 64 lanes)
-  double pY = dpp_f64<kDppWaveShr1>(yT, 0.0), pG = dpp_f64<kDppWaveShr1>(gT, 0.0),
-         pK = dpp_f64<kDppWaveShr1>(kT, 0.0);
+  double pY = dpp_f64z<kDppWaveShr1>(yT), pG = dpp_f64z<kDppWaveShr1>(gT),
+         pK = dpp_f64z<kDppWaveShr1>(kT);
   {
     const double wy = readlane_f64(yT, kWave - 1), wg = readlane_f64(gT, kWave - 1),
                  wk = readlane_f64(kT, kWave - 1);
@@ -360,7 +382,7 @@ __device__ __forceinline__ void interface_solve(const double (&eA)[NT / kWave],
   }
   // the run's unknowns
   const double zn = [&] {
-    const double v = dpp_f64<kDppWaveShl1>(z, 0.0), w0 = readlane_f64(z, 0);
+    const double v = dpp_f64z<kDppWaveShl1>(z), w0 = readlane_f64(z, 0);
     return lane == kWave - 1 ? w0 : v;
   }();
   double zr[E];
@@ -381,12 +403,12 @@ __device__ __forceinline__ void interface_solve(const double (&eA)[NT / kWave],
   }
   s = sv;
   {
-    const double v = dpp_f64<kDppWaveShl1>(sv, 0.0);
+    const double v = dpp_f64z<kDppWaveShl1>(sv);
     const double w = readlane_f64(zr[0], ((kWave / E) * (wu + 1)) & (kWave - 1));
     snext = lane == kWave - 1 ? w : v;
   }
   {
-    const double v = dpp_f64<kDppWaveShr1>(sv, 0.0);
+    const double v = dpp_f64z<kDppWaveShr1>(sv);
     const double w = readlane_f64(zr[E - 1], ((kWave / E) * wu + kWave - 1) & (kWave - 1));
     sprev = lane == 0 ? w : v;
   }
@@ -423,8 +445,10 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
   for (int j = 1; j < PMAX; ++j) {
     double a, b, c;
     row(j, a, b, c);
-    const double inv = rcp64(b - a * cprev);
-    double cj = c * inv, yj = (d(j) - a * yprev) * inv, gj = -a * gprev * inv;
+    // slot 1 starts the recurrences (c' = y' = 0, g' = 1 before it)
+    const double inv = rcp64(j == 1 ? b : b - a * cprev);
+    double cj = c * inv, yj = (j == 1 ? d(j) : d(j) - a * yprev) * inv,
+           gj = (j == 1 ? -a : -a * gprev) * inv;
     if (!FULL && j >= cnt) {
       cj = -1.0;
       yj = 0.0;
@@ -468,8 +492,8 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
   // interface equation of chunk t: a0 x_{-1} + b0 s_t + c0 x_1 = d0 with
   // x_{-1} = ypl + gpl s_{t-1} + kpl s_t (thread t-1's last row) and
   // x_1 = yn + gn s_t + kn s_{t+1}
-  double ypl = dpp_f64<kDppWaveShr1>(yL, 0.0), gpl = dpp_f64<kDppWaveShr1>(gL, 0.0),
-         kpl = dpp_f64<kDppWaveShr1>(kL, 0.0);
+  double ypl = dpp_f64z<kDppWaveShr1>(yL), gpl = dpp_f64z<kDppWaveShr1>(gL),
+         kpl = dpp_f64z<kDppWaveShr1>(kL);
   double a0, b0, c0;
   row(0, a0, b0, c0);
   const double Bp = fma(c0, gn, b0), Rp = fma(-c0, yn, d(0)), C = c0 * kn;

@@ -11,8 +11,9 @@
 // across lanes by DPP row shifts and readlane and across wavefronts through
 // one LDS record per wavefront, and the periodic images add r^(i+1) G+_{N-1} / (1 - r^N) (resp.
 // r^(N-i) G-_0 / (1 - r^N)) to the non-periodic scans G+-.  The record also
-// carries three reduction partials, so a caller can fold a workgroup
-// reduction into the same barrier.
+// carries three nonnegative reduction partials, so a caller can fold a
+// workgroup max-reduction into the same barrier; the first comes back as
+// +infinity when the right-hand side holds a non-finite value.
 #pragma once
 
 #include "device.hpp"
@@ -43,28 +44,29 @@ __device__ __forceinline__ void scan_rows(double& m, double& c) {
 #pragma unroll
   for (int d = 1; d < 16; d <<= 1) {
     double pm, pc;
-    if (d == 1) { pm = dpp_f64<CTRL + 1>(m, 1.0); pc = dpp_f64<CTRL + 1>(c, 0.0); }
-    else if (d == 2) { pm = dpp_f64<CTRL + 2>(m, 1.0); pc = dpp_f64<CTRL + 2>(c, 0.0); }
-    else if (d == 4) { pm = dpp_f64<CTRL + 4>(m, 1.0); pc = dpp_f64<CTRL + 4>(c, 0.0); }
-    else { pm = dpp_f64<CTRL + 8>(m, 1.0); pc = dpp_f64<CTRL + 8>(c, 0.0); }
+    if (d == 1) { pm = dpp_f64<CTRL + 1>(m, 1.0); pc = dpp_f64z<CTRL + 1>(c); }
+    else if (d == 2) { pm = dpp_f64<CTRL + 2>(m, 1.0); pc = dpp_f64z<CTRL + 2>(c); }
+    else if (d == 4) { pm = dpp_f64<CTRL + 4>(m, 1.0); pc = dpp_f64z<CTRL + 4>(c); }
+    else { pm = dpp_f64<CTRL + 8>(m, 1.0); pc = dpp_f64z<CTRL + 8>(c); }
     compose(pm, pc, m, c, m, c);
   }
 }
 
 // Scans of the per-wavefront records held in lanes 0..W-1 (W <= 8): forward
-// and backward affine compositions and running maxima of three partials.
+// and backward affine compositions and running maxima of three nonnegative
+// partials (lanes without a partner contribute the identities 1, 0 and 0).
 template <int W>
 __device__ __forceinline__ void record_scan(double& f0, double& f1, double& b0, double& b1,
                                             double& q0, double& q1, double& q2) {
 #define SCH_RSTEP(D)                                                              \
   if constexpr (W > D) {                                                          \
-    double pm = dpp_f64<kDppRowShr + D>(f0, 1.0), pc = dpp_f64<kDppRowShr + D>(f1, 0.0); \
+    double pm = dpp_f64<kDppRowShr + D>(f0, 1.0), pc = dpp_f64z<kDppRowShr + D>(f1); \
     compose(pm, pc, f0, f1, f0, f1);                                              \
-    double qm = dpp_f64<kDppRowShl + D>(b0, 1.0), qc = dpp_f64<kDppRowShl + D>(b1, 0.0); \
+    double qm = dpp_f64<kDppRowShl + D>(b0, 1.0), qc = dpp_f64z<kDppRowShl + D>(b1); \
     compose(qm, qc, b0, b1, b0, b1);                                              \
-    q0 = fmax(q0, dpp_f64<kDppRowShr + D>(q0, q0));                               \
-    q1 = fmax(q1, dpp_f64<kDppRowShr + D>(q1, q1));                               \
-    q2 = fmax(q2, dpp_f64<kDppRowShr + D>(q2, q2));                               \
+    q0 = vmax(q0, dpp_f64z<kDppRowShr + D>(q0));                                  \
+    q1 = vmax(q1, dpp_f64z<kDppRowShr + D>(q1));                                  \
+    q2 = vmax(q2, dpp_f64z<kDppRowShr + D>(q2));                                  \
   }
   SCH_RSTEP(1)
   SCH_RSTEP(2)
@@ -170,9 +172,9 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
     }
     // exclusive values within the wavefront (identity at the ends)
     xfm = dpp_f64<kDppWaveShr1>(fm, 1.0);
-    xfc = dpp_f64<kDppWaveShr1>(fc, 0.0);
+    xfc = dpp_f64z<kDppWaveShr1>(fc);
     xbm = dpp_f64<kDppWaveShl1>(bm, 1.0);
-    xbc = dpp_f64<kDppWaveShl1>(bc, 0.0);
+    xbc = dpp_f64z<kDppWaveShl1>(bc);
     tfm = readlane_f64(fm, kWave - 1);
     tfc = readlane_f64(fc, kWave - 1);
     tbm = readlane_f64(bm, 0);
@@ -210,6 +212,9 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   gred1 = readlane_f64(q1, W - 1);
   gred2 = readlane_f64(q2, W - 1);
   const double allfc = readlane_f64(f1, W - 1);
+  // the row's forward total is finite iff every f_j is: a non-finite input
+  // reports gred0 = +infinity
+  if (!(fabs(allfc) <= 1.7976931348623157e308)) gred0 = INFINITY;
   const double allbc = readlane_f64(b1, 0);
   const int wvu = __builtin_amdgcn_readfirstlane(wv);
   double inm = 1.0, inc = 0.0, rim = 1.0, ric = 0.0;

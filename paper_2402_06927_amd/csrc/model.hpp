@@ -101,6 +101,9 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
   constexpr bool kLds = AuxLds<PMAX, NT>::kInLds, kDLds = AuxLds<PMAX, NT>::kDInLds;
   const int cnt = ch.cnt;
   const double hdt = 0.5 * P.dt;
+  // dv is carried as dv/4, the form in which it enters the rows of A (exact:
+  // a power-of-two scaling); the products then take no literal operands
+  const double hdt4 = 0.25 * hdt;
   const double f1 = P.h / 3.0, f0 = 4.0 * P.h / 3.0;  // 2 M: (h/3, 4h/3, h/3)
   const bool bordered = FULL || K.base >= 2;
   double rD[kDLds ? 1 : PMAX], rP[kLds ? 1 : PMAX];
@@ -109,7 +112,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
   auto getP = [&](int j) -> double { if constexpr (kLds) return X.a[1][j][t]; else return rP[j]; };
   auto setP = [&](int j, double v) { if constexpr (kLds) X.a[1][j][t] = v; else rP[j] = v; };
   for (int n = 0; n < n_steps; ++n) {
-    // dU^n + dt/2 u^n, the explicit part of dv
+    // (dU^n + dt/2 u^n) / 4, the explicit part of dv / 4
     double eL, eR, mL, mR, uL, uR;
     {
       double e[PMAX];
@@ -122,6 +125,8 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
         for (int j = 0; j < PMAX; ++j)
           if (FULL || j < cnt) e[j] = fma(xq[j], w, e[j]);
       }
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) e[j] *= 0.25;
       const double fst[3] = {m[0], e[0], u[0]};
       const double lst[3] = {last_of<PMAX, FULL>(m, cnt), last_of<PMAX, FULL>(e, cnt),
                              last_of<PMAX, FULL>(u, cnt)};
@@ -160,12 +165,12 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
       for (int j = 0; j < PMAX; ++j) {
         double dj = getD(j);
         asm volatile("" : "+v"(dj));
-        dv[j] = fma(hdt, us[j], dj);
+        dv[j] = fma(hdt4, us[j], dj);  // dv / 4
       }
       double vl, vr;
       if (bordered) {
-        vl = fma(hdt, uL, eL);
-        vr = fma(hdt, uR, eR);
+        vl = fma(hdt4, uL, eL);
+        vr = fma(hdt4, uR, eR);
       } else {
         halo<PMAX, NT, FULL>(dv, cnt, L, t, vl, vr, par.hs);
       }
@@ -173,28 +178,26 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
       auto rowA = [&](int j, double& a, double& b, double& c) {
         const double vm = left_of<PMAX, FULL>(dv, j, vl);
         const double vp = right_of<PMAX, FULL>(dv, j, cnt, vr);
-        a = fma(-0.25, vm, ao);
-        b = fma(0.25, vp - vm, ad);
-        c = fma(0.25, vp, ao);
+        a = ao - vm;
+        b = ad + (vp - vm);
+        c = ao + vp;
       };
       double ms[PMAX];
       double sl, sr;  // halo of s = m^n + m*
       cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t, sl, sr);
-      // max change and max size of m*; a non-finite entry makes the change
-      // +infinity (fmax would drop a NaN), which marks the iterate as failed.
-      // fin accumulates 0 * m*_j, which stays 0 unless an entry is not finite.
-      double diff = 0.0, scale = 0.0, fin = 0.0;
+      // max change and max size of m*; a non-finite entry (which fmax would
+      // drop) reaches the Helmholtz right-hand side M m*, and solve_helm then
+      // reports the change as +infinity, which marks the iterate as failed
+      double diff = 0.0, scale = 0.0;
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) {
         ms[j] -= m[j];
         if (FULL || j < cnt) {
           diff = fmax(diff, fabs(ms[j] - getP(j)));
           scale = fmax(scale, fabs(ms[j]));
-          fin = fma(ms[j], 0.0, fin);
         }
         setP(j, ms[j]);
       }
-      diff = fin == 0.0 ? diff : INFINITY;
       diff = wave_max(diff);
       scale = wave_max(scale);
       // u* = H^{-1} M m*
