@@ -145,6 +145,19 @@ def _declare(L):
         "orc_nudge_ensemble": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_int32,
                                          C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(OrcLbfgsOpts),
                                          _dp, _ip, _ip, _ip, _ip, C.c_int32]),
+        "orc_nudged_potential": (C.c_double, [C.c_double, C.c_int32, C.c_double, _dp, _dp]),
+        "orc_jitter_pcn_ctrl": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp,
+                                          C.POINTER(OrcRng), C.c_int32, C.c_int32, _dp, _dp, _dp,
+                                          _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int32,
+                                          _ip, C.c_int32]),
+        "orc_pcn_linear_chain_ctrl": (C.c_int64, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
+                                                  _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                                  C.c_double, _dp, C.c_int32, _dp, _dp]),
+        "orc_nudged_cycle": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_uint64,
+                                       C.c_uint32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                       C.c_double, C.c_int32, C.c_int32, C.POINTER(OrcLbfgsOpts),
+                                       _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                       C.POINTER(OrcCycleStats), C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -568,3 +581,70 @@ def nudge_ensemble(model: Model, y, sigma, m, u, dW, dLam0=None, gtol=LBFGS_GTOL
                                      n_threads or n_threads_default())
     return dict(worst=worst, m=m, u=u, dLam=dLam, logG=logG, iters=iters, evals=evals,
                 lbfgs_status=lst, status=status)
+
+
+# --------------------------------------------------------------------------- nudged filter
+def nudged_potential(phi, dt, dW, dLam) -> float:
+    """phi - log G of one nudged path (flattened increments and controls)."""
+    dW = _f64(np.ravel(dW))
+    dLam = _f64(np.ravel(dLam))
+    return lib().orc_nudged_potential(float(phi), len(dW), dt, _d(dW), _d(dLam))
+
+
+def jitter_pcn_ctrl(model: Model, y, sigma, seed, cycle, temper_k, m0, u0, dW, dLam, J, m_end,
+                    u_end, theta, rho, n_jitter, n_threads=None):
+    """pCN moves of dW with the controls dLam fixed; J holds the nudged
+    potentials.  Returns (dW, J, m_end, u_end, n_accept)."""
+    y, sg = _obs_arrays(y, sigma)
+    dW = np.array(dW, dtype=np.float64, copy=True, order="C")
+    J = np.array(J, dtype=np.float64, copy=True)
+    m_end = np.array(m_end, dtype=np.float64, copy=True, order="C")
+    u_end = np.array(u_end, dtype=np.float64, copy=True, order="C")
+    P, ns = dW.shape[0], dW.shape[1]
+    acc = np.zeros(P, dtype=np.int32)
+    rg = OrcRng(seed, cycle, temper_k)
+    cm = model.c()
+    lib().orc_jitter_pcn_ctrl(C.byref(cm), len(y), _d(y), _d(sg), C.byref(rg), P, ns,
+                              _d(_f64(m0)), _d(_f64(u0)), _d(dW), _d(_f64(dLam)), _d(J),
+                              _d(m_end), _d(u_end), theta, rho, n_jitter, _i(acc),
+                              n_threads or n_threads_default())
+    return dW, J, m_end, u_end, acc
+
+
+def pcn_linear_chain_ctrl(seed, n_steps, n_modes, G, y, sigma, theta, rho, dt, lam, n_iter,
+                          x0=None):
+    G = _f64(G)
+    y = _f64(y)
+    d = n_steps * n_modes
+    lam = _f64(np.ravel(lam))
+    x0 = np.zeros(d) if x0 is None else _f64(x0)
+    samples = np.zeros((n_iter, d))
+    acc = lib().orc_pcn_linear_chain_ctrl(seed, n_steps, n_modes, len(y), _d(G), _d(y), sigma,
+                                          theta, rho, dt, _d(lam), n_iter, _d(x0), _d(samples))
+    return samples, acc
+
+
+def nudged_cycle(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_threshold, n_bisect=50,
+                 rho=0.99, n_jitter=5, max_temper=100, gtol=LBFGS_GTOL, max_iter=LBFGS_MAX_ITER,
+                 mem=LBFGS_MEM, max_back=LBFGS_MAX_BACK, n_threads=None):
+    """One cycle of the nudged filter (nudging, then tempering and jittering
+    with the weights W~).  Returns (rc, out, stats) with out a dict of the
+    window-end states m, u, the final window-start states m0, u0, increments
+    dW, controls dLam and potentials J."""
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    P = m.shape[0]
+    m0 = np.zeros_like(m)
+    u0 = np.zeros_like(u)
+    dW = np.zeros((P, n_steps, model.n_modes))
+    dLam = np.zeros_like(dW)
+    J = np.zeros(P)
+    st = OrcCycleStats()
+    opts = OrcLbfgsOpts(gtol, max_iter, mem, max_back)
+    cm = model.c()
+    rc = lib().orc_nudged_cycle(C.byref(cm), len(y), _d(y), _d(sg), seed, cycle, P, n_steps,
+                                ess_threshold, n_bisect, rho, n_jitter, max_temper,
+                                C.byref(opts), _d(m), _d(u), _d(m0), _d(u0), _d(dW), _d(dLam),
+                                _d(J), C.byref(st), n_threads or n_threads_default())
+    return rc, dict(m=m, u=u, m0=m0, u0=u0, dW=dW, dLam=dLam, J=J), st

@@ -749,6 +749,116 @@ int orc_jitter_pcn(const orc_model *md, int32_t n_obs, const double *y, const do
   return ORC_OK;
 }
 
+/* Potential of a nudged path for the tempered weights (section 3.1.3, last
+ * paragraph: W replaced by W~ = W + G in the log-weights): the negative
+ * log-likelihood plus minus the log of the discrete Girsanov factor,
+ *   J = phi + sum_i (dLam_i^2 / 2 + dLam_i dW_i) / dt,
+ * with dLam the control and dW the Brownian increment of the path. */
+double orc_nudged_potential(double phi, int32_t len, double dt, const double *dW,
+                            const double *dLam) {
+  if (!(phi < INFINITY)) return INFINITY;
+  double g = 0.0;
+  for (int32_t i = 0; i < len; ++i) g += 0.5 * dLam[i] * dLam[i] / dt + dLam[i] * dW[i] / dt;
+  double J = phi + g;
+  return isfinite(J) ? J : INFINITY;
+}
+
+/* pCN moves of the increments with the control held fixed (jittering of the
+ * nudged filter): the proposal and its uniforms are those of orc_jitter_pcn,
+ * the window runs with dW' + dLam, and the potential is the nudged J above,
+ * so the chain leaves the prior of dW tempered by exp(-theta J) invariant.
+ * phi holds J in and out. */
+int orc_jitter_pcn_ctrl(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                        const orc_rng *rng, int32_t n_particles, int32_t n_steps,
+                        const double *m0, const double *u0, double *dW, const double *dLam,
+                        double *phi, double *m_end, double *u_end, double theta, double rho,
+                        int32_t n_jitter, int32_t *n_accept, int32_t n_threads) {
+  int32_t nx = md->nx, nq = md->n_modes;
+#pragma omp parallel for num_threads(n_threads > 0 ? n_threads : 1) schedule(dynamic, 1)
+  for (int32_t p = 0; p < n_particles; ++p) {
+    size_t wlen = (size_t)n_steps * nq;
+    double *prop = (double *)malloc(sizeof(double) * wlen);
+    double *mm = (double *)malloc(sizeof(double) * nx);
+    double *uu = (double *)malloc(sizeof(double) * nx);
+    double *dWp = dW + (size_t)p * wlen;
+    const double *lam = dLam + (size_t)p * wlen;
+    int32_t acc = 0;
+    for (int32_t j = 0; j < n_jitter; ++j) {
+      uint32_t w3 = (rng->temper_k << 16) | (uint32_t)j;
+      orc_pcn_propose(rng->seed, (uint32_t)p, rng->cycle * (uint32_t)n_steps, n_steps, nq, w3,
+                      rho, md->dt, dWp, prop);
+      memcpy(mm, m0 + (size_t)p * nx, sizeof(double) * nx);
+      memcpy(uu, u0 + (size_t)p * nx, sizeof(double) * nx);
+      int32_t it = 0;
+      int st = orc_window(md, n_steps, mm, uu, prop, lam, &it);
+      double phi_new = st == ORC_OK ? orc_nll(nx, n_obs, uu, y, sigma) : INFINITY;
+      double J_new = orc_nudged_potential(isfinite(phi_new) ? phi_new : INFINITY, (int32_t)wlen,
+                                          md->dt, prop, lam);
+      double v = orc_uniform(rng->seed, (uint32_t)p, rng->cycle,
+                             (uint32_t)ORC_TAG_ACCEPT << 24, w3);
+      if (orc_pcn_accept(theta, phi[p], J_new, v)) {
+        memcpy(dWp, prop, sizeof(double) * wlen);
+        phi[p] = J_new;
+        memcpy(m_end + (size_t)p * nx, mm, sizeof(double) * nx);
+        memcpy(u_end + (size_t)p * nx, uu, sizeof(double) * nx);
+        ++acc;
+      }
+    }
+    if (n_accept) n_accept[p] = acc;
+    free(prop);
+    free(mm);
+    free(uu);
+  }
+  return ORC_OK;
+}
+
+/* The linear toy chain of orc_pcn_linear_chain with a fixed control lam:
+ * the map sees x + lam, and the potential is the nudged J of x,
+ *   J(x) = |G (x + lam) - y|^2 / (2 sigma^2) + sum (lam^2 / 2 + lam x) / dt,
+ * so x + lam is distributed as the tempered Gaussian posterior of the
+ * forcing whatever lam is.  samples is [n_iter][d] of x; returns the number
+ * of acceptances. */
+int64_t orc_pcn_linear_chain_ctrl(uint64_t seed, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                                  const double *G, const double *y, double sigma, double theta,
+                                  double rho, double dt, const double *lam, int32_t n_iter,
+                                  const double *x0, double *samples) {
+  int32_t d = n_steps * n_modes;
+  double *x = (double *)malloc(sizeof(double) * d), *prop = (double *)malloc(sizeof(double) * d);
+  double *b = (double *)malloc(sizeof(double) * d);
+  memcpy(x, x0, sizeof(double) * d);
+  double J = 0.0;
+  for (int32_t i = 0; i < d; ++i) b[i] = x[i] + lam[i];
+  for (int32_t j = 0; j < n_obs; ++j) {
+    double r = -y[j];
+    for (int32_t i = 0; i < d; ++i) r += G[(size_t)j * d + i] * b[i];
+    J += 0.5 * r * r / (sigma * sigma);
+  }
+  J = orc_nudged_potential(J, d, dt, x, lam);
+  int64_t acc = 0;
+  for (int32_t it = 0; it < n_iter; ++it) {
+    orc_pcn_propose(seed, 0u, 0u, n_steps, n_modes, (uint32_t)it, rho, dt, x, prop);
+    for (int32_t i = 0; i < d; ++i) b[i] = prop[i] + lam[i];
+    double Jn = 0.0;
+    for (int32_t j = 0; j < n_obs; ++j) {
+      double r = -y[j];
+      for (int32_t i = 0; i < d; ++i) r += G[(size_t)j * d + i] * b[i];
+      Jn += 0.5 * r * r / (sigma * sigma);
+    }
+    Jn = orc_nudged_potential(Jn, d, dt, prop, lam);
+    double v = orc_uniform(seed, 0u, 0u, (uint32_t)ORC_TAG_ACCEPT << 24, (uint32_t)it);
+    if (orc_pcn_accept(theta, J, Jn, v)) {
+      memcpy(x, prop, sizeof(double) * d);
+      J = Jn;
+      ++acc;
+    }
+    memcpy(samples + (size_t)it * d, x, sizeof(double) * d);
+  }
+  free(x);
+  free(prop);
+  free(b);
+  return acc;
+}
+
 /* The same pCN chain with the forward model replaced by a fixed linear map:
  * the increments x (dimension d = n_steps * n_modes, prior N(0, dt I)) are
  * observed as y = G x + noise(sigma), Phi(x) = |G x - y|^2 / (2 sigma^2).
@@ -1445,4 +1555,105 @@ int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, cons
     }
   }
   return worst;
+}
+
+/* ========================================================================== */
+/* Nudged filter: section 3.1.3 followed by the tempering and jittering of    */
+/* section 3.1.2 with W replaced by W~ (last paragraph of section 3.1.3).     */
+/* ========================================================================== */
+
+/* One assimilation cycle: the increments of the window are drawn (tag
+ * NUDGE) and revealed stage by stage to the sequential nudging of every
+ * particle (orc_nudge_particle from zero controls); each particle gets the
+ * potential J = phi(u_end) - log G of its nudged path; the temperature then
+ * rises from 0 to 1 in adaptive steps on the weights exp(-dtheta J) (as in
+ * orc_tempered_cycle); after each step the particles are resampled
+ * (window-start state, increments, controls, J, window-end state) and their
+ * increments jittered by n_jitter pCN moves with the controls fixed.
+ * On return m, u hold the window-end states; the optional outputs (NULL to
+ * skip) receive the final window-start states m0_out, u0_out [n][nx], the
+ * increments dW_out and controls dLam_out [n][n_steps][n_modes] and the
+ * potentials J_out [n].  st->n_accept counts accepted pCN moves;
+ * st->picard_iters is not filled. */
+int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                     uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                     double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                     int32_t max_temper, const orc_lbfgs_opts *opt, double *m, double *u,
+                     double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
+                     double *J_out, orc_cycle_stats *st, int32_t n_threads) {
+  int32_t nx = md->nx, nq = md->n_modes;
+  size_t state = (size_t)n_particles * nx, wlen = (size_t)n_particles * n_steps * nq;
+  double *m0 = (double *)malloc(sizeof(double) * state), *u0 = (double *)malloc(sizeof(double) * state);
+  double *dW = (double *)malloc(sizeof(double) * wlen);
+  double *dLam = (double *)calloc(wlen, sizeof(double));
+  double *J = (double *)malloc(sizeof(double) * n_particles);
+  double *logG = (double *)malloc(sizeof(double) * n_particles);
+  double *w = (double *)malloc(sizeof(double) * n_particles);
+  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * n_particles);
+  int32_t *stat = (int32_t *)malloc(sizeof(int32_t) * n_particles);
+  int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * n_particles);
+  memset(st, 0, sizeof(*st));
+  memcpy(m0, m, sizeof(double) * state);
+  memcpy(u0, u, sizeof(double) * state);
+
+  orc_draw_increments(seed, n_particles, n_steps, nq, cycle * (uint32_t)n_steps, ORC_TAG_NUDGE,
+                      0u, md->dt, dW);
+  orc_nudge_ensemble(md, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam, opt, logG, NULL,
+                     NULL, NULL, stat, n_threads);
+  for (int32_t p = 0; p < n_particles; ++p) {
+    double phi = stat[p] == ORC_OK ? orc_nll(nx, n_obs, u + (size_t)p * nx, y, sigma) : INFINITY;
+    J[p] = (isfinite(phi) && isfinite(logG[p])) ? phi - logG[p] : INFINITY;
+    if (!isfinite(J[p])) J[p] = INFINITY;
+  }
+  double theta = 0.0;
+  int32_t k = 0;
+  int rc = ORC_OK;
+  while (theta < 1.0) {
+    if (k >= max_temper) {
+      rc = ORC_E_DEGENERATE;
+      break;
+    }
+    double dth, ess;
+    orc_temper(n_particles, J, theta, ess_threshold, n_bisect, &dth, w, &ess);
+    if (ess == 0.0) {
+      rc = ORC_E_DEGENERATE;
+      break;
+    }
+    double theta_new = (dth == 1.0 - theta) ? 1.0 : theta + dth;
+    double ur = orc_uniform(seed, 0u, cycle, (uint32_t)ORC_TAG_RESAMPLE << 24, (uint32_t)k << 16);
+    rc = orc_resample_systematic(n_particles, w, ur, idx);
+    if (rc != ORC_OK) break;
+    gather_rows(m0, idx, n_particles, (size_t)nx);
+    gather_rows(u0, idx, n_particles, (size_t)nx);
+    gather_rows(m, idx, n_particles, (size_t)nx);
+    gather_rows(u, idx, n_particles, (size_t)nx);
+    gather_rows(dW, idx, n_particles, (size_t)n_steps * nq);
+    gather_rows(dLam, idx, n_particles, (size_t)n_steps * nq);
+    gather_rows(J, idx, n_particles, 1);
+    orc_rng rg = {seed, cycle, (uint32_t)k};
+    orc_jitter_pcn_ctrl(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, dLam, J, m, u,
+                        theta_new, rho, n_jitter, acc, n_threads);
+    for (int32_t p = 0; p < n_particles; ++p) st->n_accept += acc[p];
+    st->ess = ess;
+    theta = theta_new;
+    ++k;
+  }
+  st->n_temper = k;
+  st->status = rc;
+  if (m0_out) memcpy(m0_out, m0, sizeof(double) * state);
+  if (u0_out) memcpy(u0_out, u0, sizeof(double) * state);
+  if (dW_out) memcpy(dW_out, dW, sizeof(double) * wlen);
+  if (dLam_out) memcpy(dLam_out, dLam, sizeof(double) * wlen);
+  if (J_out) memcpy(J_out, J, sizeof(double) * n_particles);
+  free(m0);
+  free(u0);
+  free(dW);
+  free(dLam);
+  free(J);
+  free(logG);
+  free(w);
+  free(idx);
+  free(stat);
+  free(acc);
+  return rc;
 }

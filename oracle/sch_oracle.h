@@ -124,6 +124,18 @@ int orc_jitter_pcn(const orc_model *md, int32_t n_obs, const double *y, const do
                    double theta, double rho, int32_t n_jitter, int32_t *n_accept,
                    int32_t n_threads);
 
+double orc_nudged_potential(double phi, int32_t len, double dt, const double *dW,
+                            const double *dLam);
+int orc_jitter_pcn_ctrl(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                        const orc_rng *rng, int32_t n_particles, int32_t n_steps,
+                        const double *m0, const double *u0, double *dW, const double *dLam,
+                        double *phi, double *m_end, double *u_end, double theta, double rho,
+                        int32_t n_jitter, int32_t *n_accept, int32_t n_threads);
+int64_t orc_pcn_linear_chain_ctrl(uint64_t seed, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                                  const double *G, const double *y, double sigma, double theta,
+                                  double rho, double dt, const double *lam, int32_t n_iter,
+                                  const double *x0, double *samples);
+
 /* ---- filter cycles ---- */
 typedef struct orc_cycle_stats {
   double ess;          /* ESS before resampling (bootstrap) / after last step */
@@ -176,6 +188,14 @@ int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, cons
                        int32_t n_particles, int32_t n_steps, double *m, double *u, const double *dW,
                        double *dLam, const orc_lbfgs_opts *opt, double *logG, int32_t *iters,
                        int32_t *evals, int32_t *lbfgs_status, int32_t *status, int32_t n_threads);
+
+/* ---- nudged filter: nudging, then tempering and jittering with W~ ---- */
+int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                     uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                     double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                     int32_t max_temper, const orc_lbfgs_opts *opt, double *m, double *u,
+                     double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
+                     double *J_out, orc_cycle_stats *st, int32_t n_threads);
 
 #ifdef __cplusplus
 }

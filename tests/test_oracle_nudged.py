@@ -1,0 +1,145 @@
+"""Pins of the oracle's nudged filter: the nudging of section 3.1.3 followed by
+the tempering and jittering of section 3.1.2 with W replaced by W~ = W + G
+(last paragraph of section 3.1.3).
+
+The potential of a nudged path is J = phi - log G.  Two linear-Gaussian toys
+pin the way J enters: pCN moves of the increments with a fixed control must
+leave the forcing (increment + control) distributed as the tempered Gaussian
+posterior whatever the control, and importance weights exp(-J) of nudged
+samples must reproduce the posterior mean and covariance.  On the SCH model
+the cycle is checked for internal consistency (every particle's end state and
+potential recomputed from its window-start state, increments and controls),
+and for the no-data limit (zero controls, one tempering step)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2402_06927_amd import workloads as W
+
+SMALL = W.NUDGING_2048.scaled(nx=32, n_particles=8, n_modes=4, n_steps=6, n_obs=8,
+                              sigma_obs=0.05)
+
+
+def _model(orc, wl):
+    xi = W.mode_table(wl.L, wl.nx, wl.n_modes, wl.mode_amp)
+    return orc.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
+                     picard_tol=wl.picard_tol, picard_max=wl.picard_max)
+
+
+def _ensemble_and_obs(orc, wl, sigma):
+    om = _model(orc, wl)
+    u = W.initial_velocity(wl, wl.n_particles, wl.seed)
+    m = orc.momentum_from_velocity(om, u)
+    ut = W.initial_velocity(wl, 1, W.truth_seed(wl))[0]
+    mt = orc.momentum_from_velocity(om, ut)
+    dWt = orc.draw_increments(W.truth_seed(wl), 1, wl.n_steps, wl.n_modes, 0,
+                              orc.TAG_FORECAST, 0, wl.dt)[0]
+    st, mt, ut, _ = orc.window(om, mt, ut, dWt)
+    assert st == 0
+    z = W.obs_noise(wl, W.truth_seed(wl), 1)[0]
+    y = orc.observe(ut, wl.n_obs) + wl.sigma_obs * z
+    return om, m, u, y
+
+
+def test_nudged_potential_value(orc):
+    # phi = 1.5, dt = 0.5, dW = (0.1, -0.2), dLam = (0.3, 0.4):
+    # (0.045 + 0.03 + 0.08 - 0.08) / 0.5 = 0.15
+    J = orc.nudged_potential(1.5, 0.5, np.array([0.1, -0.2]), np.array([0.3, 0.4]))
+    assert J == pytest.approx(1.65, rel=1e-15)
+    assert orc.nudged_potential(np.inf, 0.5, np.zeros(2), np.ones(2)) == np.inf
+
+
+def _toy(d=4, n_obs=3, dt=0.025, sigma=0.05, theta=1.0, seed=0):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n_obs, d))
+    y = rng.standard_normal(n_obs) * 0.1
+    Sinv = np.eye(d) / dt + theta * G.T @ G / sigma ** 2
+    S = np.linalg.inv(Sinv)
+    mu = S @ (theta * G.T @ y / sigma ** 2)
+    return G, y, S, mu
+
+
+@pytest.mark.parametrize("theta,shift", [(1.0, 0.0), (1.0, -2.5), (0.6, 1.0), (0.3, -1.5)])
+def test_pcn_with_control_targets_the_bridge(orc, theta, shift):
+    """pCN moves of x (prior N(0, dt)) under exp(-theta J(x)), J the nudged
+    potential of the forcing b = x + lam.  The chain's law is Gaussian with
+    precision I/dt + theta G^T G / sigma^2 and mean
+    S (theta G^T (y - G lam) / sigma^2 - theta lam / dt); at theta = 1 this
+    makes b the posterior N(mu, S) whatever lam is.  A wrong sign or factor in
+    the Girsanov term moves the mean."""
+    d, dt, sigma = 4, 0.025, 0.05
+    G, y, S1, mu1 = _toy(d=d, dt=dt, sigma=sigma, theta=1.0)
+    lam = mu1 + shift * math.sqrt(dt) * np.array([1.0, -0.5, 0.25, 2.0])
+    Sx = np.linalg.inv(np.eye(d) / dt + theta * G.T @ G / sigma ** 2)
+    mux = Sx @ (theta * G.T @ (y - G @ lam) / sigma ** 2 - theta * lam / dt)
+    if theta == 1.0:
+        np.testing.assert_allclose(mux + lam, mu1, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(Sx, S1, rtol=1e-12)
+    s, acc = orc.pcn_linear_chain_ctrl(33, 2, 2, G, y, sigma, theta, 0.9, dt, lam, 400000)
+    x = s[20000:]
+    assert 0.05 < acc / 400000 < 0.95
+    nb = 100
+    bm = x.reshape(nb, -1, d).mean(axis=1)
+    se = bm.std(axis=0) / math.sqrt(nb)
+    assert np.all(np.abs(x.mean(axis=0) - mux) < 5 * se + 1e-4)
+    np.testing.assert_allclose(np.cov(x.T), Sx, rtol=0.15, atol=0.15 * np.abs(Sx).max())
+
+
+def test_girsanov_weights_correct_nudged_samples(orc):
+    """Importance sampling with the nudged proposal x + lam, x ~ N(0, dt), and
+    weights exp(-J(x)): the weighted forcing has the posterior's mean and
+    covariance (theta = 1)."""
+    d, dt, sigma = 4, 0.025, 0.05
+    G, y, S, mu = _toy(d=d, dt=dt, sigma=sigma, theta=1.0, seed=3)
+    lam = 0.8 * mu
+    rng = np.random.default_rng(7)
+    n = 200000
+    x = math.sqrt(dt) * rng.standard_normal((n, d))
+    b = x + lam
+    phi = 0.5 * np.sum((b @ G.T - y) ** 2, axis=1) / sigma ** 2
+    J = np.array([orc.nudged_potential(phi[i], dt, x[i], lam) for i in range(n)])
+    ess, w, _ = orc.weights(J, 1.0)
+    assert ess > 1000
+    mean = w @ b
+    cov = (b - mean).T @ ((b - mean) * w[:, None])
+    se = np.sqrt(np.diag(S) / ess)
+    assert np.all(np.abs(mean - mu) < 5 * se)
+    np.testing.assert_allclose(cov, S, rtol=0.1, atol=0.1 * np.abs(S).max())
+
+
+def test_nudged_cycle_is_consistent(orc):
+    """Every particle's end state is the window from its final window-start
+    state with its final increments plus controls, its potential is phi of
+    that end plus the Girsanov term, and its start state is a row of the
+    ensemble the cycle began with."""
+    wl = SMALL
+    om, m, u, y = _ensemble_and_obs(orc, wl, wl.sigma_obs)
+    rc, out, st = orc.nudged_cycle(om, y, wl.sigma_obs, wl.seed, 0, m, u, wl.n_steps,
+                                   ess_threshold=wl.n_particles / 2, n_bisect=50, rho=0.9,
+                                   n_jitter=3, max_temper=50, n_threads=4)
+    assert rc == 0 and st.n_temper >= 1 and st.n_accept > 0
+    for p in range(wl.n_particles):
+        assert any(np.array_equal(out["m0"][p], m[q]) for q in range(wl.n_particles))
+        s, me, ue, _ = orc.window(om, out["m0"][p], out["u0"][p], out["dW"][p], out["dLam"][p])
+        assert s == 0
+        np.testing.assert_array_equal(me, out["m"][p])
+        np.testing.assert_array_equal(ue, out["u"][p])
+        J = orc.nudged_potential(orc.nll(ue, y, wl.sigma_obs), wl.dt, out["dW"][p],
+                                 out["dLam"][p])
+        assert out["J"][p] == pytest.approx(J, rel=1e-13, abs=1e-13)
+    assert np.abs(out["dLam"]).max() > 0
+
+
+def test_nudged_cycle_without_data_keeps_zero_control(orc):
+    """sigma -> infinity: the stage optimum is dLam = 0, every J is ~0, the
+    weights are equal and one tempering step reaches theta = 1."""
+    wl = SMALL
+    om, m, u, y = _ensemble_and_obs(orc, wl, wl.sigma_obs)
+    rc, out, st = orc.nudged_cycle(om, y, 1e7, wl.seed, 0, m, u, wl.n_steps,
+                                   ess_threshold=wl.n_particles / 2, n_bisect=50, rho=0.9,
+                                   n_jitter=2, max_temper=50, n_threads=4)
+    assert rc == 0
+    assert np.abs(out["dLam"]).max() < 1e-12
+    assert st.n_temper == 1
+    assert np.abs(out["J"]).max() < 1e-6
