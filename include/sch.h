@@ -234,17 +234,23 @@ int sch_gather(int32_t n_rows, int64_t row_len, const int32_t *idx, const double
  * (The paper prints max(1, .); min is the Metropolis rule it describes.)
  * On acceptance dW, phi, m_end, u_end are replaced.  A proposal whose
  * window fails is rejected.
+ * With controls (dLambda not NULL; the nudged filter, last paragraph of
+ * section 3.1.3: W replaced by W~ in the tempered weights) the window runs
+ * with dW' + dLambda, the controls stay fixed, and phi is the potential
+ *   J = phi_obs + sum_i (dLambda_i^2 / 2 + dLambda_i dW'_i) / dt,
+ * the likelihood plus minus the log of the discrete Girsanov factor.
  *   m0, u0      [n][nx] window-start state (read)
  *   dW          [n][n_steps][n_modes] in/out;  phi [n] in/out
+ *   dLambda     [n][n_steps][n_modes] fixed controls (read) or NULL
  *   m_end,u_end [n][nx] in/out: window-end state of the current increments
  *   n_accept    out [n] or NULL
  *   workspace   >= sch_workspace_bytes(SCH_WS_JITTER, model, n, n_steps, n_jitter)
  * ------------------------------------------------------------------------ */
 int sch_jitter_pcn(const sch_model *model, const sch_obs *obs, const sch_rng *rng,
                    int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
-                   double *dW, double *phi, double *m_end, double *u_end, const double *theta,
-                   double rho, int32_t n_jitter, int32_t *n_accept, void *workspace,
-                   void *stream);
+                   double *dW, const double *dLambda, double *phi, double *m_end, double *u_end,
+                   const double *theta, double rho, int32_t n_jitter, int32_t *n_accept,
+                   void *workspace, void *stream);
 
 /* --------------------------------------------------------------------------
  * Nudging (section 3.1.3).  The control dLambda^n enters each step beside
@@ -342,6 +348,36 @@ int sch_pf_tempered_cycle(const sch_model *model, const sch_obs *obs, uint64_t s
                           double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
                           int32_t max_temper, double *m, double *u, void *workspace,
                           sch_cycle_stats *stats, void *stream);
+
+/* --------------------------------------------------------------------------
+ * sch_pf_nudged_cycle -- the nudged filter: section 3.1.3 followed by the
+ * tempering and jittering of section 3.1.2 with W replaced by W~ = W + G
+ * (last paragraph of section 3.1.3).  Draw the window's increments (tag
+ * NUDGE, counter (p, cycle * n_steps + n, pair | tag << 24, 0)), nudge every
+ * particle over the window (sch_nudge_run from zero controls, L-BFGS
+ * settings opts, checkpoints every ckpt_every steps), give it the potential
+ * J = phi(u_end) - log G, then raise the temperature from 0 to 1 in
+ * adaptive steps on the weights exp(-dtheta J); after each step resample the
+ * particles (window-start state, increments, controls, J, window-end state;
+ * uniform as sch_pf_tempered_cycle) and apply n_jitter pCN moves of the
+ * increments with the controls fixed (sch_jitter_pcn with dLambda).
+ *   m, u       in/out [n][nx]: window-start ensemble in, window-end out
+ *   dLambda    out [n][n_steps][n_modes]: the final particles' controls
+ *   workspace  >= sch_nudged_workspace_bytes(model, n, n_steps, n_jitter,
+ *              ckpt_every)
+ * stats->particle_steps counts the forecast and jitter windows (not the
+ * objective evaluations of the nudging); stats->picard_iters counts the
+ * jitter windows' iterations.  Errors as sch_pf_tempered_cycle; a particle
+ * whose nudged window fails gets J = +infinity.
+ * ------------------------------------------------------------------------ */
+size_t sch_nudged_workspace_bytes(const sch_model *model, int32_t n_particles, int32_t n_steps,
+                                  int32_t n_jitter, int32_t ckpt_every);
+int sch_pf_nudged_cycle(const sch_model *model, const sch_obs *obs, uint64_t seed,
+                        uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                        double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                        int32_t max_temper, const sch_lbfgs_opts *opts, int32_t ckpt_every,
+                        double *m, double *u, double *dLambda, void *workspace,
+                        sch_cycle_stats *stats, void *stream);
 
 /* --------------------------------------------------------------------------
  * Batched runner: many independent bootstrap filters (sch_pf_bootstrap_cycle

@@ -176,7 +176,7 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
                   const double* u0, double* dW, double* phi, double* m_end, double* u_end,
                   const double* theta, double rho, int n_jitter, int* n_accept,
                   unsigned long long* accept_acc, unsigned long long* iters_acc, double* zeta,
-                  double* vacc, hipStream_t st) {
+                  double* vacc, const double* dLam, hipStream_t st) {
   {
     const int64_t work = static_cast<int64_t>(n_jitter) * n * n_steps * ((md.n_modes + 1) / 2);
     hipLaunchKernelGGL(k_draw_pcn, dim3(grid_for(work, 256)), dim3(256), 0, st, seed,
@@ -204,6 +204,7 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
   A.sigma = ob.sigma;
   A.zeta = zeta;
   A.vacc = vacc;
+  A.dLam = dLam;
   const size_t dyn = 2 * sizeof(double) * static_cast<size_t>(n_steps) * md.n_modes;
   if (dyn > 32768) return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel");
   const HelmConst K = make_helm(md, tl);
@@ -274,6 +275,105 @@ void timing_flush() {
 }  // namespace
 
 // ===========================================================================
+// The tempering stage of the tempered and nudged cycles (section 3.1.2):
+// W.phi holds each particle's potential (phi, or J = phi - log G for the
+// nudged filter), W.m0/W.u0 the window-start states, W.dW the increments,
+// (m, u) the window-end states, and dLam the fixed controls or null.  The
+// temperature rises from 0 to 1 in adaptive steps; after each step the
+// particles are resampled (start state, increments, controls, potential, end
+// state) and jittered.  W.acc[0] and W.status hold the forecast's Picard
+// iterations and statuses on entry.
+int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t seed,
+                uint32_t cycle, int n, int n_steps, double thr, int n_bisect, double rho,
+                int n_jitter, int max_temper, double* m, double* u, double* dLam,
+                const CycleWs& W, sch_cycle_stats* stats, hipStream_t st) {
+  void* stream = st;
+  const int nx = md.nx, Q = md.n_modes;
+  const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
+  int k = 0, rc = SCH_OK;
+  double theta = 0.0, ess = 0.0;
+  int64_t psteps = static_cast<int64_t>(n) * n_steps;
+  while (theta < 1.0) {
+    if (k >= max_temper) {
+      rc = SCH_E_DEGENERATE;
+      fail(rc, "tempering did not reach theta = 1 in %d steps", max_temper);
+      break;
+    }
+    {
+      TimedScope ts(SCH_TK_TEMPER, st);
+      if (int r2 = sch_temper_ess(n, W.phi, nullptr, W.scal + 0, thr, n_bisect, W.scal + 1, W.w,
+                                  nullptr, W.scal + 2, stream))
+        return r2;
+    }
+    {
+      TimedScope ts(SCH_TK_RESAMPLE, st);
+      hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
+                         SCH_TAG_RESAMPLE << 24, static_cast<uint32_t>(k) << 16, W.scal + 3);
+      if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
+        return r2;
+    }
+    {
+      TimedScope ts(SCH_TK_GATHER, st);
+      double* fields[4] = {W.m0, W.u0, m, u};
+      for (double* f : fields) {
+        if (int r2 = sch_gather(n, nx, W.idx, f, W.scratch, stream)) return r2;
+        HIP_TRY(hipMemcpyAsync(f, W.scratch, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+      }
+      if (int r2 = sch_gather(n, static_cast<int64_t>(n_steps) * Q, W.idx, W.dW, W.scratch, stream))
+        return r2;
+      HIP_TRY(hipMemcpyAsync(W.dW, W.scratch, sizeof(double) * inc, hipMemcpyDeviceToDevice, st));
+      if (int r2 = sch_gather(n, 1, W.idx, W.phi, W.scratch, stream)) return r2;
+      HIP_TRY(hipMemcpyAsync(W.phi, W.scratch, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      if (dLam) {
+        if (int r2 = sch_gather(n, static_cast<int64_t>(n_steps) * Q, W.idx, dLam, W.scratch,
+                                stream))
+          return r2;
+        HIP_TRY(hipMemcpyAsync(dLam, W.scratch, sizeof(double) * inc, hipMemcpyDeviceToDevice,
+                               st));
+      }
+    }
+    if (n_jitter > 0) {
+      TimedScope ts(SCH_TK_JITTER, st);
+      if (int r2 = launch_jitter(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
+                                 W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
+                                 nullptr, W.acc + 1, W.acc + 2, W.zeta, W.vacc, dLam, st))
+        return r2;
+      psteps += static_cast<int64_t>(n) * n_steps * n_jitter;
+    }
+    HIP_TRY(hipMemcpyAsync(&theta, W.scal + 0, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&ess, W.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    timing_flush();
+    ++k;
+    if (!(ess > 0.0)) {
+      rc = SCH_E_DEGENERATE;
+      fail(rc, "all weights vanished in cycle %u", cycle);
+      break;
+    }
+  }
+  unsigned long long acc[3] = {0, 0, 0};
+  std::vector<int> status(n);
+  HIP_TRY(hipMemcpyAsync(acc, W.acc, sizeof acc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(status.data(), W.status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  timing_flush();
+  g_tm.iters[SCH_TK_WINDOW] += static_cast<long long>(acc[0]);
+  g_tm.iters[SCH_TK_JITTER] += static_cast<long long>(acc[2]);
+  stats->ess = ess;
+  stats->n_temper = k;
+  stats->picard_iters = static_cast<int64_t>(acc[0] + acc[2]);
+  stats->n_accept = static_cast<int64_t>(acc[1]);
+  stats->particle_steps = psteps;
+  for (int p = 0; p < n && rc == SCH_OK; ++p)
+    if (status[p] != SCH_OK) {
+      rc = status[p];
+      fail(rc, "a particle failed in the forecast of cycle %u", cycle);
+    }
+  stats->status = rc;
+  return rc;
+}
+
 extern "C" {
 
 int sch_tune_set(int32_t key, int32_t value) {
@@ -433,9 +533,10 @@ int sch_gather(int32_t n_rows, int64_t row_len, const int32_t* idx, const double
 }
 
 int sch_jitter_pcn(const sch_model* md, const sch_obs* ob, const sch_rng* rng, int32_t n,
-                   int32_t n_steps, const double* m0, const double* u0, double* dW, double* phi,
-                   double* m_end, double* u_end, const double* theta, double rho,
-                   int32_t n_jitter, int32_t* n_accept, void* workspace, void* stream) {
+                   int32_t n_steps, const double* m0, const double* u0, double* dW,
+                   const double* dLambda, double* phi, double* m_end, double* u_end,
+                   const double* theta, double rho, int32_t n_jitter, int32_t* n_accept,
+                   void* workspace, void* stream) {
   Tile tl;
   if (int rc = check_model(md, tl)) return rc;
   if (int rc = check_obs(ob)) return rc;
@@ -447,7 +548,7 @@ int sch_jitter_pcn(const sch_model* md, const sch_obs* ob, const sch_rng* rng, i
                           n_jitter);
   return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
                        dW, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
-                       W.zeta, W.vacc, S(stream));
+                       W.zeta, W.vacc, dLambda, S(stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -634,7 +735,7 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
     return fail(SCH_E_ARG, "bad arguments to sch_pf_tempered_cycle");
   hipStream_t st = S(stream);
   const int nx = md->nx, Q = md->n_modes;
-  const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
+  const size_t state = static_cast<size_t>(n) * nx;
   CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, nullptr, n_jitter);
   *stats = sch_cycle_stats{};
   sch_rng rg{seed, cycle, 0};
@@ -657,82 +758,71 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
   {
     TimedScope ts(SCH_TK_OTHER, st);
     if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
   }
-  int k = 0, rc = SCH_OK;
-  double theta = 0.0, ess = 0.0;
-  int64_t psteps = static_cast<int64_t>(n) * n_steps;
-  while (theta < 1.0) {
-    if (k >= max_temper) {
-      rc = SCH_E_DEGENERATE;
-      fail(rc, "tempering did not reach theta = 1 in %d steps", max_temper);
-      break;
-    }
-    {
-      TimedScope ts(SCH_TK_TEMPER, st);
-      if (int r2 = sch_temper_ess(n, W.phi, nullptr, W.scal + 0, thr, n_bisect, W.scal + 1, W.w,
-                                  nullptr, W.scal + 2, stream))
-        return r2;
-    }
-    {
-      TimedScope ts(SCH_TK_RESAMPLE, st);
-      hipLaunchKernelGGL(k_draw_uniform, dim3(1), dim3(64), 0, st, seed, 0u, cycle,
-                         SCH_TAG_RESAMPLE << 24, static_cast<uint32_t>(k) << 16, W.scal + 3);
-      if (int r2 = sch_resample(n, W.w, W.scal + 3, nullptr, 0.0, W.idx, W.degenerate, W.cum, stream))
-        return r2;
-    }
-    {
-      TimedScope ts(SCH_TK_GATHER, st);
-      double* fields[4] = {W.m0, W.u0, m, u};
-      for (double* f : fields) {
-        if (int r2 = sch_gather(n, nx, W.idx, f, W.scratch, stream)) return r2;
-        HIP_TRY(hipMemcpyAsync(f, W.scratch, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
-      }
-      if (int r2 = sch_gather(n, static_cast<int64_t>(n_steps) * Q, W.idx, W.dW, W.scratch, stream))
-        return r2;
-      HIP_TRY(hipMemcpyAsync(W.dW, W.scratch, sizeof(double) * inc, hipMemcpyDeviceToDevice, st));
-      if (int r2 = sch_gather(n, 1, W.idx, W.phi, W.scratch, stream)) return r2;
-      HIP_TRY(hipMemcpyAsync(W.phi, W.scratch, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    }
-    if (n_jitter > 0) {
-      TimedScope ts(SCH_TK_JITTER, st);
-      if (int r2 = launch_jitter(*md, tl, *ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
-                                 W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
-                                 nullptr, W.acc + 1, W.acc + 2, W.zeta, W.vacc, st))
-        return r2;
-      psteps += static_cast<int64_t>(n) * n_steps * n_jitter;
-    }
-    HIP_TRY(hipMemcpyAsync(&theta, W.scal + 0, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&ess, W.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    timing_flush();
-    ++k;
-    if (!(ess > 0.0)) {
-      rc = SCH_E_DEGENERATE;
-      fail(rc, "all weights vanished in cycle %u", cycle);
-      break;
-    }
+  return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                     max_temper, m, u, nullptr, W, stats, st);
+}
+
+size_t sch_nudged_workspace_bytes(const sch_model* md, int32_t n, int32_t n_steps,
+                                  int32_t n_jitter, int32_t ckpt_every) {
+  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 || ckpt_every < 1) return 0;
+  size_t a = 0, b = 0;
+  carve_cycle(nullptr, SCH_WS_TEMPERED, md->nx, md->n_modes, n, n_steps, &a, n_jitter);
+  carve_nudge(nullptr, true, md->nx, md->n_modes, n, n_steps, ckpt_every, &b);
+  return ((a + 255) & ~size_t(255)) + ((b + 255) & ~size_t(255)) +
+         static_cast<size_t>(n) * sizeof(double) + 256;
+}
+
+int sch_pf_nudged_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
+                        int32_t n, int32_t n_steps, double thr, int32_t n_bisect, double rho,
+                        int32_t n_jitter, int32_t max_temper, const sch_lbfgs_opts* opts,
+                        int32_t ckpt_every, double* m, double* u, double* dLambda,
+                        void* workspace, sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !dLambda || !workspace || !stats ||
+      !opts || n_bisect < 0 || max_temper < 1 || !(rho >= 0 && rho <= 1) || n_jitter < 0 ||
+      ckpt_every < 1)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_nudged_cycle");
+  hipStream_t st = S(stream);
+  const int nx = md->nx, Q = md->n_modes;
+  const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
+  size_t a = 0, b = 0;
+  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, &a, n_jitter);
+  carve_nudge(nullptr, true, nx, Q, n, n_steps, ckpt_every, &b);
+  char* nws = static_cast<char*>(workspace) + ((a + 255) & ~size_t(255));
+  double* logG = reinterpret_cast<double*>(nws + ((b + 255) & ~size_t(255)));
+  *stats = sch_cycle_stats{};
+  sch_rng rg{seed, cycle, 0};
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(static_cast<int64_t>(inc), 256)), dim3(256), 0, st,
+                     dLambda, 0.0, static_cast<int64_t>(inc));
+  CHECK_LAUNCH();
+  {
+    TimedScope ts(SCH_TK_GATHER, st);
+    HIP_TRY(hipMemcpyAsync(W.m0, m, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(W.u0, u, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
   }
-  unsigned long long acc[3] = {0, 0, 0};
-  std::vector<int> status(n);
-  HIP_TRY(hipMemcpyAsync(acc, W.acc, sizeof acc, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(status.data(), W.status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  timing_flush();
-  g_tm.iters[SCH_TK_WINDOW] += static_cast<long long>(acc[0]);
-  g_tm.iters[SCH_TK_JITTER] += static_cast<long long>(acc[2]);
-  stats->ess = ess;
-  stats->n_temper = k;
-  stats->picard_iters = static_cast<int64_t>(acc[0] + acc[2]);
-  stats->n_accept = static_cast<int64_t>(acc[1]);
-  stats->particle_steps = psteps;
-  for (int p = 0; p < n && rc == SCH_OK; ++p)
-    if (status[p] != SCH_OK) {
-      rc = status[p];
-      fail(rc, "a particle failed in the forecast of cycle %u", cycle);
-    }
-  stats->status = rc;
-  return rc;
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_draw_increments(&rg, SCH_TAG_NUDGE, n, n_steps, Q, md->dt, W.dW, stream))
+      return rc;
+  }
+  // sequential nudging of the window from zero controls: (m, u) become the
+  // nudged window ends, W.status the window statuses
+  if (int rc = sch_nudge_run(md, ob, n, n_steps, m, u, W.dW, dLambda, 0, opts, ckpt_every, logG,
+                             nullptr, nullptr, nullptr, W.status, nws, stream))
+    return rc;
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+    hipLaunchKernelGGL(k_nudged_potential, dim3(grid_for(n, 256)), dim3(256), 0, st, n, W.phi,
+                       logG, W.status, W.phi);
+    CHECK_LAUNCH();
+  }
+  return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                     max_temper, m, u, dLambda, W, stats, st);
 }
 
 }  // extern "C"

@@ -533,4 +533,15 @@ __global__ void k_status_merge(int* status, const int* tmp, int n) {
   if (i < n && status[i] == SCH_OK) status[i] = tmp[i];
 }
 
+// Potential of a nudged particle for the tempered weights W~ (section 3.1.3):
+// J = phi - log G, +infinity where the nudged window failed or either term
+// is not finite.
+__global__ void k_nudged_potential(int n, const double* phi, const double* logG,
+                                   const int* status, double* J) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = phi[i] - logG[i];
+  J[i] = (status[i] == SCH_OK && fabs(v) <= 1.7976931348623157e308) ? v : INFINITY;
+}
+
 }  // namespace sch

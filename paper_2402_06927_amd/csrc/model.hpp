@@ -234,12 +234,15 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
 // Point o lies in cell e = floor(o nx / n_obs) at fraction
 // r = (o nx - e n_obs) / n_obs; the thread finds its first point with one
 // integer division and walks on with integer multiplications only.
+// `extra` is a per-thread addend summed into the result (0 for the plain
+// likelihood).
 template <int PMAX, int NT, bool FULL>
 __device__ double block_nll(const double (&u)[PMAX], const Chunk& ch, int nx, int n_obs,
-                            const double* y, const double* sigma, RowLds<NT>& L, int t, int& hs) {
+                            const double* y, const double* sigma, RowLds<NT>& L, int t, int& hs,
+                            double extra = 0.0) {
   double hl, hr;
   halo<PMAX, NT, FULL>(u, ch.cnt, L, t, hl, hr, hs);
-  double acc = 0.0;
+  double acc = 2.0 * extra;
   int64_t o = (static_cast<int64_t>(ch.start) * n_obs + nx - 1) / nx;
   const double dn = static_cast<double>(n_obs);
 #pragma unroll
@@ -273,9 +276,9 @@ __device__ __forceinline__ double staged_at(const AuxLds<PMAX, NT>& X, int slot,
 // slot 0: one thread per observation point.
 template <int PMAX, int NT>
 __device__ double staged_nll(const AuxLds<PMAX, NT>& X, int nx, int n_obs, const double* y,
-                             const double* sigma, RowLds<NT>& L, int t) {
+                             const double* sigma, RowLds<NT>& L, int t, double extra = 0.0) {
   const double dn = static_cast<double>(n_obs);
-  double acc = 0.0;
+  double acc = 2.0 * extra;
   for (int o = t; o < n_obs; o += NT) {
     const int64_t num = static_cast<int64_t>(o) * nx;
     const int e = static_cast<int>(num / n_obs);
@@ -365,11 +368,15 @@ struct JitterArgs {
   const double* sigma;
   const double* zeta;  // [n_jitter][n][n_steps][n_modes]: sqrt(dt) z of the proposals
   const double* vacc;  // [n_jitter][n]: acceptance uniforms
+  const double* dLam;  // [n][n_steps][n_modes] fixed controls, or null
 };
 
 // n_jitter pCN moves of one particle's increments (section 3.1.2): proposal,
 // window rerun from the window-start state (re-read from global memory for
-// every proposal), likelihood and Metropolis accept in one launch.
+// every proposal), likelihood and Metropolis accept in one launch.  With
+// controls (the nudged filter, section 3.1.3) the window runs with the
+// proposal plus the fixed control and the potential is the likelihood plus
+// the Girsanov term sum (dLam^2 / 2 + dLam dW') / dt of the proposal.
 template <int PMAX, int NT, bool FULL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_jitter(const JitterArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
@@ -395,7 +402,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     double m[PMAX], u[PMAX];
     load_chunk<PMAX, FULL>(A.m0 + static_cast<size_t>(p) * nx, ch, m);
     load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u);
-    auto inc = [&](int n, int q) { return prop[n * Q + q]; };
+    const double* lam = A.dLam ? A.dLam + static_cast<size_t>(p) * S * Q : nullptr;
+    auto inc = [&](int n, int q) {
+      double w = prop[n * Q + q];
+      if (lam) w += lam[n * Q + q];
+      return w;
+    };
+    double girs = 0.0;  // this thread's share of the Girsanov term
+    if (lam) {
+      const double idt = 1.0 / A.P.dt;
+      for (int i = t; i < S * Q; i += NT) girs += (0.5 * lam[i] * lam[i] + lam[i] * prop[i]) * idt;
+    }
     const int st =
         run_window<PMAX, NT, FULL, false>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
     bool accept = false;
@@ -409,9 +426,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         X.a[1][jj][t] = m[jj];
       }
       __syncthreads();
-      phin = staged_nll<PMAX, NT>(X, nx, A.n_obs, A.y, A.sigma, L, t);
+      phin = staged_nll<PMAX, NT>(X, nx, A.n_obs, A.y, A.sigma, L, t, girs);
     } else {
-      phin = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t, par.hs);
+      phin = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t, par.hs, girs);
     }
     if (st != SCH_OK || !isfinite(phin)) phin = INFINITY;
     const double v = A.vacc[static_cast<size_t>(j) * gridDim.x + p];

@@ -118,12 +118,16 @@ def _declare(L):
         "sch_temper_ess": (C.c_int, [i32, _vp, _vp, _vp, f64, i32, _vp, _vp, _vp, _vp, _vp]),
         "sch_resample": (C.c_int, [i32, _vp, _vp, _vp, f64, _vp, _vp, _vp, _vp]),
         "sch_gather": (C.c_int, [i32, i64, _vp, _vp, _vp, _vp]),
-        "sch_jitter_pcn": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, f64,
-                                     i32, _vp, _vp, _vp]),
+        "sch_jitter_pcn": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                     _vp, f64, i32, _vp, _vp, _vp]),
         "sch_pf_bootstrap_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, _vp, _vp, _vp, _vp,
                                              ST, _vp]),
         "sch_pf_tempered_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
                                             _vp, _vp, _vp, ST, _vp]),
+        "sch_nudged_workspace_bytes": (C.c_size_t, [M, i32, i32, i32, i32]),
+        "sch_pf_nudged_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
+                                          C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp, _vp, ST,
+                                          _vp]),
         "sch_nudge_grad": (C.c_int, [M, O, i32, i32, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp,
                                      _vp, _vp]),
         "sch_nudge_run": (C.c_int, [M, O, i32, i32, _vp, _vp, _vp, _vp, i32,
@@ -173,9 +177,10 @@ def exported_names():
         "sch_batch_workspace_bytes", "sch_batch_create", "sch_batch_run", "sch_batch_read",
         "sch_batch_destroy", "sch_mlp_param_count", "sch_mlp_workspace_bytes", "sch_mlp_sync",
         "sch_mlp_forward", "sch_mlp_backward", "sch_mlp_adam", "sch_mlp_features",
-        "sch_mlp_colstats", "sch_mlp_encode", "sch_mlp_targets", "sch_mlp_controls", "sch_pf_tempered_cycle", "sch_tune_set", "sch_tune_get",
-        "sch_timing_enable",
-        "sch_timing_reset", "sch_timing_read",
+        "sch_mlp_colstats", "sch_mlp_encode", "sch_mlp_targets", "sch_mlp_controls",
+        "sch_pf_tempered_cycle", "sch_nudged_workspace_bytes", "sch_pf_nudged_cycle",
+        "sch_tune_set", "sch_tune_get", "sch_timing_enable", "sch_timing_reset",
+        "sch_timing_read",
     ]
 
 
@@ -331,14 +336,17 @@ def sch_jitter_pcn(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
                    m0: torch.Tensor, u0: torch.Tensor, dW: torch.Tensor, phi: torch.Tensor,
                    m_end: torch.Tensor, u_end: torch.Tensor, theta: torch.Tensor, rho: float,
                    n_jitter: int, n_accept: torch.Tensor | None = None,
-                   workspace: torch.Tensor | None = None):
+                   workspace: torch.Tensor | None = None, dLambda: torch.Tensor | None = None):
+    """pCN moves of dW; with dLambda (fixed controls) phi holds the nudged
+    potential J."""
     mc, oc = model.c(), obs.c()
     r = SchRngC(seed, cycle, temper_k)
     n, s = dW.shape[0], dW.shape[1]
     if workspace is None:
         workspace = globals()["workspace"](WS_JITTER, model, n, s, n_jitter)
     _check(lib().sch_jitter_pcn(C.byref(mc), C.byref(oc), C.byref(r), n, s, _dev(m0, name="m0"),
-                                _dev(u0, name="u0"), _dev(dW, name="dW"), _dev(phi, name="phi"),
+                                _dev(u0, name="u0"), _dev(dW, name="dW"),
+                                _dev(dLambda, name="dLambda"), _dev(phi, name="phi"),
                                 _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
                                 _dev(theta, name="theta"), rho, n_jitter,
                                 _dev(n_accept, torch.int32, "n_accept"),
@@ -412,6 +420,34 @@ def sch_nudge_run(model: Model, obs: Obs, m: torch.Tensor, u: torch.Tensor, dW: 
                                _dev(evals, torch.int32, "evals"),
                                _dev(status, torch.int32, "status"),
                                _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def nudged_workspace(model: Model, n_particles: int, n_steps: int, n_jitter: int,
+                     ckpt_every: int = 8, device="cuda") -> torch.Tensor:
+    mc = model.c()
+    nb = int(lib().sch_nudged_workspace_bytes(C.byref(mc), n_particles, n_steps, n_jitter,
+                                              ckpt_every))
+    if nb <= 0:
+        raise SchError(SCH_E_ARG, "invalid workspace request")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def sch_pf_nudged_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
+                        u: torch.Tensor, dLambda: torch.Tensor, n_steps: int,
+                        ess_threshold: float, n_bisect: int, rho: float, n_jitter: int,
+                        max_temper: int, workspace: torch.Tensor, gtol: float = LBFGS_GTOL,
+                        max_iter: int = LBFGS_MAX_ITER, mem: int = LBFGS_MEM,
+                        max_back: int = LBFGS_MAX_BACK, ckpt_every: int = 8) -> dict:
+    mc, oc = model.c(), obs.c()
+    st = SchCycleStats()
+    opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
+    _check(lib().sch_pf_nudged_cycle(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0], n_steps,
+                                     ess_threshold, n_bisect, rho, n_jitter, max_temper,
+                                     C.byref(opts), ckpt_every, _dev(m, name="m"),
+                                     _dev(u, name="u"), _dev(dLambda, name="dLambda"),
+                                     _dev(workspace, torch.uint8, "workspace"), C.byref(st),
+                                     _stream()))
+    return st.as_dict()
 
 
 @dataclass
