@@ -161,12 +161,22 @@ __device__ __forceinline__ int wave_or(int v) {
 template <int NT>
 struct RowLds {
   static constexpr int W = NT / kWave;
-  double eq[4][NT];            // interface equations (A, B, C, R), one per chunk
+  // interface equations (A, B, C, R), one per chunk, equation t at
+  // eq_pos(t) = (t % W) * 65 + t / W: a lane's W consecutive equations lie
+  // 65 words apart, so both the writes (one per thread) and the reads (W per
+  // lane) touch consecutive banks
+  double eq[4][65 * W];
   double etail[3][W];          // last-row spike values of each wavefront's last chunk
   double edge[2][W][6];        // wavefront edge values of halo exchanges, double buffered
   double red[3][W];            // workgroup reductions
   double helm[2][W][8];        // per-wavefront records of solve_helm()
 };
+
+template <int NT>
+__device__ __forceinline__ int eq_pos(int t) {
+  constexpr int W = NT / kWave;
+  return (t % W) * 65 + t / W;
+}
 
 // 1/x for the solvers' pivots: the hardware estimate (relative error about
 // 5e-8 on gfx950) and one Newton step, which squares that error (at most
@@ -204,14 +214,15 @@ __device__ __forceinline__ double right_of(const double (&v)[PMAX], int j, int c
   return last ? hr : v[j + 1 < PMAX ? j + 1 : PMAX - 1];
 }
 
-// Value in the chunk's last active slot.
+// Value in the chunk's last active slot.  For ragged chunks a sum of masked
+// terms: a select chain over the slots is turned by the compiler into a
+// dynamic register index, which moves the whole array to scratch memory.
 template <int PMAX, bool FULL>
 __device__ __forceinline__ double last_of(const double (&v)[PMAX], int cnt) {
   if (FULL) return v[PMAX - 1];
-  double r = v[0];
+  double r = 0.0;
 #pragma unroll
-  for (int j = 1; j < PMAX; ++j)
-    if (j == cnt - 1) r = v[j];
+  for (int j = 0; j < PMAX; ++j) r = fma(j == cnt - 1 ? 1.0 : 0.0, v[j], r);
   return r;
 }
 
@@ -512,10 +523,11 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     // left-tail terms (A holds a0); the reader completes it from L.etail
     const int w = t / kWave;
     const bool firstlane = lane == 0;
-    L.eq[0][t] = firstlane ? a0 : a0 * gpl;
-    L.eq[1][t] = firstlane ? Bp : fma(a0, kpl, Bp);
-    L.eq[2][t] = C;
-    L.eq[3][t] = firstlane ? Rp : fma(-a0, ypl, Rp);
+    const int pt = eq_pos<NT>(t);
+    L.eq[0][pt] = firstlane ? a0 : a0 * gpl;
+    L.eq[1][pt] = firstlane ? Bp : fma(a0, kpl, Bp);
+    L.eq[2][pt] = C;
+    L.eq[3][pt] = firstlane ? Rp : fma(-a0, ypl, Rp);
     if (lane == kWave - 1) {
       L.etail[0][w] = yL;
       L.etail[1][w] = gL;
@@ -532,10 +544,10 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     double eA[W], eB[W], eC[W], eR[W];
 #pragma unroll
     for (int e = 0; e < W; ++e) {
-      eA[e] = L.eq[0][W * lane + e];
-      eB[e] = L.eq[1][W * lane + e];
-      eC[e] = L.eq[2][W * lane + e];
-      eR[e] = L.eq[3][W * lane + e];
+      eA[e] = L.eq[0][e * 65 + lane];
+      eB[e] = L.eq[1][e * 65 + lane];
+      eC[e] = L.eq[2][e * 65 + lane];
+      eR[e] = L.eq[3][e * 65 + lane];
     }
     {
       // equation W*lane is the first of a wavefront when (W*lane) % 64 == 0

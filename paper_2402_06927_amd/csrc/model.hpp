@@ -348,6 +348,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   }
 }
 
+// v < exp(logr), kept out of line: inlined, the exponential's polynomial
+// constants are hoisted to the kernel's start and held (spilled) across the
+// window's solver loop.
+__device__ __noinline__ bool metropolis_below(double v, double logr) { return v < exp(logr); }
+
 struct JitterArgs {
   StepParams P;
   int n_steps;
@@ -408,13 +413,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
       if (lam) w += lam[n * Q + q];
       return w;
     };
-    double girs = 0.0;  // this thread's share of the Girsanov term
+    const int st =
+        run_window<PMAX, NT, FULL, false>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
+    double girs = 0.0;  // this thread's share of the Girsanov term (after the window: not
+                        // live across the solver loop)
     if (lam) {
       const double idt = 1.0 / A.P.dt;
       for (int i = t; i < S * Q; i += NT) girs += (0.5 * lam[i] * lam[i] + lam[i] * prop[i]) * idt;
     }
-    const int st =
-        run_window<PMAX, NT, FULL, false>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
     bool accept = false;
     double phin;
     if constexpr (AuxLds<PMAX, NT>::kInLds) {
@@ -434,7 +440,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     const double v = A.vacc[static_cast<size_t>(j) * gridDim.x + p];
     if (phin < INFINITY) {
       const double logr = theta * (phi - phin);
-      accept = logr >= 0.0 ? true : (v < exp(logr));
+      accept = logr >= 0.0 ? true : metropolis_below(v, logr);
     }
     if (accept) {
       for (int i = t; i < S * Q; i += NT) cur[i] = prop[i];
