@@ -207,7 +207,7 @@ __device__ __forceinline__ void store_state(double* base, int nx, const Chunk& c
 }
 
 template <int PMAX, int NT, bool FULL>
-__global__ void __launch_bounds__(NT) k_nudge_grad(const NudgeArgs A, const HelmConst K) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_nudge_grad(const NudgeArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
   __shared__ double gpart[64][NT / kWave];
