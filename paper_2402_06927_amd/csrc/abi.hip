@@ -209,6 +209,12 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
   if (dyn > 32768) return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel");
   const HelmConst K = make_helm(md, tl);
   return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+    // the workgroup's LDS (static solver and window arrays plus the
+    // increments) must fit the 160 KiB of a compute unit
+    constexpr size_t kStatic = sizeof(RowLds<NT>) + sizeof(AuxLds<PM, NT>);
+    if (kStatic + dyn > 160 * 1024)
+      return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel at nx = %d",
+                  md.nx);
     hipLaunchKernelGGL((k_jitter<PM, NT, FULL>), dim3(n), dim3(NT), dyn, st, A, K);
     CHECK_LAUNCH();
     return SCH_OK;

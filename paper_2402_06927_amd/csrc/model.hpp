@@ -62,12 +62,13 @@ struct Parity {
 
 // Two per-node arrays of the window (the explicit part of dv and the previous
 // Picard iterate) live in LDS as [slot][thread] when they fit next to the
-// solver's LDS (64 KiB for both); when only one fits, the explicit part goes
-// to LDS and the iterate stays in registers; otherwise both do.
+// solver's LDS (128 KiB for both: a workgroup may hold up to 160 KiB); when
+// only one fits, the explicit part goes to LDS and the iterate stays in
+// registers; otherwise both do.
 template <int PMAX, int NT>
 struct AuxLds {
   static constexpr size_t kBytes = static_cast<size_t>(PMAX) * NT * sizeof(double);
-  static constexpr bool kInLds = 2 * kBytes <= 65536;  // both arrays
+  static constexpr bool kInLds = 2 * kBytes <= 131072;  // both arrays
   static constexpr bool kDInLds = kBytes <= 65536;     // the explicit part
   double a[kInLds ? 2 : 1][kDInLds ? PMAX : 1][kDInLds ? NT : 1];
 };
