@@ -42,9 +42,9 @@ def flops_per_node_step(n_modes: int) -> int:
 # HBM traffic of one k_jitter launch at this workload from two rocprofv3
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
 # 1 GiB copy), valid for the kernel sources with the hash below.
-TRAFFIC_JITTER_BYTES = (93047.2 * 2.0 + 218439.4 * 1.0) * 1024
+TRAFFIC_JITTER_BYTES = (195659.53125 * 2.0 + 258374.703125 * 1.0) * 1024
 TRAFFIC_THREADS = 256
-TRAFFIC_SOURCES_HASH = "04da7758a08855d9"
+TRAFFIC_SOURCES_HASH = "3f0c081632e9d6ef"
 
 
 def kernel_sources_hash() -> str:
