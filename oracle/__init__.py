@@ -85,6 +85,10 @@ class OrcRng(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("cycle", C.c_uint32), ("temper_k", C.c_uint32)]
 
 
+class OrcMatern(C.Structure):
+    _fields_ = [("kappa", C.c_double), ("eta", C.c_double), ("k", C.c_int32)]
+
+
 class OrcCycleStats(C.Structure):
     _fields_ = [
         ("ess", C.c_double), ("resampled", C.c_int32), ("n_temper", C.c_int32),
@@ -146,6 +150,23 @@ def _declare(L):
                                          C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(OrcLbfgsOpts),
                                          _dp, _ip, _ip, _ip, _ip, C.c_int32]),
         "orc_nudged_potential": (C.c_double, [C.c_double, C.c_int32, C.c_double, _dp, _dp]),
+        "orc_step_field": (C.c_int, [C.POINTER(OrcModel), _dp, _dp, _dp, _ip]),
+        "orc_matern_field": (C.c_int, [C.c_int32, C.c_double, C.POINTER(OrcMatern), _dp, _dp]),
+        "orc_window_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern), C.c_int32,
+                                        _dp, _dp, _dp, _ip]),
+        "orc_ensemble_window_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern),
+                                                 C.c_int32, C.c_int32, _dp, _dp, _dp, _ip, _ip,
+                                                 C.c_int32]),
+        "orc_jitter_pcn_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern), C.c_int32,
+                                            _dp, _dp, C.POINTER(OrcRng), C.c_int32, C.c_int32,
+                                            _dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
+                                            C.c_int32, _ip, C.c_int32]),
+        "orc_tempered_cycle_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern),
+                                                C.c_int32, _dp, _dp, C.c_uint64, C.c_uint32,
+                                                C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                                C.c_double, C.c_int32, C.c_int32, _dp, _dp, _dp,
+                                                _dp, _dp, _dp, C.POINTER(OrcCycleStats),
+                                                C.c_int32]),
         "orc_jitter_pcn_ctrl": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp,
                                           C.POINTER(OrcRng), C.c_int32, C.c_int32, _dp, _dp, _dp,
                                           _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int32,
@@ -648,3 +669,91 @@ def nudged_cycle(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_thresho
                                 C.byref(opts), _d(m), _d(u), _d(m0), _d(u0), _d(dW), _d(dLam),
                                 _d(J), C.byref(st), n_threads or n_threads_default())
     return rc, dict(m=m, u=u, m0=m0, u0=u0, dW=dW, dLam=dLam, J=J), st
+
+
+# --------------------------------------------------------------------------- Matern noise
+def matern(kappa=1.0, eta=1.0, k=3) -> OrcMatern:
+    return OrcMatern(kappa, eta, k)
+
+
+def matern_field(nx, L, mt: OrcMatern, dWc):
+    """Nodal Delta U of the Matern-type noise from the cell increments dWc [nx]."""
+    dWc = _f64(dWc)
+    out = np.zeros(nx)
+    st = lib().orc_matern_field(nx, L, C.byref(mt), _d(dWc), _d(out))
+    assert st == ORC_OK, st
+    return out
+
+
+def step_field(model: Model, m, u, dU):
+    m = np.array(m, dtype=np.float64, copy=True)
+    u = np.array(u, dtype=np.float64, copy=True)
+    it = C.c_int32(0)
+    cm = model.c()
+    st = lib().orc_step_field(C.byref(cm), _d(m), _d(u), _d(_f64(dU)), C.byref(it))
+    return st, m, u, it.value
+
+
+def window_matern(model: Model, mt: OrcMatern, m, u, dWc):
+    m = np.array(m, dtype=np.float64, copy=True)
+    u = np.array(u, dtype=np.float64, copy=True)
+    dWc = _f64(dWc)
+    it = C.c_int32(0)
+    cm = model.c()
+    st = lib().orc_window_matern(C.byref(cm), C.byref(mt), dWc.shape[0], _d(m), _d(u), _d(dWc),
+                                 C.byref(it))
+    return st, m, u, it.value
+
+
+def ensemble_window_matern(model: Model, mt: OrcMatern, m, u, dWc, n_threads=None):
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    dWc = _f64(dWc)
+    P, S = dWc.shape[0], dWc.shape[1]
+    status = np.zeros(P, dtype=np.int32)
+    iters = np.zeros(P, dtype=np.int32)
+    cm = model.c()
+    worst = lib().orc_ensemble_window_matern(C.byref(cm), C.byref(mt), P, S, _d(m), _d(u),
+                                             _d(dWc), _i(status), _i(iters),
+                                             n_threads or n_threads_default())
+    return worst, m, u, status, iters
+
+
+def jitter_pcn_matern(model: Model, mt: OrcMatern, y, sigma, seed, cycle, temper_k, m0, u0, dWc,
+                      phi, m_end, u_end, theta, rho, n_jitter, n_threads=None):
+    y, sg = _obs_arrays(y, sigma)
+    dWc = np.array(dWc, dtype=np.float64, copy=True, order="C")
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    m_end = np.array(m_end, dtype=np.float64, copy=True, order="C")
+    u_end = np.array(u_end, dtype=np.float64, copy=True, order="C")
+    P, ns = dWc.shape[0], dWc.shape[1]
+    acc = np.zeros(P, dtype=np.int32)
+    rg = OrcRng(seed, cycle, temper_k)
+    cm = model.c()
+    lib().orc_jitter_pcn_matern(C.byref(cm), C.byref(mt), len(y), _d(y), _d(sg), C.byref(rg), P,
+                                ns, _d(_f64(m0)), _d(_f64(u0)), _d(dWc), _d(phi), _d(m_end),
+                                _d(u_end), theta, rho, n_jitter, _i(acc),
+                                n_threads or n_threads_default())
+    return dWc, phi, m_end, u_end, acc
+
+
+def tempered_cycle_matern(model: Model, mt: OrcMatern, y, sigma, seed, cycle, m, u, n_steps,
+                          ess_threshold, n_bisect=50, rho=0.99, n_jitter=5, max_temper=100,
+                          n_threads=None):
+    """Tempered + jittered cycle with the Matern-type noise.  Returns (rc, out,
+    stats), out holding m, u (window ends), m0, u0, dWc, phi."""
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    P, nx = m.shape
+    m0, u0 = np.zeros_like(m), np.zeros_like(u)
+    dWc = np.zeros((P, n_steps, nx))
+    phi = np.zeros(P)
+    st = OrcCycleStats()
+    cm = model.c()
+    rc = lib().orc_tempered_cycle_matern(C.byref(cm), C.byref(mt), len(y), _d(y), _d(sg), seed,
+                                         cycle, P, n_steps, ess_threshold, n_bisect, rho,
+                                         n_jitter, max_temper, _d(m), _d(u), _d(m0), _d(u0),
+                                         _d(dWc), _d(phi), C.byref(st),
+                                         n_threads or n_threads_default())
+    return rc, dict(m=m, u=u, m0=m0, u0=u0, dWc=dWc, phi=phi), st

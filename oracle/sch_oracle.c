@@ -361,20 +361,17 @@ int orc_momentum_from_velocity(const orc_model *md, const double *u, double *m) 
 /* iterate a pivoted linear solve) until the momentum changes by at most       */
 /* picard_tol relative in the max norm.                                        */
 /* ========================================================================== */
-int orc_step(const orc_model *md, double *m, double *u, const double *dW, const double *dLam,
-             int32_t *iters) {
+/* One implicit-midpoint step driven by the nodal noise increment dU (the
+ * step's Delta U in dv = dt (u^n + u^{n+1}) / 2 + Delta U, eq. fde1). */
+int orc_step_field(const orc_model *md, double *m, double *u, const double *dU,
+                   int32_t *iters) {
   int32_t n = md->nx;
   double h = md->L / n, dt = md->dt, mu = md->mu;
   size_t sz = sizeof(double) * (size_t)n;
-  double *dU = (double *)calloc((size_t)n, sizeof(double));
   double *dv = (double *)malloc(sz), *lo = (double *)malloc(sz), *di = (double *)malloc(sz);
   double *up = (double *)malloc(sz), *rhs = (double *)malloc(sz), *t1 = (double *)malloc(sz);
   double *ms = (double *)malloc(sz), *us = (double *)malloc(sz), *mp = (double *)malloc(sz);
 
-  for (int32_t q = 0; q < md->n_modes; ++q) {
-    double inc = dW[q] + (dLam ? dLam[q] : 0.0);
-    for (int32_t i = 0; i < n; ++i) dU[i] += md->xi[(size_t)q * n + i] * inc;
-  }
   memcpy(us, u, sz);
   memcpy(mp, m, sz);
   int st = ORC_E_NONCONVERGED;
@@ -429,7 +426,6 @@ int orc_step(const orc_model *md, double *m, double *u, const double *dW, const 
     memcpy(m, ms, sz);
     memcpy(u, us, sz);
   }
-  free(dU);
   free(dv);
   free(lo);
   free(di);
@@ -439,6 +435,20 @@ int orc_step(const orc_model *md, double *m, double *u, const double *dW, const 
   free(ms);
   free(us);
   free(mp);
+  return st;
+}
+
+/* The step with the noise of the modes form: Delta U = sum_q xi_q (dW_q + dLam_q). */
+int orc_step(const orc_model *md, double *m, double *u, const double *dW, const double *dLam,
+             int32_t *iters) {
+  int32_t n = md->nx;
+  double *dU = (double *)calloc((size_t)n, sizeof(double));
+  for (int32_t q = 0; q < md->n_modes; ++q) {
+    double inc = dW[q] + (dLam ? dLam[q] : 0.0);
+    for (int32_t i = 0; i < n; ++i) dU[i] += md->xi[(size_t)q * n + i] * inc;
+  }
+  int st = orc_step_field(md, m, u, dU, iters);
+  free(dU);
   return st;
 }
 
@@ -471,6 +481,86 @@ int orc_ensemble_window(const orc_model *md, int32_t n_particles, int32_t n_step
     int st = orc_window(md, n_steps, m + (size_t)p * nx, u + (size_t)p * nx,
                         dW + (size_t)p * n_steps * nq,
                         dLam ? dLam + (size_t)p * n_steps * nq : NULL, &it);
+    if (status) status[p] = st;
+    if (iters) iters[p] = it;
+    if (st != ORC_OK) {
+#pragma omp critical
+      worst = st;
+    }
+  }
+  return worst;
+}
+
+/* ========================================================================== */
+/* Matern-type noise (section 2, eqs. noise_solve and noise_solve2): the       */
+/* increment of the space-time white noise over a step is piecewise constant,  */
+/* Delta W_h = sum_i h^{-1/2} 1_{cell i} Delta W_i with Delta W_i ~ N(0, dt)    */
+/* iid per cell (cell i = [x_i, x_{i+1}]), and Delta U = Delta U_k solves       */
+/*   (Delta U_j, v) + kappa^{-2} (grad Delta U_j, grad v)                       */
+/*       = eta (Delta W_h, v)  (j = 1),   (Delta U_{j-1}, v)  (j > 1)          */
+/* for all P1 test functions v: (M + kappa^{-2} K) U_1 = eta b with the load    */
+/* vector b_n = (Delta W_h, phi_n) = sqrt(h) (Delta W_{n-1} + Delta W_n) / 2,  */
+/* then (M + kappa^{-2} K) U_j = M U_{j-1}.                                     */
+/* ========================================================================== */
+int orc_matern_field(int32_t nx, double L, const orc_matern *mt, const double *dWc, double *dU) {
+  double h = L / nx, ik2 = 1.0 / (mt->kappa * mt->kappa);
+  size_t sz = sizeof(double) * (size_t)nx;
+  double *a = (double *)malloc(sz), *b = (double *)malloc(sz), *c = (double *)malloc(sz);
+  double *rhs = (double *)malloc(sz);
+  for (int32_t i = 0; i < nx; ++i) {
+    a[i] = h / 6.0 - ik2 / h;
+    b[i] = 2.0 * h / 3.0 + 2.0 * ik2 / h;
+    c[i] = h / 6.0 - ik2 / h;
+    rhs[i] = mt->eta * sqrt(h) * 0.5 * (dWc[wrap(i - 1, nx)] + dWc[i]);
+  }
+  int st = ORC_OK;
+  for (int32_t j = 1; j <= mt->k && st == ORC_OK; ++j) {
+    if (j > 1) orc_apply_mass(nx, h, dU, rhs);
+    st = orc_cyclic_solve(nx, a, b, c, rhs, dU);
+  }
+  free(a);
+  free(b);
+  free(c);
+  free(rhs);
+  return st;
+}
+
+int orc_step_matern(const orc_model *md, const orc_matern *mt, double *m, double *u,
+                    const double *dWc, int32_t *iters) {
+  double *dU = (double *)malloc(sizeof(double) * (size_t)md->nx);
+  int st = orc_matern_field(md->nx, md->L, mt, dWc, dU);
+  if (st == ORC_OK) st = orc_step_field(md, m, u, dU, iters);
+  free(dU);
+  return st;
+}
+
+/* n_steps steps with cell increments dWc [n_steps][nx]. */
+int orc_window_matern(const orc_model *md, const orc_matern *mt, int32_t n_steps, double *m,
+                      double *u, const double *dWc, int32_t *iters) {
+  int32_t total = 0;
+  for (int32_t s = 0; s < n_steps; ++s) {
+    int32_t it = 0;
+    int st = orc_step_matern(md, mt, m, u, dWc + (size_t)s * md->nx, &it);
+    total += it;
+    if (st != ORC_OK) {
+      if (iters) *iters = total;
+      return st;
+    }
+  }
+  if (iters) *iters = total;
+  return ORC_OK;
+}
+
+int orc_ensemble_window_matern(const orc_model *md, const orc_matern *mt, int32_t n_particles,
+                               int32_t n_steps, double *m, double *u, const double *dWc,
+                               int32_t *status, int32_t *iters, int32_t n_threads) {
+  int worst = ORC_OK;
+  int32_t nx = md->nx;
+#pragma omp parallel for num_threads(n_threads > 0 ? n_threads : 1) schedule(dynamic, 1)
+  for (int32_t p = 0; p < n_particles; ++p) {
+    int32_t it = 0;
+    int st = orc_window_matern(md, mt, n_steps, m + (size_t)p * nx, u + (size_t)p * nx,
+                               dWc + (size_t)p * n_steps * nx, &it);
     if (status) status[p] = st;
     if (iters) iters[p] = it;
     if (st != ORC_OK) {
@@ -1653,6 +1743,139 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
   free(logG);
   free(w);
   free(idx);
+  free(stat);
+  free(acc);
+  return rc;
+}
+
+/* ========================================================================== */
+/* Tempered + jittered filter with the Matern-type noise of section 2: the     */
+/* increments are the cell values Delta W_i of the DG0 white noise per step    */
+/* ([n][n_steps][nx], N(0, dt) each), drawn, resampled and moved by pCN        */
+/* exactly as the mode increments of orc_tempered_cycle (the pCN proposal and  */
+/* its counters with nx in place of the number of modes).                      */
+/* ========================================================================== */
+int orc_jitter_pcn_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, const orc_rng *rng,
+                          int32_t n_particles, int32_t n_steps, const double *m0,
+                          const double *u0, double *dWc, double *phi, double *m_end,
+                          double *u_end, double theta, double rho, int32_t n_jitter,
+                          int32_t *n_accept, int32_t n_threads) {
+  int32_t nx = md->nx;
+#pragma omp parallel for num_threads(n_threads > 0 ? n_threads : 1) schedule(dynamic, 1)
+  for (int32_t p = 0; p < n_particles; ++p) {
+    size_t wlen = (size_t)n_steps * nx;
+    double *prop = (double *)malloc(sizeof(double) * wlen);
+    double *mm = (double *)malloc(sizeof(double) * nx);
+    double *uu = (double *)malloc(sizeof(double) * nx);
+    double *cur = dWc + (size_t)p * wlen;
+    int32_t acc = 0;
+    for (int32_t j = 0; j < n_jitter; ++j) {
+      uint32_t w3 = (rng->temper_k << 16) | (uint32_t)j;
+      orc_pcn_propose(rng->seed, (uint32_t)p, rng->cycle * (uint32_t)n_steps, n_steps, nx, w3,
+                      rho, md->dt, cur, prop);
+      memcpy(mm, m0 + (size_t)p * nx, sizeof(double) * nx);
+      memcpy(uu, u0 + (size_t)p * nx, sizeof(double) * nx);
+      int32_t it = 0;
+      int st = orc_window_matern(md, mt, n_steps, mm, uu, prop, &it);
+      double phi_new = st == ORC_OK ? orc_nll(nx, n_obs, uu, y, sigma) : INFINITY;
+      if (!isfinite(phi_new)) phi_new = INFINITY;
+      double v = orc_uniform(rng->seed, (uint32_t)p, rng->cycle,
+                             (uint32_t)ORC_TAG_ACCEPT << 24, w3);
+      if (orc_pcn_accept(theta, phi[p], phi_new, v)) {
+        memcpy(cur, prop, sizeof(double) * wlen);
+        phi[p] = phi_new;
+        memcpy(m_end + (size_t)p * nx, mm, sizeof(double) * nx);
+        memcpy(u_end + (size_t)p * nx, uu, sizeof(double) * nx);
+        ++acc;
+      }
+    }
+    if (n_accept) n_accept[p] = acc;
+    free(prop);
+    free(mm);
+    free(uu);
+  }
+  return ORC_OK;
+}
+
+/* One cycle: draw the cell increments (tag FORECAST, counter (p, cycle *
+ * n_steps + n, pair | tag << 24, 0)), run the window, then temper, resample
+ * (window-start state, increments, phi, window-end state) and jitter as
+ * orc_tempered_cycle.  Optional outputs (NULL to skip): the final
+ * window-start states m0_out, u0_out, increments dWc_out and phi_out. */
+int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                              const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
+                              int32_t n_particles, int32_t n_steps, double ess_threshold,
+                              int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                              double *m, double *u, double *m0_out, double *u0_out,
+                              double *dWc_out, double *phi_out, orc_cycle_stats *st,
+                              int32_t n_threads) {
+  int32_t nx = md->nx;
+  size_t state = (size_t)n_particles * nx, wlen = (size_t)n_particles * n_steps * nx;
+  double *m0 = (double *)malloc(sizeof(double) * state), *u0 = (double *)malloc(sizeof(double) * state);
+  double *dWc = (double *)malloc(sizeof(double) * wlen);
+  double *phi = (double *)malloc(sizeof(double) * n_particles);
+  double *w = (double *)malloc(sizeof(double) * n_particles);
+  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * n_particles);
+  int32_t *iters = (int32_t *)malloc(sizeof(int32_t) * n_particles);
+  int32_t *stat = (int32_t *)malloc(sizeof(int32_t) * n_particles);
+  int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * n_particles);
+  memset(st, 0, sizeof(*st));
+  memcpy(m0, m, sizeof(double) * state);
+  memcpy(u0, u, sizeof(double) * state);
+  orc_draw_increments(seed, n_particles, n_steps, nx, cycle * (uint32_t)n_steps, ORC_TAG_FORECAST,
+                      0u, md->dt, dWc);
+  orc_ensemble_window_matern(md, mt, n_particles, n_steps, m, u, dWc, stat, iters, n_threads);
+  for (int32_t p = 0; p < n_particles; ++p) {
+    st->picard_iters += iters[p];
+    phi[p] = stat[p] == ORC_OK ? orc_nll(nx, n_obs, u + (size_t)p * nx, y, sigma) : INFINITY;
+    if (!isfinite(phi[p])) phi[p] = INFINITY;
+  }
+  double theta = 0.0;
+  int32_t k = 0;
+  int rc = ORC_OK;
+  while (theta < 1.0) {
+    if (k >= max_temper) {
+      rc = ORC_E_DEGENERATE;
+      break;
+    }
+    double dth, ess;
+    orc_temper(n_particles, phi, theta, ess_threshold, n_bisect, &dth, w, &ess);
+    if (ess == 0.0) {
+      rc = ORC_E_DEGENERATE;
+      break;
+    }
+    double theta_new = (dth == 1.0 - theta) ? 1.0 : theta + dth;
+    double ur = orc_uniform(seed, 0u, cycle, (uint32_t)ORC_TAG_RESAMPLE << 24, (uint32_t)k << 16);
+    rc = orc_resample_systematic(n_particles, w, ur, idx);
+    if (rc != ORC_OK) break;
+    gather_rows(m0, idx, n_particles, (size_t)nx);
+    gather_rows(u0, idx, n_particles, (size_t)nx);
+    gather_rows(m, idx, n_particles, (size_t)nx);
+    gather_rows(u, idx, n_particles, (size_t)nx);
+    gather_rows(dWc, idx, n_particles, (size_t)n_steps * nx);
+    gather_rows(phi, idx, n_particles, 1);
+    orc_rng rg = {seed, cycle, (uint32_t)k};
+    orc_jitter_pcn_matern(md, mt, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dWc, phi, m,
+                          u, theta_new, rho, n_jitter, acc, n_threads);
+    for (int32_t p = 0; p < n_particles; ++p) st->n_accept += acc[p];
+    st->ess = ess;
+    theta = theta_new;
+    ++k;
+  }
+  st->n_temper = k;
+  st->status = rc;
+  if (m0_out) memcpy(m0_out, m0, sizeof(double) * state);
+  if (u0_out) memcpy(u0_out, u0, sizeof(double) * state);
+  if (dWc_out) memcpy(dWc_out, dWc, sizeof(double) * wlen);
+  if (phi_out) memcpy(phi_out, phi, sizeof(double) * n_particles);
+  free(m0);
+  free(u0);
+  free(dWc);
+  free(phi);
+  free(w);
+  free(idx);
+  free(iters);
   free(stat);
   free(acc);
   return rc;

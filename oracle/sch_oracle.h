@@ -88,6 +88,23 @@ int orc_ensemble_window(const orc_model *md, int32_t n_particles, int32_t n_step
                         double *u, const double *dW, const double *dLam, int32_t *status,
                         int32_t *iters, int32_t n_threads);
 
+int orc_step_field(const orc_model *md, double *m, double *u, const double *dU,
+                   int32_t *iters);
+
+/* ---- Matern-type noise on the DG0 white noise (k elliptic solves) ---- */
+typedef struct orc_matern {
+  double kappa, eta;
+  int32_t k;
+} orc_matern;
+int orc_matern_field(int32_t nx, double L, const orc_matern *mt, const double *dWc, double *dU);
+int orc_step_matern(const orc_model *md, const orc_matern *mt, double *m, double *u,
+                    const double *dWc, int32_t *iters);
+int orc_window_matern(const orc_model *md, const orc_matern *mt, int32_t n_steps, double *m,
+                      double *u, const double *dWc, int32_t *iters);
+int orc_ensemble_window_matern(const orc_model *md, const orc_matern *mt, int32_t n_particles,
+                               int32_t n_steps, double *m, double *u, const double *dWc,
+                               int32_t *status, int32_t *iters, int32_t n_threads);
+
 /* ---- observations and likelihood ---- */
 void orc_observe(int32_t nx, int32_t n_obs, const double *u, double *out);
 double orc_nll(int32_t nx, int32_t n_obs, const double *u, const double *y, const double *sigma);
@@ -196,6 +213,21 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
                      int32_t max_temper, const orc_lbfgs_opts *opt, double *m, double *u,
                      double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
                      double *J_out, orc_cycle_stats *st, int32_t n_threads);
+
+/* ---- tempered + jittered filter with the Matern-type noise ---- */
+int orc_jitter_pcn_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, const orc_rng *rng,
+                          int32_t n_particles, int32_t n_steps, const double *m0,
+                          const double *u0, double *dWc, double *phi, double *m_end,
+                          double *u_end, double theta, double rho, int32_t n_jitter,
+                          int32_t *n_accept, int32_t n_threads);
+int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                              const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
+                              int32_t n_particles, int32_t n_steps, double ess_threshold,
+                              int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                              double *m, double *u, double *m0_out, double *u0_out,
+                              double *dWc_out, double *phi_out, orc_cycle_stats *st,
+                              int32_t n_threads);
 
 #ifdef __cplusplus
 }
