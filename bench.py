@@ -39,6 +39,14 @@ def flops_per_node_step(n_modes: int) -> int:
     return 2 * n_modes + 5
 
 
+# With the Matern-type noise the per-step noise assembly is the dv part (1),
+# the load vector (2), k scan-form solves (5 each), k - 1 mass products (4
+# each) and the sum into dv (1), plus the right-hand-side mass product (4);
+# a pCN proposal adds 3 per cell.
+def matern_flops_per_node_step(k: int, pcn: bool) -> int:
+    return 1 + 2 + 5 * k + 4 * (k - 1) + 1 + 4 + (3 if pcn else 0)
+
+
 # HBM traffic of one k_jitter launch at this workload from two rocprofv3
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
 # 1 GiB copy), valid for the kernel sources with the hash below.
@@ -72,9 +80,16 @@ def cpu_baseline(wl, u_start, m_start, n_threads: int, psteps_per_cycle: float):
     om = O.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
                  picard_tol=wl.picard_tol, picard_max=wl.picard_max)
     n = u_start.shape[0]
-    dW = O.draw_increments(wl.seed, n, wl.n_steps, wl.n_modes, 0, O.TAG_FORECAST, 0, wl.dt)
-    t0 = time.perf_counter()
-    worst, _, _, _, _ = O.ensemble_window(om, m_start, u_start, dW, n_threads=n_threads)
+    if wl.noise == "matern":
+        cells = O.draw_increments(wl.seed, n, wl.n_steps, wl.nx, 0, O.TAG_FORECAST, 0, wl.dt)
+        mt = O.matern(wl.kappa, wl.eta, wl.k_solves)
+        t0 = time.perf_counter()
+        worst, _, _, _, _ = O.ensemble_window_matern(om, mt, m_start, u_start, cells,
+                                                     n_threads=n_threads)
+    else:
+        dW = O.draw_increments(wl.seed, n, wl.n_steps, wl.n_modes, 0, O.TAG_FORECAST, 0, wl.dt)
+        t0 = time.perf_counter()
+        worst, _, _, _, _ = O.ensemble_window(om, m_start, u_start, dW, n_threads=n_threads)
     dt = time.perf_counter() - t0
     psteps = n * wl.n_steps
     ps_rate = psteps / dt
@@ -622,10 +637,11 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--workload", choices=("tempered", "nudging", "nudged", "warmstart", "mlp",
-                                           "batch"),
+    ap.add_argument("--workload", choices=("tempered", "matern", "nudging", "nudged",
+                                           "warmstart", "mlp", "batch"),
                     default="tempered",
-                    help="tempered: the headline filter; nudging: one nudged window; "
+                    help="tempered: the headline filter; matern: the same filter with the "
+                         "Matern-type noise of section 2; nudging: one nudged window; "
                          "nudged: the nudged filter (nudging, tempering, jittering); "
                          "warmstart: plain vs learned warm-start nudging; mlp: the "
                          "warm-start network; batch: 64 uneven filters in one graph")
@@ -674,7 +690,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     sch.lib()
-    wl = W.TEMPERED_4096
+    matern = args.workload == "matern"
+    wl = W.MATERN_4096 if matern else W.TEMPERED_4096
+    mtn = sch.Matern(wl.kappa, wl.eta, wl.k_solves) if matern else None
     if args.particles:
         wl = wl.scaled(n_particles=args.particles)
     dev = "cuda"
@@ -696,15 +714,21 @@ def main():
     mt = torch.empty_like(ut)
     sch.sch_init_momentum(model, ut, mt)
     z = torch.tensor(W.obs_noise(wl, ts, n_cycles), device=dev)
-    dWt = torch.empty((1, S, Q), dtype=torch.float64, device=dev)
+    dWt = torch.empty((1, S, nx if matern else Q), dtype=torch.float64, device=dev)
     yobs = torch.empty((n_cycles, wl.n_obs), dtype=torch.float64, device=dev)
     for c in range(n_cycles):
         sch.sch_draw_increments(ts, c, 0, sch.TAG_FORECAST, dWt, wl.dt)
-        sch.sch_ensemble_step(model, mt, ut, dWt)
+        if matern:
+            sch.sch_ensemble_step_matern(model, mtn, mt, ut, dWt)
+        else:
+            sch.sch_ensemble_step(model, mt, ut, dWt)
         sch.sch_observe(model, ut, yobs[c:c + 1])
     yobs += wl.sigma_obs * z
     sigma = torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64, device=dev)
-    ws = sch.workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
+    if matern:
+        ws = sch.matern_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
+    else:
+        ws = sch.workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
     m_cpu0, u_cpu0 = None, None
     if not args.threads:
         from paper_2402_06927_amd import autotune
@@ -716,6 +740,10 @@ def main():
 
     def run_cycle(c):
         obs = sch.Obs(yobs[c].contiguous(), sigma)
+        if matern:
+            return sch.sch_pf_tempered_cycle_matern(model, mtn, obs, wl.seed, c, m, u, S,
+                                                    wl.ess_threshold, wl.n_bisect, wl.rho,
+                                                    wl.n_jitter, wl.max_temper, ws)
         return sch.sch_pf_tempered_cycle(model, obs, wl.seed, c, m, u, S, wl.ess_threshold,
                                          wl.n_bisect, wl.rho, wl.n_jitter, wl.max_temper, ws)
 
@@ -752,7 +780,9 @@ def main():
     jt = tim["jitter"]
     j_launches = max(jt["launches"], 1)
     j_psteps = j_launches * n * S * wl.n_jitter
-    j_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"] + flops_per_node_step(Q) * j_psteps)
+    per_step = (matern_flops_per_node_step(wl.k_solves, True) if matern
+                else flops_per_node_step(Q))
+    j_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"] + per_step * j_psteps)
     j_ms = jt["ms"] / j_launches
     j_tflops = (j_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
     roofline = {
@@ -762,13 +792,25 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(j_tflops / PEAK_FP64_TFLOPS, 4),
         "traffic": (TRAFFIC_JITTER_BYTES if kernel_sources_hash() == TRAFFIC_SOURCES_HASH
-                    and wl.nx == 4096 and n == 1024 and tuned == TRAFFIC_THREADS else None),
-        "kernel": "k_jitter (fused pCN proposal + window rerun + likelihood + accept)",
+                    and not matern and wl.nx == 4096 and n == 1024
+                    and tuned == TRAFFIC_THREADS else None),
+        "kernel": ("k_jitter<Matern> (pCN proposal drawn per cell + noise field + window "
+                   "rerun + likelihood + accept)" if matern else
+                   "k_jitter (fused pCN proposal + window rerun + likelihood + accept)"),
         "avg_launch_ms": round(j_ms, 3),
         "algorithmic_flops_per_launch": j_flops / j_launches,
         "picard_iters_per_step": jt["iters"] / max(j_psteps, 1),
     }
 
+    config = {
+        "workload": wl.name, "filter": "tempered+jittered", "nx": nx, "n_particles": n,
+        "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs, "sigma_obs": wl.sigma_obs,
+        "ess_threshold": wl.ess_threshold, "n_bisect": wl.n_bisect,
+        "n_jitter": wl.n_jitter, "rho": wl.rho, "threads_per_particle": tuned,
+    }
+    if matern:
+        del config["n_modes"]
+        config.update(noise="matern", kappa=wl.kappa, eta=wl.eta, k_solves=wl.k_solves)
     out = {
         "metric": "assimilation cycles/sec + particle-steps/sec at N=1024, Nx=4096, vs plain",
         "value": round(cycles_per_s, 4),
@@ -782,12 +824,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": wl.name, "filter": "tempered+jittered", "nx": nx, "n_particles": n,
-            "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs, "sigma_obs": wl.sigma_obs,
-            "ess_threshold": wl.ess_threshold, "n_bisect": wl.n_bisect,
-            "n_jitter": wl.n_jitter, "rho": wl.rho, "threads_per_particle": tuned,
-        },
+        "config": config,
         "particle_steps_per_s": round(psteps_per_s, 1),
         "tempering_steps_per_cycle": n_temper,
         "picard_iters_per_step": round(iters / max(psteps, 1), 3),

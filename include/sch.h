@@ -380,6 +380,67 @@ int sch_pf_nudged_cycle(const sch_model *model, const sch_obs *obs, uint64_t see
                         sch_cycle_stats *stats, void *stream);
 
 /* --------------------------------------------------------------------------
+ * Matern-type noise (section 2, eqs. noise_solve and noise_solve2), the
+ * paper's own noise in place of the modes form.  Per step the space-time
+ * white noise is its DG0 approximation: one increment Delta W_i ~ N(0, dt)
+ * per cell i = [x_i, x_{i+1}] (cell i beside node i), Delta W_h =
+ * sum_i h^{-1/2} 1_{cell i} Delta W_i.  The step's noise Delta U is the P1
+ * field U_k of k elliptic solves:
+ *   (M + kappa^{-2} K) U_1 = eta b,   b_i = (Delta W_h, phi_i)
+ *                                         = sqrt(h) (Delta W_{i-1} + Delta W_i) / 2,
+ *   (M + kappa^{-2} K) U_j = M U_{j-1},   j = 2..k,
+ * and enters eq. fde1 as dv = dt (u^n + u^{n+1})/2 + Delta U.  The paper
+ * takes eta = 1 and k = 3 and leaves kappa open.
+ *   kappa  > 0 (kappa h = sqrt(6), where the operator is diagonal, is
+ *          rejected);  k in 1..16
+ * Errors: SCH_E_ARG for a bad sch_matern, else as the modes-form calls.
+ * ------------------------------------------------------------------------ */
+typedef struct sch_matern {
+  double kappa; /* inverse correlation length of the field  */
+  double eta;   /* amplitude                                */
+  int32_t k;    /* number of elliptic solves (smoothness)   */
+} sch_matern;
+
+/* Delta U of n rows of cell increments: dWc, dU [n][nx] (n <= 65535). */
+int sch_matern_field(const sch_model *model, const sch_matern *mt, int32_t n_particles,
+                     const double *dWc, double *dU, void *stream);
+
+/* sch_ensemble_step with the Matern-type noise: dWc [n][n_steps][nx] holds
+ * the cell increments of every step; m, u, status, iters as sch_ensemble_step
+ * (model->xi is not read). */
+int sch_ensemble_step_matern(const sch_model *model, const sch_matern *mt, int32_t n_particles,
+                             int32_t n_steps, double *m, double *u, const double *dWc,
+                             int32_t *status, int32_t *iters, void *stream);
+
+/* Workspace of the two calls below: which = SCH_WS_JITTER or SCH_WS_TEMPERED
+ * (0 for anything else or invalid sizes). */
+size_t sch_matern_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
+                                  int32_t n_steps, int32_t n_jitter);
+
+/* sch_jitter_pcn on the cell increments dWc [n][n_steps][nx]: the same pCN
+ * proposal per cell (the cells 2k, 2k+1 of a step share one Philox block:
+ * tag PCN, counter (p, cycle * n_steps + n, k | tag << 24,
+ * temper_k << 16 | j)), the same acceptance uniform, window and likelihood.
+ * No controls.  workspace >= sch_matern_workspace_bytes(SCH_WS_JITTER, ...). */
+int sch_jitter_pcn_matern(const sch_model *model, const sch_matern *mt, const sch_obs *obs,
+                          const sch_rng *rng, int32_t n_particles, int32_t n_steps,
+                          const double *m0, const double *u0, double *dWc, double *phi,
+                          double *m_end, double *u_end, const double *theta, double rho,
+                          int32_t n_jitter, int32_t *n_accept, void *workspace, void *stream);
+
+/* sch_pf_tempered_cycle with the Matern-type noise: the window's cell
+ * increments are drawn as sch_draw_increments with nx values per step (tag
+ * FORECAST), the tempering, resampling and jittering as sch_pf_tempered_cycle
+ * with sch_jitter_pcn_matern.  workspace >=
+ * sch_matern_workspace_bytes(SCH_WS_TEMPERED, model, n, n_steps, n_jitter). */
+int sch_pf_tempered_cycle_matern(const sch_model *model, const sch_matern *mt,
+                                 const sch_obs *obs, uint64_t seed, uint32_t cycle,
+                                 int32_t n_particles, int32_t n_steps, double ess_threshold,
+                                 int32_t n_bisect, double rho, int32_t n_jitter,
+                                 int32_t max_temper, double *m, double *u, void *workspace,
+                                 sch_cycle_stats *stats, void *stream);
+
+/* --------------------------------------------------------------------------
  * Batched runner: many independent bootstrap filters (sch_pf_bootstrap_cycle
  * semantics, section 3.1.1) of uneven grid and ensemble sizes advanced one
  * assimilation cycle at a time for all of them together.  The forecast of

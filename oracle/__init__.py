@@ -104,6 +104,9 @@ def _declare(L):
         "orc_uniform": (C.c_double, [C.c_uint64] + [C.c_uint32] * 4),
         "orc_draw_increments": (None, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_uint32,
                                        C.c_uint32, C.c_uint32, C.c_double, _dp]),
+        "orc_draw_increments_rows": (None, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
+                                            C.c_int32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                            C.c_double, _dp]),
         "orc_dense_solve": (C.c_int, [C.c_int32, _dp, _dp, _dp]),
         "orc_tridiag_pivot_solve": (C.c_int, [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]),
         "orc_cyclic_solve": (C.c_int, [C.c_int32, _dp, _dp, _dp, _dp, _dp]),
@@ -234,6 +237,14 @@ def uniform(seed, c0, c1, c2, c3) -> float:
 def draw_increments(seed, n_particles, n_steps, n_modes, step0, tag, word3, dt):
     out = np.zeros((n_particles, n_steps, n_modes))
     lib().orc_draw_increments(seed, n_particles, n_steps, n_modes, step0, tag, word3, dt, _d(out))
+    return out
+
+
+def draw_increments_rows(seed, p0, n_particles, n_steps, n_modes, step0, tag, word3, dt):
+    """Rows p0 .. p0 + n_particles - 1 of draw_increments."""
+    out = np.zeros((n_particles, n_steps, n_modes))
+    lib().orc_draw_increments_rows(seed, p0, n_particles, n_steps, n_modes, step0, tag, word3, dt,
+                                   _d(out))
     return out
 
 

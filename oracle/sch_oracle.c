@@ -93,20 +93,27 @@ double orc_uniform(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_
 /* Brownian increments: iid N(0, dt) per (step, mode) (section 3.1.2:
  * "prior distribution is iid N(0, dt)").  Counter: (particle, global step,
  * mode pair | tag << 24, word3).  Modes 2k and 2k+1 take the pair's z0, z1. */
-void orc_draw_increments(uint64_t seed, int32_t n_particles, int32_t n_steps, int32_t n_modes,
-                         uint32_t step0, uint32_t tag, uint32_t word3, double dt, double *dW) {
+/* Rows p0 .. p0 + n_particles - 1 of the draw (row p of dW is particle p0 + p). */
+void orc_draw_increments_rows(uint64_t seed, int32_t p0, int32_t n_particles, int32_t n_steps,
+                              int32_t n_modes, uint32_t step0, uint32_t tag, uint32_t word3,
+                              double dt, double *dW) {
   double sdt = sqrt(dt);
   int32_t n_pairs = (n_modes + 1) / 2;
   for (int32_t p = 0; p < n_particles; ++p)
     for (int32_t n = 0; n < n_steps; ++n)
       for (int32_t k = 0; k < n_pairs; ++k) {
         double z[2];
-        orc_normal_pair(seed, (uint32_t)p, step0 + (uint32_t)n, (uint32_t)k | (tag << 24), word3,
-                        z);
+        orc_normal_pair(seed, (uint32_t)(p0 + p), step0 + (uint32_t)n, (uint32_t)k | (tag << 24),
+                        word3, z);
         double *row = dW + ((int64_t)p * n_steps + n) * n_modes;
         row[2 * k] = sdt * z[0];
         if (2 * k + 1 < n_modes) row[2 * k + 1] = sdt * z[1];
       }
+}
+
+void orc_draw_increments(uint64_t seed, int32_t n_particles, int32_t n_steps, int32_t n_modes,
+                         uint32_t step0, uint32_t tag, uint32_t word3, double dt, double *dW) {
+  orc_draw_increments_rows(seed, 0, n_particles, n_steps, n_modes, step0, tag, word3, dt, dW);
 }
 
 /* ========================================================================== */

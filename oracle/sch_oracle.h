@@ -53,6 +53,9 @@ enum {
 
 /* dW[p][n][q] = sqrt(dt) * z for particle p, global step (step0 + n), mode q,
  * drawn with the given tag and word-3 value (temper k << 16 | jitter j). */
+void orc_draw_increments_rows(uint64_t seed, int32_t p0, int32_t n_particles, int32_t n_steps,
+                              int32_t n_modes, uint32_t step0, uint32_t tag, uint32_t word3,
+                              double dt, double *dW);
 void orc_draw_increments(uint64_t seed, int32_t n_particles, int32_t n_steps, int32_t n_modes,
                          uint32_t step0, uint32_t tag, uint32_t word3, double dt, double *dW);
 

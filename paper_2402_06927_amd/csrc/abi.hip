@@ -22,14 +22,21 @@ struct CycleWs {
   unsigned long long *cum, *acc;                     // acc: [0] iters, [1] accepts
 };
 
+// With the Matern-type noise (matern != 0) nq is nx (the cells of a step),
+// and zeta is the jitter kernel's stage [n][ns][nx] for the proposals (its
+// random numbers are drawn in the kernel; no vacc).
 CycleWs carve_cycle(void* base, int which, int nx, int nq, int n, int ns, size_t* bytes,
-                    int n_jitter = 0) {
+                    int n_jitter = 0, int matern = 0) {
   Carve c(base);
   CycleWs w{};
   const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * ns * nq;
   if (which == SCH_WS_JITTER || which == SCH_WS_TEMPERED) {
-    w.zeta = c.take<double>(inc * static_cast<size_t>(n_jitter));
-    w.vacc = c.take<double>(static_cast<size_t>(n) * n_jitter);
+    if (matern) {
+      w.zeta = c.take<double>(n_jitter > 0 ? inc : 0);
+    } else {
+      w.zeta = c.take<double>(inc * static_cast<size_t>(n_jitter));
+      w.vacc = c.take<double>(static_cast<size_t>(n) * n_jitter);
+    }
     if (which == SCH_WS_JITTER) {
       if (bytes) *bytes = c.off + 256;
       return w;
@@ -54,10 +61,11 @@ CycleWs carve_cycle(void* base, int which, int nx, int nq, int n, int ns, size_t
   return w;
 }
 
+// M != null: the Matern-type noise, dW holds cells [n][n_steps][nx].
 int launch_window(const sch_model& md, const Tile& tl, int n, int n_steps, double* m, double* u,
                   const double* dW, const double* dLam, int* status, int* iters,
-                  unsigned long long* iters_acc, hipStream_t st) {
-  WindowArgs A;
+                  unsigned long long* iters_acc, hipStream_t st, const MaternDev* M = nullptr) {
+  WindowArgs A{};
   A.P = make_params(md);
   A.n_steps = n_steps;
   A.m = m;
@@ -67,12 +75,31 @@ int launch_window(const sch_model& md, const Tile& tl, int n, int n_steps, doubl
   A.status = status;
   A.iters = iters;
   A.iters_acc = iters_acc;
+  if (M) A.M = *M;
   const HelmConst K = make_helm(md, tl);
   return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
-    hipLaunchKernelGGL((k_window<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A, K);
+    if (M)
+      hipLaunchKernelGGL((k_window<PM, NT, FULL, true>), dim3(n), dim3(NT), 0, st, A, K);
+    else
+      hipLaunchKernelGGL((k_window<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A, K);
     CHECK_LAUNCH();
     return SCH_OK;
   });
+}
+
+// Constants of the Matern-type noise for the model's grid and tile.
+int make_matern(const sch_model& md, const sch_matern* mt, const Tile& tl, MaternDev& M) {
+  if (!mt || !(mt->kappa > 0) || !std::isfinite(mt->kappa) || !std::isfinite(mt->eta) ||
+      mt->k < 1 || mt->k > 16)
+    return fail(SCH_E_ARG, "need 0 < kappa < inf, finite eta and 1 <= k <= 16");
+  const double h = md.L / md.nx, a2 = 1.0 / (mt->kappa * mt->kappa);
+  if (!(std::fabs(h / 6.0 - a2 / h) > 1e-12 * (2.0 * h / 3.0 + 2.0 * a2 / h)))
+    return fail(SCH_E_ARG, "kappa h = sqrt(6): the Matern operator is diagonal");
+  M.K = make_helm_op(h, md.nx, a2, tl);
+  M.load = mt->eta * std::sqrt(h) * 0.5;
+  M.h = h;
+  M.k = mt->k;
+  return SCH_OK;
 }
 
 int launch_helm(const sch_model& md, const Tile& tl, int n, const double* in, double* out,
@@ -176,15 +203,15 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
                   const double* u0, double* dW, double* phi, double* m_end, double* u_end,
                   const double* theta, double rho, int n_jitter, int* n_accept,
                   unsigned long long* accept_acc, unsigned long long* iters_acc, double* zeta,
-                  double* vacc, const double* dLam, hipStream_t st) {
-  {
+                  double* vacc, const double* dLam, hipStream_t st, const MaternDev* M = nullptr) {
+  if (!M) {
     const int64_t work = static_cast<int64_t>(n_jitter) * n * n_steps * ((md.n_modes + 1) / 2);
     hipLaunchKernelGGL(k_draw_pcn, dim3(grid_for(work, 256)), dim3(256), 0, st, seed,
                        cycle * static_cast<uint32_t>(n_steps), cycle, temper_k << 16, n_jitter, n,
                        n_steps, md.n_modes, std::sqrt(md.dt), zeta, vacc);
     CHECK_LAUNCH();
   }
-  JitterArgs A;
+  JitterArgs A{};
   A.P = make_params(md);
   A.n_steps = n_steps;
   A.m0 = m0;
@@ -205,7 +232,14 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
   A.zeta = zeta;
   A.vacc = vacc;
   A.dLam = dLam;
-  const size_t dyn = 2 * sizeof(double) * static_cast<size_t>(n_steps) * md.n_modes;
+  A.seed = seed;
+  A.cycle = cycle;
+  A.temper_k = temper_k;
+  if (M) {
+    A.M = *M;
+    A.stage = zeta;
+  }
+  const size_t dyn = M ? 0 : 2 * sizeof(double) * static_cast<size_t>(n_steps) * md.n_modes;
   if (dyn > 32768) return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel");
   const HelmConst K = make_helm(md, tl);
   return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
@@ -215,7 +249,10 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
     if (kStatic + dyn > 160 * 1024)
       return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel at nx = %d",
                   md.nx);
-    hipLaunchKernelGGL((k_jitter<PM, NT, FULL>), dim3(n), dim3(NT), dyn, st, A, K);
+    if (M)
+      hipLaunchKernelGGL((k_jitter<PM, NT, FULL, true>), dim3(n), dim3(NT), 0, st, A, K);
+    else
+      hipLaunchKernelGGL((k_jitter<PM, NT, FULL>), dim3(n), dim3(NT), dyn, st, A, K);
     CHECK_LAUNCH();
     return SCH_OK;
   });
@@ -288,13 +325,15 @@ void timing_flush() {
 // temperature rises from 0 to 1 in adaptive steps; after each step the
 // particles are resampled (start state, increments, controls, potential, end
 // state) and jittered.  W.acc[0] and W.status hold the forecast's Picard
-// iterations and statuses on entry.
+// iterations and statuses on entry.  M != null: the Matern-type noise (the
+// increments are cells [n][n_steps][nx]).
 int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t seed,
                 uint32_t cycle, int n, int n_steps, double thr, int n_bisect, double rho,
                 int n_jitter, int max_temper, double* m, double* u, double* dLam,
-                const CycleWs& W, sch_cycle_stats* stats, hipStream_t st) {
+                const CycleWs& W, sch_cycle_stats* stats, hipStream_t st,
+                const MaternDev* M = nullptr) {
   void* stream = st;
-  const int nx = md.nx, Q = md.n_modes;
+  const int nx = md.nx, Q = M ? md.nx : md.n_modes;
   const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
   int k = 0, rc = SCH_OK;
@@ -343,7 +382,7 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
       TimedScope ts(SCH_TK_JITTER, st);
       if (int r2 = launch_jitter(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
                                  W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
-                                 nullptr, W.acc + 1, W.acc + 2, W.zeta, W.vacc, dLam, st))
+                                 nullptr, W.acc + 1, W.acc + 2, W.zeta, W.vacc, dLam, st, M))
         return r2;
       psteps += static_cast<int64_t>(n) * n_steps * n_jitter;
     }
@@ -829,6 +868,116 @@ int sch_pf_nudged_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, u
   }
   return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
                      max_temper, m, u, dLambda, W, stats, st);
+}
+
+// ---------------------------------------------------------------------------
+// Matern-type noise (section 2, eqs. noise_solve and noise_solve2).
+// ---------------------------------------------------------------------------
+int sch_matern_field(const sch_model* md, const sch_matern* mt, int32_t n, const double* dWc,
+                     double* dU, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (n < 1 || n > 65535 || !dWc || !dU) return fail(SCH_E_ARG, "bad arguments to sch_matern_field");
+  const StepParams P = make_params(*md);
+  return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+    hipLaunchKernelGGL((k_matern_field<PM, NT, FULL>), dim3(n), dim3(NT), 0, S(stream), P, M, dWc,
+                       dU);
+    CHECK_LAUNCH();
+    return SCH_OK;
+  });
+}
+
+int sch_ensemble_step_matern(const sch_model* md, const sch_matern* mt, int32_t n,
+                             int32_t n_steps, double* m, double* u, const double* dWc,
+                             int32_t* status, int32_t* iters, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 0 || !m || !u || !dWc)
+    return fail(SCH_E_ARG, "bad arguments to sch_ensemble_step_matern");
+  if (n_steps == 0) return SCH_OK;
+  return launch_window(*md, tl, n, n_steps, m, u, dWc, nullptr, status, iters, nullptr,
+                       S(stream), &M);
+}
+
+size_t sch_matern_workspace_bytes(int32_t which, const sch_model* md, int32_t n, int32_t n_steps,
+                                  int32_t n_jitter) {
+  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 ||
+      (which != SCH_WS_JITTER && which != SCH_WS_TEMPERED))
+    return 0;
+  size_t bytes = 0;
+  carve_cycle(nullptr, which, md->nx, md->nx, n, n_steps, &bytes, n_jitter, 1);
+  return bytes;
+}
+
+int sch_jitter_pcn_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
+                          const sch_rng* rng, int32_t n, int32_t n_steps, const double* m0,
+                          const double* u0, double* dWc, double* phi, double* m_end,
+                          double* u_end, const double* theta, double rho, int32_t n_jitter,
+                          int32_t* n_accept, void* workspace, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (!rng || n < 1 || n > 65535 || n_steps < 1 || !m0 || !u0 || !dWc || !phi || !m_end ||
+      !u_end || !theta || !(rho >= 0 && rho <= 1) || n_jitter < 0 ||
+      (n_jitter > 0 && !workspace))
+    return fail(SCH_E_ARG, "bad arguments to sch_jitter_pcn_matern");
+  if (n_jitter == 0) return SCH_OK;
+  CycleWs W = carve_cycle(workspace, SCH_WS_JITTER, md->nx, md->nx, n, n_steps, nullptr,
+                          n_jitter, 1);
+  return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
+                       dWc, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
+                       W.zeta, nullptr, nullptr, S(stream), &M);
+}
+
+int sch_pf_tempered_cycle_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
+                                 uint64_t seed, uint32_t cycle, int32_t n, int32_t n_steps,
+                                 double thr, int32_t n_bisect, double rho, int32_t n_jitter,
+                                 int32_t max_temper, double* m, double* u, void* workspace,
+                                 sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !workspace || !stats || n_bisect < 0 ||
+      max_temper < 1 || !(rho >= 0 && rho <= 1) || n_jitter < 0)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_tempered_cycle_matern");
+  hipStream_t st = S(stream);
+  const int nx = md->nx;
+  const size_t state = static_cast<size_t>(n) * nx;
+  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, nx, n, n_steps, nullptr, n_jitter, 1);
+  *stats = sch_cycle_stats{};
+  sch_rng rg{seed, cycle, 0};
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
+  {
+    TimedScope ts(SCH_TK_GATHER, st);
+    HIP_TRY(hipMemcpyAsync(W.m0, m, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(W.u0, u, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+  }
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    // the cell increments: nx per step, N(0, dt) each
+    if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, nx, md->dt, W.dW, stream))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_WINDOW, st);
+    if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc,
+                               st, &M))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+  }
+  return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                     max_temper, m, u, nullptr, W, stats, st, &M);
 }
 
 }  // extern "C"

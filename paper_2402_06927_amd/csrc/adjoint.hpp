@@ -241,7 +241,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     if (last) store_state<PMAX, FULL>(sg, nx, ch, m, u);
     for (int n = n0; n < n1 && st == SCH_OK; ++n) {
       auto inc1 = [&](int, int q) { return incv(n, q); };
-      st = run_window<PMAX, NT, FULL>(A.P, K, inc1, 1, m, u, ch, L, X, t, par, fit);
+      st = run_window<PMAX, NT, FULL>(A.P, K, modes_noise<PMAX, FULL>(A.P, ch, inc1), 1, m, u,
+                                      ch, L, X, t, par, fit);
       if (last) store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
     }
   }
@@ -279,7 +280,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         store_state<PMAX, FULL>(sg, nx, ch, m, u);
         for (int n = n0; n < n1 && st == SCH_OK; ++n) {
           auto inc1 = [&](int, int q) { return incv(n, q); };
-          st = run_window<PMAX, NT, FULL>(A.P, K, inc1, 1, m, u, ch, L, X, t, par, fit);
+          st = run_window<PMAX, NT, FULL>(A.P, K, modes_noise<PMAX, FULL>(A.P, ch, inc1), 1, m,
+                                          u, ch, L, X, t, par, fit);
           store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
         }
       }

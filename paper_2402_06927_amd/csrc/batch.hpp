@@ -121,7 +121,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     auto inc = [&](int n, int q) { return dW[n * Q + q]; };
     int iters = 0;
     Parity par;
-    const int st = run_window<PMAX, NT, false>(P, K, inc, B.n_steps, m, u, ch, L, X, t, par, iters);
+    const int st = run_window<PMAX, NT, false>(P, K, modes_noise<PMAX, false>(P, ch, inc), B.n_steps,
+                                                 m, u, ch, L, X, t, par, iters);
     store_chunk<PMAX, false>(mp, ch, m);
     store_chunk<PMAX, false>(up, ch, u);
     if (t == 0) {

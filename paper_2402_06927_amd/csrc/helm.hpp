@@ -2,7 +2,7 @@
 // H u = f, H = d I + o (S + S^{-1}) (S the cyclic shift; d = 2h/3 + 2 alpha^2/h,
 // o = h/6 - alpha^2/h from the first line of eq. fde1), in one barrier.
 //
-// H factors as kappa (1 - r S)(1 - r S^{-1}) with r the root in (0,1) of
+// H factors as kappa (1 - r S)(1 - r S^{-1}) with r the root of modulus < 1 of
 // r^2 + (d/o) r + 1 = 0 and kappa = -o/r, so
 //   H^{-1} f = (F+ + F- - f) / (kappa (1 - r^2)),
 // where F+ and F- are the periodic solutions of the first-order recurrences

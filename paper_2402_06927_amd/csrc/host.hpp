@@ -74,22 +74,29 @@ inline bool pick_tile(int nx, Tile& tl) {
   return true;
 }
 
-// Constants of the scan form of the Helmholtz solve (helm.hpp).
-inline HelmConst make_helm(const sch_model& md, const Tile& tl) {
+// Constants of the scan form (helm.hpp) of the solve with M + a2 K on nx
+// periodic cells of width h.
+inline HelmConst make_helm_op(double h, int nx, double a2, const Tile& tl) {
   HelmConst K{};
-  const double h = md.L / md.nx, a2 = md.alpha * md.alpha;
   K.ho = h / 6.0 - a2 / h;
   K.hd = 2.0 * h / 3.0 + 2.0 * a2 / h;
-  const double x = -K.hd / K.ho;  // > 2
-  K.r = 2.0 / (x + std::sqrt((x - 2.0) * (x + 2.0)));
+  // |x| > 2 (diagonal dominance); r is the root of r^2 - x r + 1 = 0 inside
+  // the unit interval, of the sign of x
+  const double x = -K.hd / K.ho;
+  K.r = 2.0 / (x + std::copysign(std::sqrt((x - 2.0) * (x + 2.0)), x));
   const double kappa = -K.ho / K.r;
   K.coef = 1.0 / (kappa * (1.0 - K.r) * (1.0 + K.r));
-  K.rN1 = 1.0 / (1.0 - std::pow(K.r, static_cast<double>(md.nx)));
-  K.base = md.nx / tl.nt;
+  K.rN1 = 1.0 / (1.0 - std::pow(K.r, static_cast<double>(nx)));
+  K.base = nx / tl.nt;
   K.rb = std::pow(K.r, static_cast<double>(K.base));
   K.rb1 = std::pow(K.r, static_cast<double>(K.base + 1));
   K.rinv = 1.0 / K.r;
   return K;
+}
+
+// The Helmholtz operator H = M + alpha^2 K of the model.
+inline HelmConst make_helm(const sch_model& md, const Tile& tl) {
+  return make_helm_op(md.L / md.nx, md.nx, md.alpha * md.alpha, tl);
 }
 
 template <class F>

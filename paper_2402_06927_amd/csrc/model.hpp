@@ -73,9 +73,67 @@ struct AuxLds {
   double a[kInLds ? 2 : 1][kDInLds ? PMAX : 1][kDInLds ? NT : 1];
 };
 
+// The noise of the modes form: noise(n, e) adds sum_q xi_q inc(n, q) to the
+// chunk e, inc(n, q) being the increment dW^n_q (+ dLambda^n_q) of step n,
+// mode q.
+template <int PMAX, bool FULL, class IncF>
+__device__ __forceinline__ auto modes_noise(const StepParams& P, const Chunk& ch, IncF inc) {
+  return [&P, ch, inc](int n, double (&e)[PMAX]) {
+    for (int q = 0; q < P.n_modes; ++q) {
+      const double w = inc(n, q);
+      const double* xq = P.xi + static_cast<size_t>(q) * P.nx + ch.start;
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j)
+        if (FULL || j < ch.cnt) e[j] = fma(xq[j], w, e[j]);
+    }
+  };
+}
+
+// Constants of the Matern-type noise (section 2, eq. noise_solve2): the
+// operator M + kappa^{-2} K in scan form, the load factor eta sqrt(h) / 2 of
+// the cell increments, and the number k of solves.
+struct MaternDev {
+  HelmConst K;
+  double load, h;
+  int k;
+};
+
+// Adds the Matern-type noise field of one step to e.  w holds the chunk's
+// cell increments Delta W_i (cell i = [x_i, x_{i+1}], held by the thread that
+// holds node i).  The load vector of Delta W_h is
+// b_i = eta sqrt(h) (Delta W_{i-1} + Delta W_i) / 2; then
+// (M + kappa^{-2} K) U_1 = b and (M + kappa^{-2} K) U_j = M U_{j-1}, each
+// solve in the scan form of solve_helm, the mass products with the bordering
+// values of the previous solve as halo (chunks of >= 2 rows) or an exchange.
+template <int PMAX, int NT, bool FULL>
+__device__ __forceinline__ void matern_add(const MaternDev& M, const double (&w)[PMAX],
+                                           double (&e)[PMAX], const Chunk& ch, RowLds<NT>& L,
+                                           int t, Parity& par) {
+  const int cnt = ch.cnt;
+  const bool bordered = FULL || M.K.base >= 2;
+  double wl, wr;
+  halo<PMAX, NT, FULL>(w, cnt, L, t, wl, wr, par.hs);
+  double r[PMAX], U[PMAX];
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) r[j] = M.load * (left_of<PMAX, FULL>(w, j, wl) + w[j]);
+  double uL = 0.0, uR = 0.0, g0, g1, g2;
+  for (int i = 0; i < M.k; ++i) {
+    if (i > 0) {
+      double hl = uL, hr = uR;
+      if (!bordered) halo<PMAX, NT, FULL>(U, cnt, L, t, hl, hr, par.hs);
+      mass_apply_h<PMAX, FULL>(U, r, M.h, cnt, hl, hr, 1.0);
+    }
+    solve_helm<PMAX, NT, FULL>(M.K, r, U, uL, uR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1, g2);
+    par.slot ^= 1;
+  }
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j)
+    if (FULL || j < cnt) e[j] += U[j];
+}
+
 // One assimilation window of n_steps implicit-midpoint steps (eq. fde1) for
-// the particle whose chunk is held in m, u.  inc(n, q) returns the noise
-// increment dW^n_q (+ dLambda^n_q) of step n, mode q.
+// the particle whose chunk is held in m, u.  noise(n, e) adds the step's
+// noise increment dU^n to the chunk e (modes_noise, or the Matern-type field).
 //
 // Each step solves  A(dv) s = 2 M m^n  for s = m^n + m^{n+1}, with
 //   A(dv) = M + (mu dt/2) K + (1/2) C(dv),  dv = dt (u^n + u*)/2 + dU^n,
@@ -95,8 +153,8 @@ struct AuxLds {
 // the last iterate is kept, on a non-finite iterate the step's input is kept
 // (KEEP) or the state is left undefined (!KEEP, for callers that discard a
 // failed window: u^n then need not stay live through the iteration).
-template <int PMAX, int NT, bool FULL, bool KEEP = true, class IncF>
-__device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int n_steps,
+template <int PMAX, int NT, bool FULL, bool KEEP = true, class NoiseF>
+__device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise, int n_steps,
                           double (&m)[PMAX], double (&u)[PMAX], const Chunk& ch, RowLds<NT>& L,
                           AuxLds<PMAX, NT>& X, int t, Parity& par, int& iters) {
   constexpr bool kLds = AuxLds<PMAX, NT>::kInLds, kDLds = AuxLds<PMAX, NT>::kDInLds;
@@ -119,13 +177,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, IncF inc, int
       double e[PMAX];
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) e[j] = hdt * u[j];
-      for (int q = 0; q < P.n_modes; ++q) {
-        const double w = inc(n, q);
-        const double* xq = P.xi + static_cast<size_t>(q) * P.nx + ch.start;
-#pragma unroll
-        for (int j = 0; j < PMAX; ++j)
-          if (FULL || j < cnt) e[j] = fma(xq[j], w, e[j]);
-      }
+      noise(n, e);
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) e[j] *= 0.25;
       const double fst[3] = {m[0], e[0], u[0]};
@@ -311,14 +363,15 @@ struct WindowArgs {
   int n_steps;
   double* m;
   double* u;
-  const double* dW;
+  const double* dW;    // modes: [n][n_steps][n_modes]; Matern: cells [n][n_steps][nx]
   const double* dLam;
   int* status;
   int* iters;
   unsigned long long* iters_acc;  // optional device accumulator
+  MaternDev M;                    // Matern-type noise (MATERN kernels)
 };
 
-template <int PMAX, int NT, bool FULL>
+template <int PMAX, int NT, bool FULL, bool MATERN = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_window(const WindowArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
@@ -329,17 +382,29 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   double m[PMAX], u[PMAX];
   load_chunk<PMAX, FULL>(mp, ch, m);
   load_chunk<PMAX, FULL>(up, ch, u);
-  const int Q = A.P.n_modes;
-  const double* dW = A.dW + static_cast<size_t>(p) * A.n_steps * Q;
-  const double* dL = A.dLam ? A.dLam + static_cast<size_t>(p) * A.n_steps * Q : nullptr;
-  auto inc = [&](int n, int q) {
-    double w = dW[n * Q + q];
-    if (dL) w += dL[n * Q + q];
-    return w;
-  };
-  int iters = 0;
+  int iters = 0, st;
   Parity par;
-  const int st = run_window<PMAX, NT, FULL>(A.P, K, inc, A.n_steps, m, u, ch, L, X, t, par, iters);
+  if constexpr (MATERN) {
+    const int nx = A.P.nx;
+    const double* cells = A.dW + static_cast<size_t>(p) * A.n_steps * nx;
+    auto noise = [&](int n, double (&e)[PMAX]) {
+      double w[PMAX];
+      load_chunk<PMAX, FULL>(cells + static_cast<size_t>(n) * nx, ch, w);
+      matern_add<PMAX, NT, FULL>(A.M, w, e, ch, L, t, par);
+    };
+    st = run_window<PMAX, NT, FULL>(A.P, K, noise, A.n_steps, m, u, ch, L, X, t, par, iters);
+  } else {
+    const int Q = A.P.n_modes;
+    const double* dW = A.dW + static_cast<size_t>(p) * A.n_steps * Q;
+    const double* dL = A.dLam ? A.dLam + static_cast<size_t>(p) * A.n_steps * Q : nullptr;
+    auto inc = [&](int n, int q) {
+      double w = dW[n * Q + q];
+      if (dL) w += dL[n * Q + q];
+      return w;
+    };
+    st = run_window<PMAX, NT, FULL>(A.P, K, modes_noise<PMAX, FULL>(A.P, ch, inc), A.n_steps, m,
+                                    u, ch, L, X, t, par, iters);
+  }
   store_chunk<PMAX, FULL>(mp, ch, m);
   store_chunk<PMAX, FULL>(up, ch, u);
   if (t == 0) {
@@ -375,7 +440,52 @@ struct JitterArgs {
   const double* zeta;  // [n_jitter][n][n_steps][n_modes]: sqrt(dt) z of the proposals
   const double* vacc;  // [n_jitter][n]: acceptance uniforms
   const double* dLam;  // [n][n_steps][n_modes] fixed controls, or null
+  // Matern-type noise (MATERN kernels): the increments are the cells
+  // dW [n][n_steps][nx]; proposals and uniforms are drawn in the kernel, the
+  // proposal rows go to stage [n][n_steps][nx]
+  MaternDev M;
+  double* stage;
+  uint64_t seed;
+  uint32_t cycle, temper_k;
 };
+
+// pCN proposal for the chunk's cells of one step (section 3.1.2):
+// w_i = rho c_i + sqrt(1 - rho^2) sqrt(dt) z_i, the normals of cells 2k and
+// 2k + 1 from one Philox block (tag PCN, counter (c0, c1, k | tag << 24, c3)).
+// A chunk that starts at an odd cell takes the second normal of its first
+// block.
+template <int PMAX, bool FULL>
+__device__ __forceinline__ void pcn_cells(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c3,
+                                          const Chunk& ch, double rho, double srho, double sdt,
+                                          const double* cur, double (&w)[PMAX]) {
+  constexpr uint32_t tag = SCH_TAG_PCN << 24;
+  const int s0 = ch.start;
+  double z[PMAX];
+  if (!FULL && (s0 & 1)) {
+    double za, zb;
+    normal2(seed, c0, c1, static_cast<uint32_t>(s0 >> 1) | tag, c3, za, zb);
+    z[0] = zb;
+#pragma unroll
+    for (int j = 1; j < PMAX; j += 2) {
+      za = zb = 0.0;
+      if (j < ch.cnt) normal2(seed, c0, c1, static_cast<uint32_t>((s0 + j) >> 1) | tag, c3, za, zb);
+      z[j] = za;
+      if (j + 1 < PMAX) z[j + 1] = zb;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PMAX; j += 2) {
+      double za = 0.0, zb = 0.0;
+      if (FULL || j < ch.cnt)
+        normal2(seed, c0, c1, static_cast<uint32_t>((s0 + j) >> 1) | tag, c3, za, zb);
+      z[j] = za;
+      z[j + 1] = zb;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j)
+    w[j] = (FULL || j < ch.cnt) ? rho * cur[j] + srho * (sdt * z[j]) : 0.0;
+}
 
 // n_jitter pCN moves of one particle's increments (section 3.1.2): proposal,
 // window rerun from the window-start state (re-read from global memory for
@@ -383,18 +493,31 @@ struct JitterArgs {
 // controls (the nudged filter, section 3.1.3) the window runs with the
 // proposal plus the fixed control and the potential is the likelihood plus
 // the Girsanov term sum (dLam^2 / 2 + dLam dW') / dt of the proposal.
-template <int PMAX, int NT, bool FULL>
+// MATERN: the increments are the DG0 cell values of the Matern-type noise;
+// each thread proposes its own cells step by step inside the window and
+// writes them to the stage row, and an acceptance swaps the roles of the
+// particle's stage and increment rows (one copy back at the end if needed).
+template <int PMAX, int NT, bool FULL, bool MATERN = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_jitter(const JitterArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
-  extern __shared__ double dyn[];  // [2][n_steps][n_modes]: current increments, proposal
+  extern __shared__ double dyn[];  // modes: [2][n_steps][n_modes]: current increments, proposal
   const int p = blockIdx.x, t = threadIdx.x;
   const int nx = A.P.nx, Q = A.P.n_modes, S = A.n_steps;
   const Chunk ch = chunk_of<NT>(nx, t);
-  double* cur = dyn;
-  double* prop = dyn + S * Q;
-  double* dWp = A.dW + static_cast<size_t>(p) * S * Q;
-  for (int i = t; i < S * Q; i += NT) cur[i] = dWp[i];
+  double* cur;
+  double* prop;
+  double* dWp;
+  if constexpr (MATERN) {
+    dWp = A.dW + static_cast<size_t>(p) * S * nx;
+    cur = dWp;
+    prop = A.stage + static_cast<size_t>(p) * S * nx;
+  } else {
+    cur = dyn;
+    prop = dyn + S * Q;
+    dWp = A.dW + static_cast<size_t>(p) * S * Q;
+    for (int i = t; i < S * Q; i += NT) cur[i] = dWp[i];
+  }
   double phi = A.phi[p];
   const double theta = *A.theta;
   const double srho = sqrt(1.0 - A.rho * A.rho);
@@ -402,23 +525,43 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   Parity par;
   __syncthreads();
   for (int j = 0; j < A.n_jitter; ++j) {
-    const double* zj = A.zeta + (static_cast<size_t>(j) * gridDim.x + p) * S * Q;
-    for (int i = t; i < S * Q; i += NT) prop[i] = A.rho * cur[i] + srho * zj[i];
-    __syncthreads();
+    const uint32_t w3 = (A.temper_k << 16) | static_cast<uint32_t>(j);
+    if constexpr (!MATERN) {
+      const double* zj = A.zeta + (static_cast<size_t>(j) * gridDim.x + p) * S * Q;
+      for (int i = t; i < S * Q; i += NT) prop[i] = A.rho * cur[i] + srho * zj[i];
+      __syncthreads();
+    }
     double m[PMAX], u[PMAX];
     load_chunk<PMAX, FULL>(A.m0 + static_cast<size_t>(p) * nx, ch, m);
     load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u);
     const double* lam = A.dLam ? A.dLam + static_cast<size_t>(p) * S * Q : nullptr;
-    auto inc = [&](int n, int q) {
-      double w = prop[n * Q + q];
-      if (lam) w += lam[n * Q + q];
-      return w;
-    };
-    const int st =
-        run_window<PMAX, NT, FULL, false>(A.P, K, inc, S, m, u, ch, L, X, t, par, iters);
+    int st;
+    if constexpr (MATERN) {
+      const double sdt = sqrt(A.P.dt);
+      const uint32_t step0 = A.cycle * static_cast<uint32_t>(S);
+      auto noise = [&](int n, double (&e)[PMAX]) {
+        const size_t off = static_cast<size_t>(n) * nx + ch.start;
+        double w[PMAX];
+        pcn_cells<PMAX, FULL>(A.seed, static_cast<uint32_t>(p), step0 + static_cast<uint32_t>(n),
+                              w3, ch, A.rho, srho, sdt, cur + off, w);
+#pragma unroll
+        for (int jj = 0; jj < PMAX; ++jj)
+          if (FULL || jj < ch.cnt) prop[off + jj] = w[jj];
+        matern_add<PMAX, NT, FULL>(A.M, w, e, ch, L, t, par);
+      };
+      st = run_window<PMAX, NT, FULL, false>(A.P, K, noise, S, m, u, ch, L, X, t, par, iters);
+    } else {
+      auto inc = [&](int n, int q) {
+        double w = prop[n * Q + q];
+        if (lam) w += lam[n * Q + q];
+        return w;
+      };
+      st = run_window<PMAX, NT, FULL, false>(A.P, K, modes_noise<PMAX, FULL>(A.P, ch, inc), S, m,
+                                             u, ch, L, X, t, par, iters);
+    }
     double girs = 0.0;  // this thread's share of the Girsanov term (after the window: not
                         // live across the solver loop)
-    if (lam) {
+    if (!MATERN && lam) {
       const double idt = 1.0 / A.P.dt;
       for (int i = t; i < S * Q; i += NT) girs += (0.5 * lam[i] * lam[i] + lam[i] * prop[i]) * idt;
     }
@@ -438,13 +581,23 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
       phin = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t, par.hs, girs);
     }
     if (st != SCH_OK || !isfinite(phin)) phin = INFINITY;
-    const double v = A.vacc[static_cast<size_t>(j) * gridDim.x + p];
+    double v;
+    if constexpr (MATERN)
+      v = uniform1(A.seed, static_cast<uint32_t>(p), A.cycle, SCH_TAG_ACCEPT << 24, w3);
+    else
+      v = A.vacc[static_cast<size_t>(j) * gridDim.x + p];
     if (phin < INFINITY) {
       const double logr = theta * (phi - phin);
       accept = logr >= 0.0 ? true : metropolis_below(v, logr);
     }
     if (accept) {
-      for (int i = t; i < S * Q; i += NT) cur[i] = prop[i];
+      if constexpr (MATERN) {
+        double* tmp = cur;
+        cur = prop;
+        prop = tmp;
+      } else {
+        for (int i = t; i < S * Q; i += NT) cur[i] = prop[i];
+      }
       if constexpr (AuxLds<PMAX, NT>::kInLds) {
         double* me = A.m_end + static_cast<size_t>(p) * nx;
         double* ue = A.u_end + static_cast<size_t>(p) * nx;
@@ -461,14 +614,43 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     }
     __syncthreads();
   }
-  if (acc > 0)
-    for (int i = t; i < S * Q; i += NT) dWp[i] = cur[i];
+  if constexpr (MATERN) {
+    // the accepted increments sit in the stage row after an odd number of
+    // swaps: each thread copies its own cells back
+    if (cur != dWp)
+      for (int n = 0; n < S; ++n) {
+        const size_t off = static_cast<size_t>(n) * nx + ch.start;
+#pragma unroll
+        for (int jj = 0; jj < PMAX; ++jj)
+          if (FULL || jj < ch.cnt) dWp[off + jj] = cur[off + jj];
+      }
+  } else {
+    if (acc > 0)
+      for (int i = t; i < S * Q; i += NT) dWp[i] = cur[i];
+  }
   if (t == 0) {
     A.phi[p] = phi;
     if (A.n_accept) A.n_accept[p] = acc;
     if (A.accept_acc) atomicAdd(A.accept_acc, static_cast<unsigned long long>(acc));
     if (A.iters_acc) atomicAdd(A.iters_acc, static_cast<unsigned long long>(iters));
   }
+}
+
+// Matern-type noise fields of n rows of cell increments (one workgroup per
+// row): out = Delta U_k of matern_add.
+template <int PMAX, int NT, bool FULL>
+__global__ void __launch_bounds__(NT) k_matern_field(const StepParams P, const MaternDev M,
+                                                     const double* cells, double* out) {
+  __shared__ RowLds<NT> L;
+  const int p = blockIdx.x, t = threadIdx.x;
+  const Chunk ch = chunk_of<NT>(P.nx, t);
+  double w[PMAX], e[PMAX];
+  load_chunk<PMAX, FULL>(cells + static_cast<size_t>(p) * P.nx, ch, w);
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) e[j] = 0.0;
+  Parity par;
+  matern_add<PMAX, NT, FULL>(M, w, e, ch, L, t, par);
+  store_chunk<PMAX, FULL>(out + static_cast<size_t>(p) * P.nx, ch, e);
 }
 
 // u = H^{-1} M m (mode 0) or m = M^{-1} H u (mode 1) for every particle.

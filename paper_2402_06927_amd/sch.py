@@ -55,6 +55,10 @@ class SchRngC(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("cycle", C.c_uint32), ("temper_k", C.c_uint32)]
 
 
+class SchMaternC(C.Structure):
+    _fields_ = [("kappa", C.c_double), ("eta", C.c_double), ("k", C.c_int32)]
+
+
 class SchCycleStats(C.Structure):
     _fields_ = [
         ("ess", C.c_double), ("resampled", C.c_int32), ("n_temper", C.c_int32),
@@ -104,6 +108,7 @@ def _declare(L):
     i32, u32, u64, i64, f64 = C.c_int32, C.c_uint32, C.c_uint64, C.c_int64, C.c_double
     M, O, R = C.POINTER(SchModelC), C.POINTER(SchObsC), C.POINTER(SchRngC)
     ST = C.POINTER(SchCycleStats)
+    MT = C.POINTER(SchMaternC)
     sig = {
         "sch_last_error": (C.c_char_p, []),
         "sch_version": (C.c_int, []),
@@ -159,6 +164,13 @@ def _declare(L):
         "sch_timing_reset": (C.c_int, []),
         "sch_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
+        "sch_matern_field": (C.c_int, [M, MT, i32, _vp, _vp, _vp]),
+        "sch_ensemble_step_matern": (C.c_int, [M, MT, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "sch_matern_workspace_bytes": (C.c_size_t, [i32, M, i32, i32, i32]),
+        "sch_jitter_pcn_matern": (C.c_int, [M, MT, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                            _vp, f64, i32, _vp, _vp, _vp]),
+        "sch_pf_tempered_cycle_matern": (C.c_int, [M, MT, O, u64, u32, i32, i32, f64, i32, f64,
+                                                   i32, i32, _vp, _vp, _vp, ST, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -180,7 +192,8 @@ def exported_names():
         "sch_mlp_colstats", "sch_mlp_encode", "sch_mlp_targets", "sch_mlp_controls",
         "sch_pf_tempered_cycle", "sch_nudged_workspace_bytes", "sch_pf_nudged_cycle",
         "sch_tune_set", "sch_tune_get", "sch_timing_enable", "sch_timing_reset",
-        "sch_timing_read",
+        "sch_timing_read", "sch_matern_field", "sch_ensemble_step_matern",
+        "sch_matern_workspace_bytes", "sch_jitter_pcn_matern", "sch_pf_tempered_cycle_matern",
     ]
 
 
@@ -377,6 +390,80 @@ def sch_pf_tempered_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torc
                                        max_temper, _dev(m, name="m"), _dev(u, name="u"),
                                        _dev(workspace, torch.uint8, "workspace"), C.byref(st),
                                        _stream()))
+    return st.as_dict()
+
+
+# --------------------------------------------------------------------------- Matern noise
+@dataclass
+class Matern:
+    """Matern-type noise of section 2 (eq. noise_solve2): k solves with
+    M + kappa^-2 K on the DG0 white noise, amplitude eta."""
+    kappa: float = 1.0
+    eta: float = 1.0
+    k: int = 3
+
+    def c(self) -> SchMaternC:
+        return SchMaternC(self.kappa, self.eta, self.k)
+
+
+def sch_matern_field(model: Model, mt: Matern, dWc: torch.Tensor, dU: torch.Tensor):
+    mc, tc = model.c(), mt.c()
+    _check(lib().sch_matern_field(C.byref(mc), C.byref(tc), dWc.shape[0], _dev(dWc, name="dWc"),
+                                  _dev(dU, name="dU"), _stream()))
+
+
+def sch_ensemble_step_matern(model: Model, mt: Matern, m: torch.Tensor, u: torch.Tensor,
+                             dWc: torch.Tensor, status: torch.Tensor | None = None,
+                             iters: torch.Tensor | None = None):
+    mc, tc = model.c(), mt.c()
+    n, s = dWc.shape[0], dWc.shape[1]
+    _check(lib().sch_ensemble_step_matern(C.byref(mc), C.byref(tc), n, s, _dev(m, name="m"),
+                                          _dev(u, name="u"), _dev(dWc, name="dWc"),
+                                          _dev(status, torch.int32, "status"),
+                                          _dev(iters, torch.int32, "iters"), _stream()))
+
+
+def matern_workspace(which: int, model: Model, n_particles: int, n_steps: int, n_jitter: int,
+                     device="cuda") -> torch.Tensor:
+    mc = model.c()
+    nb = int(lib().sch_matern_workspace_bytes(which, C.byref(mc), n_particles, n_steps, n_jitter))
+    if nb <= 0:
+        raise SchError(SCH_E_ARG, "invalid workspace request")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def sch_jitter_pcn_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
+                          temper_k: int, m0: torch.Tensor, u0: torch.Tensor, dWc: torch.Tensor,
+                          phi: torch.Tensor, m_end: torch.Tensor, u_end: torch.Tensor,
+                          theta: torch.Tensor, rho: float, n_jitter: int,
+                          n_accept: torch.Tensor | None = None,
+                          workspace: torch.Tensor | None = None):
+    mc, tc, oc = model.c(), mt.c(), obs.c()
+    r = SchRngC(seed, cycle, temper_k)
+    n, s = dWc.shape[0], dWc.shape[1]
+    if workspace is None:
+        workspace = matern_workspace(WS_JITTER, model, n, s, n_jitter)
+    _check(lib().sch_jitter_pcn_matern(C.byref(mc), C.byref(tc), C.byref(oc), C.byref(r), n, s,
+                                       _dev(m0, name="m0"), _dev(u0, name="u0"),
+                                       _dev(dWc, name="dWc"), _dev(phi, name="phi"),
+                                       _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
+                                       _dev(theta, name="theta"), rho, n_jitter,
+                                       _dev(n_accept, torch.int32, "n_accept"),
+                                       _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_pf_tempered_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
+                                 m: torch.Tensor, u: torch.Tensor, n_steps: int,
+                                 ess_threshold: float, n_bisect: int, rho: float, n_jitter: int,
+                                 max_temper: int, workspace: torch.Tensor) -> dict:
+    mc, tc, oc = model.c(), mt.c(), obs.c()
+    st = SchCycleStats()
+    _check(lib().sch_pf_tempered_cycle_matern(C.byref(mc), C.byref(tc), C.byref(oc), seed, cycle,
+                                              m.shape[0], n_steps, ess_threshold, n_bisect, rho,
+                                              n_jitter, max_temper, _dev(m, name="m"),
+                                              _dev(u, name="u"),
+                                              _dev(workspace, torch.uint8, "workspace"),
+                                              C.byref(st), _stream()))
     return st.as_dict()
 
 

@@ -49,6 +49,12 @@ class Workload:
     picard_tol: float = 1e-13
     picard_max: int = 50
     seed: int = MASTER_SEED
+    # noise: "modes" (dU = sum_q xi_q dW_q) or "matern" (section 2: k solves
+    # with M + kappa^-2 K on the DG0 white noise, amplitude eta)
+    noise: str = "modes"
+    kappa: float = 1.0
+    eta: float = 1.0
+    k_solves: int = 3
 
     @property
     def h(self) -> float:
@@ -89,7 +95,14 @@ PAPER_SHAPE = Workload(
     n_obs=80, sigma_obs=math.sqrt(0.5), filter="tempered", ess_frac=80.0 / 150.0,
     rho=(2.0 - 0.15) / (2.0 + 0.15))
 
-WORKLOADS = {w.name: w for w in (BOOTSTRAP_256, TEMPERED_4096, NUDGING_2048, PAPER_SHAPE)}
+# The tempered + jittered filter of TEMPERED_4096 with the paper's own noise:
+# the Matern-type field of section 2 with eta = 1, k = 3 and kappa = 1 (the
+# operator of the paper's initial-condition smoothing), nx = 4096 cell
+# increments per step.
+MATERN_4096 = replace(TEMPERED_4096, name="tempered_matern_nx4096_np1024", noise="matern")
+
+WORKLOADS = {w.name: w for w in (BOOTSTRAP_256, TEMPERED_4096, NUDGING_2048, PAPER_SHAPE,
+                                 MATERN_4096)}
 
 
 def node_positions(L: float, nx: int) -> np.ndarray:
