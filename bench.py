@@ -50,9 +50,12 @@ def matern_flops_per_node_step(k: int, pcn: bool) -> int:
 # HBM traffic of one k_jitter launch at this workload from two rocprofv3
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
 # 1 GiB copy), valid for the kernel sources with the hash below.
-TRAFFIC_JITTER_BYTES = (195659.53125 * 2.0 + 258374.703125 * 1.0) * 1024
+TRAFFIC_JITTER_BYTES = (200530.96875 * 2.0 + 259847.546875 * 1.0) * 1024
+# the same for the jitter kernel with the Matern-type noise (cells read and
+# proposals written per step)
+TRAFFIC_JITTER_MATERN_BYTES = (7622564.75 * 2.0 + 7562449.546875 * 1.0) * 1024
 TRAFFIC_THREADS = 256
-TRAFFIC_SOURCES_HASH = "3f0c081632e9d6ef"
+TRAFFIC_SOURCES_HASH = "f2d00e4df46b00e8"
 
 
 def kernel_sources_hash() -> str:
@@ -791,9 +794,9 @@ def main():
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(j_tflops / PEAK_FP64_TFLOPS, 4),
-        "traffic": (TRAFFIC_JITTER_BYTES if kernel_sources_hash() == TRAFFIC_SOURCES_HASH
-                    and not matern and wl.nx == 4096 and n == 1024
-                    and tuned == TRAFFIC_THREADS else None),
+        "traffic": ((TRAFFIC_JITTER_MATERN_BYTES if matern else TRAFFIC_JITTER_BYTES)
+                    if kernel_sources_hash() == TRAFFIC_SOURCES_HASH and wl.nx == 4096
+                    and n == 1024 and tuned == TRAFFIC_THREADS else None),
         "kernel": ("k_jitter<Matern> (pCN proposal drawn per cell + noise field + window "
                    "rerun + likelihood + accept)" if matern else
                    "k_jitter (fused pCN proposal + window rerun + likelihood + accept)"),
