@@ -154,6 +154,11 @@ def _declare(L):
                                          _dp, _ip, _ip, _ip, _ip, C.c_int32]),
         "orc_nudged_potential": (C.c_double, [C.c_double, C.c_int32, C.c_double, _dp, _dp]),
         "orc_step_field": (C.c_int, [C.POINTER(OrcModel), _dp, _dp, _dp, _ip]),
+        "orc_paper_init_from": (C.c_int, [C.c_int32, C.c_double, _dp, C.c_double, C.c_double,
+                                          _dp]),
+        "orc_paper_init": (C.c_int, [C.c_int32, C.c_double, C.c_uint64, C.c_int32, C.c_int32,
+                                     _dp]),
+        "orc_ensemble_stats": (None, [C.c_int32, C.c_int32, _dp, _dp, _dp]),
         "orc_matern_field": (C.c_int, [C.c_int32, C.c_double, C.POINTER(OrcMatern), _dp, _dp]),
         "orc_window_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern), C.c_int32,
                                         _dp, _dp, _dp, _ip]),
@@ -768,3 +773,28 @@ def tempered_cycle_matern(model: Model, mt: OrcMatern, y, sigma, seed, cycle, m,
                                          _d(dWc), _d(phi), C.byref(st),
                                          n_threads or n_threads_default())
     return rc, dict(m=m, u=u, m0=m0, u0=u0, dWc=dWc, phi=phi), st
+
+
+# --------------------------------------------------------------------------- section 4
+def paper_init_from(nx, L, W, alpha, beta):
+    """Initial velocity of eq. init_solve from the cell values W [nx] and alpha, beta."""
+    u = np.zeros(nx)
+    st = lib().orc_paper_init_from(nx, L, _d(_f64(W)), alpha, beta, _d(u))
+    assert st == ORC_OK, st
+    return u
+
+
+def paper_init(nx, L, seed, n, p0=0):
+    """Rows p0 .. p0 + n - 1 of the paper's initial ensemble (Philox tag INIT)."""
+    u = np.zeros((n, nx))
+    st = lib().orc_paper_init(nx, L, seed, p0, n, _d(u))
+    assert st == ORC_OK, st
+    return u
+
+
+def ensemble_stats(u, ua):
+    """(EMRE, RB, RES) of the ensemble u [n][nx] against the truth ua [nx]."""
+    u = _f64(np.atleast_2d(u))
+    out = np.zeros(3)
+    lib().orc_ensemble_stats(u.shape[0], u.shape[1], _d(u), _d(_f64(ua)), _d(out))
+    return out

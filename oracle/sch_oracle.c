@@ -1887,3 +1887,72 @@ int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t
   free(acc);
   return rc;
 }
+
+/* ========================================================================== */
+/* The paper's twin experiments (section 4).                                  */
+/* ========================================================================== */
+/* Initial velocity of eq. init_solve from given draws: W [nx] holds the DG0
+ * cell values (N(0, h) samples), U^{0,1} solves (I - d_xx) U = |W| in the P1
+ * weak form, (M + K) U_1 = b with b_n = (|W|, phi_n) = h (|W_{n-1}| + |W_n|)
+ * / 2, then (M + K) U_{j+1} = M U_j twice; u = alpha^2 U^{0,3} + beta^2.  This
+ * is the Matern-type field with kappa = 1, k = 3 and eta sqrt(h) = h. */
+int orc_paper_init_from(int32_t nx, double L, const double *W, double alpha, double beta,
+                        double *u) {
+  double h = L / nx;
+  orc_matern mt = {1.0, sqrt(h), 3};
+  double *aw = (double *)calloc((size_t)nx, sizeof(double));
+  for (int32_t i = 0; i < nx; ++i) aw[i] = fabs(W[i]);
+  int st = orc_matern_field(nx, L, &mt, aw, u);
+  for (int32_t i = 0; i < nx; ++i) u[i] = alpha * alpha * u[i] + beta * beta;
+  free(aw);
+  return st;
+}
+
+/* Particles p0 .. p0 + n - 1 of the paper's initial ensemble: the cell values
+ * W_i = sqrt(h) z with z from tag INIT, counter (p, 0, pair | tag << 24, 0)
+ * (cells 2k, 2k+1 share a block), and (alpha, beta) the pair of counter
+ * (p, 1, tag << 24, 0).  u [n][nx]. */
+int orc_paper_init(int32_t nx, double L, uint64_t seed, int32_t p0, int32_t n, double *u) {
+  double h = L / nx;
+  double *W = (double *)malloc(sizeof(double) * (size_t)nx);
+  int st = ORC_OK;
+  for (int32_t p = 0; p < n && st == ORC_OK; ++p) {
+    orc_draw_increments_rows(seed, p0 + p, 1, 1, nx, 0u, ORC_TAG_INIT, 0u, h, W);
+    double ab[2];
+    orc_normal_pair(seed, (uint32_t)(p0 + p), 1u, (uint32_t)ORC_TAG_INIT << 24, 0u, ab);
+    st = orc_paper_init_from(nx, L, W, ab[0], ab[1], u + (size_t)p * nx);
+  }
+  free(W);
+  return st;
+}
+
+/* Ensemble statistics of section 4 against the truth ua [nx], with the nodal
+ * Euclidean norm: out[0] = EMRE = (1/N) sum_n |ua - u_n| / |ua|,
+ * out[1] = RB = |ua - mean_n u_n| / |ua|,
+ * out[2] = RES = (1/(N-1)) sum_n |u_n - mean u| / |ua| (N > 1; 0 for N = 1). */
+void orc_ensemble_stats(int32_t n, int32_t nx, const double *u, const double *ua, double *out) {
+  double *mean = (double *)calloc((size_t)nx, sizeof(double));
+  for (int32_t p = 0; p < n; ++p)
+    for (int32_t i = 0; i < nx; ++i) mean[i] += u[(size_t)p * nx + i];
+  for (int32_t i = 0; i < nx; ++i) mean[i] /= n;
+  long double na = 0.0L, nb = 0.0L, se = 0.0L, ss = 0.0L;
+  for (int32_t i = 0; i < nx; ++i) {
+    na += (long double)ua[i] * ua[i];
+    nb += (long double)(ua[i] - mean[i]) * (ua[i] - mean[i]);
+  }
+  for (int32_t p = 0; p < n; ++p) {
+    long double a = 0.0L, b = 0.0L;
+    for (int32_t i = 0; i < nx; ++i) {
+      double d = ua[i] - u[(size_t)p * nx + i], e = u[(size_t)p * nx + i] - mean[i];
+      a += (long double)d * d;
+      b += (long double)e * e;
+    }
+    se += sqrtl(a);
+    ss += sqrtl(b);
+  }
+  long double nrm = sqrtl(na);
+  out[0] = (double)(se / n / nrm);
+  out[1] = (double)(sqrtl(nb) / nrm);
+  out[2] = n > 1 ? (double)(ss / (n - 1) / nrm) : 0.0;
+  free(mean);
+}

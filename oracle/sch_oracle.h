@@ -232,6 +232,12 @@ int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t
                               double *dWc_out, double *phi_out, orc_cycle_stats *st,
                               int32_t n_threads);
 
+/* ---- the paper's twin experiments: initialisation and statistics ---- */
+int orc_paper_init_from(int32_t nx, double L, const double *W, double alpha, double beta,
+                        double *u);
+int orc_paper_init(int32_t nx, double L, uint64_t seed, int32_t p0, int32_t n, double *u);
+void orc_ensemble_stats(int32_t n, int32_t nx, const double *u, const double *ua, double *out);
+
 #ifdef __cplusplus
 }
 #endif
