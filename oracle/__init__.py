@@ -137,6 +137,10 @@ def _declare(L):
         "orc_bootstrap_cycle": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_uint64,
                                           C.c_uint32, C.c_int32, C.c_int32, C.c_double, _dp, _dp,
                                           _dp, C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_bootstrap_cycle_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern),
+                                                 C.c_int32, _dp, _dp, C.c_uint64, C.c_uint32,
+                                                 C.c_int32, C.c_int32, C.c_double, _dp, _dp, _dp,
+                                                 C.POINTER(OrcCycleStats), C.c_int32]),
         "orc_tempered_cycle": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_uint64,
                                          C.c_uint32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                          C.c_double, C.c_int32, C.c_int32, _dp, _dp,
@@ -751,6 +755,21 @@ def jitter_pcn_matern(model: Model, mt: OrcMatern, y, sigma, seed, cycle, temper
                                 _d(u_end), theta, rho, n_jitter, _i(acc),
                                 n_threads or n_threads_default())
     return dWc, phi, m_end, u_end, acc
+
+
+def bootstrap_cycle_matern(model: Model, mt: OrcMatern, y, sigma, seed, cycle, m, u, logw,
+                           n_steps, ess_frac=0.5, n_threads=None):
+    """bootstrap_cycle with the Matern-type noise; returns (rc, m, u, logw, stats)."""
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    logw = np.array(logw, dtype=np.float64, copy=True)
+    st = OrcCycleStats()
+    cm = model.c()
+    rc = lib().orc_bootstrap_cycle_matern(C.byref(cm), C.byref(mt), len(y), _d(y), _d(sg), seed,
+                                          cycle, m.shape[0], n_steps, ess_frac, _d(m), _d(u),
+                                          _d(logw), C.byref(st), n_threads or n_threads_default())
+    return rc, m, u, logw, st
 
 
 def tempered_cycle_matern(model: Model, mt: OrcMatern, y, sigma, seed, cycle, m, u, n_steps,

@@ -1016,11 +1016,13 @@ static void gather_rows(double *a, const int32_t *idx, int32_t n, size_t row) {
  * multiply its weight by the likelihood, and resample (systematic) when the
  * ESS falls below ess_frac * N (the paper's N_p* threshold, eq. ess).  Between
  * resamplings the normalised log-weights are carried in logw. */
-int orc_bootstrap_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
-                        uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
-                        double ess_frac, double *m, double *u, double *logw,
-                        orc_cycle_stats *st, int32_t n_threads) {
-  int32_t nx = md->nx, nq = md->n_modes;
+/* The bootstrap cycle with the modes-form noise (mt == NULL) or the
+ * Matern-type noise (mt != NULL: nx cell increments per step). */
+static int bootstrap_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                           const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
+                           int32_t n_particles, int32_t n_steps, double ess_frac, double *m,
+                           double *u, double *logw, orc_cycle_stats *st, int32_t n_threads) {
+  int32_t nx = md->nx, nq = mt ? md->nx : md->n_modes;
   double *dW = (double *)malloc(sizeof(double) * (size_t)n_particles * n_steps * nq);
   int32_t *iters = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   int32_t *stat = (int32_t *)malloc(sizeof(int32_t) * n_particles);
@@ -1031,7 +1033,10 @@ int orc_bootstrap_cycle(const orc_model *md, int32_t n_obs, const double *y, con
 
   orc_draw_increments(seed, n_particles, n_steps, nq, cycle * (uint32_t)n_steps, ORC_TAG_FORECAST,
                       0u, md->dt, dW);
-  orc_ensemble_window(md, n_particles, n_steps, m, u, dW, NULL, stat, iters, n_threads);
+  if (mt)
+    orc_ensemble_window_matern(md, mt, n_particles, n_steps, m, u, dW, stat, iters, n_threads);
+  else
+    orc_ensemble_window(md, n_particles, n_steps, m, u, dW, NULL, stat, iters, n_threads);
   for (int32_t p = 0; p < n_particles; ++p) {
     st->picard_iters += iters[p];
     phi[p] = stat[p] == ORC_OK ? orc_nll(nx, n_obs, u + (size_t)p * nx, y, sigma) : INFINITY;
@@ -1060,6 +1065,23 @@ int orc_bootstrap_cycle(const orc_model *md, int32_t n_obs, const double *y, con
   free(w);
   free(idx);
   return rc;
+}
+
+int orc_bootstrap_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                        uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                        double ess_frac, double *m, double *u, double *logw,
+                        orc_cycle_stats *st, int32_t n_threads) {
+  return bootstrap_cycle(md, NULL, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_frac,
+                         m, u, logw, st, n_threads);
+}
+
+int orc_bootstrap_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                               const double *y, const double *sigma, uint64_t seed,
+                               uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                               double ess_frac, double *m, double *u, double *logw,
+                               orc_cycle_stats *st, int32_t n_threads) {
+  return bootstrap_cycle(md, mt, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_frac, m,
+                         u, logw, st, n_threads);
 }
 
 /* Tempered and jittered filter, section 3.1.2.  Each particle is the pair

@@ -217,7 +217,12 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
                      double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
                      double *J_out, orc_cycle_stats *st, int32_t n_threads);
 
-/* ---- tempered + jittered filter with the Matern-type noise ---- */
+/* ---- bootstrap and tempered + jittered filters with the Matern-type noise ---- */
+int orc_bootstrap_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                               const double *y, const double *sigma, uint64_t seed,
+                               uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                               double ess_frac, double *m, double *u, double *logw,
+                               orc_cycle_stats *st, int32_t n_threads);
 int orc_jitter_pcn_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
                           const double *y, const double *sigma, const orc_rng *rng,
                           int32_t n_particles, int32_t n_steps, const double *m0,

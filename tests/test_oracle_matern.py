@@ -160,3 +160,28 @@ def test_tempered_cycle_matern_consistency(orc):
     # the cell increments stay N(0, dt) under pCN (loose moment check)
     v = out["dWc"].ravel()
     assert abs(v.var() / wl.dt - 1.0) < 0.25
+
+
+def test_bootstrap_cycle_matern(orc):
+    # Without resampling (threshold 0) the cycle is the Matern window of the
+    # FORECAST draw plus the likelihood weights; with threshold 1 it resamples.
+    wl, om, m, u, y = _cycle_setup(orc)
+    mt = orc.matern()
+    n = wl.n_particles
+    rc, m1, u1, lw, st = orc.bootstrap_cycle_matern(om, mt, y, wl.sigma_obs, 5, 3, m, u,
+                                                    np.zeros(n), wl.n_steps, ess_frac=0.0)
+    assert rc == 0 and st.resampled == 0
+    cells = orc.draw_increments(5, n, wl.n_steps, wl.nx, 3 * wl.n_steps, orc.TAG_FORECAST, 0,
+                                wl.dt)
+    worst, me, ue, _, _ = orc.ensemble_window_matern(om, mt, m, u, cells)
+    assert worst == 0
+    np.testing.assert_array_equal(m1, me)
+    np.testing.assert_array_equal(u1, ue)
+    phi = orc.ensemble_nll(ue, y, wl.sigma_obs)
+    w = np.exp(-(phi - phi.min()))
+    np.testing.assert_allclose(np.exp(lw), w / w.sum(), rtol=1e-12, atol=1e-300)
+    rc, m2, u2, lw2, st2 = orc.bootstrap_cycle_matern(om, mt, y, wl.sigma_obs, 5, 3, m, u,
+                                                      np.zeros(n), wl.n_steps, ess_frac=1.01)
+    assert rc == 0 and st2.resampled == 1 and np.all(lw2 == 0)
+    for p in range(n):
+        assert any(np.array_equal(u2[p], ue[r]) for r in range(n))
