@@ -478,6 +478,102 @@ def bench_mlp(args):
     print(json.dumps(out), flush=True)
 
 
+def paper_cpu_baseline(wl, n_da: int, n_threads: int):
+    """The oracle's twin experiment (tempered + jittered, Matern noise) timed
+    on the host for n_da assimilation steps from the same initial ensemble."""
+    import oracle as O
+    from paper_2402_06927_amd import workloads as W
+
+    xi = W.mode_table(wl.L, wl.nx, wl.n_modes, wl.mode_amp)
+    om = O.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
+                 picard_tol=wl.picard_tol, picard_max=wl.picard_max)
+    omt = O.matern(wl.kappa, wl.eta, wl.k_solves)
+    n, nx, S = wl.n_particles, wl.nx, wl.n_steps
+    u = O.paper_init(nx, wl.L, wl.seed, n)
+    m = O.momentum_from_velocity(om, u)
+    ts = W.truth_seed(wl)
+    ut = O.paper_init(nx, wl.L, ts, 1)[0]
+    mt = O.momentum_from_velocity(om, ut)
+    z = W.obs_noise(wl, ts, n_da)
+    sig = W.sigma_vector(wl)
+    t0 = time.perf_counter()
+    for c in range(n_da):
+        cells = O.draw_increments(ts, 1, S, nx, c * S, O.TAG_FORECAST, 0, wl.dt)[0]
+        _, mt, ut, _ = O.window_matern(om, omt, mt, ut, cells)
+        y = O.observe(ut, wl.n_obs) + wl.sigma_obs * z[c]
+        _, out, _ = O.tempered_cycle_matern(om, omt, y, sig, wl.seed, c, m, u, S,
+                                            wl.ess_threshold, wl.n_bisect, wl.rho, wl.n_jitter,
+                                            wl.max_temper, n_threads=n_threads)
+        m, u = out["m"], out["u"]
+    dt = time.perf_counter() - t0
+    return {"value": n_da / dt, "unit": "DA steps/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"the first {n_da} assimilation steps of experiment 1 (tempered + "
+                      f"jittered, {n} particles) from the same initial ensemble, {dt:.1f} s"}
+
+
+def bench_paper(args):
+    """The paper's experiment 1 (section 4): nx = 100, 150 particles, Matern
+    noise, observations every 5 steps at 80 points, tempering + jittering;
+    args.steps assimilation steps timed after args.warmup untimed ones."""
+    import torch
+
+    from paper_2402_06927_amd import experiments as E
+    from paper_2402_06927_amd import sch
+    from paper_2402_06927_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    sch.lib()
+    wl = W.PAPER_SHAPE if args.exp == 1 else W.PAPER_HALF
+    if args.warmup:
+        E.run_twin(wl, "tempered", args.warmup)
+    sch.sch_timing_reset()
+    sch.sch_timing_enable(True)
+    r = E.run_twin(wl, "tempered", args.steps)
+    sch.sch_timing_enable(False)
+    tim = sch.sch_timing_read()
+    rb = E.run_twin(wl, "bootstrap", args.steps)
+    summ, summ_b = E.summary(r), E.summary(rb)
+    log(f"tempered: {summ}")
+    log(f"bootstrap: {summ_b}")
+    jt = tim["jitter"]
+    j_launches = max(jt["launches"], 1)
+    n, nx, S = wl.n_particles, wl.nx, wl.n_steps
+    j_psteps = j_launches * n * S * wl.n_jitter
+    j_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"]
+                    + matern_flops_per_node_step(wl.k_solves, True) * j_psteps)
+    j_ms = jt["ms"] / j_launches
+    j_tflops = (j_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
+    out = {
+        "metric": "assimilation steps/sec of the paper's experiment 1 (tempered + jittered)",
+        "value": round(args.steps / r["seconds"], 3),
+        "unit": "DA steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["seconds"] / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "filter": "tempered+jittered", "nx": nx,
+                   "n_particles": n, "n_steps": S, "n_obs": wl.n_obs,
+                   "n_observed": wl.n_observed or wl.n_obs, "sigma_obs": wl.sigma_obs,
+                   "ess_threshold": wl.ess_threshold, "n_jitter": wl.n_jitter, "rho": wl.rho,
+                   "noise": "matern", "kappa": wl.kappa, "eta": wl.eta, "k_solves": wl.k_solves},
+        "statistics": {"tempered": summ, "bootstrap": summ_b},
+        "kernel_ms": {k: round(v["ms"], 3) for k, v in tim.items()},
+        "roofline": {
+            "bound": "alu", "achieved": round(j_tflops, 4), "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(j_tflops / PEAK_FP64_TFLOPS, 5), "traffic": None,
+            "kernel": "k_jitter<Matern> at nx = 100 (150 workgroups: under one per CU)",
+            "avg_launch_ms": round(j_ms, 4),
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = paper_cpu_baseline(wl, min(args.steps, 40), threads)
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """64 independent bootstrap filters of uneven sizes (grids log-uniform in
     [512, 8192], ensembles log-uniform in [64, 2048]; physics of the Nx = 256
@@ -640,16 +736,19 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--workload", choices=("tempered", "matern", "nudging", "nudged",
+    ap.add_argument("--workload", choices=("tempered", "matern", "paper", "nudging", "nudged",
                                            "warmstart", "mlp", "batch"),
                     default="tempered",
                     help="tempered: the headline filter; matern: the same filter with the "
-                         "Matern-type noise of section 2; nudging: one nudged window; "
+                         "Matern-type noise of section 2; paper: the paper's twin experiment "
+                         "(--exp 1 or 2); nudging: one nudged window; "
                          "nudged: the nudged filter (nudging, tempering, jittering); "
                          "warmstart: plain vs learned warm-start nudging; mlp: the "
                          "warm-start network; batch: 64 uneven filters in one graph")
     ap.add_argument("--threads", type=int, default=0,
                     help="threads per particle of the model kernels (0 = automatic)")
+    ap.add_argument("--exp", type=int, choices=(1, 2), default=1,
+                    help="paper workload: 1 full domain observed, 2 half domain")
     ap.add_argument("--train-windows", type=int, default=4)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -670,6 +769,9 @@ def main():
         from paper_2402_06927_amd import sch as _sch
 
         _sch.sch_tune_set(_sch.TUNE_THREADS, args.threads)
+    if args.workload == "paper":
+        bench_paper(args)
+        return
     if args.workload == "nudging":
         bench_nudging(args)
         return

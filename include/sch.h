@@ -98,6 +98,8 @@ typedef struct sch_cycle_stats {
   int64_t n_accept;      /* tempered: pCN acceptances summed over the cycle       */
   int64_t particle_steps;/* model steps integrated (all particles, all windows)   */
   int32_t status;        /* SCH_OK or the first error met                         */
+  int32_t n_failed;      /* particles whose forecast window failed (not converged */
+                         /* or non-finite): weight zero, replaced when resampled  */
 } sch_cycle_stats;
 
 /* Message about the last failure on the calling thread ("" if none). */
@@ -337,6 +339,11 @@ int sch_nudge_run(const sch_model *model, const sch_obs *obs, int32_t n_particle
  * state; uniform counter (0, cycle, tag << 24, k << 16)) and apply n_jitter
  * pCN moves at the new temperature.  At most max_temper steps
  * (SCH_E_DEGENERATE beyond).  On return m, u hold the window-end states.
+ *
+ * In both cycles a particle whose forecast window fails (not converged or
+ * non-finite) gets phi = +infinity, i.e. zero weight, and is replaced at the
+ * next resampling; stats->n_failed counts such particles and the call still
+ * succeeds.  SCH_E_DEGENERATE only when every weight vanishes.
  * ------------------------------------------------------------------------ */
 int sch_pf_bootstrap_cycle(const sch_model *model, const sch_obs *obs, uint64_t seed,
                            uint32_t cycle, int32_t n_particles, int32_t n_steps, double ess_frac,
@@ -412,8 +419,8 @@ int sch_ensemble_step_matern(const sch_model *model, const sch_matern *mt, int32
                              int32_t n_steps, double *m, double *u, const double *dWc,
                              int32_t *status, int32_t *iters, void *stream);
 
-/* Workspace of the two calls below: which = SCH_WS_JITTER or SCH_WS_TEMPERED
- * (0 for anything else or invalid sizes). */
+/* Workspace of the Matern-noise jitter and cycles: which = SCH_WS_JITTER,
+ * SCH_WS_TEMPERED or SCH_WS_BOOTSTRAP (0 for anything else or invalid sizes). */
 size_t sch_matern_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
                                   int32_t n_steps, int32_t n_jitter);
 
@@ -428,6 +435,17 @@ int sch_jitter_pcn_matern(const sch_model *model, const sch_matern *mt, const sc
                           double *m_end, double *u_end, const double *theta, double rho,
                           int32_t n_jitter, int32_t *n_accept, void *workspace, void *stream);
 
+/* sch_pf_bootstrap_cycle with the Matern-type noise: cell increments drawn as
+ * sch_draw_increments with nx values per step (tag FORECAST), the Matern
+ * window, likelihood weights and conditional resampling as
+ * sch_pf_bootstrap_cycle.  workspace >=
+ * sch_matern_workspace_bytes(SCH_WS_BOOTSTRAP, model, n, n_steps, 0). */
+int sch_pf_bootstrap_cycle_matern(const sch_model *model, const sch_matern *mt,
+                                  const sch_obs *obs, uint64_t seed, uint32_t cycle,
+                                  int32_t n_particles, int32_t n_steps, double ess_frac,
+                                  double *m, double *u, double *logw, void *workspace,
+                                  sch_cycle_stats *stats, void *stream);
+
 /* sch_pf_tempered_cycle with the Matern-type noise: the window's cell
  * increments are drawn as sch_draw_increments with nx values per step (tag
  * FORECAST), the tempering, resampling and jittering as sch_pf_tempered_cycle
@@ -439,6 +457,33 @@ int sch_pf_tempered_cycle_matern(const sch_model *model, const sch_matern *mt,
                                  int32_t n_bisect, double rho, int32_t n_jitter,
                                  int32_t max_temper, double *m, double *u, void *workspace,
                                  sch_cycle_stats *stats, void *stream);
+
+/* --------------------------------------------------------------------------
+ * The paper's twin experiments (section 4).
+ *
+ * sch_paper_init -- the initial ensemble of eq. init_solve: per particle p,
+ * DG0 cell values W_i = sqrt(h) z_i ~ N(0, h) (tag INIT, counter
+ * (p, 0, pair | tag << 24, 0), cells 2k and 2k + 1 sharing a block), then
+ * U^{0,1} solves (I - d_xx) U = |W| in the P1 weak form ((M + K) U_1 = b,
+ * b_i = h (|W_{i-1}| + |W_i|) / 2) and U^{0,j+1} = (M + K)^{-1} M U^{0,j} for
+ * j = 1, 2; with (alpha, beta) the two normals of counter (p, 1, tag << 24, 0)
+ * the velocity is u_p = alpha^2 U^{0,3} + beta^2.  The truth is drawn the same
+ * way (the experiments give it its own seed).
+ *   u  out [n][nx]; the momenta follow from sch_init_momentum.
+ *
+ * sch_ensemble_stats -- the statistics of section 4 of the ensemble u [n][nx]
+ * against the truth ua [nx], with the nodal Euclidean norm |.|:
+ *   out[0] EMRE = (1/n) sum_p |ua - u_p| / |ua|
+ *   out[1] RB   = |ua - mean_p u_p| / |ua|
+ *   out[2] RES  = (1/(n-1)) sum_p |u_p - mean_p u_p| / |ua|   (0 for n = 1)
+ *   workspace  device, at least (nx + 2 n) doubles;  out device [3].
+ * Experiment 2 observes half the domain: give the unobserved points of the
+ * observation grid sigma = +inf (they then add nothing to any likelihood).
+ * ------------------------------------------------------------------------ */
+int sch_paper_init(const sch_model *model, uint64_t seed, int32_t n_particles, double *u,
+                   void *stream);
+int sch_ensemble_stats(int32_t n_particles, int32_t nx, const double *u, const double *ua,
+                       double *workspace, double *out, void *stream);
 
 /* --------------------------------------------------------------------------
  * Batched runner: many independent bootstrap filters (sch_pf_bootstrap_cycle

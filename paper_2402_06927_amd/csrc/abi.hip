@@ -410,11 +410,7 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
   stats->picard_iters = static_cast<int64_t>(acc[0] + acc[2]);
   stats->n_accept = static_cast<int64_t>(acc[1]);
   stats->particle_steps = psteps;
-  for (int p = 0; p < n && rc == SCH_OK; ++p)
-    if (status[p] != SCH_OK) {
-      rc = status[p];
-      fail(rc, "a particle failed in the forecast of cycle %u", cycle);
-    }
+  for (int p = 0; p < n; ++p) stats->n_failed += status[p] != SCH_OK;
   stats->status = rc;
   return rc;
 }
@@ -689,18 +685,18 @@ int sch_nudge_run(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_s
 // ---------------------------------------------------------------------------
 // Filter cycles.
 // ---------------------------------------------------------------------------
-int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
-                           int32_t n, int32_t n_steps, double ess_frac, double* m, double* u,
-                           double* logw, void* workspace, sch_cycle_stats* stats,
-                           void* stream) {
-  Tile tl;
-  if (int rc = check_model(md, tl)) return rc;
-  if (int rc = check_obs(ob)) return rc;
-  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !logw || !workspace || !stats)
-    return fail(SCH_E_ARG, "bad arguments to sch_pf_bootstrap_cycle");
+}  // extern "C"
+
+namespace {
+// The bootstrap cycle of section 3.1.1 with the modes-form noise (M == null)
+// or the Matern-type noise (M != null: nx cell increments per step).
+int bootstrap_cycle(const sch_model* md, const Tile& tl, const sch_obs* ob, uint64_t seed,
+                    uint32_t cycle, int32_t n, int32_t n_steps, double ess_frac, double* m,
+                    double* u, double* logw, void* workspace, sch_cycle_stats* stats,
+                    void* stream, const MaternDev* M) {
   hipStream_t st = S(stream);
-  const int nx = md->nx, Q = md->n_modes;
-  CycleWs W = carve_cycle(workspace, SCH_WS_BOOTSTRAP, nx, Q, n, n_steps, nullptr);
+  const int nx = md->nx, Q = M ? md->nx : md->n_modes;
+  CycleWs W = carve_cycle(workspace, SCH_WS_BOOTSTRAP, nx, Q, n, n_steps, nullptr, 0, M ? 1 : 0);
   *stats = sch_cycle_stats{};
   sch_rng rg{seed, cycle, 0};
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
@@ -711,12 +707,15 @@ int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed
   }
   {
     TimedScope ts(SCH_TK_WINDOW, st);
-    if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
+    if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc,
+                               st, M))
       return rc;
   }
   {
     TimedScope ts(SCH_TK_OTHER, st);
     if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+    hipLaunchKernelGGL(k_mask_failed, dim3(grid_for(n, 256)), dim3(256), 0, st, n, W.status,
+                       W.phi);
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
   }
   {
@@ -738,8 +737,7 @@ int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed
   stats->picard_iters = static_cast<int64_t>(its);
   stats->particle_steps = static_cast<int64_t>(n) * n_steps;
   int rc = SCH_OK;
-  for (int p = 0; p < n && rc == SCH_OK; ++p)
-    if (status[p] != SCH_OK) rc = status[p];
+  for (int p = 0; p < n; ++p) stats->n_failed += status[p] != SCH_OK;
   if (!(ess > 0.0)) {
     stats->status = SCH_E_DEGENERATE;
     return fail(SCH_E_DEGENERATE, "all weights vanished in cycle %u", cycle);
@@ -764,8 +762,23 @@ int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed
   HIP_TRY(hipStreamSynchronize(st));
   timing_flush();
   stats->status = rc;
-  if (rc != SCH_OK) return fail(rc, "a particle failed in cycle %u", cycle);
   return SCH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int sch_pf_bootstrap_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
+                           int32_t n, int32_t n_steps, double ess_frac, double* m, double* u,
+                           double* logw, void* workspace, sch_cycle_stats* stats,
+                           void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !logw || !workspace || !stats)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_bootstrap_cycle");
+  return bootstrap_cycle(md, tl, ob, seed, cycle, n, n_steps, ess_frac, m, u, logw, workspace,
+                         stats, stream, nullptr);
 }
 
 int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
@@ -803,6 +816,8 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
   {
     TimedScope ts(SCH_TK_OTHER, st);
     if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+    hipLaunchKernelGGL(k_mask_failed, dim3(grid_for(n, 256)), dim3(256), 0, st, n, W.status,
+                       W.phi);
   }
   return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
                      max_temper, m, u, nullptr, W, stats, st);
@@ -906,7 +921,7 @@ int sch_ensemble_step_matern(const sch_model* md, const sch_matern* mt, int32_t 
 size_t sch_matern_workspace_bytes(int32_t which, const sch_model* md, int32_t n, int32_t n_steps,
                                   int32_t n_jitter) {
   if (!md || n < 1 || n_steps < 1 || n_jitter < 0 ||
-      (which != SCH_WS_JITTER && which != SCH_WS_TEMPERED))
+      (which != SCH_WS_JITTER && which != SCH_WS_TEMPERED && which != SCH_WS_BOOTSTRAP))
     return 0;
   size_t bytes = 0;
   carve_cycle(nullptr, which, md->nx, md->nx, n, n_steps, &bytes, n_jitter, 1);
@@ -933,6 +948,55 @@ int sch_jitter_pcn_matern(const sch_model* md, const sch_matern* mt, const sch_o
   return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
                        dWc, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
                        W.zeta, nullptr, nullptr, S(stream), &M);
+}
+
+int sch_pf_bootstrap_cycle_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
+                                  uint64_t seed, uint32_t cycle, int32_t n, int32_t n_steps,
+                                  double ess_frac, double* m, double* u, double* logw,
+                                  void* workspace, sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !logw || !workspace || !stats)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_bootstrap_cycle_matern");
+  return bootstrap_cycle(md, tl, ob, seed, cycle, n, n_steps, ess_frac, m, u, logw, workspace,
+                         stats, stream, &M);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's twin experiments (section 4).
+// ---------------------------------------------------------------------------
+int sch_paper_init(const sch_model* md, uint64_t seed, int32_t n, double* u, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (n < 1 || n > 65535 || !u) return fail(SCH_E_ARG, "bad arguments to sch_paper_init");
+  const double h = md->L / md->nx;
+  const sch_matern smooth{1.0, std::sqrt(h), 3};  // (I - d_xx), load h/2, three solves
+  MaternDev M;
+  if (int rc = make_matern(*md, &smooth, tl, M)) return rc;
+  const StepParams P = make_params(*md);
+  return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+    hipLaunchKernelGGL((k_paper_init<PM, NT, FULL>), dim3(n), dim3(NT), 0, S(stream), P, M, seed,
+                       u);
+    CHECK_LAUNCH();
+    return SCH_OK;
+  });
+}
+
+int sch_ensemble_stats(int32_t n, int32_t nx, const double* u, const double* ua,
+                       double* workspace, double* out, void* stream) {
+  if (n < 1 || n > 65535 || nx < 1 || !u || !ua || !workspace || !out)
+    return fail(SCH_E_ARG, "bad arguments to sch_ensemble_stats");
+  hipStream_t st = S(stream);
+  double* mean = workspace;
+  double* sq = workspace + nx;
+  hipLaunchKernelGGL(k_ens_mean, dim3(grid_for(nx, 256)), dim3(256), 0, st, n, nx, u, mean);
+  hipLaunchKernelGGL(k_ens_norms, dim3(n), dim3(kWave), 0, st, nx, u, ua, mean, sq);
+  hipLaunchKernelGGL(k_ens_final, dim3(1), dim3(kWave), 0, st, n, nx, ua, mean, sq, out);
+  CHECK_LAUNCH();
+  return SCH_OK;
 }
 
 int sch_pf_tempered_cycle_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
@@ -975,6 +1039,8 @@ int sch_pf_tempered_cycle_matern(const sch_model* md, const sch_matern* mt, cons
   {
     TimedScope ts(SCH_TK_OTHER, st);
     if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+    hipLaunchKernelGGL(k_mask_failed, dim3(grid_for(n, 256)), dim3(256), 0, st, n, W.status,
+                       W.phi);
   }
   return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
                      max_temper, m, u, nullptr, W, stats, st, &M);

@@ -127,6 +127,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     store_chunk<PMAX, false>(up, ch, u);
     if (t == 0) {
       if (st != SCH_OK && B.status[g] == SCH_OK) B.status[g] = st;
+      // a failed window marks the particle for the likelihood (zero weight)
+      B.phi[g] = st == SCH_OK ? 0.0 : INFINITY;
       atomicAdd(B.acc, static_cast<unsigned long long>(iters));
     }
   }
@@ -141,6 +143,7 @@ __global__ void __launch_bounds__(kWave) k_batch_loglik(BatchDev B) {
   const int nx = D.P.nx, n_obs = D.n_obs;
   const double* up = D.u + static_cast<size_t>(p) * nx;
   const double* y = D.y + static_cast<size_t>(*B.cycle) * n_obs;
+  if (!(B.phi[g] < INFINITY)) return;  // the particle's window failed this cycle
   double acc = 0.0;
   for (int j = threadIdx.x; j < n_obs; j += kWave) {
     const double e = (p1_at(up, nx, n_obs, j) - y[j]) / D.sigma[j];

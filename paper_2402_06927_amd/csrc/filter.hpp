@@ -347,6 +347,70 @@ __global__ void k_gather(int n_rows, int64_t row_len, const int* idx, const doub
     d[i] = s[i];
 }
 
+// ---------------------------------------------------------------------------
+// Ensemble statistics of section 4 (EMRE, RB, RES) against a truth row.
+// ---------------------------------------------------------------------------
+// mean[i] = (1/n) sum_p u[p][i]
+__global__ void k_ens_mean(int n, int nx, const double* u, double* mean) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nx; i += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int p = 0; p < n; ++p) acc += u[static_cast<size_t>(p) * nx + i];
+    mean[i] = acc / n;
+  }
+}
+
+// Per particle (one wavefront each): |ua - u_p|^2 and |u_p - mean|^2.
+__global__ void __launch_bounds__(kWave) k_ens_norms(int nx, const double* u, const double* ua,
+                                                     const double* mean, double* sq) {
+  const int p = blockIdx.x;
+  const double* up = u + static_cast<size_t>(p) * nx;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nx; i += kWave) {
+    const double d = ua[i] - up[i], e = up[i] - mean[i];
+    a = fma(d, d, a);
+    b = fma(e, e, b);
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (threadIdx.x == 0) {
+    sq[2 * p] = a;
+    sq[2 * p + 1] = b;
+  }
+}
+
+// out = (EMRE, RB, RES) from the per-particle squares (one wavefront).
+__global__ void __launch_bounds__(kWave) k_ens_final(int n, int nx, const double* ua,
+                                                     const double* mean, const double* sq,
+                                                     double* out) {
+  double na = 0.0, nb = 0.0, se = 0.0, ss = 0.0;
+  for (int i = threadIdx.x; i < nx; i += kWave) {
+    const double d = ua[i] - mean[i];
+    na = fma(ua[i], ua[i], na);
+    nb = fma(d, d, nb);
+  }
+  for (int p = threadIdx.x; p < n; p += kWave) {
+    se += sqrt(sq[2 * p]);
+    ss += sqrt(sq[2 * p + 1]);
+  }
+  na = wave_sum(na);
+  nb = wave_sum(nb);
+  se = wave_sum(se);
+  ss = wave_sum(ss);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(na);
+    out[0] = se / n / nrm;
+    out[1] = sqrt(nb) / nrm;
+    out[2] = n > 1 ? ss / (n - 1) / nrm : 0.0;
+  }
+}
+
+// A particle whose window failed (status != SCH_OK) gets phi = +inf: zero
+// weight, so the next resampling replaces it.
+__global__ void k_mask_failed(int n, const int* status, double* phi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && status[i] != SCH_OK) phi[i] = INFINITY;
+}
+
 __global__ void k_fill(double* p, double v, int64_t n) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)

@@ -449,18 +449,15 @@ struct JitterArgs {
   uint32_t cycle, temper_k;
 };
 
-// pCN proposal for the chunk's cells of one step (section 3.1.2):
-// w_i = rho c_i + sqrt(1 - rho^2) sqrt(dt) z_i, the normals of cells 2k and
-// 2k + 1 from one Philox block (tag PCN, counter (c0, c1, k | tag << 24, c3)).
-// A chunk that starts at an odd cell takes the second normal of its first
-// block.
+// Standard normals of the chunk's cells from one Philox stream: cell i takes
+// component i & 1 of the block at counter (c0, c1, (i >> 1) | tag, c3), so
+// cells 2k and 2k + 1 share a block; a chunk that starts at an odd cell takes
+// the second normal of its first block.  Slots past the chunk get 0.
 template <int PMAX, bool FULL>
-__device__ __forceinline__ void pcn_cells(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c3,
-                                          const Chunk& ch, double rho, double srho, double sdt,
-                                          const double* cur, double (&w)[PMAX]) {
-  constexpr uint32_t tag = SCH_TAG_PCN << 24;
+__device__ __forceinline__ void cell_normals(uint64_t seed, uint32_t c0, uint32_t c1,
+                                             uint32_t tag, uint32_t c3, const Chunk& ch,
+                                             double (&z)[PMAX]) {
   const int s0 = ch.start;
-  double z[PMAX];
   if (!FULL && (s0 & 1)) {
     double za, zb;
     normal2(seed, c0, c1, static_cast<uint32_t>(s0 >> 1) | tag, c3, za, zb);
@@ -470,7 +467,7 @@ __device__ __forceinline__ void pcn_cells(uint64_t seed, uint32_t c0, uint32_t c
       za = zb = 0.0;
       if (j < ch.cnt) normal2(seed, c0, c1, static_cast<uint32_t>((s0 + j) >> 1) | tag, c3, za, zb);
       z[j] = za;
-      if (j + 1 < PMAX) z[j + 1] = zb;
+      if (j + 1 < PMAX) z[j + 1] = j + 1 < ch.cnt ? zb : 0.0;
     }
   } else {
 #pragma unroll
@@ -479,9 +476,19 @@ __device__ __forceinline__ void pcn_cells(uint64_t seed, uint32_t c0, uint32_t c
       if (FULL || j < ch.cnt)
         normal2(seed, c0, c1, static_cast<uint32_t>((s0 + j) >> 1) | tag, c3, za, zb);
       z[j] = za;
-      z[j + 1] = zb;
+      z[j + 1] = (FULL || j + 1 < ch.cnt) ? zb : 0.0;
     }
   }
+}
+
+// pCN proposal for the chunk's cells of one step (section 3.1.2):
+// w_i = rho c_i + sqrt(1 - rho^2) sqrt(dt) z_i, the normals of tag PCN.
+template <int PMAX, bool FULL>
+__device__ __forceinline__ void pcn_cells(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c3,
+                                          const Chunk& ch, double rho, double srho, double sdt,
+                                          const double* cur, double (&w)[PMAX]) {
+  double z[PMAX];
+  cell_normals<PMAX, FULL>(seed, c0, c1, SCH_TAG_PCN << 24, c3, ch, z);
 #pragma unroll
   for (int j = 0; j < PMAX; ++j)
     w[j] = (FULL || j < ch.cnt) ? rho * cur[j] + srho * (sdt * z[j]) : 0.0;
@@ -634,6 +641,35 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     if (A.accept_acc) atomicAdd(A.accept_acc, static_cast<unsigned long long>(acc));
     if (A.iters_acc) atomicAdd(A.iters_acc, static_cast<unsigned long long>(iters));
   }
+}
+
+// Initial velocities of the paper's experiments (section 4, eq. init_solve),
+// one workgroup per particle: DG0 cell values W_i = sqrt(h) z_i (tag INIT,
+// counter (p, 0, pair | tag << 24, 0)), U^{0,3} from |W| by matern_add with
+// M = (M + K, load h/2, k = 3), and (alpha, beta) from the block at
+// (p, 1, tag << 24, 0): u = alpha^2 U^{0,3} + beta^2.
+template <int PMAX, int NT, bool FULL>
+__global__ void __launch_bounds__(NT) k_paper_init(const StepParams P, const MaternDev M,
+                                                   uint64_t seed, double* u) {
+  __shared__ RowLds<NT> L;
+  const int p = blockIdx.x, t = threadIdx.x;
+  const Chunk ch = chunk_of<NT>(P.nx, t);
+  constexpr uint32_t tag = SCH_TAG_INIT << 24;
+  double z[PMAX], w[PMAX], e[PMAX];
+  cell_normals<PMAX, FULL>(seed, static_cast<uint32_t>(p), 0u, tag, 0u, ch, z);
+  const double sh = sqrt(P.h);
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) {
+    w[j] = fabs(sh * z[j]);
+    e[j] = 0.0;
+  }
+  Parity par;
+  matern_add<PMAX, NT, FULL>(M, w, e, ch, L, t, par);
+  double a, b;
+  normal2(seed, static_cast<uint32_t>(p), 1u, tag, 0u, a, b);
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) e[j] = a * a * e[j] + b * b;
+  store_chunk<PMAX, FULL>(u + static_cast<size_t>(p) * P.nx, ch, e);
 }
 
 // Matern-type noise fields of n rows of cell increments (one workgroup per

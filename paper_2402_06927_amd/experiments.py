@@ -1,0 +1,150 @@
+"""The paper's twin experiments (section 4) on the GPU.
+
+A truth run and an ensemble, both initialised by eq. init_solve
+(``sch_paper_init``), are advanced with the Matern-type noise; every
+``n_steps`` model steps the truth is observed (P u + N(0, sigma^2) errors, on
+the whole grid or only the first ``n_observed`` points) and the filter
+assimilates the observation: the bootstrap filter of section 3.1.1 or the
+tempered + jittered filter of section 3.1.2.  After each assimilation step the
+ensemble is compared with the truth by EMRE, RB and RES (``sch_ensemble_stats``).
+Every step runs in the library's kernels; this module only sequences the
+calls and collects the per-step numbers.
+
+Command line:  python -m paper_2402_06927_amd.experiments --exp 1 --filter tempered
+               --steps 1000 [--out results.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import sch
+from . import workloads as W
+
+
+def make_model(wl: W.Workload, device="cuda") -> sch.Model:
+    xi = torch.tensor(W.mode_table(wl.L, wl.nx, wl.n_modes, wl.mode_amp), device=device)
+    return sch.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
+                     picard_tol=wl.picard_tol, picard_max=wl.picard_max)
+
+
+def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0) -> dict:
+    """n_da assimilation steps of the twin experiment wl with the filter
+    "tempered" or "bootstrap".  Returns per-step EMRE, RB, RES, the tempering
+    steps (tempered) or resampling flags (bootstrap), the ESS, the particles
+    whose forecast failed (zero weight), and the final ensemble and truth as
+    numpy arrays."""
+    if filt not in ("tempered", "bootstrap"):
+        raise ValueError("filter must be 'tempered' or 'bootstrap'")
+    if wl.noise != "matern":
+        raise ValueError("the paper's experiments use the Matern-type noise")
+    dev = "cuda"
+    model = make_model(wl, dev)
+    mt = sch.Matern(wl.kappa, wl.eta, wl.k_solves)
+    n, nx, S = wl.n_particles, wl.nx, wl.n_steps
+    u = torch.empty((n, nx), dtype=torch.float64, device=dev)
+    m = torch.empty_like(u)
+    sch.sch_paper_init(model, wl.seed, u)
+    sch.sch_init_momentum(model, u, m)
+    ts = W.truth_seed(wl)
+    ut = torch.empty((1, nx), dtype=torch.float64, device=dev)
+    mtr = torch.empty_like(ut)
+    sch.sch_paper_init(model, ts, ut)
+    sch.sch_init_momentum(model, ut, mtr)
+    sigma = torch.tensor(W.sigma_vector(wl), device=dev)
+    z = torch.tensor(W.obs_noise(wl, ts, n_da), device=dev)
+    cells_t = torch.empty((1, S, nx), dtype=torch.float64, device=dev)
+    y = torch.empty((1, wl.n_obs), dtype=torch.float64, device=dev)
+    if filt == "tempered":
+        ws = sch.matern_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
+    else:
+        ws = sch.matern_workspace(sch.WS_BOOTSTRAP, model, n, S, 0)
+        logw = torch.zeros(n, dtype=torch.float64, device=dev)
+    sws = torch.empty(nx + 2 * n, dtype=torch.float64, device=dev)
+    stats = torch.empty((n_da, 3), dtype=torch.float64, device=dev)
+    init_stats = sch.sch_ensemble_stats(u, ut[0], sws).cpu().numpy()
+    n_temper, resampled, ess, failed = [], [], [], []
+    t0 = time.perf_counter()
+    for c in range(n_da):
+        # truth: one window with its own cell increments, then the observation
+        sch.sch_draw_increments(ts, c, 0, sch.TAG_FORECAST, cells_t, wl.dt)
+        sch.sch_ensemble_step_matern(model, mt, mtr, ut, cells_t)
+        sch.sch_observe(model, ut, y)
+        yc = (y[0] + wl.sigma_obs * z[c]).contiguous()
+        obs = sch.Obs(yc, sigma)
+        if filt == "tempered":
+            st = sch.sch_pf_tempered_cycle_matern(model, mt, obs, wl.seed, c, m, u, S,
+                                                  wl.ess_threshold, wl.n_bisect, wl.rho,
+                                                  wl.n_jitter, wl.max_temper, ws)
+            n_temper.append(st["n_temper"])
+        else:
+            st = sch.sch_pf_bootstrap_cycle_matern(model, mt, obs, wl.seed, c, m, u, logw, S,
+                                                   wl.ess_frac, ws)
+            resampled.append(st["resampled"])
+        ess.append(st["ess"])
+        failed.append(st["n_failed"])
+        sch.sch_ensemble_stats(u, ut[0], sws, stats[c])
+        if log_every and (c + 1) % log_every == 0:
+            s = stats[c].cpu().numpy()
+            print(f"step {c + 1}: EMRE {s[0]:.4f} RB {s[1]:.4f} RES {s[2]:.4f} ess {st['ess']:.1f}",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s = stats.cpu().numpy()
+    return {
+        "workload": wl.name, "filter": filt, "n_da": n_da, "seconds": elapsed,
+        "init": init_stats, "emre": s[:, 0], "rb": s[:, 1], "res": s[:, 2],
+        "n_temper": np.array(n_temper), "resampled": np.array(resampled), "ess": np.array(ess),
+        "n_failed": np.array(failed),
+        "u": u.cpu().numpy(), "u_truth": ut[0].cpu().numpy(),
+    }
+
+
+def summary(r: dict, window: int = 100) -> dict:
+    """Means of the statistics over the first and the last `window` steps."""
+    k = min(window, r["n_da"])
+    out = {"workload": r["workload"], "filter": r["filter"], "n_da": r["n_da"],
+           "seconds": round(r["seconds"], 2),
+           "da_steps_per_s": round(r["n_da"] / r["seconds"], 2),
+           "init": [round(float(v), 4) for v in r["init"]]}
+    for key in ("emre", "rb", "res"):
+        out[key + "_first"] = round(float(np.mean(r[key][:k])), 4)
+        out[key + "_last"] = round(float(np.mean(r[key][-k:])), 4)
+    if len(r["n_temper"]):
+        out["n_temper_mean"] = round(float(np.mean(r["n_temper"])), 2)
+        out["n_temper_range"] = [int(r["n_temper"].min()), int(r["n_temper"].max())]
+    if len(r["resampled"]):
+        out["resampling_rate"] = round(float(np.mean(r["resampled"])), 3)
+    out["failed_forecasts"] = int(np.sum(r["n_failed"]))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description="twin experiments of section 4 on the GPU")
+    ap.add_argument("--exp", type=int, choices=(1, 2), default=1,
+                    help="1: full domain observed; 2: half domain")
+    ap.add_argument("--filter", choices=("tempered", "bootstrap"), default="tempered")
+    ap.add_argument("--steps", type=int, default=100, help="assimilation steps")
+    ap.add_argument("--log-every", type=int, default=0)
+    ap.add_argument("--out", default=None, help="write the per-step statistics as JSON")
+    args = ap.parse_args()
+    if not torch.cuda.is_available():
+        print("the experiments need a GPU", file=sys.stderr)
+        sys.exit(2)
+    wl = W.PAPER_SHAPE if args.exp == 1 else W.PAPER_HALF
+    r = run_twin(wl, args.filter, args.steps, args.log_every)
+    print(json.dumps(summary(r)), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump({k: (v.tolist() if isinstance(v, np.ndarray) and v.ndim == 1 else v)
+                       for k, v in r.items() if k not in ("u", "u_truth")}, f)
+
+
+if __name__ == "__main__":
+    main()

@@ -63,7 +63,7 @@ class SchCycleStats(C.Structure):
     _fields_ = [
         ("ess", C.c_double), ("resampled", C.c_int32), ("n_temper", C.c_int32),
         ("picard_iters", C.c_int64), ("n_accept", C.c_int64), ("particle_steps", C.c_int64),
-        ("status", C.c_int32),
+        ("status", C.c_int32), ("n_failed", C.c_int32),
     ]
 
     def as_dict(self):
@@ -171,6 +171,10 @@ def _declare(L):
                                             _vp, f64, i32, _vp, _vp, _vp]),
         "sch_pf_tempered_cycle_matern": (C.c_int, [M, MT, O, u64, u32, i32, i32, f64, i32, f64,
                                                    i32, i32, _vp, _vp, _vp, ST, _vp]),
+        "sch_pf_bootstrap_cycle_matern": (C.c_int, [M, MT, O, u64, u32, i32, i32, f64, _vp, _vp,
+                                                    _vp, _vp, ST, _vp]),
+        "sch_paper_init": (C.c_int, [M, u64, i32, _vp, _vp]),
+        "sch_ensemble_stats": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -194,6 +198,7 @@ def exported_names():
         "sch_tune_set", "sch_tune_get", "sch_timing_enable", "sch_timing_reset",
         "sch_timing_read", "sch_matern_field", "sch_ensemble_step_matern",
         "sch_matern_workspace_bytes", "sch_jitter_pcn_matern", "sch_pf_tempered_cycle_matern",
+        "sch_pf_bootstrap_cycle_matern", "sch_paper_init", "sch_ensemble_stats",
     ]
 
 
@@ -465,6 +470,41 @@ def sch_pf_tempered_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, 
                                               _dev(workspace, torch.uint8, "workspace"),
                                               C.byref(st), _stream()))
     return st.as_dict()
+
+
+def sch_pf_bootstrap_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
+                                  m: torch.Tensor, u: torch.Tensor, logw: torch.Tensor,
+                                  n_steps: int, ess_frac: float, workspace: torch.Tensor) -> dict:
+    mc, tc, oc = model.c(), mt.c(), obs.c()
+    st = SchCycleStats()
+    _check(lib().sch_pf_bootstrap_cycle_matern(C.byref(mc), C.byref(tc), C.byref(oc), seed,
+                                               cycle, m.shape[0], n_steps, ess_frac,
+                                               _dev(m, name="m"), _dev(u, name="u"),
+                                               _dev(logw, name="logw"),
+                                               _dev(workspace, torch.uint8, "workspace"),
+                                               C.byref(st), _stream()))
+    return st.as_dict()
+
+
+# --------------------------------------------------------------------------- section 4
+def sch_paper_init(model: Model, seed: int, u: torch.Tensor):
+    """Initial velocities of eq. init_solve for the rows of u [n][nx]."""
+    mc = model.c()
+    _check(lib().sch_paper_init(C.byref(mc), seed, u.shape[0], _dev(u, name="u"), _stream()))
+
+
+def sch_ensemble_stats(u: torch.Tensor, ua: torch.Tensor, workspace: torch.Tensor | None = None,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+    """(EMRE, RB, RES) of the ensemble u [n][nx] against the truth ua [nx], on the GPU."""
+    n, nx = u.shape
+    if workspace is None:
+        workspace = torch.empty(nx + 2 * n, dtype=torch.float64, device=u.device)
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=u.device)
+    _check(lib().sch_ensemble_stats(n, nx, _dev(u, name="u"), _dev(ua, name="ua"),
+                                    _dev(workspace, name="workspace"), _dev(out, name="out"),
+                                    _stream()))
+    return out
 
 
 def sch_nudge_grad(model: Model, obs: Obs, m0: torch.Tensor, u0: torch.Tensor,
