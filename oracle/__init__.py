@@ -158,6 +158,18 @@ def _declare(L):
                                          _dp, _ip, _ip, _ip, _ip, C.c_int32]),
         "orc_nudged_potential": (C.c_double, [C.c_double, C.c_int32, C.c_double, _dp, _dp]),
         "orc_step_field": (C.c_int, [C.POINTER(OrcModel), _dp, _dp, _dp, _ip]),
+        "orc_pcnl_log_ratio": (C.c_double, [C.c_int32, _dp, C.c_double, _dp, _dp, C.c_double,
+                                            _dp, C.c_double, C.c_double, C.c_double]),
+        "orc_pcnl_linear_chain": (C.c_int64, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _dp,
+                                              _dp, C.c_double, C.c_double, C.c_double,
+                                              C.c_double, C.c_int32, _dp, _dp]),
+        "orc_jitter_pcnl": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.POINTER(OrcRng),
+                                      C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
+                                      C.c_double, C.c_double, C.c_int32, _ip, C.c_int32]),
+        "orc_tempered_cycle_pcnl": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_uint64,
+                                              C.c_uint32, C.c_int32, C.c_int32, C.c_double,
+                                              C.c_int32, C.c_double, C.c_int32, C.c_int32, _dp,
+                                              _dp, C.POINTER(OrcCycleStats), C.c_int32]),
         "orc_paper_init_from": (C.c_int, [C.c_int32, C.c_double, _dp, C.c_double, C.c_double,
                                           _dp]),
         "orc_paper_init": (C.c_int, [C.c_int32, C.c_double, C.c_uint64, C.c_int32, C.c_int32,
@@ -817,3 +829,53 @@ def ensemble_stats(u, ua):
     out = np.zeros(3)
     lib().orc_ensemble_stats(u.shape[0], u.shape[1], _d(u), _d(_f64(ua)), _d(out))
     return out
+
+
+# --------------------------------------------------------------------------- pCN Langevin
+def pcnl_log_ratio(x, phi_x, g_x, v, phi_v, g_v, theta, rho, dt) -> float:
+    x, g_x, v, g_v = (_f64(a) for a in (x, g_x, v, g_v))
+    return lib().orc_pcnl_log_ratio(len(x), _d(x), phi_x, _d(g_x), _d(v), phi_v, _d(g_v), theta,
+                                    rho, dt)
+
+
+def pcnl_linear_chain(seed, n_steps, n_modes, G, y, sigma, theta, rho, dt, n_iter, x0=None):
+    G = _f64(G)
+    y = _f64(y)
+    d = n_steps * n_modes
+    x0 = np.zeros(d) if x0 is None else _f64(x0)
+    samples = np.zeros((n_iter, d))
+    acc = lib().orc_pcnl_linear_chain(seed, n_steps, n_modes, len(y), _d(G), _d(y), sigma, theta,
+                                      rho, dt, n_iter, _d(x0), _d(samples))
+    return samples, acc
+
+
+def jitter_pcnl(model: Model, y, sigma, seed, cycle, temper_k, m0, u0, dW, phi, theta, rho,
+                n_jitter, n_threads=None):
+    """pCN-Langevin moves; returns (dW, phi, m_end, u_end, n_accept)."""
+    y, sg = _obs_arrays(y, sigma)
+    dW = np.array(dW, dtype=np.float64, copy=True, order="C")
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    P, ns = dW.shape[0], dW.shape[1]
+    m_end = np.zeros((P, model.nx))
+    u_end = np.zeros((P, model.nx))
+    acc = np.zeros(P, dtype=np.int32)
+    rg = OrcRng(seed, cycle, temper_k)
+    cm = model.c()
+    lib().orc_jitter_pcnl(C.byref(cm), len(y), _d(y), _d(sg), C.byref(rg), P, ns, _d(_f64(m0)),
+                          _d(_f64(u0)), _d(dW), _d(phi), _d(m_end), _d(u_end), theta, rho,
+                          n_jitter, _i(acc), n_threads or n_threads_default())
+    return dW, phi, m_end, u_end, acc
+
+
+def tempered_cycle_pcnl(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_threshold,
+                        n_bisect=50, rho=0.99, n_jitter=5, max_temper=100, n_threads=None):
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    st = OrcCycleStats()
+    cm = model.c()
+    rc = lib().orc_tempered_cycle_pcnl(C.byref(cm), len(y), _d(y), _d(sg), seed, cycle,
+                                       m.shape[0], n_steps, ess_threshold, n_bisect, rho,
+                                       n_jitter, max_temper, _d(m), _d(u), C.byref(st),
+                                       n_threads or n_threads_default())
+    return rc, m, u, st

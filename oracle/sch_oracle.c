@@ -1091,11 +1091,12 @@ int orc_bootstrap_cycle_matern(const orc_model *md, const orc_matern *mt, int32_
  * particle's increments are moved by n_jitter pCN steps targeting the
  * posterior tempered at the new cumulative theta.  Only then does the window
  * end state become the next cycle's start state. */
-int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
-                       uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
-                       double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
-                       int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
-                       int32_t n_threads) {
+/* The tempered cycle with pCN moves (pcnl == 0) or pCN-Langevin moves. */
+static int tempered_cycle(const orc_model *md, int32_t n_obs, const double *y,
+                          const double *sigma, uint64_t seed, uint32_t cycle, int32_t n_particles,
+                          int32_t n_steps, double ess_threshold, int32_t n_bisect, double rho,
+                          int32_t n_jitter, int32_t max_temper, double *m, double *u,
+                          orc_cycle_stats *st, int32_t n_threads, int pcnl) {
   int32_t nx = md->nx, nq = md->n_modes;
   size_t state = (size_t)n_particles * nx, wlen = (size_t)n_particles * n_steps * nq;
   double *m0 = (double *)malloc(sizeof(double) * state), *u0 = (double *)malloc(sizeof(double) * state);
@@ -1143,8 +1144,12 @@ int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, cons
     gather_rows(dW, idx, n_particles, (size_t)n_steps * nq);
     gather_rows(phi, idx, n_particles, 1);
     orc_rng rg = {seed, cycle, (uint32_t)k};
-    orc_jitter_pcn(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, phi, m, u,
-                   theta_new, rho, n_jitter, acc, n_threads);
+    if (pcnl)
+      orc_jitter_pcnl(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, phi, m, u,
+                      theta_new, rho, n_jitter, acc, n_threads);
+    else
+      orc_jitter_pcn(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, phi, m, u,
+                     theta_new, rho, n_jitter, acc, n_threads);
     for (int32_t p = 0; p < n_particles; ++p) st->n_accept += acc[p];
     st->ess = ess;
     theta = theta_new;
@@ -1162,6 +1167,26 @@ int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, cons
   free(stat);
   free(acc);
   return rc;
+}
+
+int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                       double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                       int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
+                       int32_t n_threads) {
+  return tempered_cycle(md, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
+                        n_bisect, rho, n_jitter, max_temper, m, u, st, n_threads, 0);
+}
+
+/* The tempered cycle with the gradient-based pCN-Langevin jitter
+ * (orc_jitter_pcnl) in place of pCN. */
+int orc_tempered_cycle_pcnl(const orc_model *md, int32_t n_obs, const double *y,
+                            const double *sigma, uint64_t seed, uint32_t cycle,
+                            int32_t n_particles, int32_t n_steps, double ess_threshold,
+                            int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                            double *m, double *u, orc_cycle_stats *st, int32_t n_threads) {
+  return tempered_cycle(md, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
+                        n_bisect, rho, n_jitter, max_temper, m, u, st, n_threads, 1);
 }
 
 /* ========================================================================== */
@@ -1977,4 +2002,175 @@ void orc_ensemble_stats(int32_t n, int32_t nx, const double *u, const double *ua
   out[1] = (double)(sqrtl(nb) / nrm);
   out[2] = n > 1 ? (double)(ss / (n - 1) / nrm) : 0.0;
   free(mean);
+}
+
+/* ========================================================================== */
+/* Gradient-based jitter: the preconditioned Crank-Nicolson Langevin move      */
+/* (pCNL; Cotter, Roberts, Stuart & White, Statist. Sci. 2013) on the          */
+/* increments x of a particle, prior N(0, dt I), target proportional to        */
+/* exp(-theta Phi(x)) N(x; 0, dt I).  The Crank-Nicolson step of the           */
+/* preconditioned Langevin equation gives the proposal                         */
+/*   v = rho x + sqrt(1 - rho^2) sqrt(dt) z - (1 - rho) dt theta grad Phi(x),  */
+/* with rho = (2 - delta)/(2 + delta) as for pCN (the pCN proposal plus a      */
+/* drift), and the move is accepted with the Metropolis-Hastings probability   */
+/* min(1, pi(v) q(v -> x) / (pi(x) q(x -> v))), q(x -> v) the Gaussian density */
+/* of the proposal: N(v; rho x - (1 - rho) dt theta grad Phi(x), (1 - rho^2) dt I).*/
+/* The paper names MALA/HMC jittering as future work (section 5).              */
+/* ========================================================================== */
+static double pcnl_log_q(int32_t d, const double *from, const double *to, const double *g_from,
+                         double rho, double dt, double theta) {
+  long double s = 0.0L;
+  for (int32_t i = 0; i < d; ++i) {
+    double r = to[i] - (rho * from[i] - (1.0 - rho) * dt * theta * g_from[i]);
+    s += (long double)r * r;
+  }
+  return (double)(-s / (2.0L * (1.0L - (long double)rho * rho) * dt));
+}
+
+static double pcnl_log_target(int32_t d, const double *x, double phi, double theta, double dt) {
+  long double s = 0.0L;
+  for (int32_t i = 0; i < d; ++i) s += (long double)x[i] * x[i];
+  return (double)(-(long double)theta * phi - s / (2.0L * dt));
+}
+
+/* log of the acceptance ratio of the move x -> v (phi and grad Phi at both). */
+double orc_pcnl_log_ratio(int32_t d, const double *x, double phi_x, const double *g_x,
+                          const double *v, double phi_v, const double *g_v, double theta,
+                          double rho, double dt) {
+  return pcnl_log_target(d, v, phi_v, theta, dt) + pcnl_log_q(d, v, x, g_v, rho, dt, theta) -
+         pcnl_log_target(d, x, phi_x, theta, dt) - pcnl_log_q(d, x, v, g_x, rho, dt, theta);
+}
+
+/* accept iff the ratio is finite and (log r >= 0 or u < exp(log r)) */
+static int pcnl_accept(double logr, double u) {
+  if (!(logr > -INFINITY) || logr != logr) return 0;
+  if (logr >= 0.0) return 1;
+  return u < exp(logr);
+}
+
+/* The linear-Gaussian toy of orc_pcn_linear_chain moved by pCNL: Phi(x) =
+ * |G x - y|^2 / (2 sigma^2), grad Phi = G^T (G x - y) / sigma^2 exactly;
+ * proposals and uniforms with the same counters. */
+int64_t orc_pcnl_linear_chain(uint64_t seed, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                              const double *G, const double *y, double sigma, double theta,
+                              double rho, double dt, int32_t n_iter, const double *x0,
+                              double *samples) {
+  int32_t d = n_steps * n_modes;
+  double *x = (double *)malloc(sizeof(double) * d), *v = (double *)malloc(sizeof(double) * d);
+  double *gx = (double *)calloc((size_t)d, sizeof(double)), *gv = (double *)calloc((size_t)d, sizeof(double));
+  double *res = (double *)malloc(sizeof(double) * (n_obs > 0 ? n_obs : 1));
+  memcpy(x, x0, sizeof(double) * d);
+  /* Phi and its gradient at a point */
+#define TOY_EVAL(pt, phi_out, g_out)                                        \
+  do {                                                                      \
+    double acc_ = 0.0;                                                      \
+    for (int32_t j = 0; j < n_obs; ++j) {                                   \
+      double r = -y[j];                                                     \
+      for (int32_t i = 0; i < d; ++i) r += G[(size_t)j * d + i] * (pt)[i];  \
+      res[j] = r;                                                           \
+      acc_ += 0.5 * r * r / (sigma * sigma);                                \
+    }                                                                       \
+    for (int32_t i = 0; i < d; ++i) {                                       \
+      double s = 0.0;                                                       \
+      for (int32_t j = 0; j < n_obs; ++j) s += G[(size_t)j * d + i] * res[j]; \
+      (g_out)[i] = s / (sigma * sigma);                                     \
+    }                                                                       \
+    (phi_out) = acc_;                                                       \
+  } while (0)
+  double phi = 0.0, phin = 0.0;
+  TOY_EVAL(x, phi, gx);
+  int64_t acc = 0;
+  for (int32_t it = 0; it < n_iter; ++it) {
+    uint32_t w3 = (uint32_t)it;
+    orc_pcn_propose(seed, 0u, (uint32_t)(it >> 16) * (uint32_t)n_steps, n_steps, n_modes, w3,
+                    rho, dt, x, v);
+    for (int32_t i = 0; i < d; ++i) v[i] -= (1.0 - rho) * dt * theta * gx[i];
+    TOY_EVAL(v, phin, gv);
+    double lr = orc_pcnl_log_ratio(d, x, phi, gx, v, phin, gv, theta, rho, dt);
+    double u = orc_uniform(seed, 0u, (uint32_t)(it >> 16), (uint32_t)ORC_TAG_ACCEPT << 24, w3);
+    if (pcnl_accept(lr, u)) {
+      memcpy(x, v, sizeof(double) * d);
+      memcpy(gx, gv, sizeof(double) * d);
+      phi = phin;
+      ++acc;
+    }
+    memcpy(samples + (size_t)it * d, x, sizeof(double) * d);
+  }
+#undef TOY_EVAL
+  free(x);
+  free(v);
+  free(gx);
+  free(gv);
+  free(res);
+  return acc;
+}
+
+/* Phi of a particle's window with increments x, and grad Phi with respect to
+ * x (the adjoint of orc_nudge_grad without controls: its gradient carries the
+ * Girsanov term x / dt, which is removed).  Phi = +inf for a failed window. */
+static int pcnl_eval(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                     int32_t n_steps, const double *m0, const double *u0, const double *x,
+                     double *phi, double *g) {
+  int32_t d = n_steps * md->n_modes;
+  double J = INFINITY;
+  int st = orc_nudge_grad(md, n_obs, y, sigma, n_steps, m0, u0, x, NULL, &J, g);
+  if (st != ORC_OK || !isfinite(J)) {
+    *phi = INFINITY;
+    return st != ORC_OK ? st : ORC_E_NONFINITE;
+  }
+  for (int32_t i = 0; i < d; ++i) g[i] -= x[i] / md->dt;
+  *phi = J;
+  return ORC_OK;
+}
+
+/* n_jitter pCNL moves of every particle's increments dW [n][n_steps][Q] at
+ * temperature theta; proposal normals and uniforms as orc_jitter_pcn (tags
+ * PCN and ACCEPT, the same counters).  phi [n] in/out.  On return m_end,
+ * u_end hold the window ends of the final increments (recomputed). */
+int orc_jitter_pcnl(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                    const orc_rng *rng, int32_t n_particles, int32_t n_steps, const double *m0,
+                    const double *u0, double *dW, double *phi, double *m_end, double *u_end,
+                    double theta, double rho, int32_t n_jitter, int32_t *n_accept,
+                    int32_t n_threads) {
+  int32_t nx = md->nx, nq = md->n_modes, d = n_steps * nq;
+#pragma omp parallel for num_threads(n_threads > 0 ? n_threads : 1) schedule(dynamic, 1)
+  for (int32_t p = 0; p < n_particles; ++p) {
+    double *x = dW + (size_t)p * d;
+    double *v = (double *)malloc(sizeof(double) * d), *gx = (double *)malloc(sizeof(double) * d);
+    double *gv = (double *)malloc(sizeof(double) * d);
+    const double *mp = m0 + (size_t)p * nx, *up = u0 + (size_t)p * nx;
+    double phx = phi[p], phv = 0.0, dummy;
+    pcnl_eval(md, n_obs, y, sigma, n_steps, mp, up, x, &dummy, gx);
+    int32_t acc = 0;
+    for (int32_t j = 0; j < n_jitter; ++j) {
+      uint32_t w3 = (rng->temper_k << 16) | (uint32_t)j;
+      orc_pcn_propose(rng->seed, (uint32_t)p, rng->cycle * (uint32_t)n_steps, n_steps, nq, w3,
+                      rho, md->dt, x, v);
+      for (int32_t i = 0; i < d; ++i) v[i] -= (1.0 - rho) * md->dt * theta * gx[i];
+      pcnl_eval(md, n_obs, y, sigma, n_steps, mp, up, v, &phv, gv);
+      double u = orc_uniform(rng->seed, (uint32_t)p, rng->cycle, (uint32_t)ORC_TAG_ACCEPT << 24,
+                             w3);
+      double lr = isfinite(phv) && isfinite(phx)
+                      ? orc_pcnl_log_ratio(d, x, phx, gx, v, phv, gv, theta, rho, md->dt)
+                      : -INFINITY;
+      if (isfinite(phv) && !isfinite(phx)) lr = INFINITY; /* leave a failed state at once */
+      if (pcnl_accept(lr, u)) {
+        memcpy(x, v, sizeof(double) * d);
+        memcpy(gx, gv, sizeof(double) * d);
+        phx = phv;
+        ++acc;
+      }
+    }
+    phi[p] = phx;
+    if (n_accept) n_accept[p] = acc;
+    double *me = m_end + (size_t)p * nx, *ue = u_end + (size_t)p * nx;
+    memcpy(me, mp, sizeof(double) * nx);
+    memcpy(ue, up, sizeof(double) * nx);
+    int32_t it = 0;
+    orc_window(md, n_steps, me, ue, x, NULL, &it);
+    free(v);
+    free(gx);
+    free(gv);
+  }
+  return ORC_OK;
 }

@@ -237,6 +237,26 @@ int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t
                               double *dWc_out, double *phi_out, orc_cycle_stats *st,
                               int32_t n_threads);
 
+/* ---- gradient-based jitter (pCN Langevin) ---- */
+double orc_pcnl_log_ratio(int32_t d, const double *x, double phi_x, const double *g_x,
+                          const double *v, double phi_v, const double *g_v, double theta,
+                          double rho, double dt);
+int64_t orc_pcnl_linear_chain(uint64_t seed, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                              const double *G, const double *y, double sigma, double theta,
+                              double rho, double dt, int32_t n_iter, const double *x0,
+                              double *samples);
+int orc_jitter_pcnl(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                    const orc_rng *rng, int32_t n_particles, int32_t n_steps, const double *m0,
+                    const double *u0, double *dW, double *phi, double *m_end, double *u_end,
+                    double theta, double rho, int32_t n_jitter, int32_t *n_accept,
+                    int32_t n_threads);
+
+int orc_tempered_cycle_pcnl(const orc_model *md, int32_t n_obs, const double *y,
+                            const double *sigma, uint64_t seed, uint32_t cycle,
+                            int32_t n_particles, int32_t n_steps, double ess_threshold,
+                            int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                            double *m, double *u, orc_cycle_stats *st, int32_t n_threads);
+
 /* ---- the paper's twin experiments: initialisation and statistics ---- */
 int orc_paper_init_from(int32_t nx, double L, const double *W, double alpha, double beta,
                         double *u);
