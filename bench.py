@@ -55,6 +55,8 @@ TRAFFIC_JITTER_BYTES = (200530.96875 * 2.0 + 259847.546875 * 1.0) * 1024
 # proposals written per step)
 TRAFFIC_JITTER_MATERN_BYTES = (7622564.75 * 2.0 + 7562449.546875 * 1.0) * 1024
 TRAFFIC_THREADS = 256
+# checkpoint interval of the adjoint passes of the pCN-Langevin jitter
+PCNL_CKPT = 8
 TRAFFIC_SOURCES_HASH = "f2d00e4df46b00e8"
 
 
@@ -736,11 +738,12 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--workload", choices=("tempered", "matern", "paper", "nudging", "nudged",
-                                           "warmstart", "mlp", "batch"),
+    ap.add_argument("--workload", choices=("tempered", "matern", "pcnl", "paper", "nudging",
+                                           "nudged", "warmstart", "mlp", "batch"),
                     default="tempered",
                     help="tempered: the headline filter; matern: the same filter with the "
-                         "Matern-type noise of section 2; paper: the paper's twin experiment "
+                         "Matern-type noise of section 2; pcnl: the same filter with "
+                         "gradient-based (pCN-Langevin) jitter; paper: the paper's twin experiment "
                          "(--exp 1 or 2); nudging: one nudged window; "
                          "nudged: the nudged filter (nudging, tempering, jittering); "
                          "warmstart: plain vs learned warm-start nudging; mlp: the "
@@ -796,6 +799,7 @@ def main():
         sys.exit(2)
     sch.lib()
     matern = args.workload == "matern"
+    pcnl = args.workload == "pcnl"
     wl = W.MATERN_4096 if matern else W.TEMPERED_4096
     mtn = sch.Matern(wl.kappa, wl.eta, wl.k_solves) if matern else None
     if args.particles:
@@ -832,6 +836,8 @@ def main():
     sigma = torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64, device=dev)
     if matern:
         ws = sch.matern_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
+    elif pcnl:
+        ws = sch.pcnl_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter, PCNL_CKPT)
     else:
         ws = sch.workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
     m_cpu0, u_cpu0 = None, None
@@ -849,6 +855,10 @@ def main():
             return sch.sch_pf_tempered_cycle_matern(model, mtn, obs, wl.seed, c, m, u, S,
                                                     wl.ess_threshold, wl.n_bisect, wl.rho,
                                                     wl.n_jitter, wl.max_temper, ws)
+        if pcnl:
+            return sch.sch_pf_tempered_cycle_pcnl(model, obs, wl.seed, c, m, u, S,
+                                                  wl.ess_threshold, wl.n_bisect, wl.rho,
+                                                  wl.n_jitter, wl.max_temper, ws, PCNL_CKPT)
         return sch.sch_pf_tempered_cycle(model, obs, wl.seed, c, m, u, S, wl.ess_threshold,
                                          wl.n_bisect, wl.rho, wl.n_jitter, wl.max_temper, ws)
 
@@ -887,6 +897,12 @@ def main():
     j_psteps = j_launches * n * S * wl.n_jitter
     per_step = (matern_flops_per_node_step(wl.k_solves, True) if matern
                 else flops_per_node_step(Q))
+    if pcnl:
+        # forward windows per launch: the start gradient, one per move, the end-state
+        # rerun; only the last one's Picard iterations are counted by the library, so
+        # the flops of the adjoint passes and their forward sweeps are left out: the
+        # figure is a lower bound
+        j_psteps = j_launches * n * S
     j_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"] + per_step * j_psteps)
     j_ms = jt["ms"] / j_launches
     j_tflops = (j_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
@@ -898,9 +914,12 @@ def main():
         "frac": round(j_tflops / PEAK_FP64_TFLOPS, 4),
         "traffic": ((TRAFFIC_JITTER_MATERN_BYTES if matern else TRAFFIC_JITTER_BYTES)
                     if kernel_sources_hash() == TRAFFIC_SOURCES_HASH and wl.nx == 4096
-                    and n == 1024 and tuned == TRAFFIC_THREADS else None),
+                    and n == 1024 and tuned == TRAFFIC_THREADS and not pcnl else None),
         "kernel": ("k_jitter<Matern> (pCN proposal drawn per cell + noise field + window "
                    "rerun + likelihood + accept)" if matern else
+                   "pCN-Langevin stage (k_nudge_grad x (moves + 1), proposals, accepts, "
+                   "end-state window); achieved counts the end-state window only (lower bound)"
+                   if pcnl else
                    "k_jitter (fused pCN proposal + window rerun + likelihood + accept)"),
         "avg_launch_ms": round(j_ms, 3),
         "algorithmic_flops_per_launch": j_flops / j_launches,
@@ -916,6 +935,9 @@ def main():
     if matern:
         del config["n_modes"]
         config.update(noise="matern", kappa=wl.kappa, eta=wl.eta, k_solves=wl.k_solves)
+    if pcnl:
+        config.update(jitter="pcn-langevin", ckpt_every=PCNL_CKPT)
+        config["workload"] = wl.name + "_pcnl"
     out = {
         "metric": "assimilation cycles/sec + particle-steps/sec at N=1024, Nx=4096, vs plain",
         "value": round(cycles_per_s, 4),
@@ -937,7 +959,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not pcnl:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle, {threads} threads ...")
         cb = cpu_baseline(wl, u_cpu0, m_cpu0, threads, psteps / args.steps)

@@ -387,6 +387,43 @@ int sch_pf_nudged_cycle(const sch_model *model, const sch_obs *obs, uint64_t see
                         sch_cycle_stats *stats, void *stream);
 
 /* --------------------------------------------------------------------------
+ * Gradient-based jitter: preconditioned Crank-Nicolson Langevin moves (pCNL;
+ * Cotter, Roberts, Stuart & White, Statist. Sci. 2013), the function-space
+ * form of the MALA sampler that the paper names as future work (section 5).
+ * For each particle, with x its increments [n_steps][n_modes] (prior
+ * N(0, dt I)) and the target exp(-theta phi(x)) N(x; 0, dt I):
+ *   v = rho x + sqrt(1 - rho^2) sqrt(dt) z - (1 - rho) dt theta grad phi(x),
+ * z and the acceptance uniform drawn exactly as sch_jitter_pcn's, accepted
+ * with probability min(1, pi(v) q(v -> x) / (pi(x) q(x -> v))), q the
+ * Gaussian density N(rho x - (1 - rho) dt theta grad phi(x), (1 - rho^2) dt I).
+ * phi and grad phi come from the discrete adjoint of sch_nudge_grad (one
+ * forward + reverse pass per proposal and one at the start; checkpoints every
+ * ckpt_every steps).  The drift helps while (1 - rho) dt theta |Hessian of
+ * phi| stays below about 1; beyond that the proposals overshoot.
+ *   rho in [0, 1);  dW, phi in/out as sch_jitter_pcn (no controls);
+ *   m_end, u_end out: the window ends of the final increments (recomputed)
+ *   workspace >= sch_pcnl_workspace_bytes(SCH_WS_JITTER, model, n, n_steps,
+ *                n_jitter, ckpt_every)
+ * sch_pf_tempered_cycle_pcnl: sch_pf_tempered_cycle with these moves
+ * (workspace: SCH_WS_TEMPERED); stats->particle_steps counts the forward
+ * windows (n_steps each: the gradient at the start, one per proposal and the
+ * end-state rerun per tempering step), not the reverse passes.
+ * ------------------------------------------------------------------------ */
+size_t sch_pcnl_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
+                                int32_t n_steps, int32_t n_jitter, int32_t ckpt_every);
+int sch_jitter_pcnl(const sch_model *model, const sch_obs *obs, const sch_rng *rng,
+                    int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
+                    double *dW, double *phi, double *m_end, double *u_end, const double *theta,
+                    double rho, int32_t n_jitter, int32_t ckpt_every, int32_t *n_accept,
+                    void *workspace, void *stream);
+int sch_pf_tempered_cycle_pcnl(const sch_model *model, const sch_obs *obs, uint64_t seed,
+                               uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                               double ess_threshold, int32_t n_bisect, double rho,
+                               int32_t n_jitter, int32_t max_temper, int32_t ckpt_every,
+                               double *m, double *u, void *workspace, sch_cycle_stats *stats,
+                               void *stream);
+
+/* --------------------------------------------------------------------------
  * Matern-type noise (section 2, eqs. noise_solve and noise_solve2), the
  * paper's own noise in place of the modes form.  Per step the space-time
  * white noise is its DG0 approximation: one increment Delta W_i ~ N(0, dt)

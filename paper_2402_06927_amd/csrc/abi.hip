@@ -10,6 +10,7 @@
 #include "host.hpp"
 #include "filter.hpp"
 #include "model.hpp"
+#include "pcnl.hpp"
 
 using namespace sch;
 
@@ -191,6 +192,38 @@ int launch_nudge_grad(const sch_model& md, const Tile& tl, const sch_obs& ob, in
   });
 }
 
+// Scratch of the pCN-Langevin jitter: the proposal draws (as pCN), the
+// adjoint's scratch, the proposal, the gradients at the current state and at
+// the proposal, J, statuses and acceptance counts.
+struct PcnlWs {
+  double *zeta, *vacc, *v, *gx, *gv, *J;
+  int *status, *acc;
+  NudgeWs nws;
+  int ce;
+};
+
+PcnlWs carve_pcnl(void* base, int nx, int nq, int n, int ns, int n_jitter, int ce,
+                  size_t* bytes) {
+  Carve c(base);
+  PcnlWs w{};
+  const size_t inc = static_cast<size_t>(n) * ns * nq;
+  w.zeta = c.take<double>(inc * static_cast<size_t>(n_jitter));
+  w.vacc = c.take<double>(static_cast<size_t>(n) * n_jitter);
+  w.v = c.take<double>(inc);
+  w.gx = c.take<double>(inc);
+  w.gv = c.take<double>(inc);
+  w.J = c.take<double>(n);
+  w.status = c.take<int>(n);
+  w.acc = c.take<int>(n);
+  size_t nb = 0;
+  carve_nudge(nullptr, false, nx, nq, n, ns, ce, &nb);
+  char* nbase = c.take<char>(nb);
+  w.nws = carve_nudge(nbase, false, nx, nq, n, ns, ce, nullptr);
+  w.ce = ce;
+  if (bytes) *bytes = c.off + 256;
+  return w;
+}
+
 int check_obs(const sch_obs* ob) {
   if (!ob || ob->n_obs < 1 || !ob->y || !ob->sigma) return fail(SCH_E_ARG, "bad observations");
   return SCH_OK;
@@ -258,6 +291,52 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
   });
 }
 
+
+// n_jitter pCN-Langevin moves of every particle's increments dW (pcnl.hpp):
+// the proposal draws as launch_jitter, one adjoint evaluation at the current
+// increments and one per proposal, the Metropolis-Hastings step per particle;
+// then the window ends of the final increments are recomputed into
+// (m_end, u_end).
+int launch_pcnl(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t seed,
+                uint32_t cycle, uint32_t temper_k, int n, int n_steps, const double* m0,
+                const double* u0, double* dW, double* phi, double* m_end, double* u_end,
+                const double* theta, double rho, int n_jitter, int* n_accept,
+                unsigned long long* iters_acc, const PcnlWs& P, hipStream_t st) {
+  const int Q = md.n_modes, d = n_steps * Q;
+  const int64_t total = static_cast<int64_t>(n) * d;
+  const int gb = grid_for(total, 256);
+  {
+    const int64_t work = static_cast<int64_t>(n_jitter) * n * n_steps * ((Q + 1) / 2);
+    hipLaunchKernelGGL(k_draw_pcn, dim3(grid_for(work, 256)), dim3(256), 0, st, seed,
+                       cycle * static_cast<uint32_t>(n_steps), cycle, temper_k << 16, n_jitter, n,
+                       n_steps, Q, std::sqrt(md.dt), P.zeta, P.vacc);
+    CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.nws.acc, 2);
+  if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, dW, nullptr, P.ce, P.J,
+                                 P.gx, P.status, nullptr, P.nws, st))
+    return rc;
+  hipLaunchKernelGGL(k_pcnl_grad, dim3(gb), dim3(256), 0, st, total, 1.0 / md.dt, dW, P.gx);
+  int* acc = n_accept ? n_accept : P.acc;
+  const double srho = std::sqrt(1.0 - rho * rho), c = (1.0 - rho) * md.dt;
+  for (int j = 0; j < n_jitter; ++j) {
+    hipLaunchKernelGGL(k_pcnl_propose, dim3(gb), dim3(256), 0, st, total, rho, srho, c, theta, dW,
+                       P.gx, P.zeta + static_cast<size_t>(j) * total, P.v);
+    if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, P.v, nullptr, P.ce,
+                                   P.J, P.gv, P.status, nullptr, P.nws, st))
+      return rc;
+    hipLaunchKernelGGL(k_pcnl_accept, dim3(n), dim3(kWave), 0, st, d, rho, md.dt, theta,
+                       P.vacc + static_cast<size_t>(j) * n, P.status, P.J, dW, P.gx, phi, P.v,
+                       P.gv, acc, j == 0 ? 1 : 0);
+    CHECK_LAUNCH();
+  }
+  if (n_jitter == 0) return SCH_OK;
+  const size_t state = sizeof(double) * static_cast<size_t>(n) * md.nx;
+  HIP_TRY(hipMemcpyAsync(m_end, m0, state, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(u_end, u0, state, hipMemcpyDeviceToDevice, st));
+  return launch_window(md, tl, n, n_steps, m_end, u_end, dW, nullptr, nullptr, nullptr,
+                       iters_acc, st);
+}
 
 // Event-based timing of kernel classes (see sch_timing_enable).
 struct Timing {
@@ -331,7 +410,7 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
                 uint32_t cycle, int n, int n_steps, double thr, int n_bisect, double rho,
                 int n_jitter, int max_temper, double* m, double* u, double* dLam,
                 const CycleWs& W, sch_cycle_stats* stats, hipStream_t st,
-                const MaternDev* M = nullptr) {
+                const MaternDev* M = nullptr, const PcnlWs* PW = nullptr) {
   void* stream = st;
   const int nx = md.nx, Q = M ? md.nx : md.n_modes;
   const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
@@ -378,7 +457,16 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
                                st));
       }
     }
-    if (n_jitter > 0) {
+    if (n_jitter > 0 && PW) {
+      TimedScope ts(SCH_TK_JITTER, st);
+      if (int r2 = launch_pcnl(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
+                               W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter, nullptr,
+                               W.acc + 2, *PW, st))
+        return r2;
+      hipLaunchKernelGGL(k_sum_i32_u64, dim3(1), dim3(256), 0, st, n, PW->acc, W.acc + 1);
+      // forward windows: the gradient at the start, one per proposal, the end-state rerun
+      psteps += static_cast<int64_t>(n) * n_steps * (n_jitter + 2);
+    } else if (n_jitter > 0) {
       TimedScope ts(SCH_TK_JITTER, st);
       if (int r2 = launch_jitter(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
                                  W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
@@ -963,6 +1051,85 @@ int sch_pf_bootstrap_cycle_matern(const sch_model* md, const sch_matern* mt, con
     return fail(SCH_E_ARG, "bad arguments to sch_pf_bootstrap_cycle_matern");
   return bootstrap_cycle(md, tl, ob, seed, cycle, n, n_steps, ess_frac, m, u, logw, workspace,
                          stats, stream, &M);
+}
+
+// ---------------------------------------------------------------------------
+// Gradient-based jitter (pCN-Langevin moves).
+// ---------------------------------------------------------------------------
+size_t sch_pcnl_workspace_bytes(int32_t which, const sch_model* md, int32_t n, int32_t n_steps,
+                                int32_t n_jitter, int32_t ckpt_every) {
+  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 || ckpt_every < 1 ||
+      (which != SCH_WS_JITTER && which != SCH_WS_TEMPERED))
+    return 0;
+  size_t a = 0, b = 0;
+  if (which == SCH_WS_TEMPERED)
+    carve_cycle(nullptr, SCH_WS_TEMPERED, md->nx, md->n_modes, n, n_steps, &a, 0);
+  carve_pcnl(nullptr, md->nx, md->n_modes, n, n_steps, n_jitter, ckpt_every, &b);
+  return ((a + 255) & ~size_t(255)) + b;
+}
+
+int sch_jitter_pcnl(const sch_model* md, const sch_obs* ob, const sch_rng* rng, int32_t n,
+                    int32_t n_steps, const double* m0, const double* u0, double* dW, double* phi,
+                    double* m_end, double* u_end, const double* theta, double rho,
+                    int32_t n_jitter, int32_t ckpt_every, int32_t* n_accept, void* workspace,
+                    void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (!rng || n < 1 || n > 65535 || n_steps < 1 || !m0 || !u0 || !dW || !phi || !m_end ||
+      !u_end || !theta || !(rho >= 0 && rho < 1) || n_jitter < 0 || ckpt_every < 1 ||
+      (n_jitter > 0 && !workspace))
+    return fail(SCH_E_ARG, "bad arguments to sch_jitter_pcnl");
+  if (n_jitter == 0) return SCH_OK;
+  PcnlWs P = carve_pcnl(workspace, md->nx, md->n_modes, n, n_steps, n_jitter, ckpt_every, nullptr);
+  return launch_pcnl(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0, dW,
+                     phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, P, S(stream));
+}
+
+int sch_pf_tempered_cycle_pcnl(const sch_model* md, const sch_obs* ob, uint64_t seed,
+                               uint32_t cycle, int32_t n, int32_t n_steps, double thr,
+                               int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                               int32_t ckpt_every, double* m, double* u, void* workspace,
+                               sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !workspace || !stats || n_bisect < 0 ||
+      max_temper < 1 || !(rho >= 0 && rho < 1) || n_jitter < 0 || ckpt_every < 1)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_tempered_cycle_pcnl");
+  hipStream_t st = S(stream);
+  const int nx = md->nx, Q = md->n_modes;
+  const size_t state = static_cast<size_t>(n) * nx;
+  size_t a = 0;
+  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, &a, 0);
+  PcnlWs P = carve_pcnl(static_cast<char*>(workspace) + ((a + 255) & ~size_t(255)), nx, Q, n,
+                        n_steps, n_jitter, ckpt_every, nullptr);
+  *stats = sch_cycle_stats{};
+  sch_rng rg{seed, cycle, 0};
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
+  {
+    TimedScope ts(SCH_TK_GATHER, st);
+    HIP_TRY(hipMemcpyAsync(W.m0, m, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(W.u0, u, sizeof(double) * state, hipMemcpyDeviceToDevice, st));
+  }
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_draw_increments(&rg, SCH_TAG_FORECAST, n, n_steps, Q, md->dt, W.dW, stream))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_WINDOW, st);
+    if (int rc = launch_window(*md, tl, n, n_steps, m, u, W.dW, nullptr, W.status, W.iters, W.acc, st))
+      return rc;
+  }
+  {
+    TimedScope ts(SCH_TK_OTHER, st);
+    if (int rc = sch_loglik(md, ob, n, u, W.phi, stream)) return rc;
+    hipLaunchKernelGGL(k_mask_failed, dim3(grid_for(n, 256)), dim3(256), 0, st, n, W.status,
+                       W.phi);
+  }
+  return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                     max_temper, m, u, nullptr, W, stats, st, nullptr, &P);
 }
 
 // ---------------------------------------------------------------------------

@@ -417,6 +417,21 @@ __global__ void k_fill(double* p, double v, int64_t n) {
     p[i] = v;
 }
 
+// *out += sum of a[0 .. n) (one workgroup of 256 threads).
+__global__ void __launch_bounds__(256) k_sum_i32_u64(int n, const int* a,
+                                                     unsigned long long* out) {
+  __shared__ unsigned long long part[256];
+  unsigned long long s = 0;
+  for (int i = threadIdx.x; i < n; i += 256) s += static_cast<unsigned long long>(a[i]);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out += part[0];
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }

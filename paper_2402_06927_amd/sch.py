@@ -174,6 +174,11 @@ def _declare(L):
         "sch_pf_bootstrap_cycle_matern": (C.c_int, [M, MT, O, u64, u32, i32, i32, f64, _vp, _vp,
                                                     _vp, _vp, ST, _vp]),
         "sch_paper_init": (C.c_int, [M, u64, i32, _vp, _vp]),
+        "sch_pcnl_workspace_bytes": (C.c_size_t, [i32, M, i32, i32, i32, i32]),
+        "sch_jitter_pcnl": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, f64,
+                                      i32, i32, _vp, _vp, _vp]),
+        "sch_pf_tempered_cycle_pcnl": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32,
+                                                 i32, i32, _vp, _vp, _vp, ST, _vp]),
         "sch_ensemble_stats": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
@@ -199,6 +204,7 @@ def exported_names():
         "sch_timing_read", "sch_matern_field", "sch_ensemble_step_matern",
         "sch_matern_workspace_bytes", "sch_jitter_pcn_matern", "sch_pf_tempered_cycle_matern",
         "sch_pf_bootstrap_cycle_matern", "sch_paper_init", "sch_ensemble_stats",
+        "sch_pcnl_workspace_bytes", "sch_jitter_pcnl", "sch_pf_tempered_cycle_pcnl",
     ]
 
 
@@ -483,6 +489,50 @@ def sch_pf_bootstrap_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int,
                                                _dev(logw, name="logw"),
                                                _dev(workspace, torch.uint8, "workspace"),
                                                C.byref(st), _stream()))
+    return st.as_dict()
+
+
+# --------------------------------------------------------------------------- pCN Langevin
+def pcnl_workspace(which: int, model: Model, n_particles: int, n_steps: int, n_jitter: int,
+                   ckpt_every: int = 8, device="cuda") -> torch.Tensor:
+    mc = model.c()
+    nb = int(lib().sch_pcnl_workspace_bytes(which, C.byref(mc), n_particles, n_steps, n_jitter,
+                                            ckpt_every))
+    if nb <= 0:
+        raise SchError(SCH_E_ARG, "invalid workspace request")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def sch_jitter_pcnl(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
+                    m0: torch.Tensor, u0: torch.Tensor, dW: torch.Tensor, phi: torch.Tensor,
+                    m_end: torch.Tensor, u_end: torch.Tensor, theta: torch.Tensor, rho: float,
+                    n_jitter: int, ckpt_every: int = 8, n_accept: torch.Tensor | None = None,
+                    workspace: torch.Tensor | None = None):
+    mc, oc = model.c(), obs.c()
+    r = SchRngC(seed, cycle, temper_k)
+    n, s = dW.shape[0], dW.shape[1]
+    if workspace is None:
+        workspace = pcnl_workspace(WS_JITTER, model, n, s, n_jitter, ckpt_every)
+    _check(lib().sch_jitter_pcnl(C.byref(mc), C.byref(oc), C.byref(r), n, s, _dev(m0, name="m0"),
+                                 _dev(u0, name="u0"), _dev(dW, name="dW"), _dev(phi, name="phi"),
+                                 _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
+                                 _dev(theta, name="theta"), rho, n_jitter, ckpt_every,
+                                 _dev(n_accept, torch.int32, "n_accept"),
+                                 _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_pf_tempered_cycle_pcnl(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
+                               u: torch.Tensor, n_steps: int, ess_threshold: float,
+                               n_bisect: int, rho: float, n_jitter: int, max_temper: int,
+                               workspace: torch.Tensor, ckpt_every: int = 8) -> dict:
+    mc, oc = model.c(), obs.c()
+    st = SchCycleStats()
+    _check(lib().sch_pf_tempered_cycle_pcnl(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0],
+                                            n_steps, ess_threshold, n_bisect, rho, n_jitter,
+                                            max_temper, ckpt_every, _dev(m, name="m"),
+                                            _dev(u, name="u"),
+                                            _dev(workspace, torch.uint8, "workspace"),
+                                            C.byref(st), _stream()))
     return st.as_dict()
 
 
