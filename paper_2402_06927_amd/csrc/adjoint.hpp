@@ -107,12 +107,16 @@ __device__ __forceinline__ void advect_t(const double (&s)[PMAX], double sl, dou
 
 // One reverse step: lam holds lambda_{n+1} on entry and lambda_n on exit,
 // gdU receives dJ/d(dU^n).  (ma, ua) is the state before the step, (mb, ub)
-// after it, w_q the step's total increment of mode q.
+// after it, w_q the step's total increment of mode q.  Where the window's two
+// LDS arrays exist (free during the reverse sweep), s and lambda_{n+1}, which
+// the fixed-point loop only reads, wait there instead of in registers.
 template <int PMAX, int NT, bool FULL, class IncF>
 __device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
                             const double* ma, const double* ua, const double* mb,
                             const double* ub, double (&lam)[PMAX], double (&gdU)[PMAX],
-                            const Chunk& ch, RowLds<NT>& L, int t, Parity& par, int& iters) {
+                            const Chunk& ch, RowLds<NT>& L, AuxLds<PMAX, NT>& X, int t,
+                            Parity& par, int& iters) {
+  constexpr bool kL = AuxLds<PMAX, NT>::kInLds;
   const int cnt = ch.cnt;
   const double hdt = 0.5 * P.dt;
   double s[PMAX], dv[PMAX];
@@ -144,11 +148,34 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
     b = fma(0.25, vp - vm, ad);
     c = fma(-0.25, dv[j], ao);
   };
+  // s and lambda_{n+1} from LDS (kL), each value laundered so that the
+  // loads stay inside the loop instead of being hoisted into registers
+  auto s_at = [&](double (&sv)[PMAX]) {
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+      double x = X.a[1][kL ? j : 0][kL ? t : 0];
+      asm volatile("" : "+v"(x));
+      sv[j] = x;
+    }
+  };
+  auto lam_at = [&](int j) -> double {
+    if constexpr (kL) {
+      double x = X.a[0][j][t];
+      asm volatile("" : "+v"(x));
+      return x;
+    } else {
+      return lam[j];
+    }
+  };
   double nu[PMAX], rhs[PMAX];
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
     nu[j] = 0.0;
     rhs[j] = lam[j];
+    if constexpr (kL) {
+      X.a[0][j][t] = lam[j];
+      X.a[1][j][t] = s[j];
+    }
   }
   // the first solve gives A^{-T} lambda; picard_max corrections follow at most
   int status = SCH_E_NONCONVERGED, k = 1;
@@ -180,22 +207,34 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
     // rhs = lambda - (dt/4) M H^{-1} D(s)^T nu
     double nl, nr, w[PMAX], z[PMAX], r[PMAX];
     halo<PMAX, NT, FULL>(nu, cnt, L, t, nl, nr, par.hs);
-    advect_t<PMAX, FULL>(s, sl, sr, nu, nl, nr, cnt, 1.0, w);
+    if constexpr (kL) {
+      double sv[PMAX];
+      s_at(sv);
+      advect_t<PMAX, FULL>(sv, sl, sr, nu, nl, nr, cnt, 1.0, w);
+    } else {
+      advect_t<PMAX, FULL>(s, sl, sr, nu, nl, nr, cnt, 1.0, w);
+    }
     double zL, zR, g0, g1, g2;
     solve_helm<PMAX, NT, FULL>(K, w, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1, g2);
     par.slot ^= 1;
     mass_apply<PMAX, NT, FULL>(z, r, P.h, cnt, L, t, 0.25 * P.dt, par.hs);
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) rhs[j] = lam[j] - r[j];
+    for (int j = 0; j < PMAX; ++j) rhs[j] = lam_at(j) - r[j];
   }
   iters += k > P.picard_max + 1 ? P.picard_max + 1 : k;
   // dJ/d(dU) = -(1/2) D(s)^T nu;  lambda_n = 2 M nu - lambda_{n+1}
   double nl, nr, mnu[PMAX];
   halo<PMAX, NT, FULL>(nu, cnt, L, t, nl, nr, par.hs);
-  advect_t<PMAX, FULL>(s, sl, sr, nu, nl, nr, cnt, -0.5, gdU);
+  if constexpr (kL) {
+    double sv[PMAX];
+    s_at(sv);
+    advect_t<PMAX, FULL>(sv, sl, sr, nu, nl, nr, cnt, -0.5, gdU);
+  } else {
+    advect_t<PMAX, FULL>(s, sl, sr, nu, nl, nr, cnt, -0.5, gdU);
+  }
   mass_apply<PMAX, NT, FULL>(nu, mnu, P.h, cnt, L, t, 2.0, par.hs);
 #pragma unroll
-  for (int j = 0; j < PMAX; ++j) lam[j] = mnu[j] - lam[j];
+  for (int j = 0; j < PMAX; ++j) lam[j] = mnu[j] - lam_at(j);
   return status;
 }
 
@@ -291,7 +330,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         double gdU[PMAX];
         auto inc1 = [&](int q) { return incv(n, q); };
         st = adjoint_step<PMAX, NT, FULL>(A.P, K, inc1, sa, sa + nx, sb, sb + nx, lam, gdU, ch, L,
-                                          t, par, ait);
+                                          X, t, par, ait);
         if (n < CS) {
           for (int q = 0; q < Q; ++q) {
             const double* xq = A.P.xi + static_cast<size_t>(q) * nx + ch.start;
