@@ -69,7 +69,7 @@ typedef struct sch_model {
   int32_t nx;        /* nodes = cells, >= 64                                 */
   int32_t n_modes;   /* noise modes Q, 1..64                                 */
   const double *xi;  /* device [n_modes][nx]: nodal values of the modes      */
-  double picard_tol; /* relative max-norm change of m that ends the solve    */
+  double picard_tol; /* relative max-norm error of m that ends the solve     */
   int32_t picard_max;/* iteration cap of the implicit solve                  */
 } sch_model;
 
@@ -152,7 +152,10 @@ int sch_init_momentum(const sch_model *model, int32_t n_particles, const double 
  *   (m^{n+1} - m^n, phi) + mu dt (d_x m^{n+1/2}, d_x phi)
  *     + (m^{n+1/2} d_x dv, phi) - (m^{n+1/2} dv, d_x phi) = 0,
  *   dv = dt (u^n + u^{n+1})/2 + sum_q xi_q (dW^n_q + dLambda^n_q),
- * each step solved to picard_tol.  dLambda is the nudging control of
+ * each step solved by Picard iteration until the iterate's estimated error
+ * c/(1-c) |m_k - m_{k-1}| (c the ratio of the last two changes, used while
+ * c < 1/2; the change itself otherwise) is at most picard_tol max|m| in the
+ * max norm.  dLambda is the nudging control of
  * eq. "SCH nudge" (NULL = zero).
  *   m, u    in/out [n_particles][nx]
  *   dW      [n_particles][n_steps][n_modes]

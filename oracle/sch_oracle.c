@@ -365,8 +365,8 @@ int orc_momentum_from_velocity(const orc_model *md, const double *u, double *m) 
 /*   A m^{n+1} = (M - (mu dt/2) K - (1/2) C(dv)) m^n.                          */
 /* dv depends on u^{n+1}, so the system is nonlinear.  The paper does not say  */
 /* how it is solved; this oracle uses Picard iteration on u^{n+1} (each        */
-/* iterate a pivoted linear solve) until the momentum changes by at most       */
-/* picard_tol relative in the max norm.                                        */
+/* iterate a pivoted linear solve) until the estimated error of the momentum  */
+/* iterate is at most picard_tol relative in the max norm.                     */
 /* ========================================================================== */
 /* One implicit-midpoint step driven by the nodal noise increment dU (the
  * step's Delta U in dv = dt (u^n + u^{n+1}) / 2 + Delta U, eq. fde1). */
@@ -383,6 +383,7 @@ int orc_step_field(const orc_model *md, double *m, double *u, const double *dU,
   memcpy(mp, m, sz);
   int st = ORC_E_NONCONVERGED;
   int32_t k;
+  double prev = 0.0;  /* the previous iteration's change of m */
   for (k = 1; k <= md->picard_max; ++k) {
     for (int32_t i = 0; i < n; ++i) dv[i] = dt * 0.5 * (u[i] + us[i]) + dU[i];
     /* rows of A: mass (h/6, 2h/3, h/6) + (mu dt/2) stiffness (-1/h, 2/h, -1/h)
@@ -423,7 +424,15 @@ int orc_step_field(const orc_model *md, double *m, double *u, const double *dU,
       break;
     }
     memcpy(mp, ms, sz);
-    if (diff <= md->picard_tol * scale) {
+    /* Stop once the iterate's error is within tolerance.  For a contraction
+     * with ratio c, |m* - m_k| <= c / (1 - c) |m_k - m_{k-1}|; c is estimated
+     * by the ratio of the last two changes and the bound used while c < 1/2,
+     * multiplied out as d_k^2 <= lim (d_{k-1} - d_k); otherwise the change
+     * itself must be within tolerance. */
+    double lim = md->picard_tol * scale;
+    int done = (k > 1 && 2.0 * diff < prev) ? diff * diff <= lim * (prev - diff) : diff <= lim;
+    prev = diff;
+    if (done) {
       st = ORC_OK;
       break;
     }

@@ -138,7 +138,8 @@ __device__ __forceinline__ void matern_add(const MaternDev& M, const double (&w)
 // Each step solves  A(dv) s = 2 M m^n  for s = m^n + m^{n+1}, with
 //   A(dv) = M + (mu dt/2) K + (1/2) C(dv),  dv = dt (u^n + u*)/2 + dU^n,
 // by Picard iteration on u* (u* = u^n initially, then u* = H^{-1} M m*), until
-// the max-norm change of m* is at most tol * max|m*|.  Rows of A at node i:
+// the estimated max-norm error of m* (from its change and the observed
+// contraction ratio) is at most tol * max|m*|.  Rows of A at node i:
 //   a_i = h/6 - mu dt/(2h) - dv_{i-1}/4
 //   b_i = 2h/3 + mu dt/h + (dv_{i+1} - dv_{i-1})/4
 //   c_i = h/6 - mu dt/(2h) + dv_{i+1}/4
@@ -206,6 +207,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) us[j] = u[j];
     int status = SCH_E_NONCONVERGED, k = 1;
+    double gprev = 0.0;  // the previous iteration's change of m*
     for (; k <= P.picard_max; ++k) {
       // Keep the step's invariants (the right-hand side 2 M m^n and the
       // LDS-resident explicit part) out of registers across iterations:
@@ -264,7 +266,15 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
         status = SCH_E_NONFINITE;
         break;
       }
-      if (gdiff <= P.tol * gscale) {
+      // stop once the iterate's error is within tolerance: for a contraction
+      // with ratio c, |m* - m_k| <= c / (1 - c) |m_k - m_{k-1}|; c is the ratio
+      // of the last two changes, the bound is used while c < 1/2 (multiplied
+      // out: d_k^2 <= lim (d_{k-1} - d_k)), the change itself otherwise
+      const double lim = P.tol * gscale;
+      const bool done = (k > 1 && 2.0 * gdiff < gprev) ? gdiff * gdiff <= lim * (gprev - gdiff)
+                                                       : gdiff <= lim;
+      gprev = gdiff;
+      if (done) {
         status = SCH_OK;
         break;
       }
