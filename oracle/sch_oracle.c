@@ -1358,6 +1358,10 @@ int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const do
     }
     st = orc_cyclic_solve(nx, tlo, di, tup, lam, nu);
     int conv = 0;
+    /* the first iterate's change from the zero start, for the error estimate */
+    double prev = 0.0;
+    for (int32_t i = 0; i < nx; ++i)
+      if (fabs(nu[i]) > prev) prev = fabs(nu[i]);
     for (int32_t k = 0; k < md->picard_max && st == ORC_OK; ++k) {
       advect_transpose(nx, s, nu, tmp);
       st = helm_solve(md, tmp, tmp2);
@@ -1372,7 +1376,12 @@ int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const do
         if (fabs(nun[i]) > scale) scale = fabs(nun[i]);
       }
       memcpy(nu, nun, sz);
-      if (diff <= md->picard_tol * scale) {
+      /* the stopping rule of the forward step: the estimated error
+       * c / (1 - c) d_k, c = d_k / d_{k-1}, while c < 1/2 */
+      double lim = md->picard_tol * scale;
+      int done = (2.0 * diff < prev) ? diff * diff <= lim * (prev - diff) : diff <= lim;
+      prev = diff;
+      if (done) {
         conv = 1;
         break;
       }

@@ -179,6 +179,7 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
   }
   // the first solve gives A^{-T} lambda; picard_max corrections follow at most
   int status = SCH_E_NONCONVERGED, k = 1;
+  double prevd = 0.0;  // the previous iteration's change of nu
   for (; k <= P.picard_max + 1; ++k) {
     double nn[PMAX];
     double xl_unused, xr_unused;
@@ -200,7 +201,14 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
       status = SCH_E_NONFINITE;
       break;
     }
-    if (diff <= P.tol * scale) {
+    // the stopping rule of the forward step: the estimated error
+    // c / (1 - c) d_k, c = d_k / d_{k-1}, while c < 1/2 (the first change is
+    // the first iterate's distance from the zero start)
+    const double lim = P.tol * scale;
+    const bool done = (k > 1 && 2.0 * diff < prevd) ? diff * diff <= lim * (prevd - diff)
+                                                    : diff <= lim;
+    prevd = diff;
+    if (done) {
       status = SCH_OK;
       break;
     }
