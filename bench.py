@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic floating-point operations per grid node (see DESIGN.md):
+# Algorithmic floating-point operations per grid node:
 # per implicit-solve iteration: dv (2) + rows of A (7) + tridiagonal
 # factor-and-solve (9) + m* (1) + mass product (4) + Helmholtz solve with
 # stored factors (5) + convergence test (3) = 31; per step: noise

@@ -102,7 +102,7 @@ def tune_batch(make_model, nxs, n_particles: int = 1024, cache: str | None = Non
     batch): grids are grouped by their tile options, each group is tuned once
     at its median grid on a sample ensemble of `n_particles` (smooth random
     states; enough workgroups to fill the chip for every tile, so that the
-    smaller tiles are not judged on a half-empty GPU), and the choice
+    smaller tiles are not timed on a half-empty GPU), and the choice
     applies to the whole group.  `make_model(nx)`
     returns an sch.Model for grid nx.  Leaves SCH_TUNE_THREADS unset."""
     import numpy as np

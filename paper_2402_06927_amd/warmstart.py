@@ -5,7 +5,7 @@ y - P u and the velocity u, standardised) to the controls dLambda of the
 window, learned from the solutions of plain nudging; its prediction seeds the
 L-BFGS stages of ``sch_nudge_run``.  Particles whose misfit norm exceeds the
 99th percentile of the training misfits keep the plain start (zero), so plain
-nudging is both the fallback and, through its own convergence test, the judge
+nudging is both the fallback and, through its own convergence test, the arbiter
 of the prediction.
 
 Orchestration only: features, standardisation statistics, the network's

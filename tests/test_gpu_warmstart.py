@@ -1,6 +1,6 @@
 """Learned warm start of nudging: trained on the GPU on plain-nudging
 solutions, it must not change what nudging converges to (plain nudging
-judges it through its own stopping rule) and should save objective
+decides through its own stopping rule) and should save objective
 evaluations; with the fallback forced for every particle it reduces to plain
 nudging exactly."""
 import sys
