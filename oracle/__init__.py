@@ -170,6 +170,15 @@ def _declare(L):
                                               C.c_uint32, C.c_int32, C.c_int32, C.c_double,
                                               C.c_int32, C.c_double, C.c_int32, C.c_int32, _dp,
                                               _dp, C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_matern_transpose": (C.c_int, [C.c_int32, C.c_double, C.POINTER(OrcMatern), _dp,
+                                           _dp]),
+        "orc_nudge_grad_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern), C.c_int32,
+                                            _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp,
+                                            C.POINTER(C.c_double), _dp]),
+        "orc_nudge_ensemble_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern),
+                                                C.c_int32, _dp, _dp, C.c_int32, C.c_int32, _dp,
+                                                _dp, _dp, _dp, C.POINTER(OrcLbfgsOpts), _dp, _ip,
+                                                _ip, _ip, _ip, C.c_int32]),
         "orc_paper_init_from": (C.c_int, [C.c_int32, C.c_double, _dp, C.c_double, C.c_double,
                                           _dp]),
         "orc_paper_init": (C.c_int, [C.c_int32, C.c_double, C.c_uint64, C.c_int32, C.c_int32,
@@ -879,3 +888,52 @@ def tempered_cycle_pcnl(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_
                                        n_jitter, max_temper, _d(m), _d(u), C.byref(st),
                                        n_threads or n_threads_default())
     return rc, m, u, st
+
+
+# --------------------------------------------------------------------------- Matern nudging
+def matern_transpose(nx, L, mt: OrcMatern, g):
+    """The transpose of matern_field's linear map, applied to g [nx]."""
+    out = np.zeros(nx)
+    st = lib().orc_matern_transpose(nx, L, C.byref(mt), _d(_f64(g)), _d(out))
+    assert st == ORC_OK, st
+    return out
+
+
+def nudge_grad_matern(model: Model, mt: OrcMatern, y, sigma, m0, u0, dW, dLam=None):
+    """(status, J, dJ/ddLam [n_steps][nx]) with the Matern-type noise."""
+    y, sg = _obs_arrays(y, sigma)
+    dW = _f64(dW)
+    J = C.c_double(0.0)
+    g = np.zeros_like(dW)
+    cm = model.c()
+    st = lib().orc_nudge_grad_matern(C.byref(cm), C.byref(mt), len(y), _d(y), _d(sg),
+                                     dW.shape[0], _d(_f64(m0)), _d(_f64(u0)), _d(dW),
+                                     _d(_f64(dLam)) if dLam is not None else None, C.byref(J),
+                                     _d(g))
+    return st, J.value, g
+
+
+def nudge_ensemble_matern(model: Model, mt: OrcMatern, y, sigma, m, u, dW, dLam0=None,
+                          gtol=LBFGS_GTOL, max_iter=LBFGS_MAX_ITER, mem=LBFGS_MEM,
+                          max_back=LBFGS_MAX_BACK, n_threads=None):
+    """nudge_ensemble with the Matern-type noise (controls per cell)."""
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    dW = _f64(dW)
+    P, S = dW.shape[0], dW.shape[1]
+    dLam = (np.zeros_like(dW) if dLam0 is None
+            else np.array(dLam0, dtype=np.float64, copy=True, order="C"))
+    logG = np.zeros(P)
+    iters = np.zeros(P, dtype=np.int32)
+    evals = np.zeros(P, dtype=np.int32)
+    lst = np.zeros(P, dtype=np.int32)
+    status = np.zeros(P, dtype=np.int32)
+    opts = OrcLbfgsOpts(gtol, max_iter, mem, max_back)
+    cm = model.c()
+    worst = lib().orc_nudge_ensemble_matern(C.byref(cm), C.byref(mt), len(y), _d(y), _d(sg), P,
+                                            S, _d(m), _d(u), _d(dW), _d(dLam), C.byref(opts),
+                                            _d(logG), _i(iters), _i(evals), _i(lst), _i(status),
+                                            n_threads or n_threads_default())
+    return dict(worst=worst, m=m, u=u, dLam=dLam, logG=logG, iters=iters, evals=evals,
+                lbfgs_status=lst, status=status)

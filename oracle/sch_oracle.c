@@ -541,6 +541,39 @@ int orc_matern_field(int32_t nx, double L, const orc_matern *mt, const double *d
   return st;
 }
 
+/* The transpose of the linear map dWc -> dU of orc_matern_field: with
+ * A = M + kappa^{-2} K and B the load operator (b_n = sqrt(h) (w_{n-1} + w_n)/2),
+ * dU = (A^{-1} M)^{k-1} A^{-1} eta B dWc, so the transpose is
+ * eta B^T A^{-1} (M A^{-1})^{k-1}: z = A^{-1} g, then z = A^{-1} M z (k - 1
+ * times), out_i = eta sqrt(h) (z_i + z_{i+1}) / 2.  (Used by the nudging
+ * gradient with the Matern-type noise.) */
+int orc_matern_transpose(int32_t nx, double L, const orc_matern *mt, const double *g,
+                         double *out) {
+  double h = L / nx, ik2 = 1.0 / (mt->kappa * mt->kappa);
+  size_t sz = sizeof(double) * (size_t)nx;
+  double *a = (double *)calloc((size_t)nx, sizeof(double));
+  double *b = (double *)calloc((size_t)nx, sizeof(double));
+  double *c = (double *)calloc((size_t)nx, sizeof(double));
+  double *z = (double *)malloc(sz), *r = (double *)malloc(sz);
+  for (int32_t i = 0; i < nx; ++i) {
+    a[i] = h / 6.0 - ik2 / h;
+    b[i] = 2.0 * h / 3.0 + 2.0 * ik2 / h;
+    c[i] = h / 6.0 - ik2 / h;
+  }
+  int st = orc_cyclic_solve(nx, a, b, c, g, z);
+  for (int32_t j = 2; j <= mt->k && st == ORC_OK; ++j) {
+    orc_apply_mass(nx, h, z, r);
+    st = orc_cyclic_solve(nx, a, b, c, r, z);
+  }
+  for (int32_t i = 0; i < nx; ++i) out[i] = mt->eta * sqrt(h) * 0.5 * (z[i] + z[wrap(i + 1, nx)]);
+  free(a);
+  free(b);
+  free(c);
+  free(z);
+  free(r);
+  return st;
+}
+
 int orc_step_matern(const orc_model *md, const orc_matern *mt, double *m, double *u,
                     const double *dWc, int32_t *iters) {
   double *dU = (double *)malloc(sizeof(double) * (size_t)md->nx);
@@ -1303,23 +1336,38 @@ static int helm_solve(const orc_model *md, const double *z, double *w) {
   return st;
 }
 
-/* dU^n = sum_q xi_q (dW^n_q + dLambda^n_q) */
-static void noise_field(const orc_model *md, const double *dW, const double *dLam, double *dU) {
+/* dU^n = sum_q xi_q (dW^n_q + dLambda^n_q) (modes form, mt == NULL), or the
+ * Matern-type field of the cells dW^n + dLambda^n (eq. "SCH nudge" with the
+ * noise of eq. noise_solve2). */
+static int noise_field(const orc_model *md, const orc_matern *mt, const double *dW,
+                       const double *dLam, double *dU) {
   int32_t n = md->nx;
+  if (mt) {
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) w[i] = dW[i] + (dLam ? dLam[i] : 0.0);
+    int st = orc_matern_field(n, md->L, mt, w, dU);
+    free(w);
+    return st;
+  }
   for (int32_t i = 0; i < n; ++i) dU[i] = 0.0;
   for (int32_t q = 0; q < md->n_modes; ++q) {
     double inc = dW[q] + (dLam ? dLam[q] : 0.0);
     for (int32_t i = 0; i < n; ++i) dU[i] += md->xi[(size_t)q * n + i] * inc;
   }
+  return ORC_OK;
 }
 
-int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
-                   int32_t n_steps, const double *m0, const double *u0, const double *dW,
-                   const double *dLam, double *J, double *grad) {
-  int32_t nx = md->nx, nq = md->n_modes;
+/* The objective and its gradient with the modes-form noise (mt == NULL,
+ * controls [n_steps][n_modes]) or the Matern-type noise (controls per cell,
+ * [n_steps][nx]). */
+static int nudge_grad(const orc_model *md, const orc_matern *mt, int32_t n_obs, const double *y,
+                      const double *sigma, int32_t n_steps, const double *m0, const double *u0,
+                      const double *dW, const double *dLam, double *J, double *grad) {
+  int32_t nx = md->nx, nq = mt ? md->nx : md->n_modes;
   double h = md->L / nx, dt = md->dt;
   size_t sz = sizeof(double) * nx;
   double *M = (double *)malloc(sz * (size_t)(n_steps + 1)), *U = (double *)malloc(sz * (size_t)(n_steps + 1));
+  double *dUf = (double *)malloc(sz);
   memcpy(M, m0, sz);
   memcpy(U, u0, sz);
   int st = ORC_OK;
@@ -1327,8 +1375,9 @@ int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const do
     memcpy(M + (size_t)(n + 1) * nx, M + (size_t)n * nx, sz);
     memcpy(U + (size_t)(n + 1) * nx, U + (size_t)n * nx, sz);
     int32_t it;
-    st = orc_step(md, M + (size_t)(n + 1) * nx, U + (size_t)(n + 1) * nx, dW + (size_t)n * nq,
-                  dLam ? dLam + (size_t)n * nq : NULL, &it);
+    st = noise_field(md, mt, dW + (size_t)n * nq, dLam ? dLam + (size_t)n * nq : NULL, dUf);
+    if (st == ORC_OK)
+      st = orc_step_field(md, M + (size_t)(n + 1) * nx, U + (size_t)(n + 1) * nx, dUf, &it);
   }
   const double *uN = U + (size_t)n_steps * nx;
   *J = orc_nll(nx, n_obs, uN, y, sigma) + girsanov_term(n_steps, nq, dt, dW, dLam);
@@ -1345,7 +1394,7 @@ int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const do
   for (int32_t n = n_steps - 1; n >= 0 && st == ORC_OK; --n) {
     const double *mn = M + (size_t)n * nx, *mn1 = M + (size_t)(n + 1) * nx;
     const double *un = U + (size_t)n * nx, *un1 = U + (size_t)(n + 1) * nx;
-    noise_field(md, dW + (size_t)n * nq, dLam ? dLam + (size_t)n * nq : NULL, dU);
+    noise_field(md, mt, dW + (size_t)n * nq, dLam ? dLam + (size_t)n * nq : NULL, dU);
     for (int32_t i = 0; i < nx; ++i) {
       s[i] = mn[i] + mn1[i];
       dv[i] = dt * 0.5 * (un[i] + un1[i]) + dU[i];
@@ -1387,21 +1436,45 @@ int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const do
       }
     }
     if (st == ORC_OK && !conv) st = ORC_E_NONCONVERGED;
-    /* gradient with respect to dU^n, then the modes */
+    /* gradient with respect to dU^n, then the modes or the cells */
     advect_transpose(nx, s, nu, g);
-    for (int32_t q = 0; q < nq; ++q) {
-      double acc = 0.0;
-      for (int32_t i = 0; i < nx; ++i) acc += md->xi[(size_t)q * nx + i] * (-0.5 * g[i]);
-      double l = dLam ? dLam[(size_t)n * nq + q] : 0.0;
-      grad[(size_t)n * nq + q] = acc + (l + dW[(size_t)n * nq + q]) / dt;
+    if (mt) {
+      for (int32_t i = 0; i < nx; ++i) g[i] *= -0.5;
+      orc_matern_transpose(nx, md->L, mt, g, tmp2);
+      for (int32_t i = 0; i < nx; ++i) {
+        double l = dLam ? dLam[(size_t)n * nq + i] : 0.0;
+        grad[(size_t)n * nq + i] = tmp2[i] + (l + dW[(size_t)n * nq + i]) / dt;
+      }
+    } else {
+      for (int32_t q = 0; q < nq; ++q) {
+        double acc = 0.0;
+        for (int32_t i = 0; i < nx; ++i) acc += md->xi[(size_t)q * nx + i] * (-0.5 * g[i]);
+        double l = dLam ? dLam[(size_t)n * nq + q] : 0.0;
+        grad[(size_t)n * nq + q] = acc + (l + dW[(size_t)n * nq + q]) / dt;
+      }
     }
     /* lambda_n = 2 M nu - lambda_{n+1} */
     orc_apply_mass(nx, h, nu, tmp);
     for (int32_t i = 0; i < nx; ++i) lam[i] = 2.0 * tmp[i] - lam[i];
   }
   free(M); free(U); free(lam); free(tmp); free(tmp2); free(nu); free(nun); free(s); free(dv);
-  free(dU); free(rhs); free(lo); free(di); free(up); free(tlo); free(tup); free(g);
+  free(dU); free(rhs); free(lo); free(di); free(up); free(tlo); free(tup); free(g); free(dUf);
   return st;
+}
+
+int orc_nudge_grad(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                   int32_t n_steps, const double *m0, const double *u0, const double *dW,
+                   const double *dLam, double *J, double *grad) {
+  return nudge_grad(md, NULL, n_obs, y, sigma, n_steps, m0, u0, dW, dLam, J, grad);
+}
+
+/* orc_nudge_grad with the Matern-type noise: dW, dLam and grad per cell
+ * [n_steps][nx]; J carries the Girsanov term summed over the cells. */
+int orc_nudge_grad_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, int32_t n_steps,
+                          const double *m0, const double *u0, const double *dW,
+                          const double *dLam, double *J, double *grad) {
+  return nudge_grad(md, mt, n_obs, y, sigma, n_steps, m0, u0, dW, dLam, J, grad);
 }
 
 /* Forward-mode (tangent-linear) gradient with dense matrices, for small nx:
@@ -1453,7 +1526,7 @@ int orc_nudge_grad_tangent(const orc_model *md, int32_t n_obs, const double *y,
       for (int32_t n = n0; n < n_steps && st == ORC_OK; ++n) {
         const double *mn = M + (size_t)n * nx, *mn1 = M + (size_t)(n + 1) * nx;
         const double *un = U + (size_t)n * nx, *un1 = U + (size_t)(n + 1) * nx;
-        noise_field(md, dW + (size_t)n * nq, dLam ? dLam + (size_t)n * nq : NULL, dU);
+        noise_field(md, NULL, dW + (size_t)n * nq, dLam ? dLam + (size_t)n * nq : NULL, dU);
         for (int32_t i = 0; i < nx; ++i) {
           s[i] = mn[i] + mn1[i];
           dv[i] = dt * 0.5 * (un[i] + un1[i]) + dU[i];
@@ -1628,17 +1701,18 @@ int orc_lbfgs(int32_t n, orc_objective fn, void *ctx, double *x, double h0, doub
  * afterwards; f = Phi(u^N) + |x|^2 / (2 dt). */
 typedef struct {
   const orc_model *md;
-  int32_t n_obs, n_steps;
+  const orc_matern *mt;
+  int32_t n_obs, n_steps, nq;
   const double *y, *sigma, *m, *u;
   double *dW, *dLam, *grad;
 } stage_ctx;
 
 static int stage_objective(void *vctx, const double *x, double *f, double *g) {
   stage_ctx *c = (stage_ctx *)vctx;
-  int32_t nq = c->md->n_modes;
+  int32_t nq = c->nq;
   memcpy(c->dLam, x, sizeof(double) * nq);
-  int st = orc_nudge_grad(c->md, c->n_obs, c->y, c->sigma, c->n_steps, c->m, c->u, c->dW,
-                          c->dLam, f, c->grad);
+  int st = nudge_grad(c->md, c->mt, c->n_obs, c->y, c->sigma, c->n_steps, c->m, c->u, c->dW,
+                      c->dLam, f, c->grad);
   memcpy(g, c->grad, sizeof(double) * nq);
   return st == ORC_OK ? 0 : 1; /* any failure rejects the point */
 }
@@ -1649,13 +1723,16 @@ static int stage_objective(void *vctx, const double *x, double *f, double *g) {
  * increment dW^n is revealed and the state advanced with dW^n + dLambda^n.
  * dLam holds the warm start on entry and the controls on exit; logG is the
  * log Girsanov factor of the realised path. */
-int orc_nudge_particle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
-                       int32_t n_steps, double *m, double *u, const double *dW, double *dLam,
-                       const orc_lbfgs_opts *opt, double *logG, int32_t *iters_total,
-                       int32_t *evals_total, int32_t *worst_status) {
-  int32_t nx = md->nx, nq = md->n_modes;
+static int nudge_particle(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, int32_t n_steps, double *m,
+                          double *u, const double *dW, double *dLam, const orc_lbfgs_opts *opt,
+                          double *logG, int32_t *iters_total, int32_t *evals_total,
+                          int32_t *worst_status) {
+  int32_t nx = md->nx, nq = mt ? md->nx : md->n_modes;
   stage_ctx c;
   c.md = md;
+  c.mt = mt;
+  c.nq = nq;
   c.n_obs = n_obs;
   c.y = y;
   c.sigma = sigma;
@@ -1681,7 +1758,10 @@ int orc_nudge_particle(const orc_model *md, int32_t n_obs, const double *y, cons
     }
     if (ls > worst) worst = ls;
     int32_t pit;
-    st = orc_step(md, m, u, dW + (size_t)n * nq, x, &pit);
+    double *dUs = (double *)malloc(sizeof(double) * (size_t)nx);
+    st = noise_field(md, mt, dW + (size_t)n * nq, x, dUs);
+    if (st == ORC_OK) st = orc_step_field(md, m, u, dUs, &pit);
+    free(dUs);
     if (st != ORC_OK) break;
     for (int32_t q = 0; q < nq; ++q)
       lg -= 0.5 * x[q] * x[q] / md->dt + x[q] * dW[(size_t)n * nq + q] / md->dt;
@@ -1697,19 +1777,28 @@ int orc_nudge_particle(const orc_model *md, int32_t n_obs, const double *y, cons
   return st;
 }
 
-int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
-                       int32_t n_particles, int32_t n_steps, double *m, double *u, const double *dW,
-                       double *dLam, const orc_lbfgs_opts *opt, double *logG, int32_t *iters,
-                       int32_t *evals, int32_t *lbfgs_status, int32_t *status, int32_t n_threads) {
-  int32_t nx = md->nx, nq = md->n_modes;
+int orc_nudge_particle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       int32_t n_steps, double *m, double *u, const double *dW, double *dLam,
+                       const orc_lbfgs_opts *opt, double *logG, int32_t *iters_total,
+                       int32_t *evals_total, int32_t *worst_status) {
+  return nudge_particle(md, NULL, n_obs, y, sigma, n_steps, m, u, dW, dLam, opt, logG,
+                        iters_total, evals_total, worst_status);
+}
+
+static int nudge_ensemble(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, int32_t n_particles,
+                          int32_t n_steps, double *m, double *u, const double *dW, double *dLam,
+                          const orc_lbfgs_opts *opt, double *logG, int32_t *iters, int32_t *evals,
+                          int32_t *lbfgs_status, int32_t *status, int32_t n_threads) {
+  int32_t nx = md->nx, nq = mt ? md->nx : md->n_modes;
   int worst = ORC_OK;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
   for (int32_t p = 0; p < n_particles; ++p) {
-    int st = orc_nudge_particle(md, n_obs, y, sigma, n_steps, m + (size_t)p * nx,
-                                u + (size_t)p * nx, dW + (size_t)p * n_steps * nq,
-                                dLam + (size_t)p * n_steps * nq, opt, logG + p,
-                                iters ? iters + p : NULL, evals ? evals + p : NULL,
-                                lbfgs_status ? lbfgs_status + p : NULL);
+    int st = nudge_particle(md, mt, n_obs, y, sigma, n_steps, m + (size_t)p * nx,
+                            u + (size_t)p * nx, dW + (size_t)p * n_steps * nq,
+                            dLam + (size_t)p * n_steps * nq, opt, logG + p,
+                            iters ? iters + p : NULL, evals ? evals + p : NULL,
+                            lbfgs_status ? lbfgs_status + p : NULL);
     if (status) status[p] = st;
     if (st != ORC_OK) {
 #pragma omp critical
@@ -1717,6 +1806,26 @@ int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, cons
     }
   }
   return worst;
+}
+
+int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                       int32_t n_particles, int32_t n_steps, double *m, double *u, const double *dW,
+                       double *dLam, const orc_lbfgs_opts *opt, double *logG, int32_t *iters,
+                       int32_t *evals, int32_t *lbfgs_status, int32_t *status, int32_t n_threads) {
+  return nudge_ensemble(md, NULL, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam, opt,
+                        logG, iters, evals, lbfgs_status, status, n_threads);
+}
+
+/* Sequential adapted nudging with the Matern-type noise: controls per cell,
+ * dW and dLam [n][n_steps][nx]; otherwise as orc_nudge_ensemble. */
+int orc_nudge_ensemble_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                              const double *y, const double *sigma, int32_t n_particles,
+                              int32_t n_steps, double *m, double *u, const double *dW,
+                              double *dLam, const orc_lbfgs_opts *opt, double *logG,
+                              int32_t *iters, int32_t *evals, int32_t *lbfgs_status,
+                              int32_t *status, int32_t n_threads) {
+  return nudge_ensemble(md, mt, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam, opt, logG,
+                        iters, evals, lbfgs_status, status, n_threads);
 }
 
 /* ========================================================================== */

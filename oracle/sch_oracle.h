@@ -217,6 +217,20 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
                      double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
                      double *J_out, orc_cycle_stats *st, int32_t n_threads);
 
+/* ---- nudging with the Matern-type noise (controls per cell) ---- */
+int orc_matern_transpose(int32_t nx, double L, const orc_matern *mt, const double *g,
+                         double *out);
+int orc_nudge_grad_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, int32_t n_steps,
+                          const double *m0, const double *u0, const double *dW,
+                          const double *dLam, double *J, double *grad);
+int orc_nudge_ensemble_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                              const double *y, const double *sigma, int32_t n_particles,
+                              int32_t n_steps, double *m, double *u, const double *dW,
+                              double *dLam, const orc_lbfgs_opts *opt, double *logG,
+                              int32_t *iters, int32_t *evals, int32_t *lbfgs_status,
+                              int32_t *status, int32_t n_threads);
+
 /* ---- bootstrap and tempered + jittered filters with the Matern-type noise ---- */
 int orc_bootstrap_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
                                const double *y, const double *sigma, uint64_t seed,
