@@ -459,10 +459,11 @@ int sch_ensemble_step_matern(const sch_model *model, const sch_matern *mt, int32
                              int32_t n_steps, double *m, double *u, const double *dWc,
                              int32_t *status, int32_t *iters, void *stream);
 
-/* Workspace of the Matern-noise jitter and cycles: which = SCH_WS_JITTER,
- * SCH_WS_TEMPERED or SCH_WS_BOOTSTRAP (0 for anything else or invalid sizes). */
+/* Workspace of the Matern-noise calls: which = SCH_WS_JITTER, SCH_WS_TEMPERED
+ * or SCH_WS_BOOTSTRAP with extra = n_jitter, SCH_WS_NUDGE_GRAD or SCH_WS_NUDGE
+ * with extra = ckpt_every (0 for anything else or invalid sizes). */
 size_t sch_matern_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
-                                  int32_t n_steps, int32_t n_jitter);
+                                  int32_t n_steps, int32_t extra);
 
 /* sch_jitter_pcn on the cell increments dWc [n][n_steps][nx]: the same pCN
  * proposal per cell (the cells 2k, 2k+1 of a step share one Philox block:
@@ -474,6 +475,32 @@ int sch_jitter_pcn_matern(const sch_model *model, const sch_matern *mt, const sc
                           const double *m0, const double *u0, double *dWc, double *phi,
                           double *m_end, double *u_end, const double *theta, double rho,
                           int32_t n_jitter, int32_t *n_accept, void *workspace, void *stream);
+
+/* sch_nudge_grad with the Matern-type noise (section 3.1.3 with the noise of
+ * section 2): the controls are per cell, so dWc, dLambdac and grad are
+ * [n][n_steps][nx]; each step's noise is the field of the cells dWc + dLambdac,
+ * the gradient with respect to the cells is the transpose of the field map
+ * applied to dJ/d(Delta U), and J carries the Girsanov term summed over the
+ * cells.  workspace >= sch_matern_workspace_bytes(SCH_WS_NUDGE_GRAD, model, n,
+ * n_steps, ckpt_every).  Errors as sch_nudge_grad, plus SCH_E_ARG for a bad
+ * sch_matern. */
+int sch_nudge_grad_matern(const sch_model *model, const sch_matern *mt, const sch_obs *obs,
+                          int32_t n_particles, int32_t n_steps, const double *m0,
+                          const double *u0, const double *dWc, const double *dLambdac,
+                          int32_t ckpt_every, double *J, double *grad, int32_t *status,
+                          void *workspace, void *stream);
+
+/* sch_nudge_run with the Matern-type noise: the stage-wise nudging over one
+ * window with one control per cell (nx per stage); dWc and dLambdac are
+ * [n][n_steps][nx], the other arguments as sch_nudge_run.  workspace >=
+ * sch_matern_workspace_bytes(SCH_WS_NUDGE, model, n, n_steps, ckpt_every).
+ * The L-BFGS state holds mem correction pairs of nx values per particle. */
+int sch_nudge_run_matern(const sch_model *model, const sch_matern *mt, const sch_obs *obs,
+                         int32_t n_particles, int32_t n_steps, double *m, double *u,
+                         const double *dWc, double *dLambdac, int32_t warm_start,
+                         const sch_lbfgs_opts *opts, int32_t ckpt_every, double *logG,
+                         int32_t *lbfgs_status, int32_t *iters, int32_t *evals,
+                         int32_t *status, void *workspace, void *stream);
 
 /* sch_pf_bootstrap_cycle with the Matern-type noise: cell increments drawn as
  * sch_draw_increments with nx values per step (tag FORECAST), the Matern

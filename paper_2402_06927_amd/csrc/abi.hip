@@ -164,7 +164,8 @@ NudgeWs carve_nudge(void* base, bool full, int nx, int nq, int n, int ns, int ce
 int launch_nudge_grad(const sch_model& md, const Tile& tl, const sch_obs& ob, int n,
                       int n_steps, int ctrl_steps, const double* m0, const double* u0,
                       const double* dW, const double* dLam, int ce, double* J, double* grad,
-                      int* status, const int* active, const NudgeWs& W, hipStream_t st) {
+                      int* status, const int* active, const NudgeWs& W, hipStream_t st,
+                      const MaternDev* M = nullptr) {
   NudgeArgs A;
   A.P = make_params(md);
   A.n_steps = n_steps;
@@ -184,9 +185,13 @@ int launch_nudge_grad(const sch_model& md, const Tile& tl, const sch_obs& ob, in
   A.ckpt = W.ckpt;
   A.seg = W.seg;
   A.iters_acc = W.acc;
+  if (M) A.M = *M;
   const HelmConst K = make_helm(md, tl);
   return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
-    hipLaunchKernelGGL((k_nudge_grad<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A, K);
+    if (M)
+      hipLaunchKernelGGL((k_nudge_grad<PM, NT, FULL, true>), dim3(n), dim3(NT), 0, st, A, K);
+    else
+      hipLaunchKernelGGL((k_nudge_grad<PM, NT, FULL>), dim3(n), dim3(NT), 0, st, A, K);
     CHECK_LAUNCH();
     return SCH_OK;
   });
@@ -699,22 +704,22 @@ int sch_nudge_grad(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_
                            status, nullptr, W, st);
 }
 
-int sch_nudge_run(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_steps, double* m,
-                  double* u, const double* dW, double* dLam, int32_t warm_start,
-                  const sch_lbfgs_opts* opts, int32_t ce, double* logG, int32_t* lbfgs_status,
-                  int32_t* iters, int32_t* evals, int32_t* status, void* workspace,
-                  void* stream) {
-  Tile tl;
-  if (int rc = check_model(md, tl)) return rc;
-  if (int rc = check_obs(ob)) return rc;
-  if (n < 1 || n_steps < 1 || ce < 1 || !m || !u || !dW || !dLam || !logG || !opts ||
-      !workspace)
-    return fail(SCH_E_ARG, "bad arguments to sch_nudge_run");
+}  // extern "C"
+
+namespace {
+// The stage-wise nudging of section 3.1.3 with the modes-form noise
+// (M == null: n_modes controls per step) or the Matern-type noise (M != null:
+// one control per cell, nx per step).
+int nudge_run(const sch_model* md, const Tile& tl, const sch_obs* ob, int32_t n, int32_t n_steps,
+              double* m, double* u, const double* dW, double* dLam, int32_t warm_start,
+              const sch_lbfgs_opts* opts, int32_t ce, double* logG, int32_t* lbfgs_status,
+              int32_t* iters, int32_t* evals, int32_t* status, void* workspace, void* stream,
+              const MaternDev* M) {
   if (!(opts->gtol >= 0) || opts->max_iter < 0 || opts->mem < 1 ||
       opts->mem > kLbfgsMaxMem || opts->max_back < 0 || opts->max_back > 60)
     return fail(SCH_E_ARG, "bad L-BFGS settings");
   hipStream_t st = S(stream);
-  const int Q = md->n_modes;
+  const int Q = M ? md->nx : md->n_modes;
   NudgeWs W = carve_nudge(workspace, true, md->nx, Q, n, n_steps, ce, nullptr);
   int* worst = lbfgs_status ? lbfgs_status : W.worst;
   int* its = iters ? iters : W.iters;
@@ -739,7 +744,7 @@ int sch_nudge_run(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_s
       {
         TimedScope ts(SCH_TK_NUDGE, st);
         if (int rc = launch_nudge_grad(*md, tl, *ob, n, n_steps - s, 1, m, u, nullptr, W.lb.xt,
-                                       ce, W.lb.ft, W.lb.gt, W.lb.est, W.lb.active, W, st))
+                                       ce, W.lb.ft, W.lb.gt, W.lb.est, W.lb.active, W, st, M))
           return rc;
       }
       hipLaunchKernelGGL(k_lbfgs_update, dim3(gb), dim3(256), 0, st, W.lb, LP);
@@ -756,7 +761,8 @@ int sch_nudge_run(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_s
     CHECK_LAUNCH();
     {
       TimedScope ts(SCH_TK_WINDOW, st);
-      if (int rc = launch_window(*md, tl, n, 1, m, u, W.inc1, nullptr, W.tmp, nullptr, W.acc, st))
+      if (int rc = launch_window(*md, tl, n, 1, m, u, W.inc1, nullptr, W.tmp, nullptr, W.acc, st,
+                                 M))
         return rc;
     }
     hipLaunchKernelGGL(k_status_merge, dim3(gb), dim3(256), 0, st, sts, W.tmp, n);
@@ -768,6 +774,25 @@ int sch_nudge_run(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_s
   timing_flush();
   g_tm.iters[SCH_TK_NUDGE] += static_cast<long long>(acc[0] + acc[1]);
   return SCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sch_nudge_run(const sch_model* md, const sch_obs* ob, int32_t n, int32_t n_steps, double* m,
+                  double* u, const double* dW, double* dLam, int32_t warm_start,
+                  const sch_lbfgs_opts* opts, int32_t ce, double* logG, int32_t* lbfgs_status,
+                  int32_t* iters, int32_t* evals, int32_t* status, void* workspace,
+                  void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n_steps < 1 || ce < 1 || !m || !u || !dW || !dLam || !logG || !opts ||
+      !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_nudge_run");
+  return nudge_run(md, tl, ob, n, n_steps, m, u, dW, dLam, warm_start, opts, ce, logG,
+                   lbfgs_status, iters, evals, status, workspace, stream, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,13 +1032,52 @@ int sch_ensemble_step_matern(const sch_model* md, const sch_matern* mt, int32_t 
 }
 
 size_t sch_matern_workspace_bytes(int32_t which, const sch_model* md, int32_t n, int32_t n_steps,
-                                  int32_t n_jitter) {
-  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 ||
-      (which != SCH_WS_JITTER && which != SCH_WS_TEMPERED && which != SCH_WS_BOOTSTRAP))
-    return 0;
+                                  int32_t extra) {
+  if (!md || n < 1 || n_steps < 1 || extra < 0) return 0;
   size_t bytes = 0;
-  carve_cycle(nullptr, which, md->nx, md->nx, n, n_steps, &bytes, n_jitter, 1);
+  if (which == SCH_WS_NUDGE_GRAD || which == SCH_WS_NUDGE) {
+    if (extra < 1) return 0;
+    carve_nudge(nullptr, which == SCH_WS_NUDGE, md->nx, md->nx, n, n_steps, extra, &bytes);
+    return bytes;
+  }
+  if (which != SCH_WS_JITTER && which != SCH_WS_TEMPERED && which != SCH_WS_BOOTSTRAP) return 0;
+  carve_cycle(nullptr, which, md->nx, md->nx, n, n_steps, &bytes, extra, 1);
   return bytes;
+}
+
+int sch_nudge_grad_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob, int32_t n,
+                          int32_t n_steps, const double* m0, const double* u0, const double* dWc,
+                          const double* dLamc, int32_t ce, double* J, double* grad,
+                          int32_t* status, void* workspace, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || ce < 1 || !m0 || !u0 || !J || !grad || !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_nudge_grad_matern");
+  NudgeWs W = carve_nudge(workspace, false, md->nx, md->nx, n, n_steps, ce, nullptr);
+  hipStream_t st = S(stream);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 2);
+  return launch_nudge_grad(*md, tl, *ob, n, n_steps, n_steps, m0, u0, dWc, dLamc, ce, J, grad,
+                           status, nullptr, W, st, &M);
+}
+
+int sch_nudge_run_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob, int32_t n,
+                         int32_t n_steps, double* m, double* u, const double* dWc, double* dLamc,
+                         int32_t warm_start, const sch_lbfgs_opts* opts, int32_t ce, double* logG,
+                         int32_t* lbfgs_status, int32_t* iters, int32_t* evals, int32_t* status,
+                         void* workspace, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || ce < 1 || !m || !u || !dWc || !dLamc || !logG ||
+      !opts || !workspace)
+    return fail(SCH_E_ARG, "bad arguments to sch_nudge_run_matern");
+  return nudge_run(md, tl, ob, n, n_steps, m, u, dWc, dLamc, warm_start, opts, ce, logG,
+                   lbfgs_status, iters, evals, status, workspace, stream, &M);
 }
 
 int sch_jitter_pcn_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,

@@ -36,8 +36,8 @@ struct NudgeArgs {
   int n_steps, ctrl_steps, ckpt_every;
   const double* m0;    // [n][nx]
   const double* u0;    // [n][nx]
-  const double* dW;    // [n][ctrl_steps][Q] or null (zero)
-  const double* dLam;  // [n][ctrl_steps][Q] or null (zero)
+  const double* dW;    // [n][ctrl_steps][Q] or null (zero); Matern: [n][ctrl_steps][nx]
+  const double* dLam;  // [n][ctrl_steps][Q] or null (zero); Matern: [n][ctrl_steps][nx]
   int n_obs;
   const double* y;
   const double* sigma;
@@ -48,6 +48,7 @@ struct NudgeArgs {
   double* ckpt;        // [n][n_segments][2][nx]
   double* seg;         // [n][ckpt_every + 1][2][nx]
   unsigned long long* iters_acc;  // [2]: forward Picard and adjoint fixed-point iterations
+  MaternDev M;                    // Matern-type noise (MATERN kernels)
 };
 
 // P^T diag(sigma^-2) (P u - y) at the chunk's nodes.  A point in cell e
@@ -107,11 +108,11 @@ __device__ __forceinline__ void advect_t(const double (&s)[PMAX], double sl, dou
 
 // One reverse step: lam holds lambda_{n+1} on entry and lambda_n on exit,
 // gdU receives dJ/d(dU^n).  (ma, ua) is the state before the step, (mb, ub)
-// after it, w_q the step's total increment of mode q.  Where the window's two
+// after it; noise(0, dv) adds the step's noise field dU^n.  Where the window's two
 // LDS arrays exist (free during the reverse sweep), s and lambda_{n+1}, which
 // the fixed-point loop only reads, wait there instead of in registers.
-template <int PMAX, int NT, bool FULL, class IncF>
-__device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
+template <int PMAX, int NT, bool FULL, class NoiseF>
+__device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF noise,
                             const double* ma, const double* ua, const double* mb,
                             const double* ub, double (&lam)[PMAX], double (&gdU)[PMAX],
                             const Chunk& ch, RowLds<NT>& L, AuxLds<PMAX, NT>& X, int t,
@@ -130,13 +131,7 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, IncF inc,
       dv[j] = 0.0;
     }
   }
-  for (int q = 0; q < P.n_modes; ++q) {
-    const double w = inc(q);
-    const double* xq = P.xi + static_cast<size_t>(q) * P.nx + ch.start;
-#pragma unroll
-    for (int j = 0; j < PMAX; ++j)
-      if (FULL || j < cnt) dv[j] = fma(xq[j], w, dv[j]);
-  }
+  noise(0, dv);  // + dU^n
   double sl, sr, vl, vr;
   halo<PMAX, NT, FULL>(s, cnt, L, t, sl, sr, par.hs);
   halo<PMAX, NT, FULL>(dv, cnt, L, t, vl, vr, par.hs);
@@ -253,31 +248,53 @@ __device__ __forceinline__ void store_state(double* base, int nx, const Chunk& c
   store_chunk<PMAX, FULL>(base + nx, ch, u);
 }
 
-template <int PMAX, int NT, bool FULL>
+// MATERN: the controls dW, dLambda and the gradient are per cell,
+// [n][ctrl_steps][nx]; each step's noise is the Matern-type field of the cells
+// dW^n + dLambda^n, and the gradient with respect to the cells is the
+// transpose of that map applied to dJ/d(dU^n), plus the Girsanov term.
+template <int PMAX, int NT, bool FULL, bool MATERN = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_nudge_grad(const NudgeArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
-  __shared__ double gpart[64][NT / kWave];
+  __shared__ double gpart[MATERN ? 1 : 64][MATERN ? 1 : NT / kWave];
   const int p = blockIdx.x, t = threadIdx.x;
   if (A.active && A.active[p] == 0) return;  // whole workgroup
   const int nx = A.P.nx, Q = A.P.n_modes, S = A.n_steps, CS = A.ctrl_steps;
+  const int nq = MATERN ? nx : Q;  // controls per step
   const int CE = A.ckpt_every, nseg = (S + CE - 1) / CE;
   const Chunk ch = chunk_of<NT>(nx, t);
-  const double* dW = A.dW ? A.dW + static_cast<size_t>(p) * CS * Q : nullptr;
-  const double* dL = A.dLam ? A.dLam + static_cast<size_t>(p) * CS * Q : nullptr;
+  const double* dW = A.dW ? A.dW + static_cast<size_t>(p) * CS * nq : nullptr;
+  const double* dL = A.dLam ? A.dLam + static_cast<size_t>(p) * CS * nq : nullptr;
   auto incv = [&](int n, int q) -> double {
     if (n >= CS) return 0.0;
     double w = 0.0;
-    if (dW) w = dW[n * Q + q];
-    if (dL) w += dL[n * Q + q];
+    if (dW) w = dW[n * nq + q];
+    if (dL) w += dL[n * nq + q];
     return w;
+  };
+  Parity par;
+  // the noise of step n added to e (uniform across the workgroup: steps past
+  // the controlled ones carry none)
+  auto step_noise = [&](int n) {
+    if constexpr (MATERN) {
+      return [&, n](int, double (&e)[PMAX]) {
+        if (n >= CS || (!dW && !dL)) return;
+        double w[PMAX];
+#pragma unroll
+        for (int j = 0; j < PMAX; ++j)
+          w[j] = (FULL || j < ch.cnt) ? incv(n, ch.start + j) : 0.0;
+        matern_add<PMAX, NT, FULL>(A.M, w, e, ch, L, t, par);
+      };
+    } else {
+      auto inc1 = [&, n](int, int q) { return incv(n, q); };
+      return modes_noise<PMAX, FULL>(A.P, ch, inc1);
+    }
   };
   double* ck = A.ckpt + static_cast<size_t>(p) * nseg * 2 * nx;
   double* sg = A.seg + static_cast<size_t>(p) * (CE + 1) * 2 * nx;
   double m[PMAX], u[PMAX];
   load_chunk<PMAX, FULL>(A.m0 + static_cast<size_t>(p) * nx, ch, m);
   load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u);
-  Parity par;
   int fit = 0, ait = 0, st = SCH_OK;
 
   // forward pass: checkpoints, and every state of the last segment
@@ -287,9 +304,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     store_state<PMAX, FULL>(ck + static_cast<size_t>(c) * 2 * nx, nx, ch, m, u);
     if (last) store_state<PMAX, FULL>(sg, nx, ch, m, u);
     for (int n = n0; n < n1 && st == SCH_OK; ++n) {
-      auto inc1 = [&](int, int q) { return incv(n, q); };
-      st = run_window<PMAX, NT, FULL>(A.P, K, modes_noise<PMAX, FULL>(A.P, ch, inc1), 1, m, u,
-                                      ch, L, X, t, par, fit);
+      st = run_window<PMAX, NT, FULL>(A.P, K, step_noise(n), 1, m, u, ch, L, X, t, par, fit);
       if (last) store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
     }
   }
@@ -297,7 +312,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   if (st == SCH_OK) {
     const double phi = block_nll<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, L, t, par.hs);
     double gs = 0.0;
-    for (int i = t; i < CS * Q; i += NT) {
+    for (int i = t; i < CS * nq; i += NT) {
       const double l = dL ? dL[i] : 0.0, w = dW ? dW[i] : 0.0;
       gs += 0.5 * l * l + l * w;
     }
@@ -326,9 +341,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         load_chunk<PMAX, FULL>(ck + static_cast<size_t>(c) * 2 * nx + nx, ch, u);
         store_state<PMAX, FULL>(sg, nx, ch, m, u);
         for (int n = n0; n < n1 && st == SCH_OK; ++n) {
-          auto inc1 = [&](int, int q) { return incv(n, q); };
-          st = run_window<PMAX, NT, FULL>(A.P, K, modes_noise<PMAX, FULL>(A.P, ch, inc1), 1, m,
-                                          u, ch, L, X, t, par, fit);
+          st = run_window<PMAX, NT, FULL>(A.P, K, step_noise(n), 1, m, u, ch, L, X, t, par, fit);
           store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
         }
       }
@@ -336,10 +349,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         const double* sa = sg + static_cast<size_t>(n - n0) * 2 * nx;
         const double* sb = sa + 2 * nx;
         double gdU[PMAX];
-        auto inc1 = [&](int q) { return incv(n, q); };
-        st = adjoint_step<PMAX, NT, FULL>(A.P, K, inc1, sa, sa + nx, sb, sb + nx, lam, gdU, ch, L,
-                                          X, t, par, ait);
-        if (n < CS) {
+        st = adjoint_step<PMAX, NT, FULL>(A.P, K, step_noise(n), sa, sa + nx, sb, sb + nx, lam,
+                                          gdU, ch, L, X, t, par, ait);
+        if (n >= CS) continue;
+        if constexpr (MATERN) {
+          double gc[PMAX];
+          matern_transpose<PMAX, NT, FULL>(A.M, gdU, gc, ch, L, t, par);
+          double* gp = A.grad + (static_cast<size_t>(p) * CS + n) * nx + ch.start;
+#pragma unroll
+          for (int j = 0; j < PMAX; ++j)
+            if (FULL || j < ch.cnt) gp[j] = gc[j] + incv(n, ch.start + j) / A.P.dt;
+        } else {
           for (int q = 0; q < Q; ++q) {
             const double* xq = A.P.xi + static_cast<size_t>(q) * nx + ch.start;
             double a = 0.0;
@@ -354,8 +374,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
             double a = 0.0;
 #pragma unroll
             for (int i = 0; i < NT / kWave; ++i) a += gpart[q][i];
-            const double l = dL ? dL[n * Q + q] : 0.0, w = dW ? dW[n * Q + q] : 0.0;
-            A.grad[(static_cast<size_t>(p) * CS + n) * Q + q] = a + (l + w) / A.P.dt;
+            A.grad[(static_cast<size_t>(p) * CS + n) * Q + q] = a + incv(n, q) / A.P.dt;
           }
           __syncthreads();
         }

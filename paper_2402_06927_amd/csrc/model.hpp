@@ -131,6 +131,36 @@ __device__ __forceinline__ void matern_add(const MaternDev& M, const double (&w)
     if (FULL || j < cnt) e[j] += U[j];
 }
 
+// The transpose of the map of matern_add (cells Delta W -> field U_k): with
+// A = M + kappa^{-2} K and B the load map, T = (A^{-1} M)^{k-1} A^{-1} B, so
+// T^T g = B^T (A^{-1} M)^{k-1} A^{-1} g (A and M symmetric): z = A^{-1} g, then
+// z = A^{-1} M z k - 1 times, and out_i = load (z_i + z_{i+1}) (cell i feeds the
+// load of nodes i and i + 1).
+template <int PMAX, int NT, bool FULL>
+__device__ __forceinline__ void matern_transpose(const MaternDev& M, const double (&g)[PMAX],
+                                                 double (&out)[PMAX], const Chunk& ch,
+                                                 RowLds<NT>& L, int t, Parity& par) {
+  const int cnt = ch.cnt;
+  const bool bordered = FULL || M.K.base >= 2;
+  double r[PMAX], z[PMAX];
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) r[j] = g[j];
+  double zL = 0.0, zR = 0.0, g0, g1, g2;
+  for (int i = 0; i < M.k; ++i) {
+    if (i > 0) {
+      double hl = zL, hr = zR;
+      if (!bordered) halo<PMAX, NT, FULL>(z, cnt, L, t, hl, hr, par.hs);
+      mass_apply_h<PMAX, FULL>(z, r, M.h, cnt, hl, hr, 1.0);
+    }
+    solve_helm<PMAX, NT, FULL>(M.K, r, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1, g2);
+    par.slot ^= 1;
+  }
+  double hl = zL, hr = zR;
+  if (!bordered) halo<PMAX, NT, FULL>(z, cnt, L, t, hl, hr, par.hs);
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) out[j] = M.load * (z[j] + right_of<PMAX, FULL>(z, j, cnt, hr));
+}
+
 // One assimilation window of n_steps implicit-midpoint steps (eq. fde1) for
 // the particle whose chunk is held in m, u.  noise(n, e) adds the step's
 // noise increment dU^n to the chunk e (modes_noise, or the Matern-type field).

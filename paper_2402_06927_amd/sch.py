@@ -180,6 +180,11 @@ def _declare(L):
         "sch_pf_tempered_cycle_pcnl": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32,
                                                  i32, i32, _vp, _vp, _vp, ST, _vp]),
         "sch_ensemble_stats": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
+        "sch_nudge_grad_matern": (C.c_int, [M, MT, O, i32, i32, _vp, _vp, _vp, _vp, i32, _vp,
+                                            _vp, _vp, _vp, _vp]),
+        "sch_nudge_run_matern": (C.c_int, [M, MT, O, i32, i32, _vp, _vp, _vp, _vp, i32,
+                                           C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp, _vp, _vp,
+                                           _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -205,6 +210,7 @@ def exported_names():
         "sch_matern_workspace_bytes", "sch_jitter_pcn_matern", "sch_pf_tempered_cycle_matern",
         "sch_pf_bootstrap_cycle_matern", "sch_paper_init", "sch_ensemble_stats",
         "sch_pcnl_workspace_bytes", "sch_jitter_pcnl", "sch_pf_tempered_cycle_pcnl",
+        "sch_nudge_grad_matern", "sch_nudge_run_matern",
     ]
 
 
@@ -434,10 +440,12 @@ def sch_ensemble_step_matern(model: Model, mt: Matern, m: torch.Tensor, u: torch
                                           _dev(iters, torch.int32, "iters"), _stream()))
 
 
-def matern_workspace(which: int, model: Model, n_particles: int, n_steps: int, n_jitter: int,
+def matern_workspace(which: int, model: Model, n_particles: int, n_steps: int, extra: int,
                      device="cuda") -> torch.Tensor:
+    """Scratch of the Matern-noise calls; extra is n_jitter (jitter and
+    cycles) or ckpt_every (WS_NUDGE_GRAD, WS_NUDGE)."""
     mc = model.c()
-    nb = int(lib().sch_matern_workspace_bytes(which, C.byref(mc), n_particles, n_steps, n_jitter))
+    nb = int(lib().sch_matern_workspace_bytes(which, C.byref(mc), n_particles, n_steps, extra))
     if nb <= 0:
         raise SchError(SCH_E_ARG, "invalid workspace request")
     return torch.empty(nb, dtype=torch.uint8, device=device)
@@ -597,6 +605,52 @@ def sch_nudge_run(model: Model, obs: Obs, m: torch.Tensor, u: torch.Tensor, dW: 
                                _dev(evals, torch.int32, "evals"),
                                _dev(status, torch.int32, "status"),
                                _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_nudge_grad_matern(model: Model, mt: Matern, obs: Obs, m0: torch.Tensor,
+                          u0: torch.Tensor, dWc: torch.Tensor | None,
+                          dLambdac: torch.Tensor | None, J: torch.Tensor, grad: torch.Tensor,
+                          ckpt_every: int = 8, status: torch.Tensor | None = None,
+                          workspace: torch.Tensor | None = None):
+    """sch_nudge_grad with the Matern-type noise: controls and gradient per
+    cell, [n][n_steps][nx]; the window length is grad.shape[1]."""
+    mc, tc, oc = model.c(), mt.c(), obs.c()
+    n, s = grad.shape[0], grad.shape[1]
+    if workspace is None:
+        workspace = matern_workspace(WS_NUDGE_GRAD, model, n, s, ckpt_every)
+    _check(lib().sch_nudge_grad_matern(C.byref(mc), C.byref(tc), C.byref(oc), n, s,
+                                       _dev(m0, name="m0"), _dev(u0, name="u0"),
+                                       _dev(dWc, name="dWc"), _dev(dLambdac, name="dLambdac"),
+                                       ckpt_every, _dev(J, name="J"), _dev(grad, name="grad"),
+                                       _dev(status, torch.int32, "status"),
+                                       _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_nudge_run_matern(model: Model, mt: Matern, obs: Obs, m: torch.Tensor, u: torch.Tensor,
+                         dWc: torch.Tensor, dLambdac: torch.Tensor, logG: torch.Tensor,
+                         warm_start: bool = False, gtol: float = LBFGS_GTOL,
+                         max_iter: int = LBFGS_MAX_ITER, mem: int = LBFGS_MEM,
+                         max_back: int = LBFGS_MAX_BACK, ckpt_every: int = 8,
+                         lbfgs_status: torch.Tensor | None = None,
+                         iters: torch.Tensor | None = None, evals: torch.Tensor | None = None,
+                         status: torch.Tensor | None = None,
+                         workspace: torch.Tensor | None = None):
+    """sch_nudge_run with the Matern-type noise: one control per cell."""
+    mc, tc, oc = model.c(), mt.c(), obs.c()
+    n, s = dWc.shape[0], dWc.shape[1]
+    if workspace is None:
+        workspace = matern_workspace(WS_NUDGE, model, n, s, ckpt_every)
+    opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
+    _check(lib().sch_nudge_run_matern(C.byref(mc), C.byref(tc), C.byref(oc), n, s,
+                                      _dev(m, name="m"), _dev(u, name="u"),
+                                      _dev(dWc, name="dWc"), _dev(dLambdac, name="dLambdac"),
+                                      1 if warm_start else 0, C.byref(opts), ckpt_every,
+                                      _dev(logG, name="logG"),
+                                      _dev(lbfgs_status, torch.int32, "lbfgs_status"),
+                                      _dev(iters, torch.int32, "iters"),
+                                      _dev(evals, torch.int32, "evals"),
+                                      _dev(status, torch.int32, "status"),
+                                      _dev(workspace, torch.uint8, "workspace"), _stream()))
 
 
 def nudged_workspace(model: Model, n_particles: int, n_steps: int, n_jitter: int,
