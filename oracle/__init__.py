@@ -212,6 +212,17 @@ def _declare(L):
                                        C.c_double, C.c_int32, C.c_int32, C.POINTER(OrcLbfgsOpts),
                                        _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                                        C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_jitter_pcn_matern_ctrl": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern),
+                                                 C.c_int32, _dp, _dp, C.POINTER(OrcRng),
+                                                 C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp,
+                                                 _dp, _dp, C.c_double, C.c_double, C.c_int32,
+                                                 _ip, C.c_int32]),
+        "orc_nudged_cycle_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern),
+                                              C.c_int32, _dp, _dp, C.c_uint64, C.c_uint32,
+                                              C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                              C.c_double, C.c_int32, C.c_int32,
+                                              C.POINTER(OrcLbfgsOpts), _dp, _dp, _dp, _dp, _dp,
+                                              _dp, _dp, C.POINTER(OrcCycleStats), C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -937,3 +948,49 @@ def nudge_ensemble_matern(model: Model, mt: OrcMatern, y, sigma, m, u, dW, dLam0
                                             n_threads or n_threads_default())
     return dict(worst=worst, m=m, u=u, dLam=dLam, logG=logG, iters=iters, evals=evals,
                 lbfgs_status=lst, status=status)
+
+
+def jitter_pcn_matern_ctrl(model: Model, mt: OrcMatern, y, sigma, seed, cycle, temper_k, m0, u0,
+                           dWc, dLamc, J, m_end, u_end, theta, rho, n_jitter, n_threads=None):
+    """pCN moves of the cells dWc with the per-cell controls dLamc fixed; J
+    holds the nudged potentials.  Returns (dWc, J, m_end, u_end, n_accept)."""
+    y, sg = _obs_arrays(y, sigma)
+    dWc = np.array(dWc, dtype=np.float64, copy=True, order="C")
+    J = np.array(J, dtype=np.float64, copy=True)
+    m_end = np.array(m_end, dtype=np.float64, copy=True, order="C")
+    u_end = np.array(u_end, dtype=np.float64, copy=True, order="C")
+    P, ns = dWc.shape[0], dWc.shape[1]
+    acc = np.zeros(P, dtype=np.int32)
+    rg = OrcRng(seed, cycle, temper_k)
+    cm = model.c()
+    lib().orc_jitter_pcn_matern_ctrl(C.byref(cm), C.byref(mt), len(y), _d(y), _d(sg),
+                                     C.byref(rg), P, ns, _d(_f64(m0)), _d(_f64(u0)), _d(dWc),
+                                     _d(_f64(dLamc)), _d(J), _d(m_end), _d(u_end), theta, rho,
+                                     n_jitter, _i(acc), n_threads or n_threads_default())
+    return dWc, J, m_end, u_end, acc
+
+
+def nudged_cycle_matern(model: Model, mt: OrcMatern, y, sigma, seed, cycle, m, u, n_steps,
+                        ess_threshold, n_bisect=50, rho=0.99, n_jitter=5, max_temper=100,
+                        gtol=LBFGS_GTOL, max_iter=LBFGS_MAX_ITER, mem=LBFGS_MEM,
+                        max_back=LBFGS_MAX_BACK, n_threads=None):
+    """nudged_cycle with the Matern-type noise (increments and controls per
+    cell); returns (rc, out, stats) as nudged_cycle."""
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    P, nx = m.shape
+    m0 = np.zeros_like(m)
+    u0 = np.zeros_like(u)
+    dW = np.zeros((P, n_steps, nx))
+    dLam = np.zeros_like(dW)
+    J = np.zeros(P)
+    st = OrcCycleStats()
+    opts = OrcLbfgsOpts(gtol, max_iter, mem, max_back)
+    cm = model.c()
+    rc = lib().orc_nudged_cycle_matern(C.byref(cm), C.byref(mt), len(y), _d(y), _d(sg), seed,
+                                       cycle, P, n_steps, ess_threshold, n_bisect, rho, n_jitter,
+                                       max_temper, C.byref(opts), _d(m), _d(u), _d(m0), _d(u0),
+                                       _d(dW), _d(dLam), _d(J), C.byref(st),
+                                       n_threads or n_threads_default())
+    return rc, dict(m=m, u=u, m0=m0, u0=u0, dW=dW, dLam=dLam, J=J), st

@@ -1833,6 +1833,13 @@ int orc_nudge_ensemble_matern(const orc_model *md, const orc_matern *mt, int32_t
 /* section 3.1.2 with W replaced by W~ (last paragraph of section 3.1.3).     */
 /* ========================================================================== */
 
+static int jitter_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                         const double *y, const double *sigma, const orc_rng *rng,
+                         int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
+                         double *dWc, const double *dLamc, double *phi, double *m_end,
+                         double *u_end, double theta, double rho, int32_t n_jitter,
+                         int32_t *n_accept, int32_t n_threads);
+
 /* One assimilation cycle: the increments of the window are drawn (tag
  * NUDGE) and revealed stage by stage to the sequential nudging of every
  * particle (orc_nudge_particle from zero controls); each particle gets the
@@ -1846,13 +1853,14 @@ int orc_nudge_ensemble_matern(const orc_model *md, const orc_matern *mt, int32_t
  * increments dW_out and controls dLam_out [n][n_steps][n_modes] and the
  * potentials J_out [n].  st->n_accept counts accepted pCN moves;
  * st->picard_iters is not filled. */
-int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
-                     uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
-                     double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
-                     int32_t max_temper, const orc_lbfgs_opts *opt, double *m, double *u,
-                     double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
-                     double *J_out, orc_cycle_stats *st, int32_t n_threads) {
-  int32_t nx = md->nx, nq = md->n_modes;
+static int nudged_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                        const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
+                        int32_t n_particles, int32_t n_steps, double ess_threshold,
+                        int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                        const orc_lbfgs_opts *opt, double *m, double *u, double *m0_out,
+                        double *u0_out, double *dW_out, double *dLam_out, double *J_out,
+                        orc_cycle_stats *st, int32_t n_threads) {
+  int32_t nx = md->nx, nq = mt ? md->nx : md->n_modes;
   size_t state = (size_t)n_particles * nx, wlen = (size_t)n_particles * n_steps * nq;
   double *m0 = (double *)malloc(sizeof(double) * state), *u0 = (double *)malloc(sizeof(double) * state);
   double *dW = (double *)malloc(sizeof(double) * wlen);
@@ -1869,8 +1877,8 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
 
   orc_draw_increments(seed, n_particles, n_steps, nq, cycle * (uint32_t)n_steps, ORC_TAG_NUDGE,
                       0u, md->dt, dW);
-  orc_nudge_ensemble(md, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam, opt, logG, NULL,
-                     NULL, NULL, stat, n_threads);
+  nudge_ensemble(md, mt, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam, opt, logG, NULL,
+                 NULL, NULL, stat, n_threads);
   for (int32_t p = 0; p < n_particles; ++p) {
     double phi = stat[p] == ORC_OK ? orc_nll(nx, n_obs, u + (size_t)p * nx, y, sigma) : INFINITY;
     J[p] = (isfinite(phi) && isfinite(logG[p])) ? phi - logG[p] : INFINITY;
@@ -1902,8 +1910,12 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
     gather_rows(dLam, idx, n_particles, (size_t)n_steps * nq);
     gather_rows(J, idx, n_particles, 1);
     orc_rng rg = {seed, cycle, (uint32_t)k};
-    orc_jitter_pcn_ctrl(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, dLam, J, m, u,
-                        theta_new, rho, n_jitter, acc, n_threads);
+    if (mt)
+      jitter_matern(md, mt, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, dLam, J, m,
+                    u, theta_new, rho, n_jitter, acc, n_threads);
+    else
+      orc_jitter_pcn_ctrl(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, dLam, J, m,
+                          u, theta_new, rho, n_jitter, acc, n_threads);
     for (int32_t p = 0; p < n_particles; ++p) st->n_accept += acc[p];
     st->ess = ess;
     theta = theta_new;
@@ -1929,6 +1941,32 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
   return rc;
 }
 
+int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                     uint64_t seed, uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                     double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                     int32_t max_temper, const orc_lbfgs_opts *opt, double *m, double *u,
+                     double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
+                     double *J_out, orc_cycle_stats *st, int32_t n_threads) {
+  return nudged_cycle(md, NULL, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
+                      n_bisect, rho, n_jitter, max_temper, opt, m, u, m0_out, u0_out, dW_out,
+                      dLam_out, J_out, st, n_threads);
+}
+
+/* orc_nudged_cycle with the Matern-type noise: the NUDGE-tag draws, the
+ * controls and the jitter act on the cells ([n][n_steps][nx]); the window,
+ * its gradient and the pCN moves use the Matern field of dW + dLam. */
+int orc_nudged_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                            const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
+                            int32_t n_particles, int32_t n_steps, double ess_threshold,
+                            int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                            const orc_lbfgs_opts *opt, double *m, double *u, double *m0_out,
+                            double *u0_out, double *dW_out, double *dLam_out, double *J_out,
+                            orc_cycle_stats *st, int32_t n_threads) {
+  return nudged_cycle(md, mt, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
+                      n_bisect, rho, n_jitter, max_temper, opt, m, u, m0_out, u0_out, dW_out,
+                      dLam_out, J_out, st, n_threads);
+}
+
 /* ========================================================================== */
 /* Tempered + jittered filter with the Matern-type noise of section 2: the     */
 /* increments are the cell values Delta W_i of the DG0 white noise per step    */
@@ -1936,31 +1974,40 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
 /* exactly as the mode increments of orc_tempered_cycle (the pCN proposal and  */
 /* its counters with nx in place of the number of modes).                      */
 /* ========================================================================== */
-int orc_jitter_pcn_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
-                          const double *y, const double *sigma, const orc_rng *rng,
-                          int32_t n_particles, int32_t n_steps, const double *m0,
-                          const double *u0, double *dWc, double *phi, double *m_end,
-                          double *u_end, double theta, double rho, int32_t n_jitter,
-                          int32_t *n_accept, int32_t n_threads) {
+/* pCN moves of the cell increments; with controls lam (the nudged filter,
+ * section 3.1.3) the window runs with the cells dW' + lam and the potential is
+ * the nudged J of orc_nudged_potential summed over the cells, as in
+ * orc_jitter_pcn_ctrl. */
+static int jitter_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                         const double *y, const double *sigma, const orc_rng *rng,
+                         int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
+                         double *dWc, const double *dLamc, double *phi, double *m_end,
+                         double *u_end, double theta, double rho, int32_t n_jitter,
+                         int32_t *n_accept, int32_t n_threads) {
   int32_t nx = md->nx;
 #pragma omp parallel for num_threads(n_threads > 0 ? n_threads : 1) schedule(dynamic, 1)
   for (int32_t p = 0; p < n_particles; ++p) {
     size_t wlen = (size_t)n_steps * nx;
     double *prop = (double *)malloc(sizeof(double) * wlen);
+    double *cells = dLamc ? (double *)malloc(sizeof(double) * wlen) : prop;
     double *mm = (double *)malloc(sizeof(double) * nx);
     double *uu = (double *)malloc(sizeof(double) * nx);
     double *cur = dWc + (size_t)p * wlen;
+    const double *lam = dLamc ? dLamc + (size_t)p * wlen : NULL;
     int32_t acc = 0;
     for (int32_t j = 0; j < n_jitter; ++j) {
       uint32_t w3 = (rng->temper_k << 16) | (uint32_t)j;
       orc_pcn_propose(rng->seed, (uint32_t)p, rng->cycle * (uint32_t)n_steps, n_steps, nx, w3,
                       rho, md->dt, cur, prop);
+      if (lam)
+        for (size_t i = 0; i < wlen; ++i) cells[i] = prop[i] + lam[i];
       memcpy(mm, m0 + (size_t)p * nx, sizeof(double) * nx);
       memcpy(uu, u0 + (size_t)p * nx, sizeof(double) * nx);
       int32_t it = 0;
-      int st = orc_window_matern(md, mt, n_steps, mm, uu, prop, &it);
+      int st = orc_window_matern(md, mt, n_steps, mm, uu, cells, &it);
       double phi_new = st == ORC_OK ? orc_nll(nx, n_obs, uu, y, sigma) : INFINITY;
       if (!isfinite(phi_new)) phi_new = INFINITY;
+      if (lam) phi_new = orc_nudged_potential(phi_new, (int32_t)wlen, md->dt, prop, lam);
       double v = orc_uniform(rng->seed, (uint32_t)p, rng->cycle,
                              (uint32_t)ORC_TAG_ACCEPT << 24, w3);
       if (orc_pcn_accept(theta, phi[p], phi_new, v)) {
@@ -1972,11 +2019,32 @@ int orc_jitter_pcn_matern(const orc_model *md, const orc_matern *mt, int32_t n_o
       }
     }
     if (n_accept) n_accept[p] = acc;
+    if (cells != prop) free(cells);
     free(prop);
     free(mm);
     free(uu);
   }
   return ORC_OK;
+}
+
+int orc_jitter_pcn_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, const orc_rng *rng,
+                          int32_t n_particles, int32_t n_steps, const double *m0,
+                          const double *u0, double *dWc, double *phi, double *m_end,
+                          double *u_end, double theta, double rho, int32_t n_jitter,
+                          int32_t *n_accept, int32_t n_threads) {
+  return jitter_matern(md, mt, n_obs, y, sigma, rng, n_particles, n_steps, m0, u0, dWc, NULL,
+                       phi, m_end, u_end, theta, rho, n_jitter, n_accept, n_threads);
+}
+
+int orc_jitter_pcn_matern_ctrl(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                               const double *y, const double *sigma, const orc_rng *rng,
+                               int32_t n_particles, int32_t n_steps, const double *m0,
+                               const double *u0, double *dWc, const double *dLamc, double *J,
+                               double *m_end, double *u_end, double theta, double rho,
+                               int32_t n_jitter, int32_t *n_accept, int32_t n_threads) {
+  return jitter_matern(md, mt, n_obs, y, sigma, rng, n_particles, n_steps, m0, u0, dWc, dLamc, J,
+                       m_end, u_end, theta, rho, n_jitter, n_accept, n_threads);
 }
 
 /* One cycle: draw the cell increments (tag FORECAST, counter (p, cycle *

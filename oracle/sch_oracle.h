@@ -243,6 +243,26 @@ int orc_jitter_pcn_matern(const orc_model *md, const orc_matern *mt, int32_t n_o
                           const double *u0, double *dWc, double *phi, double *m_end,
                           double *u_end, double theta, double rho, int32_t n_jitter,
                           int32_t *n_accept, int32_t n_threads);
+
+/* orc_jitter_pcn_matern with the per-cell controls dLamc fixed (the nudged
+ * filter): the window runs with dWc' + dLamc and J (in/out) is the nudged
+ * potential. */
+int orc_jitter_pcn_matern_ctrl(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                               const double *y, const double *sigma, const orc_rng *rng,
+                               int32_t n_particles, int32_t n_steps, const double *m0,
+                               const double *u0, double *dWc, const double *dLamc, double *J,
+                               double *m_end, double *u_end, double theta, double rho,
+                               int32_t n_jitter, int32_t *n_accept, int32_t n_threads);
+
+/* orc_nudged_cycle with the Matern-type noise: increments and controls per
+ * cell, [n][n_steps][nx]. */
+int orc_nudged_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                            const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
+                            int32_t n_particles, int32_t n_steps, double ess_threshold,
+                            int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                            const orc_lbfgs_opts *opt, double *m, double *u, double *m0_out,
+                            double *u0_out, double *dW_out, double *dLam_out, double *J_out,
+                            orc_cycle_stats *st, int32_t n_threads);
 int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
                               const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
                               int32_t n_particles, int32_t n_steps, double ess_threshold,
