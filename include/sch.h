@@ -502,6 +502,19 @@ int sch_nudge_run_matern(const sch_model *model, const sch_matern *mt, const sch
                          int32_t *lbfgs_status, int32_t *iters, int32_t *evals,
                          int32_t *status, void *workspace, void *stream);
 
+/* sch_jitter_pcn_matern with per-cell controls dLambdac [n][n_steps][nx]
+ * held fixed (the jittering of the nudged filter, section 3.1.3): the window
+ * runs with the cells dWc' + dLambdac and J (in/out) is the nudged potential
+ * phi + sum over the cells of (dLambda^2 / 2 + dLambda dW') / dt.  Proposals,
+ * uniforms and workspace as sch_jitter_pcn_matern.  SCH_E_ARG without
+ * dLambdac. */
+int sch_jitter_pcn_matern_ctrl(const sch_model *model, const sch_matern *mt, const sch_obs *obs,
+                               const sch_rng *rng, int32_t n_particles, int32_t n_steps,
+                               const double *m0, const double *u0, double *dWc,
+                               const double *dLambdac, double *J, double *m_end, double *u_end,
+                               const double *theta, double rho, int32_t n_jitter,
+                               int32_t *n_accept, void *workspace, void *stream);
+
 /* sch_pf_bootstrap_cycle with the Matern-type noise: cell increments drawn as
  * sch_draw_increments with nx values per step (tag FORECAST), the Matern
  * window, likelihood weights and conditional resampling as
@@ -524,6 +537,25 @@ int sch_pf_tempered_cycle_matern(const sch_model *model, const sch_matern *mt,
                                  int32_t n_bisect, double rho, int32_t n_jitter,
                                  int32_t max_temper, double *m, double *u, void *workspace,
                                  sch_cycle_stats *stats, void *stream);
+
+/* sch_pf_nudged_cycle with the Matern-type noise (section 3.1.3 with the
+ * noise of section 2): the NUDGE-tag cell increments (nx per step), the
+ * stage-wise nudging of sch_nudge_run_matern from zero controls, tempering on
+ * J = phi - log G (the Girsanov term summed over the cells), resampling, and
+ * pCN moves of the cells with the per-cell controls held fixed (the window
+ * runs with the cells dW' + dLambda).  dLambdac out [n][n_steps][nx]: the
+ * resampled controls.  workspace >= sch_nudged_workspace_bytes_matern(model,
+ * n, n_steps, n_jitter, ckpt_every).  Errors as sch_pf_nudged_cycle, plus
+ * SCH_E_ARG for a bad sch_matern. */
+size_t sch_nudged_workspace_bytes_matern(const sch_model *model, int32_t n_particles,
+                                         int32_t n_steps, int32_t n_jitter, int32_t ckpt_every);
+int sch_pf_nudged_cycle_matern(const sch_model *model, const sch_matern *mt, const sch_obs *obs,
+                               uint64_t seed, uint32_t cycle, int32_t n_particles,
+                               int32_t n_steps, double ess_threshold, int32_t n_bisect,
+                               double rho, int32_t n_jitter, int32_t max_temper,
+                               const sch_lbfgs_opts *opts, int32_t ckpt_every, double *m,
+                               double *u, double *dLambdac, void *workspace,
+                               sch_cycle_stats *stats, void *stream);
 
 /* --------------------------------------------------------------------------
  * The paper's twin experiments (section 4).

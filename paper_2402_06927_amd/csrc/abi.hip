@@ -287,7 +287,9 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
     if (kStatic + dyn > 160 * 1024)
       return fail(SCH_E_SHAPE, "n_steps * n_modes too large for the jitter kernel at nx = %d",
                   md.nx);
-    if (M)
+    if (M && dLam)
+      hipLaunchKernelGGL((k_jitter<PM, NT, FULL, true, true>), dim3(n), dim3(NT), 0, st, A, K);
+    else if (M)
       hipLaunchKernelGGL((k_jitter<PM, NT, FULL, true>), dim3(n), dim3(NT), 0, st, A, K);
     else
       hipLaunchKernelGGL((k_jitter<PM, NT, FULL>), dim3(n), dim3(NT), dyn, st, A, K);
@@ -936,34 +938,36 @@ int sch_pf_tempered_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed,
                      max_temper, m, u, nullptr, W, stats, st);
 }
 
-size_t sch_nudged_workspace_bytes(const sch_model* md, int32_t n, int32_t n_steps,
-                                  int32_t n_jitter, int32_t ckpt_every) {
-  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 || ckpt_every < 1) return 0;
-  size_t a = 0, b = 0;
-  carve_cycle(nullptr, SCH_WS_TEMPERED, md->nx, md->n_modes, n, n_steps, &a, n_jitter);
-  carve_nudge(nullptr, true, md->nx, md->n_modes, n, n_steps, ckpt_every, &b);
-  return ((a + 255) & ~size_t(255)) + ((b + 255) & ~size_t(255)) +
+}  // extern "C"
+
+namespace {
+// Scratch of the nudged cycle: the tempered cycle's, then the nudging's, then
+// log G [n]; q controls per step (n_modes, or nx for the Matern-type noise).
+size_t nudged_bytes(const sch_model& md, int n, int n_steps, int n_jitter, int ce, bool matern,
+                    size_t* a, size_t* b) {
+  const int q = matern ? md.nx : md.n_modes;
+  carve_cycle(nullptr, SCH_WS_TEMPERED, md.nx, q, n, n_steps, a, n_jitter, matern ? 1 : 0);
+  carve_nudge(nullptr, true, md.nx, q, n, n_steps, ce, b);
+  return ((*a + 255) & ~size_t(255)) + ((*b + 255) & ~size_t(255)) +
          static_cast<size_t>(n) * sizeof(double) + 256;
 }
 
-int sch_pf_nudged_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
-                        int32_t n, int32_t n_steps, double thr, int32_t n_bisect, double rho,
-                        int32_t n_jitter, int32_t max_temper, const sch_lbfgs_opts* opts,
-                        int32_t ckpt_every, double* m, double* u, double* dLambda,
-                        void* workspace, sch_cycle_stats* stats, void* stream) {
-  Tile tl;
-  if (int rc = check_model(md, tl)) return rc;
-  if (int rc = check_obs(ob)) return rc;
-  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !dLambda || !workspace || !stats ||
-      !opts || n_bisect < 0 || max_temper < 1 || !(rho >= 0 && rho <= 1) || n_jitter < 0 ||
-      ckpt_every < 1)
-    return fail(SCH_E_ARG, "bad arguments to sch_pf_nudged_cycle");
+// The nudged filter's cycle (section 3.1.3, last paragraph, with the
+// tempering and jittering of section 3.1.2) with the modes-form noise
+// (M == null) or the Matern-type noise (M != null: cells and controls per
+// cell).
+int nudged_cycle(const sch_model* md, const Tile& tl, const sch_obs* ob, uint64_t seed,
+                 uint32_t cycle, int32_t n, int32_t n_steps, double thr, int32_t n_bisect,
+                 double rho, int32_t n_jitter, int32_t max_temper, const sch_lbfgs_opts* opts,
+                 int32_t ckpt_every, double* m, double* u, double* dLambda, void* workspace,
+                 sch_cycle_stats* stats, void* stream, const MaternDev* M) {
   hipStream_t st = S(stream);
-  const int nx = md->nx, Q = md->n_modes;
+  const int nx = md->nx, Q = M ? md->nx : md->n_modes;
   const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
   size_t a = 0, b = 0;
-  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, &a, n_jitter);
-  carve_nudge(nullptr, true, nx, Q, n, n_steps, ckpt_every, &b);
+  nudged_bytes(*md, n, n_steps, n_jitter, ckpt_every, M != nullptr, &a, &b);
+  CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, nullptr, n_jitter,
+                          M ? 1 : 0);
   char* nws = static_cast<char*>(workspace) + ((a + 255) & ~size_t(255));
   double* logG = reinterpret_cast<double*>(nws + ((b + 255) & ~size_t(255)));
   *stats = sch_cycle_stats{};
@@ -984,8 +988,8 @@ int sch_pf_nudged_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, u
   }
   // sequential nudging of the window from zero controls: (m, u) become the
   // nudged window ends, W.status the window statuses
-  if (int rc = sch_nudge_run(md, ob, n, n_steps, m, u, W.dW, dLambda, 0, opts, ckpt_every, logG,
-                             nullptr, nullptr, nullptr, W.status, nws, stream))
+  if (int rc = nudge_run(md, tl, ob, n, n_steps, m, u, W.dW, dLambda, 0, opts, ckpt_every, logG,
+                         nullptr, nullptr, nullptr, W.status, nws, stream, M))
     return rc;
   {
     TimedScope ts(SCH_TK_OTHER, st);
@@ -995,7 +999,34 @@ int sch_pf_nudged_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, u
     CHECK_LAUNCH();
   }
   return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
-                     max_temper, m, u, dLambda, W, stats, st);
+                     max_temper, m, u, dLambda, W, stats, st, M);
+}
+}  // namespace
+
+extern "C" {
+
+size_t sch_nudged_workspace_bytes(const sch_model* md, int32_t n, int32_t n_steps,
+                                  int32_t n_jitter, int32_t ckpt_every) {
+  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 || ckpt_every < 1) return 0;
+  size_t a = 0, b = 0;
+  return nudged_bytes(*md, n, n_steps, n_jitter, ckpt_every, false, &a, &b);
+}
+
+int sch_pf_nudged_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, uint32_t cycle,
+                        int32_t n, int32_t n_steps, double thr, int32_t n_bisect, double rho,
+                        int32_t n_jitter, int32_t max_temper, const sch_lbfgs_opts* opts,
+                        int32_t ckpt_every, double* m, double* u, double* dLambda,
+                        void* workspace, sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !dLambda || !workspace || !stats ||
+      !opts || n_bisect < 0 || max_temper < 1 || !(rho >= 0 && rho <= 1) || n_jitter < 0 ||
+      ckpt_every < 1)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_nudged_cycle");
+  return nudged_cycle(md, tl, ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                      max_temper, opts, ckpt_every, m, u, dLambda, workspace, stats, stream,
+                      nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1080,11 +1111,40 @@ int sch_nudge_run_matern(const sch_model* md, const sch_matern* mt, const sch_ob
                    lbfgs_status, iters, evals, status, workspace, stream, &M);
 }
 
-int sch_jitter_pcn_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
-                          const sch_rng* rng, int32_t n, int32_t n_steps, const double* m0,
-                          const double* u0, double* dWc, double* phi, double* m_end,
-                          double* u_end, const double* theta, double rho, int32_t n_jitter,
-                          int32_t* n_accept, void* workspace, void* stream) {
+size_t sch_nudged_workspace_bytes_matern(const sch_model* md, int32_t n, int32_t n_steps,
+                                         int32_t n_jitter, int32_t ckpt_every) {
+  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 || ckpt_every < 1) return 0;
+  size_t a = 0, b = 0;
+  return nudged_bytes(*md, n, n_steps, n_jitter, ckpt_every, true, &a, &b);
+}
+
+int sch_pf_nudged_cycle_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
+                               uint64_t seed, uint32_t cycle, int32_t n, int32_t n_steps,
+                               double thr, int32_t n_bisect, double rho, int32_t n_jitter,
+                               int32_t max_temper, const sch_lbfgs_opts* opts, int32_t ckpt_every,
+                               double* m, double* u, double* dLambdac, void* workspace,
+                               sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  MaternDev M;
+  if (int rc = make_matern(*md, mt, tl, M)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !dLambdac || !workspace || !stats ||
+      !opts || n_bisect < 0 || max_temper < 1 || !(rho >= 0 && rho <= 1) || n_jitter < 0 ||
+      ckpt_every < 1)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_nudged_cycle_matern");
+  return nudged_cycle(md, tl, ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                      max_temper, opts, ckpt_every, m, u, dLambdac, workspace, stats, stream, &M);
+}
+
+}  // extern "C"
+
+namespace {
+int jitter_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
+                  const sch_rng* rng, int32_t n, int32_t n_steps, const double* m0,
+                  const double* u0, double* dWc, double* phi, double* m_end, double* u_end,
+                  const double* theta, double rho, int32_t n_jitter, int32_t* n_accept,
+                  void* workspace, void* stream, const double* dLamc) {
   Tile tl;
   if (int rc = check_model(md, tl)) return rc;
   if (int rc = check_obs(ob)) return rc;
@@ -1099,7 +1159,30 @@ int sch_jitter_pcn_matern(const sch_model* md, const sch_matern* mt, const sch_o
                           n_jitter, 1);
   return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
                        dWc, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
-                       W.zeta, nullptr, nullptr, S(stream), &M);
+                       W.zeta, nullptr, dLamc, S(stream), &M);
+}
+}  // namespace
+
+extern "C" {
+
+int sch_jitter_pcn_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
+                          const sch_rng* rng, int32_t n, int32_t n_steps, const double* m0,
+                          const double* u0, double* dWc, double* phi, double* m_end,
+                          double* u_end, const double* theta, double rho, int32_t n_jitter,
+                          int32_t* n_accept, void* workspace, void* stream) {
+  return jitter_matern(md, mt, ob, rng, n, n_steps, m0, u0, dWc, phi, m_end, u_end, theta, rho,
+                       n_jitter, n_accept, workspace, stream, nullptr);
+}
+
+int sch_jitter_pcn_matern_ctrl(const sch_model* md, const sch_matern* mt, const sch_obs* ob,
+                               const sch_rng* rng, int32_t n, int32_t n_steps, const double* m0,
+                               const double* u0, double* dWc, const double* dLamc, double* J,
+                               double* m_end, double* u_end, const double* theta, double rho,
+                               int32_t n_jitter, int32_t* n_accept, void* workspace,
+                               void* stream) {
+  if (!dLamc) return fail(SCH_E_ARG, "sch_jitter_pcn_matern_ctrl needs the controls");
+  return jitter_matern(md, mt, ob, rng, n, n_steps, m0, u0, dWc, J, m_end, u_end, theta, rho,
+                       n_jitter, n_accept, workspace, stream, dLamc);
 }
 
 int sch_pf_bootstrap_cycle_matern(const sch_model* md, const sch_matern* mt, const sch_obs* ob,

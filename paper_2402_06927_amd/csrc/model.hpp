@@ -479,7 +479,7 @@ struct JitterArgs {
   const double* sigma;
   const double* zeta;  // [n_jitter][n][n_steps][n_modes]: sqrt(dt) z of the proposals
   const double* vacc;  // [n_jitter][n]: acceptance uniforms
-  const double* dLam;  // [n][n_steps][n_modes] fixed controls, or null
+  const double* dLam;  // [n][n_steps][n_modes] (Matern: [n][n_steps][nx]) fixed controls, or null
   // Matern-type noise (MATERN kernels): the increments are the cells
   // dW [n][n_steps][nx]; proposals and uniforms are drawn in the kernel, the
   // proposal rows go to stage [n][n_steps][nx]
@@ -543,8 +543,10 @@ __device__ __forceinline__ void pcn_cells(uint64_t seed, uint32_t c0, uint32_t c
 // MATERN: the increments are the DG0 cell values of the Matern-type noise;
 // each thread proposes its own cells step by step inside the window and
 // writes them to the stage row, and an acceptance swaps the roles of the
-// particle's stage and increment rows (one copy back at the end if needed).
-template <int PMAX, int NT, bool FULL, bool MATERN = false>
+// particle's stage and increment rows (one copy back at the end if needed);
+// the per-cell controls are read only in the MCTRL variant, so that the
+// variant without them keeps its registers.
+template <int PMAX, int NT, bool FULL, bool MATERN = false, bool MCTRL = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_jitter(const JitterArgs A, const HelmConst K) {
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
@@ -581,7 +583,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     double m[PMAX], u[PMAX];
     load_chunk<PMAX, FULL>(A.m0 + static_cast<size_t>(p) * nx, ch, m);
     load_chunk<PMAX, FULL>(A.u0 + static_cast<size_t>(p) * nx, ch, u);
-    const double* lam = A.dLam ? A.dLam + static_cast<size_t>(p) * S * Q : nullptr;
+    const double* lam = (MATERN && !MCTRL) || !A.dLam
+                            ? nullptr
+                            : A.dLam + static_cast<size_t>(p) * S * (MATERN ? nx : Q);
     int st;
     if constexpr (MATERN) {
       const double sdt = sqrt(A.P.dt);
@@ -593,7 +597,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
                               w3, ch, A.rho, srho, sdt, cur + off, w);
 #pragma unroll
         for (int jj = 0; jj < PMAX; ++jj)
-          if (FULL || jj < ch.cnt) prop[off + jj] = w[jj];
+          if (FULL || jj < ch.cnt) {
+            prop[off + jj] = w[jj];
+            if (lam) w[jj] += lam[off + jj];  // the window sees dW' + dLambda
+          }
         matern_add<PMAX, NT, FULL>(A.M, w, e, ch, L, t, par);
       };
       st = run_window<PMAX, NT, FULL, false>(A.P, K, noise, S, m, u, ch, L, X, t, par, iters);
@@ -608,9 +615,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     }
     double girs = 0.0;  // this thread's share of the Girsanov term (after the window: not
                         // live across the solver loop)
-    if (!MATERN && lam) {
+    if (lam) {
       const double idt = 1.0 / A.P.dt;
-      for (int i = t; i < S * Q; i += NT) girs += (0.5 * lam[i] * lam[i] + lam[i] * prop[i]) * idt;
+      if constexpr (MATERN) {
+        // over the thread's own cells, which it wrote to the stage row itself
+        for (int n = 0; n < S; ++n) {
+          const size_t off = static_cast<size_t>(n) * nx + ch.start;
+          for (int jj = 0; jj < ch.cnt; ++jj)
+            girs += (0.5 * lam[off + jj] * lam[off + jj] + lam[off + jj] * prop[off + jj]) * idt;
+        }
+      } else {
+        for (int i = t; i < S * Q; i += NT)
+          girs += (0.5 * lam[i] * lam[i] + lam[i] * prop[i]) * idt;
+      }
     }
     bool accept = false;
     double phin;

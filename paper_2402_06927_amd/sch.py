@@ -185,6 +185,12 @@ def _declare(L):
         "sch_nudge_run_matern": (C.c_int, [M, MT, O, i32, i32, _vp, _vp, _vp, _vp, i32,
                                            C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp, _vp, _vp,
                                            _vp, _vp]),
+        "sch_nudged_workspace_bytes_matern": (C.c_size_t, [M, i32, i32, i32, i32]),
+        "sch_jitter_pcn_matern_ctrl": (C.c_int, [M, MT, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp,
+                                                 _vp, _vp, _vp, f64, i32, _vp, _vp, _vp]),
+        "sch_pf_nudged_cycle_matern": (C.c_int, [M, MT, O, u64, u32, i32, i32, f64, i32, f64, i32,
+                                                 i32, C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp,
+                                                 _vp, ST, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -210,7 +216,8 @@ def exported_names():
         "sch_matern_workspace_bytes", "sch_jitter_pcn_matern", "sch_pf_tempered_cycle_matern",
         "sch_pf_bootstrap_cycle_matern", "sch_paper_init", "sch_ensemble_stats",
         "sch_pcnl_workspace_bytes", "sch_jitter_pcnl", "sch_pf_tempered_cycle_pcnl",
-        "sch_nudge_grad_matern", "sch_nudge_run_matern",
+        "sch_nudge_grad_matern", "sch_nudge_run_matern", "sch_nudged_workspace_bytes_matern",
+        "sch_pf_nudged_cycle_matern", "sch_jitter_pcn_matern_ctrl",
     ]
 
 
@@ -471,6 +478,30 @@ def sch_jitter_pcn_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: 
                                        _dev(workspace, torch.uint8, "workspace"), _stream()))
 
 
+def sch_jitter_pcn_matern_ctrl(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
+                               temper_k: int, m0: torch.Tensor, u0: torch.Tensor,
+                               dWc: torch.Tensor, dLambdac: torch.Tensor, J: torch.Tensor,
+                               m_end: torch.Tensor, u_end: torch.Tensor, theta: torch.Tensor,
+                               rho: float, n_jitter: int, n_accept: torch.Tensor | None = None,
+                               workspace: torch.Tensor | None = None):
+    """sch_jitter_pcn_matern with the per-cell controls dLambdac held fixed;
+    J holds the nudged potentials."""
+    mc, tc, oc = model.c(), mt.c(), obs.c()
+    r = SchRngC(seed, cycle, temper_k)
+    n, s = dWc.shape[0], dWc.shape[1]
+    if workspace is None:
+        workspace = matern_workspace(WS_JITTER, model, n, s, n_jitter)
+    _check(lib().sch_jitter_pcn_matern_ctrl(C.byref(mc), C.byref(tc), C.byref(oc), C.byref(r), n,
+                                            s, _dev(m0, name="m0"), _dev(u0, name="u0"),
+                                            _dev(dWc, name="dWc"),
+                                            _dev(dLambdac, name="dLambdac"), _dev(J, name="J"),
+                                            _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
+                                            _dev(theta, name="theta"), rho, n_jitter,
+                                            _dev(n_accept, torch.int32, "n_accept"),
+                                            _dev(workspace, torch.uint8, "workspace"),
+                                            _stream()))
+
+
 def sch_pf_tempered_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
                                  m: torch.Tensor, u: torch.Tensor, n_steps: int,
                                  ess_threshold: float, n_bisect: int, rho: float, n_jitter: int,
@@ -678,6 +709,37 @@ def sch_pf_nudged_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.
                                      _dev(u, name="u"), _dev(dLambda, name="dLambda"),
                                      _dev(workspace, torch.uint8, "workspace"), C.byref(st),
                                      _stream()))
+    return st.as_dict()
+
+
+def nudged_workspace_matern(model: Model, n_particles: int, n_steps: int, n_jitter: int,
+                            ckpt_every: int = 8, device="cuda") -> torch.Tensor:
+    mc = model.c()
+    nb = int(lib().sch_nudged_workspace_bytes_matern(C.byref(mc), n_particles, n_steps,
+                                                     n_jitter, ckpt_every))
+    if nb <= 0:
+        raise SchError(SCH_E_ARG, "invalid workspace request")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def sch_pf_nudged_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
+                               m: torch.Tensor, u: torch.Tensor, dLambdac: torch.Tensor,
+                               n_steps: int, ess_threshold: float, n_bisect: int, rho: float,
+                               n_jitter: int, max_temper: int, workspace: torch.Tensor,
+                               gtol: float = LBFGS_GTOL, max_iter: int = LBFGS_MAX_ITER,
+                               mem: int = LBFGS_MEM, max_back: int = LBFGS_MAX_BACK,
+                               ckpt_every: int = 8) -> dict:
+    """sch_pf_nudged_cycle with the Matern-type noise; dLambdac [n][n_steps][nx]."""
+    mc, tc, oc = model.c(), mt.c(), obs.c()
+    st = SchCycleStats()
+    opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
+    _check(lib().sch_pf_nudged_cycle_matern(C.byref(mc), C.byref(tc), C.byref(oc), seed, cycle,
+                                            m.shape[0], n_steps, ess_threshold, n_bisect, rho,
+                                            n_jitter, max_temper, C.byref(opts), ckpt_every,
+                                            _dev(m, name="m"), _dev(u, name="u"),
+                                            _dev(dLambdac, name="dLambdac"),
+                                            _dev(workspace, torch.uint8, "workspace"),
+                                            C.byref(st), _stream()))
     return st.as_dict()
 
 

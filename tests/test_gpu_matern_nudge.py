@@ -1,12 +1,16 @@
-"""GPU (C-ABI) versus oracle for nudging with the Matern-type noise (section
-3.1.3 with the noise of section 2): one control per cell and step, the
-objective's gradient through the transpose of the Matern map, and the
-stage-wise L-BFGS nudging with per-cell controls.
+"""GPU (C-ABI) versus oracle for nudging and the nudged filter with the
+Matern-type noise (section 3.1.3 with the noise of section 2): one control per
+cell and step, the objective's gradient through the transpose of the Matern
+map, the stage-wise L-BFGS nudging with per-cell controls, the pCN moves of
+the cells with the controls fixed, and the whole nudged cycle.
 
 Bars as for the modes form: J and the gradient within relative L2 1e-10 of
 the oracle's reverse sweep; the L-BFGS controls within 1e-6 of their scale
 (two runs of one deterministic optimiser whose gradients differ by rounding
-can stop one iteration apart), the window-end states within 1e-8."""
+can stop one iteration apart), the window-end states within 1e-8 after
+nudging and 1e-6 after a nudged cycle with data; the controlled moves with
+identical acceptance decisions and potentials and states at 1e-10; the
+no-data cycle at 1e-10."""
 import sys
 from dataclasses import replace
 
@@ -199,3 +203,92 @@ def test_nudge_matern_argument_errors(sch):
     a = lib.sch_matern_workspace_bytes(sch.WS_NUDGE_GRAD, C.byref(mc), n, s, 4)
     b = lib.sch_matern_workspace_bytes(sch.WS_NUDGE, C.byref(mc), n, s, 4)
     assert 0 < a < b
+
+
+@pytest.mark.parametrize("nx,n,s,theta", [(100, 8, 5, 0.7), (600, 6, 4, 1.0), (4096, 4, 6, 0.5)])
+def test_jitter_matern_with_controls_parity(sch, nx, n, s, theta):
+    """pCN moves of the cells with per-cell controls fixed: identical
+    acceptance counts, cells at 1e-12, potentials and states at 1e-10."""
+    _say("matern jitter with controls", nx, n, s, theta)
+    wl = _wl(nx, s, sigma_obs=0.02)
+    om, gm = PR.oracle_model(wl), PR.gpu_model(wl)
+    omt, gmt = _mt(sch, wl)
+    u0, m0, ut, _ = PR.prior(wl, n)
+    dW = O.draw_increments(wl.seed, n, s, nx, 0, O.TAG_NUDGE, 0, wl.dt)
+    dLam = 0.1 * np.sqrt(wl.dt) * np.random.default_rng(nx + n).standard_normal(dW.shape)
+    worst, m1, u1, _, _ = O.ensemble_window_matern(om, omt, m0, u0, dW + dLam)
+    assert worst == 0
+    y = O.observe(ut, wl.n_obs) + wl.sigma_obs * W.random_state_noise(wl.n_obs, 3)
+    sig = np.full(wl.n_obs, wl.sigma_obs)
+    phi = O.ensemble_nll(u1, y, sig)
+    J = np.array([O.nudged_potential(phi[p], wl.dt, dW[p], dLam[p]) for p in range(n)])
+    ref = O.jitter_pcn_matern_ctrl(om, omt, y, sig, wl.seed, 2, 3, m0, u0, dW, dLam, J, m1, u1,
+                                   theta, 0.95, 4)
+    assert 0 < ref[4].sum() < 4 * n
+    gdW, gJ, gm1, gu1, gl = T(dW), T(J), T(m1), T(u1), T(dLam)
+    acc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    sch.sch_jitter_pcn_matern_ctrl(gm, gmt, sch.Obs(T(y), T(sig)), wl.seed, 2, 3, T(m0), T(u0),
+                                   gdW, gl, gJ, gm1, gu1, T([theta]), 0.95, 4, acc)
+    assert np.array_equal(N(acc), ref[4])
+    assert PR.rel_l2(N(gdW), ref[0]) < 1e-12
+    assert PR.rel_l2(N(gJ), ref[1]) < PR.REL_TOL
+    assert PR.rel_l2(N(gm1), ref[2]) < PR.REL_TOL and PR.rel_l2(N(gu1), ref[3]) < PR.REL_TOL
+    np.testing.assert_array_equal(N(gl), dLam)  # the controls are read only
+
+
+def _gpu_nudged_cycle(sch, wl, m0, u0, y, sigma, n_jitter=3):
+    gm = PR.gpu_model(wl)
+    _, gmt = _mt(sch, wl)
+    n, s = wl.n_particles, wl.n_steps
+    m, u = T(m0), T(u0)
+    dl = torch.full((n, s, wl.nx), np.nan, dtype=torch.float64, device="cuda")
+    ws = sch.nudged_workspace_matern(gm, n, s, n_jitter, 4)
+    obs = sch.Obs(T(y), T(np.full(wl.n_obs, sigma)))
+    st = sch.sch_pf_nudged_cycle_matern(gm, gmt, obs, wl.seed, 0, m, u, dl, s, n / 2, 50, 0.9,
+                                        n_jitter, 50, ws, ckpt_every=4)
+    return st, N(m), N(u), N(dl)
+
+
+def _cycle_inputs(wl):
+    u0, m0, _, _ = PR.prior(wl, wl.n_particles)
+    y = PR.oracle_observations(wl, 1)[0]
+    return m0, u0, y
+
+
+def test_nudged_cycle_matern_without_data(sch):
+    """sigma -> infinity: both sides keep every control at exactly zero: one
+    tempering step, states at the 1e-10 bar."""
+    wl = _wl(64, 3, n_particles=12)
+    m0, u0, y = _cycle_inputs(wl)
+    om = PR.oracle_model(wl)
+    omt, _ = _mt(sch, wl)
+    rc, ref, st_o = O.nudged_cycle_matern(om, omt, y, 1e7, wl.seed, 0, m0, u0, wl.n_steps,
+                                          wl.n_particles / 2, 50, 0.9, 3, 50)
+    assert rc == 0
+    st, m, u, dl = _gpu_nudged_cycle(sch, wl, m0, u0, y, 1e7)
+    assert st["status"] == 0
+    assert st["n_temper"] == st_o.n_temper == 1
+    assert st["n_accept"] == st_o.n_accept
+    np.testing.assert_array_equal(dl, 0.0)
+    assert np.all(ref["dLam"] == 0.0)
+    assert PR.rel_l2(m, ref["m"]) < PR.REL_TOL and PR.rel_l2(u, ref["u"]) < PR.REL_TOL
+
+
+@pytest.mark.parametrize("nx,n,s", [(64, 12, 3), (130, 8, 3)])
+def test_nudged_cycle_matern_parity(sch, nx, n, s):
+    _say("matern nudged cycle", nx, n, s)
+    wl = _wl(nx, s, n_particles=n, sigma_obs=0.05)
+    m0, u0, y = _cycle_inputs(wl)
+    om = PR.oracle_model(wl)
+    omt, _ = _mt(sch, wl)
+    rc, ref, st_o = O.nudged_cycle_matern(om, omt, y, wl.sigma_obs, wl.seed, 0, m0, u0, s, n / 2,
+                                          50, 0.9, 3, 50)
+    assert rc == 0
+    st, m, u, dl = _gpu_nudged_cycle(sch, wl, m0, u0, y, wl.sigma_obs)
+    assert st["status"] == 0
+    _say("n_temper", st["n_temper"], st_o.n_temper, "accept", st["n_accept"], st_o.n_accept)
+    assert st["n_temper"] == st_o.n_temper
+    scale = np.abs(ref["dLam"]).max()
+    assert scale > 0
+    np.testing.assert_allclose(dl, ref["dLam"], rtol=0, atol=1e-6 * scale)
+    assert PR.rel_l2(m, ref["m"]) < 1e-6 and PR.rel_l2(u, ref["u"]) < 1e-6
