@@ -4,8 +4,9 @@ A truth run and an ensemble, both initialised by eq. init_solve
 (``sch_paper_init``), are advanced with the Matern-type noise; every
 ``n_steps`` model steps the truth is observed (P u + N(0, sigma^2) errors, on
 the whole grid or only the first ``n_observed`` points) and the filter
-assimilates the observation: the bootstrap filter of section 3.1.1 or the
-tempered + jittered filter of section 3.1.2.  After each assimilation step the
+assimilates the observation: the bootstrap filter of section 3.1.1, the
+tempered + jittered filter of section 3.1.2, or the nudged filter of section
+3.1.3 (nudging with one control per cell, then tempering and jittering).  After each assimilation step the
 ensemble is compared with the truth by EMRE, RB and RES (``sch_ensemble_stats``).
 Every step runs in the library's kernels; this module only sequences the
 calls and collects the per-step numbers.
@@ -28,6 +29,10 @@ from . import sch
 from . import workloads as W
 
 
+FILTERS = ("tempered", "bootstrap", "nudged")
+NUDGE_CKPT = 5  # checkpoint interval of the nudging adjoint (steps)
+
+
 def make_model(wl: W.Workload, device="cuda") -> sch.Model:
     xi = torch.tensor(W.mode_table(wl.L, wl.nx, wl.n_modes, wl.mode_amp), device=device)
     return sch.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi,
@@ -36,12 +41,12 @@ def make_model(wl: W.Workload, device="cuda") -> sch.Model:
 
 def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0) -> dict:
     """n_da assimilation steps of the twin experiment wl with the filter
-    "tempered" or "bootstrap".  Returns per-step EMRE, RB, RES, the tempering
+    "tempered", "bootstrap" or "nudged".  Returns per-step EMRE, RB, RES, the tempering
     steps (tempered) or resampling flags (bootstrap), the ESS, the particles
     whose forecast failed (zero weight), and the final ensemble and truth as
     numpy arrays."""
-    if filt not in ("tempered", "bootstrap"):
-        raise ValueError("filter must be 'tempered' or 'bootstrap'")
+    if filt not in FILTERS:
+        raise ValueError("filter must be one of " + ", ".join(FILTERS))
     if wl.noise != "matern":
         raise ValueError("the paper's experiments use the Matern-type noise")
     dev = "cuda"
@@ -63,6 +68,9 @@ def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0) -> dict:
     y = torch.empty((1, wl.n_obs), dtype=torch.float64, device=dev)
     if filt == "tempered":
         ws = sch.matern_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
+    elif filt == "nudged":
+        ws = sch.nudged_workspace_matern(model, n, S, wl.n_jitter, NUDGE_CKPT)
+        dlam = torch.zeros((n, S, nx), dtype=torch.float64, device=dev)
     else:
         ws = sch.matern_workspace(sch.WS_BOOTSTRAP, model, n, S, 0)
         logw = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -82,6 +90,12 @@ def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0) -> dict:
             st = sch.sch_pf_tempered_cycle_matern(model, mt, obs, wl.seed, c, m, u, S,
                                                   wl.ess_threshold, wl.n_bisect, wl.rho,
                                                   wl.n_jitter, wl.max_temper, ws)
+            n_temper.append(st["n_temper"])
+        elif filt == "nudged":
+            st = sch.sch_pf_nudged_cycle_matern(model, mt, obs, wl.seed, c, m, u, dlam, S,
+                                                wl.ess_threshold, wl.n_bisect, wl.rho,
+                                                wl.n_jitter, wl.max_temper, ws,
+                                                ckpt_every=NUDGE_CKPT)
             n_temper.append(st["n_temper"])
         else:
             st = sch.sch_pf_bootstrap_cycle_matern(model, mt, obs, wl.seed, c, m, u, logw, S,
@@ -129,7 +143,7 @@ def main():
     ap = argparse.ArgumentParser(description="twin experiments of section 4 on the GPU")
     ap.add_argument("--exp", type=int, choices=(1, 2), default=1,
                     help="1: full domain observed; 2: half domain")
-    ap.add_argument("--filter", choices=("tempered", "bootstrap"), default="tempered")
+    ap.add_argument("--filter", choices=FILTERS, default="tempered")
     ap.add_argument("--steps", type=int, default=100, help="assimilation steps")
     ap.add_argument("--log-every", type=int, default=0)
     ap.add_argument("--out", default=None, help="write the per-step statistics as JSON")

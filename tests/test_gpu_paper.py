@@ -133,6 +133,12 @@ def _oracle_twin(wl, filt, n_da):
                                                   wl.n_jitter, wl.max_temper)
             m, u = out["m"], out["u"]
             dec = so.n_temper
+        elif filt == "nudged":
+            rc, out, so = O.nudged_cycle_matern(om, omt, y, sig, wl.seed, c, m, u, S,
+                                                wl.ess_threshold, wl.n_bisect, wl.rho,
+                                                wl.n_jitter, wl.max_temper)
+            m, u = out["m"], out["u"]
+            dec = so.n_temper
         else:
             rc, m, u, lw, so = O.bootstrap_cycle_matern(om, omt, y, sig, wl.seed, c, m, u, lw, S,
                                                         wl.ess_frac)
@@ -229,3 +235,22 @@ def test_failed_particle_gets_zero_weight(sch, kind):
     assert rc == 0 and st["status"] == 0 and st["n_failed"] == 1
     assert np.all(np.isfinite(u_o)) and np.all(np.isfinite(N(u)))
     assert PR.rel_l2(N(m), m_o) < PR.REL_TOL and PR.rel_l2(N(u), u_o) < PR.REL_TOL
+
+
+def test_twin_experiment_nudged(sch):
+    """Two assimilation steps of experiment 1 with the nudged filter (nudging
+    with one control per cell, then tempering and jittering), 16 particles:
+    equal tempering-step counts; states and statistics at the L-BFGS bar of
+    the nudging tests (controls within 1e-6 of their scale)."""
+    from paper_2402_06927_amd import experiments as E
+
+    wl = W.PAPER_SHAPE.scaled(n_particles=16)
+    n_da = 2
+    rows, u_o, ut_o = _oracle_twin(wl, "nudged", n_da)
+    r = E.run_twin(wl, "nudged", n_da)
+    assert PR.rel_l2(r["u_truth"], ut_o) < PR.REL_TOL
+    assert PR.rel_l2(r["u"], u_o) < 1e-6
+    for c, (s_o, dec) in enumerate(rows):
+        np.testing.assert_allclose([r["emre"][c], r["rb"][c], r["res"][c]], s_o, rtol=1e-5)
+        assert r["n_temper"][c] == dec
+
