@@ -126,17 +126,18 @@ def copy_probe(nbytes: int):
     print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
 
 
-def bench_nudging(args):
+def bench_nudging(args, matern=False):
     """One step = the sequential adapted nudging of one 40-step window for
     all 2048 particles at Nx = 2048 (8 modes, 256 observations, sigma 0.02,
     L-BFGS memory 8, checkpoints every 8 steps) plus the likelihood of the
-    nudged ends."""
+    nudged ends.  matern: the Matern-type noise (eta = 1, k = 3, kappa = 1)
+    with one control per cell, 2048 per step and particle."""
     import torch
 
     from paper_2402_06927_amd import sch
     from paper_2402_06927_amd import workloads as W
 
-    wl = W.NUDGING_2048
+    wl = W.NUDGING_MATERN_2048 if matern else W.NUDGING_2048
     if args.particles:
         wl = wl.scaled(n_particles=args.particles)
     dev = "cuda"
@@ -152,17 +153,25 @@ def bench_nudging(args):
     ut = torch.tensor(W.initial_velocity(wl, 1, ts), device=dev)
     mt = torch.empty_like(ut)
     sch.sch_init_momentum(model, ut, mt)
-    dWt = torch.empty((1, S, Q), dtype=torch.float64, device=dev)
+    nq = nx if matern else Q  # controls per step
+    mtn = sch.Matern(wl.kappa, wl.eta, wl.k_solves)
+    dWt = torch.empty((1, S, nq), dtype=torch.float64, device=dev)
     sch.sch_draw_increments(ts, 0, 0, sch.TAG_FORECAST, dWt, wl.dt)
-    sch.sch_ensemble_step(model, mt, ut, dWt)
+    if matern:
+        sch.sch_ensemble_step_matern(model, mtn, mt, ut, dWt)
+    else:
+        sch.sch_ensemble_step(model, mt, ut, dWt)
     y = torch.empty((1, wl.n_obs), dtype=torch.float64, device=dev)
     sch.sch_observe(model, ut, y)
     y = y[0] + wl.sigma_obs * torch.tensor(W.obs_noise(wl, ts, 1)[0], device=dev)
     obs = sch.Obs(y.contiguous(), torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64,
                                              device=dev))
-    dW = torch.empty((n, S, Q), dtype=torch.float64, device=dev)
+    dW = torch.empty((n, S, nq), dtype=torch.float64, device=dev)
     sch.sch_draw_increments(wl.seed, 0, 0, sch.TAG_NUDGE, dW, wl.dt)
-    ws = sch.workspace(sch.WS_NUDGE, model, n, S, 8)
+    if matern:
+        ws = sch.matern_workspace(sch.WS_NUDGE, model, n, S, 8)
+    else:
+        ws = sch.workspace(sch.WS_NUDGE, model, n, S, 8)
     dLam = torch.zeros_like(dW)
     logG = torch.empty(n, dtype=torch.float64, device=dev)
     iters = torch.empty(n, dtype=torch.int32, device=dev)
@@ -171,8 +180,12 @@ def bench_nudging(args):
 
     def run():
         m, u = m_init.clone(), u_init.clone()
-        sch.sch_nudge_run(model, obs, m, u, dW, dLam, logG, iters=iters, evals=evals,
-                          workspace=ws)
+        if matern:
+            sch.sch_nudge_run_matern(model, mtn, obs, m, u, dW, dLam, logG, iters=iters,
+                                     evals=evals, workspace=ws)
+        else:
+            sch.sch_nudge_run(model, obs, m, u, dW, dLam, logG, iters=iters, evals=evals,
+                              workspace=ws)
         sch.sch_loglik(model, obs, u, phi)
         return u
 
@@ -202,7 +215,8 @@ def bench_nudging(args):
         "data": "synthetic",
         "config": {"workload": wl.name, "filter": "nudging", "nx": nx, "n_particles": n,
                    "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs, "sigma_obs": wl.sigma_obs,
-                   "lbfgs_mem": 8, "ckpt_every": 8},
+                   "lbfgs_mem": 8, "ckpt_every": 8, "noise": wl.noise,
+                   "controls_per_step": nq},
         "lbfgs_evals_per_particle": round(ev, 2),
         "lbfgs_iters_per_particle": round(it, 2),
         "mean_phi_nudged": float(phi.mean()),
@@ -739,12 +753,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
     ap.add_argument("--workload", choices=("tempered", "matern", "pcnl", "paper", "nudging",
+                                           "nudging_matern",
                                            "nudged", "warmstart", "mlp", "batch"),
                     default="tempered",
                     help="tempered: the headline filter; matern: the same filter with the "
                          "Matern-type noise of section 2; pcnl: the same filter with "
                          "gradient-based (pCN-Langevin) jitter; paper: the paper's twin experiment "
-                         "(--exp 1 or 2); nudging: one nudged window; "
+                         "(--exp 1 or 2); nudging: one nudged window; nudging_matern: the same "
+                         "with the Matern-type noise and one control per cell; "
                          "nudged: the nudged filter (nudging, tempering, jittering); "
                          "warmstart: plain vs learned warm-start nudging; mlp: the "
                          "warm-start network; batch: 64 uneven filters in one graph")
@@ -775,8 +791,8 @@ def main():
     if args.workload == "paper":
         bench_paper(args)
         return
-    if args.workload == "nudging":
-        bench_nudging(args)
+    if args.workload in ("nudging", "nudging_matern"):
+        bench_nudging(args, matern=args.workload == "nudging_matern")
         return
     if args.workload == "nudged":
         bench_nudged(args)

@@ -749,7 +749,13 @@ int nudge_run(const sch_model* md, const Tile& tl, const sch_obs* ob, int32_t n,
                                        ce, W.lb.ft, W.lb.gt, W.lb.est, W.lb.active, W, st, M))
           return rc;
       }
-      hipLaunchKernelGGL(k_lbfgs_update, dim3(gb), dim3(256), 0, st, W.lb, LP);
+      // one thread per particle for a few modes, one wavefront per particle
+      // for one control per cell
+      if (Q >= kWave)
+        hipLaunchKernelGGL(k_lbfgs_update_w, dim3(grid_for(n, 256 / kWave)), dim3(256), 0, st,
+                           W.lb, LP);
+      else
+        hipLaunchKernelGGL(k_lbfgs_update, dim3(gb), dim3(256), 0, st, W.lb, LP);
       CHECK_LAUNCH();
       unsigned int act = 0;
       HIP_TRY(hipMemcpyAsync(&act, W.lb.n_active, sizeof act, hipMemcpyDeviceToHost, st));

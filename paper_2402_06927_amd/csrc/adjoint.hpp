@@ -568,6 +568,154 @@ __global__ void k_lbfgs_update(LbfgsState s, LbfgsParams P) {
   if (s.active[i]) atomicAdd(s.n_active, 1u);
 }
 
+// The same state machine with one wavefront per particle, for many unknowns
+// (one control per cell): each vector loop is strided over the 64 lanes, each
+// inner product and the gradient's max norm are wavefront reductions (their
+// values uniform across the wavefront), so every lane takes the same
+// decisions; lane 0 writes the scalar state.  The steps and tests are those of
+// lbfgs_direction / k_lbfgs_update; only the summation order differs.
+// Returns whether the particle stays active.
+__device__ bool lbfgs_direction_w(const LbfgsState& s, const LbfgsParams& P, int i, int l,
+                                  int head, int count, int k, double f) {
+  const int Q = P.Q, M = P.mem;
+  double* x = s.x + static_cast<size_t>(i) * Q;
+  double* g = s.g + static_cast<size_t>(i) * Q;
+  double* p = s.p + static_cast<size_t>(i) * Q;
+  double* xt = s.xt + static_cast<size_t>(i) * Q;
+  const double* Sm = s.S + static_cast<size_t>(i) * M * Q;
+  const double* Ym = s.Y + static_cast<size_t>(i) * M * Q;
+  const double* rho = s.rho + static_cast<size_t>(i) * M;
+  auto dot = [&](const double* a, const double* b) {
+    double d = 0.0;
+    for (int q = l; q < Q; q += kWave) d = fma(a[q], b[q], d);
+    return wave_sum(d);
+  };
+  double gmax = 0.0;
+  for (int q = l; q < Q; q += kWave) gmax = fmax(gmax, fabs(g[q]));
+  gmax = wave_max(gmax);
+  if (gmax <= P.gtol * (1.0 + fabs(f)) || k >= P.max_iter) {
+    if (l == 0) {
+      s.lstat[i] = k >= P.max_iter && !(gmax <= P.gtol * (1.0 + fabs(f))) ? 1 : 0;
+      s.active[i] = 0;
+    }
+    return false;
+  }
+  double al[kLbfgsMaxMem];
+  for (int q = l; q < Q; q += kWave) p[q] = -g[q];
+  for (int c = 0; c < count; ++c) {
+    const int j = (head - 1 - c + M) % M;
+    al[j] = rho[j] * dot(Sm + j * Q, p);
+    for (int q = l; q < Q; q += kWave) p[q] -= al[j] * Ym[j * Q + q];
+  }
+  double gamma = P.h0;
+  if (count > 0) {
+    const int j = (head - 1 + M) % M;
+    gamma = dot(Sm + j * Q, Ym + j * Q) / dot(Ym + j * Q, Ym + j * Q);
+  }
+  for (int q = l; q < Q; q += kWave) p[q] *= gamma;
+  for (int c = count - 1; c >= 0; --c) {
+    const int j = (head - 1 - c + M) % M;
+    const double b = rho[j] * dot(Ym + j * Q, p);
+    for (int q = l; q < Q; q += kWave) p[q] += (al[j] - b) * Sm[j * Q + q];
+  }
+  double gp = dot(g, p);
+  if (!(gp < 0.0)) {
+    count = 0;
+    head = 0;
+    for (int q = l; q < Q; q += kWave) p[q] = -P.h0 * g[q];
+    gp = dot(g, p);
+  }
+  if (l == 0) {
+    s.head[i] = head;
+    s.count[i] = count;
+    s.gp[i] = gp;
+    s.a[i] = 1.0;
+    s.nback[i] = 0;
+    s.phase[i] = 1;
+  }
+  for (int q = l; q < Q; q += kWave) xt[q] = x[q] + p[q];
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_lbfgs_update_w(LbfgsState s, LbfgsParams P) {
+  const int l = threadIdx.x & (kWave - 1);
+  const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (i >= P.n || s.active[i] == 0) return;  // the whole wavefront
+  const int Q = P.Q, M = P.mem;
+  if (l == 0) s.evals[i] += 1;
+  const double ft = s.ft[i];
+  const bool ok = s.est[i] == SCH_OK && isfinite(ft);
+  double* x = s.x + static_cast<size_t>(i) * Q;
+  double* g = s.g + static_cast<size_t>(i) * Q;
+  double* xt = s.xt + static_cast<size_t>(i) * Q;
+  const double* gt = s.gt + static_cast<size_t>(i) * Q;
+  bool act = true;
+  if (s.phase[i] == 0) {
+    if (!ok) {
+      if (l == 0) {
+        s.lstat[i] = 3;
+        s.active[i] = 0;
+      }
+      act = false;
+    } else {
+      if (l == 0) s.f[i] = ft;
+      for (int q = l; q < Q; q += kWave) g[q] = gt[q];
+      act = lbfgs_direction_w(s, P, i, l, s.head[i], s.count[i], s.k[i], ft);
+    }
+  } else {
+    const double f = s.f[i];
+    if (ok && ft <= f + 1e-4 * s.a[i] * s.gp[i] + 1e-13 * fabs(f)) {
+      int head = s.head[i], count = s.count[i];
+      const int k = s.k[i] + 1;
+      double* Sm = s.S + (static_cast<size_t>(i) * M + head) * Q;
+      double* Ym = s.Y + (static_cast<size_t>(i) * M + head) * Q;
+      double sy = 0.0, ss = 0.0, yy = 0.0;
+      for (int q = l; q < Q; q += kWave) {
+        const double si = xt[q] - x[q], yi = gt[q] - g[q];
+        Sm[q] = si;
+        Ym[q] = yi;
+        sy = fma(si, yi, sy);
+        ss = fma(si, si, ss);
+        yy = fma(yi, yi, yy);
+      }
+      sy = wave_sum(sy);
+      ss = wave_sum(ss);
+      yy = wave_sum(yy);
+      if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
+        if (l == 0) s.rho[static_cast<size_t>(i) * M + head] = 1.0 / sy;
+        head = (head + 1) % M;
+        if (count < M) count += 1;
+      }
+      for (int q = l; q < Q; q += kWave) {
+        x[q] = xt[q];
+        g[q] = gt[q];
+      }
+      if (l == 0) {
+        s.f[i] = ft;
+        s.k[i] = k;
+        s.head[i] = head;
+        s.count[i] = count;
+      }
+      act = lbfgs_direction_w(s, P, i, l, head, count, k, ft);
+    } else if (s.nback[i] >= P.max_back) {
+      if (l == 0) {
+        s.lstat[i] = 2;
+        s.active[i] = 0;
+      }
+      act = false;
+    } else {
+      const double a = 0.5 * s.a[i];
+      const double* p = s.p + static_cast<size_t>(i) * Q;
+      for (int q = l; q < Q; q += kWave) xt[q] = x[q] + a * p[q];
+      if (l == 0) {
+        s.a[i] = a;
+        s.nback[i] += 1;
+      }
+    }
+  }
+  if (act && l == 0) atomicAdd(s.n_active, 1u);
+}
+
 // End of a stage: record the control of step n, the increment of the step
 // (dW^n + dLambda^n) for the advance, and the log Girsanov term.
 __global__ void k_nudge_commit(LbfgsState s, LbfgsParams P, int n_steps, int step,

@@ -111,8 +111,12 @@ PAPER_HALF = replace(PAPER_SHAPE, name="paper_half_nx100_np150", n_observed=41)
 # increments per step.
 MATERN_4096 = replace(TEMPERED_4096, name="tempered_matern_nx4096_np1024", noise="matern")
 
+# The nudging workload with the Matern-type noise: one control per DG0 cell
+# and step (2048 per step and particle instead of 8).
+NUDGING_MATERN_2048 = replace(NUDGING_2048, name="nudging_matern_nx2048_np2048", noise="matern")
+
 WORKLOADS = {w.name: w for w in (BOOTSTRAP_256, TEMPERED_4096, NUDGING_2048, PAPER_SHAPE,
-                                 PAPER_HALF, MATERN_4096)}
+                                 PAPER_HALF, MATERN_4096, NUDGING_MATERN_2048)}
 
 
 def node_positions(L: float, nx: int) -> np.ndarray:
