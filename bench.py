@@ -226,7 +226,7 @@ def bench_nudging(args, matern=False):
     print(json.dumps(out), flush=True)
 
 
-def bench_nudged(args):
+def bench_nudged(args, matern=False):
     """One step = one cycle of the nudged filter at the nudging workload
     (Nx = 2048, 2048 particles, 8 modes, 40 steps, 256 observations): the
     sequential adapted nudging of the window (L-BFGS on the adjoint gradient),
@@ -239,7 +239,7 @@ def bench_nudged(args):
     from paper_2402_06927_amd import sch
     from paper_2402_06927_amd import workloads as W
 
-    wl = W.NUDGING_2048
+    wl = W.NUDGING_MATERN_2048 if matern else W.NUDGING_2048
     if args.particles:
         wl = wl.scaled(n_particles=args.particles)
     dev = "cuda"
@@ -258,19 +258,30 @@ def bench_nudged(args):
     mt = torch.empty_like(ut)
     sch.sch_init_momentum(model, ut, mt)
     z = torch.tensor(W.obs_noise(wl, ts, n_cycles), device=dev)
-    dWt = torch.empty((1, S, Q), dtype=torch.float64, device=dev)
+    nq = nx if matern else Q  # increments and controls per step
+    mtn = sch.Matern(wl.kappa, wl.eta, wl.k_solves)
+    dWt = torch.empty((1, S, nq), dtype=torch.float64, device=dev)
     yobs = torch.empty((n_cycles, wl.n_obs), dtype=torch.float64, device=dev)
     for c in range(n_cycles):
         sch.sch_draw_increments(ts, c, 0, sch.TAG_FORECAST, dWt, wl.dt)
-        sch.sch_ensemble_step(model, mt, ut, dWt)
+        if matern:
+            sch.sch_ensemble_step_matern(model, mtn, mt, ut, dWt)
+        else:
+            sch.sch_ensemble_step(model, mt, ut, dWt)
         sch.sch_observe(model, ut, yobs[c:c + 1])
     yobs += wl.sigma_obs * z
     sigma = torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64, device=dev)
-    dLam = torch.zeros((n, S, Q), dtype=torch.float64, device=dev)
-    ws = sch.nudged_workspace(model, n, S, n_jitter, 8)
+    dLam = torch.zeros((n, S, nq), dtype=torch.float64, device=dev)
+    if matern:
+        ws = sch.nudged_workspace_matern(model, n, S, n_jitter, 8)
+    else:
+        ws = sch.nudged_workspace(model, n, S, n_jitter, 8)
 
     def run_cycle(c):
         obs = sch.Obs(yobs[c].contiguous(), sigma)
+        if matern:
+            return sch.sch_pf_nudged_cycle_matern(model, mtn, obs, wl.seed, c, m, u, dLam, S,
+                                                  0.5 * n, 50, rho, n_jitter, 100, ws)
         return sch.sch_pf_nudged_cycle(model, obs, wl.seed, c, m, u, dLam, S, 0.5 * n, 50, rho,
                                        n_jitter, 100, ws)
 
@@ -301,6 +312,7 @@ def bench_nudged(args):
         "data": "synthetic",
         "config": {"workload": wl.name, "filter": "nudged+tempered+jittered", "nx": nx,
                    "n_particles": n, "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs,
+                   "noise": wl.noise, "controls_per_step": nq,
                    "sigma_obs": wl.sigma_obs, "ess_threshold": 0.5 * n, "n_jitter": n_jitter,
                    "rho": rho, "lbfgs_mem": 8, "ckpt_every": 8},
         "tempering_steps_per_cycle": [s_["n_temper"] for s_ in stats],
@@ -753,7 +765,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
     ap.add_argument("--workload", choices=("tempered", "matern", "pcnl", "paper", "nudging",
-                                           "nudging_matern",
+                                           "nudging_matern", "nudged_matern",
                                            "nudged", "warmstart", "mlp", "batch"),
                     default="tempered",
                     help="tempered: the headline filter; matern: the same filter with the "
@@ -761,7 +773,8 @@ def main():
                          "gradient-based (pCN-Langevin) jitter; paper: the paper's twin experiment "
                          "(--exp 1 or 2); nudging: one nudged window; nudging_matern: the same "
                          "with the Matern-type noise and one control per cell; "
-                         "nudged: the nudged filter (nudging, tempering, jittering); "
+                         "nudged: the nudged filter (nudging, tempering, jittering); nudged_matern: "
+                         "the same with the Matern-type noise; "
                          "warmstart: plain vs learned warm-start nudging; mlp: the "
                          "warm-start network; batch: 64 uneven filters in one graph")
     ap.add_argument("--threads", type=int, default=0,
@@ -794,8 +807,8 @@ def main():
     if args.workload in ("nudging", "nudging_matern"):
         bench_nudging(args, matern=args.workload == "nudging_matern")
         return
-    if args.workload == "nudged":
-        bench_nudged(args)
+    if args.workload in ("nudged", "nudged_matern"):
+        bench_nudged(args, matern=args.workload == "nudged_matern")
         return
     if args.workload == "warmstart":
         bench_warmstart(args)
