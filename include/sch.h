@@ -469,7 +469,8 @@ size_t sch_matern_workspace_bytes(int32_t which, const sch_model *model, int32_t
  * proposal per cell (the cells 2k, 2k+1 of a step share one Philox block:
  * tag PCN, counter (p, cycle * n_steps + n, k | tag << 24,
  * temper_k << 16 | j)), the same acceptance uniform, window and likelihood.
- * No controls.  workspace >= sch_matern_workspace_bytes(SCH_WS_JITTER, ...). */
+ * No controls (sch_jitter_pcn_matern_ctrl takes them).  workspace >=
+ * sch_matern_workspace_bytes(SCH_WS_JITTER, ...). */
 int sch_jitter_pcn_matern(const sch_model *model, const sch_matern *mt, const sch_obs *obs,
                           const sch_rng *rng, int32_t n_particles, int32_t n_steps,
                           const double *m0, const double *u0, double *dWc, double *phi,
