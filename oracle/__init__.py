@@ -145,6 +145,11 @@ def _declare(L):
                                          C.c_uint32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                          C.c_double, C.c_int32, C.c_int32, _dp, _dp,
                                          C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_tempered_cycle_linear": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _dp,
+                                                _dp, _dp, _dp, C.c_double, C.c_double, C.c_uint64,
+                                                C.c_uint32, C.c_int32, C.c_double, C.c_int32,
+                                                C.c_double, C.c_int32, C.c_int32, _dp,
+                                                C.POINTER(OrcCycleStats), C.c_int32]),
         "orc_nudge_objective": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_int32,
                                           _dp, _dp, _dp, _dp, _dp]),
         "orc_nudge_grad": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_int32, _dp,
@@ -550,6 +555,30 @@ def tempered_cycle(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_thres
                                   max_temper, _d(m), _d(u), C.byref(st),
                                   n_threads or n_threads_default())
     return rc, m, u, st
+
+
+PLANT_NONE = 0
+PLANT_JITTER_PRE_THETA = 1
+PLANT_CUMULATIVE_WEIGHTS = 2
+
+
+def tempered_cycle_linear(F, B, G, y, sigma, dt, seed, cycle, x, n_steps, n_modes,
+                          ess_threshold, n_bisect=50, rho=0.99, n_jitter=5, max_temper=100,
+                          plant=PLANT_NONE):
+    """The tempering loop of the tempered drivers with the linear-Gaussian
+    plug-in window e = F s + B xi, Phi = |G e - y|^2 / (2 sigma^2) (see
+    orc_tempered_cycle_linear).  x [n][ds]: start states in; returns
+    (rc, end states, stats)."""
+    F, B, G, y = _f64(F), _f64(B), _f64(G), _f64(y)
+    x = np.array(x, dtype=np.float64, copy=True, order="C")
+    ds = x.shape[1]
+    assert F.shape == (ds, ds) and B.shape == (ds, n_steps * n_modes) and G.shape == (len(y), ds)
+    st = OrcCycleStats()
+    rc = lib().orc_tempered_cycle_linear(ds, n_steps, n_modes, len(y), _d(F), _d(B), _d(G), _d(y),
+                                         sigma, dt, seed, cycle, x.shape[0], ess_threshold,
+                                         n_bisect, rho, n_jitter, max_temper, _d(x), C.byref(st),
+                                         plant)
+    return rc, x, st
 
 
 # --------------------------------------------------------------------------- nudging

@@ -365,8 +365,8 @@ int orc_momentum_from_velocity(const orc_model *md, const double *u, double *m) 
 /*   A m^{n+1} = (M - (mu dt/2) K - (1/2) C(dv)) m^n.                          */
 /* dv depends on u^{n+1}, so the system is nonlinear.  The paper does not say  */
 /* how it is solved; this oracle uses Picard iteration on u^{n+1} (each        */
-/* iterate a pivoted linear solve) until the estimated error of the momentum  */
-/* iterate is at most picard_tol relative in the max norm.                     */
+/* iterate a pivoted linear solve) until the momentum iterate changes by at   */
+/* most picard_tol relative in the max norm (reading G5).                      */
 /* ========================================================================== */
 /* One implicit-midpoint step driven by the nodal noise increment dU (the
  * step's Delta U in dv = dt (u^n + u^{n+1}) / 2 + Delta U, eq. fde1). */
@@ -383,7 +383,6 @@ int orc_step_field(const orc_model *md, double *m, double *u, const double *dU,
   memcpy(mp, m, sz);
   int st = ORC_E_NONCONVERGED;
   int32_t k;
-  double prev = 0.0;  /* the previous iteration's change of m */
   for (k = 1; k <= md->picard_max; ++k) {
     for (int32_t i = 0; i < n; ++i) dv[i] = dt * 0.5 * (u[i] + us[i]) + dU[i];
     /* rows of A: mass (h/6, 2h/3, h/6) + (mu dt/2) stiffness (-1/h, 2/h, -1/h)
@@ -424,15 +423,11 @@ int orc_step_field(const orc_model *md, double *m, double *u, const double *dU,
       break;
     }
     memcpy(mp, ms, sz);
-    /* Stop once the iterate's error is within tolerance.  For a contraction
-     * with ratio c, |m* - m_k| <= c / (1 - c) |m_k - m_{k-1}|; c is estimated
-     * by the ratio of the last two changes and the bound used while c < 1/2,
-     * multiplied out as d_k^2 <= lim (d_{k-1} - d_k); otherwise the change
-     * itself must be within tolerance. */
-    double lim = md->picard_tol * scale;
-    int done = (k > 1 && 2.0 * diff < prev) ? diff * diff <= lim * (prev - diff) : diff <= lim;
-    prev = diff;
-    if (done) {
+    /* Stop once the change of the momentum iterate is within tolerance
+     * (reading G5 as stated: |m_k - m_{k-1}|_inf <= tol |m_k|_inf).  For a
+     * contraction with ratio c the iterate's error is then at most
+     * c / (1 - c) tol |m_k|, below tol |m_k| whenever c < 1/2. */
+    if (diff <= md->picard_tol * scale) {
       st = ORC_OK;
       break;
     }
@@ -1126,13 +1121,116 @@ int orc_bootstrap_cycle_matern(const orc_model *md, const orc_matern *mt, int32_
                          u, logw, st, n_threads);
 }
 
+/* The tempering loop of section 3.1.2, shared by every tempered driver
+ * (modes, pCN-Langevin, Matern-type noise, nudged): the temperature theta
+ * climbs from 0 to 1 in adaptive steps; at each step the increment dtheta is
+ * the largest with ESS(exp(-dtheta pot)) >= threshold (orc_temper), the
+ * ensemble is resampled with those incremental weights (uniform of tag
+ * RESAMPLE, counter (0, cycle, tag << 24, k << 16)), every row set of the
+ * particles and their potentials are gathered by the same indices, and the
+ * jitter moves the increments at the new cumulative temperature (reading
+ * G16).  The jitter callback receives theta and the step's RNG keys and
+ * writes the per-particle acceptance counts.
+ *
+ * `plant` exists only for the pins of this loop (ORC_PLANT_*): a nonzero value
+ * plants a known mistake so that the tests can show their power. */
+typedef void (*jitter_fn)(void *ctx, const orc_rng *rng, double theta, int32_t *acc);
+typedef struct {
+  double *a;
+  size_t len; /* doubles per particle */
+} row_set;
+
+static int temper_loop(int32_t n, double *pot, row_set *rows, int32_t n_rows, uint64_t seed,
+                       uint32_t cycle, double ess_threshold, int32_t n_bisect, int32_t max_temper,
+                       jitter_fn jitter, void *ctx, orc_cycle_stats *st, int32_t plant) {
+  double *w = (double *)malloc(sizeof(double) * n);
+  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * n);
+  int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * n);
+  double theta = 0.0;
+  int32_t k = 0;
+  int rc = ORC_OK;
+  while (theta < 1.0) {
+    if (k >= max_temper) {
+      rc = ORC_E_DEGENERATE;
+      break;
+    }
+    double dth, ess;
+    orc_temper(n, pot, theta, ess_threshold, n_bisect, &dth, w, &ess);
+    if (ess == 0.0) {
+      rc = ORC_E_DEGENERATE;
+      break;
+    }
+    double theta_new = (dth == 1.0 - theta) ? 1.0 : theta + dth;
+    if (plant == ORC_PLANT_CUMULATIVE_WEIGHTS) orc_weights(n, pot, NULL, theta_new, w, NULL);
+    double ur = orc_uniform(seed, 0u, cycle, (uint32_t)ORC_TAG_RESAMPLE << 24, (uint32_t)k << 16);
+    rc = orc_resample_systematic(n, w, ur, idx);
+    if (rc != ORC_OK) break;
+    for (int32_t r = 0; r < n_rows; ++r) gather_rows(rows[r].a, idx, n, rows[r].len);
+    gather_rows(pot, idx, n, 1);
+    orc_rng rg = {seed, cycle, (uint32_t)k};
+    jitter(ctx, &rg, plant == ORC_PLANT_JITTER_PRE_THETA ? theta : theta_new, acc);
+    for (int32_t p = 0; p < n; ++p) st->n_accept += acc[p];
+    st->ess = ess;
+    theta = theta_new;
+    ++k;
+  }
+  st->n_temper = k;
+  free(w);
+  free(idx);
+  free(acc);
+  return rc;
+}
+
+/* The jitters of the SCH drivers behind the callback of temper_loop. */
+enum { JIT_PCN = 0, JIT_PCNL = 1, JIT_PCN_CTRL = 2, JIT_MATERN = 3 };
+static int jitter_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                         const double *y, const double *sigma, const orc_rng *rng,
+                         int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
+                         double *dWc, const double *dLamc, double *phi, double *m_end,
+                         double *u_end, double theta, double rho, int32_t n_jitter,
+                         int32_t *n_accept, int32_t n_threads);
+typedef struct {
+  int kind;
+  const orc_model *md;
+  const orc_matern *mt;
+  int32_t n_obs, n_particles, n_steps, n_jitter, n_threads;
+  const double *y, *sigma, *m0, *u0, *dLam;
+  double *dW, *pot, *m, *u;
+  double rho;
+} sch_jitter_ctx;
+
+static void sch_jitter(void *vctx, const orc_rng *rg, double theta, int32_t *acc) {
+  sch_jitter_ctx *c = (sch_jitter_ctx *)vctx;
+  switch (c->kind) {
+    case JIT_PCNL:
+      orc_jitter_pcnl(c->md, c->n_obs, c->y, c->sigma, rg, c->n_particles, c->n_steps, c->m0,
+                      c->u0, c->dW, c->pot, c->m, c->u, theta, c->rho, c->n_jitter, acc,
+                      c->n_threads);
+      break;
+    case JIT_PCN_CTRL:
+      orc_jitter_pcn_ctrl(c->md, c->n_obs, c->y, c->sigma, rg, c->n_particles, c->n_steps,
+                          c->m0, c->u0, c->dW, c->dLam, c->pot, c->m, c->u, theta, c->rho,
+                          c->n_jitter, acc, c->n_threads);
+      break;
+    case JIT_MATERN:
+      jitter_matern(c->md, c->mt, c->n_obs, c->y, c->sigma, rg, c->n_particles, c->n_steps,
+                    c->m0, c->u0, c->dW, c->dLam, c->pot, c->m, c->u, theta, c->rho, c->n_jitter,
+                    acc, c->n_threads);
+      break;
+    default:
+      orc_jitter_pcn(c->md, c->n_obs, c->y, c->sigma, rg, c->n_particles, c->n_steps, c->m0,
+                     c->u0, c->dW, c->pot, c->m, c->u, theta, c->rho, c->n_jitter, acc,
+                     c->n_threads);
+  }
+}
+
 /* Tempered and jittered filter, section 3.1.2.  Each particle is the pair
  * (window-start state, increments over the window).  After the forecast, the
- * temperature theta climbs from 0 to 1 in adaptive steps; after every step the
- * ensemble is resampled with the tempered weights exp(-dtheta Phi) and every
- * particle's increments are moved by n_jitter pCN steps targeting the
- * posterior tempered at the new cumulative theta.  Only then does the window
- * end state become the next cycle's start state. */
+ * temperature climbs from 0 to 1 in the steps of temper_loop; after every
+ * step the ensemble is resampled with the tempered weights exp(-dtheta Phi)
+ * and every particle's increments are moved by n_jitter pCN steps targeting
+ * the posterior tempered at the new cumulative theta.  Only then does the
+ * window end state become the next cycle's start state. */
 /* The tempered cycle with pCN moves (pcnl == 0) or pCN-Langevin moves. */
 static int tempered_cycle(const orc_model *md, int32_t n_obs, const double *y,
                           const double *sigma, uint64_t seed, uint32_t cycle, int32_t n_particles,
@@ -1144,11 +1242,8 @@ static int tempered_cycle(const orc_model *md, int32_t n_obs, const double *y,
   double *m0 = (double *)malloc(sizeof(double) * state), *u0 = (double *)malloc(sizeof(double) * state);
   double *dW = (double *)malloc(sizeof(double) * wlen);
   double *phi = (double *)malloc(sizeof(double) * n_particles);
-  double *w = (double *)malloc(sizeof(double) * n_particles);
-  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   int32_t *iters = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   int32_t *stat = (int32_t *)malloc(sizeof(int32_t) * n_particles);
-  int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   memset(st, 0, sizeof(*st));
   memcpy(m0, m, sizeof(double) * state);
   memcpy(u0, u, sizeof(double) * state);
@@ -1161,53 +1256,19 @@ static int tempered_cycle(const orc_model *md, int32_t n_obs, const double *y,
     phi[p] = stat[p] == ORC_OK ? orc_nll(nx, n_obs, u + (size_t)p * nx, y, sigma) : INFINITY;
     if (!isfinite(phi[p])) phi[p] = INFINITY;
   }
-  double theta = 0.0;
-  int32_t k = 0;
-  int rc = ORC_OK;
-  while (theta < 1.0) {
-    if (k >= max_temper) {
-      rc = ORC_E_DEGENERATE;
-      break;
-    }
-    double dth, ess;
-    orc_temper(n_particles, phi, theta, ess_threshold, n_bisect, &dth, w, &ess);
-    if (ess == 0.0) {
-      rc = ORC_E_DEGENERATE;
-      break;
-    }
-    double theta_new = (dth == 1.0 - theta) ? 1.0 : theta + dth;
-    double ur = orc_uniform(seed, 0u, cycle, (uint32_t)ORC_TAG_RESAMPLE << 24, (uint32_t)k << 16);
-    rc = orc_resample_systematic(n_particles, w, ur, idx);
-    if (rc != ORC_OK) break;
-    gather_rows(m0, idx, n_particles, (size_t)nx);
-    gather_rows(u0, idx, n_particles, (size_t)nx);
-    gather_rows(m, idx, n_particles, (size_t)nx);
-    gather_rows(u, idx, n_particles, (size_t)nx);
-    gather_rows(dW, idx, n_particles, (size_t)n_steps * nq);
-    gather_rows(phi, idx, n_particles, 1);
-    orc_rng rg = {seed, cycle, (uint32_t)k};
-    if (pcnl)
-      orc_jitter_pcnl(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, phi, m, u,
-                      theta_new, rho, n_jitter, acc, n_threads);
-    else
-      orc_jitter_pcn(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, phi, m, u,
-                     theta_new, rho, n_jitter, acc, n_threads);
-    for (int32_t p = 0; p < n_particles; ++p) st->n_accept += acc[p];
-    st->ess = ess;
-    theta = theta_new;
-    ++k;
-  }
-  st->n_temper = k;
+  row_set rows[5] = {{m0, (size_t)nx}, {u0, (size_t)nx}, {m, (size_t)nx}, {u, (size_t)nx},
+                     {dW, (size_t)n_steps * nq}};
+  sch_jitter_ctx jc = {pcnl ? JIT_PCNL : JIT_PCN, md, NULL, n_obs, n_particles, n_steps,
+                       n_jitter, n_threads, y, sigma, m0, u0, NULL, dW, phi, m, u, rho};
+  int rc = temper_loop(n_particles, phi, rows, 5, seed, cycle, ess_threshold, n_bisect,
+                       max_temper, sch_jitter, &jc, st, ORC_PLANT_NONE);
   st->status = rc;
   free(m0);
   free(u0);
   free(dW);
   free(phi);
-  free(w);
-  free(idx);
   free(iters);
   free(stat);
-  free(acc);
   return rc;
 }
 
@@ -1229,6 +1290,95 @@ int orc_tempered_cycle_pcnl(const orc_model *md, int32_t n_obs, const double *y,
                             double *m, double *u, orc_cycle_stats *st, int32_t n_threads) {
   return tempered_cycle(md, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
                         n_bisect, rho, n_jitter, max_temper, m, u, st, n_threads, 1);
+}
+
+/* The linear-Gaussian plug-in of the tempering loop (declared in the header
+ * with its meaning): e = F s + B xi, Phi = |G e - y|^2 / (2 sigma^2). */
+typedef struct {
+  int32_t ds, d, n_obs;
+  const double *F, *B, *G, *y;
+  double sigma;
+} lin_model;
+
+static double lin_window(const lin_model *lm, const double *s, const double *xi, double *e) {
+  for (int32_t i = 0; i < lm->ds; ++i) {
+    double a = 0.0;
+    for (int32_t j = 0; j < lm->ds; ++j) a += lm->F[(size_t)i * lm->ds + j] * s[j];
+    for (int32_t j = 0; j < lm->d; ++j) a += lm->B[(size_t)i * lm->d + j] * xi[j];
+    e[i] = a;
+  }
+  double phi = 0.0;
+  for (int32_t o = 0; o < lm->n_obs; ++o) {
+    double r = -lm->y[o];
+    for (int32_t i = 0; i < lm->ds; ++i) r += lm->G[(size_t)o * lm->ds + i] * e[i];
+    phi += 0.5 * r * r / (lm->sigma * lm->sigma);
+  }
+  return phi;
+}
+
+typedef struct {
+  const lin_model *lm;
+  int32_t n_particles, n_steps, n_modes, n_jitter;
+  double rho, dt;
+  const double *x0;
+  double *xi, *pot, *x;
+} lin_jitter_ctx;
+
+/* n_jitter pCN moves of every particle's increments at temperature theta, with
+ * the proposal, counters and acceptance rule of orc_jitter_pcn. */
+static void lin_jitter(void *vctx, const orc_rng *rg, double theta, int32_t *acc) {
+  lin_jitter_ctx *c = (lin_jitter_ctx *)vctx;
+  const lin_model *lm = c->lm;
+  double *prop = (double *)malloc(sizeof(double) * lm->d);
+  double *e = (double *)malloc(sizeof(double) * lm->ds);
+  for (int32_t p = 0; p < c->n_particles; ++p) {
+    double *xp = c->xi + (size_t)p * lm->d;
+    acc[p] = 0;
+    for (int32_t j = 0; j < c->n_jitter; ++j) {
+      uint32_t w3 = (rg->temper_k << 16) | (uint32_t)j;
+      orc_pcn_propose(rg->seed, (uint32_t)p, rg->cycle * (uint32_t)c->n_steps, c->n_steps,
+                      c->n_modes, w3, c->rho, c->dt, xp, prop);
+      double phin = lin_window(lm, c->x0 + (size_t)p * lm->ds, prop, e);
+      double v = orc_uniform(rg->seed, (uint32_t)p, rg->cycle, (uint32_t)ORC_TAG_ACCEPT << 24, w3);
+      if (orc_pcn_accept(theta, c->pot[p], phin, v)) {
+        memcpy(xp, prop, sizeof(double) * lm->d);
+        memcpy(c->x + (size_t)p * lm->ds, e, sizeof(double) * lm->ds);
+        c->pot[p] = phin;
+        ++acc[p];
+      }
+    }
+  }
+  free(prop);
+  free(e);
+}
+
+int orc_tempered_cycle_linear(int32_t ds, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                              const double *F, const double *B, const double *G, const double *y,
+                              double sigma, double dt, uint64_t seed, uint32_t cycle,
+                              int32_t n_particles, double ess_threshold, int32_t n_bisect,
+                              double rho, int32_t n_jitter, int32_t max_temper, double *x,
+                              orc_cycle_stats *st, int32_t plant) {
+  if (ds <= 0 || n_steps <= 0 || n_modes <= 0 || n_obs <= 0 || n_particles <= 0) return ORC_E_ARG;
+  lin_model lm = {ds, n_steps * n_modes, n_obs, F, B, G, y, sigma};
+  size_t state = (size_t)n_particles * ds, wlen = (size_t)n_particles * lm.d;
+  double *x0 = (double *)malloc(sizeof(double) * state);
+  double *xi = (double *)malloc(sizeof(double) * wlen);
+  double *pot = (double *)malloc(sizeof(double) * n_particles);
+  memset(st, 0, sizeof(*st));
+  memcpy(x0, x, sizeof(double) * state);
+  orc_draw_increments(seed, n_particles, n_steps, n_modes, cycle * (uint32_t)n_steps,
+                      ORC_TAG_FORECAST, 0u, dt, xi);
+  for (int32_t p = 0; p < n_particles; ++p)
+    pot[p] = lin_window(&lm, x0 + (size_t)p * ds, xi + (size_t)p * lm.d, x + (size_t)p * ds);
+  row_set rows[3] = {{x0, (size_t)ds}, {x, (size_t)ds}, {xi, (size_t)lm.d}};
+  lin_jitter_ctx jc = {&lm, n_particles, n_steps, n_modes, n_jitter, rho, dt, x0, xi, pot, x};
+  int rc = temper_loop(n_particles, pot, rows, 3, seed, cycle, ess_threshold, n_bisect,
+                       max_temper, lin_jitter, &jc, st, plant);
+  st->status = rc;
+  free(x0);
+  free(xi);
+  free(pot);
+  return rc;
 }
 
 /* ========================================================================== */
@@ -1407,10 +1557,6 @@ static int nudge_grad(const orc_model *md, const orc_matern *mt, int32_t n_obs, 
     }
     st = orc_cyclic_solve(nx, tlo, di, tup, lam, nu);
     int conv = 0;
-    /* the first iterate's change from the zero start, for the error estimate */
-    double prev = 0.0;
-    for (int32_t i = 0; i < nx; ++i)
-      if (fabs(nu[i]) > prev) prev = fabs(nu[i]);
     for (int32_t k = 0; k < md->picard_max && st == ORC_OK; ++k) {
       advect_transpose(nx, s, nu, tmp);
       st = helm_solve(md, tmp, tmp2);
@@ -1425,12 +1571,8 @@ static int nudge_grad(const orc_model *md, const orc_matern *mt, int32_t n_obs, 
         if (fabs(nun[i]) > scale) scale = fabs(nun[i]);
       }
       memcpy(nu, nun, sz);
-      /* the stopping rule of the forward step: the estimated error
-       * c / (1 - c) d_k, c = d_k / d_{k-1}, while c < 1/2 */
-      double lim = md->picard_tol * scale;
-      int done = (2.0 * diff < prev) ? diff * diff <= lim * (prev - diff) : diff <= lim;
-      prev = diff;
-      if (done) {
+      /* the stopping rule of the forward step: the change within tolerance */
+      if (diff <= md->picard_tol * scale) {
         conv = 1;
         break;
       }
@@ -1867,10 +2009,7 @@ static int nudged_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs
   double *dLam = (double *)calloc(wlen, sizeof(double));
   double *J = (double *)malloc(sizeof(double) * n_particles);
   double *logG = (double *)malloc(sizeof(double) * n_particles);
-  double *w = (double *)malloc(sizeof(double) * n_particles);
-  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   int32_t *stat = (int32_t *)malloc(sizeof(int32_t) * n_particles);
-  int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   memset(st, 0, sizeof(*st));
   memcpy(m0, m, sizeof(double) * state);
   memcpy(u0, u, sizeof(double) * state);
@@ -1884,44 +2023,12 @@ static int nudged_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs
     J[p] = (isfinite(phi) && isfinite(logG[p])) ? phi - logG[p] : INFINITY;
     if (!isfinite(J[p])) J[p] = INFINITY;
   }
-  double theta = 0.0;
-  int32_t k = 0;
-  int rc = ORC_OK;
-  while (theta < 1.0) {
-    if (k >= max_temper) {
-      rc = ORC_E_DEGENERATE;
-      break;
-    }
-    double dth, ess;
-    orc_temper(n_particles, J, theta, ess_threshold, n_bisect, &dth, w, &ess);
-    if (ess == 0.0) {
-      rc = ORC_E_DEGENERATE;
-      break;
-    }
-    double theta_new = (dth == 1.0 - theta) ? 1.0 : theta + dth;
-    double ur = orc_uniform(seed, 0u, cycle, (uint32_t)ORC_TAG_RESAMPLE << 24, (uint32_t)k << 16);
-    rc = orc_resample_systematic(n_particles, w, ur, idx);
-    if (rc != ORC_OK) break;
-    gather_rows(m0, idx, n_particles, (size_t)nx);
-    gather_rows(u0, idx, n_particles, (size_t)nx);
-    gather_rows(m, idx, n_particles, (size_t)nx);
-    gather_rows(u, idx, n_particles, (size_t)nx);
-    gather_rows(dW, idx, n_particles, (size_t)n_steps * nq);
-    gather_rows(dLam, idx, n_particles, (size_t)n_steps * nq);
-    gather_rows(J, idx, n_particles, 1);
-    orc_rng rg = {seed, cycle, (uint32_t)k};
-    if (mt)
-      jitter_matern(md, mt, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, dLam, J, m,
-                    u, theta_new, rho, n_jitter, acc, n_threads);
-    else
-      orc_jitter_pcn_ctrl(md, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dW, dLam, J, m,
-                          u, theta_new, rho, n_jitter, acc, n_threads);
-    for (int32_t p = 0; p < n_particles; ++p) st->n_accept += acc[p];
-    st->ess = ess;
-    theta = theta_new;
-    ++k;
-  }
-  st->n_temper = k;
+  row_set rows[6] = {{m0, (size_t)nx}, {u0, (size_t)nx}, {m, (size_t)nx}, {u, (size_t)nx},
+                     {dW, (size_t)n_steps * nq}, {dLam, (size_t)n_steps * nq}};
+  sch_jitter_ctx jc = {mt ? JIT_MATERN : JIT_PCN_CTRL, md, mt, n_obs, n_particles, n_steps,
+                       n_jitter, n_threads, y, sigma, m0, u0, dLam, dW, J, m, u, rho};
+  int rc = temper_loop(n_particles, J, rows, 6, seed, cycle, ess_threshold, n_bisect, max_temper,
+                       sch_jitter, &jc, st, ORC_PLANT_NONE);
   st->status = rc;
   if (m0_out) memcpy(m0_out, m0, sizeof(double) * state);
   if (u0_out) memcpy(u0_out, u0, sizeof(double) * state);
@@ -1934,10 +2041,7 @@ static int nudged_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs
   free(dLam);
   free(J);
   free(logG);
-  free(w);
-  free(idx);
   free(stat);
-  free(acc);
   return rc;
 }
 
@@ -2064,11 +2168,8 @@ int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t
   double *m0 = (double *)malloc(sizeof(double) * state), *u0 = (double *)malloc(sizeof(double) * state);
   double *dWc = (double *)malloc(sizeof(double) * wlen);
   double *phi = (double *)malloc(sizeof(double) * n_particles);
-  double *w = (double *)malloc(sizeof(double) * n_particles);
-  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   int32_t *iters = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   int32_t *stat = (int32_t *)malloc(sizeof(int32_t) * n_particles);
-  int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * n_particles);
   memset(st, 0, sizeof(*st));
   memcpy(m0, m, sizeof(double) * state);
   memcpy(u0, u, sizeof(double) * state);
@@ -2080,39 +2181,12 @@ int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t
     phi[p] = stat[p] == ORC_OK ? orc_nll(nx, n_obs, u + (size_t)p * nx, y, sigma) : INFINITY;
     if (!isfinite(phi[p])) phi[p] = INFINITY;
   }
-  double theta = 0.0;
-  int32_t k = 0;
-  int rc = ORC_OK;
-  while (theta < 1.0) {
-    if (k >= max_temper) {
-      rc = ORC_E_DEGENERATE;
-      break;
-    }
-    double dth, ess;
-    orc_temper(n_particles, phi, theta, ess_threshold, n_bisect, &dth, w, &ess);
-    if (ess == 0.0) {
-      rc = ORC_E_DEGENERATE;
-      break;
-    }
-    double theta_new = (dth == 1.0 - theta) ? 1.0 : theta + dth;
-    double ur = orc_uniform(seed, 0u, cycle, (uint32_t)ORC_TAG_RESAMPLE << 24, (uint32_t)k << 16);
-    rc = orc_resample_systematic(n_particles, w, ur, idx);
-    if (rc != ORC_OK) break;
-    gather_rows(m0, idx, n_particles, (size_t)nx);
-    gather_rows(u0, idx, n_particles, (size_t)nx);
-    gather_rows(m, idx, n_particles, (size_t)nx);
-    gather_rows(u, idx, n_particles, (size_t)nx);
-    gather_rows(dWc, idx, n_particles, (size_t)n_steps * nx);
-    gather_rows(phi, idx, n_particles, 1);
-    orc_rng rg = {seed, cycle, (uint32_t)k};
-    orc_jitter_pcn_matern(md, mt, n_obs, y, sigma, &rg, n_particles, n_steps, m0, u0, dWc, phi, m,
-                          u, theta_new, rho, n_jitter, acc, n_threads);
-    for (int32_t p = 0; p < n_particles; ++p) st->n_accept += acc[p];
-    st->ess = ess;
-    theta = theta_new;
-    ++k;
-  }
-  st->n_temper = k;
+  row_set rows[5] = {{m0, (size_t)nx}, {u0, (size_t)nx}, {m, (size_t)nx}, {u, (size_t)nx},
+                     {dWc, (size_t)n_steps * nx}};
+  sch_jitter_ctx jc = {JIT_MATERN, md, mt, n_obs, n_particles, n_steps, n_jitter, n_threads, y,
+                       sigma, m0, u0, NULL, dWc, phi, m, u, rho};
+  int rc = temper_loop(n_particles, phi, rows, 5, seed, cycle, ess_threshold, n_bisect,
+                       max_temper, sch_jitter, &jc, st, ORC_PLANT_NONE);
   st->status = rc;
   if (m0_out) memcpy(m0_out, m0, sizeof(double) * state);
   if (u0_out) memcpy(u0_out, u0, sizeof(double) * state);
@@ -2122,11 +2196,8 @@ int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t
   free(u0);
   free(dWc);
   free(phi);
-  free(w);
-  free(idx);
   free(iters);
   free(stat);
-  free(acc);
   return rc;
 }
 

@@ -177,6 +177,29 @@ int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, cons
                        int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
                        int32_t n_threads);
 
+/* Pin of the tempering loop shared by the tempered drivers (section 3.1.2),
+ * with the forward window replaced by a linear-Gaussian plug-in: the window
+ * of a particle maps its start state s [ds] and increments xi
+ * [n_steps][n_modes] (prior N(0, dt) each, drawn as the SCH forecast) to the
+ * end state e = F s + B xi (F [ds][ds], B [ds][n_steps * n_modes]) and its
+ * potential is Phi = |G e - y|^2 / (2 sigma^2) (G [n_obs][ds]).  The forecast,
+ * the tempering steps, the resampling, the gathers and the pCN jitter (its
+ * proposal, counters and acceptance rule) are those of orc_tempered_cycle.
+ * x [n][ds] holds the start states on entry and the end states on return.
+ * With these Gaussian ingredients the end states after the cycle sample the
+ * Kalman filter's posterior, which the tests compare against.
+ * `plant` plants a known mistake for the tests' power checks:
+ * ORC_PLANT_JITTER_PRE_THETA jitters at the temperature before the step,
+ * ORC_PLANT_CUMULATIVE_WEIGHTS resamples with exp(-theta_new Phi) instead of
+ * exp(-dtheta Phi). */
+enum { ORC_PLANT_NONE = 0, ORC_PLANT_JITTER_PRE_THETA = 1, ORC_PLANT_CUMULATIVE_WEIGHTS = 2 };
+int orc_tempered_cycle_linear(int32_t ds, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                              const double *F, const double *B, const double *G, const double *y,
+                              double sigma, double dt, uint64_t seed, uint32_t cycle,
+                              int32_t n_particles, double ess_threshold, int32_t n_bisect,
+                              double rho, int32_t n_jitter, int32_t max_temper, double *x,
+                              orc_cycle_stats *st, int32_t plant);
+
 /* ---- nudging objective and its gradient ---- */
 int orc_nudge_objective(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
                         int32_t n_steps, const double *m0, const double *u0, const double *dW,

@@ -112,10 +112,12 @@ def test_window_parity(sch, nx, n, q, s):
     for p in range(n):
         assert PR.rel_l2(N(m)[p], m_ref[p]) < PR.REL_TOL
         assert PR.rel_l2(N(u)[p], u_ref[p]) < PR.REL_TOL
-    # same iterates in exact arithmetic: the counts agree up to a rare
+    # the oracle stops on the change of the iterate, the kernel on the
+    # estimated error (c / (1 - c) times the change), which is met no later:
+    # per step the kernel takes the oracle's count or one fewer, up to a rare
     # rounding-level decision at the tolerance boundary
-    assert np.abs(N(iters) - it_ref).max() <= 1
-    assert (N(iters) == it_ref).mean() >= 0.8
+    d = it_ref - N(iters)
+    assert d.min() >= -1 and d.max() <= s + 1
 
 
 def test_window_with_nudging_control(sch):
