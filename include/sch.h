@@ -257,6 +257,26 @@ int sch_jitter_pcn(const sch_model *model, const sch_obs *obs, const sch_rng *rn
                    const double *theta, double rho, int32_t n_jitter, int32_t *n_accept,
                    void *workspace, void *stream);
 
+/* sch_jitter_pcn_noalloc: for callers that cannot allocate device memory --
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same moves as sch_jitter_pcn (same kernels, bit-identical
+ * results) with every argument but the workspace: the proposal normals and
+ * acceptance uniforms, n_jitter * n * n_steps * n_modes + n_jitter * n
+ * doubles (plus 512 bytes of alignment), go to a device array of the library
+ * of sch_jitter_pcn_noalloc_max_bytes() = 16 MiB, one per GPU, held until
+ * the process ends (16 MiB covers 5 moves of 1024 particles x 40 steps x 8
+ * modes).  Larger requests fail with SCH_E_SHAPE before any device work.  The
+ * call itself allocates nothing; the array's address is looked up once per
+ * device on the first call there.  Every call on a GPU uses the same array:
+ * calls that overlap on one GPU (different streams, threads or processes
+ * sharing a context) race and must be serialised by the caller. */
+size_t sch_jitter_pcn_noalloc_max_bytes(void);
+int sch_jitter_pcn_noalloc(const sch_model *model, const sch_obs *obs, const sch_rng *rng,
+                           int32_t n_particles, int32_t n_steps, const double *m0,
+                           const double *u0, double *dW, const double *dLambda, double *phi,
+                           double *m_end, double *u_end, const double *theta, double rho,
+                           int32_t n_jitter, int32_t *n_accept, void *stream);
+
 /* --------------------------------------------------------------------------
  * Nudging (section 3.1.3).  The control dLambda^n enters each step beside
  * the increment (eq. "SCH nudge": dU^n = sum_q xi_q (dW^n_q + dLambda^n_q)),

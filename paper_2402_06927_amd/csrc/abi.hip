@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -668,19 +669,96 @@ int sch_gather(int32_t n_rows, int64_t row_len, const int32_t* idx, const double
   return SCH_OK;
 }
 
+static int check_jitter_args(const sch_model* md, const sch_obs* ob, const sch_rng* rng,
+                             int32_t n, int32_t n_steps, const double* m0, const double* u0,
+                             const double* dW, const double* phi, const double* m_end,
+                             const double* u_end, const double* theta, double rho,
+                             int32_t n_jitter, Tile& tl, const char* who) {
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (!rng || n < 1 || n_steps < 1 || !m0 || !u0 || !dW || !phi || !m_end || !u_end || !theta ||
+      !(rho >= 0 && rho <= 1) || n_jitter < 0)
+    return fail(SCH_E_ARG, "bad arguments to %s", who);
+  return SCH_OK;
+}
+
 int sch_jitter_pcn(const sch_model* md, const sch_obs* ob, const sch_rng* rng, int32_t n,
                    int32_t n_steps, const double* m0, const double* u0, double* dW,
                    const double* dLambda, double* phi, double* m_end, double* u_end,
                    const double* theta, double rho, int32_t n_jitter, int32_t* n_accept,
                    void* workspace, void* stream) {
   Tile tl;
-  if (int rc = check_model(md, tl)) return rc;
-  if (int rc = check_obs(ob)) return rc;
-  if (!rng || n < 1 || n_steps < 1 || !m0 || !u0 || !dW || !phi || !m_end || !u_end || !theta ||
-      !(rho >= 0 && rho <= 1) || n_jitter < 0 || (n_jitter > 0 && !workspace))
-    return fail(SCH_E_ARG, "bad arguments to sch_jitter_pcn");
+  if (int rc = check_jitter_args(md, ob, rng, n, n_steps, m0, u0, dW, phi, m_end, u_end, theta,
+                                 rho, n_jitter, tl, "sch_jitter_pcn"))
+    return rc;
+  if (n_jitter > 0 && !workspace) return fail(SCH_E_ARG, "sch_jitter_pcn: workspace is NULL");
   if (n_jitter == 0) return SCH_OK;
   CycleWs W = carve_cycle(workspace, SCH_WS_JITTER, md->nx, md->n_modes, n, n_steps, nullptr,
+                          n_jitter);
+  return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
+                       dW, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,
+                       W.zeta, W.vacc, dLambda, S(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The jitter without a workspace: the proposal normals and acceptance
+// uniforms go to a device array of the library, one per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, so the
+// array's device address is taken with hipGetSymbolAddress once per device
+// (with that device current) and only that address is used.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device.
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SCH_E_ARG, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SCH_E_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SCH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t sch_jitter_pcn_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int sch_jitter_pcn_noalloc(const sch_model* md, const sch_obs* ob, const sch_rng* rng, int32_t n,
+                           int32_t n_steps, const double* m0, const double* u0, double* dW,
+                           const double* dLambda, double* phi, double* m_end, double* u_end,
+                           const double* theta, double rho, int32_t n_jitter, int32_t* n_accept,
+                           void* stream) {
+  Tile tl;
+  if (int rc = check_jitter_args(md, ob, rng, n, n_steps, m0, u0, dW, phi, m_end, u_end, theta,
+                                 rho, n_jitter, tl, "sch_jitter_pcn_noalloc"))
+    return rc;
+  if (n_jitter == 0) return SCH_OK;
+  size_t need = 0;
+  carve_cycle(nullptr, SCH_WS_JITTER, md->nx, md->n_modes, n, n_steps, &need, n_jitter);
+  if (need > kNoAllocScratchBytes)
+    return fail(SCH_E_SHAPE,
+                "sch_jitter_pcn_noalloc: %d moves x %d particles x %d steps x %d modes need %zu "
+                "bytes of draws, above the library's %zu-byte scratch array; call sch_jitter_pcn "
+                "with a workspace",
+                n_jitter, n, n_steps, md->n_modes, need, kNoAllocScratchBytes);
+  void* base = nullptr;
+  if (int rc = scratch_of_current_device(&base)) return rc;
+  CycleWs W = carve_cycle(base, SCH_WS_JITTER, md->nx, md->n_modes, n, n_steps, nullptr,
                           n_jitter);
   return launch_jitter(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0,
                        dW, phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, nullptr,

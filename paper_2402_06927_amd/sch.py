@@ -125,6 +125,9 @@ def _declare(L):
         "sch_gather": (C.c_int, [i32, i64, _vp, _vp, _vp, _vp]),
         "sch_jitter_pcn": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                      _vp, f64, i32, _vp, _vp, _vp]),
+        "sch_jitter_pcn_noalloc_max_bytes": (C.c_size_t, []),
+        "sch_jitter_pcn_noalloc": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                             _vp, _vp, f64, i32, _vp, _vp]),
         "sch_pf_bootstrap_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, _vp, _vp, _vp, _vp,
                                              ST, _vp]),
         "sch_pf_tempered_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
@@ -205,7 +208,7 @@ def exported_names():
         "sch_philox_blocks",
         "sch_velocity", "sch_init_momentum", "sch_ensemble_step", "sch_observe", "sch_loglik",
         "sch_temper_ess", "sch_resample", "sch_gather", "sch_jitter_pcn",
-        "sch_nudge_grad", "sch_nudge_run", "sch_pf_bootstrap_cycle",
+        "sch_jitter_pcn_noalloc_max_bytes", "sch_jitter_pcn_noalloc", "sch_nudge_grad", "sch_nudge_run", "sch_pf_bootstrap_cycle",
         "sch_batch_workspace_bytes", "sch_batch_create", "sch_batch_run", "sch_batch_read",
         "sch_batch_destroy", "sch_mlp_param_count", "sch_mlp_workspace_bytes", "sch_mlp_sync",
         "sch_mlp_forward", "sch_mlp_backward", "sch_mlp_adam", "sch_mlp_features",
@@ -388,6 +391,26 @@ def sch_jitter_pcn(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
                                 _dev(theta, name="theta"), rho, n_jitter,
                                 _dev(n_accept, torch.int32, "n_accept"),
                                 _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_jitter_pcn_noalloc(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
+                           m0: torch.Tensor, u0: torch.Tensor, dW: torch.Tensor,
+                           phi: torch.Tensor, m_end: torch.Tensor, u_end: torch.Tensor,
+                           theta: torch.Tensor, rho: float, n_jitter: int,
+                           n_accept: torch.Tensor | None = None,
+                           dLambda: torch.Tensor | None = None):
+    """sch_jitter_pcn with its proposal draws in the library's own device
+    array (no workspace; at most sch_jitter_pcn_noalloc_max_bytes())."""
+    mc, oc = model.c(), obs.c()
+    r = SchRngC(seed, cycle, temper_k)
+    n, s = dW.shape[0], dW.shape[1]
+    _check(lib().sch_jitter_pcn_noalloc(C.byref(mc), C.byref(oc), C.byref(r), n, s,
+                                        _dev(m0, name="m0"), _dev(u0, name="u0"),
+                                        _dev(dW, name="dW"), _dev(dLambda, name="dLambda"),
+                                        _dev(phi, name="phi"), _dev(m_end, name="m_end"),
+                                        _dev(u_end, name="u_end"), _dev(theta, name="theta"),
+                                        rho, n_jitter, _dev(n_accept, torch.int32, "n_accept"),
+                                        _stream()))
 
 
 def sch_pf_bootstrap_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
