@@ -39,6 +39,33 @@ def flops_per_node_step(n_modes: int) -> int:
     return 2 * n_modes + 5
 
 
+# The coarser per-node model of the step used for the headline roofline
+# fraction: 60 flops per node per Picard iteration (about 25 for assembling
+# the rows, 20 for the cyclic solve with one reciprocal per row, 11 for the
+# Helmholtz solve, 2 for the test) and 20 per node per step outside it.
+MODEL_FLOPS_PER_NODE_ITER = 60
+MODEL_FLOPS_PER_NODE_STEP = 20
+
+
+def host_cpu() -> dict:
+    """The host's logical CPU count, the CPUs this process may use, and the
+    CPU model name."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable": usable, "model": model}
+
+
 # With the Matern-type noise the per-step noise assembly is the dv part (1),
 # the load vector (2), k scan-form solves (5 each), k - 1 mass products (4
 # each) and the sum into dv (1), plus the right-hand-side mass product (4);
@@ -98,16 +125,29 @@ def cpu_baseline(wl, u_start, m_start, n_threads: int, psteps_per_cycle: float):
     dt = time.perf_counter() - t0
     psteps = n * wl.n_steps
     ps_rate = psteps / dt
+    # the plain single-threaded oracle on the first n1 particles of the same window
+    n1 = min(n, 48)
+    t0 = time.perf_counter()
+    if wl.noise == "matern":
+        O.ensemble_window_matern(om, mt, m_start[:n1], u_start[:n1], cells[:n1], n_threads=1)
+    else:
+        O.ensemble_window(om, m_start[:n1], u_start[:n1], dW[:n1], n_threads=1)
+    dt1 = time.perf_counter() - t0
+    ps1 = n1 * wl.n_steps / dt1
     return {
         "value": ps_rate / psteps_per_cycle,
         "unit": "cycles/s",
         "cores": n_threads,
         "kind": "oracle",
         "sample": (f"one forecast window of all {n} particles x {wl.n_steps} steps at Nx={wl.nx} "
-                   f"({psteps} particle-steps, {dt:.1f} s, {ps_rate:.1f} particle-steps/s), "
-                   f"scaled by the {psteps_per_cycle:.0f} particle-steps per cycle measured on "
-                   f"the GPU; oracle status {worst}"),
+                   f"on {n_threads} threads ({psteps} particle-steps, {dt:.1f} s, "
+                   f"{ps_rate:.1f} particle-steps/s), scaled by the {psteps_per_cycle:.0f} "
+                   f"particle-steps per cycle measured on the GPU; oracle status {worst}; "
+                   f"single-threaded: {n1} particles of the same window, {dt1:.1f} s"),
         "particle_steps_per_s": ps_rate,
+        "single_thread": {"value": ps1 / psteps_per_cycle, "unit": "cycles/s", "cores": 1,
+                          "particle_steps_per_s": ps1},
+        "host": host_cpu(),
     }
 
 
@@ -932,9 +972,15 @@ def main():
         # the flops of the adjoint passes and their forward sweeps are left out: the
         # figure is a lower bound
         j_psteps = j_launches * n * S
-    j_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"] + per_step * j_psteps)
+    j_min_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"] + per_step * j_psteps)
+    # (the Matern-type noise's own per-step work exceeds the 20 of the modes form)
+    model_step = max(MODEL_FLOPS_PER_NODE_STEP, per_step)
+    j_flops = nx * (MODEL_FLOPS_PER_NODE_ITER * jt["iters"] + model_step * j_psteps)
     j_ms = jt["ms"] / j_launches
     j_tflops = (j_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
+    j_min_tflops = (j_min_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
+    traffic_ok = (kernel_sources_hash() == TRAFFIC_SOURCES_HASH and wl.nx == 4096 and n == 1024
+                  and tuned == TRAFFIC_THREADS and not pcnl)
     roofline = {
         "bound": "alu",
         "achieved": round(j_tflops, 3),
@@ -942,8 +988,20 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(j_tflops / PEAK_FP64_TFLOPS, 4),
         "traffic": ((TRAFFIC_JITTER_MATERN_BYTES if matern else TRAFFIC_JITTER_BYTES)
-                    if kernel_sources_hash() == TRAFFIC_SOURCES_HASH and wl.nx == 4096
-                    and n == 1024 and tuned == TRAFFIC_THREADS and not pcnl else None),
+                    if traffic_ok else None),
+        "flop_count": (f"achieved/frac: {MODEL_FLOPS_PER_NODE_ITER} flops per node per Picard "
+                       f"iteration + {model_step} per node per step, with the "
+                       f"iterations the launches took; achieved_min/frac_min: the minimal "
+                       f"count {FLOPS_PER_NODE_ITER} per node per iteration + {per_step} per "
+                       f"node per step"),
+        "achieved_min": round(j_min_tflops, 3),
+        "frac_min": round(j_min_tflops / PEAK_FP64_TFLOPS, 4),
+        "traffic_source": ("constant from two rocprofv3 counter runs (FETCH_SIZE x 2.0 + "
+                           "WRITE_SIZE x 1.0, the factors of a plain copy) on the kernel "
+                           f"sources with hash {TRAFFIC_SOURCES_HASH}; null when the sources, "
+                           "grid, ensemble or tile differ" if traffic_ok else
+                           "null: kernel sources, grid, ensemble or tile differ from the "
+                           "counter runs"),
         "kernel": ("k_jitter<Matern> (pCN proposal drawn per cell + noise field + window "
                    "rerun + likelihood + accept)" if matern else
                    "pCN-Langevin stage (k_nudge_grad x (moves + 1), proposals, accepts, "
@@ -952,6 +1010,7 @@ def main():
                    "k_jitter (fused pCN proposal + window rerun + likelihood + accept)"),
         "avg_launch_ms": round(j_ms, 3),
         "algorithmic_flops_per_launch": j_flops / j_launches,
+        "min_flops_per_launch": j_min_flops / j_launches,
         "picard_iters_per_step": jt["iters"] / max(j_psteps, 1),
     }
 

@@ -47,6 +47,9 @@ extern "C" {
 #define SCH_E_NONFINITE (-4)    /* a NaN or infinity appeared in a particle state   */
 #define SCH_E_DEGENERATE (-5)   /* all weights zero, or the tempering-step cap hit  */
 #define SCH_E_HIP (-6)          /* the HIP runtime reported an error                */
+#define SCH_E_UNSTABLE (-7)     /* an implicit-step system outside the range where  */
+                                /* elimination without pivoting is safe (growth of */
+                                /* the eliminated super-diagonal above 2^16)        */
 
 /* Stage tags of the counter-based generator (bits 24..31 of counter word 2). */
 #define SCH_TAG_INIT 0u

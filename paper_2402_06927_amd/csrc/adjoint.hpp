@@ -177,11 +177,12 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF nois
   double prevd = 0.0;  // the previous iteration's change of nu
   for (; k <= P.picard_max + 1; ++k) {
     double nn[PMAX];
-    double xl_unused, xr_unused;
+    double xl_unused, xr_unused, grow = 0.0;
     cyclic_solve<PMAX, NT, FULL>(rowAT, [&](int j) { return rhs[j]; }, nn, cnt, L, t, xl_unused,
-                                 xr_unused);
+                                 xr_unused, grow);
     double diff = 0.0, scale = 0.0;
-    int bad = 0;
+    // bit 0: a non-finite iterate; bit 1: elimination growth above kMaxGrowth
+    int bad = grow <= kMaxGrowth ? 0 : 2;
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) {
       if (FULL || j < cnt) {
@@ -193,7 +194,7 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF nois
     }
     block_max2_or<NT>(diff, scale, bad, L, t);
     if (bad) {
-      status = SCH_E_NONFINITE;
+      status = (bad & 2) ? SCH_E_UNSTABLE : SCH_E_NONFINITE;
       break;
     }
     // the stopping rule of the forward step: the estimated error

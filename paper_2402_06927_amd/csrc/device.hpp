@@ -295,16 +295,20 @@ __device__ __forceinline__ void halo(const double (&v)[PMAX], int cnt, RowLds<NT
 // whose first unknown z_0 and whose successor z_E (the next run's z_0) are
 // kept: on exit z_j = y[j] + g[j] z_0 + k[j] z_E for j = 1..E-1.  The
 // coefficient arrays are indexed by the run's rows.
+// `grow` receives the running maximum of the eliminated super-diagonal
+// |c'_j| = |C_j / pivot_j| (see cyclic_solve).
 template <int E>
 __device__ __forceinline__ void spike_eliminate(const double (&A)[E], const double (&B)[E],
                                                 const double (&C)[E], const double (&R)[E],
-                                                double (&y)[E], double (&g)[E], double (&k)[E]) {
+                                                double (&y)[E], double (&g)[E], double (&k)[E],
+                                                double& grow) {
   double cp[E];
   double cprev = 0.0, yprev = 0.0, gprev = 1.0;
 #pragma unroll
   for (int j = 1; j < E; ++j) {
     const double inv = rcp64(j == 1 ? B[j] : B[j] - A[j] * cprev);
     cp[j] = C[j] * inv;
+    grow = fmax(grow, fabs(cp[j]));
     y[j] = (j == 1 ? R[j] : R[j] - A[j] * yprev) * inv;
     g[j] = (j == 1 ? -A[j] : -A[j] * gprev) * inv;
     cprev = cp[j];
@@ -336,14 +340,14 @@ __device__ __forceinline__ void interface_solve(const double (&eA)[NT / kWave],
                                                 const double (&eB)[NT / kWave],
                                                 const double (&eC)[NT / kWave],
                                                 const double (&eR)[NT / kWave], int t, double& s,
-                                                double& snext, double& sprev) {
+                                                double& snext, double& sprev, double& grow) {
   constexpr int E = NT / kWave;
   const int lane = t & (kWave - 1);
   double y[E], g[E], k[E];
   y[0] = 0.0;
   g[0] = 1.0;
   k[0] = 0.0;
-  spike_eliminate<E>(eA, eB, eC, eR, y, g, k);
+  spike_eliminate<E>(eA, eB, eC, eR, y, g, k, grow);
   // run tails: the last unknown in terms of (z_0, z_E); first interior row
   const double yT = E > 1 ? y[E - 1] : 0.0, gT = E > 1 ? g[E - 1] : 1.0,
                kT = E > 1 ? k[E - 1] : 0.0;
@@ -435,15 +439,32 @@ __device__ __forceinline__ void interface_solve(const double (&eA)[NT / kWave],
 // chunk is recombined.  row(j, a, b, c) returns the coefficients of local
 // slot j and d(j) its right-hand side (both evaluated once per slot).  xl and
 // xr receive the solution at the row before the chunk and the row after it
-// (the halo of x, from the interface values, without another exchange).  No
-// pivoting: the systems solved here (mass, Helmholtz and the implicit-
-// midpoint matrix at the model's parameters) are diagonally dominant.
+// (the halo of x, from the interface values, without another exchange).
+//
+// No pivoting.  The mass and Helmholtz matrices are symmetric positive
+// definite and diagonally dominant.  A row of the implicit-midpoint matrix,
+// (o - v_-, d + v_+ - v_-, o + v_+) with o = h/6 - mu dt/(2h),
+// d = 2h/3 + mu dt/h (so d + 2o = h) and v_-+ = dv_{i-+1}/4, is diagonally
+// dominant whenever |dv| / 4 <= |o| everywhere and, for o < 0, the
+// compression dv_{i-1} - dv_{i+1} stays below 2h; without pivoting the LU
+// factors then satisfy |L||U| <= 3|A|.  Outside that range (steep or very
+// large dv) the elimination can still be accurate, and its growth is
+// measured instead: row j of |L||U| is bounded by |A|'s row plus
+// 2 |a_j| |c'_{j-1}|, c'_j = c_j / pivot_j the eliminated super-diagonal, so
+// the solution's error grows about like max |c'| times the unit roundoff
+// (near-zero pivots of a compressive saw-tooth dv: max |c'| = 250 gives a
+// relative error of 1e-14, 2.5e5 gives 6e-13, 2.5e8 gives 6e-10).  `grow`
+// receives the running maximum of |c'_j| over the chunk's rows and the
+// interface elimination, and callers reject a system whose growth exceeds
+// kMaxGrowth = 2^16 (errors below about 1e-12).
+constexpr double kMaxGrowth = 65536.0;
 #ifndef SCH_SWEEP_FENCE
 #define SCH_SWEEP_FENCE 4
 #endif
 template <int PMAX, int NT, bool FULL, class RowF, class DF>
 __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], int cnt,
-                                             RowLds<NT>& L, int t, double& xl, double& xr) {
+                                             RowLds<NT>& L, int t, double& xl, double& xr,
+                                             double& grow) {
   static_assert(PMAX >= 2, "need at least two rows per thread");
   constexpr int W = NT / kWave;
   const int lane = t & (kWave - 1);
@@ -465,6 +486,7 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
       yj = 0.0;
       gj = 0.0;
     }
+    grow = fmax(grow, fabs(cj));
     cp[j] = cj;
     x[j] = yj;
     g[j] = gj;
@@ -517,7 +539,7 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     kpl = lane == 0 ? wk : kpl;
     const double eA[1] = {a0 * gpl}, eB[1] = {fma(a0, kpl, Bp)}, eC[1] = {C},
                  eR[1] = {fma(-a0, ypl, Rp)};
-    interface_solve<NT>(eA, eB, eC, eR, t, s, snext, sprev);
+    interface_solve<NT>(eA, eB, eC, eR, t, s, snext, sprev, grow);
   } else {
     // the equation of each wavefront's first chunk goes to LDS without its
     // left-tail terms (A holds a0); the reader completes it from L.etail
@@ -559,7 +581,7 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
       eB[0] = first ? fma(a, tk, eB[0]) : eB[0];
       eR[0] = first ? fma(-a, ty, eR[0]) : eR[0];
     }
-    interface_solve<NT>(eA, eB, eC, eR, t, s, snext, sprev);
+    interface_solve<NT>(eA, eB, eC, eR, t, s, snext, sprev, grow);
   }
   // last row of chunk t-1: y + g s_{t-1} + k s_t with its tail values
   xl = fma(kpl, s, fma(gpl, sprev, ypl));
@@ -573,7 +595,16 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
   }
 }
 
-// Workgroup-wide max of two values and logical or of a flag.
+// The same for the constant symmetric positive definite systems (no growth
+// to watch).
+template <int PMAX, int NT, bool FULL, class RowF, class DF>
+__device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], int cnt,
+                                             RowLds<NT>& L, int t, double& xl, double& xr) {
+  double grow = 0.0;
+  cyclic_solve<PMAX, NT, FULL>(row, d, x, cnt, L, t, xl, xr, grow);
+}
+
+// Workgroup-wide max of two values and bitwise or of small nonnegative flags.
 template <int NT>
 __device__ __forceinline__ void block_max2_or(double& a, double& b, int& f, RowLds<NT>& L, int t) {
   a = wave_max(a);
@@ -583,19 +614,19 @@ __device__ __forceinline__ void block_max2_or(double& a, double& b, int& f, RowL
   if ((t & (kWave - 1)) == 0) {
     L.red[0][w] = a;
     L.red[1][w] = b;
-    L.red[2][w] = f ? 1.0 : 0.0;
+    L.red[2][w] = static_cast<double>(f);
   }
   __syncthreads();
   a = L.red[0][0];
   b = L.red[1][0];
-  double ff = L.red[2][0];
+  int ff = static_cast<int>(L.red[2][0]);
 #pragma unroll
   for (int i = 1; i < NT / kWave; ++i) {
     a = fmax(a, L.red[0][i]);
     b = fmax(b, L.red[1][i]);
-    ff = fmax(ff, L.red[2][i]);
+    ff |= static_cast<int>(L.red[2][i]);
   }
-  f = ff > 0.0;
+  f = ff;
   __syncthreads();
 }
 

@@ -181,9 +181,10 @@ __device__ __forceinline__ void matern_transpose(const MaternDev& M, const doubl
 // the chunk's ends (chunks of at least two rows), so an iteration has two
 // barriers: the interface solve and the Helmholtz solve.
 // Returns SCH_OK or the status of the first failing step; on non-convergence
-// the last iterate is kept, on a non-finite iterate the step's input is kept
-// (KEEP) or the state is left undefined (!KEEP, for callers that discard a
-// failed window: u^n then need not stay live through the iteration).
+// the last iterate is kept, on a non-finite iterate or a system whose
+// elimination growth exceeds kMaxGrowth (SCH_E_UNSTABLE) the step's input is
+// kept (KEEP) or the state is left undefined (!KEEP, for callers that discard
+// a failed window: u^n then need not stay live through the iteration).
 template <int PMAX, int NT, bool FULL, bool KEEP = true, class NoiseF>
 __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise, int n_steps,
                           double (&m)[PMAX], double (&u)[PMAX], const Chunk& ch, RowLds<NT>& L,
@@ -238,6 +239,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
     for (int j = 0; j < PMAX; ++j) us[j] = u[j];
     int status = SCH_E_NONCONVERGED, k = 1;
     double gprev = 0.0;  // the previous iteration's change of m*
+    double grow = 0.0;   // elimination growth of the step's solves (cyclic_solve)
     for (; k <= P.picard_max; ++k) {
       // Keep the step's invariants (the right-hand side 2 M m^n and the
       // LDS-resident explicit part) out of registers across iterations:
@@ -269,7 +271,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
       };
       double ms[PMAX];
       double sl, sr;  // halo of s = m^n + m*
-      cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t, sl, sr);
+      cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t, sl, sr, grow);
       // max change and max size of m*; a non-finite entry (which fmax would
       // drop) reaches the Helmholtz right-hand side M m*, and solve_helm then
       // reports the change as +infinity, which marks the iterate as failed
@@ -288,10 +290,16 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
       // u* = H^{-1} M m*
       double r[PMAX];
       mass_apply_h<PMAX, FULL>(ms, r, P.h, cnt, sl - mL, sr - mR, 1.0);
-      double gdiff, gscale, gunused;
-      solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale, 0.0,
-                                 gdiff, gscale, gunused);
+      // the growth test rides on the Helmholtz record as a wave-uniform flag
+      const double wbad = __any(!(grow <= kMaxGrowth)) ? 1.0 : 0.0;
+      double gdiff, gscale, gbad;
+      solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale, wbad,
+                                 gdiff, gscale, gbad);
       par.slot ^= 1;
+      if (gbad > 0.0) {
+        status = SCH_E_UNSTABLE;
+        break;
+      }
       if (!(gdiff < INFINITY)) {
         status = SCH_E_NONFINITE;
         break;
@@ -310,7 +318,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
       }
     }
     iters += k > P.picard_max ? P.picard_max : k;
-    if (KEEP && status == SCH_E_NONFINITE) return status;
+    if (KEEP && (status == SCH_E_NONFINITE || status == SCH_E_UNSTABLE)) return status;
     // the accepted iterate m* was stored as the last "previous iterate"
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) {

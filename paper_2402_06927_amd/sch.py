@@ -25,6 +25,7 @@ SCH_E_NONCONVERGED = -3
 SCH_E_NONFINITE = -4
 SCH_E_DEGENERATE = -5
 SCH_E_HIP = -6
+SCH_E_UNSTABLE = -7
 
 TAG_INIT, TAG_FORECAST, TAG_PCN, TAG_ACCEPT, TAG_RESAMPLE, TAG_OBS, TAG_NUDGE = range(7)
 WS_RESAMPLE, WS_BOOTSTRAP, WS_TEMPERED, WS_JITTER, WS_NUDGE_GRAD, WS_NUDGE = 1, 2, 3, 4, 5, 6

@@ -145,7 +145,57 @@ def test_window_nonconvergence_reported(sch):
     sch.sch_ensemble_step(gm, m, u, T(dW), None, status)
     got = N(status)
     assert np.all(got != 0) and np.all(st_ref != 0)
-    assert np.all(np.isin(got, [O.ORC_E_NONCONVERGED, O.ORC_E_NONFINITE]))
+    assert np.all(np.isin(got, [O.ORC_E_NONCONVERGED, O.ORC_E_NONFINITE, sch.SCH_E_UNSTABLE]))
+
+
+def _sawtooth_case(dt, amp):
+    """A saw-tooth velocity u_i = amp (-1)^i with mu = 0 and no noise: the
+    step's dv = dt u is compressive at every other node, so the rows of the
+    step matrix lose diagonal dominance and the products of their
+    off-diagonals are positive; the saw-tooth is a steady state of the step
+    (C(dv) m vanishes for it), which the oracle's pivoted solves reach in one
+    iteration."""
+    wl = W.BOOTSTRAP_256.scaled(nx=256, n_modes=4, n_steps=1, mu=0.0, dt=dt)
+    om, gm = PR.oracle_model(wl), PR.gpu_model(wl)
+    i = np.arange(wl.nx)
+    u0 = (amp * np.where(i % 2 == 0, 1.0, -1.0))[None, :]
+    m0 = O.momentum_from_velocity(om, u0)
+    return wl, om, gm, m0, u0, np.zeros((1, 1, 4))
+
+
+def test_unstable_elimination_reported(sch):
+    """The GPU eliminates without pivoting.  Chunks start their elimination at
+    odd nodes, where this saw-tooth gives the pivot d - (h/6 + dv/4)^2 / d
+    = -1e-9 d (d = 2h/3): growth of about 1e9, above the bound 2^16, and the
+    GPU reports SCH_E_UNSTABLE for the particle instead of a state; the
+    oracle's pivoted solves converge there."""
+    h = 40.0 / 256
+    dt = 0.025
+    V = 4 * (2 * h / 3 * math.sqrt(1 + 1e-9) - h / 6)
+    wl, om, gm, m0, u0, dW = _sawtooth_case(dt, V / dt)
+    worst, _, _, st_ref, _ = O.ensemble_window(om, m0, u0, dW)
+    assert worst == 0 and st_ref[0] == 0
+    status = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    m, u = T(m0), T(u0)
+    sch.sch_ensemble_step(gm, m, u, T(dW), None, status)
+    assert N(status)[0] == sch.SCH_E_UNSTABLE
+    # KEEP semantics: the step's input is kept
+    assert np.array_equal(N(m), m0) and np.array_equal(N(u), u0)
+
+
+def test_moderate_growth_matches_the_pivoted_oracle(sch):
+    """Rows far from diagonal dominance (|dv| / 4 = 0.25 against a diagonal of
+    0.104) but with elimination growth of about 3 in the GPU's four-row
+    chunks, below the bound: the unpivoted GPU step equals the oracle's
+    pivoted one."""
+    wl, om, gm, m0, u0, dW = _sawtooth_case(0.1, 10.0)
+    worst, m_ref, u_ref, _, _ = O.ensemble_window(om, m0, u0, dW)
+    assert worst == 0
+    status = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    m, u = T(m0), T(u0)
+    sch.sch_ensemble_step(gm, m, u, T(dW), None, status)
+    assert N(status)[0] == 0
+    assert PR.rel_l2(N(m), m_ref) < PR.REL_TOL and PR.rel_l2(N(u), u_ref) < PR.REL_TOL
 
 
 def test_window_full_size_sampled(sch):
