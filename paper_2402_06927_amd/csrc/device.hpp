@@ -131,6 +131,13 @@ __device__ __forceinline__ double vmax(double a, double b) {
   asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
+// max(acc, |x|) as one v_max_f64 with the absolute-value source modifier (for
+// accumulating the growth of an elimination; a NaN x leaves acc unchanged).
+__device__ __forceinline__ double vmax_abs(double acc, double x) {
+  double r;
+  asm("v_max_f64 %0, %1, |%2|" : "=v"(r) : "v"(acc), "v"(x));
+  return r;
+}
 // (of nonnegative values: lanes without a partner take 0).  After the row
 // steps, lane 15 of each row is broadcast into the next row and lane 31 into
 // rows 2 and 3, so lane 63 holds the wave's maximum.
@@ -308,7 +315,7 @@ __device__ __forceinline__ void spike_eliminate(const double (&A)[E], const doub
   for (int j = 1; j < E; ++j) {
     const double inv = rcp64(j == 1 ? B[j] : B[j] - A[j] * cprev);
     cp[j] = C[j] * inv;
-    grow = fmax(grow, fabs(cp[j]));
+    grow = vmax_abs(grow, cp[j]);
     y[j] = (j == 1 ? R[j] : R[j] - A[j] * yprev) * inv;
     g[j] = (j == 1 ? -A[j] : -A[j] * gprev) * inv;
     cprev = cp[j];
@@ -486,7 +493,7 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
       yj = 0.0;
       gj = 0.0;
     }
-    grow = fmax(grow, fabs(cj));
+    grow = vmax_abs(grow, cj);
     cp[j] = cj;
     x[j] = yj;
     g[j] = gj;

@@ -198,20 +198,26 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
   const double f1 = P.h / 3.0, f0 = 4.0 * P.h / 3.0;  // 2 M: (h/3, 4h/3, h/3)
   const bool bordered = FULL || K.base >= 2;
   double rD[kDLds ? 1 : PMAX], rP[kLds ? 1 : PMAX];
-  auto getD = [&](int j) -> double { if constexpr (kDLds) return X.a[0][j][t]; else return rD[j]; };
-  auto setD = [&](int j, double v) { if constexpr (kDLds) X.a[0][j][t] = v; else rD[j] = v; };
-  auto getP = [&](int j) -> double { if constexpr (kLds) return X.a[1][j][t]; else return rP[j]; };
-  auto setP = [&](int j, double v) { if constexpr (kLds) X.a[1][j][t] = v; else rP[j] = v; };
+  // The thread's column of the LDS arrays.  It is laundered once per Picard
+  // iteration, so the loads of the step's invariants are redone inside the
+  // iteration (not hoisted into registers) and still issue back to back.
+  int tx = t;
+  auto getD = [&](int j) -> double { if constexpr (kDLds) return X.a[0][j][tx]; else return rD[j]; };
+  auto setD = [&](int j, double v) { if constexpr (kDLds) X.a[0][j][tx] = v; else rD[j] = v; };
+  auto getP = [&](int j) -> double { if constexpr (kLds) return X.a[1][j][tx]; else return rP[j]; };
+  auto setP = [&](int j, double v) { if constexpr (kLds) X.a[1][j][tx] = v; else rP[j] = v; };
   for (int n = 0; n < n_steps; ++n) {
-    // (dU^n + dt/2 u^n) / 4, the explicit part of dv / 4
+    // (dU^n + dt/2 u^n) / 4 + o, the explicit part of dv / 4 + o
     double eL, eR, mL, mR, uL, uR;
     {
       double e[PMAX];
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) e[j] = hdt * u[j];
       noise(n, e);
+      // stored with the constant off-diagonal of the step rows added:
+      // w = dv/4 + o (o = h/6 - mu dt/(2h)) is then the row's upper entry
 #pragma unroll
-      for (int j = 0; j < PMAX; ++j) e[j] *= 0.25;
+      for (int j = 0; j < PMAX; ++j) e[j] = fma(e[j], 0.25, P.a_off);
       const double fst[3] = {m[0], e[0], u[0]};
       const double lst[3] = {last_of<PMAX, FULL>(m, cnt), last_of<PMAX, FULL>(e, cnt),
                              last_of<PMAX, FULL>(u, cnt)};
@@ -239,6 +245,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
     for (int j = 0; j < PMAX; ++j) us[j] = u[j];
     int status = SCH_E_NONCONVERGED, k = 1;
     double gprev = 0.0;  // the previous iteration's change of m*
+    double lim = 0.0;    // tolerance times the first iterate's max |m*|
     double grow = 0.0;   // elimination growth of the step's solves (cyclic_solve)
     for (; k <= P.picard_max; ++k) {
       // Keep the step's invariants (the right-hand side 2 M m^n and the
@@ -247,13 +254,10 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
       // workgroups a compute unit holds.
 #pragma unroll
       for (int j = 0; j < PMAX; ++j) asm volatile("" : "+v"(m[j]));
+      asm volatile("" : "+v"(tx));
       double dv[PMAX];
 #pragma unroll
-      for (int j = 0; j < PMAX; ++j) {
-        double dj = getD(j);
-        asm volatile("" : "+v"(dj));
-        dv[j] = fma(hdt4, us[j], dj);  // dv / 4
-      }
+      for (int j = 0; j < PMAX; ++j) dv[j] = fma(hdt4, us[j], getD(j));  // dv / 4 + o
       double vl, vr;
       if (bordered) {
         vl = fma(hdt4, uL, eL);
@@ -261,32 +265,46 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
       } else {
         halo<PMAX, NT, FULL>(dv, cnt, L, t, vl, vr, par.hs);
       }
-      const double ao = P.a_off, ad = P.a_diag;
+      // rows (o - v_-, d + v_+ - v_-, o + v_+) from w = v + o:
+      // (2o - w_-, d + (w_+ - w_-), w_+)
+      const double ao2 = 2.0 * P.a_off, ad = P.a_diag;
       auto rowA = [&](int j, double& a, double& b, double& c) {
         const double vm = left_of<PMAX, FULL>(dv, j, vl);
         const double vp = right_of<PMAX, FULL>(dv, j, cnt, vr);
-        a = ao - vm;
+        a = ao2 - vm;
         b = ad + (vp - vm);
-        c = ao + vp;
+        c = vp;
       };
       double ms[PMAX];
       double sl, sr;  // halo of s = m^n + m*
       cyclic_solve<PMAX, NT, FULL>(rowA, fget, ms, cnt, L, t, sl, sr, grow);
-      // max change and max size of m*; a non-finite entry (which fmax would
-      // drop) reaches the Helmholtz right-hand side M m*, and solve_helm then
-      // reports the change as +infinity, which marks the iterate as failed
+      // max change of m*, and on the first iteration its max size, the scale
+      // of the tolerance (later iterates differ from the first by its first
+      // correction, about 1e-4 of it at the workloads' steps); a non-finite
+      // entry (which fmax would drop) reaches the Helmholtz right-hand side
+      // M m*, and solve_helm then reports the change as +infinity, which
+      // marks the iterate as failed
       double diff = 0.0, scale = 0.0;
+      if (k == 1) {
 #pragma unroll
-      for (int j = 0; j < PMAX; ++j) {
-        ms[j] -= m[j];
-        if (FULL || j < cnt) {
-          diff = fmax(diff, fabs(ms[j] - getP(j)));
-          scale = fmax(scale, fabs(ms[j]));
+        for (int j = 0; j < PMAX; ++j) {
+          ms[j] -= m[j];
+          if (FULL || j < cnt) {
+            diff = fmax(diff, fabs(ms[j] - getP(j)));
+            scale = fmax(scale, fabs(ms[j]));
+          }
+          setP(j, ms[j]);
         }
-        setP(j, ms[j]);
+        scale = wave_max(scale);
+      } else {
+#pragma unroll
+        for (int j = 0; j < PMAX; ++j) {
+          ms[j] -= m[j];
+          if (FULL || j < cnt) diff = fmax(diff, fabs(ms[j] - getP(j)));
+          setP(j, ms[j]);
+        }
       }
       diff = wave_max(diff);
-      scale = wave_max(scale);
       // u* = H^{-1} M m*
       double r[PMAX];
       mass_apply_h<PMAX, FULL>(ms, r, P.h, cnt, sl - mL, sr - mR, 1.0);
@@ -304,11 +322,11 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
         status = SCH_E_NONFINITE;
         break;
       }
+      if (k == 1) lim = P.tol * gscale;
       // stop once the iterate's error is within tolerance: for a contraction
       // with ratio c, |m* - m_k| <= c / (1 - c) |m_k - m_{k-1}|; c is the ratio
       // of the last two changes, the bound is used while c < 1/2 (multiplied
       // out: d_k^2 <= lim (d_{k-1} - d_k)), the change itself otherwise
-      const double lim = P.tol * gscale;
       const bool done = (k > 1 && 2.0 * gdiff < gprev) ? gdiff * gdiff <= lim * (gprev - gdiff)
                                                        : gdiff <= lim;
       gprev = gdiff;

@@ -246,6 +246,47 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+def _shape(t: torch.Tensor | None, shape: tuple, name: str):
+    """Raise SchError(SCH_E_SHAPE) unless t (if given) has exactly `shape`;
+    the kernels index the caller's arrays from these sizes, so a mismatch
+    would read or write outside them on the device."""
+    if t is None:
+        return
+    if tuple(t.shape) != tuple(int(d) for d in shape):
+        raise SchError(SCH_E_SHAPE, f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _at_least(t: torch.Tensor | None, numel: int, name: str):
+    if t is None:
+        return
+    if t.numel() < numel:
+        raise SchError(SCH_E_SHAPE, f"{name} has {t.numel()} elements, needs at least {numel}")
+
+
+def _ws(ws: torch.Tensor, nbytes: int, name: str = "workspace"):
+    """The workspace must hold the bytes its *_workspace_bytes query gives."""
+    if nbytes <= 0:
+        raise SchError(SCH_E_ARG, f"invalid {name} request")
+    have = ws.numel() * ws.element_size()
+    if have < nbytes:
+        raise SchError(SCH_E_SHAPE, f"{name} has {have} bytes, the call needs {nbytes}")
+
+
+def _state(model: "Model", n: int, **arrays):
+    for k, v in arrays.items():
+        _shape(v, (n, model.nx), k)
+
+
+def _inc(n: int, s: int, q: int, **arrays):
+    for k, v in arrays.items():
+        _shape(v, (n, s, q), k)
+
+
+def _vec(n: int, **arrays):
+    for k, v in arrays.items():
+        _shape(v, (n,), k)
+
+
 @dataclass
 class Model:
     """SCH model parameters (section 2) with the noise-mode table on the GPU."""
@@ -276,6 +317,7 @@ class Obs:
     sigma: torch.Tensor  # [n_obs]
 
     def c(self) -> SchObsC:
+        _shape(self.sigma, tuple(self.y.shape), "sigma")
         return SchObsC(int(self.y.numel()), _dev(self.y, name="y"), _dev(self.sigma, name="sigma"))
 
 
@@ -313,12 +355,14 @@ def sch_philox_blocks(seed: int, ctr: torch.Tensor, out: torch.Tensor):
 
 def sch_velocity(model: Model, m: torch.Tensor, u: torch.Tensor):
     mc = model.c()
+    _state(model, m.shape[0], m=m, u=u)
     _check(lib().sch_velocity(C.byref(mc), m.shape[0], _dev(m, name="m"), _dev(u, name="u"),
                               _stream()))
 
 
 def sch_init_momentum(model: Model, u: torch.Tensor, m: torch.Tensor):
     mc = model.c()
+    _state(model, u.shape[0], u=u, m=m)
     _check(lib().sch_init_momentum(C.byref(mc), u.shape[0], _dev(u, name="u"), _dev(m, name="m"),
                                    _stream()))
 
@@ -328,6 +372,9 @@ def sch_ensemble_step(model: Model, m: torch.Tensor, u: torch.Tensor, dW: torch.
                       iters: torch.Tensor | None = None):
     mc = model.c()
     n, s = dW.shape[0], dW.shape[1]
+    _state(model, n, m=m, u=u)
+    _inc(n, s, model.n_modes, dW=dW, dLambda=dLambda)
+    _vec(n, status=status, iters=iters)
     _check(lib().sch_ensemble_step(C.byref(mc), n, s, _dev(m, name="m"), _dev(u, name="u"),
                                    _dev(dW, name="dW"), _dev(dLambda, name="dLambda"),
                                    _dev(status, torch.int32, "status"),
@@ -336,12 +383,16 @@ def sch_ensemble_step(model: Model, m: torch.Tensor, u: torch.Tensor, dW: torch.
 
 def sch_observe(model: Model, u: torch.Tensor, out: torch.Tensor):
     mc = model.c()
+    _state(model, u.shape[0], u=u)
+    _shape(out, (u.shape[0], out.shape[-1]), "out")
     _check(lib().sch_observe(C.byref(mc), out.shape[-1], u.shape[0], _dev(u, name="u"),
                              _dev(out, name="out"), _stream()))
 
 
 def sch_loglik(model: Model, obs: Obs, u: torch.Tensor, phi: torch.Tensor):
     mc, oc = model.c(), obs.c()
+    _state(model, u.shape[0], u=u)
+    _vec(u.shape[0], phi=phi)
     _check(lib().sch_loglik(C.byref(mc), C.byref(oc), u.shape[0], _dev(u, name="u"),
                             _dev(phi, name="phi"), _stream()))
 
@@ -349,6 +400,11 @@ def sch_loglik(model: Model, obs: Obs, u: torch.Tensor, phi: torch.Tensor):
 def sch_temper_ess(phi: torch.Tensor, theta: torch.Tensor, ess_threshold: float, n_bisect: int,
                    dtheta: torch.Tensor, w: torch.Tensor, ess: torch.Tensor,
                    logw_extra: torch.Tensor | None = None, logw_out: torch.Tensor | None = None):
+    n = phi.numel()
+    _vec(n, w=w, logw_extra=logw_extra, logw_out=logw_out)
+    _at_least(theta, 1, "theta")
+    _at_least(dtheta, 1, "dtheta")
+    _at_least(ess, 1, "ess")
     _check(lib().sch_temper_ess(phi.numel(), _dev(phi, name="phi"),
                                 _dev(logw_extra, name="logw_extra"), _dev(theta, name="theta"),
                                 ess_threshold, n_bisect, _dev(dtheta, name="dtheta"),
@@ -359,6 +415,11 @@ def sch_temper_ess(phi: torch.Tensor, theta: torch.Tensor, ess_threshold: float,
 def sch_resample(w: torch.Tensor, u0: torch.Tensor, idx: torch.Tensor, workspace: torch.Tensor,
                  cond_ess: torch.Tensor | None = None, cond_threshold: float = 0.0,
                  degenerate: torch.Tensor | None = None):
+    n = w.numel()
+    _vec(n, idx=idx)
+    _at_least(u0, 1, "u0")
+    _at_least(cond_ess, 1, "cond_ess")
+    _ws(workspace, workspace_bytes(WS_RESAMPLE, None, n))
     _check(lib().sch_resample(w.numel(), _dev(w, name="w"), _dev(u0, name="u0"),
                               _dev(cond_ess, name="cond_ess"), cond_threshold,
                               _dev(idx, torch.int32, "idx"), _dev(degenerate, torch.int32,
@@ -369,6 +430,8 @@ def sch_resample(w: torch.Tensor, u0: torch.Tensor, idx: torch.Tensor, workspace
 def sch_gather(idx: torch.Tensor, src: torch.Tensor, dst: torch.Tensor):
     n = idx.numel()
     row = src.numel() // src.shape[0]
+    if dst.shape[1:] != src.shape[1:] or dst.shape[0] != n:
+        raise SchError(SCH_E_SHAPE, f"dst {tuple(dst.shape)} must be [{n}] + {tuple(src.shape[1:])}")
     _check(lib().sch_gather(n, row, _dev(idx, torch.int32, "idx"), _dev(src, name="src"),
                             _dev(dst, name="dst"), _stream()))
 
@@ -383,8 +446,13 @@ def sch_jitter_pcn(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
     mc, oc = model.c(), obs.c()
     r = SchRngC(seed, cycle, temper_k)
     n, s = dW.shape[0], dW.shape[1]
+    _state(model, n, m0=m0, u0=u0, m_end=m_end, u_end=u_end)
+    _inc(n, s, model.n_modes, dW=dW, dLambda=dLambda)
+    _vec(n, phi=phi, n_accept=n_accept)
+    _at_least(theta, 1, "theta")
     if workspace is None:
         workspace = globals()["workspace"](WS_JITTER, model, n, s, n_jitter)
+    _ws(workspace, workspace_bytes(WS_JITTER, model, n, s, n_jitter))
     _check(lib().sch_jitter_pcn(C.byref(mc), C.byref(oc), C.byref(r), n, s, _dev(m0, name="m0"),
                                 _dev(u0, name="u0"), _dev(dW, name="dW"),
                                 _dev(dLambda, name="dLambda"), _dev(phi, name="phi"),
@@ -405,6 +473,10 @@ def sch_jitter_pcn_noalloc(model: Model, obs: Obs, seed: int, cycle: int, temper
     mc, oc = model.c(), obs.c()
     r = SchRngC(seed, cycle, temper_k)
     n, s = dW.shape[0], dW.shape[1]
+    _state(model, n, m0=m0, u0=u0, m_end=m_end, u_end=u_end)
+    _inc(n, s, model.n_modes, dW=dW, dLambda=dLambda)
+    _vec(n, phi=phi, n_accept=n_accept)
+    _at_least(theta, 1, "theta")
     _check(lib().sch_jitter_pcn_noalloc(C.byref(mc), C.byref(oc), C.byref(r), n, s,
                                         _dev(m0, name="m0"), _dev(u0, name="u0"),
                                         _dev(dW, name="dW"), _dev(dLambda, name="dLambda"),
@@ -418,6 +490,10 @@ def sch_pf_bootstrap_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: tor
                            u: torch.Tensor, logw: torch.Tensor, n_steps: int, ess_frac: float,
                            workspace: torch.Tensor) -> dict:
     mc, oc = model.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _vec(n, logw=logw)
+    _ws(workspace, workspace_bytes(WS_BOOTSTRAP, model, n, n_steps))
     st = SchCycleStats()
     _check(lib().sch_pf_bootstrap_cycle(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0],
                                         n_steps, ess_frac, _dev(m, name="m"), _dev(u, name="u"),
@@ -432,6 +508,9 @@ def sch_pf_tempered_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torc
                           rho: float, n_jitter: int, max_temper: int,
                           workspace: torch.Tensor) -> dict:
     mc, oc = model.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _ws(workspace, workspace_bytes(WS_TEMPERED, model, n, n_steps, n_jitter))
     st = SchCycleStats()
     _check(lib().sch_pf_tempered_cycle(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0],
                                        n_steps, ess_threshold, n_bisect, rho, n_jitter,
@@ -456,6 +535,7 @@ class Matern:
 
 def sch_matern_field(model: Model, mt: Matern, dWc: torch.Tensor, dU: torch.Tensor):
     mc, tc = model.c(), mt.c()
+    _state(model, dWc.shape[0], dWc=dWc, dU=dU)
     _check(lib().sch_matern_field(C.byref(mc), C.byref(tc), dWc.shape[0], _dev(dWc, name="dWc"),
                                   _dev(dU, name="dU"), _stream()))
 
@@ -465,6 +545,9 @@ def sch_ensemble_step_matern(model: Model, mt: Matern, m: torch.Tensor, u: torch
                              iters: torch.Tensor | None = None):
     mc, tc = model.c(), mt.c()
     n, s = dWc.shape[0], dWc.shape[1]
+    _state(model, n, m=m, u=u)
+    _inc(n, s, model.nx, dWc=dWc)
+    _vec(n, status=status, iters=iters)
     _check(lib().sch_ensemble_step_matern(C.byref(mc), C.byref(tc), n, s, _dev(m, name="m"),
                                           _dev(u, name="u"), _dev(dWc, name="dWc"),
                                           _dev(status, torch.int32, "status"),
@@ -475,11 +558,17 @@ def matern_workspace(which: int, model: Model, n_particles: int, n_steps: int, e
                      device="cuda") -> torch.Tensor:
     """Scratch of the Matern-noise calls; extra is n_jitter (jitter and
     cycles) or ckpt_every (WS_NUDGE_GRAD, WS_NUDGE)."""
+    return torch.empty(matern_workspace_bytes(which, model, n_particles, n_steps, extra),
+                       dtype=torch.uint8, device=device)
+
+
+def matern_workspace_bytes(which: int, model: Model, n_particles: int, n_steps: int,
+                           extra: int) -> int:
     mc = model.c()
     nb = int(lib().sch_matern_workspace_bytes(which, C.byref(mc), n_particles, n_steps, extra))
     if nb <= 0:
         raise SchError(SCH_E_ARG, "invalid workspace request")
-    return torch.empty(nb, dtype=torch.uint8, device=device)
+    return nb
 
 
 def sch_jitter_pcn_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
@@ -491,8 +580,13 @@ def sch_jitter_pcn_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: 
     mc, tc, oc = model.c(), mt.c(), obs.c()
     r = SchRngC(seed, cycle, temper_k)
     n, s = dWc.shape[0], dWc.shape[1]
+    _state(model, n, m0=m0, u0=u0, m_end=m_end, u_end=u_end)
+    _inc(n, s, model.nx, dWc=dWc)
+    _vec(n, phi=phi, n_accept=n_accept)
+    _at_least(theta, 1, "theta")
     if workspace is None:
         workspace = matern_workspace(WS_JITTER, model, n, s, n_jitter)
+    _ws(workspace, matern_workspace_bytes(WS_JITTER, model, n, s, n_jitter))
     _check(lib().sch_jitter_pcn_matern(C.byref(mc), C.byref(tc), C.byref(oc), C.byref(r), n, s,
                                        _dev(m0, name="m0"), _dev(u0, name="u0"),
                                        _dev(dWc, name="dWc"), _dev(phi, name="phi"),
@@ -513,8 +607,13 @@ def sch_jitter_pcn_matern_ctrl(model: Model, mt: Matern, obs: Obs, seed: int, cy
     mc, tc, oc = model.c(), mt.c(), obs.c()
     r = SchRngC(seed, cycle, temper_k)
     n, s = dWc.shape[0], dWc.shape[1]
+    _state(model, n, m0=m0, u0=u0, m_end=m_end, u_end=u_end)
+    _inc(n, s, model.nx, dWc=dWc, dLambdac=dLambdac)
+    _vec(n, J=J, n_accept=n_accept)
+    _at_least(theta, 1, "theta")
     if workspace is None:
         workspace = matern_workspace(WS_JITTER, model, n, s, n_jitter)
+    _ws(workspace, matern_workspace_bytes(WS_JITTER, model, n, s, n_jitter))
     _check(lib().sch_jitter_pcn_matern_ctrl(C.byref(mc), C.byref(tc), C.byref(oc), C.byref(r), n,
                                             s, _dev(m0, name="m0"), _dev(u0, name="u0"),
                                             _dev(dWc, name="dWc"),
@@ -531,6 +630,9 @@ def sch_pf_tempered_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, 
                                  ess_threshold: float, n_bisect: int, rho: float, n_jitter: int,
                                  max_temper: int, workspace: torch.Tensor) -> dict:
     mc, tc, oc = model.c(), mt.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _ws(workspace, matern_workspace_bytes(WS_TEMPERED, model, n, n_steps, n_jitter))
     st = SchCycleStats()
     _check(lib().sch_pf_tempered_cycle_matern(C.byref(mc), C.byref(tc), C.byref(oc), seed, cycle,
                                               m.shape[0], n_steps, ess_threshold, n_bisect, rho,
@@ -545,6 +647,10 @@ def sch_pf_bootstrap_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int,
                                   m: torch.Tensor, u: torch.Tensor, logw: torch.Tensor,
                                   n_steps: int, ess_frac: float, workspace: torch.Tensor) -> dict:
     mc, tc, oc = model.c(), mt.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _vec(n, logw=logw)
+    _ws(workspace, matern_workspace_bytes(WS_BOOTSTRAP, model, n, n_steps, 0))
     st = SchCycleStats()
     _check(lib().sch_pf_bootstrap_cycle_matern(C.byref(mc), C.byref(tc), C.byref(oc), seed,
                                                cycle, m.shape[0], n_steps, ess_frac,
@@ -558,12 +664,18 @@ def sch_pf_bootstrap_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int,
 # --------------------------------------------------------------------------- pCN Langevin
 def pcnl_workspace(which: int, model: Model, n_particles: int, n_steps: int, n_jitter: int,
                    ckpt_every: int = 8, device="cuda") -> torch.Tensor:
+    return torch.empty(pcnl_workspace_bytes(which, model, n_particles, n_steps, n_jitter,
+                                            ckpt_every), dtype=torch.uint8, device=device)
+
+
+def pcnl_workspace_bytes(which: int, model: Model, n_particles: int, n_steps: int,
+                         n_jitter: int, ckpt_every: int = 8) -> int:
     mc = model.c()
     nb = int(lib().sch_pcnl_workspace_bytes(which, C.byref(mc), n_particles, n_steps, n_jitter,
                                             ckpt_every))
     if nb <= 0:
         raise SchError(SCH_E_ARG, "invalid workspace request")
-    return torch.empty(nb, dtype=torch.uint8, device=device)
+    return nb
 
 
 def sch_jitter_pcnl(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
@@ -574,8 +686,13 @@ def sch_jitter_pcnl(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int
     mc, oc = model.c(), obs.c()
     r = SchRngC(seed, cycle, temper_k)
     n, s = dW.shape[0], dW.shape[1]
+    _state(model, n, m0=m0, u0=u0, m_end=m_end, u_end=u_end)
+    _inc(n, s, model.n_modes, dW=dW)
+    _vec(n, phi=phi, n_accept=n_accept)
+    _at_least(theta, 1, "theta")
     if workspace is None:
         workspace = pcnl_workspace(WS_JITTER, model, n, s, n_jitter, ckpt_every)
+    _ws(workspace, pcnl_workspace_bytes(WS_JITTER, model, n, s, n_jitter, ckpt_every))
     _check(lib().sch_jitter_pcnl(C.byref(mc), C.byref(oc), C.byref(r), n, s, _dev(m0, name="m0"),
                                  _dev(u0, name="u0"), _dev(dW, name="dW"), _dev(phi, name="phi"),
                                  _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
@@ -589,6 +706,9 @@ def sch_pf_tempered_cycle_pcnl(model: Model, obs: Obs, seed: int, cycle: int, m:
                                n_bisect: int, rho: float, n_jitter: int, max_temper: int,
                                workspace: torch.Tensor, ckpt_every: int = 8) -> dict:
     mc, oc = model.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _ws(workspace, pcnl_workspace_bytes(WS_TEMPERED, model, n, n_steps, n_jitter, ckpt_every))
     st = SchCycleStats()
     _check(lib().sch_pf_tempered_cycle_pcnl(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0],
                                             n_steps, ess_threshold, n_bisect, rho, n_jitter,
@@ -603,6 +723,7 @@ def sch_pf_tempered_cycle_pcnl(model: Model, obs: Obs, seed: int, cycle: int, m:
 def sch_paper_init(model: Model, seed: int, u: torch.Tensor):
     """Initial velocities of eq. init_solve for the rows of u [n][nx]."""
     mc = model.c()
+    _state(model, u.shape[0], u=u)
     _check(lib().sch_paper_init(C.byref(mc), seed, u.shape[0], _dev(u, name="u"), _stream()))
 
 
@@ -610,10 +731,13 @@ def sch_ensemble_stats(u: torch.Tensor, ua: torch.Tensor, workspace: torch.Tenso
                        out: torch.Tensor | None = None) -> torch.Tensor:
     """(EMRE, RB, RES) of the ensemble u [n][nx] against the truth ua [nx], on the GPU."""
     n, nx = u.shape
+    _shape(ua, (nx,), "ua")
     if workspace is None:
         workspace = torch.empty(nx + 2 * n, dtype=torch.float64, device=u.device)
     if out is None:
         out = torch.empty(3, dtype=torch.float64, device=u.device)
+    _at_least(workspace, nx + 2 * n, "workspace")
+    _at_least(out, 3, "out")
     _check(lib().sch_ensemble_stats(n, nx, _dev(u, name="u"), _dev(ua, name="ua"),
                                     _dev(workspace, name="workspace"), _dev(out, name="out"),
                                     _stream()))
@@ -627,8 +751,12 @@ def sch_nudge_grad(model: Model, obs: Obs, m0: torch.Tensor, u0: torch.Tensor,
     """J [n] and dJ/d(dLambda) [n][n_steps][Q]; the window length is grad.shape[1]."""
     mc, oc = model.c(), obs.c()
     n, s = grad.shape[0], grad.shape[1]
+    _state(model, n, m0=m0, u0=u0)
+    _inc(n, s, model.n_modes, grad=grad, dW=dW, dLambda=dLambda)
+    _vec(n, J=J, status=status)
     if workspace is None:
         workspace = globals()["workspace"](WS_NUDGE_GRAD, model, n, s, ckpt_every)
+    _ws(workspace, workspace_bytes(WS_NUDGE_GRAD, model, n, s, ckpt_every))
     _check(lib().sch_nudge_grad(C.byref(mc), C.byref(oc), n, s, _dev(m0, name="m0"),
                                 _dev(u0, name="u0"), _dev(dW, name="dW"),
                                 _dev(dLambda, name="dLambda"), ckpt_every, _dev(J, name="J"),
@@ -648,8 +776,12 @@ def sch_nudge_run(model: Model, obs: Obs, m: torch.Tensor, u: torch.Tensor, dW: 
                   workspace: torch.Tensor | None = None):
     mc, oc = model.c(), obs.c()
     n, s = dW.shape[0], dW.shape[1]
+    _state(model, n, m=m, u=u)
+    _inc(n, s, model.n_modes, dW=dW, dLambda=dLambda)
+    _vec(n, logG=logG, lbfgs_status=lbfgs_status, iters=iters, evals=evals, status=status)
     if workspace is None:
         workspace = globals()["workspace"](WS_NUDGE, model, n, s, ckpt_every)
+    _ws(workspace, workspace_bytes(WS_NUDGE, model, n, s, ckpt_every))
     opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
     _check(lib().sch_nudge_run(C.byref(mc), C.byref(oc), n, s, _dev(m, name="m"),
                                _dev(u, name="u"), _dev(dW, name="dW"),
@@ -671,8 +803,12 @@ def sch_nudge_grad_matern(model: Model, mt: Matern, obs: Obs, m0: torch.Tensor,
     cell, [n][n_steps][nx]; the window length is grad.shape[1]."""
     mc, tc, oc = model.c(), mt.c(), obs.c()
     n, s = grad.shape[0], grad.shape[1]
+    _state(model, n, m0=m0, u0=u0)
+    _inc(n, s, model.nx, grad=grad, dWc=dWc, dLambdac=dLambdac)
+    _vec(n, J=J, status=status)
     if workspace is None:
         workspace = matern_workspace(WS_NUDGE_GRAD, model, n, s, ckpt_every)
+    _ws(workspace, matern_workspace_bytes(WS_NUDGE_GRAD, model, n, s, ckpt_every))
     _check(lib().sch_nudge_grad_matern(C.byref(mc), C.byref(tc), C.byref(oc), n, s,
                                        _dev(m0, name="m0"), _dev(u0, name="u0"),
                                        _dev(dWc, name="dWc"), _dev(dLambdac, name="dLambdac"),
@@ -693,8 +829,12 @@ def sch_nudge_run_matern(model: Model, mt: Matern, obs: Obs, m: torch.Tensor, u:
     """sch_nudge_run with the Matern-type noise: one control per cell."""
     mc, tc, oc = model.c(), mt.c(), obs.c()
     n, s = dWc.shape[0], dWc.shape[1]
+    _state(model, n, m=m, u=u)
+    _inc(n, s, model.nx, dWc=dWc, dLambdac=dLambdac)
+    _vec(n, logG=logG, lbfgs_status=lbfgs_status, iters=iters, evals=evals, status=status)
     if workspace is None:
         workspace = matern_workspace(WS_NUDGE, model, n, s, ckpt_every)
+    _ws(workspace, matern_workspace_bytes(WS_NUDGE, model, n, s, ckpt_every))
     opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
     _check(lib().sch_nudge_run_matern(C.byref(mc), C.byref(tc), C.byref(oc), n, s,
                                       _dev(m, name="m"), _dev(u, name="u"),
@@ -710,12 +850,18 @@ def sch_nudge_run_matern(model: Model, mt: Matern, obs: Obs, m: torch.Tensor, u:
 
 def nudged_workspace(model: Model, n_particles: int, n_steps: int, n_jitter: int,
                      ckpt_every: int = 8, device="cuda") -> torch.Tensor:
+    return torch.empty(nudged_workspace_bytes(model, n_particles, n_steps, n_jitter, ckpt_every),
+                       dtype=torch.uint8, device=device)
+
+
+def nudged_workspace_bytes(model: Model, n_particles: int, n_steps: int, n_jitter: int,
+                           ckpt_every: int = 8) -> int:
     mc = model.c()
     nb = int(lib().sch_nudged_workspace_bytes(C.byref(mc), n_particles, n_steps, n_jitter,
                                               ckpt_every))
     if nb <= 0:
         raise SchError(SCH_E_ARG, "invalid workspace request")
-    return torch.empty(nb, dtype=torch.uint8, device=device)
+    return nb
 
 
 def sch_pf_nudged_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
@@ -725,6 +871,10 @@ def sch_pf_nudged_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.
                         max_iter: int = LBFGS_MAX_ITER, mem: int = LBFGS_MEM,
                         max_back: int = LBFGS_MAX_BACK, ckpt_every: int = 8) -> dict:
     mc, oc = model.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _inc(n, n_steps, model.n_modes, dLambda=dLambda)
+    _ws(workspace, nudged_workspace_bytes(model, n, n_steps, n_jitter, ckpt_every))
     st = SchCycleStats()
     opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
     _check(lib().sch_pf_nudged_cycle(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0], n_steps,
@@ -738,12 +888,19 @@ def sch_pf_nudged_cycle(model: Model, obs: Obs, seed: int, cycle: int, m: torch.
 
 def nudged_workspace_matern(model: Model, n_particles: int, n_steps: int, n_jitter: int,
                             ckpt_every: int = 8, device="cuda") -> torch.Tensor:
+    return torch.empty(nudged_workspace_bytes_matern(model, n_particles, n_steps, n_jitter,
+                                                     ckpt_every),
+                       dtype=torch.uint8, device=device)
+
+
+def nudged_workspace_bytes_matern(model: Model, n_particles: int, n_steps: int, n_jitter: int,
+                                  ckpt_every: int = 8) -> int:
     mc = model.c()
     nb = int(lib().sch_nudged_workspace_bytes_matern(C.byref(mc), n_particles, n_steps,
                                                      n_jitter, ckpt_every))
     if nb <= 0:
         raise SchError(SCH_E_ARG, "invalid workspace request")
-    return torch.empty(nb, dtype=torch.uint8, device=device)
+    return nb
 
 
 def sch_pf_nudged_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, cycle: int,
@@ -755,6 +912,10 @@ def sch_pf_nudged_cycle_matern(model: Model, mt: Matern, obs: Obs, seed: int, cy
                                ckpt_every: int = 8) -> dict:
     """sch_pf_nudged_cycle with the Matern-type noise; dLambdac [n][n_steps][nx]."""
     mc, tc, oc = model.c(), mt.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _inc(n, n_steps, model.nx, dLambdac=dLambdac)
+    _ws(workspace, nudged_workspace_bytes_matern(model, n, n_steps, n_jitter, ckpt_every))
     st = SchCycleStats()
     opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
     _check(lib().sch_pf_nudged_cycle_matern(C.byref(mc), C.byref(tc), C.byref(oc), seed, cycle,
@@ -842,7 +1003,7 @@ def sch_mlp_param_count(n_in: int, n_hidden: int, n_out: int) -> int:
 @dataclass
 class Mlp:
     """Warm-start network: float32 master parameters and their bfloat16 weight
-    copy (GPU tensors)."""
+    copy (GPU tensors, sizes checked against the layer widths)."""
     n_in: int
     n_hidden: int
     n_out: int
@@ -850,6 +1011,10 @@ class Mlp:
     weights_bf16: torch.Tensor  # bfloat16 [H F + H H + O H]
 
     def c(self) -> SchMlpC:
+        _at_least(self.params, sch_mlp_param_count(self.n_in, self.n_hidden, self.n_out),
+                  "params")
+        _at_least(self.weights_bf16, self.n_hidden * self.n_in + self.n_hidden * self.n_hidden
+                  + self.n_out * self.n_hidden, "weights_bf16")
         return SchMlpC(self.n_in, self.n_hidden, self.n_out,
                        _dev(self.params, torch.float32, "params"),
                        _dev(self.weights_bf16, torch.bfloat16, "weights_bf16"))
@@ -867,6 +1032,10 @@ def sch_mlp_sync(net: Mlp):
 
 def sch_mlp_forward(net: Mlp, X: torch.Tensor, Y: torch.Tensor, workspace: torch.Tensor):
     nc = net.c()
+    B = X.shape[0]
+    _shape(X, (B, net.n_in), "X")
+    _shape(Y, (B, net.n_out), "Y")
+    _ws(workspace, sch_mlp_workspace_bytes(net, B))
     _check(lib().sch_mlp_forward(C.byref(nc), X.shape[0], _dev(X, torch.bfloat16, "X"),
                                  _dev(Y, torch.float32, "Y"),
                                  _dev(workspace, torch.uint8, "workspace"), _stream()))
@@ -875,6 +1044,13 @@ def sch_mlp_forward(net: Mlp, X: torch.Tensor, Y: torch.Tensor, workspace: torch
 def sch_mlp_backward(net: Mlp, X: torch.Tensor, Y: torch.Tensor, T: torch.Tensor,
                      loss: torch.Tensor, grad: torch.Tensor, workspace: torch.Tensor):
     nc = net.c()
+    B = X.shape[0]
+    _shape(X, (B, net.n_in), "X")
+    _shape(Y, (B, net.n_out), "Y")
+    _shape(T, (B, net.n_out), "T")
+    _at_least(loss, 1, "loss")
+    _at_least(grad, net.params.numel(), "grad")
+    _ws(workspace, sch_mlp_workspace_bytes(net, B))
     _check(lib().sch_mlp_backward(C.byref(nc), X.shape[0], _dev(X, torch.bfloat16, "X"),
                                   _dev(Y, torch.float32, "Y"), _dev(T, torch.float32, "T"),
                                   _dev(loss, torch.float64, "loss"),
@@ -885,6 +1061,10 @@ def sch_mlp_backward(net: Mlp, X: torch.Tensor, Y: torch.Tensor, T: torch.Tensor
 def sch_mlp_adam(net: Mlp, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
                  lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
     nc = net.c()
+    k = net.params.numel()
+    _at_least(grad, k, "grad")
+    _at_least(m, k, "m")
+    _at_least(v, k, "v")
     _check(lib().sch_mlp_adam(C.byref(nc), _dev(grad, torch.float32, "grad"),
                               _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"), step,
                               lr, beta1, beta2, eps, _stream()))

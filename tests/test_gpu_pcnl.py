@@ -97,8 +97,7 @@ def test_pcnl_argument_errors(sch):
     n, s, q = 2, 3, wl.n_modes
     z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
     obs = sch.Obs(z(4) + 1.0, z(4) + 1.0)
-    with pytest.raises(sch.SchError):   # rho = 1 leaves no proposal noise
+    with pytest.raises(sch.SchError, match="bad arguments"):   # rho = 1: no proposal noise
         sch.sch_jitter_pcnl(gm, obs, 1, 0, 0, z(n, wl.nx), z(n, wl.nx), z(n, s, q), z(n),
-                            z(n, wl.nx), z(n, wl.nx), z(1), 1.0, 2, 4,
-                            workspace=torch.zeros(8, dtype=torch.uint8, device="cuda"))
+                            z(n, wl.nx), z(n, wl.nx), z(1), 1.0, 2, 4)
     assert sch.lib().sch_pcnl_workspace_bytes(sch.WS_BOOTSTRAP, None, n, s, 2, 4) == 0
