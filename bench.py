@@ -365,24 +365,36 @@ PEAK_BF16_TFLOPS = 2500.0
 
 
 def bench_warmstart(args):
-    """Plain versus warm-started nudging at the nudging workload (Nx = 2048,
-    2048 particles, 40 steps, 8 modes, 256 observations): the network
-    (256 + 2048 -> 256 -> 256 -> 320) is trained on the GPU on the plain-
-    nudging solutions of --train-windows windows, then one step = one nudged
-    window of the whole ensemble, timed for both starts on the same inputs."""
+    """The learned warm start of nudging against plain nudging, at 4096 nodes x
+    4096 particles (8 modes, 40-step windows, 256 observations, sigma 0.02).
+    The network (256 misfits + 4096 velocities -> 256 -> 256 -> 320 controls,
+    BF16 on the matrix cores) is trained on the GPU on the plain-nudging
+    solutions of --train-windows consecutive windows (25: 102400 pairs).  Then
+    one step = one cycle of the nudged filter (nudging, tempering, jittering),
+    run for --steps cycles by four ensembles from the same start on the same
+    observations and seeds: plain nudging from zero controls; the network's
+    controls as they are; the network's controls as the L-BFGS start with one
+    accepted step per stage; and one step per stage from zero (the ablation
+    that shows what the network adds).  The line's value is the third arm,
+    the learned form that reaches plain nudging's likelihood; particles whose
+    misfit lies outside the training range are nudged from zero in every
+    learned arm.  The same four are also compared on identical inputs (mean
+    likelihood and objective after nudging one window, objective evaluations
+    per particle)."""
     import torch
 
     from paper_2402_06927_amd import sch
     from paper_2402_06927_amd import warmstart as WS
     from paper_2402_06927_amd import workloads as W
 
-    wl = W.NUDGING_2048
+    wl = W.WARMSTART_4096
     if args.particles:
         wl = wl.scaled(n_particles=args.particles)
     dev = "cuda"
     n, nx, Q, S, nobs = wl.n_particles, wl.nx, wl.n_modes, wl.n_steps, wl.n_obs
-    n_train = args.train_windows
-    log(f"bench: warm start, {wl.name}, {n_train} training windows")
+    n_train, n_cycles = args.train_windows, args.steps
+    n_jit, ckpt, thr = wl.n_jitter, 8, wl.ess_threshold
+    log(f"bench: warm start, {wl.name}, {n_train} training windows, {n_cycles} cycles")
     xi = torch.tensor(W.mode_table(wl.L, nx, Q, wl.mode_amp), device=dev)
     model = sch.Model(L=wl.L, alpha=wl.alpha, mu=wl.mu, dt=wl.dt, xi=xi)
     ts = W.truth_seed(wl)
@@ -392,7 +404,7 @@ def bench_warmstart(args):
     u = torch.tensor(W.initial_velocity(wl, n, wl.seed), device=dev)
     m = torch.empty_like(u)
     sch.sch_init_momentum(model, u, m)
-    z = torch.tensor(W.obs_noise(wl, ts, n_train + 1), device=dev)
+    z = torch.tensor(W.obs_noise(wl, ts, n_train + n_cycles), device=dev)
     sig = torch.full((nobs,), wl.sigma_obs, dtype=torch.float64, device=dev)
 
     def obs_for(c):
@@ -403,75 +415,158 @@ def bench_warmstart(args):
         sch.sch_observe(model, ut, y)
         return sch.Obs((y[0] + wl.sigma_obs * z[c]).contiguous(), sig)
 
+    def mean_phi(obs, uu):
+        phi = torch.empty(uu.shape[0], dtype=torch.float64, device=dev)
+        sch.sch_loglik(model, obs, uu, phi)
+        return float(phi.mean())
+
+    # ---- training data: plain nudging of consecutive windows
     ws = WS.WarmStart(nobs, nx, S, Q)
-    nws = sch.workspace(sch.WS_NUDGE, model, n, S, 8)
+    nws = sch.workspace(sch.WS_NUDGE, model, n, S, ckpt)
     parts = []
+    t0 = time.perf_counter()
     for c in range(n_train):
         obs = obs_for(c)
         dW = torch.empty((n, S, Q), dtype=torch.float64, device=dev)
         sch.sch_draw_increments(wl.seed, c, 0, sch.TAG_NUDGE, dW, wl.dt)
         parts.append(ws.collect(model, obs, m, u, dW, nws))
-        log(f"training window {c} collected")
+        log(f"training window {c} collected ({time.perf_counter() - t0:.0f} s)")
+    del nws
     data = WS.concat(parts)
+    del parts
     ws.fit_scaling(data)
     X, T = ws.encode(data)
+    n_pairs = int(X.shape[0])
+    del data
     B = 256
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
-    hist = ws.train(X, T, epochs=args.epochs, batch=B, lr=1e-3, log=log)
+    hist = ws.train(X, T, epochs=args.epochs, batch=B, lr=1e-3,
+                    log=lambda s: log(s) if s.endswith("0") or True else None)
     e1.record()
     torch.cuda.synchronize()
     train_ms = e0.elapsed_time(e1)
-    steps = args.epochs * (X.shape[0] // B)
+    steps_train = args.epochs * (n_pairs // B)
     F, H, O = ws.F, ws.H, ws.O
-    # training step: forward 2 B (F H + H H + H O), backward twice that
     flops_step = 3 * 2 * B * (F * H + H * H + H * O)
-    obs = obs_for(n_train)
+    del X, T
+
+    # ---- the nudged forecasts on identical inputs (the first cycle's window)
+    c0 = n_train
+    ut0, mt0 = ut.clone(), mt.clone()  # the truth at the first filter cycle's start
+    obs0 = obs_for(c0)
     dW = torch.empty((n, S, Q), dtype=torch.float64, device=dev)
-    sch.sch_draw_increments(wl.seed, n_train, 0, sch.TAG_NUDGE, dW, wl.dt)
-    res = {}
-    for mode in ("plain", "warm"):
-        times, evs, phis = [], [], []
-        for rep in range(args.warmup + args.steps):
-            mm, uu = m.clone(), u.clone()
-            dl = torch.zeros_like(dW)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            if mode == "warm":
-                ws.predict(model, obs, uu, dl)
-            logG = torch.empty(n, dtype=torch.float64, device=dev)
-            ev = torch.empty(n, dtype=torch.int32, device=dev)
-            sch.sch_nudge_run(model, obs, mm, uu, dW, dl, logG, warm_start=(mode == "warm"),
+    sch.sch_draw_increments(wl.seed, c0, 0, sch.TAG_NUDGE, dW, wl.dt)
+    mm, uu = m.clone(), u.clone()
+    sch.sch_ensemble_step(model, mm, uu, dW)
+    same = {"none": mean_phi(obs0, uu)}
+    nws = sch.workspace(sch.WS_NUDGE, model, n, S, ckpt)
+    for arm in ("plain", "plain_1iter", "learned_1iter", "learned"):
+        mm, uu = m.clone(), u.clone()
+        dl = torch.zeros_like(dW)
+        logG = torch.empty(n, dtype=torch.float64, device=dev)
+        ev = torch.zeros(n, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        if arm in ("plain", "plain_1iter"):
+            sch.sch_nudge_run(model, obs0, mm, uu, dW, dl, logG, evals=ev, workspace=nws,
+                              max_iter=1 if arm == "plain_1iter" else sch.LBFGS_MAX_ITER)
+        elif arm == "learned_1iter":
+            ws.predict(model, obs0, uu, dl)
+            sch.sch_nudge_run(model, obs0, mm, uu, dW, dl, logG, warm_start=True, max_iter=1,
                               evals=ev, workspace=nws)
-            phi = torch.empty(n, dtype=torch.float64, device=dev)
-            sch.sch_loglik(model, obs, uu, phi)
+        else:
+            # the network's controls as they are (zero where the misfit is out of
+            # range: this diagnostic leaves those particles un-nudged)
+            ws.predict(model, obs0, uu, dl)
+            sch.sch_ensemble_step(model, mm, uu, dW, dl)
+            logG = -((0.5 * dl * dl + dl * dW).sum(dim=(1, 2)) / wl.dt)
+        torch.cuda.synchronize()
+        phi = torch.empty(n, dtype=torch.float64, device=dev)
+        sch.sch_loglik(model, obs0, uu, phi)
+        same[arm] = {"mean_phi": float(phi.mean()), "mean_J": float((phi - logG).mean()),
+                     "evals_per_particle": float(ev.double().mean()),
+                     "seconds": round(time.perf_counter() - ta, 3)}
+        log(f"same inputs, {arm}: {same[arm]}")
+    del nws
+
+    # ---- the nudged filter, arm by arm, cycle by cycle
+    # plain: nudging from zero with the default stopping rule; learned_keep: the
+    # network's controls as they are (plain nudging past the training range);
+    # learned_1iter: the network's controls as the L-BFGS start, one accepted
+    # step per stage; plain_1iter: the same optimiser budget from zero (what
+    # the network adds over the method without it).
+    arms = {"plain": (None, {}), "learned_keep": (sch.NUDGE_KEEP, {}),
+            "learned_1iter": (sch.NUDGE_FROM_GIVEN, {"max_iter": 1}),
+            "plain_1iter": (None, {"max_iter": 1})}
+    cws = sch.nudged_workspace(model, n, S, n_jit, ckpt)
+    res = {a: {"seconds": [], "n_temper": [], "final_phi": [], "fallback": []} for a in arms}
+    for arm, (keep, lb) in arms.items():
+        ut.copy_(ut0)
+        mt.copy_(mt0)
+        ma, ua = m.clone(), u.clone()
+        for c in range(n_cycles):
+            obs = obs_for(c0 + c)
+            dl = torch.zeros((n, S, Q), dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
-            if rep >= args.warmup:
-                times.append(time.perf_counter() - t0)
-                evs.append(float(ev.double().mean()))
-                phis.append(float(phi.mean()))
-        res[mode] = {"windows_per_s": len(times) / sum(times),
-                     "evals_per_particle": sum(evs) / len(evs),
-                     "mean_phi": sum(phis) / len(phis)}
-        log(f"{mode}: {res[mode]}")
-    train_tflops = flops_step * steps / (train_ms * 1e-3) / 1e12
+            ta = time.perf_counter()
+            if keep is None:
+                st = sch.sch_pf_nudged_cycle(model, obs, wl.seed, c0 + c, ma, ua, dl, S, thr,
+                                             wl.n_bisect, wl.rho, n_jit, wl.max_temper, cws,
+                                             ckpt_every=ckpt, **lb)
+                nfb = 0
+            else:
+                mode = torch.empty(n, dtype=torch.int32, device=dev)
+                ws.predict(model, obs, ua, dl, True, mode, keep)
+                st = sch.sch_pf_nudged_cycle_warm(model, obs, wl.seed, c0 + c, ma, ua, dl, mode,
+                                                  S, thr, wl.n_bisect, wl.rho, n_jit,
+                                                  wl.max_temper, cws, ckpt_every=ckpt, **lb)
+                nfb = int((mode == sch.NUDGE_FROM_ZERO).sum())
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - ta
+            r = res[arm]
+            r["seconds"].append(round(dt, 3))
+            r["n_temper"].append(st["n_temper"])
+            r["final_phi"].append(mean_phi(obs, ua))
+            r["fallback"].append(nfb)
+            log(f"{arm} cycle {c}: {dt:.2f} s, tempering steps {st['n_temper']}, "
+                f"fallback {nfb}, final mean phi {r['final_phi'][-1]:.2f}")
+        del ma, ua
+    for arm in res:
+        r = res[arm]
+        r["cycles_per_s"] = n_cycles / sum(r["seconds"])
+        r["mean_final_phi"] = sum(r["final_phi"]) / n_cycles
+    def versus(a, b):
+        return {"speedup": round(res[a]["cycles_per_s"] / res[b]["cycles_per_s"], 3),
+                "final_phi_rel_diff": (res[a]["mean_final_phi"] - res[b]["mean_final_phi"])
+                / res[b]["mean_final_phi"]}
+
+    le = res["learned_1iter"]
+    train_tflops = flops_step * steps_train / (train_ms * 1e-3) / 1e12
     out = {
-        "metric": "nudged windows/s with the learned warm start (plain nudging beside it)",
-        "value": round(res["warm"]["windows_per_s"], 4),
-        "unit": "windows/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 / res["warm"]["windows_per_s"], 2),
+        "metric": "nudged-filter assimilation cycles/s with the learned warm start "
+                  "(plain nudging beside it)",
+        "value": round(le["cycles_per_s"], 4),
+        "unit": "cycles/s",
+        "n_gpus": 1, "steps": n_cycles, "warmup": 0,
+        "ms_per_step": round(1e3 / le["cycles_per_s"], 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 model, bf16/f32 network", "data": "synthetic",
-        "config": {"workload": wl.name + "_warmstart", "nx": nx, "n_particles": n,
-                   "n_modes": Q, "n_steps": S, "n_obs": nobs, "network": [F, H, H, O],
-                   "training_pairs": int(X.shape[0]), "epochs": args.epochs, "batch": B},
-        "plain": res["plain"], "warm": res["warm"],
-        "speedup": round(res["warm"]["windows_per_s"] / res["plain"]["windows_per_s"], 4),
-        "phi_rel_diff": abs(res["warm"]["mean_phi"] - res["plain"]["mean_phi"])
-        / res["plain"]["mean_phi"],
-        "training_loss": [hist[0], hist[-1]],
+        "config": {"workload": wl.name, "nx": nx, "n_particles": n, "n_modes": Q, "n_steps": S,
+                   "n_obs": nobs, "network": [F, H, H, O], "training_pairs": n_pairs,
+                   "epochs": args.epochs, "batch": B, "n_jitter": n_jit, "rho": wl.rho,
+                   "value_arm": "learned_1iter"},
+        "arms": res,
+        "learned_keep_vs_plain": versus("learned_keep", "plain"),
+        "learned_1iter_vs_plain": versus("learned_1iter", "plain"),
+        "plain_1iter_vs_plain": versus("plain_1iter", "plain"),
+        "network_gain_at_1iter": versus("learned_1iter", "plain_1iter"),
+        "same_inputs": same,
+        "same_inputs_phi_rel_diff": (same["learned"]["mean_phi"] - same["plain"]["mean_phi"])
+        / same["plain"]["mean_phi"],
+        "training": {"loss_first_last": [hist[0], hist[-1]], "ms": round(train_ms, 1),
+                     "steps": steps_train, "tflops": round(train_tflops, 3)},
         "roofline": {"bound": "mfma", "achieved": round(train_tflops, 3),
                      "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(train_tflops / PEAK_BF16_TFLOPS, 5), "traffic": None,
@@ -821,7 +916,7 @@ def main():
                     help="threads per particle of the model kernels (0 = automatic)")
     ap.add_argument("--exp", type=int, choices=(1, 2), default=1,
                     help="paper workload: 1 full domain observed, 2 half domain")
-    ap.add_argument("--train-windows", type=int, default=4)
+    ap.add_argument("--train-windows", type=int, default=25)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="run only a plain copy of BYTES (traffic-counter calibration)")

@@ -412,6 +412,27 @@ int sch_pf_nudged_cycle(const sch_model *model, const sch_obs *obs, uint64_t see
                         double *m, double *u, double *dLambda, void *workspace,
                         sch_cycle_stats *stats, void *stream);
 
+/* sch_pf_nudged_cycle_warm: the nudged filter with given start controls, for
+ * a learned warm start of the nudging stages (an extension of section 3.1.3).
+ * dLambda [n][n_steps][n_modes] holds the start controls on entry and the
+ * final particles' controls on return; mode[p] (device int32 [n]) selects
+ * how particle p's stages start:
+ *   SCH_NUDGE_KEEP       the window runs with the given controls, no L-BFGS
+ *                        steps (its log G and J follow from them)
+ *   SCH_NUDGE_FROM_GIVEN each stage's L-BFGS starts from the given control
+ *   SCH_NUDGE_FROM_ZERO  plain nudging from zero (the fallback)
+ * Everything else as sch_pf_nudged_cycle (same workspace).  Values of mode
+ * outside 0..2 are taken as FROM_ZERO. */
+#define SCH_NUDGE_KEEP 0
+#define SCH_NUDGE_FROM_GIVEN 1
+#define SCH_NUDGE_FROM_ZERO 2
+int sch_pf_nudged_cycle_warm(const sch_model *model, const sch_obs *obs, uint64_t seed,
+                             uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                             double ess_threshold, int32_t n_bisect, double rho, int32_t n_jitter,
+                             int32_t max_temper, const sch_lbfgs_opts *opts, int32_t ckpt_every,
+                             double *m, double *u, double *dLambda, const int32_t *mode,
+                             void *workspace, sch_cycle_stats *stats, void *stream);
+
 /* --------------------------------------------------------------------------
  * Gradient-based jitter: preconditioned Crank-Nicolson Langevin moves (pCNL;
  * Cotter, Roberts, Stuart & White, Statist. Sci. 2013), the function-space
@@ -719,7 +740,11 @@ int sch_batch_destroy(sch_batch *batch);
  * sch_mlp_targets: T = (dLambda - mean) / sdev as float32 (plain float32 copy
  *   when mean is NULL); dLambda is [n][cols] double.
  * sch_mlp_controls: dLambda = Y sdev + mean as double, or 0 for particles with
- *   misfit[p] > threshold (misfit may be NULL: no fallback).
+ *   misfit[p] > threshold (misfit may be NULL: no fallback); mode (device
+ *   int32 [n], or NULL) receives each particle's start mode for
+ *   sch_pf_nudged_cycle_warm: keep_mode (SCH_NUDGE_KEEP or
+ *   SCH_NUDGE_FROM_GIVEN) where the prediction is used, SCH_NUDGE_FROM_ZERO
+ *   (plain nudging) where the misfit is above the threshold.
  * ------------------------------------------------------------------------ */
 typedef struct sch_mlp {
   int32_t n_in;
@@ -749,7 +774,7 @@ int sch_mlp_targets(int32_t n, int32_t cols, const double *dLambda, const float 
                     const float *sdev, float *T, void *stream);
 int sch_mlp_controls(int32_t n, int32_t cols, const float *Y, const float *mean,
                      const float *sdev, const double *misfit, double threshold,
-                     double *dLambda, void *stream);
+                     double *dLambda, int32_t *mode, int32_t keep_mode, void *stream);
 
 /* --------------------------------------------------------------------------
  * Tuning knobs (process-global).  SCH_TUNE_THREADS forces the threads per

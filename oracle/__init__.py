@@ -217,6 +217,12 @@ def _declare(L):
                                        C.c_double, C.c_int32, C.c_int32, C.POINTER(OrcLbfgsOpts),
                                        _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                                        C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_nudged_cycle_warm": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp,
+                                            C.c_uint64, C.c_uint32, C.c_int32, C.c_int32,
+                                            C.c_double, C.c_int32, C.c_double, C.c_int32,
+                                            C.c_int32, C.POINTER(OrcLbfgsOpts), _dp, _ip, _dp,
+                                            _dp, _dp, _dp, _dp, _dp, _dp,
+                                            C.POINTER(OrcCycleStats), C.c_int32]),
         "orc_jitter_pcn_matern_ctrl": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern),
                                                  C.c_int32, _dp, _dp, C.POINTER(OrcRng),
                                                  C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp,
@@ -749,6 +755,37 @@ def nudged_cycle(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_thresho
                                 ess_threshold, n_bisect, rho, n_jitter, max_temper,
                                 C.byref(opts), _d(m), _d(u), _d(m0), _d(u0), _d(dW), _d(dLam),
                                 _d(J), C.byref(st), n_threads or n_threads_default())
+    return rc, dict(m=m, u=u, m0=m0, u0=u0, dW=dW, dLam=dLam, J=J), st
+
+
+NUDGE_KEEP, NUDGE_FROM_GIVEN, NUDGE_FROM_ZERO = 0, 1, 2
+
+
+def nudged_cycle_warm(model: Model, y, sigma, seed, cycle, m, u, dLam_start, mode, n_steps,
+                      ess_threshold, n_bisect=50, rho=0.99, n_jitter=5, max_temper=100,
+                      gtol=LBFGS_GTOL, max_iter=LBFGS_MAX_ITER, mem=LBFGS_MEM,
+                      max_back=LBFGS_MAX_BACK, n_threads=None):
+    """nudged_cycle with given start controls dLam_start [n][n_steps][Q] and a
+    per-particle start mode (NUDGE_KEEP / NUDGE_FROM_GIVEN / NUDGE_FROM_ZERO)."""
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    P = m.shape[0]
+    lam0 = _f64(dLam_start)
+    mode = np.ascontiguousarray(mode, dtype=np.int32)
+    assert lam0.shape == (P, n_steps, model.n_modes) and mode.shape == (P,)
+    m0, u0 = np.zeros_like(m), np.zeros_like(u)
+    dW = np.zeros((P, n_steps, model.n_modes))
+    dLam = np.zeros_like(dW)
+    J = np.zeros(P)
+    st = OrcCycleStats()
+    opts = OrcLbfgsOpts(gtol, max_iter, mem, max_back)
+    cm = model.c()
+    rc = lib().orc_nudged_cycle_warm(C.byref(cm), len(y), _d(y), _d(sg), seed, cycle, P, n_steps,
+                                     ess_threshold, n_bisect, rho, n_jitter, max_temper,
+                                     C.byref(opts), _d(lam0), _i(mode), _d(m), _d(u), _d(m0),
+                                     _d(u0), _d(dW), _d(dLam), _d(J), C.byref(st),
+                                     n_threads or n_threads_default())
     return rc, dict(m=m, u=u, m0=m0, u0=u0, dW=dW, dLam=dLam, J=J), st
 
 

@@ -1927,19 +1927,28 @@ int orc_nudge_particle(const orc_model *md, int32_t n_obs, const double *y, cons
                         iters_total, evals_total, worst_status);
 }
 
-static int nudge_ensemble(const orc_model *md, const orc_matern *mt, int32_t n_obs,
-                          const double *y, const double *sigma, int32_t n_particles,
-                          int32_t n_steps, double *m, double *u, const double *dW, double *dLam,
-                          const orc_lbfgs_opts *opt, double *logG, int32_t *iters, int32_t *evals,
-                          int32_t *lbfgs_status, int32_t *status, int32_t n_threads) {
+/* mode (NULL: every particle nudged from the controls in dLam) selects per
+ * particle how its stages start: ORC_NUDGE_KEEP uses the controls in dLam as
+ * they are (no L-BFGS steps), ORC_NUDGE_FROM_GIVEN runs the stages' L-BFGS
+ * from them, ORC_NUDGE_FROM_ZERO zeroes them first. */
+static int nudge_ensemble_modes(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                                const double *y, const double *sigma, int32_t n_particles,
+                                int32_t n_steps, double *m, double *u, const double *dW,
+                                double *dLam, const int32_t *mode, const orc_lbfgs_opts *opt,
+                                double *logG, int32_t *iters, int32_t *evals,
+                                int32_t *lbfgs_status, int32_t *status, int32_t n_threads) {
   int32_t nx = md->nx, nq = mt ? md->nx : md->n_modes;
   int worst = ORC_OK;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
   for (int32_t p = 0; p < n_particles; ++p) {
+    int32_t mp = mode ? mode[p] : ORC_NUDGE_FROM_GIVEN;
+    double *lam = dLam + (size_t)p * n_steps * nq;
+    orc_lbfgs_opts op = *opt;
+    if (mp == ORC_NUDGE_FROM_ZERO) memset(lam, 0, sizeof(double) * (size_t)n_steps * nq);
+    if (mp == ORC_NUDGE_KEEP) op.max_iter = 0;
     int st = nudge_particle(md, mt, n_obs, y, sigma, n_steps, m + (size_t)p * nx,
-                            u + (size_t)p * nx, dW + (size_t)p * n_steps * nq,
-                            dLam + (size_t)p * n_steps * nq, opt, logG + p,
-                            iters ? iters + p : NULL, evals ? evals + p : NULL,
+                            u + (size_t)p * nx, dW + (size_t)p * n_steps * nq, lam, &op,
+                            logG + p, iters ? iters + p : NULL, evals ? evals + p : NULL,
                             lbfgs_status ? lbfgs_status + p : NULL);
     if (status) status[p] = st;
     if (st != ORC_OK) {
@@ -1948,6 +1957,15 @@ static int nudge_ensemble(const orc_model *md, const orc_matern *mt, int32_t n_o
     }
   }
   return worst;
+}
+
+static int nudge_ensemble(const orc_model *md, const orc_matern *mt, int32_t n_obs,
+                          const double *y, const double *sigma, int32_t n_particles,
+                          int32_t n_steps, double *m, double *u, const double *dW, double *dLam,
+                          const orc_lbfgs_opts *opt, double *logG, int32_t *iters, int32_t *evals,
+                          int32_t *lbfgs_status, int32_t *status, int32_t n_threads) {
+  return nudge_ensemble_modes(md, mt, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam,
+                              NULL, opt, logG, iters, evals, lbfgs_status, status, n_threads);
 }
 
 int orc_nudge_ensemble(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
@@ -1999,7 +2017,8 @@ static int nudged_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs
                         const double *y, const double *sigma, uint64_t seed, uint32_t cycle,
                         int32_t n_particles, int32_t n_steps, double ess_threshold,
                         int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
-                        const orc_lbfgs_opts *opt, double *m, double *u, double *m0_out,
+                        const orc_lbfgs_opts *opt, const double *dLam_start,
+                        const int32_t *mode, double *m, double *u, double *m0_out,
                         double *u0_out, double *dW_out, double *dLam_out, double *J_out,
                         orc_cycle_stats *st, int32_t n_threads) {
   int32_t nx = md->nx, nq = mt ? md->nx : md->n_modes;
@@ -2016,8 +2035,9 @@ static int nudged_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs
 
   orc_draw_increments(seed, n_particles, n_steps, nq, cycle * (uint32_t)n_steps, ORC_TAG_NUDGE,
                       0u, md->dt, dW);
-  nudge_ensemble(md, mt, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam, opt, logG, NULL,
-                 NULL, NULL, stat, n_threads);
+  if (dLam_start) memcpy(dLam, dLam_start, sizeof(double) * wlen);
+  nudge_ensemble_modes(md, mt, n_obs, y, sigma, n_particles, n_steps, m, u, dW, dLam,
+                       dLam_start ? mode : NULL, opt, logG, NULL, NULL, NULL, stat, n_threads);
   for (int32_t p = 0; p < n_particles; ++p) {
     double phi = stat[p] == ORC_OK ? orc_nll(nx, n_obs, u + (size_t)p * nx, y, sigma) : INFINITY;
     J[p] = (isfinite(phi) && isfinite(logG[p])) ? phi - logG[p] : INFINITY;
@@ -2052,8 +2072,23 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
                      double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
                      double *J_out, orc_cycle_stats *st, int32_t n_threads) {
   return nudged_cycle(md, NULL, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
-                      n_bisect, rho, n_jitter, max_temper, opt, m, u, m0_out, u0_out, dW_out,
-                      dLam_out, J_out, st, n_threads);
+                      n_bisect, rho, n_jitter, max_temper, opt, NULL, NULL, m, u, m0_out, u0_out,
+                      dW_out, dLam_out, J_out, st, n_threads);
+}
+
+int orc_nudged_cycle_warm(const orc_model *md, int32_t n_obs, const double *y,
+                          const double *sigma, uint64_t seed, uint32_t cycle, int32_t n_particles,
+                          int32_t n_steps, double ess_threshold, int32_t n_bisect, double rho,
+                          int32_t n_jitter, int32_t max_temper, const orc_lbfgs_opts *opt,
+                          const double *dLam_start, const int32_t *mode, double *m, double *u,
+                          double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
+                          double *J_out, orc_cycle_stats *st, int32_t n_threads) {
+  if (!dLam_start || !mode) return ORC_E_ARG;
+  for (int32_t p = 0; p < n_particles; ++p)
+    if (mode[p] < ORC_NUDGE_KEEP || mode[p] > ORC_NUDGE_FROM_ZERO) return ORC_E_ARG;
+  return nudged_cycle(md, NULL, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
+                      n_bisect, rho, n_jitter, max_temper, opt, dLam_start, mode, m, u, m0_out,
+                      u0_out, dW_out, dLam_out, J_out, st, n_threads);
 }
 
 /* orc_nudged_cycle with the Matern-type noise: the NUDGE-tag draws, the
@@ -2067,8 +2102,8 @@ int orc_nudged_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t n
                             double *u0_out, double *dW_out, double *dLam_out, double *J_out,
                             orc_cycle_stats *st, int32_t n_threads) {
   return nudged_cycle(md, mt, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
-                      n_bisect, rho, n_jitter, max_temper, opt, m, u, m0_out, u0_out, dW_out,
-                      dLam_out, J_out, st, n_threads);
+                      n_bisect, rho, n_jitter, max_temper, opt, NULL, NULL, m, u, m0_out, u0_out,
+                      dW_out, dLam_out, J_out, st, n_threads);
 }
 
 /* ========================================================================== */

@@ -240,6 +240,21 @@ int orc_nudged_cycle(const orc_model *md, int32_t n_obs, const double *y, const 
                      double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
                      double *J_out, orc_cycle_stats *st, int32_t n_threads);
 
+/* The nudged filter with given start controls (the learned warm start of the
+ * nudging stages): dLam_start [n][n_steps][n_modes] and, per particle,
+ * mode[p] = ORC_NUDGE_KEEP (the window runs with the given controls, no
+ * L-BFGS steps), ORC_NUDGE_FROM_GIVEN (the stages' L-BFGS starts from them)
+ * or ORC_NUDGE_FROM_ZERO (plain nudging from zero, the fallback).  Otherwise
+ * orc_nudged_cycle (which is this call with every particle FROM_ZERO). */
+enum { ORC_NUDGE_KEEP = 0, ORC_NUDGE_FROM_GIVEN = 1, ORC_NUDGE_FROM_ZERO = 2 };
+int orc_nudged_cycle_warm(const orc_model *md, int32_t n_obs, const double *y,
+                          const double *sigma, uint64_t seed, uint32_t cycle, int32_t n_particles,
+                          int32_t n_steps, double ess_threshold, int32_t n_bisect, double rho,
+                          int32_t n_jitter, int32_t max_temper, const orc_lbfgs_opts *opt,
+                          const double *dLam_start, const int32_t *mode, double *m, double *u,
+                          double *m0_out, double *u0_out, double *dW_out, double *dLam_out,
+                          double *J_out, orc_cycle_stats *st, int32_t n_threads);
+
 /* ---- nudging with the Matern-type noise (controls per cell) ---- */
 int orc_matern_transpose(int32_t nx, double L, const orc_matern *mt, const double *g,
                          double *out);

@@ -790,11 +790,14 @@ namespace {
 // The stage-wise nudging of section 3.1.3 with the modes-form noise
 // (M == null: n_modes controls per step) or the Matern-type noise (M != null:
 // one control per cell, nx per step).
+// mode (null: all particles warm or cold by warm_start) gives each
+// particle's start: SCH_NUDGE_KEEP, _FROM_GIVEN or _FROM_ZERO, the given
+// controls being in dLam.
 int nudge_run(const sch_model* md, const Tile& tl, const sch_obs* ob, int32_t n, int32_t n_steps,
               double* m, double* u, const double* dW, double* dLam, int32_t warm_start,
               const sch_lbfgs_opts* opts, int32_t ce, double* logG, int32_t* lbfgs_status,
               int32_t* iters, int32_t* evals, int32_t* status, void* workspace, void* stream,
-              const MaternDev* M) {
+              const MaternDev* M, const int32_t* mode = nullptr) {
   if (!(opts->gtol >= 0) || opts->max_iter < 0 || opts->mem < 1 ||
       opts->mem > kLbfgsMaxMem || opts->max_back < 0 || opts->max_back > 60)
     return fail(SCH_E_ARG, "bad L-BFGS settings");
@@ -815,7 +818,8 @@ int nudge_run(const sch_model* md, const Tile& tl, const sch_obs* ob, int32_t n,
   const int64_t max_ev = 1 + static_cast<int64_t>(opts->max_iter) * (opts->max_back + 1);
   for (int s = 0; s < n_steps; ++s) {
     hipLaunchKernelGGL(k_lbfgs_init, dim3(gb), dim3(256), 0, st, W.lb, LP,
-                       warm_start ? dLam + static_cast<size_t>(s) * Q : nullptr, n_steps * Q);
+                       (warm_start || mode) ? dLam + static_cast<size_t>(s) * Q : nullptr,
+                       n_steps * Q, mode);
     CHECK_LAUNCH();
     bool done = false;
     for (int64_t ev = 0; ev <= max_ev && !done; ++ev) {
@@ -1040,11 +1044,14 @@ size_t nudged_bytes(const sch_model& md, int n, int n_steps, int n_jitter, int c
 // tempering and jittering of section 3.1.2) with the modes-form noise
 // (M == null) or the Matern-type noise (M != null: cells and controls per
 // cell).
+// mode == null: plain nudging from zero controls; otherwise dLambda holds the
+// start controls and mode[p] each particle's start (nudge_run).
 int nudged_cycle(const sch_model* md, const Tile& tl, const sch_obs* ob, uint64_t seed,
                  uint32_t cycle, int32_t n, int32_t n_steps, double thr, int32_t n_bisect,
                  double rho, int32_t n_jitter, int32_t max_temper, const sch_lbfgs_opts* opts,
                  int32_t ckpt_every, double* m, double* u, double* dLambda, void* workspace,
-                 sch_cycle_stats* stats, void* stream, const MaternDev* M) {
+                 sch_cycle_stats* stats, void* stream, const MaternDev* M,
+                 const int32_t* mode = nullptr) {
   hipStream_t st = S(stream);
   const int nx = md->nx, Q = M ? md->nx : md->n_modes;
   const size_t state = static_cast<size_t>(n) * nx, inc = static_cast<size_t>(n) * n_steps * Q;
@@ -1057,8 +1064,9 @@ int nudged_cycle(const sch_model* md, const Tile& tl, const sch_obs* ob, uint64_
   *stats = sch_cycle_stats{};
   sch_rng rg{seed, cycle, 0};
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(static_cast<int64_t>(inc), 256)), dim3(256), 0, st,
-                     dLambda, 0.0, static_cast<int64_t>(inc));
+  if (!mode)
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(static_cast<int64_t>(inc), 256)), dim3(256), 0, st,
+                       dLambda, 0.0, static_cast<int64_t>(inc));
   CHECK_LAUNCH();
   {
     TimedScope ts(SCH_TK_GATHER, st);
@@ -1070,10 +1078,10 @@ int nudged_cycle(const sch_model* md, const Tile& tl, const sch_obs* ob, uint64_
     if (int rc = sch_draw_increments(&rg, SCH_TAG_NUDGE, n, n_steps, Q, md->dt, W.dW, stream))
       return rc;
   }
-  // sequential nudging of the window from zero controls: (m, u) become the
-  // nudged window ends, W.status the window statuses
+  // sequential nudging of the window (from zero controls, or as mode says):
+  // (m, u) become the nudged window ends, W.status the window statuses
   if (int rc = nudge_run(md, tl, ob, n, n_steps, m, u, W.dW, dLambda, 0, opts, ckpt_every, logG,
-                         nullptr, nullptr, nullptr, W.status, nws, stream, M))
+                         nullptr, nullptr, nullptr, W.status, nws, stream, M, mode))
     return rc;
   {
     TimedScope ts(SCH_TK_OTHER, st);
@@ -1111,6 +1119,24 @@ int sch_pf_nudged_cycle(const sch_model* md, const sch_obs* ob, uint64_t seed, u
   return nudged_cycle(md, tl, ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
                       max_temper, opts, ckpt_every, m, u, dLambda, workspace, stats, stream,
                       nullptr);
+}
+
+int sch_pf_nudged_cycle_warm(const sch_model* md, const sch_obs* ob, uint64_t seed,
+                             uint32_t cycle, int32_t n, int32_t n_steps, double thr,
+                             int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                             const sch_lbfgs_opts* opts, int32_t ckpt_every, double* m, double* u,
+                             double* dLambda, const int32_t* mode, void* workspace,
+                             sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !dLambda || !mode || !workspace ||
+      !stats || !opts || n_bisect < 0 || max_temper < 1 || !(rho >= 0 && rho <= 1) ||
+      n_jitter < 0 || ckpt_every < 1)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_nudged_cycle_warm");
+  return nudged_cycle(md, tl, ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                      max_temper, opts, ckpt_every, m, u, dLambda, workspace, stats, stream,
+                      nullptr, mode);
 }
 
 // ---------------------------------------------------------------------------

@@ -490,11 +490,20 @@ __device__ void lbfgs_direction(const LbfgsState& s, const LbfgsParams& P, int i
 }
 
 // Initial state: x = x0 (a [n][stride] array read at offset 0, or zero).
-__global__ void k_lbfgs_init(LbfgsState s, LbfgsParams P, const double* x0, int x0_stride) {
+// Start of a stage's L-BFGS.  mode (null: every particle starts from x0, or
+// from zero without x0) selects per particle: kNudgeKeep takes x0 as the
+// stage's control without any step (the particle is inactive from the
+// start), kNudgeFromGiven starts the iteration at x0, kNudgeFromZero at 0.
+constexpr int kNudgeKeep = 0, kNudgeFromGiven = 1, kNudgeFromZero = 2;
+__global__ void k_lbfgs_init(LbfgsState s, LbfgsParams P, const double* x0, int x0_stride,
+                             const int* mode = nullptr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P.n) return;
+  int md = mode ? mode[i] : (x0 ? kNudgeFromGiven : kNudgeFromZero);
+  if (md != kNudgeKeep && md != kNudgeFromGiven) md = kNudgeFromZero;
+  const bool given = x0 && md != kNudgeFromZero;
   for (int q = 0; q < P.Q; ++q) {
-    const double v = x0 ? x0[static_cast<size_t>(i) * x0_stride + q] : 0.0;
+    const double v = given ? x0[static_cast<size_t>(i) * x0_stride + q] : 0.0;
     s.x[static_cast<size_t>(i) * P.Q + q] = v;
     s.xt[static_cast<size_t>(i) * P.Q + q] = v;
   }
@@ -503,8 +512,8 @@ __global__ void k_lbfgs_init(LbfgsState s, LbfgsParams P, const double* x0, int 
   s.k[i] = 0;
   s.nback[i] = 0;
   s.phase[i] = 0;
-  s.lstat[i] = 1;
-  s.active[i] = 1;
+  s.lstat[i] = md == kNudgeKeep ? 0 : 1;
+  s.active[i] = md == kNudgeKeep ? 0 : 1;
   s.evals[i] = 0;
 }
 

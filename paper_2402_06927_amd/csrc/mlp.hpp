@@ -336,15 +336,19 @@ __global__ void k_mlp_targets(int64_t n, int cols, const double* dLam, const flo
 
 // Warm start from the network output: dLambda = Y sdev + mean, or zero (the
 // plain start) for particles whose misfit norm exceeds the threshold.
+// mode (optional): per particle, keep_mode where the prediction is used and
+// fallback_mode where the misfit is above the threshold (the start modes of
+// sch_pf_nudged_cycle_warm).
 __global__ void k_mlp_controls(int64_t n, int cols, const float* Y, const float* mean,
                                const float* sdev, const double* misfit, double threshold,
-                               double* dLam) {
+                               double* dLam, int* mode, int keep_mode, int fallback_mode) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int c = static_cast<int>(i % cols);
     const int64_t p = i / cols;
     const bool plain = misfit && !(misfit[p] <= threshold);
     dLam[i] = plain ? 0.0 : static_cast<double>(Y[i] * sdev[c] + mean[c]);
+    if (mode && c == 0) mode[p] = plain ? fallback_mode : keep_mode;
   }
 }
 

@@ -242,12 +242,14 @@ int sch_mlp_targets(int32_t n, int32_t cols, const double* dLam, const float* me
 
 int sch_mlp_controls(int32_t n, int32_t cols, const float* Y, const float* mean,
                      const float* sdev, const double* misfit, double threshold, double* dLam,
-                     void* stream) {
-  if (n < 1 || cols < 1 || !Y || !mean || !sdev || !dLam)
+                     int32_t* mode, int32_t keep_mode, void* stream) {
+  if (n < 1 || cols < 1 || !Y || !mean || !sdev || !dLam ||
+      (mode && keep_mode != SCH_NUDGE_KEEP && keep_mode != SCH_NUDGE_FROM_GIVEN))
     return fail(SCH_E_ARG, "bad arguments to sch_mlp_controls");
   const int64_t total = static_cast<int64_t>(n) * cols;
   hipLaunchKernelGGL(k_mlp_controls, dim3(grid_for(total, 256)), dim3(256), 0, S(stream), total,
-                     cols, Y, mean, sdev, misfit, threshold, dLam);
+                     cols, Y, mean, sdev, misfit, threshold, dLam, mode, keep_mode,
+                     SCH_NUDGE_FROM_ZERO);
   CHECK_LAUNCH();
   return SCH_OK;
 }

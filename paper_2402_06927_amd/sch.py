@@ -137,6 +137,9 @@ def _declare(L):
         "sch_pf_nudged_cycle": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
                                           C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp, _vp, ST,
                                           _vp]),
+        "sch_pf_nudged_cycle_warm": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32,
+                                               i32, C.POINTER(SchLbfgsOpts), i32, _vp, _vp, _vp,
+                                               _vp, _vp, ST, _vp]),
         "sch_nudge_grad": (C.c_int, [M, O, i32, i32, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp,
                                      _vp, _vp]),
         "sch_nudge_run": (C.c_int, [M, O, i32, i32, _vp, _vp, _vp, _vp, i32,
@@ -161,7 +164,7 @@ def _declare(L):
         "sch_mlp_colstats": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp]),
         "sch_mlp_encode": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
         "sch_mlp_targets": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
-        "sch_mlp_controls": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, f64, _vp, _vp]),
+        "sch_mlp_controls": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, f64, _vp, _vp, i32, _vp]),
         "sch_tune_set": (C.c_int, [i32, i32]),
         "sch_tune_get": (C.c_int, [i32]),
         "sch_timing_enable": (C.c_int, [C.c_int]),
@@ -215,6 +218,7 @@ def exported_names():
         "sch_mlp_forward", "sch_mlp_backward", "sch_mlp_adam", "sch_mlp_features",
         "sch_mlp_colstats", "sch_mlp_encode", "sch_mlp_targets", "sch_mlp_controls",
         "sch_pf_tempered_cycle", "sch_nudged_workspace_bytes", "sch_pf_nudged_cycle",
+        "sch_pf_nudged_cycle_warm",
         "sch_tune_set", "sch_tune_get", "sch_timing_enable", "sch_timing_reset",
         "sch_timing_read", "sch_matern_field", "sch_ensemble_step_matern",
         "sch_matern_workspace_bytes", "sch_jitter_pcn_matern", "sch_pf_tempered_cycle_matern",
@@ -893,6 +897,36 @@ def nudged_workspace_matern(model: Model, n_particles: int, n_steps: int, n_jitt
                        dtype=torch.uint8, device=device)
 
 
+NUDGE_KEEP, NUDGE_FROM_GIVEN, NUDGE_FROM_ZERO = 0, 1, 2
+
+
+def sch_pf_nudged_cycle_warm(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
+                             u: torch.Tensor, dLambda: torch.Tensor, mode: torch.Tensor,
+                             n_steps: int, ess_threshold: float, n_bisect: int, rho: float,
+                             n_jitter: int, max_temper: int, workspace: torch.Tensor,
+                             gtol: float = LBFGS_GTOL, max_iter: int = LBFGS_MAX_ITER,
+                             mem: int = LBFGS_MEM, max_back: int = LBFGS_MAX_BACK,
+                             ckpt_every: int = 8) -> dict:
+    """The nudged filter from given start controls dLambda (in/out) with a
+    per-particle start mode (NUDGE_KEEP, NUDGE_FROM_GIVEN, NUDGE_FROM_ZERO)."""
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _inc(n, n_steps, model.n_modes, dLambda=dLambda)
+    _vec(n, mode=mode)
+    _ws(workspace, nudged_workspace_bytes(model, n, n_steps, n_jitter, ckpt_every))
+    mc, oc = model.c(), obs.c()
+    st = SchCycleStats()
+    opts = SchLbfgsOpts(gtol, max_iter, mem, max_back)
+    _check(lib().sch_pf_nudged_cycle_warm(C.byref(mc), C.byref(oc), seed, cycle, n, n_steps,
+                                          ess_threshold, n_bisect, rho, n_jitter, max_temper,
+                                          C.byref(opts), ckpt_every, _dev(m, name="m"),
+                                          _dev(u, name="u"), _dev(dLambda, name="dLambda"),
+                                          _dev(mode, torch.int32, "mode"),
+                                          _dev(workspace, torch.uint8, "workspace"), C.byref(st),
+                                          _stream()))
+    return st.as_dict()
+
+
 def nudged_workspace_bytes_matern(model: Model, n_particles: int, n_steps: int, n_jitter: int,
                                   ckpt_every: int = 8) -> int:
     mc = model.c()
@@ -1105,14 +1139,18 @@ def sch_mlp_targets(dLam: torch.Tensor, mean: torch.Tensor | None, sdev: torch.T
 
 
 def sch_mlp_controls(Y: torch.Tensor, mean: torch.Tensor, sdev: torch.Tensor,
-                     misfit: torch.Tensor | None, threshold: float, dLam: torch.Tensor):
+                     misfit: torch.Tensor | None, threshold: float, dLam: torch.Tensor,
+                     mode: torch.Tensor | None = None, keep_mode: int = 0):
     n = Y.shape[0]
     cols = Y.numel() // n
+    _at_least(dLam, n * cols, "dLambda")
+    _vec(n, misfit=misfit, mode=mode)
     _check(lib().sch_mlp_controls(n, cols, _dev(Y, torch.float32, "Y"),
                                   _dev(mean, torch.float32, "mean"),
                                   _dev(sdev, torch.float32, "sdev"),
                                   _dev(misfit, name="misfit"), threshold,
-                                  _dev(dLam, name="dLambda"), _stream()))
+                                  _dev(dLam, name="dLambda"), _dev(mode, torch.int32, "mode"),
+                                  keep_mode, _stream()))
 
 
 TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other", "nudge")

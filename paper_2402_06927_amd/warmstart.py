@@ -119,9 +119,13 @@ class WarmStart:
 
     # ----------------------------------------------------------------- inference
     def predict(self, model: sch.Model, obs: sch.Obs, u: torch.Tensor, dLam: torch.Tensor,
-                fallback: bool = True) -> torch.Tensor:
+                fallback: bool = True, mode: torch.Tensor | None = None,
+                keep_mode: int = sch.NUDGE_KEEP) -> torch.Tensor:
         """Warm-start controls for the particles u into dLam [n][S][Q]; returns
-        the misfit norms."""
+        the misfit norms.  mode (int32 [n], optional) receives the start mode
+        of every particle for sch_pf_nudged_cycle_warm: keep_mode where the
+        prediction is used, NUDGE_FROM_ZERO (plain nudging) where the misfit is
+        above the training range."""
         n = u.shape[0]
         X = torch.empty((n, self.F), dtype=torch.bfloat16, device=self.device)
         mis = torch.empty(n, dtype=torch.float64, device=self.device)
@@ -131,8 +135,24 @@ class WarmStart:
                          device=self.device)
         sch.sch_mlp_forward(self.net, X, Y, ws)
         sch.sch_mlp_controls(Y, self.y_mean, self.y_sdev, mis if fallback else None,
-                             self.threshold, dLam)
+                             self.threshold, dLam, mode, keep_mode)
         return mis
+
+    def nudged_cycle(self, model: sch.Model, obs: sch.Obs, seed: int, cycle: int,
+                     m: torch.Tensor, u: torch.Tensor, dLam: torch.Tensor, n_steps: int,
+                     ess_threshold: float, n_bisect: int, rho: float, n_jitter: int,
+                     max_temper: int, workspace: torch.Tensor, keep_mode: int = sch.NUDGE_KEEP,
+                     **lbfgs) -> dict:
+        """One cycle of the nudged filter with the network's controls: every
+        particle whose misfit lies in the training range takes the predicted
+        controls (as they are with NUDGE_KEEP, as the L-BFGS start with
+        NUDGE_FROM_GIVEN), the others are nudged from zero; then tempering and
+        jittering with the weights W~ as in sch_pf_nudged_cycle."""
+        mode = torch.empty(u.shape[0], dtype=torch.int32, device=self.device)
+        self.predict(model, obs, u, dLam, True, mode, keep_mode)
+        return sch.sch_pf_nudged_cycle_warm(model, obs, seed, cycle, m, u, dLam, mode, n_steps,
+                                            ess_threshold, n_bisect, rho, n_jitter, max_temper,
+                                            workspace, **lbfgs)
 
 
 def concat(parts: list[Dataset]) -> Dataset:

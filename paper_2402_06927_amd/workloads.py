@@ -115,8 +115,15 @@ MATERN_4096 = replace(TEMPERED_4096, name="tempered_matern_nx4096_np1024", noise
 # and step (2048 per step and particle instead of 8).
 NUDGING_MATERN_2048 = replace(NUDGING_2048, name="nudging_matern_nx2048_np2048", noise="matern")
 
+# The learned warm start of nudging: the tempered workload's physics and
+# observations (nx = 4096, 8 modes, 40 steps, 256 observations, sigma 0.02)
+# with 4096 particles; the network is trained on plain-nudging solutions of
+# consecutive windows (25 windows = 102400 pairs).
+WARMSTART_4096 = replace(NUDGING_2048, name="warmstart_nx4096_np4096", nx=4096,
+                         n_particles=4096)
+
 WORKLOADS = {w.name: w for w in (BOOTSTRAP_256, TEMPERED_4096, NUDGING_2048, PAPER_SHAPE,
-                                 PAPER_HALF, MATERN_4096, NUDGING_MATERN_2048)}
+                                 PAPER_HALF, MATERN_4096, NUDGING_MATERN_2048, WARMSTART_4096)}
 
 
 def node_positions(L: float, nx: int) -> np.ndarray:

@@ -200,7 +200,10 @@ def test_features_scaling_and_controls(sch):
     ys = torch.linspace(0.5, 2, Oo, dtype=torch.float32, device="cuda")
     dl = torch.empty((n, wl.n_steps, wl.n_modes), dtype=torch.float64, device="cuda")
     thr = float(np.median(N(mis)))
-    S.sch_mlp_controls(Y, ym, ys, mis, thr, dl)
+    mode = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    S.sch_mlp_controls(Y, ym, ys, mis, thr, dl, mode, S.NUDGE_FROM_GIVEN)
     expect = N(Y) * N(ys) + N(ym)
     expect[N(mis) > thr] = 0.0
     np.testing.assert_allclose(N(dl).reshape(n, Oo), expect, rtol=1e-6, atol=1e-7)
+    np.testing.assert_array_equal(
+        N(mode), np.where(N(mis) > thr, S.NUDGE_FROM_ZERO, S.NUDGE_FROM_GIVEN))

@@ -148,9 +148,70 @@ def test_nudged_cycle_argument_errors(sch):
     obs = sch.Obs(T(y), T(np.full(wl.n_obs, 0.05)))
     with pytest.raises(sch.SchError) as e:
         sch.sch_pf_nudged_cycle(gm, obs, wl.seed, 0, T(m0), T(u0), None, 3, 2.0, 50, 0.9, 2, 50,
-                                ws)
+                                ws, ckpt_every=4)
     assert e.value.code == sch.SCH_E_ARG
+    with pytest.raises(sch.SchError) as e:  # sized for checkpoints every 4 steps, not 8
+        sch.sch_pf_nudged_cycle(gm, obs, wl.seed, 0, T(m0), T(u0),
+                                torch.zeros((4, 3, 4), dtype=torch.float64, device="cuda"), 3,
+                                2.0, 50, 0.9, 2, 50, ws, ckpt_every=8)
+    assert e.value.code == sch.SCH_E_SHAPE
     with pytest.raises(sch.SchError):
         sch.sch_pf_nudged_cycle(gm, obs, wl.seed, 0, T(m0), T(u0),
                                 torch.zeros((4, 3, 4), dtype=torch.float64, device="cuda"), 3,
                                 2.0, 50, 0.9, 2, 50, ws, ckpt_every=0)
+
+
+def _gpu_cycle_warm(sch, wl, m0, u0, y, sigma, lam0, mode, n_jitter=3):
+    gm = PR.gpu_model(wl)
+    n, s = wl.n_particles, wl.n_steps
+    m, u, dl = T(m0), T(u0), T(lam0)
+    ws = sch.nudged_workspace(gm, n, s, n_jitter, 4)
+    obs = sch.Obs(T(y), T(np.full(wl.n_obs, sigma)))
+    st = sch.sch_pf_nudged_cycle_warm(gm, obs, wl.seed, 0, m, u, dl, T(mode, torch.int32), s,
+                                      n / 2, 50, 0.9, n_jitter, 50, ws, ckpt_every=4)
+    return st, N(m), N(u), N(dl)
+
+
+def test_warm_cycle_keep_matches_at_the_tight_bar(sch):
+    """Every particle KEEP: no optimiser runs on either side, so the nudged
+    forecast is a deterministic window with increments plus the given controls
+    and the whole cycle (tempering steps, acceptances, states) matches at the
+    1e-10 bar; the final controls are rows of the given ones."""
+    wl = W.NUDGING_2048.scaled(nx=130, n_particles=12, n_modes=8, n_steps=5, n_obs=16,
+                               sigma_obs=0.05)
+    m0, u0, y = _cycle_inputs(wl)
+    om = PR.oracle_model(wl)
+    lam0 = 0.02 * W.random_state_noise((wl.n_particles, wl.n_steps, wl.n_modes), 6)
+    mode = np.full(wl.n_particles, sch.NUDGE_KEEP, dtype=np.int32)
+    rc, ref, st_o = O.nudged_cycle_warm(om, y, wl.sigma_obs, wl.seed, 0, m0, u0, lam0, mode,
+                                        wl.n_steps, wl.n_particles / 2, 50, 0.9, 3, 50)
+    assert rc == 0
+    st, m, u, dl = _gpu_cycle_warm(sch, wl, m0, u0, y, wl.sigma_obs, lam0, mode)
+    assert st["status"] == 0
+    assert st["n_temper"] == st_o.n_temper and st["n_accept"] == st_o.n_accept
+    np.testing.assert_array_equal(dl, ref["dLam"])
+    assert PR.rel_l2(m, ref["m"]) < PR.REL_TOL and PR.rel_l2(u, ref["u"]) < PR.REL_TOL
+
+
+@pytest.mark.parametrize("nx,n,q,s", [(64, 16, 4, 6), (130, 10, 8, 5)])
+def test_warm_cycle_mixed_modes_parity(sch, nx, n, q, s):
+    """A third of the particles KEEP their given controls, a third start
+    their L-BFGS from them, a third nudge from zero (the fallback); bars of
+    the plain nudged cycle."""
+    _say("warm nudged cycle", nx, n, q, s)
+    wl = W.NUDGING_2048.scaled(nx=nx, n_particles=n, n_modes=q, n_steps=s, n_obs=min(nx, 16),
+                               sigma_obs=0.05)
+    m0, u0, y = _cycle_inputs(wl)
+    om = PR.oracle_model(wl)
+    lam0 = 0.02 * W.random_state_noise((n, s, q), 7)
+    mode = (np.arange(n) % 3).astype(np.int32)
+    rc, ref, st_o = O.nudged_cycle_warm(om, y, wl.sigma_obs, wl.seed, 0, m0, u0, lam0, mode, s,
+                                        n / 2, 50, 0.9, 3, 50)
+    assert rc == 0
+    st, m, u, dl = _gpu_cycle_warm(sch, wl, m0, u0, y, wl.sigma_obs, lam0, mode)
+    assert st["status"] == 0
+    _say("n_temper", st["n_temper"], st_o.n_temper, "accept", st["n_accept"], st_o.n_accept)
+    assert st["n_temper"] == st_o.n_temper
+    scale = np.abs(ref["dLam"]).max()
+    np.testing.assert_allclose(dl, ref["dLam"], rtol=0, atol=1e-6 * scale)
+    assert PR.rel_l2(m, ref["m"]) < 1e-6 and PR.rel_l2(u, ref["u"]) < 1e-6

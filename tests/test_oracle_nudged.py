@@ -143,3 +143,76 @@ def test_nudged_cycle_without_data_keeps_zero_control(orc):
     assert np.abs(out["dLam"]).max() < 1e-12
     assert st.n_temper == 1
     assert np.abs(out["J"]).max() < 1e-6
+
+
+# ----------------------------------------------------------------------------- warm start
+def _warm(orc, wl, om, m, u, y, lam0, mode, **kw):
+    return orc.nudged_cycle_warm(om, y, wl.sigma_obs, wl.seed, 0, m, u, lam0, mode, wl.n_steps,
+                                 ess_threshold=wl.n_particles / 2, n_bisect=50, rho=0.9,
+                                 n_jitter=kw.get("n_jitter", 3), max_temper=50, n_threads=4)
+
+
+def test_warm_cycle_from_zero_is_the_plain_cycle(orc):
+    """Every particle FROM_ZERO discards the given controls: the cycle is the
+    plain nudged cycle bit for bit."""
+    wl = SMALL
+    om, m, u, y = _ensemble_and_obs(orc, wl, wl.sigma_obs)
+    lam0 = 0.3 * W.random_state_noise((wl.n_particles, wl.n_steps, wl.n_modes), 4)
+    mode = np.full(wl.n_particles, orc.NUDGE_FROM_ZERO)
+    rc, out, st = _warm(orc, wl, om, m, u, y, lam0, mode)
+    rc2, ref, st2 = orc.nudged_cycle(om, y, wl.sigma_obs, wl.seed, 0, m, u, wl.n_steps,
+                                     ess_threshold=wl.n_particles / 2, n_bisect=50, rho=0.9,
+                                     n_jitter=3, max_temper=50, n_threads=4)
+    assert rc == rc2 == 0 and st.n_temper == st2.n_temper and st.n_accept == st2.n_accept
+    for k in ("m", "u", "dW", "dLam", "J"):
+        np.testing.assert_array_equal(out[k], ref[k])
+
+
+def test_warm_cycle_keep_runs_the_given_controls(orc):
+    """KEEP: no optimisation; each final particle carries the given controls
+    of its resampled parent, and its end state and potential are those of the
+    window driven by increments plus those controls."""
+    wl = SMALL
+    om, m, u, y = _ensemble_and_obs(orc, wl, wl.sigma_obs)
+    lam0 = 0.02 * W.random_state_noise((wl.n_particles, wl.n_steps, wl.n_modes), 5)
+    mode = np.full(wl.n_particles, orc.NUDGE_KEEP)
+    rc, out, st = _warm(orc, wl, om, m, u, y, lam0, mode)
+    assert rc == 0 and st.n_temper >= 1
+    for p in range(wl.n_particles):
+        q = [k for k in range(wl.n_particles) if np.array_equal(out["m0"][p], m[k])]
+        assert len(q) == 1 and np.array_equal(out["dLam"][p], lam0[q[0]])
+        s, me, ue, _ = orc.window(om, out["m0"][p], out["u0"][p], out["dW"][p], out["dLam"][p])
+        assert s == 0
+        np.testing.assert_array_equal(me, out["m"][p])
+        J = orc.nudged_potential(orc.nll(ue, y, wl.sigma_obs), wl.dt, out["dW"][p],
+                                 out["dLam"][p])
+        assert out["J"][p] == pytest.approx(J, rel=1e-13, abs=1e-13)
+
+
+def test_warm_cycle_from_the_optimum_keeps_it(orc):
+    """FROM_GIVEN started at plain nudging's own stage optima (the same
+    revealed increments) stops at once: the controls and the potentials of the
+    nudged forecast are plain nudging's, and the cycle is the plain one."""
+    wl = SMALL
+    om, m, u, y = _ensemble_and_obs(orc, wl, wl.sigma_obs)
+    dW = orc.draw_increments(wl.seed, wl.n_particles, wl.n_steps, wl.n_modes, 0, orc.TAG_NUDGE,
+                             0, wl.dt)
+    opt = orc.nudge_ensemble(om, y, wl.sigma_obs, m, u, dW, n_threads=4)
+    assert opt["worst"] == 0
+    mode = np.full(wl.n_particles, orc.NUDGE_FROM_GIVEN)
+    rc, out, st = _warm(orc, wl, om, m, u, y, opt["dLam"], mode)
+    rc2, ref, st2 = orc.nudged_cycle(om, y, wl.sigma_obs, wl.seed, 0, m, u, wl.n_steps,
+                                     ess_threshold=wl.n_particles / 2, n_bisect=50, rho=0.9,
+                                     n_jitter=3, max_temper=50, n_threads=4)
+    assert rc == rc2 == 0 and st.n_temper == st2.n_temper
+    scale = np.abs(ref["dLam"]).max()
+    assert np.abs(out["dLam"] - ref["dLam"]).max() <= 1e-6 * scale
+    np.testing.assert_allclose(out["J"], ref["J"], rtol=1e-8)
+
+
+def test_warm_cycle_rejects_bad_modes(orc):
+    wl = SMALL
+    om, m, u, y = _ensemble_and_obs(orc, wl, wl.sigma_obs)
+    lam0 = np.zeros((wl.n_particles, wl.n_steps, wl.n_modes))
+    rc, _, _ = _warm(orc, wl, om, m, u, y, lam0, np.full(wl.n_particles, 3))
+    assert rc == orc.ORC_E_ARG
