@@ -523,7 +523,11 @@ template <int PMAX, bool FULL>
 __device__ __forceinline__ void cell_normals(uint64_t seed, uint32_t c0, uint32_t c1,
                                              uint32_t tag, uint32_t c3, const Chunk& ch,
                                              double (&z)[PMAX]) {
-  const int s0 = ch.start;
+  // the thread's first cell, laundered per call: otherwise the generator's
+  // per-thread first-round products, the same for every step, are hoisted
+  // out of the callers' step loops and held (in spill slots) across them
+  int s0 = ch.start;
+  asm volatile("" : "+v"(s0));
   if (!FULL && (s0 & 1)) {
     double za, zb;
     normal2(seed, c0, c1, static_cast<uint32_t>(s0 >> 1) | tag, c3, za, zb);
@@ -706,14 +710,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   }
   if constexpr (MATERN) {
     // the accepted increments sit in the stage row after an odd number of
-    // swaps: each thread copies its own cells back
-    if (cur != dWp)
-      for (int n = 0; n < S; ++n) {
-        const size_t off = static_cast<size_t>(n) * nx + ch.start;
-#pragma unroll
-        for (int jj = 0; jj < PMAX; ++jj)
-          if (FULL || jj < ch.cnt) dWp[off + jj] = cur[off + jj];
-      }
+    // swaps: the workgroup copies the row back, consecutive threads on
+    // consecutive values (the last move's barrier has made every thread's
+    // proposal stores visible)
+    if (cur != dWp) {
+      const size_t len = static_cast<size_t>(S) * nx;
+      for (size_t i = t; i < len; i += NT) dWp[i] = cur[i];
+    }
   } else {
     if (acc > 0)
       for (int i = t; i < S * Q; i += NT) dWp[i] = cur[i];
