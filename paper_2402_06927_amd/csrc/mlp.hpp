@@ -177,26 +177,64 @@ __global__ void k_mse(int64_t n, const float* Y, const float* T, float inv_count
     dY16[i] = f2bf(d);
     acc += static_cast<double>(r) * r;
   }
+  // one atomic per workgroup (blockDim.x = 256): per-wavefront atomics on the
+  // one address serialise
+  __shared__ double part[4];
   acc = wave_sum(acc);
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(loss, acc * inv_count);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, ((part[0] + part[1]) + (part[2] + part[3])) * inv_count);
 }
 
-// out[c] = sum_r A[r][c]: 256 threads per 32 columns, 8 row lanes each
-// summing every 8th row in float64, then the 8 partials in a fixed order.
-__global__ void __launch_bounds__(256) k_colsum(int rows, int cols, const float* A, float* out) {
-  __shared__ double part[8][32];
-  const int cl = threadIdx.x & 31, rl = threadIdx.x >> 5;
-  const int c = blockIdx.x * 32 + cl;
+// Column sums out[c] = sum_r A[r][c] in two passes with a fixed order.
+// Pass 1 (grid (ceil(cols / 64), ceil(rows / kColsumRows)), 256 threads):
+// workgroup (x, b) sums the rows of slice b for 64 columns, 4 row lanes each
+// taking every 4th row in float64, the lanes combined in lane order, into
+// part[b][c].  Pass 2 adds the slices' partials in slice order.  Every
+// workgroup's share is short, so the sums are spread over the whole chip.
+constexpr int kColsumRows = 64;
+
+__global__ void __launch_bounds__(256) k_colsum_part(int rows, int cols, const float* A,
+                                                     double* part) {
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int r0 = blockIdx.y * kColsumRows, r1 = min(rows, r0 + kColsumRows);
   double s = 0.0;
   if (c < cols)
-    for (int r = rl; r < rows; r += 8) s += A[static_cast<int64_t>(r) * cols + c];
-  part[rl][cl] = s;
+    for (int r = r0 + rl; r < r1; r += 4) s += A[static_cast<int64_t>(r) * cols + c];
+  red[rl][cl] = s;
   __syncthreads();
-  if (rl == 0 && c < cols) {
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t += part[i][cl];
-    out[c] = static_cast<float>(t);
+  if (rl == 0 && c < cols)
+    part[static_cast<int64_t>(blockIdx.y) * cols + c] =
+        ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
+__global__ void k_colsum_final(int n_part, int cols, const double* part, float* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double t = 0.0;
+  for (int b = 0; b < n_part; ++b) t += part[static_cast<int64_t>(b) * cols + c];
+  out[c] = static_cast<float>(t);
+}
+
+// out[c][r] = in[r][c] for a rows x cols bfloat16 matrix (leading dimensions
+// ldi, ldo), through LDS in 64 x 64 tiles: both the reads and the writes
+// move consecutive elements across consecutive threads.
+__global__ void __launch_bounds__(256) k_transpose_bf16(int rows, int cols, const uint16_t* in,
+                                                        int64_t ldi, uint16_t* out, int64_t ldo) {
+  __shared__ uint16_t tile[64][66];
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int r = i >> 6, c = i & 63;
+    const int gr = r0 + r, gc = c0 + c;
+    tile[r][c] = (gr < rows && gc < cols) ? in[gr * ldi + gc] : uint16_t(0);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int c = i >> 6, r = i & 63;
+    const int gr = r0 + r, gc = c0 + c;
+    if (gr < rows && gc < cols) out[gc * ldo + gr] = tile[r][c];
   }
 }
 

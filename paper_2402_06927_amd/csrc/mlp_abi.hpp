@@ -15,12 +15,18 @@ bool mlp_ok(const sch_mlp* n) {
 
 // Activations of the last forward pass, kept in the caller's workspace for
 // the backward pass: Z1, Z2 (float32), H1, H2 (bf16), then the backward
-// temporaries dY (float32, bf16), dZ2, dZ1 (float32, bf16).
+// temporaries dY (float32, bf16), dZ2, dZ1 (float32, bf16); the transposed
+// bf16 copies (...T) that put every backward product's operands contiguous
+// along its summation index; the column-sum partials.
 struct MlpWs {
   float *Z1, *Z2, *dY32, *dZ2, *dZ1;
   uint16_t *H1, *H2, *dY16, *dZ2b, *dZ1b;
+  uint16_t *XT, *dYT, *H1T, *H2T, *dZ2T, *dZ1T, *W2T, *W3T;
+  double* part;
   size_t bytes;
 };
+
+int colsum_parts(int rows) { return (rows + kColsumRows - 1) / kColsumRows; }
 
 MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
   Carve c(base);
@@ -36,8 +42,31 @@ MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
   w.dZ2b = c.take<uint16_t>(bh);
   w.dZ1 = c.take<float>(bh);
   w.dZ1b = c.take<uint16_t>(bh);
+  w.XT = c.take<uint16_t>(static_cast<size_t>(batch) * d.F);
+  w.dYT = c.take<uint16_t>(bo);
+  w.H1T = c.take<uint16_t>(bh);
+  w.H2T = c.take<uint16_t>(bh);
+  w.dZ2T = c.take<uint16_t>(bh);
+  w.dZ1T = c.take<uint16_t>(bh);
+  w.W2T = c.take<uint16_t>(static_cast<size_t>(d.H) * d.H);
+  w.W3T = c.take<uint16_t>(static_cast<size_t>(d.H) * d.O);
+  w.part = c.take<double>(static_cast<size_t>(colsum_parts(batch)) * (d.H > d.O ? d.H : d.O));
   w.bytes = c.off + 256;
   return w;
+}
+
+void transpose_bf16(int rows, int cols, const uint16_t* in, uint16_t* out, hipStream_t st) {
+  const dim3 grid((cols + 63) / 64, (rows + 63) / 64);
+  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, st, rows, cols, in, int64_t(cols), out,
+                     int64_t(rows));
+}
+
+void colsum(int rows, int cols, const float* A, double* part, float* out, hipStream_t st) {
+  const int nb = colsum_parts(rows);
+  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, nb), dim3(256), 0, st, rows, cols, A,
+                     part);
+  hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, nb, cols, part,
+                     out);
 }
 
 GemmArgs gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
@@ -139,15 +168,31 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, loss, 0.0, int64_t(1));
   hipLaunchKernelGGL(k_mse, dim3(grid_for(bo, 256)), dim3(256), 0, st, bo, Y, T,
                      1.0f / static_cast<float>(bo), w.dY32, w.dY16, loss);
+  // Every product below runs with both operands contiguous along its sum
+  // (the fast loader): the weights W2, W3 are transposed once per call, and
+  // for a batch that is a multiple of 8 the activations and X are too, so the
+  // weight gradients (summed over the batch) take that loader as well;
+  // otherwise those take the element-wise loader on the original layouts.
+  // Transposing moves bf16 values unchanged: the products' rounding is the
+  // same either way.
+  const bool tr = batch % 8 == 0;
+  transpose_bf16(H, H, wb + d.qW2, w.W2T, st);
+  transpose_bf16(O, H, wb + d.qW3, w.W3T, st);
+  if (tr) {
+    transpose_bf16(batch, O, w.dY16, w.dYT, st);
+    transpose_bf16(batch, H, w.H2, w.H2T, st);
+    transpose_bf16(batch, H, w.H1, w.H1T, st);
+    transpose_bf16(batch, F, X, w.XT, st);
+  }
   // dW3 = dY^T H2, db3 = column sums of dY
-  GemmArgs g = gemm(O, H, batch, w.dY16, 1, O, w.H2, H, 1);
+  GemmArgs g = tr ? gemm(O, H, batch, w.dYT, batch, 1, w.H2T, 1, batch)
+                  : gemm(O, H, batch, w.dY16, 1, O, w.H2, H, 1);
   g.C32 = grad + d.oW3;
   g.ldc = H;
   launch_gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3((O + 31) / 32), dim3(256), 0, st, batch, O, w.dY32,
-                     grad + d.ob3);
+  colsum(batch, O, w.dY32, w.part, grad + d.ob3, st);
   // dZ2 = (dY W3) * [Z2 > 0]
-  g = gemm(batch, H, O, w.dY16, O, 1, wb + d.qW3, H, 1);
+  g = gemm(batch, H, O, w.dY16, O, 1, w.W3T, 1, O);
   g.mask = w.Z2;
   g.ldm = H;
   g.C32 = w.dZ2;
@@ -156,14 +201,15 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   g.ldc16 = H;
   launch_gemm(g, st);
   // dW2 = dZ2^T H1, db2
-  g = gemm(H, H, batch, w.dZ2b, 1, H, w.H1, H, 1);
+  if (tr) transpose_bf16(batch, H, w.dZ2b, w.dZ2T, st);
+  g = tr ? gemm(H, H, batch, w.dZ2T, batch, 1, w.H1T, 1, batch)
+         : gemm(H, H, batch, w.dZ2b, 1, H, w.H1, H, 1);
   g.C32 = grad + d.oW2;
   g.ldc = H;
   launch_gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 31) / 32), dim3(256), 0, st, batch, H, w.dZ2,
-                     grad + d.ob2);
+  colsum(batch, H, w.dZ2, w.part, grad + d.ob2, st);
   // dZ1 = (dZ2 W2) * [Z1 > 0]
-  g = gemm(batch, H, H, w.dZ2b, H, 1, wb + d.qW2, H, 1);
+  g = gemm(batch, H, H, w.dZ2b, H, 1, w.W2T, 1, H);
   g.mask = w.Z1;
   g.ldm = H;
   g.C32 = w.dZ1;
@@ -172,12 +218,13 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   g.ldc16 = H;
   launch_gemm(g, st);
   // dW1 = dZ1^T X, db1
-  g = gemm(H, F, batch, w.dZ1b, 1, H, X, F, 1);
+  if (tr) transpose_bf16(batch, H, w.dZ1b, w.dZ1T, st);
+  g = tr ? gemm(H, F, batch, w.dZ1T, batch, 1, w.XT, 1, batch)
+         : gemm(H, F, batch, w.dZ1b, 1, H, X, F, 1);
   g.C32 = grad + d.oW1;
   g.ldc = F;
   launch_gemm(g, st);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 31) / 32), dim3(256), 0, st, batch, H, w.dZ1,
-                     grad + d.ob1);
+  colsum(batch, H, w.dZ1, w.part, grad + d.ob1, st);
   CHECK_LAUNCH();
   return SCH_OK;
 }
