@@ -1,5 +1,5 @@
 // helm.hpp -- workgroup solve of the constant periodic Helmholtz system
-// H u = f, H = d I + o (S + S^{-1}) (S the cyclic shift; d = 2h/3 + 2 alpha^2/h,
+// H u = f (or H u = M f), H = d I + o (S + S^{-1}) (S the cyclic shift; d = 2h/3 + 2 alpha^2/h,
 // o = h/6 - alpha^2/h from the first line of eq. fde1), in one barrier.
 //
 // H factors as kappa (1 - r S)(1 - r S^{-1}) with r the root of modulus < 1 of
@@ -27,6 +27,12 @@ struct HelmConst {
   double rb, rb1;   // r^base, r^(base+1): multipliers of chunks of base / base+1 rows
   int base;         // nx / NT
   double ho, hd;    // off-diagonal and diagonal of H
+  // The mass matrix M (rows h/6, 2h/3, h/6) lies in the span of I and H:
+  // M = beta H + gamma I with beta = (h/6) / ho, gamma = 2h/3 - beta hd, so
+  // H^{-1} M f = beta f + gamma H^{-1} f = mg (F+ + F-) + mf f with
+  // mg = gamma coef and mf = beta - gamma coef (the scan form below).
+  double mg, mf;
+  double mh6, mh23;  // h/6 and 2h/3
 };
 
 // Composition of affine carries: apply (m1, c1) then (m2, c2).
@@ -74,12 +80,14 @@ __device__ __forceinline__ void record_scan(double& f0, double& f1, double& b0, 
 #undef SCH_RSTEP
 }
 
-template <int PMAX, int NT, bool FULL, class LT>
+// MASS: u = H^{-1} M f instead of H^{-1} f, with fl, fr the values of f at
+// the nodes bordering the chunk (for the bordering values of u).
+template <int PMAX, int NT, bool FULL, bool MASS = false, class LT>
 __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)[PMAX],
                                            double (&u)[PMAX], double& uL, double& uR, int cnt,
                                            LT& L, int slot, int t, double red0, double red1,
                                            double red2, double& gred0, double& gred1,
-                                           double& gred2) {
+                                           double& gred2, double fl = 0.0, double fr = 0.0) {
   constexpr int W = NT / kWave;
   const int lane = t & (kWave - 1), wv = t / kWave;
   const double r = K.r;
@@ -242,30 +250,34 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
     acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
-    u[j] = acc - f[j];
+    u[j] = MASS ? acc : acc - f[j];
   }
   acc = Em;
 #pragma unroll
   for (int j = PMAX - 1; j >= 0; --j) {
     acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
-    u[j] = K.coef * (u[j] + acc);
+    u[j] = MASS ? fma(K.mg, u[j] + acc, K.mf * f[j]) : K.coef * (u[j] + acc);
   }
   // bordering values from the Helmholtz rows of the first and last node,
-  // o u_{i-1} + d u_i + o u_{i+1} = f_i (meaningful for chunks of >= 2 rows)
+  // o u_{i-1} + d u_i + o u_{i+1} = g_i with g = f, or g = M f (MASS)
+  // (meaningful for chunks of >= 2 rows)
   const int last = FULL ? PMAX - 1 : cnt - 1;
-  double ul = u[PMAX - 1], ulm = u[PMAX - 2], fl = f[PMAX - 1];
+  double ul = u[PMAX - 1], ulm = u[PMAX - 2], fla = f[PMAX - 1], flm = f[PMAX - 2];
   if (!FULL) {
 #pragma unroll
     for (int j = 1; j < PMAX; ++j)
       if (j == last) {
         ul = u[j];
         ulm = u[j - 1];
-        fl = f[j];
+        fla = f[j];
+        flm = f[j - 1];
       }
   }
+  const double g0 = MASS ? fma(K.mh6, fl + f[1], K.mh23 * f[0]) : f[0];
+  const double gl = MASS ? fma(K.mh6, flm + fr, K.mh23 * fla) : fla;
   const double iho = 1.0 / K.ho;
-  uL = (f[0] - K.hd * u[0] - K.ho * u[1]) * iho;
-  uR = (fl - K.hd * ul - K.ho * ulm) * iho;
+  uL = (g0 - K.hd * u[0] - K.ho * u[1]) * iho;
+  uR = (gl - K.hd * ul - K.ho * ulm) * iho;
 }
 
 }  // namespace sch

@@ -91,6 +91,11 @@ inline HelmConst make_helm_op(double h, int nx, double a2, const Tile& tl) {
   K.rb = std::pow(K.r, static_cast<double>(K.base));
   K.rb1 = std::pow(K.r, static_cast<double>(K.base + 1));
   K.rinv = 1.0 / K.r;
+  K.mh6 = h / 6.0;
+  K.mh23 = 2.0 * h / 3.0;
+  const double beta = K.mh6 / K.ho, gamma = K.mh23 - beta * K.hd;
+  K.mg = gamma * K.coef;
+  K.mf = beta - K.mg;
   return K;
 }
 

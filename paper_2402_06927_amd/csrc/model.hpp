@@ -281,9 +281,9 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
       // max change of m*, and on the first iteration its max size, the scale
       // of the tolerance (later iterates differ from the first by its first
       // correction, about 1e-4 of it at the workloads' steps); a non-finite
-      // entry (which fmax would drop) reaches the Helmholtz right-hand side
-      // M m*, and solve_helm then reports the change as +infinity, which
-      // marks the iterate as failed
+      // entry (which fmax would drop) reaches the Helmholtz solve, and
+      // solve_helm then reports the change as +infinity, which marks the
+      // iterate as failed
       double diff = 0.0, scale = 0.0;
       if (k == 1) {
 #pragma unroll
@@ -304,15 +304,15 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
           setP(j, ms[j]);
         }
       }
-      diff = wave_max(diff);
-      // u* = H^{-1} M m*
-      double r[PMAX];
-      mass_apply_h<PMAX, FULL>(ms, r, P.h, cnt, sl - mL, sr - mR, 1.0);
+      // an upper bound within 2^-20 (a few units of the tolerance's last
+      // digit): the test below can only stop later, never earlier
+      diff = wave_max_bound(diff);
+      // u* = H^{-1} M m* (the mass product folded into the scan form)
       // the growth test rides on the Helmholtz record as a wave-uniform flag
       const double wbad = __any(!(grow <= kMaxGrowth)) ? 1.0 : 0.0;
       double gdiff, gscale, gbad;
-      solve_helm<PMAX, NT, FULL>(K, r, us, uL, uR, cnt, L, par.slot, t, diff, scale, wbad,
-                                 gdiff, gscale, gbad);
+      solve_helm<PMAX, NT, FULL, true>(K, ms, us, uL, uR, cnt, L, par.slot, t, diff, scale, wbad,
+                                       gdiff, gscale, gbad, sl - mL, sr - mR);
       par.slot ^= 1;
       if (gbad > 0.0) {
         status = SCH_E_UNSTABLE;
