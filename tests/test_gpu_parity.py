@@ -54,6 +54,18 @@ def test_philox_words_bit_exact(sch):
         assert np.array_equal(got[:300], ref)
 
 
+def test_philox_known_answers(sch):
+    """The device generator against the published known-answer vectors of
+    Philox4x32-10 (tests/golden/philox4x32_10_kat.txt)."""
+    from test_oracle_philox_kat import kat_vectors
+
+    for ctr, seed, want in kat_vectors():
+        c = np.array([ctr], dtype=np.uint32)
+        out = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+        sch.sch_philox_blocks(seed, T(c.view(np.int32), torch.int32), out)
+        assert [int(x) for x in N(out).view(np.uint32)[0]] == want, (ctr, hex(seed))
+
+
 def test_increments_match_oracle(sch):
     for (n, s, q, step0, tag, k) in [(37, 20, 4, 0, 1, 0), (5, 40, 8, 80, 2, 3), (3, 7, 5, 7, 6, 1)]:
         dW = torch.empty((n, s, q), dtype=torch.float64, device="cuda")
