@@ -1,7 +1,8 @@
 """Tile autotuner of the model kernels.
 
 A particle's row of nx nodes is split over NT threads (a power of two,
-64..512) holding nx / NT nodes each (4, 8 or 16 register slots).  For a grid
+64..512) holding nx / NT nodes each (4, 8 or 16 register slots; 2 on one
+wavefront for nx <= 128).  For a grid
 size the tuner times the library's ensemble step (``sch_ensemble_step``, the
 kernel every filter stage reruns) on the caller's own ensemble for every
 tile the library provides, keeps the fastest, and can cache the choice per
@@ -19,11 +20,13 @@ import torch
 from . import sch
 
 # (threads per particle, register slots) of the compiled model kernels
-TILES = ((64, 4), (64, 8), (128, 8), (256, 8), (256, 16), (512, 8), (512, 16))
+TILES = ((64, 2), (64, 4), (64, 8), (128, 8), (256, 8), (256, 16), (512, 8), (512, 16))
 
 
 def slots(nx: int, nt: int) -> int:
     need = math.ceil(nx / nt)
+    if nt == 64 and need <= 2:
+        return 2
     return 4 if need <= 4 else (8 if need <= 8 else 16)
 
 

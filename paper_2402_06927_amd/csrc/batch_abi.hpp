@@ -34,13 +34,21 @@ using namespace sch;
 
 
 // Tile of one instance: the threads the caller asked for, else the model
-// calls' choice; nodes per thread 4, 8 or 16.
+// calls' choice; nodes per thread 4, 8 or 16 (the batched kernels take
+// ragged chunks, so a 2-slot choice runs on 4 slots).
 bool batch_tile(const sch_instance& in, Tile& tl) {
-  if (in.threads == 0) return pick_tile(in.nx, tl);
-  const int nt = in.threads;
-  if (nt < 64 || nt > 512 || (nt & (nt - 1)) != 0 || in.nx < nt || (in.nx + nt - 1) / nt > 16)
-    return false;
-  tl = tile_for(in.nx, nt);
+  if (in.threads == 0) {
+    if (!pick_tile(in.nx, tl)) return false;
+  } else {
+    const int nt = in.threads;
+    if (nt < 64 || nt > 512 || (nt & (nt - 1)) != 0 || in.nx < nt || (in.nx + nt - 1) / nt > 16)
+      return false;
+    tl = tile_for(in.nx, nt);
+  }
+  if (tl.pmax < 4) {
+    tl.pmax = 4;
+    tl.full = false;
+  }
   return true;
 }
 

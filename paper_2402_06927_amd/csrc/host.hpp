@@ -43,18 +43,21 @@ inline int grid_for(int64_t work, int block) {
 
 // ---------------------------------------------------------------------------
 // Tile choice: NT threads per particle (power of two, 64..512), each holding
-// up to PMAX consecutive nodes in registers.  By default NT is the smallest
+// up to PMAX consecutive nodes in registers (tile_for).  By default NT is the smallest
 // power of two with nx / NT <= 8; SCH_TUNE_THREADS overrides it.
 struct Tile {
   int nt, pmax;
   bool full;
 };
 
+// Slots per thread: 4, 8 or 16, and 2 on a single wavefront (nx <= 128),
+// where the chunk sweeps would otherwise carry masked slots beside one or two
+// rows.
 inline Tile tile_for(int nx, int nt) {
   Tile tl{};
   tl.nt = nt;
   const int need = (nx + nt - 1) / nt;
-  tl.pmax = need <= 4 ? 4 : (need <= 8 ? 8 : 16);
+  tl.pmax = (nt == 64 && need <= 2) ? 2 : need <= 4 ? 4 : (need <= 8 ? 8 : 16);
   tl.full = (nx % nt == 0) && (nx / nt == tl.pmax);
   return tl;
 }
@@ -110,6 +113,7 @@ inline int with_tile(const Tile& tl, F&& f) {
   if (tl.nt == NT_ && tl.pmax == PM_)                                            \
     return tl.full ? f.template operator()<PM_, NT_, true>()                     \
                    : f.template operator()<PM_, NT_, false>();
+  SCH_CASE(64, 2)
   SCH_CASE(64, 4)
   SCH_CASE(64, 8)
   SCH_CASE(128, 8)

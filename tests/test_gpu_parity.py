@@ -398,7 +398,7 @@ def test_tempered_cycle_parity(sch):
         assert PR.rel_l2(N(u), u_o) < PR.REL_TOL, c
 
 
-@pytest.mark.parametrize("nx", [100, 600, 1000, 2048, 4096, 6000, 8192])
+@pytest.mark.parametrize("nx", [64, 100, 128, 600, 1000, 2048, 4096, 6000, 8192])
 def test_window_parity_every_tile(sch, nx):
     """Every compiled tile (threads per particle x register slots) the tuner
     may choose for this grid gives the oracle's window."""
