@@ -209,7 +209,7 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF nois
       break;
     }
     // rhs = lambda - (dt/4) M H^{-1} D(s)^T nu
-    double nl, nr, w[PMAX], z[PMAX], r[PMAX];
+    double nl, nr, w[PMAX], z[PMAX];
     halo<PMAX, NT, FULL>(nu, cnt, L, t, nl, nr, par.hs);
     if constexpr (kL) {
       double sv[PMAX];
@@ -218,12 +218,15 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF nois
     } else {
       advect_t<PMAX, FULL>(s, sl, sr, nu, nl, nr, cnt, 1.0, w);
     }
+    // M H^{-1} w = H^{-1} M w (the two circulants commute): the mass product
+    // folded into the scan form; the bordering values are not used
     double zL, zR, g0, g1, g2;
-    solve_helm<PMAX, NT, FULL>(K, w, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1, g2);
+    solve_helm<PMAX, NT, FULL, true>(K, w, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1,
+                                     g2, 0.0, 0.0);
     par.slot ^= 1;
-    mass_apply<PMAX, NT, FULL>(z, r, P.h, cnt, L, t, 0.25 * P.dt, par.hs);
+    const double q = 0.25 * P.dt;
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) rhs[j] = lam_at(j) - r[j];
+    for (int j = 0; j < PMAX; ++j) rhs[j] = fma(-q, z[j], lam_at(j));
   }
   iters += k > P.picard_max + 1 ? P.picard_max + 1 : k;
   // dJ/d(dU) = -(1/2) D(s)^T nu;  lambda_n = 2 M nu - lambda_{n+1}
@@ -327,12 +330,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     // lambda_S = M H^{-1} P^T diag(sigma^-2) (P u^S - y)
     double lam[PMAX];
     {
-      double w[PMAX], z[PMAX], zL, zR, g0, g1, g2;
+      double w[PMAX], zL, zR, g0, g1, g2;
       obs_adjoint<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, w, L, t, par.hs);
-      solve_helm<PMAX, NT, FULL>(K, w, z, zL, zR, ch.cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1,
-                                 g2);
+      // M H^{-1} w as H^{-1} M w (the bordering values are not used)
+      solve_helm<PMAX, NT, FULL, true>(K, w, lam, zL, zR, ch.cnt, L, par.slot, t, 0.0, 0.0, 0.0,
+                                       g0, g1, g2, 0.0, 0.0);
       par.slot ^= 1;
-      mass_apply<PMAX, NT, FULL>(z, lam, A.P.h, ch.cnt, L, t, 1.0, par.hs);
     }
     const int lane = t & (kWave - 1), wv = t / kWave;
     for (int c = nseg - 1; c >= 0 && st == SCH_OK; --c) {

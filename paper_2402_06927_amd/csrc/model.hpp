@@ -792,10 +792,11 @@ __global__ void __launch_bounds__(NT) k_helmholtz(const HelmArgs A, const HelmCo
   load_chunk<PMAX, FULL>(A.in + static_cast<size_t>(p) * A.P.nx, ch, v);
   int hs = 0;
   if (A.mode == 0) {
-    double r[PMAX];
-    mass_apply<PMAX, NT, FULL>(v, r, A.P.h, ch.cnt, L, t, 1.0, hs);
+    // the mass product folded into the scan form (the bordering values are
+    // not used)
     double uL, uR, g0, g1, g2;
-    solve_helm<PMAX, NT, FULL>(K, r, o, uL, uR, ch.cnt, L, 0, t, 0.0, 0.0, 0.0, g0, g1, g2);
+    solve_helm<PMAX, NT, FULL, true>(K, v, o, uL, uR, ch.cnt, L, 0, t, 0.0, 0.0, 0.0, g0, g1, g2,
+                                     0.0, 0.0);
   } else {
     // right-hand side H u = M u + alpha^2 K u, then the mass solve
     double hl, hr;
