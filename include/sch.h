@@ -471,6 +471,45 @@ int sch_pf_tempered_cycle_pcnl(const sch_model *model, const sch_obs *obs, uint6
                                void *stream);
 
 /* --------------------------------------------------------------------------
+ * Gradient-based jitter: Hybrid Monte Carlo moves, the second sampler the
+ * paper names as future work (section 5), in the function-space form of
+ * Beskos, Pinski, Sanz-Serna & Stuart (Stoch. Proc. Appl. 2011).  For each
+ * particle, with x its increments [n_steps][n_modes] (prior N(0, dt I)) and
+ * the target exp(-theta phi(x)) N(x; 0, dt I): a velocity v = sqrt(dt) z (the
+ * normals sch_jitter_pcn draws for the move), then n_leap leapfrog steps of
+ * angle h of H(x, v) = theta phi(x) + (|x|^2 + |v|^2) / (2 dt), each a half
+ * kick v -= (h/2) dt theta grad phi(x), the rotation
+ * (x, v) -> (cos h x + sin h v, -sin h x + cos h v) and a half kick, and the
+ * Metropolis test with probability min(1, exp(H(x, v) - H(x', v'))) (the
+ * acceptance uniform as sch_jitter_pcn's).  phi and grad phi come from the
+ * discrete adjoint of sch_nudge_grad: one forward + reverse pass at the start
+ * and n_leap per move (checkpoints every ckpt_every steps).  A trajectory
+ * that meets a failed window is rejected.
+ *   h in (0, pi), n_leap in 1..64 (else SCH_E_ARG); dW, phi in/out as
+ *   sch_jitter_pcn (no controls); m_end, u_end out: the window ends of the
+ *   final increments (recomputed)
+ *   workspace >= sch_hmc_workspace_bytes(SCH_WS_JITTER, model, n, n_steps,
+ *                n_jitter, ckpt_every)
+ * sch_pf_tempered_cycle_hmc: sch_pf_tempered_cycle with these moves
+ * (workspace: SCH_WS_TEMPERED); stats->particle_steps counts the forward
+ * windows (the gradient at the start, n_leap per move and the end-state rerun
+ * per tempering step), not the reverse passes.
+ * ------------------------------------------------------------------------ */
+size_t sch_hmc_workspace_bytes(int32_t which, const sch_model *model, int32_t n_particles,
+                               int32_t n_steps, int32_t n_jitter, int32_t ckpt_every);
+int sch_jitter_hmc(const sch_model *model, const sch_obs *obs, const sch_rng *rng,
+                   int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
+                   double *dW, double *phi, double *m_end, double *u_end, const double *theta,
+                   double h, int32_t n_leap, int32_t n_jitter, int32_t ckpt_every,
+                   int32_t *n_accept, void *workspace, void *stream);
+int sch_pf_tempered_cycle_hmc(const sch_model *model, const sch_obs *obs, uint64_t seed,
+                              uint32_t cycle, int32_t n_particles, int32_t n_steps,
+                              double ess_threshold, int32_t n_bisect, double h, int32_t n_leap,
+                              int32_t n_jitter, int32_t max_temper, int32_t ckpt_every,
+                              double *m, double *u, void *workspace, sch_cycle_stats *stats,
+                              void *stream);
+
+/* --------------------------------------------------------------------------
  * Matern-type noise (section 2, eqs. noise_solve and noise_solve2), the
  * paper's own noise in place of the modes form.  Per step the space-time
  * white noise is its DG0 approximation: one increment Delta W_i ~ N(0, dt)

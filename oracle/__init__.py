@@ -175,6 +175,21 @@ def _declare(L):
                                               C.c_uint32, C.c_int32, C.c_int32, C.c_double,
                                               C.c_int32, C.c_double, C.c_int32, C.c_int32, _dp,
                                               _dp, C.POINTER(OrcCycleStats), C.c_int32]),
+        "orc_hmc_trajectory_linear": (None, [C.c_int32, C.c_int32, _dp, _dp, C.c_double,
+                                             C.c_double, C.c_double, C.c_int32, C.c_double,
+                                             _dp, _dp]),
+        "orc_hmc_linear_chain": (C.c_int64, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _dp,
+                                             _dp, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                             C.c_double, C.c_int32, _dp, _dp, C.c_int32]),
+        "orc_jitter_hmc": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.POINTER(OrcRng),
+                                     C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     C.c_double, C.c_double, C.c_int32, C.c_int32, _ip,
+                                     C.c_int32]),
+        "orc_tempered_cycle_hmc": (C.c_int, [C.POINTER(OrcModel), C.c_int32, _dp, _dp, C.c_uint64,
+                                             C.c_uint32, C.c_int32, C.c_int32, C.c_double,
+                                             C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                             C.c_int32, _dp, _dp, C.POINTER(OrcCycleStats),
+                                             C.c_int32]),
         "orc_matern_transpose": (C.c_int, [C.c_int32, C.c_double, C.POINTER(OrcMatern), _dp,
                                            _dp]),
         "orc_nudge_grad_matern": (C.c_int, [C.POINTER(OrcModel), C.POINTER(OrcMatern), C.c_int32,
@@ -566,6 +581,7 @@ def tempered_cycle(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_thres
 PLANT_NONE = 0
 PLANT_JITTER_PRE_THETA = 1
 PLANT_CUMULATIVE_WEIGHTS = 2
+PLANT_HMC_NO_KINETIC = 3
 
 
 def tempered_cycle_linear(F, B, G, y, sigma, dt, seed, cycle, x, n_steps, n_modes,
@@ -964,6 +980,63 @@ def tempered_cycle_pcnl(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_
                                        m.shape[0], n_steps, ess_threshold, n_bisect, rho,
                                        n_jitter, max_temper, _d(m), _d(u), C.byref(st),
                                        n_threads or n_threads_default())
+    return rc, m, u, st
+
+
+# --------------------------------------------------------------------------- Hybrid Monte Carlo
+def hmc_trajectory_linear(G, y, sigma, theta, h, n_leap, dt, x, v):
+    """n_leap leapfrog steps of the HMC integrator for the linear-Gaussian toy
+    Phi(x) = |G x - y|^2 / (2 sigma^2); returns the final (x, v)."""
+    G = _f64(G)
+    y = _f64(y)
+    x = np.array(x, dtype=np.float64, copy=True)
+    v = np.array(v, dtype=np.float64, copy=True)
+    lib().orc_hmc_trajectory_linear(len(x), len(y), _d(G), _d(y), sigma, theta, h, n_leap, dt,
+                                    _d(x), _d(v))
+    return x, v
+
+
+def hmc_linear_chain(seed, n_steps, n_modes, G, y, sigma, theta, h, n_leap, dt, n_iter,
+                     x0=None, plant=0):
+    G = _f64(G)
+    y = _f64(y)
+    d = n_steps * n_modes
+    x0 = np.zeros(d) if x0 is None else _f64(x0)
+    samples = np.zeros((n_iter, d))
+    acc = lib().orc_hmc_linear_chain(seed, n_steps, n_modes, len(y), _d(G), _d(y), sigma, theta,
+                                     h, n_leap, dt, n_iter, _d(x0), _d(samples), plant)
+    return samples, acc
+
+
+def jitter_hmc(model: Model, y, sigma, seed, cycle, temper_k, m0, u0, dW, phi, theta, h, n_leap,
+               n_jitter, n_threads=None):
+    """Hybrid Monte Carlo moves; returns (rc, dW, phi, m_end, u_end, n_accept)."""
+    y, sg = _obs_arrays(y, sigma)
+    dW = np.array(dW, dtype=np.float64, copy=True, order="C")
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    P, ns = dW.shape[0], dW.shape[1]
+    m_end = np.zeros((P, model.nx))
+    u_end = np.zeros((P, model.nx))
+    acc = np.zeros(P, dtype=np.int32)
+    rg = OrcRng(seed, cycle, temper_k)
+    cm = model.c()
+    rc = lib().orc_jitter_hmc(C.byref(cm), len(y), _d(y), _d(sg), C.byref(rg), P, ns,
+                              _d(_f64(m0)), _d(_f64(u0)), _d(dW), _d(phi), _d(m_end), _d(u_end),
+                              theta, h, n_leap, n_jitter, _i(acc), n_threads or n_threads_default())
+    return rc, dW, phi, m_end, u_end, acc
+
+
+def tempered_cycle_hmc(model: Model, y, sigma, seed, cycle, m, u, n_steps, ess_threshold,
+                       n_bisect=50, h=0.3, n_leap=3, n_jitter=5, max_temper=100, n_threads=None):
+    y, sg = _obs_arrays(y, sigma)
+    m = np.array(m, dtype=np.float64, copy=True, order="C")
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    st = OrcCycleStats()
+    cm = model.c()
+    rc = lib().orc_tempered_cycle_hmc(C.byref(cm), len(y), _d(y), _d(sg), seed, cycle,
+                                      m.shape[0], n_steps, ess_threshold, n_bisect, h, n_leap,
+                                      n_jitter, max_temper, _d(m), _d(u), C.byref(st),
+                                      n_threads or n_threads_default())
     return rc, m, u, st
 
 

@@ -1182,7 +1182,7 @@ static int temper_loop(int32_t n, double *pot, row_set *rows, int32_t n_rows, ui
 }
 
 /* The jitters of the SCH drivers behind the callback of temper_loop. */
-enum { JIT_PCN = 0, JIT_PCNL = 1, JIT_PCN_CTRL = 2, JIT_MATERN = 3 };
+enum { JIT_PCN = 0, JIT_PCNL = 1, JIT_PCN_CTRL = 2, JIT_MATERN = 3, JIT_HMC = 4 };
 static int jitter_matern(const orc_model *md, const orc_matern *mt, int32_t n_obs,
                          const double *y, const double *sigma, const orc_rng *rng,
                          int32_t n_particles, int32_t n_steps, const double *m0, const double *u0,
@@ -1197,6 +1197,8 @@ typedef struct {
   const double *y, *sigma, *m0, *u0, *dLam;
   double *dW, *pot, *m, *u;
   double rho;
+  double h;       /* HMC: leapfrog angle */
+  int32_t n_leap; /* HMC: leapfrog steps per move */
 } sch_jitter_ctx;
 
 static void sch_jitter(void *vctx, const orc_rng *rg, double theta, int32_t *acc) {
@@ -1206,6 +1208,11 @@ static void sch_jitter(void *vctx, const orc_rng *rg, double theta, int32_t *acc
       orc_jitter_pcnl(c->md, c->n_obs, c->y, c->sigma, rg, c->n_particles, c->n_steps, c->m0,
                       c->u0, c->dW, c->pot, c->m, c->u, theta, c->rho, c->n_jitter, acc,
                       c->n_threads);
+      break;
+    case JIT_HMC:
+      orc_jitter_hmc(c->md, c->n_obs, c->y, c->sigma, rg, c->n_particles, c->n_steps, c->m0,
+                     c->u0, c->dW, c->pot, c->m, c->u, theta, c->h, c->n_leap, c->n_jitter, acc,
+                     c->n_threads);
       break;
     case JIT_PCN_CTRL:
       orc_jitter_pcn_ctrl(c->md, c->n_obs, c->y, c->sigma, rg, c->n_particles, c->n_steps,
@@ -1236,7 +1243,8 @@ static int tempered_cycle(const orc_model *md, int32_t n_obs, const double *y,
                           const double *sigma, uint64_t seed, uint32_t cycle, int32_t n_particles,
                           int32_t n_steps, double ess_threshold, int32_t n_bisect, double rho,
                           int32_t n_jitter, int32_t max_temper, double *m, double *u,
-                          orc_cycle_stats *st, int32_t n_threads, int pcnl) {
+                          orc_cycle_stats *st, int32_t n_threads, int kind, double h,
+                          int32_t n_leap) {
   int32_t nx = md->nx, nq = md->n_modes;
   size_t state = (size_t)n_particles * nx, wlen = (size_t)n_particles * n_steps * nq;
   double *m0 = (double *)malloc(sizeof(double) * state), *u0 = (double *)malloc(sizeof(double) * state);
@@ -1258,8 +1266,8 @@ static int tempered_cycle(const orc_model *md, int32_t n_obs, const double *y,
   }
   row_set rows[5] = {{m0, (size_t)nx}, {u0, (size_t)nx}, {m, (size_t)nx}, {u, (size_t)nx},
                      {dW, (size_t)n_steps * nq}};
-  sch_jitter_ctx jc = {pcnl ? JIT_PCNL : JIT_PCN, md, NULL, n_obs, n_particles, n_steps,
-                       n_jitter, n_threads, y, sigma, m0, u0, NULL, dW, phi, m, u, rho};
+  sch_jitter_ctx jc = {kind, md, NULL, n_obs, n_particles, n_steps, n_jitter, n_threads, y,
+                       sigma, m0, u0, NULL, dW, phi, m, u, rho, h, n_leap};
   int rc = temper_loop(n_particles, phi, rows, 5, seed, cycle, ess_threshold, n_bisect,
                        max_temper, sch_jitter, &jc, st, ORC_PLANT_NONE);
   st->status = rc;
@@ -1278,7 +1286,8 @@ int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, cons
                        int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
                        int32_t n_threads) {
   return tempered_cycle(md, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
-                        n_bisect, rho, n_jitter, max_temper, m, u, st, n_threads, 0);
+                        n_bisect, rho, n_jitter, max_temper, m, u, st, n_threads, JIT_PCN, 0.0,
+                        0);
 }
 
 /* The tempered cycle with the gradient-based pCN-Langevin jitter
@@ -1289,7 +1298,21 @@ int orc_tempered_cycle_pcnl(const orc_model *md, int32_t n_obs, const double *y,
                             int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
                             double *m, double *u, orc_cycle_stats *st, int32_t n_threads) {
   return tempered_cycle(md, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
-                        n_bisect, rho, n_jitter, max_temper, m, u, st, n_threads, 1);
+                        n_bisect, rho, n_jitter, max_temper, m, u, st, n_threads, JIT_PCNL, 0.0,
+                        0);
+}
+
+/* The tempered cycle with the Hybrid Monte Carlo jitter (orc_jitter_hmc) in
+ * place of pCN. */
+int orc_tempered_cycle_hmc(const orc_model *md, int32_t n_obs, const double *y,
+                           const double *sigma, uint64_t seed, uint32_t cycle,
+                           int32_t n_particles, int32_t n_steps, double ess_threshold,
+                           int32_t n_bisect, double h, int32_t n_leap, int32_t n_jitter,
+                           int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
+                           int32_t n_threads) {
+  return tempered_cycle(md, n_obs, y, sigma, seed, cycle, n_particles, n_steps, ess_threshold,
+                        n_bisect, 0.0, n_jitter, max_temper, m, u, st, n_threads, JIT_HMC, h,
+                        n_leap);
 }
 
 /* The linear-Gaussian plug-in of the tempering loop (declared in the header
@@ -2046,7 +2069,7 @@ static int nudged_cycle(const orc_model *md, const orc_matern *mt, int32_t n_obs
   row_set rows[6] = {{m0, (size_t)nx}, {u0, (size_t)nx}, {m, (size_t)nx}, {u, (size_t)nx},
                      {dW, (size_t)n_steps * nq}, {dLam, (size_t)n_steps * nq}};
   sch_jitter_ctx jc = {mt ? JIT_MATERN : JIT_PCN_CTRL, md, mt, n_obs, n_particles, n_steps,
-                       n_jitter, n_threads, y, sigma, m0, u0, dLam, dW, J, m, u, rho};
+                       n_jitter, n_threads, y, sigma, m0, u0, dLam, dW, J, m, u, rho, 0.0, 0};
   int rc = temper_loop(n_particles, J, rows, 6, seed, cycle, ess_threshold, n_bisect, max_temper,
                        sch_jitter, &jc, st, ORC_PLANT_NONE);
   st->status = rc;
@@ -2219,7 +2242,7 @@ int orc_tempered_cycle_matern(const orc_model *md, const orc_matern *mt, int32_t
   row_set rows[5] = {{m0, (size_t)nx}, {u0, (size_t)nx}, {m, (size_t)nx}, {u, (size_t)nx},
                      {dWc, (size_t)n_steps * nx}};
   sch_jitter_ctx jc = {JIT_MATERN, md, mt, n_obs, n_particles, n_steps, n_jitter, n_threads, y,
-                       sigma, m0, u0, NULL, dWc, phi, m, u, rho};
+                       sigma, m0, u0, NULL, dWc, phi, m, u, rho, 0.0, 0};
   int rc = temper_loop(n_particles, phi, rows, 5, seed, cycle, ess_threshold, n_bisect,
                        max_temper, sch_jitter, &jc, st, ORC_PLANT_NONE);
   st->status = rc;
@@ -2472,6 +2495,190 @@ int orc_jitter_pcnl(const orc_model *md, int32_t n_obs, const double *y, const d
     free(v);
     free(gx);
     free(gv);
+  }
+  return ORC_OK;
+}
+
+/* ========================================================================== */
+/* Gradient-based jitter: Hybrid Monte Carlo on the increments x of a particle */
+/* (prior N(0, dt I), target proportional to exp(-theta Phi(x)) N(x; 0, dt I)),*/
+/* the second sampler the paper names as future work (section 5).  With the    */
+/* velocity v distributed as the prior, the Hamiltonian is                     */
+/*   H(x, v) = theta Phi(x) + (|x|^2 + |v|^2) / (2 dt)                         */
+/* and its flow dx/dt = v, dv/dt = -x - dt theta grad Phi(x) is split into     */
+/* kicks v -= tau dt theta grad Phi(x) (the Phi part) and the exact flow of the*/
+/* Gaussian part, a rotation of (x, v) by the angle tau.  One leapfrog step of */
+/* angle h is a half kick, the rotation and a half kick (Strang splitting:     */
+/* reversible and volume-preserving), so the Metropolis test on               */
+/* exp(H(x0, v0) - H(xL, vL)) makes the move exact for the tempered target     */
+/* (Beskos, Pinski, Sanz-Serna & Stuart, Stoch. Proc. Appl. 2011, for the      */
+/* function-space form).  v0 is the pCN normals sqrt(dt) z of the move (tag    */
+/* PCN), the uniform that of orc_jitter_pcn (tag ACCEPT).                      */
+/* ========================================================================== */
+static void hmc_kick(int32_t d, double tau, double dt, double theta, const double *g,
+                     double *v) {
+  for (int32_t i = 0; i < d; ++i) v[i] -= tau * dt * theta * g[i];
+}
+
+static void hmc_rotate(int32_t d, double c, double s, double *x, double *v) {
+  for (int32_t i = 0; i < d; ++i) {
+    double xi = x[i], vi = v[i];
+    x[i] = c * xi + s * vi;
+    v[i] = -s * xi + c * vi;
+  }
+}
+
+static long double hmc_gauss(int32_t d, const double *x, const double *v, double dt) {
+  long double s = 0.0L;
+  for (int32_t i = 0; i < d; ++i) s += (long double)x[i] * x[i] + (long double)v[i] * v[i];
+  return s / (2.0L * dt);
+}
+
+/* The linear-Gaussian toy: Phi(x) = |G x - y|^2 / (2 sigma^2) and its
+ * gradient G^T (G x - y) / sigma^2 (G [n_obs][d]). */
+static double toy_eval(int32_t d, int32_t n_obs, const double *G, const double *y, double sigma,
+                       const double *x, double *g, double *res) {
+  double phi = 0.0;
+  for (int32_t j = 0; j < n_obs; ++j) {
+    double r = -y[j];
+    for (int32_t i = 0; i < d; ++i) r += G[(size_t)j * d + i] * x[i];
+    res[j] = r;
+    phi += 0.5 * r * r / (sigma * sigma);
+  }
+  for (int32_t i = 0; i < d; ++i) {
+    double a = 0.0;
+    for (int32_t j = 0; j < n_obs; ++j) a += G[(size_t)j * d + i] * res[j];
+    g[i] = a / (sigma * sigma);
+  }
+  return phi;
+}
+
+void orc_hmc_trajectory_linear(int32_t d, int32_t n_obs, const double *G, const double *y,
+                               double sigma, double theta, double h, int32_t n_leap, double dt,
+                               double *x, double *v) {
+  double *g = (double *)malloc(sizeof(double) * d);
+  double *res = (double *)malloc(sizeof(double) * (n_obs > 0 ? n_obs : 1));
+  double c = cos(h), s = sin(h);
+  toy_eval(d, n_obs, G, y, sigma, x, g, res);
+  for (int32_t l = 0; l < n_leap; ++l) {
+    hmc_kick(d, 0.5 * h, dt, theta, g, v);
+    hmc_rotate(d, c, s, x, v);
+    toy_eval(d, n_obs, G, y, sigma, x, g, res);
+    hmc_kick(d, 0.5 * h, dt, theta, g, v);
+  }
+  free(g);
+  free(res);
+}
+
+int64_t orc_hmc_linear_chain(uint64_t seed, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                             const double *G, const double *y, double sigma, double theta,
+                             double h, int32_t n_leap, double dt, int32_t n_iter,
+                             const double *x0, double *samples, int32_t plant) {
+  int32_t d = n_steps * n_modes;
+  double *x = (double *)malloc(sizeof(double) * d), *xp = (double *)malloc(sizeof(double) * d);
+  double *v0 = (double *)malloc(sizeof(double) * d), *v = (double *)malloc(sizeof(double) * d);
+  double *g = (double *)malloc(sizeof(double) * d);
+  double *res = (double *)malloc(sizeof(double) * (n_obs > 0 ? n_obs : 1));
+  memcpy(x, x0, sizeof(double) * d);
+  double phi = toy_eval(d, n_obs, G, y, sigma, x, g, res);
+  int64_t acc = 0;
+  for (int32_t it = 0; it < n_iter; ++it) {
+    uint32_t w3 = (uint32_t)it;
+    orc_pcn_propose(seed, 0u, (uint32_t)(it >> 16) * (uint32_t)n_steps, n_steps, n_modes, w3, 0.0,
+                    dt, x, v0);
+    memcpy(xp, x, sizeof(double) * d);
+    memcpy(v, v0, sizeof(double) * d);
+    orc_hmc_trajectory_linear(d, n_obs, G, y, sigma, theta, h, n_leap, dt, xp, v);
+    double phin = toy_eval(d, n_obs, G, y, sigma, xp, g, res);
+    if (plant == ORC_PLANT_HMC_NO_KINETIC) {
+      memset(v0, 0, sizeof(double) * d);
+      memset(v, 0, sizeof(double) * d);
+    }
+    double lr = (double)(((long double)theta * phi + hmc_gauss(d, x, v0, dt)) -
+                         ((long double)theta * phin + hmc_gauss(d, xp, v, dt)));
+    double u = orc_uniform(seed, 0u, (uint32_t)(it >> 16), (uint32_t)ORC_TAG_ACCEPT << 24, w3);
+    if (pcnl_accept(lr, u)) {
+      memcpy(x, xp, sizeof(double) * d);
+      phi = phin;
+      ++acc;
+    }
+    memcpy(samples + (size_t)it * d, x, sizeof(double) * d);
+  }
+  free(x);
+  free(xp);
+  free(v0);
+  free(v);
+  free(g);
+  free(res);
+  return acc;
+}
+
+/* n_jitter HMC moves of every particle's increments dW [n][n_steps][Q] at
+ * temperature theta, n_leap leapfrog steps of angle h each; Phi and grad Phi
+ * of a window from the adjoint (pcnl_eval), the gradient at the current state
+ * carried from move to move.  A trajectory that meets a failed window is
+ * rejected; a failed current state is left for any finite proposal.  phi [n]
+ * in/out; m_end, u_end: the window ends of the final increments. */
+int orc_jitter_hmc(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                   const orc_rng *rng, int32_t n_particles, int32_t n_steps, const double *m0,
+                   const double *u0, double *dW, double *phi, double *m_end, double *u_end,
+                   double theta, double h, int32_t n_leap, int32_t n_jitter, int32_t *n_accept,
+                   int32_t n_threads) {
+  int32_t nx = md->nx, nq = md->n_modes, d = n_steps * nq;
+  if (!(h > 0.0) || n_leap < 1) return ORC_E_ARG;
+  double c = cos(h), s = sin(h);
+#pragma omp parallel for num_threads(n_threads > 0 ? n_threads : 1) schedule(dynamic, 1)
+  for (int32_t p = 0; p < n_particles; ++p) {
+    double *x = dW + (size_t)p * d;
+    double *xp = (double *)malloc(sizeof(double) * d), *v0 = (double *)malloc(sizeof(double) * d);
+    double *v = (double *)malloc(sizeof(double) * d), *gx = (double *)malloc(sizeof(double) * d);
+    double *gp = (double *)malloc(sizeof(double) * d);
+    const double *mp = m0 + (size_t)p * nx, *up = u0 + (size_t)p * nx;
+    double phx = phi[p], php = INFINITY, dummy;
+    if (pcnl_eval(md, n_obs, y, sigma, n_steps, mp, up, x, &dummy, gx) != ORC_OK)
+      memset(gx, 0, sizeof(double) * d); /* a failed state: any finite proposal leaves it */
+    int32_t acc = 0;
+    for (int32_t j = 0; j < n_jitter; ++j) {
+      uint32_t w3 = (rng->temper_k << 16) | (uint32_t)j;
+      orc_pcn_propose(rng->seed, (uint32_t)p, rng->cycle * (uint32_t)n_steps, n_steps, nq, w3,
+                      0.0, md->dt, x, v0);
+      memcpy(xp, x, sizeof(double) * d);
+      memcpy(v, v0, sizeof(double) * d);
+      memcpy(gp, gx, sizeof(double) * d);
+      int ok = 1;
+      for (int32_t l = 0; l < n_leap && ok; ++l) {
+        hmc_kick(d, 0.5 * h, md->dt, theta, gp, v);
+        hmc_rotate(d, c, s, xp, v);
+        ok = pcnl_eval(md, n_obs, y, sigma, n_steps, mp, up, xp, &php, gp) == ORC_OK;
+        if (ok) hmc_kick(d, 0.5 * h, md->dt, theta, gp, v);
+      }
+      if (!ok) php = INFINITY;
+      double u = orc_uniform(rng->seed, (uint32_t)p, rng->cycle, (uint32_t)ORC_TAG_ACCEPT << 24,
+                             w3);
+      double lr = -INFINITY;
+      if (isfinite(php) && isfinite(phx))
+        lr = (double)(((long double)theta * phx + hmc_gauss(d, x, v0, md->dt)) -
+                      ((long double)theta * php + hmc_gauss(d, xp, v, md->dt)));
+      if (isfinite(php) && !isfinite(phx)) lr = INFINITY; /* leave a failed state at once */
+      if (pcnl_accept(lr, u)) {
+        memcpy(x, xp, sizeof(double) * d);
+        memcpy(gx, gp, sizeof(double) * d);
+        phx = php;
+        ++acc;
+      }
+    }
+    phi[p] = phx;
+    if (n_accept) n_accept[p] = acc;
+    double *me = m_end + (size_t)p * nx, *ue = u_end + (size_t)p * nx;
+    memcpy(me, mp, sizeof(double) * nx);
+    memcpy(ue, up, sizeof(double) * nx);
+    int32_t it = 0;
+    orc_window(md, n_steps, me, ue, x, NULL, &it);
+    free(xp);
+    free(v0);
+    free(v);
+    free(gx);
+    free(gp);
   }
   return ORC_OK;
 }

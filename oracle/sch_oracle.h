@@ -192,7 +192,8 @@ int orc_tempered_cycle(const orc_model *md, int32_t n_obs, const double *y, cons
  * ORC_PLANT_JITTER_PRE_THETA jitters at the temperature before the step,
  * ORC_PLANT_CUMULATIVE_WEIGHTS resamples with exp(-theta_new Phi) instead of
  * exp(-dtheta Phi). */
-enum { ORC_PLANT_NONE = 0, ORC_PLANT_JITTER_PRE_THETA = 1, ORC_PLANT_CUMULATIVE_WEIGHTS = 2 };
+enum { ORC_PLANT_NONE = 0, ORC_PLANT_JITTER_PRE_THETA = 1, ORC_PLANT_CUMULATIVE_WEIGHTS = 2,
+       ORC_PLANT_HMC_NO_KINETIC = 3 };
 int orc_tempered_cycle_linear(int32_t ds, int32_t n_steps, int32_t n_modes, int32_t n_obs,
                               const double *F, const double *B, const double *G, const double *y,
                               double sigma, double dt, uint64_t seed, uint32_t cycle,
@@ -328,6 +329,37 @@ int orc_tempered_cycle_pcnl(const orc_model *md, int32_t n_obs, const double *y,
                             int32_t n_particles, int32_t n_steps, double ess_threshold,
                             int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
                             double *m, double *u, orc_cycle_stats *st, int32_t n_threads);
+
+/* ---- gradient-based jitter (Hybrid Monte Carlo on the increments) ----
+ * Per move: velocity v ~ N(0, dt I) (the pCN normals sqrt(dt) z of the move),
+ * n_leap leapfrog steps of angle h of the Hamiltonian
+ * H(x, v) = theta Phi(x) + (|x|^2 + |v|^2) / (2 dt), split as half kicks
+ * v -= (h/2) dt theta grad Phi(x) around the exact rotation of the Gaussian
+ * part (x, v) -> (cos h x + sin h v, -sin h x + cos h v); accepted with
+ * probability min(1, exp(H(x0, v0) - H(xL, vL))).
+ * orc_hmc_trajectory_linear: the n_leap steps alone for the linear-Gaussian
+ * toy Phi(x) = |G x - y|^2 / (2 sigma^2) (x, v in/out).
+ * orc_hmc_linear_chain: n_iter moves of that toy (as orc_pcnl_linear_chain);
+ * plant ORC_PLANT_HMC_NO_KINETIC (for tests only) leaves the velocities'
+ * energy out of the Metropolis ratio, a mistake that changes the target. */
+void orc_hmc_trajectory_linear(int32_t d, int32_t n_obs, const double *G, const double *y,
+                               double sigma, double theta, double h, int32_t n_leap, double dt,
+                               double *x, double *v);
+int64_t orc_hmc_linear_chain(uint64_t seed, int32_t n_steps, int32_t n_modes, int32_t n_obs,
+                             const double *G, const double *y, double sigma, double theta,
+                             double h, int32_t n_leap, double dt, int32_t n_iter,
+                             const double *x0, double *samples, int32_t plant);
+int orc_jitter_hmc(const orc_model *md, int32_t n_obs, const double *y, const double *sigma,
+                   const orc_rng *rng, int32_t n_particles, int32_t n_steps, const double *m0,
+                   const double *u0, double *dW, double *phi, double *m_end, double *u_end,
+                   double theta, double h, int32_t n_leap, int32_t n_jitter, int32_t *n_accept,
+                   int32_t n_threads);
+int orc_tempered_cycle_hmc(const orc_model *md, int32_t n_obs, const double *y,
+                           const double *sigma, uint64_t seed, uint32_t cycle,
+                           int32_t n_particles, int32_t n_steps, double ess_threshold,
+                           int32_t n_bisect, double h, int32_t n_leap, int32_t n_jitter,
+                           int32_t max_temper, double *m, double *u, orc_cycle_stats *st,
+                           int32_t n_threads);
 
 /* ---- the paper's twin experiments: initialisation and statistics ---- */
 int orc_paper_init_from(int32_t nx, double L, const double *W, double alpha, double beta,

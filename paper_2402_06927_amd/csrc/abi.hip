@@ -198,18 +198,25 @@ int launch_nudge_grad(const sch_model& md, const Tile& tl, const sch_obs& ob, in
   });
 }
 
-// Scratch of the pCN-Langevin jitter: the proposal draws (as pCN), the
+// Scratch of the gradient-based jitters: the proposal draws (as pCN), the
 // adjoint's scratch, the proposal, the gradients at the current state and at
-// the proposal, J, statuses and acceptance counts.
+// the proposal, J, statuses and acceptance counts; for Hybrid Monte Carlo
+// (hmc) also the velocity and a per-particle failure flag, and the leapfrog
+// angle and step count.
 struct PcnlWs {
   double *zeta, *vacc, *v, *gx, *gv, *J;
   int *status, *acc;
   NudgeWs nws;
   int ce;
+  double *vel;
+  int* bad;
+  bool hmc;
+  double h;
+  int n_leap;
 };
 
 PcnlWs carve_pcnl(void* base, int nx, int nq, int n, int ns, int n_jitter, int ce,
-                  size_t* bytes) {
+                  size_t* bytes, bool hmc = false) {
   Carve c(base);
   PcnlWs w{};
   const size_t inc = static_cast<size_t>(n) * ns * nq;
@@ -221,6 +228,11 @@ PcnlWs carve_pcnl(void* base, int nx, int nq, int n, int ns, int n_jitter, int c
   w.J = c.take<double>(n);
   w.status = c.take<int>(n);
   w.acc = c.take<int>(n);
+  if (hmc) {
+    w.vel = c.take<double>(inc);
+    w.bad = c.take<int>(n);
+  }
+  w.hmc = hmc;
   size_t nb = 0;
   carve_nudge(nullptr, false, nx, nq, n, ns, ce, &nb);
   char* nbase = c.take<char>(nb);
@@ -336,6 +348,57 @@ int launch_pcnl(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
     hipLaunchKernelGGL(k_pcnl_accept, dim3(n), dim3(kWave), 0, st, d, rho, md.dt, theta,
                        P.vacc + static_cast<size_t>(j) * n, P.status, P.J, dW, P.gx, phi, P.v,
                        P.gv, acc, j == 0 ? 1 : 0);
+    CHECK_LAUNCH();
+  }
+  if (n_jitter == 0) return SCH_OK;
+  const size_t state = sizeof(double) * static_cast<size_t>(n) * md.nx;
+  HIP_TRY(hipMemcpyAsync(m_end, m0, state, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(u_end, u0, state, hipMemcpyDeviceToDevice, st));
+  return launch_window(md, tl, n, n_steps, m_end, u_end, dW, nullptr, nullptr, nullptr,
+                       iters_acc, st);
+}
+
+// n_jitter Hybrid Monte Carlo moves (pcnl.hpp) of every particle's
+// increments: the draws as pCN (the normals give the velocities), the
+// gradient at the current state, then per move n_leap leapfrog steps, each
+// one adjoint evaluation at its new position, and the Metropolis test; the
+// window ends of the final increments are recomputed as for pCNL.
+int launch_hmc(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t seed,
+               uint32_t cycle, uint32_t temper_k, int n, int n_steps, const double* m0,
+               const double* u0, double* dW, double* phi, double* m_end, double* u_end,
+               const double* theta, int n_jitter, int* n_accept,
+               unsigned long long* iters_acc, const PcnlWs& P, hipStream_t st) {
+  const int Q = md.n_modes, d = n_steps * Q;
+  const int64_t total = static_cast<int64_t>(n) * d;
+  const int gb = grid_for(total, 256);
+  {
+    const int64_t work = static_cast<int64_t>(n_jitter) * n * n_steps * ((Q + 1) / 2);
+    hipLaunchKernelGGL(k_draw_pcn, dim3(grid_for(work, 256)), dim3(256), 0, st, seed,
+                       cycle * static_cast<uint32_t>(n_steps), cycle, temper_k << 16, n_jitter, n,
+                       n_steps, Q, std::sqrt(md.dt), P.zeta, P.vacc);
+    CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.nws.acc, 2);
+  if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, dW, nullptr, P.ce, P.J,
+                                 P.gx, P.status, nullptr, P.nws, st))
+    return rc;
+  hipLaunchKernelGGL(k_pcnl_grad, dim3(gb), dim3(256), 0, st, total, 1.0 / md.dt, dW, P.gx);
+  int* acc = n_accept ? n_accept : P.acc;
+  const double a = (0.5 * P.h) * md.dt, c = std::cos(P.h), s = std::sin(P.h);
+  for (int j = 0; j < n_jitter; ++j) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, P.bad, 0, n);
+    const double* zj = P.zeta + static_cast<size_t>(j) * total;
+    for (int l = 0; l < P.n_leap; ++l) {
+      hipLaunchKernelGGL(k_hmc_step, dim3(gb), dim3(256), 0, st, total, d, l == 0 ? 1 : 0, a,
+                         theta, c, s, dW, P.gx, zj, P.v, P.vel, P.gv, P.status, P.bad);
+      if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, P.v, nullptr, P.ce,
+                                     P.J, P.gv, P.status, nullptr, P.nws, st))
+        return rc;
+      hipLaunchKernelGGL(k_pcnl_grad, dim3(gb), dim3(256), 0, st, total, 1.0 / md.dt, P.v, P.gv);
+    }
+    hipLaunchKernelGGL(k_hmc_accept, dim3(n), dim3(kWave), 0, st, d, a, md.dt, theta,
+                       P.vacc + static_cast<size_t>(j) * n, P.status, P.bad, P.J, dW, P.gx, phi,
+                       P.v, P.gv, P.vel, zj, acc, j == 0 ? 1 : 0);
     CHECK_LAUNCH();
   }
   if (n_jitter == 0) return SCH_OK;
@@ -467,13 +530,22 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
     }
     if (n_jitter > 0 && PW) {
       TimedScope ts(SCH_TK_JITTER, st);
-      if (int r2 = launch_pcnl(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
-                               W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter, nullptr,
-                               W.acc + 2, *PW, st))
-        return r2;
+      if (PW->hmc) {
+        if (int r2 = launch_hmc(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
+                                W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, n_jitter, nullptr,
+                                W.acc + 2, *PW, st))
+          return r2;
+      } else {
+        if (int r2 = launch_pcnl(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
+                                 W.m0, W.u0, W.dW, W.phi, m, u, W.scal + 0, rho, n_jitter,
+                                 nullptr, W.acc + 2, *PW, st))
+          return r2;
+      }
       hipLaunchKernelGGL(k_sum_i32_u64, dim3(1), dim3(256), 0, st, n, PW->acc, W.acc + 1);
-      // forward windows: the gradient at the start, one per proposal, the end-state rerun
-      psteps += static_cast<int64_t>(n) * n_steps * (n_jitter + 2);
+      // forward windows: the gradient at the start, one per proposal (n_leap per HMC
+      // move), the end-state rerun
+      psteps += static_cast<int64_t>(n) * n_steps *
+                (static_cast<int64_t>(n_jitter) * (PW->hmc ? PW->n_leap : 1) + 2);
     } else if (n_jitter > 0) {
       TimedScope ts(SCH_TK_JITTER, st);
       if (int r2 = launch_jitter(md, tl, ob, seed, cycle, static_cast<uint32_t>(k), n, n_steps,
@@ -1343,24 +1415,26 @@ int sch_jitter_pcnl(const sch_model* md, const sch_obs* ob, const sch_rng* rng, 
                      phi, m_end, u_end, theta, rho, n_jitter, n_accept, nullptr, P, S(stream));
 }
 
-int sch_pf_tempered_cycle_pcnl(const sch_model* md, const sch_obs* ob, uint64_t seed,
-                               uint32_t cycle, int32_t n, int32_t n_steps, double thr,
-                               int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
-                               int32_t ckpt_every, double* m, double* u, void* workspace,
-                               sch_cycle_stats* stats, void* stream) {
-  Tile tl;
-  if (int rc = check_model(md, tl)) return rc;
-  if (int rc = check_obs(ob)) return rc;
-  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !workspace || !stats || n_bisect < 0 ||
-      max_temper < 1 || !(rho >= 0 && rho < 1) || n_jitter < 0 || ckpt_every < 1)
-    return fail(SCH_E_ARG, "bad arguments to sch_pf_tempered_cycle_pcnl");
+}  // extern "C"
+
+namespace {
+
+// The tempered cycle with a gradient-based jitter (pCNL, or HMC when hmc):
+// forecast, likelihood, then the tempering loop with those moves.
+int gradient_cycle(const sch_model* md, const Tile& tl, const sch_obs* ob, uint64_t seed,
+                   uint32_t cycle, int32_t n, int32_t n_steps, double thr, int32_t n_bisect,
+                   double rho, int32_t n_jitter, int32_t max_temper, int32_t ckpt_every,
+                   double* m, double* u, void* workspace, sch_cycle_stats* stats, void* stream,
+                   bool hmc, double h, int32_t n_leap) {
   hipStream_t st = S(stream);
   const int nx = md->nx, Q = md->n_modes;
   const size_t state = static_cast<size_t>(n) * nx;
   size_t a = 0;
   CycleWs W = carve_cycle(workspace, SCH_WS_TEMPERED, nx, Q, n, n_steps, &a, 0);
   PcnlWs P = carve_pcnl(static_cast<char*>(workspace) + ((a + 255) & ~size_t(255)), nx, Q, n,
-                        n_steps, n_jitter, ckpt_every, nullptr);
+                        n_steps, n_jitter, ckpt_every, nullptr, hmc);
+  P.h = h;
+  P.n_leap = n_leap;
   *stats = sch_cycle_stats{};
   sch_rng rg{seed, cycle, 0};
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, W.acc, 4);
@@ -1387,6 +1461,80 @@ int sch_pf_tempered_cycle_pcnl(const sch_model* md, const sch_obs* ob, uint64_t 
   }
   return temper_loop(*md, tl, *ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
                      max_temper, m, u, nullptr, W, stats, st, nullptr, &P);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sch_pf_tempered_cycle_pcnl(const sch_model* md, const sch_obs* ob, uint64_t seed,
+                               uint32_t cycle, int32_t n, int32_t n_steps, double thr,
+                               int32_t n_bisect, double rho, int32_t n_jitter, int32_t max_temper,
+                               int32_t ckpt_every, double* m, double* u, void* workspace,
+                               sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !workspace || !stats || n_bisect < 0 ||
+      max_temper < 1 || !(rho >= 0 && rho < 1) || n_jitter < 0 || ckpt_every < 1)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_tempered_cycle_pcnl");
+  return gradient_cycle(md, tl, ob, seed, cycle, n, n_steps, thr, n_bisect, rho, n_jitter,
+                        max_temper, ckpt_every, m, u, workspace, stats, stream, false, 0.0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Gradient-based jitter: Hybrid Monte Carlo moves.
+// ---------------------------------------------------------------------------
+size_t sch_hmc_workspace_bytes(int32_t which, const sch_model* md, int32_t n, int32_t n_steps,
+                               int32_t n_jitter, int32_t ckpt_every) {
+  if (!md || n < 1 || n_steps < 1 || n_jitter < 0 || ckpt_every < 1 ||
+      (which != SCH_WS_JITTER && which != SCH_WS_TEMPERED))
+    return 0;
+  size_t a = 0, b = 0;
+  if (which == SCH_WS_TEMPERED)
+    carve_cycle(nullptr, SCH_WS_TEMPERED, md->nx, md->n_modes, n, n_steps, &a, 0);
+  carve_pcnl(nullptr, md->nx, md->n_modes, n, n_steps, n_jitter, ckpt_every, &b, true);
+  return ((a + 255) & ~size_t(255)) + b;
+}
+
+static bool hmc_ok(double h, int32_t n_leap) {
+  return h > 0.0 && h < 3.14159 && n_leap >= 1 && n_leap <= 64;
+}
+
+int sch_jitter_hmc(const sch_model* md, const sch_obs* ob, const sch_rng* rng, int32_t n,
+                   int32_t n_steps, const double* m0, const double* u0, double* dW, double* phi,
+                   double* m_end, double* u_end, const double* theta, double h, int32_t n_leap,
+                   int32_t n_jitter, int32_t ckpt_every, int32_t* n_accept, void* workspace,
+                   void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (!rng || n < 1 || n > 65535 || n_steps < 1 || !m0 || !u0 || !dW || !phi || !m_end ||
+      !u_end || !theta || !hmc_ok(h, n_leap) || n_jitter < 0 || ckpt_every < 1 ||
+      (n_jitter > 0 && !workspace))
+    return fail(SCH_E_ARG, "bad arguments to sch_jitter_hmc");
+  if (n_jitter == 0) return SCH_OK;
+  PcnlWs P = carve_pcnl(workspace, md->nx, md->n_modes, n, n_steps, n_jitter, ckpt_every,
+                        nullptr, true);
+  P.h = h;
+  P.n_leap = n_leap;
+  return launch_hmc(*md, tl, *ob, rng->seed, rng->cycle, rng->temper_k, n, n_steps, m0, u0, dW,
+                    phi, m_end, u_end, theta, n_jitter, n_accept, nullptr, P, S(stream));
+}
+
+int sch_pf_tempered_cycle_hmc(const sch_model* md, const sch_obs* ob, uint64_t seed,
+                              uint32_t cycle, int32_t n, int32_t n_steps, double thr,
+                              int32_t n_bisect, double h, int32_t n_leap, int32_t n_jitter,
+                              int32_t max_temper, int32_t ckpt_every, double* m, double* u,
+                              void* workspace, sch_cycle_stats* stats, void* stream) {
+  Tile tl;
+  if (int rc = check_model(md, tl)) return rc;
+  if (int rc = check_obs(ob)) return rc;
+  if (n < 1 || n > 65535 || n_steps < 1 || !m || !u || !workspace || !stats || n_bisect < 0 ||
+      max_temper < 1 || !hmc_ok(h, n_leap) || n_jitter < 0 || ckpt_every < 1)
+    return fail(SCH_E_ARG, "bad arguments to sch_pf_tempered_cycle_hmc");
+  return gradient_cycle(md, tl, ob, seed, cycle, n, n_steps, thr, n_bisect, 0.0, n_jitter,
+                        max_temper, ckpt_every, m, u, workspace, stats, stream, true, h, n_leap);
 }
 
 // ---------------------------------------------------------------------------

@@ -186,6 +186,11 @@ def _declare(L):
                                       i32, i32, _vp, _vp, _vp]),
         "sch_pf_tempered_cycle_pcnl": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32,
                                                  i32, i32, _vp, _vp, _vp, ST, _vp]),
+        "sch_hmc_workspace_bytes": (C.c_size_t, [i32, M, i32, i32, i32, i32]),
+        "sch_jitter_hmc": (C.c_int, [M, O, R, i32, i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, f64,
+                                     i32, i32, i32, _vp, _vp, _vp]),
+        "sch_pf_tempered_cycle_hmc": (C.c_int, [M, O, u64, u32, i32, i32, f64, i32, f64, i32, i32,
+                                                i32, i32, _vp, _vp, _vp, ST, _vp]),
         "sch_ensemble_stats": (C.c_int, [i32, i32, _vp, _vp, _vp, _vp, _vp]),
         "sch_nudge_grad_matern": (C.c_int, [M, MT, O, i32, i32, _vp, _vp, _vp, _vp, i32, _vp,
                                             _vp, _vp, _vp, _vp]),
@@ -224,6 +229,7 @@ def exported_names():
         "sch_matern_workspace_bytes", "sch_jitter_pcn_matern", "sch_pf_tempered_cycle_matern",
         "sch_pf_bootstrap_cycle_matern", "sch_paper_init", "sch_ensemble_stats",
         "sch_pcnl_workspace_bytes", "sch_jitter_pcnl", "sch_pf_tempered_cycle_pcnl",
+        "sch_hmc_workspace_bytes", "sch_jitter_hmc", "sch_pf_tempered_cycle_hmc",
         "sch_nudge_grad_matern", "sch_nudge_run_matern", "sch_nudged_workspace_bytes_matern",
         "sch_pf_nudged_cycle_matern", "sch_jitter_pcn_matern_ctrl",
     ]
@@ -720,6 +726,65 @@ def sch_pf_tempered_cycle_pcnl(model: Model, obs: Obs, seed: int, cycle: int, m:
                                             _dev(u, name="u"),
                                             _dev(workspace, torch.uint8, "workspace"),
                                             C.byref(st), _stream()))
+    return st.as_dict()
+
+
+# --------------------------------------------------------------------------- Hybrid Monte Carlo
+def hmc_workspace(which: int, model: Model, n_particles: int, n_steps: int, n_jitter: int,
+                  ckpt_every: int = 8, device="cuda") -> torch.Tensor:
+    return torch.empty(hmc_workspace_bytes(which, model, n_particles, n_steps, n_jitter,
+                                           ckpt_every), dtype=torch.uint8, device=device)
+
+
+def hmc_workspace_bytes(which: int, model: Model, n_particles: int, n_steps: int,
+                        n_jitter: int, ckpt_every: int = 8) -> int:
+    mc = model.c()
+    nb = int(lib().sch_hmc_workspace_bytes(which, C.byref(mc), n_particles, n_steps, n_jitter,
+                                           ckpt_every))
+    if nb <= 0:
+        raise SchError(SCH_E_ARG, "invalid workspace request")
+    return nb
+
+
+def sch_jitter_hmc(model: Model, obs: Obs, seed: int, cycle: int, temper_k: int,
+                   m0: torch.Tensor, u0: torch.Tensor, dW: torch.Tensor, phi: torch.Tensor,
+                   m_end: torch.Tensor, u_end: torch.Tensor, theta: torch.Tensor, h: float,
+                   n_leap: int, n_jitter: int, ckpt_every: int = 8,
+                   n_accept: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    mc, oc = model.c(), obs.c()
+    r = SchRngC(seed, cycle, temper_k)
+    n, s = dW.shape[0], dW.shape[1]
+    _state(model, n, m0=m0, u0=u0, m_end=m_end, u_end=u_end)
+    _inc(n, s, model.n_modes, dW=dW)
+    _vec(n, phi=phi, n_accept=n_accept)
+    _at_least(theta, 1, "theta")
+    if workspace is None:
+        workspace = hmc_workspace(WS_JITTER, model, n, s, n_jitter, ckpt_every)
+    _ws(workspace, hmc_workspace_bytes(WS_JITTER, model, n, s, n_jitter, ckpt_every))
+    _check(lib().sch_jitter_hmc(C.byref(mc), C.byref(oc), C.byref(r), n, s, _dev(m0, name="m0"),
+                                _dev(u0, name="u0"), _dev(dW, name="dW"), _dev(phi, name="phi"),
+                                _dev(m_end, name="m_end"), _dev(u_end, name="u_end"),
+                                _dev(theta, name="theta"), h, n_leap, n_jitter, ckpt_every,
+                                _dev(n_accept, torch.int32, "n_accept"),
+                                _dev(workspace, torch.uint8, "workspace"), _stream()))
+
+
+def sch_pf_tempered_cycle_hmc(model: Model, obs: Obs, seed: int, cycle: int, m: torch.Tensor,
+                              u: torch.Tensor, n_steps: int, ess_threshold: float,
+                              n_bisect: int, h: float, n_leap: int, n_jitter: int,
+                              max_temper: int, workspace: torch.Tensor,
+                              ckpt_every: int = 8) -> dict:
+    mc, oc = model.c(), obs.c()
+    n = m.shape[0]
+    _state(model, n, m=m, u=u)
+    _ws(workspace, hmc_workspace_bytes(WS_TEMPERED, model, n, n_steps, n_jitter, ckpt_every))
+    st = SchCycleStats()
+    _check(lib().sch_pf_tempered_cycle_hmc(C.byref(mc), C.byref(oc), seed, cycle, m.shape[0],
+                                           n_steps, ess_threshold, n_bisect, h, n_leap, n_jitter,
+                                           max_temper, ckpt_every, _dev(m, name="m"),
+                                           _dev(u, name="u"),
+                                           _dev(workspace, torch.uint8, "workspace"),
+                                           C.byref(st), _stream()))
     return st.as_dict()
 
 

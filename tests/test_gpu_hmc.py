@@ -1,0 +1,135 @@
+"""GPU (C-ABI) versus oracle for the Hybrid Monte Carlo jitter (leapfrog
+trajectories with the adjoint gradient) and the tempered cycle that uses it.
+
+Bars: identical acceptance counts and tempering steps; increments,
+potentials and window-end states at relative L2 1e-10 (each trajectory
+carries n_leap adjoint gradients, which both sides compute to about 1e-12)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import pairing as PR
+from paper_2402_06927_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sch():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_06927_amd import sch as S
+
+    S.lib()
+    return S
+
+
+def T(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("nx,n,q,s,ce,h", [(100, 7, 4, 6, 2, 0.6), (600, 5, 8, 5, 8, 0.3)])
+def test_jitter_hmc_parity(sch, nx, n, q, s, ce, h):
+    _say("hmc jitter", nx, n, q, s, ce, h)
+    sig, L = 0.002, 3
+    wl = W.TEMPERED_4096.scaled(nx=nx, n_modes=q, n_steps=s, n_obs=40, sigma_obs=sig)
+    om, gm = PR.oracle_model(wl), PR.gpu_model(wl)
+    u0, m0, ut, _ = PR.prior(wl, n)
+    dW = O.draw_increments(wl.seed, n, s, q, 0, O.TAG_FORECAST, 0, wl.dt)
+    _, m1, u1, _, _ = O.ensemble_window(om, m0, u0, dW)
+    y = O.observe(ut, 40) + sig * W.random_state_noise(40, 3)
+    sg = np.full(40, sig)
+    phi = O.ensemble_nll(u1, y, sg)
+    rc, rdW, rphi, rme, rue, racc = O.jitter_hmc(om, y, sg, wl.seed, 2, 3, m0, u0, dW, phi, 1.0,
+                                                 h, L, 4)
+    assert rc == 0 and 0 < racc.sum() < 4 * n
+    gdW, gphi = T(dW), T(phi)
+    gme, gue = torch.zeros_like(T(m0)), torch.zeros_like(T(u0))
+    acc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    sch.sch_jitter_hmc(gm, sch.Obs(T(y), T(sg)), wl.seed, 2, 3, T(m0), T(u0), gdW, gphi, gme, gue,
+                       T([1.0]), h, L, 4, ce, acc)
+    _say("accepted", N(acc).tolist(), racc.tolist())
+    assert np.array_equal(N(acc), racc)
+    assert PR.rel_l2(N(gdW), rdW) < PR.REL_TOL
+    assert PR.rel_l2(N(gphi), rphi) < PR.REL_TOL
+    assert PR.rel_l2(N(gme), rme) < PR.REL_TOL and PR.rel_l2(N(gue), rue) < PR.REL_TOL
+
+
+def test_jitter_hmc_at_theta_zero_is_pcn(sch):
+    """theta = 0: every move is the rotation by n_leap h, i.e. the pCN move
+    with rho = cos(n_leap h) on the same normals (every proposal accepted)."""
+    import math
+
+    wl = W.TEMPERED_4096.scaled(nx=100, n_modes=4, n_steps=5, n_obs=40, sigma_obs=0.01)
+    gm = PR.gpu_model(wl)
+    n, s, q, h, L = 6, wl.n_steps, wl.n_modes, 0.2, 3
+    u0, m0, ut, _ = PR.prior(wl, n)
+    dW = O.draw_increments(wl.seed, n, s, q, 0, O.TAG_FORECAST, 0, wl.dt)
+    obs = sch.Obs(T(O.observe(ut, 40)), T(np.full(40, 0.01)))
+    phi = T(np.full(n, 1.0))
+    res = {}
+    for kind in ("hmc", "pcn"):
+        gdW, gphi = T(dW), phi.clone()
+        me, ue = torch.zeros_like(T(m0)), torch.zeros_like(T(u0))
+        acc = torch.zeros(n, dtype=torch.int32, device="cuda")
+        if kind == "hmc":
+            sch.sch_jitter_hmc(gm, obs, wl.seed, 1, 2, T(m0), T(u0), gdW, gphi, me, ue, T([0.0]),
+                               h, L, 3, 4, acc)
+        else:
+            sch.sch_jitter_pcn(gm, obs, wl.seed, 1, 2, T(m0), T(u0), gdW, gphi, me, ue, T([0.0]),
+                               math.cos(L * h), 3, acc)
+        res[kind] = (N(gdW), N(acc))
+    assert np.all(res["hmc"][1] == 3) and np.all(res["pcn"][1] == 3)
+    np.testing.assert_allclose(res["hmc"][0], res["pcn"][0], rtol=0, atol=1e-14)
+
+
+def test_tempered_cycle_hmc_parity(sch):
+    """Two tempered cycles with HMC jitter: nx = 128, 16 particles, 4 modes,
+    6 steps, 32 observations (sigma 0.01), 3 moves of 3 leapfrog steps of
+    angle 0.5."""
+    wl = W.BOOTSTRAP_256.scaled(nx=128, n_particles=16, n_steps=6, n_obs=32, sigma_obs=0.01)
+    om, gm = PR.oracle_model(wl), PR.gpu_model(wl)
+    n, h, L = wl.n_particles, 0.5, 3
+    u0, m0, _, _ = PR.prior(wl, n)
+    ys = PR.oracle_observations(wl, 2)
+    sg = np.full(wl.n_obs, wl.sigma_obs)
+    m_o, u_o = m0.copy(), u0.copy()
+    m, u = T(m0), T(u0)
+    ws = sch.hmc_workspace(sch.WS_TEMPERED, gm, n, wl.n_steps, 3, 4)
+    for c in range(2):
+        _say("hmc tempered cycle", c)
+        rc, m_o, u_o, st_o = O.tempered_cycle_hmc(om, ys[c], sg, wl.seed, c, m_o, u_o,
+                                                  wl.n_steps, n / 2, 50, h, L, 3, 100)
+        assert rc == 0
+        st = sch.sch_pf_tempered_cycle_hmc(gm, sch.Obs(T(ys[c]), T(sg)), wl.seed, c, m, u,
+                                           wl.n_steps, n / 2, 50, h, L, 3, 100, ws, 4)
+        assert st["n_temper"] == st_o.n_temper and st_o.n_temper >= 2
+        assert st["n_accept"] == st_o.n_accept
+        assert st["particle_steps"] == n * wl.n_steps * (1 + st["n_temper"] * (3 * L + 2))
+        assert PR.rel_l2(N(m), m_o) < PR.REL_TOL, c
+        assert PR.rel_l2(N(u), u_o) < PR.REL_TOL, c
+
+
+def test_hmc_argument_errors(sch):
+    wl = W.BOOTSTRAP_256.scaled(nx=128)
+    gm = PR.gpu_model(wl)
+    n, s, q = 2, 3, wl.n_modes
+    z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+    obs = sch.Obs(z(4) + 1.0, z(4) + 1.0)
+    for h, L in ((0.0, 3), (0.2, 0), (3.2, 2)):
+        with pytest.raises(sch.SchError, match="bad arguments"):
+            sch.sch_jitter_hmc(gm, obs, 1, 0, 0, z(n, wl.nx), z(n, wl.nx), z(n, s, q), z(n),
+                               z(n, wl.nx), z(n, wl.nx), z(1), h, L, 2, 4)
+    assert sch.lib().sch_hmc_workspace_bytes(sch.WS_BOOTSTRAP, None, n, s, 2, 4) == 0
