@@ -84,6 +84,9 @@ TRAFFIC_JITTER_MATERN_BYTES = (5684638.09375 * 2.0 + 7861150.828125 * 1.0) * 102
 TRAFFIC_THREADS = 256
 # checkpoint interval of the adjoint passes of the pCN-Langevin jitter
 PCNL_CKPT = 8
+# Hybrid Monte Carlo jitter of the bench: leapfrog angle and steps per move
+HMC_H = 0.5
+HMC_LEAP = 3
 TRAFFIC_SOURCES_HASH = "6f519fc322d21564"
 
 
@@ -899,13 +902,14 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the ensemble size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--workload", choices=("tempered", "matern", "pcnl", "paper", "nudging",
-                                           "nudging_matern", "nudged_matern",
+    ap.add_argument("--workload", choices=("tempered", "matern", "pcnl", "hmc", "paper",
+                                           "nudging", "nudging_matern", "nudged_matern",
                                            "nudged", "warmstart", "mlp", "batch"),
                     default="tempered",
                     help="tempered: the headline filter; matern: the same filter with the "
                          "Matern-type noise of section 2; pcnl: the same filter with "
-                         "gradient-based (pCN-Langevin) jitter; paper: the paper's twin experiment "
+                         "gradient-based (pCN-Langevin) jitter; hmc: the same filter with Hybrid "
+                         "Monte Carlo jitter; paper: the paper's twin experiment "
                          "(--exp 1 or 2); nudging: one nudged window; nudging_matern: the same "
                          "with the Matern-type noise and one control per cell; "
                          "nudged: the nudged filter (nudging, tempering, jittering); nudged_matern: "
@@ -963,7 +967,8 @@ def main():
         sys.exit(2)
     sch.lib()
     matern = args.workload == "matern"
-    pcnl = args.workload == "pcnl"
+    hmc = args.workload == "hmc"
+    pcnl = args.workload == "pcnl" or hmc
     wl = W.MATERN_4096 if matern else W.TEMPERED_4096
     mtn = sch.Matern(wl.kappa, wl.eta, wl.k_solves) if matern else None
     if args.particles:
@@ -1000,6 +1005,8 @@ def main():
     sigma = torch.full((wl.n_obs,), wl.sigma_obs, dtype=torch.float64, device=dev)
     if matern:
         ws = sch.matern_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter)
+    elif hmc:
+        ws = sch.hmc_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter, PCNL_CKPT)
     elif pcnl:
         ws = sch.pcnl_workspace(sch.WS_TEMPERED, model, n, S, wl.n_jitter, PCNL_CKPT)
     else:
@@ -1019,6 +1026,10 @@ def main():
             return sch.sch_pf_tempered_cycle_matern(model, mtn, obs, wl.seed, c, m, u, S,
                                                     wl.ess_threshold, wl.n_bisect, wl.rho,
                                                     wl.n_jitter, wl.max_temper, ws)
+        if hmc:
+            return sch.sch_pf_tempered_cycle_hmc(model, obs, wl.seed, c, m, u, S,
+                                                 wl.ess_threshold, wl.n_bisect, HMC_H, HMC_LEAP,
+                                                 wl.n_jitter, wl.max_temper, ws, PCNL_CKPT)
         if pcnl:
             return sch.sch_pf_tempered_cycle_pcnl(model, obs, wl.seed, c, m, u, S,
                                                   wl.ess_threshold, wl.n_bisect, wl.rho,
@@ -1101,7 +1112,10 @@ def main():
                    "rerun + likelihood + accept)" if matern else
                    "pCN-Langevin stage (k_nudge_grad x (moves + 1), proposals, accepts, "
                    "end-state window); achieved counts the end-state window only (lower bound)"
-                   if pcnl else
+                   if pcnl and not hmc else
+                   "Hybrid Monte Carlo stage (k_nudge_grad x (moves x leapfrog steps + 1), kicks "
+                   "and rotations, accepts, end-state window); achieved counts the end-state "
+                   "window only (lower bound)" if hmc else
                    "k_jitter (fused pCN proposal + window rerun + likelihood + accept)"),
         "avg_launch_ms": round(j_ms, 3),
         "algorithmic_flops_per_launch": j_flops / j_launches,
@@ -1118,7 +1132,12 @@ def main():
     if matern:
         del config["n_modes"]
         config.update(noise="matern", kappa=wl.kappa, eta=wl.eta, k_solves=wl.k_solves)
-    if pcnl:
+    if hmc:
+        del config["rho"]
+        config.update(jitter="hybrid-monte-carlo", h=HMC_H, n_leap=HMC_LEAP,
+                      ckpt_every=PCNL_CKPT)
+        config["workload"] = wl.name + "_hmc"
+    elif pcnl:
         config.update(jitter="pcn-langevin", ckpt_every=PCNL_CKPT)
         config["workload"] = wl.name + "_pcnl"
     out = {
