@@ -110,8 +110,9 @@ __device__ __forceinline__ void advect_t(const double (&s)[PMAX], double sl, dou
 // gdU receives dJ/d(dU^n).  (ma, ua) is the state before the step, (mb, ub)
 // after it; noise(0, dv) adds the step's noise field dU^n.  Where the window's two
 // LDS arrays exist (free during the reverse sweep), s and lambda_{n+1}, which
-// the fixed-point loop only reads, wait there instead of in registers.
-template <int PMAX, int NT, bool FULL, class NoiseF>
+// the fixed-point loop only reads, wait there instead of in registers.  PWT
+// selects the table form of the Helmholtz solves (solve_helm).
+template <int PMAX, int NT, bool FULL, bool PWT, class NoiseF>
 __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF noise,
                             const double* ma, const double* ua, const double* mb,
                             const double* ub, double (&lam)[PMAX], double (&gdU)[PMAX],
@@ -221,8 +222,8 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF nois
     // M H^{-1} w = H^{-1} M w (the two circulants commute): the mass product
     // folded into the scan form; the bordering values are not used
     double zL, zR, g0, g1, g2;
-    solve_helm<PMAX, NT, FULL, true>(K, w, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1,
-                                     g2, 0.0, 0.0);
+    solve_helm<PMAX, NT, FULL, true, PWT>(K, w, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0,
+                                          g1, g2, 0.0, 0.0);
     par.slot ^= 1;
     const double q = 0.25 * P.dt;
 #pragma unroll
@@ -308,7 +309,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     store_state<PMAX, FULL>(ck + static_cast<size_t>(c) * 2 * nx, nx, ch, m, u);
     if (last) store_state<PMAX, FULL>(sg, nx, ch, m, u);
     for (int n = n0; n < n1 && st == SCH_OK; ++n) {
-      st = run_window<PMAX, NT, FULL>(A.P, K, step_noise(n), 1, m, u, ch, L, X, t, par, fit);
+      st = run_window<PMAX, NT, FULL, true, MATERN>(A.P, K, step_noise(n), 1, m, u, ch, L, X, t,
+                                                    par, fit);
       if (last) store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
     }
   }
@@ -333,8 +335,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
       double w[PMAX], zL, zR, g0, g1, g2;
       obs_adjoint<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, w, L, t, par.hs);
       // M H^{-1} w as H^{-1} M w (the bordering values are not used)
-      solve_helm<PMAX, NT, FULL, true>(K, w, lam, zL, zR, ch.cnt, L, par.slot, t, 0.0, 0.0, 0.0,
-                                       g0, g1, g2, 0.0, 0.0);
+      solve_helm<PMAX, NT, FULL, true, MATERN>(K, w, lam, zL, zR, ch.cnt, L, par.slot, t, 0.0, 0.0,
+                                               0.0, g0, g1, g2, 0.0, 0.0);
       par.slot ^= 1;
     }
     const int lane = t & (kWave - 1), wv = t / kWave;
@@ -345,7 +347,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         load_chunk<PMAX, FULL>(ck + static_cast<size_t>(c) * 2 * nx + nx, ch, u);
         store_state<PMAX, FULL>(sg, nx, ch, m, u);
         for (int n = n0; n < n1 && st == SCH_OK; ++n) {
-          st = run_window<PMAX, NT, FULL>(A.P, K, step_noise(n), 1, m, u, ch, L, X, t, par, fit);
+          st = run_window<PMAX, NT, FULL, true, MATERN>(A.P, K, step_noise(n), 1, m, u, ch, L, X,
+                                                        t, par, fit);
           store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
         }
       }
@@ -353,8 +356,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         const double* sa = sg + static_cast<size_t>(n - n0) * 2 * nx;
         const double* sb = sa + 2 * nx;
         double gdU[PMAX];
-        st = adjoint_step<PMAX, NT, FULL>(A.P, K, step_noise(n), sa, sa + nx, sb, sb + nx, lam,
-                                          gdU, ch, L, X, t, par, ait);
+        st = adjoint_step<PMAX, NT, FULL, MATERN>(A.P, K, step_noise(n), sa, sa + nx, sb, sb + nx,
+                                                  lam, gdU, ch, L, X, t, par, ait);
         if (n >= CS) continue;
         if constexpr (MATERN) {
           double gc[PMAX];

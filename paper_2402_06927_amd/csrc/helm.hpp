@@ -33,6 +33,10 @@ struct HelmConst {
   // mg = gamma coef and mf = beta - gamma coef (the scan form below).
   double mg, mf;
   double mh6, mh23;  // h/6 and 2h/3
+  // rb^e for e = 0..64, formed on the host by the same binary powering as
+  // the solve's own (the products rb^(2^i) in increasing i): the PWT solves
+  // read the lane scans' factors from this table
+  double pwt[65];
 };
 
 // Composition of affine carries: apply (m1, c1) then (m2, c2).
@@ -82,7 +86,15 @@ __device__ __forceinline__ void record_scan(double& f0, double& f1, double& b0, 
 
 // MASS: u = H^{-1} M f instead of H^{-1} f, with fl, fr the values of f at
 // the nodes bordering the chunk (for the bordering values of u).
-template <int PMAX, int NT, bool FULL, bool MASS = false, class LT>
+// PWT (full chunks): the lane scans' powers of r^PMAX are loaded from K.pwt
+// at every call instead of being formed per lane.  Formed powers are loop
+// invariants that the compiler hoists out of the caller's loops into
+// registers; where registers are short (the kernels with the Matern-type
+// noise, which also hold that operator's powers) they are spilled and
+// reloaded from scratch every iteration, and loading them from the table
+// is cheaper.  Elsewhere forming them costs fewer instructions.  Both give
+// the same bits.
+template <int PMAX, int NT, bool FULL, bool MASS = false, bool PWT = false, class LT>
 __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)[PMAX],
                                            double (&u)[PMAX], double& uL, double& uR, int cnt,
                                            LT& L, int slot, int t, double red0, double red1,
@@ -109,9 +121,22 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   if constexpr (FULL) {
     // Every chunk has PMAX rows, so the factor of any run of lanes is a
     // power of r^PMAX: only the offsets need cross-lane steps.
-    const double rb = K.rb, rb2 = rb * rb, rb4 = rb2 * rb2, rb8 = rb4 * rb4, rb16 = rb8 * rb8,
-                 rb32 = rb16 * rb16, rb64 = rb32 * rb32;
+    const double* pt = K.pwt;
+    int ln = lane;
+    if constexpr (PWT) {
+      // opaque indices keep the loads at the call (scalar loads for the
+      // uniform powers, four vector loads of the table for the per-lane ones)
+      int z = 0;
+      asm volatile("" : "+s"(z));
+      pt += z;
+      asm volatile("" : "+v"(ln));
+    }
+    const double rb = PWT ? pt[1] : K.rb, rb2 = PWT ? pt[2] : rb * rb,
+                 rb4 = PWT ? pt[4] : rb2 * rb2, rb8 = PWT ? pt[8] : rb4 * rb4,
+                 rb16 = PWT ? pt[16] : rb8 * rb8, rb32 = rb16 * rb16,
+                 rb64 = PWT ? pt[64] : rb32 * rb32;
     auto pw = [&](int e) {  // rb^e, 0 <= e <= 64
+      if constexpr (PWT) return pt[e];
       double p = (e & 1) ? rb : 1.0;
       p *= (e & 2) ? rb2 : 1.0;
       p *= (e & 4) ? rb4 : 1.0;
@@ -120,7 +145,7 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
       p *= (e & 32) ? rb32 : 1.0;
       return (e & 64) ? p * rb64 : p;
     };
-    const int i16 = lane & 15;
+    const int i16 = ln & 15;
     fc = fma(rb, dpp_f64z<kDppRowShr + 1>(fc), fc);
     fc = fma(rb2, dpp_f64z<kDppRowShr + 2>(fc), fc);
     fc = fma(rb4, dpp_f64z<kDppRowShr + 4>(fc), fc);
@@ -141,9 +166,9 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
       const double hc = row == 3 ? 0.0 : row == 2 ? t3c : row == 1 ? h1c : h0c;
       bc = fma(pw(16 - i16), hc, bc);
     }
-    xfm = pw(lane);
+    xfm = pw(ln);
     xfc = dpp_f64z<kDppWaveShr1>(fc);
-    xbm = pw(kWave - 1 - lane);
+    xbm = pw(kWave - 1 - ln);
     xbc = dpp_f64z<kDppWaveShl1>(bc);
     tfm = rb64;
     tfc = readlane_f64(fc, kWave - 1);

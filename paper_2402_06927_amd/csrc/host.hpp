@@ -99,6 +99,18 @@ inline HelmConst make_helm_op(double h, int nx, double a2, const Tile& tl) {
   const double beta = K.mh6 / K.ho, gamma = K.mh23 - beta * K.hd;
   K.mg = gamma * K.coef;
   K.mf = beta - K.mg;
+  // powers of rb in the order the scan form's lane factors are built
+  const double rb2 = K.rb * K.rb, rb4 = rb2 * rb2, rb8 = rb4 * rb4, rb16 = rb8 * rb8,
+               rb32 = rb16 * rb16, rb64 = rb32 * rb32;
+  for (int e = 0; e <= 64; ++e) {
+    double p = (e & 1) ? K.rb : 1.0;
+    p *= (e & 2) ? rb2 : 1.0;
+    p *= (e & 4) ? rb4 : 1.0;
+    p *= (e & 8) ? rb8 : 1.0;
+    p *= (e & 16) ? rb16 : 1.0;
+    p *= (e & 32) ? rb32 : 1.0;
+    K.pwt[e] = (e & 64) ? p * rb64 : p;
+  }
   return K;
 }
 

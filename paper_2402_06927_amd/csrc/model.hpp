@@ -123,7 +123,8 @@ __device__ __forceinline__ void matern_add(const MaternDev& M, const double (&w)
       if (!bordered) halo<PMAX, NT, FULL>(U, cnt, L, t, hl, hr, par.hs);
       mass_apply_h<PMAX, FULL>(U, r, M.h, cnt, hl, hr, 1.0);
     }
-    solve_helm<PMAX, NT, FULL>(M.K, r, U, uL, uR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1, g2);
+    solve_helm<PMAX, NT, FULL, false, true>(M.K, r, U, uL, uR, cnt, L, par.slot, t, 0.0, 0.0, 0.0,
+                                            g0, g1, g2);
     par.slot ^= 1;
   }
 #pragma unroll
@@ -152,7 +153,8 @@ __device__ __forceinline__ void matern_transpose(const MaternDev& M, const doubl
       if (!bordered) halo<PMAX, NT, FULL>(z, cnt, L, t, hl, hr, par.hs);
       mass_apply_h<PMAX, FULL>(z, r, M.h, cnt, hl, hr, 1.0);
     }
-    solve_helm<PMAX, NT, FULL>(M.K, r, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0, g0, g1, g2);
+    solve_helm<PMAX, NT, FULL, false, true>(M.K, r, z, zL, zR, cnt, L, par.slot, t, 0.0, 0.0, 0.0,
+                                            g0, g1, g2);
     par.slot ^= 1;
   }
   double hl = zL, hr = zR;
@@ -184,8 +186,10 @@ __device__ __forceinline__ void matern_transpose(const MaternDev& M, const doubl
 // the last iterate is kept, on a non-finite iterate or a system whose
 // elimination growth exceeds kMaxGrowth (SCH_E_UNSTABLE) the step's input is
 // kept (KEEP) or the state is left undefined (!KEEP, for callers that discard
-// a failed window: u^n then need not stay live through the iteration).
-template <int PMAX, int NT, bool FULL, bool KEEP = true, class NoiseF>
+// a failed window: u^n then need not stay live through the iteration).  PWT
+// selects the table form of the Helmholtz solve (solve_helm), which the
+// kernels with the Matern-type noise take.
+template <int PMAX, int NT, bool FULL, bool KEEP = true, bool PWT = false, class NoiseF>
 __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise, int n_steps,
                           double (&m)[PMAX], double (&u)[PMAX], const Chunk& ch, RowLds<NT>& L,
                           AuxLds<PMAX, NT>& X, int t, Parity& par, int& iters) {
@@ -311,8 +315,8 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
       // the growth test rides on the Helmholtz record as a wave-uniform flag
       const double wbad = __any(!(grow <= kMaxGrowth)) ? 1.0 : 0.0;
       double gdiff, gscale, gbad;
-      solve_helm<PMAX, NT, FULL, true>(K, ms, us, uL, uR, cnt, L, par.slot, t, diff, scale, wbad,
-                                       gdiff, gscale, gbad, sl - mL, sr - mR);
+      solve_helm<PMAX, NT, FULL, true, PWT>(K, ms, us, uL, uR, cnt, L, par.slot, t, diff, scale,
+                                            wbad, gdiff, gscale, gbad, sl - mL, sr - mR);
       par.slot ^= 1;
       if (gbad > 0.0) {
         status = SCH_E_UNSTABLE;
@@ -458,7 +462,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
       load_chunk<PMAX, FULL>(cells + static_cast<size_t>(n) * nx, ch, w);
       matern_add<PMAX, NT, FULL>(A.M, w, e, ch, L, t, par);
     };
-    st = run_window<PMAX, NT, FULL>(A.P, K, noise, A.n_steps, m, u, ch, L, X, t, par, iters);
+    st = run_window<PMAX, NT, FULL, true, true>(A.P, K, noise, A.n_steps, m, u, ch, L, X, t, par,
+                                                iters);
   } else {
     const int Q = A.P.n_modes;
     const double* dW = A.dW + static_cast<size_t>(p) * A.n_steps * Q;
@@ -633,7 +638,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
           }
         matern_add<PMAX, NT, FULL>(A.M, w, e, ch, L, t, par);
       };
-      st = run_window<PMAX, NT, FULL, false>(A.P, K, noise, S, m, u, ch, L, X, t, par, iters);
+      st = run_window<PMAX, NT, FULL, false, true>(A.P, K, noise, S, m, u, ch, L, X, t, par, iters);
     } else {
       auto inc = [&](int n, int q) {
         double w = prop[n * Q + q];
