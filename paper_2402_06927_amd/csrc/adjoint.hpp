@@ -262,6 +262,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   __shared__ RowLds<NT> L;
   __shared__ AuxLds<PMAX, NT> X;
   __shared__ double gpart[MATERN ? 1 : 64][MATERN ? 1 : NT / kWave];
+  // the table form of the Helmholtz solves where registers are short (the
+  // Matern-type noise, 16-node chunks)
+  constexpr bool PWT = MATERN || PMAX >= 16;
   const int p = blockIdx.x, t = threadIdx.x;
   if (A.active && A.active[p] == 0) return;  // whole workgroup
   const int nx = A.P.nx, Q = A.P.n_modes, S = A.n_steps, CS = A.ctrl_steps;
@@ -309,7 +312,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     store_state<PMAX, FULL>(ck + static_cast<size_t>(c) * 2 * nx, nx, ch, m, u);
     if (last) store_state<PMAX, FULL>(sg, nx, ch, m, u);
     for (int n = n0; n < n1 && st == SCH_OK; ++n) {
-      st = run_window<PMAX, NT, FULL, true, MATERN>(A.P, K, step_noise(n), 1, m, u, ch, L, X, t,
+      st = run_window<PMAX, NT, FULL, true, PWT>(A.P, K, step_noise(n), 1, m, u, ch, L, X, t,
                                                     par, fit);
       if (last) store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
     }
@@ -335,7 +338,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
       double w[PMAX], zL, zR, g0, g1, g2;
       obs_adjoint<PMAX, NT, FULL>(u, ch, nx, A.n_obs, A.y, A.sigma, w, L, t, par.hs);
       // M H^{-1} w as H^{-1} M w (the bordering values are not used)
-      solve_helm<PMAX, NT, FULL, true, MATERN>(K, w, lam, zL, zR, ch.cnt, L, par.slot, t, 0.0, 0.0,
+      solve_helm<PMAX, NT, FULL, true, PWT>(K, w, lam, zL, zR, ch.cnt, L, par.slot, t, 0.0, 0.0,
                                                0.0, g0, g1, g2, 0.0, 0.0);
       par.slot ^= 1;
     }
@@ -347,7 +350,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         load_chunk<PMAX, FULL>(ck + static_cast<size_t>(c) * 2 * nx + nx, ch, u);
         store_state<PMAX, FULL>(sg, nx, ch, m, u);
         for (int n = n0; n < n1 && st == SCH_OK; ++n) {
-          st = run_window<PMAX, NT, FULL, true, MATERN>(A.P, K, step_noise(n), 1, m, u, ch, L, X,
+          st = run_window<PMAX, NT, FULL, true, PWT>(A.P, K, step_noise(n), 1, m, u, ch, L, X,
                                                         t, par, fit);
           store_state<PMAX, FULL>(sg + static_cast<size_t>(n - n0 + 1) * 2 * nx, nx, ch, m, u);
         }
@@ -356,7 +359,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         const double* sa = sg + static_cast<size_t>(n - n0) * 2 * nx;
         const double* sb = sa + 2 * nx;
         double gdU[PMAX];
-        st = adjoint_step<PMAX, NT, FULL, MATERN>(A.P, K, step_noise(n), sa, sa + nx, sb, sb + nx,
+        st = adjoint_step<PMAX, NT, FULL, PWT>(A.P, K, step_noise(n), sa, sa + nx, sb, sb + nx,
                                                   lam, gdU, ch, L, X, t, par, ait);
         if (n >= CS) continue;
         if constexpr (MATERN) {
