@@ -48,12 +48,15 @@ struct GemmArgs {
 
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 8;  // LDS rows of 80 bytes
 
-// Epilogue and matrix-core steps shared by both loaders.
-__device__ __forceinline__ void gemm_chunk(const uint16_t (&As)[kGM][kGK + kGPad],
-                                           const uint16_t (&Bs)[kGN][kGK + kGPad], int wm,
+// Epilogue and matrix-core steps shared by both loaders: a chunk of KC
+// values of k in steps of 16 (the sums run over k in the same order for any
+// chunk width).
+template <int KC>
+__device__ __forceinline__ void gemm_chunk(const uint16_t (&As)[kGM][KC + kGPad],
+                                           const uint16_t (&Bs)[kGN][KC + kGPad], int wm,
                                            int wn, int lane, f32x4 (&acc)[2][2]) {
 #pragma unroll
-  for (int ks = 0; ks < kGK; ks += 16) {
+  for (int ks = 0; ks < KC; ks += 16) {
     bf16x4 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -115,53 +118,201 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmArgs g) {
       Bs[nn][kb] = (gn < g.N && gkb < g.K) ? g.B[gkb * g.sbk + gn * g.sbn] : uint16_t(0);
     }
     __syncthreads();
-    gemm_chunk(As, Bs, wm, wn, lane, acc);
+    gemm_chunk<kGK>(As, Bs, wm, wn, lane, acc);
     __syncthreads();
   }
   gemm_store(g, m0, n0, wm, wn, lane, acc);
 }
 
 // Both operands contiguous along K (sak = sbk = 1), K, sam, sbn multiples of 8
-// and 16-byte aligned rows: each thread moves 8 bf16 of A and of B per chunk
-// with one 16-byte load each, and the next chunk is fetched into registers
-// while the matrix cores work on the current one.
+// and 16-byte aligned rows.  K advances in chunks of KC staged in LDS, each
+// thread moving KC / 32 segments of 8 bf16 of A and of B per chunk with
+// 16-byte loads (a wavefront's load covers 256 / KC * 4 rows of whole
+// 2 KC-byte spans).  With one workgroup per compute unit (the large products
+// have only about as many tiles as the chip has units) every chunk pays a
+// serial chain of LDS stores, a barrier, LDS reads and dependent matrix-core
+// steps, so the chunks are wide (128 values of k), the LDS tile is double
+// buffered (one barrier per chunk) and DEPTH chunks are loaded ahead into
+// registers.  Tile order: consecutive workgroups go to different XCDs
+// (round-robin), each with its own L2; the tiles are renumbered so that the
+// column tiles of one row block run on the same XCD and read that block of A
+// through one L2.  The sums are those of k_gemm_bf16, in the same order.
+template <int KC, int DEPTH>
 __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[kGM][kGK + kGPad];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[kGN][kGK + kGPad];
+  static_assert(DEPTH % 2 == 0, "the LDS buffer of a stage is fixed");
+  static_assert(KC % 32 == 0 && KC <= 128, "chunk of whole 32-value passes");
+  constexpr int SEGS = KC / 8, PASS = KC / 32, RSTEP = 256 / SEGS;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][kGM][KC + kGPad];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGN][KC + kGPad];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int m0 = blockIdx.y * kGM, n0 = blockIdx.x * kGN;
+  const int nbx = gridDim.x, ntile = gridDim.x * gridDim.y;
+  int tile = blockIdx.y * nbx + blockIdx.x;
+  if (ntile % 8 == 0) tile = (tile % 8) * (ntile / 8) + tile / 8;
+  const int m0 = (tile / nbx) * kGM, n0 = (tile % nbx) * kGN;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  const int row = t >> 2, seg = (t & 3) * 8;  // 64 rows x 4 segments of 8
-  const int gm = m0 + row, gn = n0 + row;
-  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-  // a segment is read only when it lies inside the row (k0 + seg < K implies
-  // k0 + seg + 8 <= K since both are multiples of 8)
-  auto fetch = [&](int k0, uint4& ra, uint4& rb) {
-    const bool in_k = k0 + seg < g.K;
-    ra = (gm < g.M && in_k) ? *reinterpret_cast<const uint4*>(g.A + gm * g.sam + k0 + seg) : zero;
-    rb = (gn < g.N && in_k) ? *reinterpret_cast<const uint4*>(g.B + gn * g.sbn + k0 + seg) : zero;
+  const int row0 = t / SEGS, seg = (t % SEGS) * 8;  // rows row0 + RSTEP i
+  // Loads are never predicated (a branch around them would make the compiler
+  // wait for every load in flight before the next LDS store): rows past M or
+  // N and segments past K read the last valid row or segment, and the value
+  // is replaced by zero.  Segments start at multiples of 8 and K is one, so a
+  // segment lies inside the row or wholly past K.
+  const uint16_t* pa[PASS];
+  const uint16_t* pb[PASS];
+  bool arow[PASS], brow[PASS];
+#pragma unroll
+  for (int i = 0; i < PASS; ++i) {
+    const int gm = m0 + row0 + RSTEP * i, gn = n0 + row0 + RSTEP * i;
+    pa[i] = g.A + static_cast<int64_t>(min(gm, g.M - 1)) * g.sam;
+    pb[i] = g.B + static_cast<int64_t>(min(gn, g.N - 1)) * g.sbn;
+    arow[i] = gm < g.M;
+    brow[i] = gn < g.N;
+  }
+  auto ld = [&](const uint16_t* p, bool ok, int k0) -> uint4 {
+    const int k = k0 + seg;
+    uint4 v = *reinterpret_cast<const uint4*>(p + min(k, g.K - 8));
+    ok = ok && k < g.K;
+    v.x = ok ? v.x : 0u;
+    v.y = ok ? v.y : 0u;
+    v.z = ok ? v.z : 0u;
+    v.w = ok ? v.w : 0u;
+    return v;
   };
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  uint4 ra, rb;
-  fetch(0, ra, rb);
-  for (int k0 = 0; k0 < g.K; k0 += kGK) {
-    // K is a multiple of 8 but maybe not of 32: zero the segments past K
-    if (k0 + seg >= g.K) {
-      ra = zero;
-      rb = zero;
+  // the chunk count is rounded up to a multiple of DEPTH: the chunks past K
+  // are zero and add exact zeros
+  const int nk = (g.K + KC - 1) / KC;
+  uint4 ra[DEPTH][PASS], rb[DEPTH][PASS];
+#pragma unroll
+  for (int s = 0; s < DEPTH; ++s)
+#pragma unroll
+    for (int i = 0; i < PASS; ++i) {
+      ra[s][i] = ld(pa[i], arow[i], s * KC);
+      rb[s][i] = ld(pb[i], brow[i], s * KC);
     }
-    *reinterpret_cast<uint4*>(&As[row][seg]) = ra;
-    *reinterpret_cast<uint4*>(&Bs[row][seg]) = rb;
-    __syncthreads();
-    if (k0 + kGK < g.K) fetch(k0 + kGK, ra, rb);
-    gemm_chunk(As, Bs, wm, wn, lane, acc);
-    __syncthreads();
+  for (int c0 = 0; c0 < nk; c0 += DEPTH) {
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s) {
+      const int c = c0 + s, b = s & 1;  // DEPTH is even: buffer c % 2
+#pragma unroll
+      for (int i = 0; i < PASS; ++i) {
+        *reinterpret_cast<uint4*>(&As[b][row0 + RSTEP * i][seg]) = ra[s][i];
+        *reinterpret_cast<uint4*>(&Bs[b][row0 + RSTEP * i][seg]) = rb[s][i];
+      }
+      // every wavefront has finished chunk c - 1 (which read the other
+      // buffer) before any passes this barrier, and chunk c - 2 (which read
+      // this one) before it stored chunk c - 1
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < PASS; ++i) {
+        ra[s][i] = ld(pa[i], arow[i], (c + DEPTH) * KC);
+        rb[s][i] = ld(pb[i], brow[i], (c + DEPTH) * KC);
+      }
+      gemm_chunk<KC>(As[b], Bs[b], wm, wn, lane, acc);
+    }
   }
   gemm_store(g, m0, n0, wm, wn, lane, acc);
+}
+
+// Operands contiguous along K with K a multiple of kLC, sam, sbn multiples of
+// 8 and 16-byte aligned rows.  The operands travel from global memory to LDS
+// without registers (global_load_lds_dwordx4): one instruction moves a block
+// of 16 rows x 32 values of k, lane l taking row l % 16 and values
+// 8 (l / 16) .. + 7, and lands it in LDS in lane order, which is the layout
+// in which the 16 x 16 x 32 bf16 matrix instruction takes its operands (lane
+// l: row l % 16, the same eight values of k for A and B), so each operand is
+// read back with one conflict-free 16-byte LDS read per lane.  A ring of kLS
+// stages of kLC values of k (32 KB each: 16 blocks of A and 16 of B) keeps
+// kLS - 1 chunks in flight per compute unit, as the products are bound by
+// the latency of their loads; one barrier per chunk.  Rows past M or N read
+// the last row (their results are not stored).  Tile order as in
+// k_gemm_bf16_kc.  Within a chunk the sums run over k in steps of 32.
+constexpr int kLC = 128, kLS = 4;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  // s_waitcnt with vmcnt = N (bits 3:0 and 15:14), expcnt and lgkmcnt at
+  // their maxima (no wait)
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16_lds(const GemmArgs g) {
+  // [stage][operand][block = 4 row blocks x 4 k blocks][lane]
+  __shared__ __attribute__((aligned(16))) uint4 T[kLS][2][16][64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nbx = gridDim.x, ntile = gridDim.x * gridDim.y;
+  int tile = blockIdx.y * nbx + blockIdx.x;
+  if (ntile % 8 == 0) tile = (tile % 8) * (ntile / 8) + tile / 8;
+  const int m0 = (tile / nbx) * kGM, n0 = (tile % nbx) * kGN;
+  // an LDS store the compiler can see (never taken for valid sizes): without
+  // one it takes the array for never written and drops the reads
+  if (g.M <= 0) T[0][0][0][lane] = make_uint4(0u, 0u, 0u, 0u);
+  // wave w loads the blocks of row block w of A and of B: lane l of block
+  // (w, q) reads row 16 w + l % 16 at k = 32 q + 8 (l / 16)
+  const int r = 16 * w + (lane & 15), kl = 8 * (lane >> 4);
+  const uint16_t* pa = g.A + static_cast<int64_t>(min(m0 + r, g.M - 1)) * g.sam + kl;
+  const uint16_t* pb = g.B + static_cast<int64_t>(min(n0 + r, g.N - 1)) * g.sbn + kl;
+  auto issue = [&](int c, int st) {
+    const int k0 = c * kLC;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __builtin_amdgcn_global_load_lds(pa + k0 + 32 * q, &T[st][0][4 * w + q][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(pb + k0 + 32 * q, &T[st][1][4 * w + q][0], 16, 0, 0);
+    }
+  };
+  const int wm = (w >> 1) * 2, wn = (w & 1) * 2;  // this wave's row and column blocks
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = g.K / kLC;
+#pragma unroll
+  for (int c = 0; c < kLS - 1; ++c)
+    if (c < nk) issue(c, c);
+  for (int c = 0; c < nk; ++c) {
+    // this wave's loads of chunk c are done once at most those of the chunks
+    // issued after it (8 instructions each) are outstanding
+    const int after = min(kLS - 2, nk - 1 - c);
+    if (after >= 2)
+      wait_vmcnt<16>();
+    else if (after == 1)
+      wait_vmcnt<8>();
+    else
+      wait_vmcnt<0>();
+    // every wavefront's part of chunk c is in LDS, and every wavefront has
+    // finished chunk c - 1, whose stage is refilled next.  A plain barrier:
+    // __syncthreads() would also wait for every load in flight (its fence),
+    // and each wavefront has already waited for its own part of chunk c;
+    // the LDS reads of chunk c - 1 completed before the matrix steps that
+    // used them.  The empty asm with a memory clobber keeps the compiler from
+    // moving LDS accesses across the barrier.
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (c + kLS - 1 < nk) issue(c + kLS - 1, (c + kLS - 1) % kLS);
+    const int st = c % kLS;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const bf16x8*>(&T[st][0][4 * (wm + i) + q][lane]);
+        b[i] = *reinterpret_cast<const bf16x8*>(&T[st][1][4 * (wn + i) + q][lane]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  gemm_store(g, m0, n0, 16 * wm, 16 * wn, lane, acc);
 }
 
 // Mean-squared error of Y against T ([rows][cols]) and its gradient

@@ -90,8 +90,12 @@ void launch_gemm(const GemmArgs& g, hipStream_t st) {
   const dim3 grid((g.N + kGN - 1) / kGN, (g.M + kGM - 1) / kGM);
   const bool kc = g.sak == 1 && g.sbk == 1 && g.K % 8 == 0 && g.sam % 8 == 0 &&
                   g.sbn % 8 == 0 && aligned16(g.A) && aligned16(g.B);
-  if (kc)
-    hipLaunchKernelGGL(k_gemm_bf16_kc, grid, dim3(256), 0, st, g);
+  // long K (the first layer's products): loads straight to LDS, four chunks
+  // in flight; shorter K: register prefetch, which measured faster there
+  if (kc && g.K >= 2048 && g.K % kLC == 0)
+    hipLaunchKernelGGL(k_gemm_bf16_lds, grid, dim3(256), 0, st, g);
+  else if (kc)
+    hipLaunchKernelGGL((k_gemm_bf16_kc<128, 2>), grid, dim3(256), 0, st, g);
   else
     hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
 }

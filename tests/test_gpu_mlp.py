@@ -56,7 +56,10 @@ def close(a, b, norm=1e-3, elem=1e-2):
     assert np.abs(a - b).max() <= elem * scale, np.abs(a - b).max() / scale
 
 
-CASES = [((100, 256, 40), 77), ((64, 32, 8), 5), ((300, 96, 50), 130)]
+# the first cases take the element-wise and register-prefetch products (K
+# below, inside and past one 128-wide chunk); the last one's first layer
+# (K = 2048) the products that load straight to LDS, over a ragged 200 rows
+CASES = [((100, 256, 40), 77), ((64, 32, 8), 5), ((300, 96, 50), 130), ((2048, 64, 24), 200)]
 
 
 @pytest.mark.parametrize("dims,B", CASES)
