@@ -11,8 +11,17 @@ ensemble is compared with the truth by EMRE, RB and RES (``sch_ensemble_stats``)
 Every step runs in the library's kernels; this module only sequences the
 calls and collects the per-step numbers.
 
+A run can log one JSON record per assimilation step (``jsonl``) and leave a
+snapshot at its last cycle boundary (``snapshot``: the ensemble and truth
+states, the carried log-weights or controls, the cycle index and the seeds,
+as a NumPy ``.npz`` of plain arrays) from which a later run continues
+(``resume``).  Every random draw is keyed by (seed, cycle, ...) rather than
+drawn from a running stream, so a resumed run reproduces the uninterrupted
+one bit for bit.
+
 Command line:  python -m paper_2402_06927_amd.experiments --exp 1 --filter tempered
-               --steps 1000 [--out results.json]
+               --steps 1000 [--out results.json] [--jsonl steps.jsonl]
+               [--snapshot state.npz] [--resume state.npz]
 """
 from __future__ import annotations
 
@@ -39,12 +48,40 @@ def make_model(wl: W.Workload, device="cuda") -> sch.Model:
                      picard_tol=wl.picard_tol, picard_max=wl.picard_max)
 
 
-def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0) -> dict:
-    """n_da assimilation steps of the twin experiment wl with the filter
-    "tempered", "bootstrap" or "nudged".  Returns per-step EMRE, RB, RES, the tempering
-    steps (tempered) or resampling flags (bootstrap), the ESS, the particles
-    whose forecast failed (zero weight), and the final ensemble and truth as
-    numpy arrays."""
+SNAPSHOT_VERSION = 1
+
+
+def save_snapshot(path: str, wl: W.Workload, filt: str, cycle: int, state: dict) -> None:
+    """Write the state at the boundary after assimilation step `cycle`: the
+    tensors of `state` (moved to the host) and the run's identity."""
+    arrays = {k: v.detach().cpu().numpy() for k, v in state.items()}
+    np.savez(path, version=np.array(SNAPSHOT_VERSION), workload=np.array(wl.name),
+             filter=np.array(filt), seed=np.array(wl.seed), cycle=np.array(cycle), **arrays)
+
+
+def load_snapshot(path: str, wl: W.Workload, filt: str) -> tuple[int, dict]:
+    """The cycle index and arrays of a snapshot written by save_snapshot for the
+    same workload, filter and seed (plain arrays only: no pickled objects)."""
+    with np.load(path, allow_pickle=False) as z:
+        if int(z["version"]) != SNAPSHOT_VERSION:
+            raise ValueError(f"{path}: snapshot version {int(z['version'])}")
+        if str(z["workload"]) != wl.name or str(z["filter"]) != filt or int(z["seed"]) != wl.seed:
+            raise ValueError(f"{path}: snapshot of {str(z['workload'])} / {str(z['filter'])} "
+                             f"/ seed {int(z['seed'])}, not {wl.name} / {filt} / {wl.seed}")
+        meta = {"version", "workload", "filter", "seed", "cycle"}
+        return int(z["cycle"]), {k: z[k] for k in z.files if k not in meta}
+
+
+def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0,
+             jsonl: str | None = None, snapshot: str | None = None,
+             resume: str | None = None) -> dict:
+    """Assimilation steps up to n_da of the twin experiment wl with the filter
+    "tempered", "bootstrap" or "nudged" (from the start, or from the step
+    after a `resume` snapshot's cycle).  Returns per-step EMRE, RB, RES, the
+    tempering steps (tempered) or resampling flags (bootstrap), the ESS, the
+    particles whose forecast failed (zero weight), and the final ensemble and
+    truth as numpy arrays.  `jsonl`: one JSON record per step appended to that
+    file; `snapshot`: the state after the last step written there."""
     if filt not in FILTERS:
         raise ValueError("filter must be one of " + ", ".join(FILTERS))
     if wl.noise != "matern":
@@ -75,11 +112,28 @@ def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0) -> dict:
         ws = sch.matern_workspace(sch.WS_BOOTSTRAP, model, n, S, 0)
         logw = torch.zeros(n, dtype=torch.float64, device=dev)
     sws = torch.empty(nx + 2 * n, dtype=torch.float64, device=dev)
-    stats = torch.empty((n_da, 3), dtype=torch.float64, device=dev)
+    carried = {"m": m, "u": u, "m_truth": mtr, "u_truth": ut}
+    if filt == "nudged":
+        carried["dlam"] = dlam
+    elif filt == "bootstrap":
+        carried["logw"] = logw
+    c0 = 0
     init_stats = sch.sch_ensemble_stats(u, ut[0], sws).cpu().numpy()
+    if resume:
+        cyc, arrays = load_snapshot(resume, wl, filt)
+        for k, t in carried.items():
+            if k not in arrays or tuple(arrays[k].shape) != tuple(t.shape):
+                raise ValueError(f"{resume}: missing or misshaped {k}")
+            t.copy_(torch.from_numpy(arrays[k]))
+        init_stats = arrays["init_stats"]
+        c0 = cyc + 1
+    if c0 > n_da:
+        raise ValueError(f"the snapshot is past step {n_da}")
+    stats = torch.empty((n_da, 3), dtype=torch.float64, device=dev)
     n_temper, resampled, ess, failed = [], [], [], []
+    logf = open(jsonl, "a") if jsonl else None
     t0 = time.perf_counter()
-    for c in range(n_da):
+    for c in range(c0, n_da):
         # truth: one window with its own cell increments, then the observation
         sch.sch_draw_increments(ts, c, 0, sch.TAG_FORECAST, cells_t, wl.dt)
         sch.sch_ensemble_step_matern(model, mt, mtr, ut, cells_t)
@@ -104,15 +158,32 @@ def run_twin(wl: W.Workload, filt: str, n_da: int, log_every: int = 0) -> dict:
         ess.append(st["ess"])
         failed.append(st["n_failed"])
         sch.sch_ensemble_stats(u, ut[0], sws, stats[c])
+        if logf:
+            s = stats[c].cpu().numpy()
+            rec = {"step": c, "emre": float(s[0]), "rb": float(s[1]), "res": float(s[2]),
+                   "ess": float(st["ess"]), "n_failed": int(st["n_failed"]),
+                   "seconds": round(time.perf_counter() - t0, 6)}
+            for key in ("n_temper", "n_accept", "resampled", "particle_steps", "picard_iters"):
+                if key in st:
+                    rec[key] = int(st[key])
+            logf.write(json.dumps(rec) + "\n")
+            logf.flush()
         if log_every and (c + 1) % log_every == 0:
             s = stats[c].cpu().numpy()
             print(f"step {c + 1}: EMRE {s[0]:.4f} RB {s[1]:.4f} RES {s[2]:.4f} ess {st['ess']:.1f}",
                   file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    s = stats.cpu().numpy()
+    if logf:
+        logf.close()
+    if snapshot:
+        st_all = dict(carried)
+        st_all["init_stats"] = torch.from_numpy(np.asarray(init_stats))
+        save_snapshot(snapshot, wl, filt, n_da - 1, st_all)
+    s = stats.cpu().numpy()[c0:]
     return {
-        "workload": wl.name, "filter": filt, "n_da": n_da, "seconds": elapsed,
+        "workload": wl.name, "filter": filt, "n_da": n_da - c0, "first_step": c0,
+        "seconds": elapsed,
         "init": init_stats, "emre": s[:, 0], "rb": s[:, 1], "res": s[:, 2],
         "n_temper": np.array(n_temper), "resampled": np.array(resampled), "ess": np.array(ess),
         "n_failed": np.array(failed),
@@ -147,12 +218,18 @@ def main():
     ap.add_argument("--steps", type=int, default=100, help="assimilation steps")
     ap.add_argument("--log-every", type=int, default=0)
     ap.add_argument("--out", default=None, help="write the per-step statistics as JSON")
+    ap.add_argument("--jsonl", default=None, help="append one JSON record per step to this file")
+    ap.add_argument("--snapshot", default=None,
+                    help="write the state after the last step to this .npz file")
+    ap.add_argument("--resume", default=None,
+                    help="continue from a snapshot up to --steps assimilation steps in all")
     args = ap.parse_args()
     if not torch.cuda.is_available():
         print("the experiments need a GPU", file=sys.stderr)
         sys.exit(2)
     wl = W.PAPER_SHAPE if args.exp == 1 else W.PAPER_HALF
-    r = run_twin(wl, args.filter, args.steps, args.log_every)
+    r = run_twin(wl, args.filter, args.steps, args.log_every, args.jsonl, args.snapshot,
+                 args.resume)
     print(json.dumps(summary(r)), flush=True)
     if args.out:
         with open(args.out, "w") as f:
