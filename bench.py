@@ -1072,16 +1072,22 @@ def main():
     j_psteps = j_launches * n * S * wl.n_jitter
     per_step = (matern_flops_per_node_step(wl.k_solves, True) if matern
                 else flops_per_node_step(Q))
+    adj_iters = 0
     if pcnl:
-        # forward windows per launch: the start gradient, one per move, the end-state
-        # rerun; only the last one's Picard iterations are counted by the library, so
-        # the flops of the adjoint passes and their forward sweeps are left out: the
-        # figure is a lower bound
-        j_psteps = j_launches * n * S
-    j_min_flops = nx * (FLOPS_PER_NODE_ITER * jt["iters"] + per_step * j_psteps)
+        # forward windows per stage: the gradient at the start, one per proposal
+        # (n_leap per HMC move), the end-state rerun; jt["iters"] holds the Picard
+        # iterations of all of them and of the adjoint's segment recomputations, the
+        # adjoint class the transposed fixed-point iterations, counted at the minimal
+        # forward count (the same operations, transposed); the reverse sweeps'
+        # per-step work and the recomputations' are left out: a lower bound
+        evals = wl.n_jitter * (HMC_LEAP if hmc else 1) + 2
+        j_psteps = j_launches * n * S * evals
+        adj_iters = tim["adjoint"]["iters"]
+    j_min_flops = nx * (FLOPS_PER_NODE_ITER * (jt["iters"] + adj_iters) + per_step * j_psteps)
     # (the Matern-type noise's own per-step work exceeds the 20 of the modes form)
     model_step = max(MODEL_FLOPS_PER_NODE_STEP, per_step)
-    j_flops = nx * (MODEL_FLOPS_PER_NODE_ITER * jt["iters"] + model_step * j_psteps)
+    j_flops = nx * (MODEL_FLOPS_PER_NODE_ITER * jt["iters"] + FLOPS_PER_NODE_ITER * adj_iters
+                    + model_step * j_psteps)
     j_ms = jt["ms"] / j_launches
     j_tflops = (j_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
     j_min_tflops = (j_min_flops / j_launches) / (j_ms * 1e-3) / 1e12 if jt["ms"] > 0 else 0.0
@@ -1111,17 +1117,24 @@ def main():
         "kernel": ("k_jitter<Matern> (pCN proposal drawn per cell + noise field + window "
                    "rerun + likelihood + accept)" if matern else
                    "pCN-Langevin stage (k_nudge_grad x (moves + 1), proposals, accepts, "
-                   "end-state window); achieved counts the end-state window only (lower bound)"
+                   "end-state window); the adjoint's transposed iterations at the minimal "
+                   "count, its reverse sweeps' per-step work left out (lower bound)"
                    if pcnl and not hmc else
                    "Hybrid Monte Carlo stage (k_nudge_grad x (moves x leapfrog steps + 1), kicks "
-                   "and rotations, accepts, end-state window); achieved counts the end-state "
-                   "window only (lower bound)" if hmc else
+                   "and rotations, accepts, end-state window); the adjoint's transposed "
+                   "iterations at the minimal count, its reverse sweeps' per-step work left out "
+                   "(lower bound)" if hmc else
                    "k_jitter (fused pCN proposal + window rerun + likelihood + accept)"),
         "avg_launch_ms": round(j_ms, 3),
         "algorithmic_flops_per_launch": j_flops / j_launches,
         "min_flops_per_launch": j_min_flops / j_launches,
         "picard_iters_per_step": jt["iters"] / max(j_psteps, 1),
     }
+    if pcnl:
+        ad = tim["adjoint"]
+        roofline.update(adjoint_evals_per_launch=ad["launches"] / j_launches,
+                        adjoint_ms_per_eval=round(ad["ms"] / max(ad["launches"], 1), 3),
+                        transposed_iters_per_step=adj_iters / max(ad["launches"] * n * S, 1))
 
     config = {
         "workload": wl.name, "filter": "tempered+jittered", "nx": nx, "n_particles": n,

@@ -843,7 +843,12 @@ int sch_tune_get(int32_t key);
 #define SCH_TK_GATHER 4   /* particle copies after resampling */
 #define SCH_TK_OTHER 5    /* likelihood, draws, fills        */
 #define SCH_TK_NUDGE 6    /* nudging objective + adjoint     */
-#define SCH_TK_COUNT 7
+#define SCH_TK_ADJOINT 7  /* adjoint evaluations of the gradient-based jitter
+                           * (inside SCH_TK_JITTER's time); iters: their
+                           * transposed fixed-point iterations, while the
+                           * Picard iterations of their forward sweeps are
+                           * counted with SCH_TK_JITTER's */
+#define SCH_TK_COUNT 8
 int sch_timing_enable(int on);
 int sch_timing_reset(void);
 int sch_timing_read(double *ms, int64_t *launches, int64_t *iters);

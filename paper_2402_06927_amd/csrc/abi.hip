@@ -312,6 +312,13 @@ int launch_jitter(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64
 }
 
 
+// One batched adjoint evaluation of the gradient-based jitter at the
+// increments x into g (defined with the timing below: its launches form the
+// timing class SCH_TK_ADJOINT).
+int adjoint_eval(const sch_model& md, const Tile& tl, const sch_obs& ob, int n, int n_steps,
+                 const double* m0, const double* u0, const double* x, double* g,
+                 const PcnlWs& P, hipStream_t st);
+
 // n_jitter pCN-Langevin moves of every particle's increments dW (pcnl.hpp):
 // the proposal draws as launch_jitter, one adjoint evaluation at the current
 // increments and one per proposal, the Metropolis-Hastings step per particle;
@@ -333,18 +340,14 @@ int launch_pcnl(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
     CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.nws.acc, 2);
-  if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, dW, nullptr, P.ce, P.J,
-                                 P.gx, P.status, nullptr, P.nws, st))
-    return rc;
+  if (int rc = adjoint_eval(md, tl, ob, n, n_steps, m0, u0, dW, P.gx, P, st)) return rc;
   hipLaunchKernelGGL(k_pcnl_grad, dim3(gb), dim3(256), 0, st, total, 1.0 / md.dt, dW, P.gx);
   int* acc = n_accept ? n_accept : P.acc;
   const double srho = std::sqrt(1.0 - rho * rho), c = (1.0 - rho) * md.dt;
   for (int j = 0; j < n_jitter; ++j) {
     hipLaunchKernelGGL(k_pcnl_propose, dim3(gb), dim3(256), 0, st, total, rho, srho, c, theta, dW,
                        P.gx, P.zeta + static_cast<size_t>(j) * total, P.v);
-    if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, P.v, nullptr, P.ce,
-                                   P.J, P.gv, P.status, nullptr, P.nws, st))
-      return rc;
+    if (int rc = adjoint_eval(md, tl, ob, n, n_steps, m0, u0, P.v, P.gv, P, st)) return rc;
     hipLaunchKernelGGL(k_pcnl_accept, dim3(n), dim3(kWave), 0, st, d, rho, md.dt, theta,
                        P.vacc + static_cast<size_t>(j) * n, P.status, P.J, dW, P.gx, phi, P.v,
                        P.gv, acc, j == 0 ? 1 : 0);
@@ -379,9 +382,7 @@ int launch_hmc(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t 
     CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.nws.acc, 2);
-  if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, dW, nullptr, P.ce, P.J,
-                                 P.gx, P.status, nullptr, P.nws, st))
-    return rc;
+  if (int rc = adjoint_eval(md, tl, ob, n, n_steps, m0, u0, dW, P.gx, P, st)) return rc;
   hipLaunchKernelGGL(k_pcnl_grad, dim3(gb), dim3(256), 0, st, total, 1.0 / md.dt, dW, P.gx);
   int* acc = n_accept ? n_accept : P.acc;
   const double a = (0.5 * P.h) * md.dt, c = std::cos(P.h), s = std::sin(P.h);
@@ -391,9 +392,7 @@ int launch_hmc(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t 
     for (int l = 0; l < P.n_leap; ++l) {
       hipLaunchKernelGGL(k_hmc_step, dim3(gb), dim3(256), 0, st, total, d, l == 0 ? 1 : 0, a,
                          theta, c, s, dW, P.gx, zj, P.v, P.vel, P.gv, P.status, P.bad);
-      if (int rc = launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, P.v, nullptr, P.ce,
-                                     P.J, P.gv, P.status, nullptr, P.nws, st))
-        return rc;
+      if (int rc = adjoint_eval(md, tl, ob, n, n_steps, m0, u0, P.v, P.gv, P, st)) return rc;
       hipLaunchKernelGGL(k_pcnl_grad, dim3(gb), dim3(256), 0, st, total, 1.0 / md.dt, P.v, P.gv);
     }
     hipLaunchKernelGGL(k_hmc_accept, dim3(n), dim3(kWave), 0, st, d, a, md.dt, theta,
@@ -451,6 +450,14 @@ struct TimedScope {
   }
 };
 
+int adjoint_eval(const sch_model& md, const Tile& tl, const sch_obs& ob, int n, int n_steps,
+                 const double* m0, const double* u0, const double* x, double* g,
+                 const PcnlWs& P, hipStream_t st) {
+  TimedScope ts(SCH_TK_ADJOINT, st);
+  return launch_nudge_grad(md, tl, ob, n, n_steps, n_steps, m0, u0, x, nullptr, P.ce, P.J, g,
+                           P.status, nullptr, P.nws, st);
+}
+
 // Called after a stream synchronisation: all pending events have completed.
 void timing_flush() {
   for (auto& p : g_tm.pend) {
@@ -488,6 +495,7 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, W.scal, 0.0, int64_t(1));  // theta = 0
   int k = 0, rc = SCH_OK;
   double theta = 0.0, ess = 0.0;
+  unsigned long long adj_iters[2] = {0, 0};  // forward and transposed, while timing
   int64_t psteps = static_cast<int64_t>(n) * n_steps;
   while (theta < 1.0) {
     if (k >= max_temper) {
@@ -542,6 +550,9 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
           return r2;
       }
       hipLaunchKernelGGL(k_sum_i32_u64, dim3(1), dim3(256), 0, st, n, PW->acc, W.acc + 1);
+      if (g_tm.on)
+        HIP_TRY(hipMemcpyAsync(adj_iters, PW->nws.acc, sizeof adj_iters, hipMemcpyDeviceToHost,
+                               st));
       // forward windows: the gradient at the start, one per proposal (n_leap per HMC
       // move), the end-state rerun
       psteps += static_cast<int64_t>(n) * n_steps *
@@ -558,6 +569,12 @@ int temper_loop(const sch_model& md, const Tile& tl, const sch_obs& ob, uint64_t
     HIP_TRY(hipMemcpyAsync(&ess, W.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     timing_flush();
+    // the adjoint evaluations of a gradient-based stage: the Picard iterations
+    // of their forward sweeps count with the stage's, the transposed ones with
+    // their own class
+    g_tm.iters[SCH_TK_JITTER] += static_cast<long long>(adj_iters[0]);
+    g_tm.iters[SCH_TK_ADJOINT] += static_cast<long long>(adj_iters[1]);
+    adj_iters[0] = adj_iters[1] = 0;
     ++k;
     if (!(ess > 0.0)) {
       rc = SCH_E_DEGENERATE;

@@ -1218,7 +1218,7 @@ def sch_mlp_controls(Y: torch.Tensor, mean: torch.Tensor, sdev: torch.Tensor,
                                   keep_mode, _stream()))
 
 
-TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other", "nudge")
+TIMING_KINDS = ("window", "jitter", "temper", "resample", "gather", "other", "nudge", "adjoint")
 
 
 def sch_timing_enable(on: bool = True):

@@ -122,6 +122,40 @@ def test_tempered_cycle_hmc_parity(sch):
         assert PR.rel_l2(N(u), u_o) < PR.REL_TOL, c
 
 
+def test_timing_counts_the_adjoint_evaluations(sch):
+    """With timing on, a tempered cycle with HMC jitter books its adjoint
+    evaluations (the start gradient and n_leap per move, per tempering step)
+    in the adjoint class with their transposed fixed-point iterations, and the
+    Picard iterations of their forward sweeps with the jitter stage's."""
+    wl = W.BOOTSTRAP_256.scaled(nx=128, n_particles=16, n_steps=6, n_obs=32, sigma_obs=0.01)
+    gm = PR.gpu_model(wl)
+    n, h, L, nj = wl.n_particles, 0.5, 3, 2
+    u0, m0, _, _ = PR.prior(wl, n)
+    ys = PR.oracle_observations(wl, 1)
+    sg = np.full(wl.n_obs, wl.sigma_obs)
+    m, u = T(m0), T(u0)
+    ws = sch.hmc_workspace(sch.WS_TEMPERED, gm, n, wl.n_steps, nj, 4)
+    sch.sch_timing_reset()
+    sch.sch_timing_enable(True)
+    try:
+        st = sch.sch_pf_tempered_cycle_hmc(gm, sch.Obs(T(ys[0]), T(sg)), wl.seed, 0, m, u,
+                                           wl.n_steps, n / 2, 50, h, L, nj, 100, ws, 4)
+        torch.cuda.synchronize()
+    finally:
+        sch.sch_timing_enable(False)
+    tim = sch.sch_timing_read()
+    k = st["n_temper"]
+    assert k >= 1
+    assert tim["adjoint"]["launches"] == k * (nj * L + 1)
+    assert tim["jitter"]["launches"] == k
+    # every evaluation runs at least one transposed iteration per step and
+    # particle, and its forward sweep at least one Picard iteration per step
+    evals = tim["adjoint"]["launches"]
+    assert tim["adjoint"]["iters"] >= evals * n * wl.n_steps
+    assert tim["jitter"]["iters"] >= (evals + k) * n * wl.n_steps
+    assert 0.0 < tim["adjoint"]["ms"] <= tim["jitter"]["ms"]
+
+
 def test_hmc_argument_errors(sch):
     wl = W.BOOTSTRAP_256.scaled(nx=128)
     gm = PR.gpu_model(wl)
