@@ -20,7 +20,8 @@ import torch
 from . import sch
 
 # (threads per particle, register slots) of the compiled model kernels
-TILES = ((64, 2), (64, 4), (64, 8), (128, 8), (256, 8), (256, 16), (512, 8), (512, 16))
+TILES = ((64, 2), (64, 4), (64, 8), (64, 16), (128, 8), (128, 16), (256, 8), (256, 16), (512, 8),
+         (512, 16))
 
 
 def slots(nx: int, nt: int) -> int:

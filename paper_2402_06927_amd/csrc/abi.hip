@@ -187,8 +187,15 @@ int launch_nudge_grad(const sch_model& md, const Tile& tl, const sch_obs& ob, in
   A.seg = W.seg;
   A.iters_acc = W.acc;
   if (M) A.M = *M;
-  const HelmConst K = make_helm(md, tl);
-  return with_tile(tl, [&]<int PM, int NT, bool FULL>() -> int {
+  // The adjoint kernel holds more per node than the window (the reverse
+  // sweep's source, checkpoints, the transposed solve's right-hand side):
+  // on 16 nodes per thread it spills and ran 7-110% slower than on twice the
+  // threads with 8 nodes each at every grid measured, so a 16-node tile is
+  // doubled where 512 threads allow it.  The Matern-noise kernels keep the
+  // caller's tile, to which the noise operator's constants belong.
+  const Tile ta = (!M && tl.pmax == 16 && tl.nt <= 256) ? tile_for(md.nx, 2 * tl.nt) : tl;
+  const HelmConst K = make_helm(md, ta);
+  return with_tile(ta, [&]<int PM, int NT, bool FULL>() -> int {
     if (M)
       hipLaunchKernelGGL((k_nudge_grad<PM, NT, FULL, true>), dim3(n), dim3(NT), 0, st, A, K);
     else

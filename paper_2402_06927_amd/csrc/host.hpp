@@ -128,7 +128,9 @@ inline int with_tile(const Tile& tl, F&& f) {
   SCH_CASE(64, 2)
   SCH_CASE(64, 4)
   SCH_CASE(64, 8)
+  SCH_CASE(64, 16)
   SCH_CASE(128, 8)
+  SCH_CASE(128, 16)
   SCH_CASE(256, 8)
   SCH_CASE(256, 16)
   SCH_CASE(512, 8)

@@ -96,6 +96,35 @@ def test_nudge_grad_parity(sch, nx, n, q, s, ce):
         assert PR.rel_l2(gg[p] - gir, gr - gir) < 1e-9
 
 
+@pytest.mark.parametrize("nx,threads", [(1000, 64), (2048, 128), (4096, 256)])
+def test_nudge_grad_on_a_16_node_tile(sch, nx, threads):
+    """A 16-node tile (64 x 16 at 1000 nodes, 128 x 16 at 2048, 256 x 16 at
+    4096) runs the adjoint on twice the threads with 8 nodes each: the same
+    bits as asking for that tile, and the oracle's gradient."""
+    _say("nudge_grad tile", nx, threads)
+    wl = W.NUDGING_2048.scaled(nx=nx, n_modes=8, n_steps=10, n_obs=64)
+    n = 2
+    m, u, y, dW, dLam = _problem(wl, n)
+    gm = PR.gpu_model(wl)
+    om = PR.oracle_model(wl)
+    out = []
+    try:
+        for nt in (threads, 2 * threads):
+            sch.sch_tune_set(sch.TUNE_THREADS, nt)
+            J = torch.empty(n, dtype=torch.float64, device="cuda")
+            g = torch.empty((n, wl.n_steps, 8), dtype=torch.float64, device="cuda")
+            sch.sch_nudge_grad(gm, _obs(sch, wl, y), T(m), T(u), T(dW), T(dLam), J, g, 4)
+            out.append((N(J), N(g)))
+    finally:
+        sch.sch_tune_set(sch.TUNE_THREADS, 0)
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    for p in range(n):
+        rs, Jr, gr = O.nudge_grad(om, y, wl.sigma_obs, m[p], u[p], dW[p], dLam[p])
+        assert rs == 0 and abs(out[0][0][p] - Jr) <= 1e-10 * abs(Jr)
+        assert PR.rel_l2(out[0][1][p], gr) < PR.REL_TOL
+
+
 def test_nudge_grad_null_inputs_and_no_data(sch):
     wl = W.NUDGING_2048.scaled(nx=256, n_steps=6, n_modes=4, n_obs=32)
     n = 3
