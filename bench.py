@@ -319,6 +319,18 @@ def bench_nudged(args, matern=False):
         ws = sch.nudged_workspace_matern(model, n, S, n_jitter, 8)
     else:
         ws = sch.nudged_workspace(model, n, S, n_jitter, 8)
+    # the tile of the window kernels, tuned as for the headline filter (the
+    # adjoint takes its own from it); the Matern-noise kernels keep the
+    # default, to which the noise operator's constants and its adjoint belong
+    tuned = None
+    if not matern and not args.threads:
+        from paper_2402_06927_amd import autotune
+
+        tuned, tile_ms = autotune.tune(model, m, u)
+        log(f"autotuned threads per particle: {tuned} ({tile_ms})")
+    elif args.threads:
+        sch.sch_tune_set(sch.TUNE_THREADS, args.threads)
+        tuned = args.threads
 
     def run_cycle(c):
         obs = sch.Obs(yobs[c].contiguous(), sigma)
@@ -357,7 +369,8 @@ def bench_nudged(args, matern=False):
                    "n_particles": n, "n_modes": Q, "n_steps": S, "n_obs": wl.n_obs,
                    "noise": wl.noise, "controls_per_step": nq,
                    "sigma_obs": wl.sigma_obs, "ess_threshold": 0.5 * n, "n_jitter": n_jitter,
-                   "rho": rho, "lbfgs_mem": 8, "ckpt_every": 8},
+                   "rho": rho, "lbfgs_mem": 8, "ckpt_every": 8,
+                   "threads_per_particle": tuned},
         "tempering_steps_per_cycle": [s_["n_temper"] for s_ in stats],
         "kernel_ms": {k: round(v["ms"], 3) for k, v in tim.items()},
     }
