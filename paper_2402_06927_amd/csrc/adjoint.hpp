@@ -82,7 +82,7 @@ __device__ void obs_adjoint(const double (&u)[PMAX], const Chunk& ch, int nx, in
     const int64_t node = ch.start + j;
     const int64_t lim = (node + 1) * n_obs, base = node * n_obs;
     const double ur = right_of<PMAX, FULL>(u, j, ch.cnt, hr);
-    const bool own_next = (j + 1 < PMAX) && (FULL || j + 1 < ch.cnt);
+    const bool own_next = (j + 1 < PMAX) && slot_live<PMAX, FULL>(j + 1, ch.cnt);
     for (; o * nx < lim; ++o) {
       const double r = static_cast<double>(o * nx - base) / dn;
       const double s = sigma[o];
@@ -124,7 +124,7 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF nois
   double s[PMAX], dv[PMAX];
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
-    if (FULL || j < cnt) {
+    if (slot_live<PMAX, FULL>(j, cnt)) {
       s[j] = ma[ch.start + j] + mb[ch.start + j];
       dv[j] = hdt * (ua[ch.start + j] + ub[ch.start + j]);
     } else {
@@ -186,7 +186,7 @@ __device__ int adjoint_step(const StepParams& P, const HelmConst& K, NoiseF nois
     int bad = grow <= kMaxGrowth ? 0 : 2;
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) {
-      if (FULL || j < cnt) {
+      if (slot_live<PMAX, FULL>(j, cnt)) {
         diff = fmax(diff, fabs(nn[j] - nu[j]));
         scale = fmax(scale, fabs(nn[j]));
         bad |= !isfinite(nn[j]);
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         double w[PMAX];
 #pragma unroll
         for (int j = 0; j < PMAX; ++j)
-          w[j] = (FULL || j < ch.cnt) ? incv(n, ch.start + j) : 0.0;
+          w[j] = slot_live<PMAX, FULL>(j, ch.cnt) ? incv(n, ch.start + j) : 0.0;
         matern_add<PMAX, NT, FULL>(A.M, w, e, ch, L, t, par);
       };
     } else {
@@ -368,14 +368,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
           double* gp = A.grad + (static_cast<size_t>(p) * CS + n) * nx + ch.start;
 #pragma unroll
           for (int j = 0; j < PMAX; ++j)
-            if (FULL || j < ch.cnt) gp[j] = gc[j] + incv(n, ch.start + j) / A.P.dt;
+            if (slot_live<PMAX, FULL>(j, ch.cnt)) gp[j] = gc[j] + incv(n, ch.start + j) / A.P.dt;
         } else {
           for (int q = 0; q < Q; ++q) {
             const double* xq = A.P.xi + static_cast<size_t>(q) * nx + ch.start;
             double a = 0.0;
 #pragma unroll
             for (int j = 0; j < PMAX; ++j)
-              if (FULL || j < ch.cnt) a = fma(xq[j], gdU[j], a);
+              if (slot_live<PMAX, FULL>(j, ch.cnt)) a = fma(xq[j], gdU[j], a);
             a = wave_sum(a);
             if (lane == 0) gpart[q][wv] = a;
           }

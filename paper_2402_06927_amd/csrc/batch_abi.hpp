@@ -49,7 +49,7 @@ bool batch_tile(const sch_instance& in, Tile& tl) {
     tl.pmax = 4;
     tl.full = false;
   }
-  return true;
+  return tile_rows_ok(in.nx, tl);
 }
 
 struct Layout {

@@ -230,6 +230,23 @@ __device__ __forceinline__ Chunk chunk_of(int nx, int t) {
   return c;
 }
 
+// Rows every chunk holds: chunk_of deals nx / NT or nx / NT + 1 rows, and the
+// tiles (tile_for) take 8 slots only when nx > 4 NT, 16 only when nx > 8 NT,
+// and always nx >= NT; the host refuses a tile that breaks this.  Slots below
+// kMinRows are live in every chunk, so the masks of ragged chunks start there
+// (compile-time true below it).
+template <int PMAX>
+inline constexpr int kMinRows = PMAX >= 8 ? PMAX / 2 : 1;
+template <int PMAX, bool FULL>
+__device__ __forceinline__ bool slot_live(int j, int cnt) {
+  return FULL || j < kMinRows<PMAX> || j < cnt;
+}
+// slot j is the chunk's last live one
+template <int PMAX, bool FULL>
+__device__ __forceinline__ bool slot_last(int j, int cnt) {
+  return FULL ? j == PMAX - 1 : (j >= kMinRows<PMAX> - 1 && j == cnt - 1);
+}
+
 // Value of slot j's left / right neighbour given the halo values.
 template <int PMAX, bool FULL>
 __device__ __forceinline__ double left_of(const double (&v)[PMAX], int j, double hl) {
@@ -237,8 +254,7 @@ __device__ __forceinline__ double left_of(const double (&v)[PMAX], int j, double
 }
 template <int PMAX, bool FULL>
 __device__ __forceinline__ double right_of(const double (&v)[PMAX], int j, int cnt, double hr) {
-  const bool last = FULL ? (j == PMAX - 1) : (j == cnt - 1);
-  return last ? hr : v[j + 1 < PMAX ? j + 1 : PMAX - 1];
+  return slot_last<PMAX, FULL>(j, cnt) ? hr : v[j + 1 < PMAX ? j + 1 : PMAX - 1];
 }
 
 // Value in the chunk's last active slot.  For ragged chunks a sum of masked
@@ -249,7 +265,7 @@ __device__ __forceinline__ double last_of(const double (&v)[PMAX], int cnt) {
   if (FULL) return v[PMAX - 1];
   double r = 0.0;
 #pragma unroll
-  for (int j = 0; j < PMAX; ++j) r = fma(j == cnt - 1 ? 1.0 : 0.0, v[j], r);
+  for (int j = kMinRows<PMAX> - 1; j < PMAX; ++j) r = fma(j == cnt - 1 ? 1.0 : 0.0, v[j], r);
   return r;
 }
 
@@ -508,7 +524,7 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     const double inv = rcp64(j == 1 ? b : b - a * cprev);
     double cj = c * inv, yj = (j == 1 ? d(j) : d(j) - a * yprev) * inv,
            gj = (j == 1 ? -a : -a * gprev) * inv;
-    if (!FULL && j >= cnt) {
+    if (!slot_live<PMAX, FULL>(j, cnt)) {
       cj = -1.0;
       yj = 0.0;
       gj = 0.0;
@@ -538,7 +554,7 @@ __device__ __forceinline__ void cyclic_solve(RowF row, DF d, double (&x)[PMAX], 
     yn = yj;
     gn = gj;
     kn = kj;
-    if (!FULL && j == cnt - 1) {
+    if (!FULL && slot_last<PMAX, FULL>(j, cnt)) {
       yL = yj;
       gL = gj;
       kL = kj;

@@ -107,11 +107,11 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   // the local backward scan at its first node
   double acc = 0.0;
 #pragma unroll
-  for (int j = 0; j < PMAX; ++j) acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+  for (int j = 0; j < PMAX; ++j) acc = slot_live<PMAX, FULL>(j, cnt) ? fma(r, acc, f[j]) : acc;
   const double cpl = acc;
   acc = 0.0;
 #pragma unroll
-  for (int j = PMAX - 1; j >= 0; --j) acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+  for (int j = PMAX - 1; j >= 0; --j) acc = slot_live<PMAX, FULL>(j, cnt) ? fma(r, acc, f[j]) : acc;
   const double cmn = acc;
   const double mth = (FULL || cnt == K.base) ? K.rb : K.rb1;
   const int row = lane >> 4;
@@ -274,13 +274,13 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   acc = Ep;
 #pragma unroll
   for (int j = 0; j < PMAX; ++j) {
-    acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+    acc = slot_live<PMAX, FULL>(j, cnt) ? fma(r, acc, f[j]) : acc;
     u[j] = MASS ? acc : acc - f[j];
   }
   acc = Em;
 #pragma unroll
   for (int j = PMAX - 1; j >= 0; --j) {
-    acc = (FULL || j < cnt) ? fma(r, acc, f[j]) : acc;
+    acc = slot_live<PMAX, FULL>(j, cnt) ? fma(r, acc, f[j]) : acc;
     u[j] = MASS ? fma(K.mg, u[j] + acc, K.mf * f[j]) : K.coef * (u[j] + acc);
   }
   // bordering values from the Helmholtz rows of the first and last node,
@@ -291,7 +291,7 @@ __device__ __forceinline__ void solve_helm(const HelmConst& K, const double (&f)
   if (!FULL) {
 #pragma unroll
     for (int j = 1; j < PMAX; ++j)
-      if (j == last) {
+      if (j >= kMinRows<PMAX> - 1 && j == last) {
         ul = u[j];
         ulm = u[j - 1];
         fla = f[j];

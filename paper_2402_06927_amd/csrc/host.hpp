@@ -62,6 +62,13 @@ inline Tile tile_for(int nx, int nt) {
   return tl;
 }
 
+// The kernels take every chunk to hold at least kMinRows<PMAX> rows (their
+// ragged-chunk masks start there): PMAX / 2 for 8 and 16 slots, else 1.
+inline bool tile_rows_ok(int nx, const Tile& tl) {
+  const int min_rows = tl.pmax >= 8 ? tl.pmax / 2 : 1;
+  return nx / tl.nt >= min_rows && (nx + tl.nt - 1) / tl.nt <= tl.pmax;
+}
+
 inline int g_tune_threads = 0;  // SCH_TUNE_THREADS
 
 inline bool pick_tile(int nx, Tile& tl) {
@@ -74,7 +81,7 @@ inline bool pick_tile(int nx, Tile& tl) {
   }
   if (nx < nt || (nx + nt - 1) / nt > 16) return false;
   tl = tile_for(nx, nt);
-  return true;
+  return tile_rows_ok(nx, tl);
 }
 
 // Constants of the scan form (helm.hpp) of the solve with M + a2 K on nx

@@ -88,7 +88,8 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 void launch_gemm(const GemmArgs& g, hipStream_t st) {
   const dim3 grid((g.N + kGN - 1) / kGN, (g.M + kGM - 1) / kGM);
-  const bool kc = g.sak == 1 && g.sbk == 1 && g.K % 8 == 0 && g.sam % 8 == 0 &&
+  // (the K-contiguous loaders clamp their reads to K - 8: K >= 8)
+  const bool kc = g.sak == 1 && g.sbk == 1 && g.K >= 8 && g.K % 8 == 0 && g.sam % 8 == 0 &&
                   g.sbn % 8 == 0 && aligned16(g.A) && aligned16(g.B);
   // long K (the first layer's products): loads straight to LDS, four chunks
   // in flight; shorter K: register prefetch, which measured faster there

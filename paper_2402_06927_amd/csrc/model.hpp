@@ -84,7 +84,7 @@ __device__ __forceinline__ auto modes_noise(const StepParams& P, const Chunk& ch
       const double* xq = P.xi + static_cast<size_t>(q) * P.nx + ch.start;
 #pragma unroll
       for (int j = 0; j < PMAX; ++j)
-        if (FULL || j < ch.cnt) e[j] = fma(xq[j], w, e[j]);
+        if (slot_live<PMAX, FULL>(j, ch.cnt)) e[j] = fma(xq[j], w, e[j]);
     }
   };
 }
@@ -129,7 +129,7 @@ __device__ __forceinline__ void matern_add(const MaternDev& M, const double (&w)
   }
 #pragma unroll
   for (int j = 0; j < PMAX; ++j)
-    if (FULL || j < cnt) e[j] += U[j];
+    if (slot_live<PMAX, FULL>(j, cnt)) e[j] += U[j];
 }
 
 // The transpose of the map of matern_add (cells Delta W -> field U_k): with
@@ -293,7 +293,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
 #pragma unroll
         for (int j = 0; j < PMAX; ++j) {
           ms[j] -= m[j];
-          if (FULL || j < cnt) {
+          if (slot_live<PMAX, FULL>(j, cnt)) {
             diff = fmax(diff, fabs(ms[j] - getP(j)));
             scale = fmax(scale, fabs(ms[j]));
           }
@@ -304,7 +304,7 @@ __device__ int run_window(const StepParams& P, const HelmConst& K, NoiseF noise,
 #pragma unroll
         for (int j = 0; j < PMAX; ++j) {
           ms[j] -= m[j];
-          if (FULL || j < cnt) diff = fmax(diff, fabs(ms[j] - getP(j)));
+          if (slot_live<PMAX, FULL>(j, cnt)) diff = fmax(diff, fabs(ms[j] - getP(j)));
           setP(j, ms[j]);
         }
       }
@@ -416,13 +416,13 @@ __device__ double staged_nll(const AuxLds<PMAX, NT>& X, int nx, int n_obs, const
 template <int PMAX, bool FULL>
 __device__ __forceinline__ void load_chunk(const double* g, const Chunk& ch, double (&v)[PMAX]) {
 #pragma unroll
-  for (int j = 0; j < PMAX; ++j) v[j] = (FULL || j < ch.cnt) ? g[ch.start + j] : 0.0;
+  for (int j = 0; j < PMAX; ++j) v[j] = slot_live<PMAX, FULL>(j, ch.cnt) ? g[ch.start + j] : 0.0;
 }
 template <int PMAX, bool FULL>
 __device__ __forceinline__ void store_chunk(double* g, const Chunk& ch, const double (&v)[PMAX]) {
 #pragma unroll
   for (int j = 0; j < PMAX; ++j)
-    if (FULL || j < ch.cnt) g[ch.start + j] = v[j];
+    if (slot_live<PMAX, FULL>(j, ch.cnt)) g[ch.start + j] = v[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -548,10 +548,10 @@ __device__ __forceinline__ void cell_normals(uint64_t seed, uint32_t c0, uint32_
 #pragma unroll
     for (int j = 0; j < PMAX; j += 2) {
       double za = 0.0, zb = 0.0;
-      if (FULL || j < ch.cnt)
+      if (slot_live<PMAX, FULL>(j, ch.cnt))
         normal2(seed, c0, c1, static_cast<uint32_t>((s0 + j) >> 1) | tag, c3, za, zb);
       z[j] = za;
-      z[j + 1] = (FULL || j + 1 < ch.cnt) ? zb : 0.0;
+      z[j + 1] = slot_live<PMAX, FULL>(j + 1, ch.cnt) ? zb : 0.0;
     }
   }
 }
@@ -566,7 +566,7 @@ __device__ __forceinline__ void pcn_cells(uint64_t seed, uint32_t c0, uint32_t c
   cell_normals<PMAX, FULL>(seed, c0, c1, SCH_TAG_PCN << 24, c3, ch, z);
 #pragma unroll
   for (int j = 0; j < PMAX; ++j)
-    w[j] = (FULL || j < ch.cnt) ? rho * cur[j] + srho * (sdt * z[j]) : 0.0;
+    w[j] = slot_live<PMAX, FULL>(j, ch.cnt) ? rho * cur[j] + srho * (sdt * z[j]) : 0.0;
 }
 
 // n_jitter pCN moves of one particle's increments (section 3.1.2): proposal,
@@ -632,7 +632,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
                               w3, ch, A.rho, srho, sdt, cur + off, w);
 #pragma unroll
         for (int jj = 0; jj < PMAX; ++jj)
-          if (FULL || jj < ch.cnt) {
+          if (slot_live<PMAX, FULL>(jj, ch.cnt)) {
             prop[off + jj] = w[jj];
             if (lam) w[jj] += lam[off + jj];  // the window sees dW' + dLambda
           }
