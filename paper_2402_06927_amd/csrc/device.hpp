@@ -207,7 +207,9 @@ __device__ __forceinline__ int eq_pos(int t) {
 
 // 1/x for the solvers' pivots: the hardware estimate (relative error about
 // 5e-8 on gfx950) and one Newton step, which squares that error (at most
-// about 11 ulp, 2e-15 relative); the pivots are bounded away from zero.
+// about 11 ulp, 2e-15 relative).  Small pivots are not excluded by the
+// matrices themselves: an elimination that meets them grows its eliminated
+// super-diagonal, which the solvers measure (kMaxGrowth below).
 __device__ __forceinline__ double rcp64(double x) {
   const double r = __builtin_amdgcn_rcp(x);
   return fma(r, fma(-x, r, 1.0), r);
