@@ -77,17 +77,17 @@ def matern_flops_per_node_step(k: int, pcn: bool) -> int:
 # HBM traffic of one k_jitter launch at this workload from two rocprofv3
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of a plain
 # 1 GiB copy), valid for the kernel sources with the hash below.
-TRAFFIC_JITTER_BYTES = (199738.90625 * 2.0 + 268405.171875 * 1.0) * 1024
+TRAFFIC_JITTER_BYTES = (199964.40625 * 2.0 + 268370.109375 * 1.0) * 1024
 # the same for the jitter kernel with the Matern-type noise (cells read and
 # proposals written per step)
-TRAFFIC_JITTER_MATERN_BYTES = (3907785.34375 * 2.0 + 7411347.15625 * 1.0) * 1024
+TRAFFIC_JITTER_MATERN_BYTES = (3907625.34375 * 2.0 + 7411383.984375 * 1.0) * 1024
 TRAFFIC_THREADS = 256
 # checkpoint interval of the adjoint passes of the pCN-Langevin jitter
 PCNL_CKPT = 8
 # Hybrid Monte Carlo jitter of the bench: leapfrog angle and steps per move
 HMC_H = 0.5
 HMC_LEAP = 3
-TRAFFIC_SOURCES_HASH = "9ca22a2dd89ce85d"
+TRAFFIC_SOURCES_HASH = "ee65545743aecf33"
 
 
 def kernel_sources_hash() -> str:
