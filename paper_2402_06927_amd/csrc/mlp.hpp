@@ -44,6 +44,7 @@ struct GemmArgs {
   const float* mask;
   int64_t ldm;
   int relu;
+  float* kpart;  // split-K partial products [gridDim.z][M][N] (k_gemm_bf16_lds), or null
 };
 
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 8;  // LDS rows of 80 bytes
@@ -71,8 +72,18 @@ __device__ __forceinline__ void gemm_chunk(const uint16_t (&As)[kGM][KC + kGPad]
   }
 }
 
+// Epilogue of one element of C.
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int m, int n, float v) {
+  if (g.bias) v += g.bias[n];
+  if (g.mask && !(g.mask[m * g.ldm + n] > 0.f)) v = 0.f;
+  if (g.C32) g.C32[m * g.ldc + n] = v;
+  if (g.C16) g.C16[m * g.ldc16 + n] = f2bf(g.relu ? fmaxf(v, 0.f) : v);
+}
+
+// RAW: the accumulators go to the split-K partials of slice `z` instead.
+template <bool RAW = false>
 __device__ __forceinline__ void gemm_store(const GemmArgs& g, int m0, int n0, int wm, int wn,
-                                           int lane, const f32x4 (&acc)[2][2]) {
+                                           int lane, const f32x4 (&acc)[2][2], int z = 0) {
   // lane l of a 16 x 16 tile holds rows 4 (l / 16) .. + 3 of column l % 16
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -83,11 +94,10 @@ __device__ __forceinline__ void gemm_store(const GemmArgs& g, int m0, int n0, in
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
         const int n = n0 + wn + 16 * j + (lane & 15);
         if (m >= g.M || n >= g.N) continue;
-        float v = acc[i][j][r];
-        if (g.bias) v += g.bias[n];
-        if (g.mask && !(g.mask[m * g.ldm + n] > 0.f)) v = 0.f;
-        if (g.C32) g.C32[m * g.ldc + n] = v;
-        if (g.C16) g.C16[m * g.ldc16 + n] = f2bf(g.relu ? fmaxf(v, 0.f) : v);
+        if constexpr (RAW)
+          g.kpart[(static_cast<int64_t>(z) * g.M + m) * g.N + n] = acc[i][j][r];
+        else
+          gemm_epilogue(g, m, n, acc[i][j][r]);
       }
 }
 
@@ -230,6 +240,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
 // the latency of their loads; one barrier per chunk.  Rows past M or N read
 // the last row (their results are not stored).  Tile order as in
 // k_gemm_bf16_kc.  Within a chunk the sums run over k in steps of 32.
+// Split K (gridDim.z > 1, when the tiles alone would leave compute units
+// idle): slice z takes chunks [z nk / Z, (z + 1) nk / Z) and writes its raw
+// sums to g.kpart; k_gemm_reduce adds the slices in order and applies the
+// epilogue.
 constexpr int kLC = 128, kLS = 4;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -271,7 +285,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_lds(const GemmArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int nk = g.K / kLC;
+  const int nk_all = g.K / kLC, nz = gridDim.z, z = blockIdx.z;
+  const int c_lo = (nk_all * z) / nz, nk = (nk_all * (z + 1)) / nz - c_lo;
+  pa += static_cast<int64_t>(c_lo) * kLC;
+  pb += static_cast<int64_t>(c_lo) * kLC;
 #pragma unroll
   for (int c = 0; c < kLS - 1; ++c)
     if (c < nk) issue(c, c);
@@ -312,7 +329,22 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_lds(const GemmArgs g) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-  gemm_store(g, m0, n0, 16 * wm, 16 * wn, lane, acc);
+  if (nz > 1)
+    gemm_store<true>(g, m0, n0, 16 * wm, 16 * wn, lane, acc, z);
+  else
+    gemm_store(g, m0, n0, 16 * wm, 16 * wn, lane, acc);
+}
+
+// The sum of the nz split-K slices of k_gemm_bf16_lds (in slice order), then
+// the epilogue, one element per thread.
+__global__ void k_gemm_reduce(const GemmArgs g, int nz) {
+  const int64_t mn = static_cast<int64_t>(g.M) * g.N;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < mn;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float v = g.kpart[i];
+    for (int z = 1; z < nz; ++z) v += g.kpart[z * mn + i];
+    gemm_epilogue(g, static_cast<int>(i / g.N), static_cast<int>(i % g.N), v);
+  }
 }
 
 // Mean-squared error of Y against T ([rows][cols]) and its gradient

@@ -20,6 +20,7 @@ bool mlp_ok(const sch_mlp* n) {
 // along its summation index; the column-sum partials.
 struct MlpWs {
   float *Z1, *Z2, *dY32, *dZ2, *dZ1;
+  float* kpart;  // split-K partials of the first layer's product
   uint16_t *H1, *H2, *dY16, *dZ2b, *dZ1b;
   uint16_t *XT, *dYT, *H1T, *H2T, *dZ2T, *dZ1T, *W2T, *W3T;
   double* part;
@@ -28,12 +29,26 @@ struct MlpWs {
 
 int colsum_parts(int rows) { return (rows + kColsumRows - 1) / kColsumRows; }
 
+// Slices of K for a product on the straight-to-LDS loader: its 64 x 64 tiles
+// alone fill fewer than half the chip's 256 compute units when M x N is small
+// (the training batch's first layer: 64 tiles), so K is split until the
+// slices fill it (at most 4, at least 2 chunks of kLC per slice).
+int ksplit_for(int M, int N, int K) {
+  const int tiles = ((M + kGM - 1) / kGM) * ((N + kGN - 1) / kGN);
+  if (K < 2048 || K % kLC != 0 || tiles >= 128) return 1;
+  int z = 1;
+  while (z < 4 && tiles * 2 * z <= 256 && K / kLC >= 2 * (2 * z)) z *= 2;
+  return z;
+}
+
 MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
   Carve c(base);
   MlpWs w{};
   const size_t bh = static_cast<size_t>(batch) * d.H, bo = static_cast<size_t>(batch) * d.O;
   w.Z1 = c.take<float>(bh);
   w.Z2 = c.take<float>(bh);
+  const int kz = ksplit_for(batch, d.H, d.F);
+  w.kpart = c.take<float>(kz > 1 ? static_cast<size_t>(kz) * bh : 0);
   w.H1 = c.take<uint16_t>(bh);
   w.H2 = c.take<uint16_t>(bh);
   w.dY32 = c.take<float>(bo);
@@ -92,10 +107,15 @@ void launch_gemm(const GemmArgs& g, hipStream_t st) {
   const bool kc = g.sak == 1 && g.sbk == 1 && g.K >= 8 && g.K % 8 == 0 && g.sam % 8 == 0 &&
                   g.sbn % 8 == 0 && aligned16(g.A) && aligned16(g.B);
   // long K (the first layer's products): loads straight to LDS, four chunks
-  // in flight; shorter K: register prefetch, which measured faster there
-  if (kc && g.K >= 2048 && g.K % kLC == 0)
-    hipLaunchKernelGGL(k_gemm_bf16_lds, grid, dim3(256), 0, st, g);
-  else if (kc)
+  // in flight, K split over idle compute units where the caller gave the
+  // partials' buffer; shorter K: register prefetch, which measured faster there
+  if (kc && g.K >= 2048 && g.K % kLC == 0) {
+    const int kz = g.kpart ? ksplit_for(g.M, g.N, g.K) : 1;
+    hipLaunchKernelGGL(k_gemm_bf16_lds, dim3(grid.x, grid.y, kz), dim3(256), 0, st, g);
+    if (kz > 1)
+      hipLaunchKernelGGL(k_gemm_reduce, dim3(grid_for(static_cast<int64_t>(g.M) * g.N, 256)),
+                         dim3(256), 0, st, g, kz);
+  } else if (kc)
     hipLaunchKernelGGL((k_gemm_bf16_kc<128, 2>), grid, dim3(256), 0, st, g);
   else
     hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
@@ -136,6 +156,7 @@ int sch_mlp_forward(const sch_mlp* net, int32_t batch, const uint16_t* X, float*
   const uint16_t* wb = net->weights_bf16;
   const int F = d.F, H = d.H, O = d.O;
   GemmArgs g = gemm(batch, H, F, X, F, 1, wb, 1, F);  // Z1 = X W1^T + b1
+  g.kpart = w.kpart;
   g.bias = p + d.ob1;
   g.C32 = w.Z1;
   g.ldc = H;
