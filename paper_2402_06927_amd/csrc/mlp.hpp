@@ -29,7 +29,8 @@ __device__ __forceinline__ float bf2f(uint16_t b) {
 // C(m, n) = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
 // B(k, n) = B[k sbk + n sbn] (one of the two strides of each operand is 1).
 // Epilogue: v = C + bias[n]; v = 0 where mask[m][n] <= 0; C32 receives v,
-// C16 receives bf16(relu ? max(v, 0) : v).
+// C16 receives bf16(relu ? max(v, 0) : v) and C16T the same value transposed
+// (C16T[n ldt + m]; ldt a multiple of 4 and C16T 8-byte aligned).
 struct GemmArgs {
   int M, N, K;
   const uint16_t* A;
@@ -40,6 +41,8 @@ struct GemmArgs {
   int64_t ldc;
   uint16_t* C16;
   int64_t ldc16;
+  uint16_t* C16T;
+  int64_t ldt;
   const float* bias;
   const float* mask;
   int64_t ldm;
@@ -72,12 +75,17 @@ __device__ __forceinline__ void gemm_chunk(const uint16_t (&As)[kGM][KC + kGPad]
   }
 }
 
-// Epilogue of one element of C.
-__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int m, int n, float v) {
+// Epilogue of one element of C; returns its bf16 value. TP: write the
+// transposed copy here (the tiled stores write it four rows at a time).
+template <bool TP = true>
+__device__ __forceinline__ uint16_t gemm_epilogue(const GemmArgs& g, int m, int n, float v) {
   if (g.bias) v += g.bias[n];
   if (g.mask && !(g.mask[m * g.ldm + n] > 0.f)) v = 0.f;
   if (g.C32) g.C32[m * g.ldc + n] = v;
-  if (g.C16) g.C16[m * g.ldc16 + n] = f2bf(g.relu ? fmaxf(v, 0.f) : v);
+  const uint16_t b = f2bf(g.relu ? fmaxf(v, 0.f) : v);
+  if (g.C16) g.C16[m * g.ldc16 + n] = b;
+  if (TP && g.C16T) g.C16T[n * g.ldt + m] = b;
+  return b;
 }
 
 // RAW: the accumulators go to the split-K partials of slice `z` instead.
@@ -85,6 +93,29 @@ template <bool RAW = false>
 __device__ __forceinline__ void gemm_store(const GemmArgs& g, int m0, int n0, int wm, int wn,
                                            int lane, const f32x4 (&acc)[2][2], int z = 0) {
   // lane l of a 16 x 16 tile holds rows 4 (l / 16) .. + 3 of column l % 16
+  if (!RAW && g.C16T) {
+    // m0, wm are multiples of 16: the four rows start at a multiple of 4 and
+    // land in one 8-byte word of the transposed copy
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4);
+        const int n = n0 + wn + 16 * j + (lane & 15);
+        if (n >= g.N) continue;
+        if (m + 3 < g.M) {
+          uint16_t b[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) b[r] = gemm_epilogue<false>(g, m + r, n, acc[i][j][r]);
+          *reinterpret_cast<uint2*>(g.C16T + n * g.ldt + m) =
+              make_uint2(b[0] | (static_cast<uint32_t>(b[1]) << 16),
+                         b[2] | (static_cast<uint32_t>(b[3]) << 16));
+        } else {
+          for (int r = 0; r < 4 && m + r < g.M; ++r) gemm_epilogue(g, m + r, n, acc[i][j][r]);
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -369,19 +400,32 @@ __global__ void k_mse(int64_t n, const float* Y, const float* T, float inv_count
   if (threadIdx.x == 0) atomicAdd(loss, ((part[0] + part[1]) + (part[2] + part[3])) * inv_count);
 }
 
-// Column sums out[c] = sum_r A[r][c] in two passes with a fixed order.
-// Pass 1 (grid (ceil(cols / 64), ceil(rows / kColsumRows)), 256 threads):
-// workgroup (x, b) sums the rows of slice b for 64 columns, 4 row lanes each
-// taking every 4th row in float64, the lanes combined in lane order, into
-// part[b][c].  Pass 2 adds the slices' partials in slice order.  Every
-// workgroup's share is short, so the sums are spread over the whole chip.
-constexpr int kColsumRows = 64;
+// Column sums out_k[c] = sum_r A_k[r][c] of up to kColsumBatch float32
+// matrices with the same number of rows, in two passes with a fixed order.
+// Pass 1 (grid (total column tiles of 64, ceil(rows / kColsumRows)), 256
+// threads): workgroup (x, b) sums the rows of slice b for 64 columns of one
+// matrix (matrix k owns column tiles tile0[k] .. tile0[k + 1] - 1), 4 row
+// lanes each taking every 4th row in float64, the lanes combined in lane
+// order, into part[b][coff[k] + c].  Pass 2 adds the slices' partials in
+// slice order.  Every workgroup's share is short, so the sums are spread
+// over the whole chip.
+constexpr int kColsumRows = 64, kColsumBatch = 4;
+struct ColsumBatch {
+  int n;
+  int cols[kColsumBatch];
+  int tile0[kColsumBatch + 1], coff[kColsumBatch + 1];
+  const float* A[kColsumBatch];
+  float* out[kColsumBatch];
+};
 
-__global__ void __launch_bounds__(256) k_colsum_part(int rows, int cols, const float* A,
+__global__ void __launch_bounds__(256) k_colsum_part(int rows, const ColsumBatch b,
                                                      double* part) {
   __shared__ double red[4][64];
+  int k = 0;
+  while (k + 1 < b.n && static_cast<int>(blockIdx.x) >= b.tile0[k + 1]) ++k;
   const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + cl;
+  const int c = (blockIdx.x - b.tile0[k]) * 64 + cl, cols = b.cols[k];
+  const float* A = b.A[k];
   const int r0 = blockIdx.y * kColsumRows, r1 = min(rows, r0 + kColsumRows);
   double s = 0.0;
   if (c < cols)
@@ -389,35 +433,52 @@ __global__ void __launch_bounds__(256) k_colsum_part(int rows, int cols, const f
   red[rl][cl] = s;
   __syncthreads();
   if (rl == 0 && c < cols)
-    part[static_cast<int64_t>(blockIdx.y) * cols + c] =
+    part[static_cast<int64_t>(blockIdx.y) * b.coff[b.n] + b.coff[k] + c] =
         ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
-__global__ void k_colsum_final(int n_part, int cols, const double* part, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+__global__ void k_colsum_final(int n_part, const ColsumBatch b, const double* part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, ctot = b.coff[b.n];
+  if (c >= ctot) return;
+  int k = 0;
+  while (k + 1 < b.n && c >= b.coff[k + 1]) ++k;
   double t = 0.0;
-  for (int b = 0; b < n_part; ++b) t += part[static_cast<int64_t>(b) * cols + c];
-  out[c] = static_cast<float>(t);
+  for (int s = 0; s < n_part; ++s) t += part[static_cast<int64_t>(s) * ctot + c];
+  b.out[k][c - b.coff[k]] = static_cast<float>(t);
 }
 
-// out[c][r] = in[r][c] for a rows x cols bfloat16 matrix (leading dimensions
-// ldi, ldo), through LDS in 64 x 64 tiles: both the reads and the writes
-// move consecutive elements across consecutive threads.
-__global__ void __launch_bounds__(256) k_transpose_bf16(int rows, int cols, const uint16_t* in,
-                                                        int64_t ldi, uint16_t* out, int64_t ldo) {
+// Up to kTransposeBatch independent transposes out[c][r] = in[r][c] of dense
+// rows x cols bfloat16 matrices in one launch, through LDS in 64 x 64 tiles
+// (both the reads and the writes move consecutive elements across
+// consecutive threads): matrix i owns workgroups tile0[i] .. tile0[i + 1] - 1,
+// its tiles numbered along the columns first (tx[i] tiles to a row of tiles).
+constexpr int kTransposeBatch = 8;
+struct TransposeBatch {
+  int n;
+  int rows[kTransposeBatch], cols[kTransposeBatch], tx[kTransposeBatch];
+  int tile0[kTransposeBatch + 1];
+  const uint16_t* in[kTransposeBatch];
+  uint16_t* out[kTransposeBatch];
+};
+
+__global__ void __launch_bounds__(256) k_transpose_bf16(const TransposeBatch b) {
   __shared__ uint16_t tile[64][66];
-  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  int k = 0;
+  while (k + 1 < b.n && static_cast<int>(blockIdx.x) >= b.tile0[k + 1]) ++k;
+  const int loc = blockIdx.x - b.tile0[k], rows = b.rows[k], cols = b.cols[k];
+  const int r0 = (loc / b.tx[k]) * 64, c0 = (loc % b.tx[k]) * 64;
+  const uint16_t* in = b.in[k];
+  uint16_t* out = b.out[k];
   for (int i = threadIdx.x; i < 64 * 64; i += 256) {
     const int r = i >> 6, c = i & 63;
     const int gr = r0 + r, gc = c0 + c;
-    tile[r][c] = (gr < rows && gc < cols) ? in[gr * ldi + gc] : uint16_t(0);
+    tile[r][c] = (gr < rows && gc < cols) ? in[static_cast<int64_t>(gr) * cols + gc] : uint16_t(0);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 64 * 64; i += 256) {
     const int c = i >> 6, r = i & 63;
     const int gr = r0 + r, gc = c0 + c;
-    if (gr < rows && gc < cols) out[gc * ldo + gr] = tile[r][c];
+    if (gr < rows && gc < cols) out[static_cast<int64_t>(gc) * rows + gr] = tile[r][c];
   }
 }
 

@@ -65,24 +65,49 @@ MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
   w.dZ1T = c.take<uint16_t>(bh);
   w.W2T = c.take<uint16_t>(static_cast<size_t>(d.H) * d.H);
   w.W3T = c.take<uint16_t>(static_cast<size_t>(d.H) * d.O);
-  w.part = c.take<double>(static_cast<size_t>(colsum_parts(batch)) * (d.H > d.O ? d.H : d.O));
+  w.part = c.take<double>(static_cast<size_t>(colsum_parts(batch)) * (2 * d.H + d.O));
   w.bytes = c.off + 256;
   return w;
 }
 
-void transpose_bf16(int rows, int cols, const uint16_t* in, uint16_t* out, hipStream_t st) {
-  const dim3 grid((cols + 63) / 64, (rows + 63) / 64);
-  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, st, rows, cols, in, int64_t(cols), out,
-                     int64_t(rows));
-}
+// Collects up to kTransposeBatch dense transposes and issues them as one launch.
+struct TransposeList {
+  TransposeBatch b{};
+  void add(int rows, int cols, const uint16_t* in, uint16_t* out) {
+    if (rows <= 0 || cols <= 0) return;
+    const int k = b.n++;
+    b.rows[k] = rows;
+    b.cols[k] = cols;
+    b.tx[k] = (cols + 63) / 64;
+    b.in[k] = in;
+    b.out[k] = out;
+    b.tile0[k + 1] = b.tile0[k] + b.tx[k] * ((rows + 63) / 64);
+  }
+  void launch(hipStream_t st) const {
+    if (b.n > 0)
+      hipLaunchKernelGGL(k_transpose_bf16, dim3(b.tile0[b.n]), dim3(256), 0, st, b);
+  }
+};
 
-void colsum(int rows, int cols, const float* A, double* part, float* out, hipStream_t st) {
-  const int nb = colsum_parts(rows);
-  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, nb), dim3(256), 0, st, rows, cols, A,
-                     part);
-  hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, nb, cols, part,
-                     out);
-}
+// Collects up to kColsumBatch column sums over the same rows and issues them
+// as one pair of launches (part: colsum_parts(rows) x the total columns).
+struct ColsumList {
+  ColsumBatch b{};
+  void add(int cols, const float* A, float* out) {
+    const int k = b.n++;
+    b.cols[k] = cols;
+    b.A[k] = A;
+    b.out[k] = out;
+    b.tile0[k + 1] = b.tile0[k] + (cols + 63) / 64;
+    b.coff[k + 1] = b.coff[k] + cols;
+  }
+  void launch(int rows, double* part, hipStream_t st) const {
+    const int nb = colsum_parts(rows);
+    hipLaunchKernelGGL(k_colsum_part, dim3(b.tile0[b.n], nb), dim3(256), 0, st, rows, b, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3((b.coff[b.n] + 255) / 256), dim3(256), 0, st, nb, b,
+                       part);
+  }
+};
 
 GemmArgs gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
               const uint16_t* B, int64_t sbk, int64_t sbn) {
@@ -192,7 +217,9 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   const int F = d.F, H = d.H, O = d.O;
   const int64_t bo = static_cast<int64_t>(batch) * O;
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, loss, 0.0, int64_t(1));
-  hipLaunchKernelGGL(k_mse, dim3(grid_for(bo, 256)), dim3(256), 0, st, bo, Y, T,
+  // at most 128 workgroups: each adds its share to *loss with one atomic, and
+  // atomics on one address serialise
+  hipLaunchKernelGGL(k_mse, dim3(std::min(grid_for(bo, 256), 128)), dim3(256), 0, st, bo, Y, T,
                      1.0f / static_cast<float>(bo), w.dY32, w.dY16, loss);
   // Every product below runs with both operands contiguous along its sum
   // (the fast loader): the weights W2, W3 are transposed once per call, and
@@ -202,21 +229,25 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   // Transposing moves bf16 values unchanged: the products' rounding is the
   // same either way.
   const bool tr = batch % 8 == 0;
-  transpose_bf16(H, H, wb + d.qW2, w.W2T, st);
-  transpose_bf16(O, H, wb + d.qW3, w.W3T, st);
+  TransposeList tl;
+  tl.add(H, H, wb + d.qW2, w.W2T);
+  tl.add(O, H, wb + d.qW3, w.W3T);
   if (tr) {
-    transpose_bf16(batch, O, w.dY16, w.dYT, st);
-    transpose_bf16(batch, H, w.H2, w.H2T, st);
-    transpose_bf16(batch, H, w.H1, w.H1T, st);
-    transpose_bf16(batch, F, X, w.XT, st);
+    tl.add(batch, O, w.dY16, w.dYT);
+    tl.add(batch, H, w.H2, w.H2T);
+    tl.add(batch, H, w.H1, w.H1T);
+    tl.add(batch, F, X, w.XT);
   }
+  tl.launch(st);
+  // the bias gradients (column sums of dY, dZ2, dZ1) run together at the end
+  ColsumList cs;
   // dW3 = dY^T H2, db3 = column sums of dY
   GemmArgs g = tr ? gemm(O, H, batch, w.dYT, batch, 1, w.H2T, 1, batch)
                   : gemm(O, H, batch, w.dY16, 1, O, w.H2, H, 1);
   g.C32 = grad + d.oW3;
   g.ldc = H;
   launch_gemm(g, st);
-  colsum(batch, O, w.dY32, w.part, grad + d.ob3, st);
+  cs.add(O, w.dY32, grad + d.ob3);
   // dZ2 = (dY W3) * [Z2 > 0]
   g = gemm(batch, H, O, w.dY16, O, 1, w.W3T, 1, O);
   g.mask = w.Z2;
@@ -225,32 +256,40 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
   g.ldc = H;
   g.C16 = w.dZ2b;
   g.ldc16 = H;
+  if (tr) {
+    g.C16T = w.dZ2T;
+    g.ldt = batch;
+  }
   launch_gemm(g, st);
   // dW2 = dZ2^T H1, db2
-  if (tr) transpose_bf16(batch, H, w.dZ2b, w.dZ2T, st);
   g = tr ? gemm(H, H, batch, w.dZ2T, batch, 1, w.H1T, 1, batch)
          : gemm(H, H, batch, w.dZ2b, 1, H, w.H1, H, 1);
   g.C32 = grad + d.oW2;
   g.ldc = H;
   launch_gemm(g, st);
-  colsum(batch, H, w.dZ2, w.part, grad + d.ob2, st);
+  cs.add(H, w.dZ2, grad + d.ob2);
   // dZ1 = (dZ2 W2) * [Z1 > 0]
   g = gemm(batch, H, H, w.dZ2b, H, 1, w.W2T, 1, H);
   g.mask = w.Z1;
   g.ldm = H;
   g.C32 = w.dZ1;
   g.ldc = H;
-  g.C16 = w.dZ1b;
-  g.ldc16 = H;
+  if (tr) {
+    g.C16T = w.dZ1T;
+    g.ldt = batch;
+  } else {
+    g.C16 = w.dZ1b;
+    g.ldc16 = H;
+  }
   launch_gemm(g, st);
   // dW1 = dZ1^T X, db1
-  if (tr) transpose_bf16(batch, H, w.dZ1b, w.dZ1T, st);
   g = tr ? gemm(H, F, batch, w.dZ1T, batch, 1, w.XT, 1, batch)
          : gemm(H, F, batch, w.dZ1b, 1, H, X, F, 1);
   g.C32 = grad + d.oW1;
   g.ldc = F;
   launch_gemm(g, st);
-  colsum(batch, H, w.dZ1, w.part, grad + d.ob1, st);
+  cs.add(H, w.dZ1, grad + d.ob1);
+  cs.launch(batch, w.part, st);
   CHECK_LAUNCH();
   return SCH_OK;
 }

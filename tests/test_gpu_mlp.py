@@ -57,9 +57,12 @@ def close(a, b, norm=1e-3, elem=1e-2):
 
 
 # the first cases take the element-wise and register-prefetch products (K
-# below, inside and past one 128-wide chunk); the last one's first layer
-# (K = 2048) the products that load straight to LDS, over a ragged 200 rows
-CASES = [((100, 256, 40), 77), ((64, 32, 8), 5), ((300, 96, 50), 130), ((2048, 64, 24), 200)]
+# below, inside and past one 128-wide chunk); the fourth one's first layer
+# (K = 2048) the products that load straight to LDS, over a ragged 200 rows;
+# the last one (batch a multiple of 8, widths not) has the element-wise
+# products of the backward pass write the transposed copies as well
+CASES = [((100, 256, 40), 77), ((64, 32, 8), 5), ((300, 96, 50), 130), ((2048, 64, 24), 200),
+         ((40, 36, 5), 64)]
 
 
 @pytest.mark.parametrize("dims,B", CASES)
