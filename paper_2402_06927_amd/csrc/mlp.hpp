@@ -47,7 +47,7 @@ struct GemmArgs {
   const float* mask;
   int64_t ldm;
   int relu;
-  float* kpart;  // split-K partial products [gridDim.z][M][N] (k_gemm_bf16_lds), or null
+  float* kpart;  // split-K partial products [gridDim.z][M][N] (K-contiguous loaders), or null
 };
 
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 8;  // LDS rows of 80 bytes
@@ -178,6 +178,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const GemmArgs g) {
 // (round-robin), each with its own L2; the tiles are renumbered so that the
 // column tiles of one row block run on the same XCD and read that block of A
 // through one L2.  The sums are those of k_gemm_bf16, in the same order.
+// Split K as in k_gemm_bf16_lds (below), in whole chunks of KC.
 template <int KC, int DEPTH>
 __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
   static_assert(DEPTH % 2 == 0, "the LDS buffer of a stage is fixed");
@@ -192,6 +193,11 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
   const int m0 = (tile / nbx) * kGM, n0 = (tile % nbx) * kGN;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   const int row0 = t / SEGS, seg = (t % SEGS) * 8;  // rows row0 + RSTEP i
+  // split K (gridDim.z > 1, K a multiple of KC): slice z takes the chunks
+  // c_lo .. c_hi - 1 of KC values and stores raw partial sums
+  const int nz = gridDim.z, z = blockIdx.z;
+  const int c_lo = nz > 1 ? z * (g.K / KC) / nz : 0;
+  const int kl = nz > 1 ? ((z + 1) * (g.K / KC) / nz - c_lo) * KC : g.K;
   // Loads are never predicated (a branch around them would make the compiler
   // wait for every load in flight before the next LDS store): rows past M or
   // N and segments past K read the last valid row or segment, and the value
@@ -203,15 +209,15 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
 #pragma unroll
   for (int i = 0; i < PASS; ++i) {
     const int gm = m0 + row0 + RSTEP * i, gn = n0 + row0 + RSTEP * i;
-    pa[i] = g.A + static_cast<int64_t>(min(gm, g.M - 1)) * g.sam;
-    pb[i] = g.B + static_cast<int64_t>(min(gn, g.N - 1)) * g.sbn;
+    pa[i] = g.A + static_cast<int64_t>(min(gm, g.M - 1)) * g.sam + c_lo * KC;
+    pb[i] = g.B + static_cast<int64_t>(min(gn, g.N - 1)) * g.sbn + c_lo * KC;
     arow[i] = gm < g.M;
     brow[i] = gn < g.N;
   }
   auto ld = [&](const uint16_t* p, bool ok, int k0) -> uint4 {
     const int k = k0 + seg;
-    uint4 v = *reinterpret_cast<const uint4*>(p + min(k, g.K - 8));
-    ok = ok && k < g.K;
+    uint4 v = *reinterpret_cast<const uint4*>(p + min(k, kl - 8));
+    ok = ok && k < kl;
     v.x = ok ? v.x : 0u;
     v.y = ok ? v.y : 0u;
     v.z = ok ? v.z : 0u;
@@ -225,7 +231,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   // the chunk count is rounded up to a multiple of DEPTH: the chunks past K
   // are zero and add exact zeros
-  const int nk = (g.K + KC - 1) / KC;
+  const int nk = (kl + KC - 1) / KC;
   uint4 ra[DEPTH][PASS], rb[DEPTH][PASS];
 #pragma unroll
   for (int s = 0; s < DEPTH; ++s)
@@ -255,7 +261,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
       gemm_chunk<KC>(As[b], Bs[b], wm, wn, lane, acc);
     }
   }
-  gemm_store(g, m0, n0, wm, wn, lane, acc);
+  if (nz > 1)
+    gemm_store<true>(g, m0, n0, wm, wn, lane, acc, z);
+  else
+    gemm_store(g, m0, n0, wm, wn, lane, acc);
 }
 
 // Operands contiguous along K with K a multiple of kLC, sam, sbn multiples of
@@ -366,7 +375,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_lds(const GemmArgs g) {
     gemm_store(g, m0, n0, 16 * wm, 16 * wn, lane, acc);
 }
 
-// The sum of the nz split-K slices of k_gemm_bf16_lds (in slice order), then
+// The sum of the nz split-K slices of a K-contiguous loader (in slice order), then
 // the epilogue, one element per thread.
 __global__ void k_gemm_reduce(const GemmArgs g, int nz) {
   const int64_t mn = static_cast<int64_t>(g.M) * g.N;

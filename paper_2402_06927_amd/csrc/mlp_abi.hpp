@@ -20,7 +20,7 @@ bool mlp_ok(const sch_mlp* n) {
 // along its summation index; the column-sum partials.
 struct MlpWs {
   float *Z1, *Z2, *dY32, *dZ2, *dZ1;
-  float* kpart;  // split-K partials of the first layer's product
+  float* kpart;  // split-K partials (the first layer, the weight gradients)
   uint16_t *H1, *H2, *dY16, *dZ2b, *dZ1b;
   uint16_t *XT, *dYT, *H1T, *H2T, *dZ2T, *dZ1T, *W2T, *W3T;
   double* part;
@@ -29,13 +29,14 @@ struct MlpWs {
 
 int colsum_parts(int rows) { return (rows + kColsumRows - 1) / kColsumRows; }
 
-// Slices of K for a product on the straight-to-LDS loader: its 64 x 64 tiles
-// alone fill fewer than half the chip's 256 compute units when M x N is small
-// (the training batch's first layer: 64 tiles), so K is split until the
-// slices fill it (at most 4, at least 2 chunks of kLC per slice).
+// Slices of K for a product on a K-contiguous loader: when its 64 x 64 tiles
+// alone fill fewer than half the chip's 256 compute units (the training
+// batch's first layer: 64 tiles; the weight gradients of the second and third
+// layers: 16 and 20), K is split until the slices fill it (at most 4, each at
+// least 2 chunks of kLC; K a multiple of kLC).
 int ksplit_for(int M, int N, int K) {
   const int tiles = ((M + kGM - 1) / kGM) * ((N + kGN - 1) / kGN);
-  if (K < 2048 || K % kLC != 0 || tiles >= 128) return 1;
+  if (K % kLC != 0 || tiles >= 128) return 1;
   int z = 1;
   while (z < 4 && tiles * 2 * z <= 256 && K / kLC >= 2 * (2 * z)) z *= 2;
   return z;
@@ -47,8 +48,16 @@ MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
   const size_t bh = static_cast<size_t>(batch) * d.H, bo = static_cast<size_t>(batch) * d.O;
   w.Z1 = c.take<float>(bh);
   w.Z2 = c.take<float>(bh);
-  const int kz = ksplit_for(batch, d.H, d.F);
-  w.kpart = c.take<float>(kz > 1 ? static_cast<size_t>(kz) * bh : 0);
+  // split-K partials of the first layer and of the three weight gradients
+  // (one product at a time)
+  size_t kp = 0;
+  const int split[4][3] = {{batch, d.H, d.F}, {d.O, d.H, batch}, {d.H, d.H, batch},
+                           {d.H, d.F, batch}};
+  for (const auto& p : split) {
+    const int kz = ksplit_for(p[0], p[1], p[2]);
+    if (kz > 1) kp = std::max(kp, static_cast<size_t>(kz) * p[0] * p[1]);
+  }
+  w.kpart = c.take<float>(kp);
   w.H1 = c.take<uint16_t>(bh);
   w.H2 = c.take<uint16_t>(bh);
   w.dY32 = c.take<float>(bo);
@@ -131,19 +140,20 @@ void launch_gemm(const GemmArgs& g, hipStream_t st) {
   // (the K-contiguous loaders clamp their reads to K - 8: K >= 8)
   const bool kc = g.sak == 1 && g.sbk == 1 && g.K >= 8 && g.K % 8 == 0 && g.sam % 8 == 0 &&
                   g.sbn % 8 == 0 && aligned16(g.A) && aligned16(g.B);
+  // K split over idle compute units where the caller gave the partials'
+  // buffer (kz > 1 only for K a multiple of kLC, the chunk of both loaders)
+  const int kz = kc && g.kpart ? ksplit_for(g.M, g.N, g.K) : 1;
   // long K (the first layer's products): loads straight to LDS, four chunks
-  // in flight, K split over idle compute units where the caller gave the
-  // partials' buffer; shorter K: register prefetch, which measured faster there
-  if (kc && g.K >= 2048 && g.K % kLC == 0) {
-    const int kz = g.kpart ? ksplit_for(g.M, g.N, g.K) : 1;
+  // in flight; shorter K: register prefetch, which measured faster there
+  if (kc && g.K >= 2048 && g.K % kLC == 0)
     hipLaunchKernelGGL(k_gemm_bf16_lds, dim3(grid.x, grid.y, kz), dim3(256), 0, st, g);
-    if (kz > 1)
-      hipLaunchKernelGGL(k_gemm_reduce, dim3(grid_for(static_cast<int64_t>(g.M) * g.N, 256)),
-                         dim3(256), 0, st, g, kz);
-  } else if (kc)
-    hipLaunchKernelGGL((k_gemm_bf16_kc<128, 2>), grid, dim3(256), 0, st, g);
+  else if (kc)
+    hipLaunchKernelGGL((k_gemm_bf16_kc<kLC, 2>), dim3(grid.x, grid.y, kz), dim3(256), 0, st, g);
   else
     hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+  if (kz > 1)
+    hipLaunchKernelGGL(k_gemm_reduce, dim3(grid_for(static_cast<int64_t>(g.M) * g.N, 256)),
+                       dim3(256), 0, st, g, kz);
 }
 
 }  // namespace
@@ -246,6 +256,7 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
                   : gemm(O, H, batch, w.dY16, 1, O, w.H2, H, 1);
   g.C32 = grad + d.oW3;
   g.ldc = H;
+  g.kpart = w.kpart;
   launch_gemm(g, st);
   cs.add(O, w.dY32, grad + d.ob3);
   // dZ2 = (dY W3) * [Z2 > 0]
@@ -266,6 +277,7 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
          : gemm(H, H, batch, w.dZ2b, 1, H, w.H1, H, 1);
   g.C32 = grad + d.oW2;
   g.ldc = H;
+  g.kpart = w.kpart;
   launch_gemm(g, st);
   cs.add(H, w.dZ2, grad + d.ob2);
   // dZ1 = (dZ2 W2) * [Z1 > 0]
@@ -287,6 +299,7 @@ int sch_mlp_backward(const sch_mlp* net, int32_t batch, const uint16_t* X, const
          : gemm(H, F, batch, w.dZ1b, 1, H, X, F, 1);
   g.C32 = grad + d.oW1;
   g.ldc = F;
+  g.kpart = w.kpart;
   launch_gemm(g, st);
   cs.add(H, w.dZ1, grad + d.ob1);
   cs.launch(batch, w.part, st);

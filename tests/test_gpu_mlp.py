@@ -59,10 +59,12 @@ def close(a, b, norm=1e-3, elem=1e-2):
 # the first cases take the element-wise and register-prefetch products (K
 # below, inside and past one 128-wide chunk); the fourth one's first layer
 # (K = 2048) the products that load straight to LDS, over a ragged 200 rows;
-# the last one (batch a multiple of 8, widths not) has the element-wise
-# products of the backward pass write the transposed copies as well
+# the fifth one (batch a multiple of 8, widths not) has the element-wise
+# products of the backward pass write the transposed copies as well; in the
+# last one (K = 1024 over the batch) the three weight gradients split K four
+# ways on the register-prefetch loader, over a ragged 72-wide hidden layer
 CASES = [((100, 256, 40), 77), ((64, 32, 8), 5), ((300, 96, 50), 130), ((2048, 64, 24), 200),
-         ((40, 36, 5), 64)]
+         ((40, 36, 5), 64), ((96, 72, 20), 1024)]
 
 
 @pytest.mark.parametrize("dims,B", CASES)
