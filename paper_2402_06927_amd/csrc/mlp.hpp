@@ -267,19 +267,25 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_kc(const GemmArgs g) {
     gemm_store(g, m0, n0, wm, wn, lane, acc);
 }
 
-// Operands contiguous along K with K a multiple of kLC, sam, sbn multiples of
-// 8 and 16-byte aligned rows.  The operands travel from global memory to LDS
-// without registers (global_load_lds_dwordx4): one instruction moves a block
-// of 16 rows x 32 values of k, lane l taking row l % 16 and values
-// 8 (l / 16) .. + 7, and lands it in LDS in lane order, which is the layout
-// in which the 16 x 16 x 32 bf16 matrix instruction takes its operands (lane
-// l: row l % 16, the same eight values of k for A and B), so each operand is
-// read back with one conflict-free 16-byte LDS read per lane.  A ring of kLS
-// stages of kLC values of k (32 KB each: 16 blocks of A and 16 of B) keeps
-// kLS - 1 chunks in flight per compute unit, as the products are bound by
-// the latency of their loads; one barrier per chunk.  Rows past M or N read
-// the last row (their results are not stored).  Tile order as in
-// k_gemm_bf16_kc.  Within a chunk the sums run over k in steps of 32.
+// Output tiles of TM x TM (64 or 128).  Operands contiguous along K with K a
+// multiple of kLC, sam, sbn multiples of 8 and 16-byte aligned rows.  The
+// operands travel from global memory to LDS without registers
+// (global_load_lds_dwordx4): one instruction moves a block of 16 rows x 32
+// values of k, lane l taking row l % 16 and values 8 (l / 16) .. + 7, and
+// lands it in LDS in lane order, which is the layout in which the
+// 16 x 16 x 32 bf16 matrix instruction takes its operands (lane l: row
+// l % 16, the same eight values of k for A and B), so each operand is read
+// back with one conflict-free 16-byte LDS read per lane.  A stage holds 16
+// blocks of each operand: TM / 16 row blocks by KC / 32 blocks of k, so a
+// chunk is KC = 512 / (TM / 16) values of k (128 for 64-row tiles, 64 for
+// 128-row ones).  A ring of kLS stages (32 KB each) keeps kLS - 1 chunks in
+// flight per compute unit, as the products are bound by the rate at which
+// their loads arrive; one barrier per chunk.  Each wavefront computes a
+// (TM / 2) x (TM / 2) quarter of the tile.  Rows past M or N read the last
+// row (their results are not stored).  Tile order as in k_gemm_bf16_kc.
+// Within a chunk the sums run over k in steps of 32.  The 128-row tile moves
+// half the bytes per product of the 64-row one (each unit's loads are the
+// bound: about 30 GB/s per unit from L2).
 // Split K (gridDim.z > 1, when the tiles alone would leave compute units
 // idle): slice z takes chunks [z nk / Z, (z + 1) nk / Z) and writes its raw
 // sums to g.kpart; k_gemm_reduce adds the slices in order and applies the
@@ -295,40 +301,61 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
+// 16 bytes per lane from global memory straight to LDS, in lane order from
+// the wavefront's base address lds
+__device__ __forceinline__ void load_lds16(const uint16_t* p, uint4* lds) {
+  __builtin_amdgcn_global_load_lds(p, lds, 16, 0, 0);
+}
+
+template <int TM>
 __global__ void __launch_bounds__(256) k_gemm_bf16_lds(const GemmArgs g) {
-  // [stage][operand][block = 4 row blocks x 4 k blocks][lane]
+  static_assert(TM == 64 || TM == 128, "tile edge");
+  // RB row blocks of 16 by QB blocks of 32 values of k per operand and stage;
+  // each wavefront loads RPW row blocks, and computes WB x WB matrix-core tiles
+  constexpr int RB = TM / 16, QB = 16 / RB, KC = 32 * QB, RPW = RB / 4, WB = TM / 32;
+  static_assert(2 * RPW * QB == 8, "eight loads per wavefront and chunk (the waits below)");
+  // [stage][operand][block = row block x QB + k block][lane]
   __shared__ __attribute__((aligned(16))) uint4 T[kLS][2][16][64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int nbx = gridDim.x, ntile = gridDim.x * gridDim.y;
   int tile = blockIdx.y * nbx + blockIdx.x;
   if (ntile % 8 == 0) tile = (tile % 8) * (ntile / 8) + tile / 8;
-  const int m0 = (tile / nbx) * kGM, n0 = (tile % nbx) * kGN;
+  const int m0 = (tile / nbx) * TM, n0 = (tile % nbx) * TM;
   // an LDS store the compiler can see (never taken for valid sizes): without
   // one it takes the array for never written and drops the reads
   if (g.M <= 0) T[0][0][0][lane] = make_uint4(0u, 0u, 0u, 0u);
-  // wave w loads the blocks of row block w of A and of B: lane l of block
-  // (w, q) reads row 16 w + l % 16 at k = 32 q + 8 (l / 16)
-  const int r = 16 * w + (lane & 15), kl = 8 * (lane >> 4);
-  const uint16_t* pa = g.A + static_cast<int64_t>(min(m0 + r, g.M - 1)) * g.sam + kl;
-  const uint16_t* pb = g.B + static_cast<int64_t>(min(n0 + r, g.N - 1)) * g.sbn + kl;
-  auto issue = [&](int c, int st) {
-    const int k0 = c * kLC;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      __builtin_amdgcn_global_load_lds(pa + k0 + 32 * q, &T[st][0][4 * w + q][0], 16, 0, 0);
-      __builtin_amdgcn_global_load_lds(pb + k0 + 32 * q, &T[st][1][4 * w + q][0], 16, 0, 0);
-    }
-  };
-  const int wm = (w >> 1) * 2, wn = (w & 1) * 2;  // this wave's row and column blocks
-  f32x4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int nk_all = g.K / kLC, nz = gridDim.z, z = blockIdx.z;
+  // wave w loads row blocks RPW w .. + RPW - 1 of A and of B: lane l of block
+  // (rb, q) reads row 16 rb + l % 16 at k = 32 q + 8 (l / 16)
+  const int kl = 8 * (lane >> 4);
+  const int nk_all = g.K / KC, nz = gridDim.z, z = blockIdx.z;
   const int c_lo = (nk_all * z) / nz, nk = (nk_all * (z + 1)) / nz - c_lo;
-  pa += static_cast<int64_t>(c_lo) * kLC;
-  pb += static_cast<int64_t>(c_lo) * kLC;
+  const uint16_t* pa[RPW];
+  const uint16_t* pb[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = 16 * (RPW * w + i) + (lane & 15);
+    pa[i] = g.A + static_cast<int64_t>(min(m0 + r, g.M - 1)) * g.sam + kl +
+            static_cast<int64_t>(c_lo) * KC;
+    pb[i] = g.B + static_cast<int64_t>(min(n0 + r, g.N - 1)) * g.sbn + kl +
+            static_cast<int64_t>(c_lo) * KC;
+  }
+  auto issue = [&](int c, int st) {
+    const int k0 = c * KC;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int b = (RPW * w + i) * QB + q;
+        load_lds16(pa[i] + k0 + 32 * q, &T[st][0][b][0]);
+        load_lds16(pb[i] + k0 + 32 * q, &T[st][1][b][0]);
+      }
+  };
+  const int wm = (w >> 1) * WB, wn = (w & 1) * WB;  // this wave's first row and column blocks
+  f32x4 acc[WB][WB];
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < kLS - 1; ++c)
     if (c < nk) issue(c, c);
@@ -355,28 +382,36 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_lds(const GemmArgs g) {
     if (c + kLS - 1 < nk) issue(c + kLS - 1, (c + kLS - 1) % kLS);
     const int st = c % kLS;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      bf16x8 a[2], b[2];
+    for (int q = 0; q < QB; ++q) {
+      bf16x8 a[WB], b[WB];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const bf16x8*>(&T[st][0][4 * (wm + i) + q][lane]);
-        b[i] = *reinterpret_cast<const bf16x8*>(&T[st][1][4 * (wn + i) + q][lane]);
+      for (int i = 0; i < WB; ++i) {
+        a[i] = *reinterpret_cast<const bf16x8*>(&T[st][0][(wm + i) * QB + q][lane]);
+        b[i] = *reinterpret_cast<const bf16x8*>(&T[st][1][(wn + i) * QB + q][lane]);
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-  if (nz > 1)
-    gemm_store<true>(g, m0, n0, 16 * wm, 16 * wn, lane, acc, z);
-  else
-    gemm_store(g, m0, n0, 16 * wm, 16 * wn, lane, acc);
+  // the stores take 2 x 2 matrix-core tiles at a time
+#pragma unroll
+  for (int qi = 0; qi < WB; qi += 2)
+#pragma unroll
+    for (int qj = 0; qj < WB; qj += 2) {
+      const f32x4 sub[2][2] = {{acc[qi][qj], acc[qi][qj + 1]}, {acc[qi + 1][qj], acc[qi + 1][qj + 1]}};
+      if (nz > 1)
+        gemm_store<true>(g, m0, n0, 16 * (wm + qi), 16 * (wn + qj), lane, sub, z);
+      else
+        gemm_store(g, m0, n0, 16 * (wm + qi), 16 * (wn + qj), lane, sub);
+    }
 }
 
 // The sum of the nz split-K slices of a K-contiguous loader (in slice order), then
-// the epilogue, one element per thread.
+// the epilogue, one element per thread (consecutive elements across lanes, so
+// the epilogue's stores coalesce).
 __global__ void k_gemm_reduce(const GemmArgs g, int nz) {
   const int64_t mn = static_cast<int64_t>(g.M) * g.N;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < mn;

@@ -29,17 +29,39 @@ struct MlpWs {
 
 int colsum_parts(int rows) { return (rows + kColsumRows - 1) / kColsumRows; }
 
-// Slices of K for a product on a K-contiguous loader: when its 64 x 64 tiles
-// alone fill fewer than half the chip's 256 compute units (the training
-// batch's first layer: 64 tiles; the weight gradients of the second and third
-// layers: 16 and 20), K is split until the slices fill it (at most 4, each at
-// least 2 chunks of kLC; K a multiple of kLC).
-int ksplit_for(int M, int N, int K) {
-  const int tiles = ((M + kGM - 1) / kGM) * ((N + kGN - 1) / kGN);
-  if (K % kLC != 0 || tiles >= 128) return 1;
+// Slices of K for a product on a K-contiguous loader with tm x tm tiles and
+// chunks of kc values of k: when its tiles alone fill fewer than half the
+// chip's 256 compute units (the first layer: 64 tiles, of 128 x 128 at 4096
+// rows and of 64 x 64 at 1024; the weight gradients of the second and third
+// layers: 16 and 20 tiles of 64 x 64), K is split until the slices fill it
+// (at most 16, each at least 2 chunks; K a multiple of kc).
+int ksplit(int M, int N, int K, int tm, int kc) {
+  const int tiles = ((M + tm - 1) / tm) * ((N + tm - 1) / tm);
+  if (K % kc != 0 || tiles >= 128) return 1;
   int z = 1;
-  while (z < 4 && tiles * 2 * z <= 256 && K / kLC >= 2 * (2 * z)) z *= 2;
+  while (z < 16 && tiles * 2 * z <= 256 && K / kc >= 2 * (2 * z)) z *= 2;
   return z;
+}
+
+// The loader launch_gemm takes for a product whose operands are contiguous
+// along K: long K (the first layer's products) loads straight to LDS, on
+// 128 x 128 tiles where at least 64 of them cover the product (a quarter of
+// the chip, so a split of at most 4 fills it: the first layer at 4096 rows,
+// 31 us against 40 on 64 x 64 tiles) and on 64 x 64 tiles otherwise (at 1024
+// rows 16 tiles of 128 split 16 ways took 12.3 + 7.4 us for the sum of the
+// slices, 64 tiles of 64 split 4 ways 13.0 + 4.1); shorter K takes the
+// register prefetch, which measured faster there.
+struct GemmPlan {
+  bool lds;
+  int tm, kc, kz;
+};
+GemmPlan plan_gemm(int M, int N, int K, bool split) {
+  GemmPlan p{};
+  p.lds = K >= 2048 && K % kLC == 0;
+  p.tm = p.lds && ((M + 127) / 128) * ((N + 127) / 128) >= 64 ? 128 : 64;
+  p.kc = p.tm == 128 ? kLC / 2 : kLC;
+  p.kz = split ? ksplit(M, N, K, p.tm, p.kc) : 1;
+  return p;
 }
 
 MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
@@ -54,7 +76,7 @@ MlpWs carve_mlp(void* base, const MlpDims& d, int batch) {
   const int split[4][3] = {{batch, d.H, d.F}, {d.O, d.H, batch}, {d.H, d.H, batch},
                            {d.H, d.F, batch}};
   for (const auto& p : split) {
-    const int kz = ksplit_for(p[0], p[1], p[2]);
+    const int kz = plan_gemm(p[0], p[1], p[2], true).kz;
     if (kz > 1) kp = std::max(kp, static_cast<size_t>(kz) * p[0] * p[1]);
   }
   w.kpart = c.take<float>(kp);
@@ -136,24 +158,27 @@ GemmArgs gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 void launch_gemm(const GemmArgs& g, hipStream_t st) {
-  const dim3 grid((g.N + kGN - 1) / kGN, (g.M + kGM - 1) / kGM);
   // (the K-contiguous loaders clamp their reads to K - 8: K >= 8)
   const bool kc = g.sak == 1 && g.sbk == 1 && g.K >= 8 && g.K % 8 == 0 && g.sam % 8 == 0 &&
                   g.sbn % 8 == 0 && aligned16(g.A) && aligned16(g.B);
+  if (!kc) {
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((g.N + kGN - 1) / kGN, (g.M + kGM - 1) / kGM),
+                       dim3(256), 0, st, g);
+    return;
+  }
   // K split over idle compute units where the caller gave the partials'
-  // buffer (kz > 1 only for K a multiple of kLC, the chunk of both loaders)
-  const int kz = kc && g.kpart ? ksplit_for(g.M, g.N, g.K) : 1;
-  // long K (the first layer's products): loads straight to LDS, four chunks
-  // in flight; shorter K: register prefetch, which measured faster there
-  if (kc && g.K >= 2048 && g.K % kLC == 0)
-    hipLaunchKernelGGL(k_gemm_bf16_lds, dim3(grid.x, grid.y, kz), dim3(256), 0, st, g);
-  else if (kc)
-    hipLaunchKernelGGL((k_gemm_bf16_kc<kLC, 2>), dim3(grid.x, grid.y, kz), dim3(256), 0, st, g);
+  // buffer
+  const GemmPlan p = plan_gemm(g.M, g.N, g.K, g.kpart != nullptr);
+  const dim3 grid((g.N + p.tm - 1) / p.tm, (g.M + p.tm - 1) / p.tm, p.kz);
+  if (p.lds && p.tm == 128)
+    hipLaunchKernelGGL((k_gemm_bf16_lds<128>), grid, dim3(256), 0, st, g);
+  else if (p.lds)
+    hipLaunchKernelGGL((k_gemm_bf16_lds<64>), grid, dim3(256), 0, st, g);
   else
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
-  if (kz > 1)
+    hipLaunchKernelGGL((k_gemm_bf16_kc<kLC, 2>), grid, dim3(256), 0, st, g);
+  if (p.kz > 1)
     hipLaunchKernelGGL(k_gemm_reduce, dim3(grid_for(static_cast<int64_t>(g.M) * g.N, 256)),
-                       dim3(256), 0, st, g, kz);
+                       dim3(256), 0, st, g, p.kz);
 }
 
 }  // namespace

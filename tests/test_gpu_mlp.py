@@ -61,10 +61,13 @@ def close(a, b, norm=1e-3, elem=1e-2):
 # (K = 2048) the products that load straight to LDS, over a ragged 200 rows;
 # the fifth one (batch a multiple of 8, widths not) has the element-wise
 # products of the backward pass write the transposed copies as well; in the
-# last one (K = 1024 over the batch) the three weight gradients split K four
-# ways on the register-prefetch loader, over a ragged 72-wide hidden layer
+# sixth one (K = 1024 over the batch) the three weight gradients split K four
+# ways on the register-prefetch loader, over a ragged 72-wide hidden layer;
+# in the seventh one the first layer takes 128 x 128 tiles (16 x 5 of them,
+# ragged both ways) with K = 2048 split 2 ways; in the last one the first
+# layer's split product is 66 wide (ragged tiles of 64, split 8 ways)
 CASES = [((100, 256, 40), 77), ((64, 32, 8), 5), ((300, 96, 50), 130), ((2048, 64, 24), 200),
-         ((40, 36, 5), 64), ((96, 72, 20), 1024)]
+         ((40, 36, 5), 64), ((96, 72, 20), 1024), ((2048, 520, 24), 2000), ((2048, 66, 24), 200)]
 
 
 @pytest.mark.parametrize("dims,B", CASES)
