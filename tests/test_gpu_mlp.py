@@ -117,6 +117,42 @@ def test_full_size_forward(sch):
     close(N(Y), Yr)
 
 
+def test_bench_shapes(sch):
+    """The configured network at the benchmark's shapes: inference of 4096
+    particles (the first layer on 128 x 128 tiles, K split 4 ways) and a
+    training step's loss and gradient on 1024 rows (the first layer on
+    64 x 64 tiles split 4 ways, the small weight gradients split on the
+    register-prefetch loader)."""
+    dims = (4352, 256, 320)
+    theta = M.f32(W.mlp_init_params(*dims, 5))
+    g = np.random.default_rng(4)
+    X = M.bf16(g.standard_normal((4096, dims[0])))
+    net = net_on_gpu(sch, theta, dims)
+    ws = torch.empty(sch.sch_mlp_workspace_bytes(net, 4096), dtype=torch.uint8, device="cuda")
+    Xg = bf16_tensor(X)
+    Y = torch.empty((4096, dims[2]), dtype=torch.float32, device="cuda")
+    _say("mlp inference 4096")
+    sch.sch_mlp_forward(net, Xg, Y, ws)
+    Yr, _ = M.forward_bf16(theta, X, dims)
+    close(N(Y), Yr)
+    B = 1024
+    T = M.f32(g.standard_normal((B, dims[2])))
+    Y1 = torch.empty((B, dims[2]), dtype=torch.float32, device="cuda")
+    _say("mlp training step 1024")
+    sch.sch_mlp_forward(net, Xg[:B], Y1, ws)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(theta.size, dtype=torch.float32, device="cuda")
+    sch.sch_mlp_backward(net, Xg[:B], Y1, torch.tensor(T, dtype=torch.float32, device="cuda"),
+                         loss, grad, ws)
+    lr_, gr = M.loss_grad_bf16(theta, X[:B], T, dims)
+    assert abs(N(loss)[0] - lr_) <= 1e-4 * lr_
+    gg = N(grad)
+    lay, _ = M.layout(*dims)
+    for name, (off, shape) in lay.items():
+        size = int(np.prod(shape))
+        close(gg[off:off + size], gr[off:off + size], norm=3e-3, elem=3e-2)
+
+
 def test_adam_matches_oracle(sch):
     dims = (40, 24, 6)
     theta = M.f32(W.mlp_init_params(*dims, 9))
