@@ -116,3 +116,37 @@ def test_window_and_jitter_are_bitwise_deterministic(sch):
             assert np.array_equal(a, b)
     finally:
         sch.sch_tune_set(sch.TUNE_THREADS, 0)
+
+
+def test_network_products_are_bitwise_deterministic(sch):
+    """Two forward and backward passes of the configured network (4096-row
+    inference on 128 x 128 tiles with K split 4 ways, a 1024-row training step
+    with split first layer and weight gradients) give the same outputs and
+    gradients bit for bit: the split-K slices are summed in slice order and
+    no product uses atomics.  (The loss sums its workgroups' shares with
+    atomics, so it is compared to rounding.)"""
+    F, H, O = 4352, 256, 320
+    g = np.random.default_rng(7)
+    k = sch.sch_mlp_param_count(F, H, O)
+    theta = torch.tensor(W.mlp_init_params(F, H, O, 2), dtype=torch.float32, device="cuda")
+    net = sch.Mlp(F, H, O, theta, torch.empty(H * F + H * H + O * H, dtype=torch.bfloat16,
+                                              device="cuda"))
+    sch.sch_mlp_sync(net)
+    X = torch.tensor(g.standard_normal((4096, F)), dtype=torch.float32,
+                     device="cuda").to(torch.bfloat16)
+    T = torch.tensor(g.standard_normal((1024, O)), dtype=torch.float32, device="cuda")
+    ws = torch.empty(sch.sch_mlp_workspace_bytes(net, 4096), dtype=torch.uint8, device="cuda")
+    runs = []
+    for _ in range(2):
+        Y = torch.empty((4096, O), dtype=torch.float32, device="cuda")
+        sch.sch_mlp_forward(net, X, Y, ws)
+        Y1 = torch.empty((1024, O), dtype=torch.float32, device="cuda")
+        sch.sch_mlp_forward(net, X[:1024], Y1, ws)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        grad = torch.zeros(k, dtype=torch.float32, device="cuda")
+        sch.sch_mlp_backward(net, X[:1024], Y1, T, loss, grad, ws)
+        torch.cuda.synchronize()
+        runs.append([t.cpu().numpy() for t in (Y, Y1, grad, loss)])
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert np.array_equal(a, b)
+    np.testing.assert_allclose(runs[0][3], runs[1][3], rtol=1e-12, atol=0)
